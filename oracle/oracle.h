@@ -1,0 +1,142 @@
+/*
+ * FP64 CPU oracle for the UGKWP particle phase and source iteration
+ * (Yang, Zhu, Liu & Xu, "Unified gas-kinetic wave-particle method for
+ * frequency-dependent radiation transport", arXiv 2312.16981).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, obviously-correct
+ * reference that the GPU library is checked against.  Only the tests, the
+ * smoke check and the benchmark's CPU-baseline leg may load it.  It shares
+ * no code, header or table with the GPU library.
+ *
+ * Every function follows one passage of the paper; the comment above each
+ * names it.  Readings of passages that are silent or ambiguous are listed in
+ * the design notes of the repository and restated at the point of use here.
+ *
+ * Parity status: the whole-step result has no printed value in the paper
+ * ("parity unpinned" beyond the invariants the tests check: free streaming,
+ * diffusion limit, equilibrium, 0-D relaxation, energy conservation, per-cell
+ * particle ledger, symmetry).  The scalar pieces (Philox, Planck integral,
+ * flux coefficients, frequency sampler) are pinned against independent
+ * implementations / closed forms / brute force.
+ */
+#ifndef UGKWP_ORACLE_H
+#define UGKWP_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------- scalar building blocks ---------------- */
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): out[4] = bijection of
+ * the 128-bit counter ctr[4] under the 64-bit key key[2]. */
+void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Uniform draw in (0,1) keyed by (seed, particle id, step, purpose, draw d).
+ * Counter = (id_lo, id_hi, step, purpose<<24 | d/2), key = (seed_lo, seed_hi);
+ * draw d uses words (r0,r1) if d is even, (r2,r3) if odd; u = (k + 1/2) 2^-52
+ * with k = r_a<<20 | r_b>>12. */
+double ora_uniform(uint64_t seed, uint64_t id, uint32_t step, uint32_t purpose, uint32_t d);
+enum { ORA_PURPOSE_BIRTH = 1, ORA_PURPOSE_FLIGHT = 2 };
+
+/* Incomplete Planck integral Pi(x) = int_x^inf t^3/(e^t - 1) dt. */
+double ora_planck_tail(double x);
+/* L(x) = int_0^x t^3/(e^t-1) dt  (small-argument Bernoulli series, x < 2). */
+double ora_planck_head(double x);
+/* Group equilibrium value of rho: phi_g(T) = a c T^4 (15/pi^4) int_{nl/T}^{nh/T} t^3/(e^t-1) dt. */
+double ora_phi_group(double T, double nl, double nh, double a, double c);
+/* d phi_g / dT. */
+double ora_dphi_group(double T, double nl, double nh, double a, double c);
+
+/* Flux coefficients of the UGKS free-transport / equilibrium fluxes as
+ * functions of s = dt / tau = c sigma dt / eps^2. */
+double ora_coef_c4(double s);          /* C4 = (1 - e^{-s}) / s           */
+double ora_coef_w(double s);           /* W  = C4 - e^{-s}                 */
+double ora_coef_c2_over_dt(double s);  /* C2 / dt  (C2 of the F^eq flux)   */
+
+/* Linear-frequency sampling: slope beta = (B(nh) - B(nl)) / B(nmid), limited
+ * to [-2, 2], at temperature T. */
+double ora_freq_slope(double nl, double nh, double T);
+/* Inverse of the linear CDF on [nl, nh] with slope beta for a uniform U. */
+double ora_sample_nu(double nl, double nh, double beta, double U);
+
+/* ---------------- simulation ---------------- */
+
+enum { ORA_BC_VACUUM = 0, ORA_BC_PLANCK = 1, ORA_BC_REFLECT = 2 };
+enum { ORA_OK = 0, ORA_EINVAL = -1, ORA_ENOMEM = -2, ORA_EPOOL = -3,
+       ORA_ENOCONV = -4, ORA_ENONFINITE = -5 };
+enum { ORA_FLAG_GROUP_SIGMA = 1 };  /* flights use the group (Simpson) sigma */
+
+typedef struct {
+    int dim;              /* 1 or 2 */
+    int nx, ny;           /* ny = 1 for dim 1 */
+    double x0, x1, y0, y1;
+    int bc[4];            /* XLO, XHI, YLO, YHI */
+    double bcT[4];        /* Planckian boundary temperatures */
+    int G;
+    const double* nu;     /* G+1 ascending edges */
+    double nu_power;      /* sigma(nu) = kappa * nu^-p */
+    double c, a, eps, dt;
+    double w_ref;         /* particle energy per unit volume: target weight w_ref * V */
+    int64_t n_cap;        /* max births per (cell, group) per step */
+    uint64_t seed;
+    int64_t pool_cap;
+    int si_max_iters;
+    double si_tol;
+    int flags;
+} ora_params;
+
+typedef struct ora_sim ora_sim;
+
+typedef struct {
+    int64_t n_alive_in, n_births, n_alive_out, n_collided, n_exited;
+    int64_t n_crossings;
+    int sweeps;
+    double e_start, e_end;      /* total energy (radiation rho/c + material) */
+    double inflow_wave, inflow_eq, exit_particles, injection;
+    double residual;            /* e_end - e_start - (inflow_wave + inflow_eq - exit + injection) */
+    double si_drho, si_rho, si_dT, si_T;
+} ora_diag;
+
+ora_sim* ora_create(const ora_params* p);
+void ora_destroy(ora_sim* s);
+int ora_set_opacity(ora_sim* s, const double* kappa);            /* [ncell][G] */
+int ora_set_material(ora_sim* s, const double* cv, const double* T0,
+                     const double* Tr0, const unsigned char* pinned);
+int ora_step(ora_sim* s, int nsteps);
+int ora_get_fields(const ora_sim* s, double* rho, double* T, double* rhop);
+/* Tallies of the last step: face gross crossings [face][G][2] (x-faces, then
+ * y-faces), deposition and survivor weights [cell][G], births per (cell, g),
+ * new-particle weight per (cell, g), static source Q [cell][G]. */
+int ora_get_tallies(const ora_sim* s, double* fx, double* fy, double* dep,
+                    double* surv, int64_t* nbirth, double* wnew, double* Q);
+int64_t ora_pool_size(const ora_sim* s);
+int ora_get_pool(const ora_sim* s, double* x, double* y, double* ox, double* oy,
+                 double* nu, double* w, uint64_t* id, int32_t* cell, int32_t* g);
+int ora_set_pool(ora_sim* s, int64_t n, const double* x, const double* y,
+                 const double* ox, const double* oy, const double* nu,
+                 const double* w, const uint64_t* id, const int32_t* cell,
+                 const int32_t* g, uint64_t birth_counter, const double* rhop);
+int ora_get_diag(const ora_sim* s, ora_diag* d);
+int ora_get_counters(const ora_sim* s, uint64_t* birth_counter, int* step);
+/* Per-(cell, g) particle ledger of the last step: weight present at the
+ * start (survivors + births) of every (cell, g). */
+int ora_get_start_weights(const ora_sim* s, double* start);
+
+/* ---------------- adjoint of the frozen-tally macroscopic map ----------------
+ * With recording on, every step stores what the particle phase handed to the
+ * macroscopic solve (net particle flux, survivor density, sampled flags) plus
+ * the start-of-step state.  ora_adjoint returns dJ/dkappa for
+ * J = sum_i V_i sum_k dJdT[i] * T_i(final) (dJdT = C_v gives the material energy),
+ * holding the recorded particle outputs fixed.  ora_replay_frozen reruns the
+ * recorded steps from the recorded initial state with a new kappa and the same
+ * frozen particle outputs (used for finite differences). */
+int ora_record(ora_sim* s, int on);
+int ora_adjoint(ora_sim* s, const double* dJdT, double* grad_kappa);
+int ora_replay_frozen(ora_sim* s, const double* kappa, double* T_final);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

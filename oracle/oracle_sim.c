@@ -1,0 +1,846 @@
+/*
+ * FP64 CPU oracle -- one UGKWP time step (Algorithm 1 of the paper) for the
+ * multigroup radiative transfer system, in 1-D slabs and 2-D Cartesian meshes.
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Step n -> n+1, in the order of Algorithm 1:
+ *   coefficients    s = c sigma dt / eps^2, e^{-s}, C4, W = C4 - e^{-s}, C2 at faces
+ *   wave split      rho^h = rho^n - rho^p;  sample E = e^{-s} rho^h V  (Eq. IhpFormula)
+ *                   as N = floor(E / (w_ref V)) particles of weight E/N (Sec. 2.2, omega_k)
+ *   free flight     t_f = min(-tau ln eta, dt) for old particles (Eq. particle tf formula),
+ *                   t_f = dt for new ones; reset at every interface (Remark 1)
+ *   tallies         w^{fr,p} = sum_in - sum_out (Eq. wfrpFormula)
+ *   wave flux       F^{fr,wave} with C4 - e^{-s}, or C4 where no particle was
+ *                   sampled (Remark 3); zero slopes
+ *   implicit solve  Eq. macroSysFinal by source iteration (Appendix B, Algorithm 2)
+ *   absorb          collided particles are deleted
+ *
+ * Readings (the paper is silent or ambiguous here):
+ *  - rho is the angle-integrated group intensity; its equilibrium value is
+ *    phi_g(T) (4 pi B_g in 3-D, "2 B_g" in Appendix B).  F^eq = C2 (c/eps)^2 (1/3) d phi/dx.
+ *  - flights use sigma(nu_k, cell) = kappa_{g,cell} nu_k^-p (Remark 2); the macroscopic
+ *    terms use the Simpson group opacity (Sec. 3, group opacity).
+ *  - free flight is reset at every interior crossing; a particle ending exactly on
+ *    a face stays in its cell; crossing requires t_face < t_rem strictly; an exact
+ *    x/y tie crosses x first.
+ *  - wave flux uses the start-of-step rho^h and each upwind cell's own s.
+ *  - boundary ghosts sit one cell width away: Planckian (phi = rho^h = phi(T_b),
+ *    never sampled, sigma of the interior cell), vacuum (0), reflective (mirror;
+ *    specular reflection of particles, not tallied).
+ *  - source iteration updates T with the explicit emission phi^k of Eq.
+ *    macroSysAppendixIte and stops when max|d rho| <= tol max|rho| and
+ *    max|dT| <= tol max T over the whole mesh.  The exchange term
+ *    sigma (rho^{k+1} - phi^k) is evaluated in the algebraically identical form
+ *    sigma (b - phi^k)/(1 + lam), b = Q + (dt/V) sum_f S_f D_f (phi_nb - phi), which
+ *    does not cancel in optically thick groups.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include "oracle.h"
+
+#define XLO 0
+#define XHI 1
+#define YLO 2
+#define YHI 3
+
+typedef struct {
+    double *rho, *T, *rhop, *rhoh, *wnet; unsigned char* sampled;
+} ora_rec_step;
+
+struct ora_sim {
+    ora_params p;
+    double* nu;            /* G+1 edges */
+    double* simpson;       /* [G]: Simpson mean of nu^-p over the group */
+    int ncell;
+    double dx, dy, V;
+    int have_opacity, have_material;
+    double* kappa;         /* [ncell][G] */
+    double* cv; double* T; double* rho; double* rhop; unsigned char* pinned;
+    /* particle pool (structure of arrays) */
+    int64_t np;
+    double *px, *py, *pox, *poy, *pnu, *pw; uint64_t* pid; int32_t* pcell; int32_t* pg;
+    uint64_t nbirth;
+    int step;
+    /* tallies of the last step */
+    double *ftx, *fty, *dep, *surv, *start, *wnew, *Q;
+    int64_t* nb;
+    ora_diag diag;
+    /* adjoint recording */
+    int recording;
+    int nrec, caprec;
+    ora_rec_step* rec;
+    double *kappa0, *T0rec, *rho0rec;
+};
+
+static void* zalloc(size_t n) { void* q = calloc(n ? n : 1, 1); return q; }
+
+static double nupow(double nu, double p)
+{
+    if (p == 3.0) return 1.0 / (nu * nu * nu);
+    return pow(nu, -p);
+}
+
+ora_sim* ora_create(const ora_params* p)
+{
+    if (!p || (p->dim != 1 && p->dim != 2) || p->nx < 1 || p->ny < 1) return NULL;
+    if (p->dim == 1 && p->ny != 1) return NULL;
+    if (p->G < 1 || !p->nu) return NULL;
+    if (!(p->dt > 0) || !(p->c > 0) || !(p->eps > 0) || !(p->a > 0) || !(p->w_ref > 0)) return NULL;
+    if (!(p->x1 > p->x0)) return NULL;
+    if (p->dim == 2 && !(p->y1 > p->y0)) return NULL;
+    for (int g = 0; g < p->G; ++g) if (!(p->nu[g] > 0) || !(p->nu[g + 1] > p->nu[g])) return NULL;
+    ora_sim* s = (ora_sim*)zalloc(sizeof(ora_sim));
+    s->p = *p;
+    int G = p->G;
+    s->nu = (double*)zalloc(sizeof(double) * (G + 1));
+    memcpy(s->nu, p->nu, sizeof(double) * (G + 1));
+    s->p.nu = s->nu;
+    s->simpson = (double*)zalloc(sizeof(double) * G);
+    for (int g = 0; g < G; ++g) {
+        double nl = s->nu[g], nh = s->nu[g + 1], nm = 0.5 * (nl + nh);
+        s->simpson[g] = (nupow(nl, p->nu_power) + 4.0 * nupow(nm, p->nu_power) + nupow(nh, p->nu_power)) / 6.0;
+    }
+    s->ncell = p->nx * p->ny;
+    s->dx = (p->x1 - p->x0) / p->nx;
+    s->dy = (p->dim == 2) ? (p->y1 - p->y0) / p->ny : 1.0;
+    s->V = s->dx * s->dy;
+    size_t ncg = (size_t)s->ncell * G;
+    s->kappa = (double*)zalloc(sizeof(double) * ncg);
+    s->cv = (double*)zalloc(sizeof(double) * s->ncell);
+    s->T = (double*)zalloc(sizeof(double) * s->ncell);
+    s->rho = (double*)zalloc(sizeof(double) * ncg);
+    s->rhop = (double*)zalloc(sizeof(double) * ncg);
+    s->pinned = (unsigned char*)zalloc(s->ncell);
+    int64_t cap = p->pool_cap > 0 ? p->pool_cap : 1;
+    s->px = (double*)zalloc(sizeof(double) * cap);
+    s->py = (double*)zalloc(sizeof(double) * cap);
+    s->pox = (double*)zalloc(sizeof(double) * cap);
+    s->poy = (double*)zalloc(sizeof(double) * cap);
+    s->pnu = (double*)zalloc(sizeof(double) * cap);
+    s->pw = (double*)zalloc(sizeof(double) * cap);
+    s->pid = (uint64_t*)zalloc(sizeof(uint64_t) * cap);
+    s->pcell = (int32_t*)zalloc(sizeof(int32_t) * cap);
+    s->pg = (int32_t*)zalloc(sizeof(int32_t) * cap);
+    size_t nfx = (size_t)(p->nx + 1) * p->ny, nfy = (size_t)p->nx * (p->ny + 1);
+    s->ftx = (double*)zalloc(sizeof(double) * nfx * G * 2);
+    s->fty = (double*)zalloc(sizeof(double) * nfy * G * 2);
+    s->dep = (double*)zalloc(sizeof(double) * ncg);
+    s->surv = (double*)zalloc(sizeof(double) * ncg);
+    s->start = (double*)zalloc(sizeof(double) * ncg);
+    s->wnew = (double*)zalloc(sizeof(double) * ncg);
+    s->Q = (double*)zalloc(sizeof(double) * ncg);
+    s->nb = (int64_t*)zalloc(sizeof(int64_t) * ncg);
+    return s;
+}
+
+static void free_rec(ora_sim* s)
+{
+    for (int k = 0; k < s->nrec; ++k) {
+        free(s->rec[k].rho); free(s->rec[k].T); free(s->rec[k].rhop);
+        free(s->rec[k].rhoh); free(s->rec[k].wnet); free(s->rec[k].sampled);
+    }
+    free(s->rec); s->rec = NULL; s->nrec = 0; s->caprec = 0;
+    free(s->kappa0); s->kappa0 = NULL;
+}
+
+void ora_destroy(ora_sim* s)
+{
+    if (!s) return;
+    free_rec(s);
+    free(s->nu); free(s->simpson); free(s->kappa); free(s->cv); free(s->T); free(s->rho);
+    free(s->rhop); free(s->pinned); free(s->px); free(s->py); free(s->pox); free(s->poy);
+    free(s->pnu); free(s->pw); free(s->pid); free(s->pcell); free(s->pg); free(s->ftx);
+    free(s->fty); free(s->dep); free(s->surv); free(s->start); free(s->wnew); free(s->Q);
+    free(s->nb); free(s);
+}
+
+int ora_set_opacity(ora_sim* s, const double* kappa)
+{
+    size_t ncg = (size_t)s->ncell * s->p.G;
+    for (size_t k = 0; k < ncg; ++k) if (!(kappa[k] >= 0) || !isfinite(kappa[k])) return ORA_EINVAL;
+    memcpy(s->kappa, kappa, sizeof(double) * ncg);
+    s->have_opacity = 1;
+    return ORA_OK;
+}
+
+int ora_set_material(ora_sim* s, const double* cv, const double* T0, const double* Tr0,
+                     const unsigned char* pinned)
+{
+    int G = s->p.G;
+    for (int i = 0; i < s->ncell; ++i) {
+        if (!(cv[i] > 0) || !(T0[i] > 0) || !(Tr0[i] > 0) || !isfinite(cv[i]) || !isfinite(T0[i])
+            || !isfinite(Tr0[i])) return ORA_EINVAL;
+    }
+    for (int i = 0; i < s->ncell; ++i) {
+        s->cv[i] = cv[i];
+        s->T[i] = T0[i];
+        s->pinned[i] = pinned ? pinned[i] : 0;
+        for (int g = 0; g < G; ++g)
+            s->rho[(size_t)i * G + g] = ora_phi_group(Tr0[i], s->nu[g], s->nu[g + 1], s->p.a, s->p.c);
+    }
+    memset(s->rhop, 0, sizeof(double) * (size_t)s->ncell * G);
+    s->np = 0;
+    s->nbirth = 0;
+    s->step = 0;
+    s->have_material = 1;
+    return ORA_OK;
+}
+
+/* Opacity seen by a particle of frequency nu in (cell, g). */
+static double particle_sigma(const ora_sim* s, size_t cg, double nu, int g)
+{
+    if (s->p.flags & ORA_FLAG_GROUP_SIGMA) return s->kappa[cg] * s->simpson[g];
+    return s->kappa[cg] * nupow(nu, s->p.nu_power);
+}
+
+/* Harmonic mean face opacity (Appendix B); zero if either side is zero. */
+static double harmonic(double a, double b)
+{
+    if (a + b > 0.0) return 2.0 * a * b / (a + b);
+    return 0.0;
+}
+
+/* Ghost-cell value of phi / rho^h beyond a domain face. */
+static double ghost_phi(const ora_sim* s, int side, int g, double interior)
+{
+    int bc = s->p.bc[side];
+    if (bc == ORA_BC_PLANCK) return ora_phi_group(s->p.bcT[side], s->nu[g], s->nu[g + 1], s->p.a, s->p.c);
+    if (bc == ORA_BC_REFLECT) return interior;
+    return 0.0;
+}
+
+/* ---------------- the particle push (A3) ---------------- */
+
+typedef struct { double x, y, ox, oy, nu, w; uint64_t id; int32_t cell, g; } particle;
+
+/* Outcome: 0 survives, 1 collided (absorbed), 2 exited through the domain boundary. */
+static int push_1d(ora_sim* s, particle* pp, int is_new, double* exit_w, int64_t* ncross)
+{
+    const ora_params* P = &s->p;
+    const int G = P->G, nx = P->nx;
+    const double e2c = P->eps * P->eps / P->c, cv = P->c / P->eps, dt = P->dt;
+    int ix = pp->cell;
+    int g = pp->g;
+    double x = pp->x, mu = pp->ox;
+    uint32_t d = 0;
+    double t = 0.0, t_rem;
+    int coll;
+    double sig = particle_sigma(s, (size_t)ix * G + g, pp->nu, g);
+    if (!is_new) {
+        double u = ora_uniform(P->seed, pp->id, (uint32_t)s->step, ORA_PURPOSE_FLIGHT, d++);
+        double tau = e2c / sig;
+        double a = -tau * log(u);
+        coll = a < dt;
+        t_rem = coll ? a : dt;
+    } else {
+        coll = 0;
+        t_rem = dt;
+    }
+    for (;;) {
+        double v = cv * mu;
+        double xl = P->x0 + (double)ix * s->dx;
+        double xr = P->x0 + (double)(ix + 1) * s->dx;
+        double tf;
+        if (v > 0) tf = (xr - x) / v;
+        else if (v < 0) tf = (xl - x) / v;
+        else tf = INFINITY;
+        if (tf < t_rem) {
+            int right = v > 0;
+            x = right ? xr : xl;
+            t = t + tf;
+            int face = right ? ix + 1 : ix;
+            int dir = right ? 0 : 1;
+            int boundary = right ? (ix == nx - 1) : (ix == 0);
+            if (boundary) {
+                int side = right ? XHI : XLO;
+                if (P->bc[side] == ORA_BC_REFLECT) {
+                    mu = -mu;
+                    t_rem = t_rem - tf;
+                    continue;
+                }
+                s->ftx[((size_t)face * G + g) * 2 + dir] += pp->w;
+                *exit_w += pp->w;
+                (*ncross)++;
+                pp->x = x; pp->cell = ix; pp->ox = mu;
+                return 2;
+            }
+            s->ftx[((size_t)face * G + g) * 2 + dir] += pp->w;
+            (*ncross)++;
+            ix += right ? 1 : -1;
+            sig = particle_sigma(s, (size_t)ix * G + g, pp->nu, g);
+            double u = ora_uniform(P->seed, pp->id, (uint32_t)s->step, ORA_PURPOSE_FLIGHT, d++);
+            double tau = e2c / sig;
+            double a = -tau * log(u);
+            coll = a < dt - t;
+            t_rem = coll ? a : dt - t;
+        } else {
+            double xn = x + v * t_rem;
+            if (xn < xl) xn = xl;
+            if (xn > xr) xn = xr;
+            x = xn;
+            break;
+        }
+    }
+    pp->x = x; pp->cell = ix; pp->ox = mu;
+    return coll ? 1 : 0;
+}
+
+static int push_2d(ora_sim* s, particle* pp, int is_new, double* exit_w, int64_t* ncross)
+{
+    const ora_params* P = &s->p;
+    const int G = P->G, nx = P->nx, ny = P->ny;
+    const double e2c = P->eps * P->eps / P->c, cv = P->c / P->eps, dt = P->dt;
+    int ix = pp->cell % nx, iy = pp->cell / nx;
+    int g = pp->g;
+    double x = pp->x, y = pp->y, ox = pp->ox, oy = pp->oy;
+    uint32_t d = 0;
+    double t = 0.0, t_rem;
+    int coll;
+    double sig = particle_sigma(s, ((size_t)iy * nx + ix) * G + g, pp->nu, g);
+    if (!is_new) {
+        double u = ora_uniform(P->seed, pp->id, (uint32_t)s->step, ORA_PURPOSE_FLIGHT, d++);
+        double tau = e2c / sig;
+        double a = -tau * log(u);
+        coll = a < dt;
+        t_rem = coll ? a : dt;
+    } else {
+        coll = 0;
+        t_rem = dt;
+    }
+    for (;;) {
+        double vx = cv * ox, vy = cv * oy;
+        double xl = P->x0 + (double)ix * s->dx, xr = P->x0 + (double)(ix + 1) * s->dx;
+        double yl = P->y0 + (double)iy * s->dy, yr = P->y0 + (double)(iy + 1) * s->dy;
+        double tx, ty;
+        if (vx > 0) tx = (xr - x) / vx;
+        else if (vx < 0) tx = (xl - x) / vx;
+        else tx = INFINITY;
+        if (vy > 0) ty = (yr - y) / vy;
+        else if (vy < 0) ty = (yl - y) / vy;
+        else ty = INFINITY;
+        int xaxis = tx <= ty;
+        double tf = xaxis ? tx : ty;
+        if (tf < t_rem) {
+            t = t + tf;
+            int pos, boundary, side;
+            size_t bin;
+            if (xaxis) {
+                pos = vx > 0;
+                x = pos ? xr : xl;
+                double yn = y + vy * tf;
+                if (yn < yl) yn = yl;
+                if (yn > yr) yn = yr;
+                y = yn;
+                boundary = pos ? (ix == nx - 1) : (ix == 0);
+                side = pos ? XHI : XLO;
+                int face = iy * (nx + 1) + (pos ? ix + 1 : ix);
+                bin = ((size_t)face * G + g) * 2 + (pos ? 0 : 1);
+            } else {
+                pos = vy > 0;
+                y = pos ? yr : yl;
+                double xn = x + vx * tf;
+                if (xn < xl) xn = xl;
+                if (xn > xr) xn = xr;
+                x = xn;
+                boundary = pos ? (iy == ny - 1) : (iy == 0);
+                side = pos ? YHI : YLO;
+                int face = (pos ? iy + 1 : iy) * nx + ix;
+                bin = ((size_t)face * G + g) * 2 + (pos ? 0 : 1);
+            }
+            double* tally = xaxis ? s->ftx : s->fty;
+            if (boundary) {
+                if (P->bc[side] == ORA_BC_REFLECT) {
+                    if (xaxis) ox = -ox; else oy = -oy;
+                    t_rem = t_rem - tf;
+                    continue;
+                }
+                tally[bin] += pp->w;
+                *exit_w += pp->w;
+                (*ncross)++;
+                pp->x = x; pp->y = y; pp->ox = ox; pp->oy = oy; pp->cell = iy * nx + ix;
+                return 2;
+            }
+            tally[bin] += pp->w;
+            (*ncross)++;
+            if (xaxis) ix += pos ? 1 : -1; else iy += pos ? 1 : -1;
+            sig = particle_sigma(s, ((size_t)iy * nx + ix) * G + g, pp->nu, g);
+            double u = ora_uniform(P->seed, pp->id, (uint32_t)s->step, ORA_PURPOSE_FLIGHT, d++);
+            double tau = e2c / sig;
+            double a = -tau * log(u);
+            coll = a < dt - t;
+            t_rem = coll ? a : dt - t;
+        } else {
+            double xn = x + vx * t_rem, yn = y + vy * t_rem;
+            if (xn < xl) xn = xl;
+            if (xn > xr) xn = xr;
+            if (yn < yl) yn = yl;
+            if (yn > yr) yn = yr;
+            x = xn; y = yn;
+            break;
+        }
+    }
+    pp->x = x; pp->y = y; pp->ox = ox; pp->oy = oy; pp->cell = iy * nx + ix;
+    return coll ? 1 : 0;
+}
+
+/* ---------------- the macroscopic part ---------------- */
+
+/* Per-face diffusion coefficient D = -(c/eps)^2 (1/3) C2(s_f) / h >= 0 so that the
+ * equilibrium flux through a face with normal +n is -D (phi_next - phi_this). */
+static double face_D(const ora_sim* s, double sigf, double h)
+{
+    const ora_params* P = &s->p;
+    double sf = P->c * sigf * P->dt / (P->eps * P->eps);
+    double c2 = P->dt * ora_coef_c2_over_dt(sf);
+    return -(P->c * P->c / (3.0 * P->eps * P->eps)) * c2 / h;
+}
+
+/* Neighbour description for one of the 2*dim faces of a cell. */
+typedef struct { int nb; int side; double S; double h; int tx, ty; } nbface;
+
+static int cell_faces(const ora_sim* s, int i, nbface f[4])
+{
+    const ora_params* P = &s->p;
+    int nx = P->nx, ny = P->ny, ix = i % nx, iy = i / nx;
+    int n = 0;
+    f[n].nb = ix > 0 ? i - 1 : -1; f[n].side = XLO; f[n].S = s->dy; f[n].h = s->dx; n++;
+    f[n].nb = ix < nx - 1 ? i + 1 : -1; f[n].side = XHI; f[n].S = s->dy; f[n].h = s->dx; n++;
+    if (P->dim == 2) {
+        f[n].nb = iy > 0 ? i - nx : -1; f[n].side = YLO; f[n].S = s->dx; f[n].h = s->dy; n++;
+        f[n].nb = iy < ny - 1 ? i + nx : -1; f[n].side = YHI; f[n].S = s->dx; f[n].h = s->dy; n++;
+    }
+    return n;
+}
+
+/* Gross particle crossing into / out of (cell i, group g) during the step. */
+static void cell_particle_flux(const ora_sim* s, int i, int g, double* in, double* out)
+{
+    const ora_params* P = &s->p;
+    int nx = P->nx, G = P->G, ix = i % nx, iy = i / nx;
+    size_t fl = (size_t)iy * (nx + 1) + ix, fr = fl + 1;
+    double a_in = s->ftx[(fl * G + g) * 2 + 0] + s->ftx[(fr * G + g) * 2 + 1];
+    double a_out = s->ftx[(fl * G + g) * 2 + 1] + s->ftx[(fr * G + g) * 2 + 0];
+    if (P->dim == 2) {
+        size_t fb = (size_t)iy * nx + ix, ft = (size_t)(iy + 1) * nx + ix;
+        a_in += s->fty[(fb * G + g) * 2 + 0] + s->fty[(ft * G + g) * 2 + 1];
+        a_out += s->fty[(fb * G + g) * 2 + 1] + s->fty[(ft * G + g) * 2 + 0];
+    }
+    *in = a_in; *out = a_out;
+}
+
+static void rec_push(ora_sim* s, const double* rhoh, const double* wnet, const unsigned char* sampled)
+{
+    size_t ncg = (size_t)s->ncell * s->p.G;
+    if (s->nrec == s->caprec) {
+        s->caprec = s->caprec ? 2 * s->caprec : 16;
+        s->rec = (ora_rec_step*)realloc(s->rec, sizeof(ora_rec_step) * s->caprec);
+    }
+    ora_rec_step* r = &s->rec[s->nrec++];
+    r->rho = (double*)malloc(sizeof(double) * ncg); memcpy(r->rho, s->rho, sizeof(double) * ncg);
+    r->T = (double*)malloc(sizeof(double) * s->ncell); memcpy(r->T, s->T, sizeof(double) * s->ncell);
+    r->rhop = (double*)malloc(sizeof(double) * ncg); memcpy(r->rhop, s->rhop, sizeof(double) * ncg);
+    r->rhoh = (double*)malloc(sizeof(double) * ncg); memcpy(r->rhoh, rhoh, sizeof(double) * ncg);
+    r->wnet = (double*)malloc(sizeof(double) * ncg); memcpy(r->wnet, wnet, sizeof(double) * ncg);
+    r->sampled = (unsigned char*)malloc(ncg); memcpy(r->sampled, sampled, ncg);
+}
+
+static int step_once(ora_sim* s)
+{
+    const ora_params* P = &s->p;
+    const int G = P->G, nc = s->ncell;
+    const size_t ncg = (size_t)nc * G;
+    const double V = s->V, dt = P->dt, c = P->c, eps = P->eps;
+    ora_diag dg;
+    memset(&dg, 0, sizeof(dg));
+
+    /* ---- coefficients (A0) ---- */
+    double* sig = (double*)malloc(sizeof(double) * ncg);
+    double* sv = (double*)malloc(sizeof(double) * ncg);
+    double* es = (double*)malloc(sizeof(double) * ncg);
+    double* rhoh = (double*)malloc(sizeof(double) * ncg);
+    double* A = (double*)malloc(sizeof(double) * ncg);
+    double* wnet = (double*)malloc(sizeof(double) * ncg);
+    unsigned char* sampled = (unsigned char*)malloc(ncg);
+    for (int i = 0; i < nc; ++i)
+        for (int g = 0; g < G; ++g) {
+            size_t k = (size_t)i * G + g;
+            sig[k] = s->kappa[k] * s->simpson[g];
+            sv[k] = c * sig[k] * dt / (eps * eps);
+            es[k] = exp(-sv[k]);
+        }
+
+    /* ---- wave split and sample counts (A1) ---- */
+    int64_t total = 0;
+    for (size_t k = 0; k < ncg; ++k) {
+        rhoh[k] = s->rho[k] - s->rhop[k];
+        double e_over_v = es[k] * rhoh[k];
+        double E = e_over_v * V;
+        int64_t N = 0;
+        if (E > 0.0) {
+            double q = e_over_v / P->w_ref;
+            if (q >= (double)P->n_cap) N = P->n_cap;
+            else N = (int64_t)floor(q);
+        }
+        s->nb[k] = N;
+        s->wnew[k] = N >= 1 ? E / (double)N : 0.0;
+        sampled[k] = N >= 1;
+        total += N;
+    }
+    int64_t n_old = s->np;
+    if (n_old + total > P->pool_cap) {
+        free(sig); free(sv); free(es); free(rhoh); free(A); free(wnet); free(sampled);
+        return ORA_EPOOL;
+    }
+    dg.n_alive_in = n_old;
+    dg.n_births = total;
+
+    /* ---- sample the collisionless wave particles (A2) ---- */
+    int64_t slot = n_old;
+    uint64_t id = s->nbirth;
+    for (int i = 0; i < nc; ++i) {
+        int ix = i % P->nx, iy = i / P->nx;
+        double xl = P->x0 + (double)ix * s->dx;
+        double yl = P->y0 + (double)iy * s->dy;
+        for (int g = 0; g < G; ++g) {
+            size_t k = (size_t)i * G + g;
+            if (s->nb[k] == 0) continue;
+            double nl = s->nu[g], nh = s->nu[g + 1];
+            double beta = ora_freq_slope(nl, nh, s->T[i]);
+            for (int64_t j = 0; j < s->nb[k]; ++j, ++id, ++slot) {
+                uint32_t st = (uint32_t)s->step;
+                s->px[slot] = xl + ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 0) * s->dx;
+                if (P->dim == 1) {
+                    s->pox[slot] = 2.0 * ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 1) - 1.0;
+                    s->py[slot] = 0.0;
+                    s->poy[slot] = 0.0;
+                    s->pnu[slot] = ora_sample_nu(nl, nh, beta, ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 2));
+                } else {
+                    s->py[slot] = yl + ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 1) * s->dy;
+                    double oz = 2.0 * ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 2) - 1.0;
+                    double psi = 6.283185307179586 * ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 3);
+                    double sn = sqrt(1.0 - oz * oz);
+                    s->pox[slot] = sn * cos(psi);
+                    s->poy[slot] = sn * sin(psi);
+                    s->pnu[slot] = ora_sample_nu(nl, nh, beta, ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 4));
+                }
+                s->pw[slot] = s->wnew[k];
+                s->pid[slot] = id;
+                s->pcell[slot] = i;
+                s->pg[slot] = g;
+            }
+        }
+    }
+    int64_t n_all = n_old + total;
+
+    /* ---- free transport of every particle (A3) ---- */
+    size_t nfx = (size_t)(P->nx + 1) * P->ny, nfy = (size_t)P->nx * (P->ny + 1);
+    memset(s->ftx, 0, sizeof(double) * nfx * G * 2);
+    memset(s->fty, 0, sizeof(double) * nfy * G * 2);
+    memset(s->dep, 0, sizeof(double) * ncg);
+    memset(s->surv, 0, sizeof(double) * ncg);
+    memset(s->start, 0, sizeof(double) * ncg);
+    double exit_w = 0.0;
+    int64_t ncross = 0, keep = 0;
+    for (int64_t k = 0; k < n_all; ++k) {
+        particle pp = { s->px[k], s->py[k], s->pox[k], s->poy[k], s->pnu[k], s->pw[k],
+                        s->pid[k], s->pcell[k], s->pg[k] };
+        s->start[(size_t)pp.cell * G + pp.g] += pp.w;
+        int out = (P->dim == 1) ? push_1d(s, &pp, k >= n_old, &exit_w, &ncross)
+                                : push_2d(s, &pp, k >= n_old, &exit_w, &ncross);
+        size_t kk = (size_t)pp.cell * G + pp.g;
+        if (out == 1) { s->dep[kk] += pp.w; dg.n_collided++; }
+        else if (out == 2) { dg.n_exited++; }
+        else {
+            s->surv[kk] += pp.w;
+            s->px[keep] = pp.x; s->py[keep] = pp.y; s->pox[keep] = pp.ox; s->poy[keep] = pp.oy;
+            s->pnu[keep] = pp.nu; s->pw[keep] = pp.w; s->pid[keep] = pp.id;
+            s->pcell[keep] = pp.cell; s->pg[keep] = pp.g;
+            keep++;
+        }
+    }
+    dg.n_alive_out = keep;
+    dg.n_crossings = ncross;
+    dg.exit_particles = exit_w / c;
+
+    /* ---- wave free-transport flux and the static source Q (A4) ---- */
+    const double cq = c / (4.0 * eps);
+    for (size_t k = 0; k < ncg; ++k) A[k] = sampled[k] ? ora_coef_w(sv[k]) : ora_coef_c4(sv[k]);
+    double inflow_wave = 0.0;
+    for (int i = 0; i < nc; ++i) {
+        nbface f[4];
+        int nf = cell_faces(s, i, f);
+        for (int g = 0; g < G; ++g) {
+            size_t k = (size_t)i * G + g;
+            double fsum = 0.0;   /* sum over faces of S * (flux into the cell) */
+            for (int q = 0; q < nf; ++q) {
+                /* outward sign: the LO faces have inward normal +axis */
+                int lo = (f[q].side == XLO || f[q].side == YLO);
+                double here = A[k] * rhoh[k];
+                double there;
+                if (f[q].nb >= 0) {
+                    size_t kn = (size_t)f[q].nb * G + g;
+                    there = A[kn] * rhoh[kn];
+                } else {
+                    int bc = P->bc[f[q].side];
+                    if (bc == ORA_BC_REFLECT) continue;
+                    there = (bc == ORA_BC_PLANCK)
+                                ? ora_coef_c4(sv[k]) * ghost_phi(s, f[q].side, g, 0.0)
+                                : 0.0;
+                }
+                /* flux along +axis through the face: cq (A_left rho^h_left - A_right rho^h_right) */
+                double Fpos = lo ? cq * (there - here) : cq * (here - there);
+                double Fin = lo ? Fpos : -Fpos;
+                fsum += f[q].S * Fin;
+                if (f[q].nb < 0) inflow_wave += dt * f[q].S * Fin / c;
+            }
+            double in, out;
+            cell_particle_flux(s, i, g, &in, &out);
+            wnet[k] = in - out;
+            s->Q[k] = s->rho[k] + (dt / V) * fsum + wnet[k] / V;
+        }
+    }
+    dg.inflow_wave = inflow_wave;
+
+    /* ---- source iteration for Eq. macroSysFinal (A5; Appendix B, Algorithm 2) ---- */
+    double* lam = sv;    /* c sigma dt / eps^2 */
+    double* phi = (double*)malloc(sizeof(double) * ncg);
+    double* phin = (double*)malloc(sizeof(double) * ncg);
+    double* rk = (double*)malloc(sizeof(double) * ncg);
+    double* Tk = (double*)malloc(sizeof(double) * nc);
+    double* Tn1 = (double*)malloc(sizeof(double) * nc);
+    double* rn1 = (double*)malloc(sizeof(double) * ncg);
+    double* em = (double*)malloc(sizeof(double) * ncg);
+    /* face coefficients D for the 2*dim faces of every cell */
+    double* Df = (double*)malloc(sizeof(double) * ncg * 4);
+    for (int i = 0; i < nc; ++i) {
+        nbface f[4];
+        int nf = cell_faces(s, i, f);
+        for (int g = 0; g < G; ++g) {
+            size_t k = (size_t)i * G + g;
+            for (int q = 0; q < nf; ++q) {
+                double sf = f[q].nb >= 0 ? harmonic(sig[k], sig[(size_t)f[q].nb * G + g]) : sig[k];
+                Df[k * 4 + q] = face_D(s, sf, f[q].h);
+            }
+        }
+    }
+    for (int i = 0; i < nc; ++i) {
+        Tk[i] = s->T[i];
+        for (int g = 0; g < G; ++g)
+            phi[(size_t)i * G + g] = ora_phi_group(s->T[i], s->nu[g], s->nu[g + 1], P->a, c);
+    }
+    memcpy(rk, s->rho, sizeof(double) * ncg);
+    int converged = 0, sweeps = 0, bad = 0;
+    double drho = 0, mrho = 0, dT = 0, mT = 0;
+    for (int it = 0; it < P->si_max_iters; ++it) {
+        drho = mrho = dT = mT = 0.0;
+        for (int i = 0; i < nc; ++i) {
+            nbface f[4];
+            int nf = cell_faces(s, i, f);
+            double sum = 0.0;
+            for (int g = 0; g < G; ++g) {
+                size_t k = (size_t)i * G + g;
+                double lap = 0.0;
+                for (int q = 0; q < nf; ++q) {
+                    double pn = f[q].nb >= 0 ? phi[(size_t)f[q].nb * G + g]
+                                             : ghost_phi(s, f[q].side, g, phi[k]);
+                    lap += f[q].S * Df[k * 4 + q] * (pn - phi[k]);
+                }
+                /* rho^{k+1} = (b + lam phi^k)/(1 + lam) with b = Q + (dt/V) lap; the
+                 * material exchange sigma (rho^{k+1} - phi^k) is evaluated through the
+                 * identical expression sigma (b - phi^k)/(1 + lam), which does not cancel
+                 * when lam = c sigma dt / eps^2 is large. */
+                double b = s->Q[k] + (dt / V) * lap;
+                double r = (b + lam[k] * phi[k]) / (1.0 + lam[k]);
+                rn1[k] = r;
+                em[k] = (b - phi[k]) / (1.0 + lam[k]);
+                sum += sig[k] * em[k];
+                double dr = fabs(r - rk[k]);
+                if (dr > drho || dr != dr) drho = dr;
+                if (fabs(r) > mrho) mrho = fabs(r);
+            }
+            double Tnew = s->pinned[i] ? s->T[i] : s->T[i] + (dt / (eps * eps * s->cv[i])) * sum;
+            if (!(Tnew > 0.0) || !isfinite(Tnew)) bad = 1;
+            Tn1[i] = Tnew;
+            double dd = fabs(Tnew - Tk[i]);
+            if (dd > dT || dd != dd) dT = dd;
+            if (Tnew > mT) mT = Tnew;
+        }
+        sweeps = it + 1;
+        if (bad) break;
+        /* energy bookkeeping uses the phi^k that produced this sweep */
+        if (drho <= P->si_tol * mrho && dT <= P->si_tol * mT) {
+            converged = 1;
+        }
+        if (converged || it + 1 == P->si_max_iters) break;
+        for (int i = 0; i < nc; ++i)
+            for (int g = 0; g < G; ++g)
+                phin[(size_t)i * G + g] = ora_phi_group(Tn1[i], s->nu[g], s->nu[g + 1], P->a, c);
+        memcpy(phi, phin, sizeof(double) * ncg);
+        memcpy(rk, rn1, sizeof(double) * ncg);
+        memcpy(Tk, Tn1, sizeof(double) * nc);
+    }
+    int status = ORA_OK;
+    if (bad) status = ORA_ENONFINITE;
+    else if (!converged) status = ORA_ENOCONV;
+
+    if (status == ORA_OK) {
+        /* boundary equilibrium inflow and pinned-cell injection with the final phi^k */
+        double inflow_eq = 0.0, inj = 0.0;
+        for (int i = 0; i < nc; ++i) {
+            nbface f[4];
+            int nf = cell_faces(s, i, f);
+            for (int g = 0; g < G; ++g) {
+                size_t k = (size_t)i * G + g;
+                for (int q = 0; q < nf; ++q) {
+                    if (f[q].nb >= 0) continue;
+                    double pn = ghost_phi(s, f[q].side, g, phi[k]);
+                    inflow_eq += dt * f[q].S * Df[k * 4 + q] * (pn - phi[k]) / c;
+                }
+                if (s->pinned[i]) inj -= V * (dt * sig[k] / (eps * eps)) * em[k];
+            }
+        }
+        double e0 = 0.0, e1 = 0.0;
+        for (int i = 0; i < nc; ++i) {
+            double r0 = 0.0, r1 = 0.0;
+            for (int g = 0; g < G; ++g) { r0 += s->rho[(size_t)i * G + g]; r1 += rn1[(size_t)i * G + g]; }
+            e0 += V * (r0 / c + s->cv[i] * s->T[i]);
+            e1 += V * (r1 / c + s->cv[i] * Tn1[i]);
+        }
+        dg.inflow_eq = inflow_eq;
+        dg.injection = inj;
+        dg.e_start = e0;
+        dg.e_end = e1;
+        dg.residual = e1 - e0 - (dg.inflow_wave + inflow_eq - dg.exit_particles + inj);
+        dg.sweeps = sweeps;
+        dg.si_drho = drho; dg.si_rho = mrho; dg.si_dT = dT; dg.si_T = mT;
+
+        if (s->recording) rec_push(s, rhoh, wnet, sampled);
+
+        /* ---- commit (absorb collided particles: already dropped from the pool) ---- */
+        memcpy(s->rho, rn1, sizeof(double) * ncg);
+        memcpy(s->T, Tn1, sizeof(double) * nc);
+        for (size_t k = 0; k < ncg; ++k) s->rhop[k] = s->surv[k] / V;
+        s->np = keep;
+        s->nbirth += (uint64_t)total;
+        s->step++;
+        s->diag = dg;
+    }
+    free(sig); free(sv); free(es); free(rhoh); free(A); free(wnet); free(sampled);
+    free(phi); free(phin); free(rk); free(Tk); free(Tn1); free(rn1); free(em); free(Df);
+    return status;
+}
+
+int ora_step(ora_sim* s, int nsteps)
+{
+    if (!s->have_opacity || !s->have_material) return ORA_EINVAL;
+    for (int n = 0; n < nsteps; ++n) {
+        int st = step_once(s);
+        if (st != ORA_OK) return st;
+    }
+    return ORA_OK;
+}
+
+int ora_get_fields(const ora_sim* s, double* rho, double* T, double* rhop)
+{
+    size_t ncg = (size_t)s->ncell * s->p.G;
+    if (rho) memcpy(rho, s->rho, sizeof(double) * ncg);
+    if (T) memcpy(T, s->T, sizeof(double) * s->ncell);
+    if (rhop) memcpy(rhop, s->rhop, sizeof(double) * ncg);
+    return ORA_OK;
+}
+
+int ora_get_tallies(const ora_sim* s, double* fx, double* fy, double* dep, double* surv,
+                    int64_t* nbirth, double* wnew, double* Q)
+{
+    const ora_params* P = &s->p;
+    size_t ncg = (size_t)s->ncell * P->G;
+    size_t nfx = (size_t)(P->nx + 1) * P->ny, nfy = (size_t)P->nx * (P->ny + 1);
+    if (fx) memcpy(fx, s->ftx, sizeof(double) * nfx * P->G * 2);
+    if (fy) memcpy(fy, s->fty, sizeof(double) * nfy * P->G * 2);
+    if (dep) memcpy(dep, s->dep, sizeof(double) * ncg);
+    if (surv) memcpy(surv, s->surv, sizeof(double) * ncg);
+    if (nbirth) memcpy(nbirth, s->nb, sizeof(int64_t) * ncg);
+    if (wnew) memcpy(wnew, s->wnew, sizeof(double) * ncg);
+    if (Q) memcpy(Q, s->Q, sizeof(double) * ncg);
+    return ORA_OK;
+}
+
+int ora_get_start_weights(const ora_sim* s, double* start)
+{
+    memcpy(start, s->start, sizeof(double) * (size_t)s->ncell * s->p.G);
+    return ORA_OK;
+}
+
+int64_t ora_pool_size(const ora_sim* s) { return s->np; }
+
+int ora_get_pool(const ora_sim* s, double* x, double* y, double* ox, double* oy, double* nu,
+                 double* w, uint64_t* id, int32_t* cell, int32_t* g)
+{
+    size_t n = (size_t)s->np;
+    if (x) memcpy(x, s->px, sizeof(double) * n);
+    if (y) memcpy(y, s->py, sizeof(double) * n);
+    if (ox) memcpy(ox, s->pox, sizeof(double) * n);
+    if (oy) memcpy(oy, s->poy, sizeof(double) * n);
+    if (nu) memcpy(nu, s->pnu, sizeof(double) * n);
+    if (w) memcpy(w, s->pw, sizeof(double) * n);
+    if (id) memcpy(id, s->pid, sizeof(uint64_t) * n);
+    if (cell) memcpy(cell, s->pcell, sizeof(int32_t) * n);
+    if (g) memcpy(g, s->pg, sizeof(int32_t) * n);
+    return ORA_OK;
+}
+
+int ora_set_pool(ora_sim* s, int64_t n, const double* x, const double* y, const double* ox,
+                 const double* oy, const double* nu, const double* w, const uint64_t* id,
+                 const int32_t* cell, const int32_t* g, uint64_t birth_counter, const double* rhop)
+{
+    if (n < 0 || n > s->p.pool_cap) return ORA_EPOOL;
+    size_t k = (size_t)n;
+    memcpy(s->px, x, sizeof(double) * k);
+    if (y) memcpy(s->py, y, sizeof(double) * k); else memset(s->py, 0, sizeof(double) * k);
+    memcpy(s->pox, ox, sizeof(double) * k);
+    if (oy) memcpy(s->poy, oy, sizeof(double) * k); else memset(s->poy, 0, sizeof(double) * k);
+    memcpy(s->pnu, nu, sizeof(double) * k);
+    memcpy(s->pw, w, sizeof(double) * k);
+    memcpy(s->pid, id, sizeof(uint64_t) * k);
+    memcpy(s->pcell, cell, sizeof(int32_t) * k);
+    memcpy(s->pg, g, sizeof(int32_t) * k);
+    s->np = n;
+    s->nbirth = birth_counter;
+    if (rhop) memcpy(s->rhop, rhop, sizeof(double) * (size_t)s->ncell * s->p.G);
+    return ORA_OK;
+}
+
+int ora_get_diag(const ora_sim* s, ora_diag* d) { *d = s->diag; return ORA_OK; }
+
+int ora_get_counters(const ora_sim* s, uint64_t* birth_counter, int* step)
+{
+    if (birth_counter) *birth_counter = s->nbirth;
+    if (step) *step = s->step;
+    return ORA_OK;
+}
+
+/* Recording hooks used by the adjoint (oracle_adjoint.c). */
+int ora_record(ora_sim* s, int on)
+{
+    free_rec(s);
+    s->recording = on ? 1 : 0;
+    if (on) {
+        size_t ncg = (size_t)s->ncell * s->p.G;
+        s->kappa0 = (double*)malloc(sizeof(double) * ncg);
+        memcpy(s->kappa0, s->kappa, sizeof(double) * ncg);
+    }
+    return ORA_OK;
+}
+
+/* Accessors for oracle_adjoint.c (same translation unit family, not exported in the header). */
+int ora__nrec(const ora_sim* s) { return s->nrec; }
+const ora_rec_step* ora__rec(const ora_sim* s, int k) { return &s->rec[k]; }
+const ora_params* ora__params(const ora_sim* s) { return &s->p; }
+const double* ora__simpson(const ora_sim* s) { return s->simpson; }
+const double* ora__cv(const ora_sim* s) { return s->cv; }
+const unsigned char* ora__pinned(const ora_sim* s) { return s->pinned; }
+double ora__V(const ora_sim* s) { return s->V; }
+double ora__dx(const ora_sim* s) { return s->dx; }
+double ora__dy(const ora_sim* s) { return s->dy; }

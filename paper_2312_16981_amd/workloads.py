@@ -1,0 +1,159 @@
+"""Seeded synthetic problem definitions (inputs only, no method arithmetic).
+
+Both the GPU library and the CPU oracle take these as inputs.  The shapes,
+sizes and value distributions follow the paper's workloads (Sec. 3):
+log-spaced frequency groups (Sec. 3, group set-up), opacities of the form
+kappa * nu^-3 (Eq. sigmaMarsharkMF without the temperature factor), cold
+initial state with a Planckian incident boundary (Sec. 3.1), sharp opacity
+jumps (Sec. 3.2, 3.3), and a 2-D block-structured medium with a central
+source (Sec. 3.5, whose block layout is not printed, so a checkerboard
+lattice stands in for it).  Nothing here comes from the paper's figures.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+from typing import List, Optional
+
+import numpy as np
+
+BC_VACUUM, BC_PLANCK, BC_REFLECT = 0, 1, 2
+FLAG_GROUP_SIGMA = 1
+
+
+@dataclass
+class Problem:
+    name: str
+    dim: int
+    nx: int
+    ny: int
+    x0: float
+    x1: float
+    y0: float
+    y1: float
+    bc: List[int]            # XLO, XHI, YLO, YHI
+    bcT: List[float]
+    nu_edges: np.ndarray     # G+1 ascending
+    kappa: np.ndarray        # [ncell, G]
+    cv: np.ndarray           # [ncell]
+    T0: np.ndarray           # [ncell]
+    Tr0: np.ndarray          # [ncell]
+    pinned: np.ndarray       # [ncell] uint8
+    dt: float
+    steps: int
+    w_ref: float
+    nu_power: float = 3.0
+    c: float = 1.0
+    a: float = 1.0
+    eps: float = 1.0
+    n_cap: int = 1 << 20
+    seed: int = 0
+    pool_cap: int = 1 << 20
+    si_max_iters: int = 200
+    si_tol: float = 1e-13
+    flags: int = 0
+
+    @property
+    def G(self) -> int:
+        return len(self.nu_edges) - 1
+
+    @property
+    def ncell(self) -> int:
+        return self.nx * self.ny
+
+    def with_(self, **kw) -> "Problem":
+        return replace(self, **kw)
+
+
+def log_edges(numin: float, numax: float, G: int) -> np.ndarray:
+    """Log-spaced group edges numin * (numax/numin)^(j/G), j = 0..G."""
+    j = np.arange(G + 1, dtype=np.float64)
+    e = numin * (numax / numin) ** (j / G)
+    e[0], e[-1] = numin, numax
+    return e
+
+
+def slab(nx: int, G: int, kappa_of_x, *, dt: float, steps: int, w_ref: float,
+         numin: float = 0.01, numax: float = 10.0, T0: float = 1e-3, Tb: float = 1.0,
+         bc_right: int = BC_VACUUM, pool_cap: int = 1 << 20, seed: int = 0,
+         name: str = "slab", **kw) -> Problem:
+    """1-D slab on [0,1]: Planckian incident left boundary at Tb, cold interior."""
+    xc = (np.arange(nx) + 0.5) / nx
+    kap = np.asarray(kappa_of_x(xc), dtype=np.float64)
+    kappa = np.repeat(kap[:, None], G, axis=1).copy()
+    return Problem(name=name, dim=1, nx=nx, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
+                   bc=[BC_PLANCK, bc_right, BC_VACUUM, BC_VACUUM], bcT=[Tb, 0.0, 0.0, 0.0],
+                   nu_edges=log_edges(numin, numax, G), kappa=kappa,
+                   cv=np.ones(nx), T0=np.full(nx, T0), Tr0=np.full(nx, T0),
+                   pinned=np.zeros(nx, np.uint8), dt=dt, steps=steps, w_ref=w_ref,
+                   pool_cap=pool_cap, seed=seed, **kw)
+
+
+def c1_marshak_like(**kw) -> Problem:
+    """100 cells x 10 groups, kappa = 1 (sigma = nu^-3), dt = 1e-3, 100 steps."""
+    p = dict(dt=1e-3, steps=100, w_ref=2e-5, pool_cap=1 << 19, name="slab100_g10")
+    p.update(kw)
+    return slab(100, 10, lambda x: np.ones_like(x), **p)
+
+
+def c2_two_material(nx: int = 2000, G: int = 64, **kw) -> Problem:
+    """Two-material slab: kappa = 0.01 for x < 0.5, 1000 for x >= 0.5 (cell-centre rule)."""
+    p = dict(dt=1e-4, steps=1000, w_ref=4e-6, pool_cap=1 << 25, name=f"slab{nx}_g{G}_jump")
+    p.update(kw)
+    return slab(nx, G, lambda x: np.where(x < 0.5, 0.01, 1000.0), **p)
+
+
+def c3_lattice(n: int = 256, G: int = 32, **kw) -> Problem:
+    """2-D lattice on [0,7]^2: unit squares (a,b), absorber kappa=100 iff a+b odd,
+    background kappa=1; cells with centres in [3,4]^2 pinned at T = 1; vacuum walls."""
+    L = 7.0
+    xc = (np.arange(n) + 0.5) * (L / n)
+    X, Y = np.meshgrid(xc, xc, indexing="xy")     # [iy][ix]
+    a = np.floor(X).astype(int)
+    b = np.floor(Y).astype(int)
+    kap = np.where((a + b) % 2 == 1, 100.0, 1.0).reshape(-1)
+    src = ((X >= 3.0) & (X <= 4.0) & (Y >= 3.0) & (Y <= 4.0)).reshape(-1)
+    ncell = n * n
+    T0 = np.full(ncell, 1e-3)
+    T0[src] = 1.0
+    p = dict(dt=1e-3, steps=500, w_ref=2e-4, pool_cap=1 << 26, seed=0)
+    p.update(kw)
+    return Problem(name=f"lattice{n}x{n}_g{G}", dim=2, nx=n, ny=n, x0=0.0, x1=L, y0=0.0, y1=L,
+                   bc=[BC_VACUUM] * 4, bcT=[0.0] * 4, nu_edges=log_edges(0.01, 10.0, G),
+                   kappa=np.repeat(kap[:, None], G, axis=1).copy(), cv=np.ones(ncell), T0=T0,
+                   Tr0=np.full(ncell, 1e-3), pinned=src.astype(np.uint8), **p)
+
+
+def c5_lognormal(n: int = 128, G: int = 16, **kw) -> Problem:
+    """2-D [0,1]^2, per-cell kappa = exp(1.5 Z), Z ~ N(0,1) (numpy default_rng(7)),
+    Planckian left wall at T = 1, other walls vacuum."""
+    rng = np.random.default_rng(7)
+    Z = rng.standard_normal(n * n)
+    kap = np.exp(1.5 * Z)
+    ncell = n * n
+    p = dict(dt=1e-3, steps=100, w_ref=1e-4, pool_cap=1 << 24, seed=0)
+    p.update(kw)
+    return Problem(name=f"lognormal{n}x{n}_g{G}", dim=2, nx=n, ny=n, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
+                   bc=[BC_PLANCK, BC_VACUUM, BC_VACUUM, BC_VACUUM], bcT=[1.0, 0.0, 0.0, 0.0],
+                   nu_edges=log_edges(0.01, 10.0, G),
+                   kappa=np.repeat(kap[:, None], G, axis=1).copy(), cv=np.ones(ncell),
+                   T0=np.full(ncell, 1e-3), Tr0=np.full(ncell, 1e-3),
+                   pinned=np.zeros(ncell, np.uint8), **p)
+
+
+def c4_batch(n_inst: int = 512, nx_range=(64, 4096), groups=(16, 32, 64), steps: int = 200,
+             dt: float = 1e-4, w_ref: float = 2e-5, key: int = 1) -> List[Problem]:
+    """Independent 1-D slabs with uneven sizes: nx ~ U{64..4096}, G in {16,32,64},
+    kappa_L, kappa_R ~ logU[1e-2, 1e3], jump position ~ U(0,1); instance seeds 0..n-1.
+    Instance parameters come from numpy's Philox bit generator with the given key."""
+    rng = np.random.Generator(np.random.Philox(key=key))
+    out = []
+    for k in range(n_inst):
+        nx = int(rng.integers(nx_range[0], nx_range[1] + 1))
+        G = int(rng.choice(np.asarray(groups)))
+        kl, kr = 10.0 ** rng.uniform(-2.0, 3.0, size=2)
+        xj = float(rng.uniform(0.0, 1.0))
+        pr = slab(nx, G, lambda x, kl=kl, kr=kr, xj=xj: np.where(x < xj, kl, kr),
+                  dt=dt, steps=steps, w_ref=w_ref, seed=k, pool_cap=1 << 20,
+                  name=f"inst{k}_nx{nx}_g{G}")
+        out.append(pr)
+    return out
