@@ -1,0 +1,198 @@
+/*
+ * ugkwp.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot
+ * path of the unified gas-kinetic wave-particle (UGKWP) method for
+ * frequency-dependent radiative transfer (Yang, Zhu, Liu & Xu, arXiv 2312.16981).
+ *
+ * One call to ugkwp_step advances every problem instance held by a context by
+ * one time step of the paper's Algorithm 1:
+ *   - sample the collisionless particles of each cell's wave part
+ *     (Eq. IhpFormula, weights from Sec. 2.2) with linear-frequency sampling
+ *     (Eqs. Blinear, kg; Appendix A);
+ *   - draw free-flight times t_f = min(-tau ln eta, dt) (Eq. particle tf formula),
+ *     stream the particles, reset t_f at every interface crossing (Remark 1),
+ *     tally gross face crossings (Eq. wfrpFormula), delete collided particles;
+ *   - add the wave free-transport flux (Sec. 2.2, F^{fr,wave}; Remark 3);
+ *   - solve the implicit macroscopic system (Eq. macroSysFinal) by the
+ *     matrix-free source iteration of Appendix B (Algorithm 2).
+ *
+ * Conventions
+ *   - Every function returns UGKWP_OK (0) or a negative UGKWP_E* code; the
+ *     message of the last failure of a context is ugkwp_last_error(ctx).
+ *   - Host input arrays are copied and validated; the caller keeps ownership.
+ *   - Output arrays are host memory unless the call takes dst_is_device = 1,
+ *     in which case they are device pointers written on the context's stream.
+ *   - The library owns all device memory of a context (allocated by
+ *     init calls, released by ugkwp_destroy).
+ *   - Field layout: cells are row-major [iy][ix] (ny = 1 in 1-D), fields are
+ *     [cell][G] with the group index fastest.  Several instances are stored one
+ *     after the other in instance order.
+ *   - Units are the paper's nondimensional ones with h = k = 1: nu and T share
+ *     units, B(nu,T) = 2 nu^3/(c^2 (e^{nu/T}-1)) scaled so that the full
+ *     spectrum carries a c T^4 (Sec. 2.1).
+ *   - A context is used by one host thread at a time.
+ *   - A failed ugkwp_step leaves the state as it was at the start of the failing
+ *     step (fields, particle pool, counters).
+ */
+#ifndef UGKWP_H
+#define UGKWP_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    UGKWP_OK = 0,
+    UGKWP_EINVAL = -1,      /* invalid argument or call order                  */
+    UGKWP_ENOMEM = -2,      /* device allocation failed                          */
+    UGKWP_EPOOL = -3,       /* particle pool capacity would be exceeded          */
+    UGKWP_ENOCONV = -4,     /* source iteration hit its iteration limit          */
+    UGKWP_ENONFINITE = -5,  /* non-positive or non-finite temperature            */
+    UGKWP_EHIP = -6         /* HIP runtime error                                 */
+};
+
+enum { UGKWP_BC_VACUUM = 0, UGKWP_BC_PLANCK = 1, UGKWP_BC_REFLECT = 2 };
+enum { UGKWP_SIDE_XLO = 0, UGKWP_SIDE_XHI = 1, UGKWP_SIDE_YLO = 2, UGKWP_SIDE_YHI = 3 };
+
+/* Flags */
+enum {
+    UGKWP_FLAG_GROUP_SIGMA = 1   /* particle flights use the Simpson group opacity
+                                    instead of kappa * nu_k^-p (Remark 2)        */
+};
+
+typedef struct ugkwp_ctx ugkwp_ctx;
+
+/* Parameters shared by all instances of a context. */
+typedef struct {
+    double c;            /* speed of light                                         */
+    double a;            /* radiation constant                                     */
+    double eps;          /* Knudsen number epsilon of Eq. mfGovI                   */
+    double dt;           /* time step                                              */
+    double nu_power;     /* p in sigma(nu) = kappa * nu^-p (3 for the paper's tests) */
+    int64_t n_cap;       /* max particles sampled per (cell, group) and step       */
+    int64_t pool_capacity; /* particle slots of the context (all instances)        */
+    int si_max_iters;    /* source-iteration limit (Algorithm 2)                   */
+    double si_tol;       /* relative max-norm tolerance on rho and on T            */
+    uint32_t flags;      /* UGKWP_FLAG_*                                           */
+} ugkwp_params;
+
+/* One problem instance (a slab in 1-D, a rectangle in 2-D). */
+typedef struct {
+    int dim;                 /* 1 or 2                                                 */
+    int nx, ny;              /* cells; ny = 1 in 1-D                                    */
+    double x0, x1, y0, y1;   /* domain                                                  */
+    int bc[4];               /* boundary type per side (XLO, XHI, YLO, YHI)             */
+    double bcT[4];           /* Planckian boundary temperatures                          */
+    int G;                   /* frequency groups, 1..64                                 */
+    const double* nu_edges;  /* G+1 ascending group edges (Sec. 2.1 multigroup)         */
+    uint64_t seed;           /* Philox key of this instance                              */
+    double w_ref;            /* target particle energy per unit cell volume (Sec. 3)     */
+    const double* kappa;     /* [ncell][G] >= 0: sigma(nu, cell) = kappa[cell][g] nu^-p  */
+    const double* cv;        /* [ncell] > 0 heat capacity                                */
+    const double* T0;        /* [ncell] > 0 initial material temperature                 */
+    const double* Tr0;       /* [ncell] > 0 initial radiation temperature: rho = phi(Tr0) */
+    const uint8_t* pinned;   /* [ncell] or NULL: cells whose T is held fixed (sources)   */
+} ugkwp_instance;
+
+/* Per-context counters and energy bookkeeping of the last step, summed over instances. */
+typedef struct {
+    int64_t n_alive_in;      /* particles entering the step                    */
+    int64_t n_births;        /* particles sampled in the step                  */
+    int64_t n_alive_out;     /* survivors after the step                       */
+    int64_t n_pushed;        /* n_alive_in + n_births                          */
+    int sweeps_max;          /* largest source-iteration sweep count           */
+    int sweeps_sum;          /* sum over instances                              */
+    double e_start, e_end;   /* total energy sum V (sum_g rho/c + Cv T)        */
+    double inflow_wave, inflow_eq, exit_particles, injection;
+    double residual;         /* e_end - e_start - (inflow_wave + inflow_eq - exit + injection) */
+    /* GPU time of the phases of the step, in ms, from HIP events on the context
+     * stream: count + scan + sample (incl. one host read of the birth total and
+     * the tally clears), the push kernel alone, wave flux + source set-up, and the
+     * source iteration (incl. its host convergence polls), and the counting sort
+     * that keeps the pool ordered by (cell, group). */
+    double ms_sample, ms_push, ms_macro, ms_si, ms_sort;
+} ugkwp_diag;
+
+/* ---- context ---- */
+
+/* Create a context.  hip_stream: a hipStream_t to run on, or NULL for a stream
+ * owned by the context.  No device memory is allocated yet. */
+int ugkwp_create(ugkwp_ctx** out, const ugkwp_params* p, void* hip_stream);
+void ugkwp_destroy(ugkwp_ctx* ctx);
+const char* ugkwp_last_error(const ugkwp_ctx* ctx);
+
+/* ---- problem set-up (the paper's statement of the problem, Sec. 2.1 and Sec. 3) ---- */
+
+/* Single-instance set-up, in three calls.  init_mesh fixes the geometry, the
+ * boundary conditions (Planckian incident, vacuum, reflective: Sec. 3) and the
+ * frequency groups; it allocates device memory. */
+int ugkwp_init_mesh(ugkwp_ctx* ctx, int dim, int nx, int ny, const double lo[2],
+                    const double hi[2], const int bc[4], const double bcT[4], int G,
+                    const double* nu_edges, uint64_t seed, double w_ref);
+/* kappa [ncell][G] (host): sigma(nu, cell) = kappa nu^-p; group opacity by
+ * Simpson's rule over each group (Sec. 3).  Non-negative and finite. */
+int ugkwp_set_opacity(ugkwp_ctx* ctx, const double* kappa);
+/* Heat capacity, initial T and radiation temperature per cell (rho^0 = phi(Tr0),
+ * no particles: Sec. 3.1), optional pinned-source mask. */
+int ugkwp_set_material(ugkwp_ctx* ctx, const double* cv, const double* T0,
+                       const double* Tr0, const uint8_t* pinned);
+
+/* Batched set-up: n_inst independent instances of one dimension with uneven
+ * cell and group counts, all advanced by one launch per kernel per step. */
+int ugkwp_init_batch(ugkwp_ctx* ctx, int n_inst, const ugkwp_instance* inst);
+
+/* ---- time stepping ---- */
+
+/* Advance every instance by nsteps steps of Algorithm 1.  Asynchronous on the
+ * context stream inside a step; synchronises once per step for the status. */
+int ugkwp_step(ugkwp_ctx* ctx, int nsteps);
+
+/* ---- results ---- */
+
+int ugkwp_num_instances(const ugkwp_ctx* ctx);
+/* Fields of instance `inst` (or of all instances, concatenated, when inst < 0):
+ * rho [ncell][G], T [ncell], rhop = survivor density [ncell][G]; any may be NULL. */
+int ugkwp_get_fields(ugkwp_ctx* ctx, int inst, double* rho, double* T, double* rhop,
+                     int dst_is_device);
+/* Tallies of the last step for instance `inst`: gross face crossings
+ * fx [(nx+1)*ny][G][2], fy [nx*(ny+1)][G][2] (direction 0 = +axis, 1 = -axis),
+ * deposition dep and survivor weight surv [ncell][G], births nbirth [ncell][G],
+ * new-particle weight wnew [ncell][G], static source Q [ncell][G].  Host arrays;
+ * any may be NULL. */
+int ugkwp_get_tallies(ugkwp_ctx* ctx, int inst, double* fx, double* fy, double* dep,
+                      double* surv, int64_t* nbirth, double* wnew, double* Q);
+int ugkwp_get_diag(ugkwp_ctx* ctx, ugkwp_diag* d);
+/* Birth counter and step index of instance `inst`. */
+int ugkwp_get_counters(ugkwp_ctx* ctx, int inst, uint64_t* birth_counter, int* step);
+
+/* Particle pool (all instances).  cell is the context-global cell index. */
+int64_t ugkwp_pool_size(ugkwp_ctx* ctx);
+int ugkwp_get_pool(ugkwp_ctx* ctx, double* x, double* y, double* ox, double* oy,
+                   double* nu, double* w, uint64_t* id, int32_t* cell, int32_t* g);
+/* Replace the pool of a single-instance context (y, oy may be NULL in 1-D) and
+ * set its birth counter; rhop [ncell][G] (may be NULL) sets the survivor density. */
+int ugkwp_set_pool(ugkwp_ctx* ctx, int64_t n, const double* x, const double* y,
+                   const double* ox, const double* oy, const double* nu, const double* w,
+                   const uint64_t* id, const int32_t* cell, const int32_t* g,
+                   uint64_t birth_counter, const double* rhop);
+
+/* ---- device building blocks, exposed for element-wise checks (host arrays) ---- */
+
+/* out[i] = phi_g(T[i]) for g < G (group equilibrium value of rho, Sec. 2.1),
+ * out laid out [n][G]. */
+int ugkwp_eval_phi(int n, const double* T, int G, const double* nu_edges, double a, double c,
+                   double* out);
+/* C4(s), C4(s) - e^{-s} and C2(s)/dt (Eq. C2Formula) for each s[i] = c sigma dt / eps^2. */
+int ugkwp_eval_coef(int n, const double* s, double* c4, double* w, double* c2_over_dt);
+/* Uniform draws u(seed, id[i], step, purpose, d[i]) of the keyed Philox4x32-10 stream. */
+int ugkwp_eval_uniform(int n, uint64_t seed, const uint64_t* id, uint32_t step,
+                       uint32_t purpose, const uint32_t* d, double* out);
+/* Linear-frequency sampling (Appendix A): slope beta at T[i] and the sampled nu
+ * for U[i] in group [nl[i], nh[i]]. */
+int ugkwp_eval_sample_nu(int n, const double* nl, const double* nh, const double* T,
+                         const double* U, double* beta, double* nu);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -195,10 +195,11 @@ static double particle_sigma(const ora_sim* s, size_t cg, double nu, int g)
     return s->kappa[cg] * nupow(nu, s->p.nu_power);
 }
 
-/* Harmonic mean face opacity (Appendix B); zero if either side is zero. */
+/* Harmonic mean face opacity (Appendix B); zero if either side is zero.
+ * Written symmetric in (a, b) so both cells of a face see the same value. */
 static double harmonic(double a, double b)
 {
-    if (a + b > 0.0) return 2.0 * a * b / (a + b);
+    if (a + b > 0.0) return 2.0 * (a * b) / (a + b);
     return 0.0;
 }
 

@@ -1,0 +1,136 @@
+// Shared layout of the device state of a UGKWP context.
+//
+// A context holds n_inst independent instances of one dimension.  Per-cell
+// fields are stored instance after instance; per-(cell, group) fields use a
+// padded group stride Gp (the power of two >= G, at most 64) so that the Gp
+// lanes of one cell sit in one 64-wide wavefront, and each instance's block
+// of (cell, group) slots starts on a multiple of 64 so that no wavefront spans
+// two instances.  Face quantities use the same Gp stride per face.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ugk {
+
+constexpr int WAVE = 64;
+constexpr int MAX_G = 64;
+constexpr int RES_SLOTS = 3;     // rotating residual slots of the source iteration
+
+enum { BC_VACUUM = 0, BC_PLANCK = 1, BC_REFLECT = 2 };
+enum { XLO = 0, XHI = 1, YLO = 2, YHI = 3 };
+
+struct Inst {
+    int dim, nx, ny, ncell;
+    int G, Gp, lgGp;
+    int cell_off;          // first global cell index
+    int edge_off;          // group edges at nu[edge_off .. edge_off + G]
+    int bc[4];
+    int64_t cg_off;        // first (cell, group) slot, multiple of 64
+    int64_t fx_off;        // first x-face slot ((nx+1)*ny faces, stride Gp)
+    int64_t fy_off;        // first y-face slot (nx*(ny+1) faces, stride Gp)
+    double x0, y0, dx, dy, V;
+    double bcT[4];
+    double w_ref;
+    uint64_t seed;
+};
+
+// Context-wide constants.
+struct Consts {
+    double c, a, eps, dt;
+    double e2c;            // eps^2 / c   (tau = e2c / sigma)
+    double cv;             // c / eps     (particle speed)
+    double lam_scale;      // c dt / eps^2
+    double nu_power;
+    double si_tol;
+    int64_t n_cap;
+    uint32_t flags;
+    int n_inst;
+    int64_t n_cg;          // total (cell, group) slots incl. padding
+    int64_t n_fx2;         // x-face tally entries (2 per x-face slot)
+    int ncell;             // total cells
+};
+
+// Residual accumulators of one source-iteration sweep (non-negative doubles as
+// their IEEE bit patterns, so that integer atomicMax orders them; NaN wins).
+struct Resid {
+    unsigned long long drho, rho, dT, T;
+};
+
+// Per-instance step state.
+struct InstState {
+    int conv_sweeps;       // sweeps used by the converged source iteration, 0 = running
+    int bad;               // non-finite / non-positive temperature seen
+    uint64_t births;       // birth counter B_n
+};
+
+struct Pool {
+    double* x;
+    double* y;
+    double* ox;            // mu in 1-D
+    double* oy;
+    double* nu;
+    double* w;
+    uint64_t* id;
+    int32_t* cell;         // global cell index
+    int32_t* g;
+};
+
+struct Dev {
+    const Inst* inst;
+    const int64_t* inst_cg;     // [n_inst+1] padded starts (for binary search)
+    const int32_t* cell_inst;   // [ncell]
+    const double* nu;           // edges
+    const double* simpson;      // [edge_off + g]
+    const double* phib;         // [inst][4][MAX_G] Planckian ghost phi
+    // per (cell, group) slot
+    const double* kappa;
+    double* sig;
+    double* sv;                 // s = c sigma dt / eps^2 (= lambda of the source iteration)
+    double* es;                 // e^{-s}
+    double* c4;
+    double* wc;                 // C4 - e^{-s}
+    double* rho;                // rho^n
+    double* rho_new;            // rho^k during the source iteration, rho^{n+1} after
+    double* rhop;               // survivor density from the previous step
+    double* rhoh;               // rho^h = rho^n - rhop (start of step)
+    double* Q;
+    double* phi0;
+    double* phi1;
+    int32_t* nb;                // births per slot
+    int64_t* boff;              // exclusive scan of nb
+    double* wnew;
+    double* beta;
+    double* dep;
+    double* surv;
+    uint32_t* scount;           // survivors per slot (counting sort of the pool)
+    int64_t* soff;              // exclusive scan of scount, then write cursor
+    // per face slot
+    double* ftx;                // [slot*2 + dir]
+    double* fty;
+    double* Dx;
+    double* Dy;
+    // per cell
+    const double* cvol;         // heat capacity
+    double* T;
+    double* T_new;
+    const uint8_t* pinned;
+    // per instance
+    InstState* ist;
+    Resid* res;                 // [n_inst][RES_SLOTS]
+    double* diag;               // [n_inst][8]
+    // context-wide counters
+    unsigned long long* counters;   // [0] survivors written, [1] crossings, ...
+    int64_t* n_births_total;        // scan total
+};
+
+__host__ __device__ inline int find_inst(const int64_t* starts, int n, int64_t j)
+{
+    int lo = 0, hi = n;         // starts[lo] <= j < starts[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (starts[mid] <= j) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace ugk

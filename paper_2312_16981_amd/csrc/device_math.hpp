@@ -1,0 +1,217 @@
+// Device-side scalar building blocks of the UGKWP hot path (gfx950).
+//
+//  - keyed counter-based random numbers: Philox4x32-10 (Salmon et al., SC'11);
+//    the paper only requires eta ~ U(0,1) (Sec. 2.2, collision times;
+//    Appendix A, frequencies);
+//  - the group Planck integral behind B_g (Sec. 2.1);
+//  - the UGKS time-averaged flux coefficients C4, C4 - e^{-s} (Sec. 2.2,
+//    F^{fr,UGKS}, F^{fr,wave}) and C2 (Eq. C2Formula);
+//  - the linear-frequency sampler (Eqs. Blinear, kg; Appendix A).
+//
+// Every expression that feeds a discrete decision (a collision test, a face
+// crossing, a particle count) is written in a fixed evaluation order; the
+// library is compiled with floating-point contraction off so the rounding is
+// exactly that of the written order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ugk {
+
+enum : uint32_t { PURPOSE_BIRTH = 1, PURPOSE_FLIGHT = 2 };
+
+// pi^4 / 15 = int_0^inf t^3/(e^t-1) dt
+#define UGK_PI4_15 6.49393940226682914909602217
+
+struct Philox4 { uint32_t v[4]; };
+
+__host__ __device__ inline Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                 uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t lo = (uint64_t)0xD2511F53u * c0;
+        const uint64_t hi = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(hi >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(lo >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)hi;
+        c3 = (uint32_t)lo;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Philox4 o;
+    o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+    return o;
+}
+
+// Two 52-bit uniforms in (0,1) per Philox call: u = (k + 1/2) 2^-52.
+__host__ __device__ inline double u52(uint32_t hi, uint32_t lo)
+{
+    const uint64_t k = ((uint64_t)hi << 20) | (uint64_t)(lo >> 12);
+    return ((double)k + 0.5) * 2.220446049250313080847e-16;   // 2^-52
+}
+
+// Draw d of (seed, particle id, step, purpose): counter (id_lo, id_hi, step,
+// purpose<<24 | d/2), key (seed_lo, seed_hi); even d takes words 0,1, odd d 2,3.
+__host__ __device__ inline double keyed_uniform(uint64_t seed, uint64_t id, uint32_t step,
+                                                uint32_t purpose, uint32_t d)
+{
+    const Philox4 r = philox4x32_10((uint32_t)id, (uint32_t)(id >> 32), step,
+                                    (purpose << 24) | (d >> 1), (uint32_t)seed,
+                                    (uint32_t)(seed >> 32));
+    return (d & 1u) ? u52(r.v[2], r.v[3]) : u52(r.v[0], r.v[1]);
+}
+
+// Both draws of one Philox call (d0 even): out0 = draw d0, out1 = draw d0+1.
+__host__ __device__ inline void keyed_uniform_pair(uint64_t seed, uint64_t id, uint32_t step,
+                                                   uint32_t purpose, uint32_t d0, double& out0,
+                                                   double& out1)
+{
+    const Philox4 r = philox4x32_10((uint32_t)id, (uint32_t)(id >> 32), step,
+                                    (purpose << 24) | (d0 >> 1), (uint32_t)seed,
+                                    (uint32_t)(seed >> 32));
+    out0 = u52(r.v[0], r.v[1]);
+    out1 = u52(r.v[2], r.v[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Planck band integrals.  head(x) = int_0^x t^3/(e^t-1) dt by its Taylor series
+// in x (x < 2, coefficients in constant memory supplied by the host);
+// tail(x) = int_x^inf t^3/(e^t-1) dt = sum_n e^{-nx}(x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4).
+
+struct HeadSeries {
+    int nterm;                 // even-power terms after x^3, x^4
+    double c[40];              // coefficient of x^(5 + 2j)
+};
+
+__device__ inline double planck_head(double x, const HeadSeries& hs)
+{
+    // x^3/3 - x^4/8 + sum_j c_j x^(5+2j), Horner in x^2
+    const double x2 = x * x;
+    double acc = 0.0;
+    for (int j = hs.nterm - 1; j >= 0; --j) acc = acc * x2 + hs.c[j];
+    const double x3 = x2 * x;
+    return x3 * (1.0 / 3.0) - x3 * x * 0.125 + acc * x3 * x2;
+}
+
+__device__ inline double planck_tail_series(double x)
+{
+    const double e1 = exp(-x);
+    if (e1 == 0.0) return 0.0;
+    const double x2 = x * x, x3 = x2 * x;
+    double en = e1, sum = 0.0;
+    for (int n = 1; n < 64; ++n) {
+        const double dn = (double)n, in = 1.0 / dn;
+        const double term = en * (((6.0 * in + 6.0 * x) * in + 3.0 * x2) * in + x3) * in;
+        sum += term;
+        if (term <= 1e-18 * sum) break;
+        en *= e1;
+    }
+    return sum;
+}
+
+// Edge value used by group bands: head(x) below 2, tail(x) from 2 on.
+__device__ inline double planck_edge_value(double x, const HeadSeries& hs)
+{
+    return x < 2.0 ? planck_head(x, hs) : planck_tail_series(x);
+}
+
+// int_{xl}^{xh} t^3/(e^t-1) from edge values vl = edge_value(xl), vh = edge_value(xh).
+__device__ inline double planck_band_from_edges(double xl, double vl, double xh, double vh)
+{
+    if (xh < 2.0) return vh - vl;                       // both heads
+    if (xl < 2.0) return (UGK_PI4_15 - vl) - vh;        // head below, tail above
+    return vl - vh;                                     // both tails
+}
+
+// phi_g(T) = a c T^4 (15/pi^4) band
+__device__ inline double phi_from_band(double a, double c, double T, double band)
+{
+    const double T2 = T * T;
+    return a * c * T2 * T2 * band / UGK_PI4_15;
+}
+
+// ---------------------------------------------------------------------------
+// Flux coefficients as functions of s = c sigma dt / eps^2.
+
+__host__ __device__ inline double coef_c4(double s)
+{
+    return s == 0.0 ? 1.0 : -expm1(-s) / s;
+}
+
+// C4 - e^{-s}; alternating series below s = 1 to avoid cancellation.
+__host__ __device__ inline double coef_w(double s)
+{
+    if (s < 1.0) {
+        double term_pow = 1.0, inv_fact = 1.0, sum = 0.0;
+        for (int n = 1; n < 60; ++n) {
+            term_pow *= s;
+            inv_fact /= (double)(n + 1);
+            const double t = (double)n * term_pow * inv_fact;
+            sum += (n & 1) ? t : -t;
+            if (t < 1e-18 * fabs(sum)) break;
+        }
+        return sum;
+    }
+    return coef_c4(s) - exp(-s);
+}
+
+// C2/dt = [2 C4 - 1 - e^{-s}] / s; series sum_{n>=2} (-1)^{n+1} (n-1) s^{n-1}/(n+1)! below s = 2.
+__host__ __device__ inline double coef_c2_over_dt(double s)
+{
+    if (s < 2.0) {
+        double p = 1.0, inv_fact = 0.5, sum = 0.0;       // p = s^{n-1}, inv_fact = 1/(n+1)!
+        for (int n = 2; n < 80; ++n) {
+            p *= s;
+            inv_fact /= (double)(n + 1);
+            const double t = (double)(n - 1) * p * inv_fact;
+            sum += (n & 1) ? t : -t;
+            if (t < 1e-18 * fabs(sum)) break;
+        }
+        return sum;
+    }
+    return (2.0 * coef_c4(s) - 1.0 - exp(-s)) / s;
+}
+
+// ---------------------------------------------------------------------------
+// Linear-frequency sampling.  beta = (B(nh) - B(nl)) / B(nmid) limited to [-2, 2]
+// (keeps the linear pdf non-negative on the group); evaluated as ratios of
+// Planck functions so that nothing under- or overflows for steep Wien tails.
+__host__ __device__ inline double freq_slope(double nl, double nh, double T)
+{
+    const double nm = 0.5 * (nl + nh);
+    const double em = -expm1(-nm / T);
+    const double rh = nh / nm, rl = nl / nm;
+    const double bh = rh * rh * rh * exp(-(nh - nm) / T) * em / (-expm1(-nh / T));
+    const double bl = rl * rl * rl * exp(-(nl - nm) / T) * em / (-expm1(-nl / T));
+    double beta = bh - bl;
+    beta = beta > 2.0 ? 2.0 : beta;
+    beta = beta < -2.0 ? -2.0 : beta;
+    return beta;
+}
+
+// Inverse CDF of the pdf (1 + beta u')/dnu, u' = (nu - nmid)/dnu in [-1/2, 1/2]:
+// (beta/2) u'^2 + u' + q = 0, q = 1/2 - beta/8 - U, stable root -2q/(1 + sqrt(1 - 2 beta q)).
+__host__ __device__ inline double sample_nu(double nl, double nh, double beta, double U)
+{
+    const double nm = 0.5 * (nl + nh);
+    const double dnu = nh - nl;
+    const double q = 0.5 - 0.125 * beta - U;
+    double disc = 1.0 - 2.0 * beta * q;
+    disc = disc < 0.0 ? 0.0 : disc;
+    const double up = -2.0 * q / (1.0 + sqrt(disc));
+    double nu = nm + up * dnu;
+    nu = nu < nl ? nl : nu;
+    nu = nu > nh ? nh : nu;
+    return nu;
+}
+
+// nu^-p with the exact cube for the paper's p = 3.
+__host__ __device__ inline double nu_pow(double nu, double p)
+{
+    return p == 3.0 ? 1.0 / (nu * nu * nu) : pow(nu, -p);
+}
+
+}  // namespace ugk

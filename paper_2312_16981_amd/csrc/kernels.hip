@@ -1,0 +1,1134 @@
+// HIP kernels (gfx950) of one UGKWP time step; see the paper's Algorithm 1.
+//
+//   k_tables       per (cell, group): Simpson group opacity (Sec. 3), s = c sigma dt / eps^2,
+//                  e^{-s}, C4 and C4 - e^{-s} (Sec. 2.2)
+//   k_face_D       per face and group: harmonic face opacity and
+//                  D = -(c/eps)^2 (1/3) C2 / h (Appendix B, K_g and M_g)
+//   k_count        wave split rho^h = rho^n - rho^p (Sec. 2.2) and the number of
+//                  collisionless particles N = floor(e^{-s} rho^h / w_ref) (Eq. IhpFormula)
+//   k_scan_*       exclusive scan of N -> particle slots and birth ids
+//   k_sample       new particles: uniform position, isotropic direction,
+//                  linear-frequency nu (Appendix A), t_f = dt
+//   k_push         free flight with reset at interfaces (Eq. particle tf formula,
+//                  Remark 1), gross face tallies (Eq. wfrpFormula), deletion of
+//                  collided particles, stable wavefront-ballot compaction of survivors
+//   k_wave_source  wave free-transport flux (Sec. 2.2, F^{fr,wave}; Remark 3) and the
+//                  static part Q of the macroscopic update (Eq. macroSysFinal)
+//   k_si_init, k_si_sweep
+//                  source iteration (Appendix B, Eq. macroSysAppendixIte, Algorithm 2)
+//   k_commit, k_diag
+#include "common.hpp"
+#include "device_math.hpp"
+#include "kernels.hpp"
+
+namespace ugk {
+
+__constant__ HeadSeries c_head;
+
+// ---------------------------------------------------------------------------
+// helpers
+
+struct Slot {
+    int inst, lcell, g;
+    bool cell_ok, active;
+};
+
+__device__ inline Slot decode_slot(const Dev& D, const Consts& K, int64_t j)
+{
+    Slot s;
+    const bool in = j < K.n_cg;
+    s.inst = in ? find_inst(D.inst_cg, K.n_inst, j) : K.n_inst - 1;
+    const Inst& I = D.inst[s.inst];
+    const int64_t local = j - I.cg_off;
+    s.lcell = (int)(local >> I.lgGp);
+    s.g = (int)(local & (I.Gp - 1));
+    s.cell_ok = in && local >= 0 && s.lcell < I.ncell;
+    s.active = s.cell_ok && s.g < I.G;
+    return s;
+}
+
+__device__ inline double particle_sigma(const Dev& D, const Consts& K, const Inst& I, int64_t cg,
+                                        double nu, int g)
+{
+    if (K.flags & 1u) return D.kappa[cg] * D.simpson[I.edge_off + g];
+    return D.kappa[cg] * nu_pow(nu, K.nu_power);
+}
+
+__device__ inline double phi_group_direct(double T, double nl, double nh, double a, double c)
+{
+    const double xl = nl / T, xh = nh / T;
+    const double band = planck_band_from_edges(xl, planck_edge_value(xl, c_head), xh,
+                                               planck_edge_value(xh, c_head));
+    return phi_from_band(a, c, T, band);
+}
+
+__device__ inline unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
+__device__ inline double bitsd(unsigned long long v) { return __longlong_as_double((long long)v); }
+
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, WAVE));
+    return v;
+}
+
+// NaN-propagating max (fmax drops NaN)
+__device__ inline double nmax(double a, double b) { return (a != a || a > b) ? a : b; }
+
+__device__ inline double wave_nmax(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = nmax(v, __shfl_xor(v, m, WAVE));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// set-up kernels
+
+__global__ void k_tables(Dev D, Consts K)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= K.n_cg) return;
+    const Slot s = decode_slot(D, K, j);
+    if (!s.active) {
+        D.sig[j] = 0.0; D.sv[j] = 0.0; D.es[j] = 1.0; D.c4[j] = 1.0; D.wc[j] = 0.0;
+        return;
+    }
+    const Inst& I = D.inst[s.inst];
+    const double sg = D.kappa[j] * D.simpson[I.edge_off + s.g];
+    const double sv = K.c * sg * K.dt / (K.eps * K.eps);
+    D.sig[j] = sg;
+    D.sv[j] = sv;
+    D.es[j] = exp(-sv);
+    D.c4[j] = coef_c4(sv);
+    D.wc[j] = coef_w(sv);
+}
+
+// One instance, one axis: faces (nx+1)*ny (axis 0) or nx*(ny+1) (axis 1), Gp groups each.
+__global__ void k_face_D(Dev D, Consts K, int inst, int axis)
+{
+    const Inst& I = D.inst[inst];
+    const int64_t nface = axis == 0 ? (int64_t)(I.nx + 1) * I.ny : (int64_t)I.nx * (I.ny + 1);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nface * I.Gp) return;
+    const int64_t f = j >> I.lgGp;
+    const int g = (int)(j & (I.Gp - 1));
+    double* Dout = axis == 0 ? D.Dx + I.fx_off : D.Dy + I.fy_off;
+    if (g >= I.G) { Dout[j] = 0.0; return; }
+    int cl, cr;     // local cells on the low / high side (-1 = outside)
+    double h;
+    if (axis == 0) {
+        const int iy = (int)(f / (I.nx + 1)), fx = (int)(f % (I.nx + 1));
+        cl = fx > 0 ? iy * I.nx + fx - 1 : -1;
+        cr = fx < I.nx ? iy * I.nx + fx : -1;
+        h = I.dx;
+    } else {
+        const int fy = (int)(f / I.nx), ix = (int)(f % I.nx);
+        cl = fy > 0 ? (fy - 1) * I.nx + ix : -1;
+        cr = fy < I.ny ? fy * I.nx + ix : -1;
+        h = I.dy;
+    }
+    double sf;
+    if (cl >= 0 && cr >= 0) {
+        const double a = D.sig[I.cg_off + ((int64_t)cl << I.lgGp) + g];
+        const double b = D.sig[I.cg_off + ((int64_t)cr << I.lgGp) + g];
+        sf = (a + b > 0.0) ? 2.0 * (a * b) / (a + b) : 0.0;
+    } else {
+        sf = D.sig[I.cg_off + ((int64_t)(cl >= 0 ? cl : cr) << I.lgGp) + g];
+    }
+    const double s = K.c * sf * K.dt / (K.eps * K.eps);
+    const double c2 = K.dt * coef_c2_over_dt(s);
+    Dout[j] = -(K.c * K.c / (3.0 * K.eps * K.eps)) * c2 / h;
+}
+
+// Planckian ghost values phi_g(T_b) per instance and side.
+__global__ void k_ghost_phi(Dev D, Consts K, double* phib)
+{
+    const int inst = blockIdx.x;
+    const int side = threadIdx.x / MAX_G, g = threadIdx.x % MAX_G;
+    const Inst& I = D.inst[inst];
+    double v = 0.0;
+    if (g < I.G && I.bc[side] == BC_PLANCK)
+        v = phi_group_direct(I.bcT[side], D.nu[I.edge_off + g], D.nu[I.edge_off + g + 1], K.a, K.c);
+    phib[((int64_t)inst * 4 + side) * MAX_G + g] = v;
+}
+
+// rho^0 = phi(Tr0) per (cell, group)
+__global__ void k_init_rho(Dev D, Consts K, const double* Tr0)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= K.n_cg) return;
+    const Slot s = decode_slot(D, K, j);
+    double v = 0.0;
+    if (s.active) {
+        const Inst& I = D.inst[s.inst];
+        v = phi_group_direct(Tr0[I.cell_off + s.lcell], D.nu[I.edge_off + s.g],
+                             D.nu[I.edge_off + s.g + 1], K.a, K.c);
+    }
+    D.rho[j] = v;
+    D.rhop[j] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// A1: wave split and particle counts
+
+__global__ void k_count(Dev D, Consts K)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= K.n_cg) return;
+    const Slot s = decode_slot(D, K, j);
+    if (!s.active) {
+        D.nb[j] = 0;
+        D.rhoh[j] = 0.0;
+        D.wnew[j] = 0.0;
+        return;
+    }
+    const Inst& I = D.inst[s.inst];
+    const double rh = D.rho[j] - D.rhop[j];
+    D.rhoh[j] = rh;
+    const double eov = D.es[j] * rh;
+    const double E = eov * I.V;
+    int N = 0;
+    if (E > 0.0) {
+        const double q = eov / I.w_ref;
+        N = (q >= (double)K.n_cap) ? (int)K.n_cap : (int)floor(q);
+    }
+    D.nb[j] = N;
+    D.wnew[j] = N >= 1 ? E / (double)N : 0.0;
+    if (N >= 1)
+        D.beta[j] = freq_slope(D.nu[I.edge_off + s.g], D.nu[I.edge_off + s.g + 1],
+                               D.T[I.cell_off + s.lcell]);
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of nb (int32) -> boff (int64); 256 threads x 16 items per block
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_ITEMS;
+
+__device__ inline int64_t block_excl_scan(int64_t v, int64_t* total)
+{
+    __shared__ int64_t wsum[SCAN_THREADS / WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    int64_t inc = v;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const int64_t o = __shfl_up(inc, d, WAVE);
+        if (lane >= d) inc += o;
+    }
+    if (lane == WAVE - 1) wsum[wid] = inc;
+    __syncthreads();
+    int64_t woff = 0, tot = 0;
+    for (int w = 0; w < SCAN_THREADS / WAVE; ++w) {
+        if (w < wid) woff += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return woff + inc - v;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(const int32_t* in, int64_t n, int64_t* part)
+{
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+        if (base + k < n) sum += in[base + k];
+    int64_t tot;
+    block_excl_scan(sum, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(int64_t* part, int64_t nblk, int64_t* total)
+{
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nblk; b0 += SCAN_THREADS) {
+        const int64_t b = b0 + threadIdx.x;
+        const int64_t v = b < nblk ? part[b] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan(v, &tot);
+        if (b < nblk) part[b] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(const int32_t* in, int64_t n, const int64_t* part,
+                                                          int64_t* out)
+{
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int32_t v[SCAN_ITEMS];
+    int64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0;
+        sum += v[k];
+    }
+    int64_t tot;
+    int64_t run = part[blockIdx.x] + block_excl_scan(sum, &tot);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// A2: sample the collisionless wave particles
+
+template <int DIM>
+__global__ void k_sample(Dev D, Consts K, Pool P, int64_t base, int64_t total, uint32_t step)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= total) return;
+    int64_t lo = 0, hi = K.n_cg;           // boff[lo] <= j < boff[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (D.boff[mid] <= j) lo = mid; else hi = mid;
+    }
+    const int64_t cg = lo;
+    const int inst = find_inst(D.inst_cg, K.n_inst, cg);
+    const Inst& I = D.inst[inst];
+    const int64_t local = cg - I.cg_off;
+    const int lcell = (int)(local >> I.lgGp), g = (int)(local & (I.Gp - 1));
+    const uint64_t id = D.ist[inst].births + (uint64_t)(j - D.boff[I.cg_off]);
+    const double nl = D.nu[I.edge_off + g], nh = D.nu[I.edge_off + g + 1];
+    const double beta = D.beta[cg];
+    const int ix = lcell % I.nx, iy = lcell / I.nx;
+    const double xl = I.x0 + (double)ix * I.dx;
+    const int64_t o = base + j;
+    double u0, u1, u2, u3;
+    keyed_uniform_pair(I.seed, id, step, PURPOSE_BIRTH, 0, u0, u1);
+    if (DIM == 1) {
+        u2 = keyed_uniform(I.seed, id, step, PURPOSE_BIRTH, 2);
+        P.x[o] = xl + u0 * I.dx;
+        P.ox[o] = 2.0 * u1 - 1.0;
+        P.nu[o] = sample_nu(nl, nh, beta, u2);
+    } else {
+        const double yl = I.y0 + (double)iy * I.dy;
+        keyed_uniform_pair(I.seed, id, step, PURPOSE_BIRTH, 2, u2, u3);
+        const double u4 = keyed_uniform(I.seed, id, step, PURPOSE_BIRTH, 4);
+        P.x[o] = xl + u0 * I.dx;
+        P.y[o] = yl + u1 * I.dy;
+        const double oz = 2.0 * u2 - 1.0;
+        const double psi = 6.283185307179586 * u3;
+        const double sn = sqrt(1.0 - oz * oz);
+        P.ox[o] = sn * cos(psi);
+        P.oy[o] = sn * sin(psi);
+        P.nu[o] = sample_nu(nl, nh, beta, u4);
+    }
+    P.w[o] = D.wnew[cg];
+    P.id[o] = id;
+    P.cell[o] = I.cell_off + lcell;
+    P.g[o] = g;
+}
+
+// ---------------------------------------------------------------------------
+// A3: free flight, reset at interfaces, tallies, deletion, compaction
+//
+// One thread per particle, PUSH_PPT particles per thread.  Tallies (survivor
+// and deposited weight per (cell, group), gross face crossings per face, group
+// and direction, survivor counts per (cell, group)) are accumulated in a
+// per-block LDS hash table and flushed with one global atomic per distinct bin:
+// the pool is kept sorted by (cell, group) slot, so a block's particles fall
+// into a handful of bins.
+
+constexpr int PUSH_THREADS = 256;
+constexpr int PUSH_PPT = 4;
+constexpr int HT_BITS = 11;
+constexpr int HT_SIZE = 1 << HT_BITS;
+constexpr uint32_t HT_EMPTY = 0xFFFFFFFFu;
+constexpr int HT_PROBES = 32;
+
+enum : uint32_t { TAL_SURV = 0, TAL_DEP = 1, TAL_FX = 2, TAL_FY = 3 };
+
+struct TallyTable {
+    uint32_t key[HT_SIZE];     // (index << 2) | type
+    uint32_t cnt[HT_SIZE];     // survivor count (TAL_SURV only)
+    double val[HT_SIZE];
+};
+
+__device__ inline double* tally_target(const Dev& D, uint32_t type, uint32_t index)
+{
+    switch (type) {
+        case TAL_SURV: return D.surv + index;
+        case TAL_DEP: return D.dep + index;
+        case TAL_FX: return D.ftx + index;
+        default: return D.fty + index;
+    }
+}
+
+__device__ inline void lds_tally(TallyTable& T, const Dev& D, uint32_t type, uint32_t index, double w)
+{
+    const uint32_t key = (index << 2) | type;
+    uint32_t h = (key * 2654435761u) >> (32 - HT_BITS);
+    for (int probe = 0; probe < HT_PROBES; ++probe) {
+        const uint32_t prev = atomicCAS(&T.key[h], HT_EMPTY, key);
+        if (prev == HT_EMPTY || prev == key) {
+            __hip_atomic_fetch_add(&T.val[h], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (type == TAL_SURV)
+                __hip_atomic_fetch_add(&T.cnt[h], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return;
+        }
+        h = (h + 1) & (HT_SIZE - 1);
+    }
+    // table crowded: go straight to memory
+    unsafeAtomicAdd(tally_target(D, type, index), w);
+    if (type == TAL_SURV) atomicAdd(D.scount + index, 1u);
+}
+
+struct Flight {
+    double x, y, ox, oy;   // position and direction (mu in 1-D)
+    double t, t_rem, sig;
+    uint32_t d;            // FLIGHT draws used
+    int ix, iy;
+    bool coll;
+};
+
+__device__ inline void draw_flight(const Consts& K, const Inst& I, uint64_t id, uint32_t step, Flight& f)
+{
+    const double u = keyed_uniform(I.seed, id, step, PURPOSE_FLIGHT, f.d++);
+    const double tau = K.e2c / f.sig;
+    const double a = -tau * log(u);
+    f.coll = a < K.dt - f.t;
+    f.t_rem = f.coll ? a : K.dt - f.t;
+}
+
+// Flight of one particle through the step.  Returns 0 survives, 1 collided, 2 left the domain.
+template <int DIM>
+__device__ inline int fly(const Dev& D, const Consts& K, const Inst& I, TallyTable& T, uint64_t id,
+                          uint32_t step, double nu, int g, double w, Flight& f)
+{
+    for (;;) {
+        const double vx = K.cv * f.ox;
+        const double xl = I.x0 + (double)f.ix * I.dx, xr = I.x0 + (double)(f.ix + 1) * I.dx;
+        double tx;
+        if (vx > 0) tx = (xr - f.x) / vx;
+        else if (vx < 0) tx = (xl - f.x) / vx;
+        else tx = INFINITY;
+        double vy = 0.0, yl = 0.0, yr = 0.0, ty = INFINITY;
+        if (DIM == 2) {
+            vy = K.cv * f.oy;
+            yl = I.y0 + (double)f.iy * I.dy;
+            yr = I.y0 + (double)(f.iy + 1) * I.dy;
+            if (vy > 0) ty = (yr - f.y) / vy;
+            else if (vy < 0) ty = (yl - f.y) / vy;
+        }
+        const bool xaxis = DIM == 1 || tx <= ty;
+        const double tf = xaxis ? tx : ty;
+        if (!(tf < f.t_rem)) {
+            double xn = f.x + vx * f.t_rem;
+            xn = xn < xl ? xl : xn;
+            xn = xn > xr ? xr : xn;
+            f.x = xn;
+            if (DIM == 2) {
+                double yn = f.y + vy * f.t_rem;
+                yn = yn < yl ? yl : yn;
+                yn = yn > yr ? yr : yn;
+                f.y = yn;
+            }
+            return f.coll ? 1 : 0;
+        }
+        f.t = f.t + tf;
+        bool pos, boundary;
+        int side;
+        uint32_t type, index;
+        if (xaxis) {
+            pos = vx > 0;
+            f.x = pos ? xr : xl;
+            if (DIM == 2) {
+                double yn = f.y + vy * tf;
+                yn = yn < yl ? yl : yn;
+                yn = yn > yr ? yr : yn;
+                f.y = yn;
+            }
+            boundary = pos ? (f.ix == I.nx - 1) : (f.ix == 0);
+            side = pos ? XHI : XLO;
+            const int64_t face = (int64_t)f.iy * (I.nx + 1) + (pos ? f.ix + 1 : f.ix);
+            type = TAL_FX;
+            index = (uint32_t)(((I.fx_off + (face << I.lgGp) + g) << 1) + (pos ? 0 : 1));
+        } else {
+            pos = vy > 0;
+            f.y = pos ? yr : yl;
+            double xn = f.x + vx * tf;
+            xn = xn < xl ? xl : xn;
+            xn = xn > xr ? xr : xn;
+            f.x = xn;
+            boundary = pos ? (f.iy == I.ny - 1) : (f.iy == 0);
+            side = pos ? YHI : YLO;
+            const int64_t face = (int64_t)(pos ? f.iy + 1 : f.iy) * I.nx + f.ix;
+            type = TAL_FY;
+            index = (uint32_t)(((I.fy_off + (face << I.lgGp) + g) << 1) + (pos ? 0 : 1));
+        }
+        if (boundary) {
+            if (I.bc[side] == BC_REFLECT) {
+                if (xaxis) f.ox = -f.ox; else f.oy = -f.oy;
+                f.t_rem = f.t_rem - tf;
+                continue;
+            }
+            lds_tally(T, D, type, index, w);
+            return 2;
+        }
+        lds_tally(T, D, type, index, w);
+        if (xaxis) f.ix += pos ? 1 : -1; else f.iy += pos ? 1 : -1;
+        f.sig = particle_sigma(D, K, I, I.cg_off + ((int64_t)(f.iy * I.nx + f.ix) << I.lgGp) + g, nu, g);
+        draw_flight(K, I, id, step, f);
+    }
+}
+
+template <int DIM, bool SINGLE>
+__global__ __launch_bounds__(PUSH_THREADS) void k_push(Dev D, Consts K, Pool A, Pool B, int64_t n_alive,
+                                                       int64_t n_total, uint32_t step)
+{
+    __shared__ TallyTable T;
+    __shared__ int wcount[PUSH_THREADS / WAVE];
+    __shared__ unsigned long long bbase;
+    for (int h = threadIdx.x; h < HT_SIZE; h += PUSH_THREADS) {
+        T.key[h] = HT_EMPTY;
+        T.cnt[h] = 0u;
+        T.val[h] = 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const int64_t base = (int64_t)blockIdx.x * (PUSH_THREADS * PUSH_PPT);
+    for (int r = 0; r < PUSH_PPT; ++r) {
+        const int64_t i = base + (int64_t)r * PUSH_THREADS + threadIdx.x;
+        const bool valid = i < n_total;
+        bool keep = false;
+        Flight f;
+        double nu = 0.0, w = 0.0;
+        uint64_t id = 0;
+        int g = 0, inst = 0;
+        const int cell = valid ? A.cell[i] : 0;
+        const bool rec_ok = cell >= 0 && cell < K.ncell;
+        if (valid && !rec_ok) atomicOr((unsigned long long*)(D.counters + 2), 4ull);   // corrupt record
+        if (valid && rec_ok) {
+            f.x = A.x[i];
+            f.ox = A.ox[i];
+            if (DIM == 2) { f.y = A.y[i]; f.oy = A.oy[i]; } else { f.y = 0.0; f.oy = 0.0; }
+            nu = A.nu[i];
+            w = A.w[i];
+            id = A.id[i];
+            g = A.g[i];
+            if (!SINGLE) inst = D.cell_inst[cell];
+            const Inst& I = D.inst[SINGLE ? 0 : inst];
+            const int lcell = cell - I.cell_off;
+            f.ix = DIM == 1 ? lcell : lcell % I.nx;
+            f.iy = DIM == 1 ? 0 : lcell / I.nx;
+            f.t = 0.0;
+            f.d = 0;
+            f.sig = particle_sigma(D, K, I, I.cg_off + ((int64_t)lcell << I.lgGp) + g, nu, g);
+            if (i < n_alive) draw_flight(K, I, id, step, f);   // old particle: t_f = min(-tau ln eta, dt)
+            else { f.coll = false; f.t_rem = K.dt; }           // new collisionless particle: t_f = dt
+            const int out = fly<DIM>(D, K, I, T, id, step, nu, g, w, f);
+            if (out != 2) {
+                const uint32_t cg = (uint32_t)(I.cg_off + ((int64_t)(f.iy * I.nx + f.ix) << I.lgGp) + g);
+                lds_tally(T, D, out == 0 ? TAL_SURV : TAL_DEP, cg, w);
+            }
+            keep = out == 0;
+        }
+        // stable compaction of this round: ballot per wavefront, prefix over wavefronts
+        const unsigned long long mask = __ballot(keep);
+        const int pre = __popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0) wcount[wid] = __popcll(mask);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int k = 0; k < PUSH_THREADS / WAVE; ++k) tot += wcount[k];
+            bbase = tot ? atomicAdd(D.counters, (unsigned long long)tot) : 0ull;
+        }
+        __syncthreads();
+        if (keep) {
+            const Inst& I = D.inst[SINGLE ? 0 : inst];
+            int woff = 0;
+            for (int k = 0; k < wid; ++k) woff += wcount[k];
+            const int64_t o = (int64_t)bbase + woff + pre;
+            B.x[o] = f.x;
+            B.ox[o] = f.ox;
+            if (DIM == 2) { B.y[o] = f.y; B.oy[o] = f.oy; }
+            B.nu[o] = nu;
+            B.w[o] = w;
+            B.id[o] = id;
+            B.cell[o] = I.cell_off + f.iy * I.nx + f.ix;
+            B.g[o] = g;
+        }
+        __syncthreads();
+    }
+    // flush the block's tallies: one global atomic per distinct bin
+    for (int h = threadIdx.x; h < HT_SIZE; h += PUSH_THREADS) {
+        const uint32_t key = T.key[h];
+        if (key == HT_EMPTY) continue;
+        const uint32_t type = key & 3u, index = key >> 2;
+        unsafeAtomicAdd(tally_target(D, type, index), T.val[h]);
+        if (type == TAL_SURV) atomicAdd(D.scount + index, T.cnt[h]);
+    }
+}
+
+// Counting-sort scatter of the survivors (B -> A) by (cell, group) slot.  soff
+// holds the exclusive scan of the survivor counts and serves as the per-slot
+// write cursor; each run of equal slots within a wavefront reserves its range
+// with one atomic.
+template <int DIM, bool SINGLE>
+__global__ __launch_bounds__(256) void k_sort_scatter(Dev D, Consts K, Pool B, Pool A)
+{
+    // survivor count written by the push's compaction
+    const int64_t n = (int64_t)D.counters[0];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & (WAVE - 1);
+    bool valid = i < n;
+    int64_t key = -1;
+    int cell = 0;
+    if (valid) {
+        cell = B.cell[i];
+        const int g = B.g[i];
+        if (cell < 0 || cell >= K.ncell) {
+            valid = false;
+        } else {
+            const int inst = SINGLE ? 0 : D.cell_inst[cell];
+            const Inst& I = D.inst[inst];
+            key = I.cg_off + ((int64_t)(cell - I.cell_off) << I.lgGp) + g;
+            if (g < 0 || g >= I.G) valid = false;
+        }
+        if (!valid) {
+            key = -1;
+            atomicOr((unsigned long long*)(D.counters + 2), 2ull);   // corrupt record
+        }
+    }
+    const int64_t kprev = __shfl_up(key, 1, WAVE);
+    const bool head = valid && (lane == 0 || kprev != key);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long upto = lane == WAVE - 1 ? ~0ull : ((2ull << lane) - 1ull);
+    const int hl = 63 - __clzll(heads & upto);                    // head lane of my run
+    const unsigned long long after = heads & ~upto;
+    int nexth = after ? __ffsll((long long)after) - 1 : WAVE;     // next run's head (or end)
+    const unsigned long long vmask = __ballot(valid);
+    const int nvalid = __popcll(vmask);
+    if (nexth > nvalid) nexth = nvalid;
+    int64_t rbase = 0;
+    if (head) rbase = (int64_t)atomicAdd((unsigned long long*)(D.soff + key), (unsigned long long)(nexth - lane));
+    rbase = __shfl(rbase, hl < 0 ? 0 : hl, WAVE);
+    const int64_t o = rbase + (lane - hl);
+    if (valid && (o < 0 || o >= n)) atomicOr((unsigned long long*)(D.counters + 2), 1ull);   // count mismatch
+    if (valid && o >= 0 && o < n) {
+        A.x[o] = B.x[i];
+        A.ox[o] = B.ox[i];
+        if (DIM == 2) { A.y[o] = B.y[i]; A.oy[o] = B.oy[i]; }
+        A.nu[o] = B.nu[i];
+        A.w[o] = B.w[i];
+        A.id[o] = B.id[i];
+        A.cell[o] = cell;
+        A.g[o] = B.g[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// A4: wave free-transport flux and the static source Q
+
+__global__ void k_wave_source(Dev D, Consts K)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= K.n_cg) return;
+    const Slot s = decode_slot(D, K, j);
+    if (!s.active) { D.Q[j] = 0.0; return; }
+    const Inst& I = D.inst[s.inst];
+    const int Gp = I.Gp, g = s.g, nx = I.nx;
+    const int ix = s.lcell % nx, iy = s.lcell / nx;
+    const double cq = K.c / (4.0 * K.eps);
+    const double Ah = D.nb[j] > 0 ? D.wc[j] : D.c4[j];
+    const double here = Ah * D.rhoh[j];
+    const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
+    double fsum = 0.0, inflow = 0.0;
+    // faces in the order XLO, XHI, YLO, YHI; flux through a face along +axis is
+    // cq (A_low rho^h_low - A_high rho^h_high)
+    for (int q = 0; q < 2 * I.dim; ++q) {
+        const int axis = q >> 1;
+        const bool lo = (q & 1) == 0;
+        bool inside;
+        int64_t nbj = 0;
+        if (axis == 0) {
+            inside = lo ? ix > 0 : ix < nx - 1;
+            nbj = j + (lo ? -Gp : Gp);
+        } else {
+            inside = lo ? iy > 0 : iy < I.ny - 1;
+            nbj = j + (lo ? -(int64_t)nx * Gp : (int64_t)nx * Gp);
+        }
+        const double S = axis == 0 ? I.dy : I.dx;
+        double there;
+        if (inside) {
+            const double An = D.nb[nbj] > 0 ? D.wc[nbj] : D.c4[nbj];
+            there = An * D.rhoh[nbj];
+        } else {
+            const int bc = I.bc[q];
+            if (bc == BC_REFLECT) continue;
+            there = bc == BC_PLANCK ? D.c4[j] * phib[q * MAX_G + g] : 0.0;
+        }
+        const double Fpos = lo ? cq * (there - here) : cq * (here - there);
+        const double Fin = lo ? Fpos : -Fpos;
+        fsum += S * Fin;
+        if (!inside) inflow += K.dt * S * Fin / K.c;
+    }
+    // gross particle crossings into / out of the cell
+    const int64_t fl = I.fx_off + (((int64_t)iy * (nx + 1) + ix) << I.lgGp) + g;
+    const int64_t fr = fl + Gp;
+    double a_in = D.ftx[fl * 2 + 0] + D.ftx[fr * 2 + 1];
+    double a_out = D.ftx[fl * 2 + 1] + D.ftx[fr * 2 + 0];
+    if (I.dim == 2) {
+        const int64_t fb = I.fy_off + (((int64_t)iy * nx + ix) << I.lgGp) + g;
+        const int64_t ft = fb + ((int64_t)nx << I.lgGp);
+        a_in += D.fty[fb * 2 + 0] + D.fty[ft * 2 + 1];
+        a_out += D.fty[fb * 2 + 1] + D.fty[ft * 2 + 0];
+    }
+    D.Q[j] = D.rho[j] + (K.dt / I.V) * fsum + (a_in - a_out) / I.V;
+    if (inflow != 0.0) atomicAdd(D.diag + s.inst * 8 + 0, inflow);
+}
+
+// ---------------------------------------------------------------------------
+// A5: source iteration.  Thread per (cell, group) slot; the Gp slots of a cell
+// share one wavefront, so the group sum of the temperature update and the
+// group-edge sharing of the Planck integrals are wavefront shuffles.
+
+__global__ void k_si_init(Dev D, Consts K)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const Slot s = decode_slot(D, K, j);
+    if (j >= K.n_cg) return;
+    if (s.cell_ok) {
+        const Inst& I = D.inst[s.inst];
+        const int cell = I.cell_off + s.lcell;
+        const double T = D.T[cell];
+        double v = 0.0;
+        if (s.active)
+            v = phi_group_direct(T, D.nu[I.edge_off + s.g], D.nu[I.edge_off + s.g + 1], K.a, K.c);
+        D.phi0[j] = v;
+        D.rho_new[j] = D.rho[j];
+        if (s.g == 0) D.T_new[cell] = T;
+    } else {
+        D.phi0[j] = 0.0;
+        D.phi1[j] = 0.0;
+        D.rho_new[j] = 0.0;
+    }
+    if (j == D.inst[s.inst].cg_off) {
+        Resid z = {0ull, 0ull, 0ull, 0ull};
+        D.res[s.inst * RES_SLOTS + 0] = z;
+        D.ist[s.inst].conv_sweeps = 0;
+        D.ist[s.inst].bad = 0;
+    }
+}
+
+constexpr int SI_THREADS = 256;
+
+__global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k, const double* phi_in,
+                                                          double* phi_out, int check_only)
+{
+    const int64_t j = (int64_t)blockIdx.x * SI_THREADS + threadIdx.x;
+    const Slot s = decode_slot(D, K, j);
+    const Inst& I = D.inst[s.inst];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const bool first = j == I.cg_off;
+
+    // convergence decision from the previous sweep (identical in every thread of the instance)
+    bool run = D.ist[s.inst].conv_sweeps == 0 && j < K.n_cg;
+    if (run && k > 0) {
+        const Resid r = D.res[s.inst * RES_SLOTS + (k - 1) % RES_SLOTS];
+        const double drho = bitsd(r.drho), mrho = bitsd(r.rho), dT = bitsd(r.dT), mT = bitsd(r.T);
+        if (drho <= K.si_tol * mrho && dT <= K.si_tol * mT) {
+            run = false;
+            if (first) D.ist[s.inst].conv_sweeps = k;
+        }
+    }
+    if (first && !check_only) {
+        Resid z = {0ull, 0ull, 0ull, 0ull};
+        D.res[s.inst * RES_SLOTS + (k + 1) % RES_SLOTS] = z;
+    }
+    if (check_only) run = false;
+
+    double dr = 0.0, mr = 0.0, dT = 0.0, mT = 0.0;
+    const int g = s.g, Gp = I.Gp, G = I.G;
+    const bool work = run && s.cell_ok;
+    double contrib = 0.0;
+    if (work && s.active) {
+        const int nx = I.nx;
+        const int ix = s.lcell % nx, iy = s.lcell / nx;
+        const double phi = phi_in[j];
+        const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
+        double lap = 0.0;
+        for (int q = 0; q < 2 * I.dim; ++q) {
+            const int axis = q >> 1;
+            const bool lo = (q & 1) == 0;
+            bool inside;
+            int64_t nbj, fslot;
+            double S;
+            if (axis == 0) {
+                inside = lo ? ix > 0 : ix < nx - 1;
+                nbj = j + (lo ? -Gp : Gp);
+                fslot = I.fx_off + (((int64_t)iy * (nx + 1) + ix + (lo ? 0 : 1)) << I.lgGp) + g;
+                S = I.dy;
+            } else {
+                inside = lo ? iy > 0 : iy < I.ny - 1;
+                nbj = j + (lo ? -(int64_t)nx * Gp : (int64_t)nx * Gp);
+                fslot = I.fy_off + (((int64_t)(iy + (lo ? 0 : 1)) * nx + ix) << I.lgGp) + g;
+                S = I.dx;
+            }
+            const double Df = axis == 0 ? D.Dx[fslot] : D.Dy[fslot];
+            double pn;
+            if (inside) pn = phi_in[nbj];
+            else {
+                const int bc = I.bc[q];
+                pn = bc == BC_PLANCK ? phib[q * MAX_G + g] : (bc == BC_REFLECT ? phi : 0.0);
+            }
+            lap += S * Df * (pn - phi);
+        }
+        const double lam = D.sv[j];
+        const double b = D.Q[j] + (K.dt / I.V) * lap;
+        const double r = (b + lam * phi) / (1.0 + lam);
+        const double em = (b - phi) / (1.0 + lam);
+        contrib = D.sig[j] * em;
+        dr = fabs(r - D.rho_new[j]);
+        mr = fabs(r);
+        D.rho_new[j] = r;
+    }
+    // group sum over the Gp lanes of the cell (butterfly: every lane gets the same bits)
+    for (int m = 1; m < Gp; m <<= 1) contrib += __shfl_xor(contrib, m, WAVE);
+
+    double Tnew = 1.0;
+    if (work) {
+        const int cell = I.cell_off + s.lcell;
+        const double Tk = D.T_new[cell];
+        const double Tn = D.T[cell];
+        Tnew = D.pinned[cell] ? Tn : Tn + (K.dt / (K.eps * K.eps * D.cvol[cell])) * contrib;
+        if (!(Tnew > 0.0) || !isfinite(Tnew)) {
+            if (g == 0) atomicOr(&D.ist[s.inst].bad, 1);
+            Tnew = 1.0;
+        }
+        if (g == 0) {
+            D.T_new[cell] = Tnew;
+            dT = fabs(Tnew - Tk);
+            mT = Tnew;
+        }
+    }
+    // phi^{k+1}: lane g evaluates the Planck edge value at its lower edge nu_g / T,
+    // takes the upper one from lane g+1 (lane G-1 evaluates it itself when G = Gp)
+    {
+        const bool edge_lane = work && g <= G;
+        const double xe = edge_lane ? D.nu[I.edge_off + g] / Tnew : 0.0;
+        const double ve = edge_lane ? planck_edge_value(xe, c_head) : 0.0;
+        double xh = __shfl_down(xe, 1, Gp < 2 ? 2 : Gp);
+        double vh = __shfl_down(ve, 1, Gp < 2 ? 2 : Gp);
+        if (work && g == G - 1 && (G == Gp)) {
+            xh = D.nu[I.edge_off + G] / Tnew;
+            vh = planck_edge_value(xh, c_head);
+        }
+        if (work && s.active)
+            phi_out[j] = phi_from_band(K.a, K.c, Tnew, planck_band_from_edges(xe, ve, xh, vh));
+    }
+    // residual maxima: wavefront, then runs of wavefronts of one instance in the block
+    dr = wave_nmax(dr);
+    mr = wave_nmax(mr);
+    dT = wave_nmax(dT);
+    mT = wave_nmax(mT);
+    __shared__ double wres[SI_THREADS / WAVE][4];
+    __shared__ int winst[SI_THREADS / WAVE];
+    __shared__ int wrun[SI_THREADS / WAVE];
+    if (lane == 0) {
+        wres[wid][0] = dr; wres[wid][1] = mr; wres[wid][2] = dT; wres[wid][3] = mT;
+        winst[wid] = s.inst;
+        wrun[wid] = work ? 1 : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int w0 = 0;
+        const int nw = SI_THREADS / WAVE;
+        while (w0 < nw) {
+            int w1 = w0;
+            double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            int any = 0;
+            while (w1 < nw && winst[w1] == winst[w0]) {
+                if (wrun[w1]) {
+                    any = 1;
+                    a0 = nmax(a0, wres[w1][0]); a1 = nmax(a1, wres[w1][1]);
+                    a2 = nmax(a2, wres[w1][2]); a3 = nmax(a3, wres[w1][3]);
+                }
+                ++w1;
+            }
+            if (any) {
+                Resid* r = D.res + winst[w0] * RES_SLOTS + k % RES_SLOTS;
+                atomicMax(&r->drho, dbits(a0));
+                atomicMax(&r->rho, dbits(a1));
+                atomicMax(&r->dT, dbits(a2));
+                atomicMax(&r->T, dbits(a3));
+            }
+            w0 = w1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// commit and diagnostics
+
+__global__ void k_commit(Dev D, Consts K)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= K.n_cg) return;
+    const Slot s = decode_slot(D, K, j);
+    const Inst& I = D.inst[s.inst];
+    D.rhop[j] = s.active ? D.surv[j] / I.V : 0.0;
+    if (j == I.cg_off) {
+        const int64_t end = s.inst + 1 < K.n_inst ? D.boff[D.inst_cg[s.inst + 1]] : *D.n_births_total;
+        D.ist[s.inst].births += (uint64_t)(end - D.boff[I.cg_off]);
+    }
+}
+
+// Energy bookkeeping of the step per instance: diag[inst*8 + q],
+// q = 0 inflow_wave (written by k_wave_source), 1 inflow_eq, 2 exit, 3 injection,
+// 4 e_start, 5 e_end.  Uses the final source-iteration input phi^k.  Sums are
+// reduced per wavefront and per run of same-instance wavefronts of the block
+// before one atomic per quantity.
+constexpr int DIAG_THREADS = 256;
+
+__global__ __launch_bounds__(DIAG_THREADS) void k_diag(Dev D, Consts K)
+{
+    const int64_t j = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x;
+    const Slot s = decode_slot(D, K, j);
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // inflow_eq, exit/c, injection, e0, e1
+    if (s.active) {
+        const Inst& I = D.inst[s.inst];
+        const int ns = D.ist[s.inst].conv_sweeps;
+        const double* phik = ((ns - 1) & 1) ? D.phi1 : D.phi0;
+        const int nx = I.nx, ix = s.lcell % nx, iy = s.lcell / nx, g = s.g;
+        const int cell = I.cell_off + s.lcell;
+        const double phi = phik[j];
+        const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
+        for (int q = 0; q < 2 * I.dim; ++q) {
+            const int axis = q >> 1;
+            const bool lo = (q & 1) == 0;
+            const bool boundary = axis == 0 ? (lo ? ix == 0 : ix == nx - 1) : (lo ? iy == 0 : iy == I.ny - 1);
+            if (!boundary) continue;
+            int64_t fslot;
+            double S;
+            if (axis == 0) {
+                fslot = I.fx_off + (((int64_t)iy * (nx + 1) + ix + (lo ? 0 : 1)) << I.lgGp) + g;
+                S = I.dy;
+            } else {
+                fslot = I.fy_off + (((int64_t)(iy + (lo ? 0 : 1)) * nx + ix) << I.lgGp) + g;
+                S = I.dx;
+            }
+            const double Df = axis == 0 ? D.Dx[fslot] : D.Dy[fslot];
+            const int bc = I.bc[q];
+            const double pn = bc == BC_PLANCK ? phib[q * MAX_G + g] : (bc == BC_REFLECT ? phi : 0.0);
+            v[0] += K.dt * S * Df * (pn - phi) / K.c;
+            const double* tal = axis == 0 ? D.ftx : D.fty;
+            v[1] += tal[fslot * 2 + (lo ? 1 : 0)] / K.c;
+        }
+        if (D.pinned[cell]) v[2] = I.V * (K.dt * D.sig[j] / (K.eps * K.eps)) * (phi - D.rho_new[j]);
+        v[3] = I.V * D.rho[j] / K.c;
+        v[4] = I.V * D.rho_new[j] / K.c;
+        if (g == 0) {
+            v[3] += I.V * D.cvol[cell] * D.T[cell];
+            v[4] += I.V * D.cvol[cell] * D.T_new[cell];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+        for (int m = 32; m >= 1; m >>= 1) v[q] += __shfl_xor(v[q], m, WAVE);
+    __shared__ double wsum[DIAG_THREADS / WAVE][5];
+    __shared__ int winst[DIAG_THREADS / WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    if (lane == 0) {
+        for (int q = 0; q < 5; ++q) wsum[wid][q] = v[q];
+        winst[wid] = j < K.n_cg ? s.inst : -1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = DIAG_THREADS / WAVE;
+        int w0 = 0;
+        while (w0 < nw) {
+            int w1 = w0;
+            double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            while (w1 < nw && winst[w1] == winst[w0]) {
+                for (int q = 0; q < 5; ++q) acc[q] += wsum[w1][q];
+                ++w1;
+            }
+            if (winst[w0] >= 0) {
+                double* dg = D.diag + winst[w0] * 8;
+                for (int q = 0; q < 5; ++q)
+                    if (acc[q] != 0.0) atomicAdd(dg + 1 + q, acc[q]);
+            }
+            w0 = w1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// element-wise entry points
+
+__global__ void k_eval_phi(int n, const double* T, int G, const double* nu, double a, double c, double* out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= (int64_t)n * G) return;
+    const int i = (int)(j / G), g = (int)(j % G);
+    out[j] = phi_group_direct(T[i], nu[g], nu[g + 1], a, c);
+}
+
+__global__ void k_eval_coef(int n, const double* s, double* c4, double* w, double* c2)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    c4[j] = coef_c4(s[j]);
+    w[j] = coef_w(s[j]);
+    c2[j] = coef_c2_over_dt(s[j]);
+}
+
+__global__ void k_eval_uniform(int n, uint64_t seed, const uint64_t* id, uint32_t step, uint32_t purpose,
+                               const uint32_t* d, double* out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    out[j] = keyed_uniform(seed, id[j], step, purpose, d[j]);
+}
+
+__global__ void k_eval_sample_nu(int n, const double* nl, const double* nh, const double* T, const double* U,
+                                 double* beta, double* nu)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double b = freq_slope(nl[j], nh[j], T[j]);
+    beta[j] = b;
+    nu[j] = sample_nu(nl[j], nh[j], b, U[j]);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static inline unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t set_head_series(const HeadSeries& hs)
+{
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_head), &hs, sizeof(HeadSeries));
+}
+
+void launch_tables(const Dev& D, const Consts& K, hipStream_t st)
+{
+    k_tables<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K);
+}
+
+void launch_face_D(const Dev& D, const Consts& K, int inst, int axis, int64_t nslots, hipStream_t st)
+{
+    if (nslots > 0) k_face_D<<<blocks(nslots, 256), 256, 0, st>>>(D, K, inst, axis);
+}
+
+void launch_ghost_phi(const Dev& D, const Consts& K, double* phib, hipStream_t st)
+{
+    k_ghost_phi<<<K.n_inst, 4 * MAX_G, 0, st>>>(D, K, phib);
+}
+
+void launch_init_rho(const Dev& D, const Consts& K, const double* Tr0, hipStream_t st)
+{
+    k_init_rho<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K, Tr0);
+}
+
+void launch_count(const Dev& D, const Consts& K, hipStream_t st)
+{
+    k_count<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K);
+}
+
+int64_t scan_partials_size(int64_t n) { return (n + SCAN_CHUNK - 1) / SCAN_CHUNK; }
+
+void launch_scan(const int32_t* in, int64_t n, int64_t* part, int64_t* out, int64_t* total, hipStream_t st)
+{
+    const int64_t nb = scan_partials_size(n);
+    k_scan_partials<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, n, part);
+    k_scan_top<<<1, SCAN_THREADS, 0, st>>>(part, nb, total);
+    k_scan_final<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, n, part, out);
+}
+
+void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, int64_t base, int64_t total,
+                   uint32_t step, hipStream_t st)
+{
+    if (total <= 0) return;
+    if (dim == 1) k_sample<1><<<blocks(total, 256), 256, 0, st>>>(D, K, P, base, total, step);
+    else k_sample<2><<<blocks(total, 256), 256, 0, st>>>(D, K, P, base, total, step);
+}
+
+void launch_push(int dim, const Dev& D, const Consts& K, const Pool& A, const Pool& B, int64_t n_alive,
+                 int64_t n_total, uint32_t step, hipStream_t st)
+{
+    if (n_total <= 0) return;
+    const unsigned nb = blocks(n_total, PUSH_THREADS * PUSH_PPT);
+    const bool single = K.n_inst == 1;
+    if (dim == 1) {
+        if (single) k_push<1, true><<<nb, PUSH_THREADS, 0, st>>>(D, K, A, B, n_alive, n_total, step);
+        else k_push<1, false><<<nb, PUSH_THREADS, 0, st>>>(D, K, A, B, n_alive, n_total, step);
+    } else {
+        if (single) k_push<2, true><<<nb, PUSH_THREADS, 0, st>>>(D, K, A, B, n_alive, n_total, step);
+        else k_push<2, false><<<nb, PUSH_THREADS, 0, st>>>(D, K, A, B, n_alive, n_total, step);
+    }
+}
+
+void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& B, const Pool& A, int64_t n_max,
+                         hipStream_t st)
+{
+    if (n_max <= 0) return;
+    const unsigned nb = blocks(n_max, 256);
+    const bool single = K.n_inst == 1;
+    if (dim == 1) {
+        if (single) k_sort_scatter<1, true><<<nb, 256, 0, st>>>(D, K, B, A);
+        else k_sort_scatter<1, false><<<nb, 256, 0, st>>>(D, K, B, A);
+    } else {
+        if (single) k_sort_scatter<2, true><<<nb, 256, 0, st>>>(D, K, B, A);
+        else k_sort_scatter<2, false><<<nb, 256, 0, st>>>(D, K, B, A);
+    }
+}
+
+void launch_wave_source(const Dev& D, const Consts& K, hipStream_t st)
+{
+    k_wave_source<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K);
+}
+
+void launch_si_init(const Dev& D, const Consts& K, hipStream_t st)
+{
+    k_si_init<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K);
+}
+
+void launch_si_sweep(const Dev& D, const Consts& K, int k, bool check_only, hipStream_t st)
+{
+    const double* pin = (k & 1) ? D.phi1 : D.phi0;
+    double* pout = (k & 1) ? D.phi0 : D.phi1;
+    k_si_sweep<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, pin, pout, check_only ? 1 : 0);
+}
+
+void launch_commit(const Dev& D, const Consts& K, hipStream_t st)
+{
+    k_commit<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K);
+}
+
+void launch_diag(const Dev& D, const Consts& K, hipStream_t st)
+{
+    k_diag<<<blocks(K.n_cg, DIAG_THREADS), DIAG_THREADS, 0, st>>>(D, K);
+}
+
+void launch_eval_phi(int n, const double* T, int G, const double* nu, double a, double c, double* out,
+                     hipStream_t st)
+{
+    k_eval_phi<<<blocks((int64_t)n * G, 256), 256, 0, st>>>(n, T, G, nu, a, c, out);
+}
+
+void launch_eval_coef(int n, const double* s, double* c4, double* w, double* c2, hipStream_t st)
+{
+    k_eval_coef<<<blocks(n, 256), 256, 0, st>>>(n, s, c4, w, c2);
+}
+
+void launch_eval_uniform(int n, uint64_t seed, const uint64_t* id, uint32_t step, uint32_t purpose,
+                         const uint32_t* d, double* out, hipStream_t st)
+{
+    k_eval_uniform<<<blocks(n, 256), 256, 0, st>>>(n, seed, id, step, purpose, d, out);
+}
+
+void launch_eval_sample_nu(int n, const double* nl, const double* nh, const double* T, const double* U,
+                           double* beta, double* nu, hipStream_t st)
+{
+    k_eval_sample_nu<<<blocks(n, 256), 256, 0, st>>>(n, nl, nh, T, U, beta, nu);
+}
+
+}  // namespace ugk

@@ -1,0 +1,37 @@
+// Launchers of the UGKWP kernels (kernels.hip), called by the host runtime.
+#pragma once
+#include "common.hpp"
+#include "device_math.hpp"
+
+namespace ugk {
+
+hipError_t set_head_series(const HeadSeries& hs);
+
+void launch_tables(const Dev& D, const Consts& K, hipStream_t st);
+void launch_face_D(const Dev& D, const Consts& K, int inst, int axis, int64_t nslots, hipStream_t st);
+void launch_ghost_phi(const Dev& D, const Consts& K, double* phib, hipStream_t st);
+void launch_init_rho(const Dev& D, const Consts& K, const double* Tr0, hipStream_t st);
+void launch_count(const Dev& D, const Consts& K, hipStream_t st);
+int64_t scan_partials_size(int64_t n);
+void launch_scan(const int32_t* in, int64_t n, int64_t* part, int64_t* out, int64_t* total, hipStream_t st);
+void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, int64_t base, int64_t total,
+                   uint32_t step, hipStream_t st);
+void launch_push(int dim, const Dev& D, const Consts& K, const Pool& A, const Pool& B, int64_t n_alive,
+                 int64_t n_total, uint32_t step, hipStream_t st);
+void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& B, const Pool& A, int64_t n_max,
+                         hipStream_t st);
+void launch_wave_source(const Dev& D, const Consts& K, hipStream_t st);
+void launch_si_init(const Dev& D, const Consts& K, hipStream_t st);
+void launch_si_sweep(const Dev& D, const Consts& K, int k, bool check_only, hipStream_t st);
+void launch_commit(const Dev& D, const Consts& K, hipStream_t st);
+void launch_diag(const Dev& D, const Consts& K, hipStream_t st);
+
+void launch_eval_phi(int n, const double* T, int G, const double* nu, double a, double c, double* out,
+                     hipStream_t st);
+void launch_eval_coef(int n, const double* s, double* c4, double* w, double* c2, hipStream_t st);
+void launch_eval_uniform(int n, uint64_t seed, const uint64_t* id, uint32_t step, uint32_t purpose,
+                         const uint32_t* d, double* out, hipStream_t st);
+void launch_eval_sample_nu(int n, const double* nl, const double* nh, const double* T, const double* U,
+                           double* beta, double* nu, hipStream_t st);
+
+}  // namespace ugk

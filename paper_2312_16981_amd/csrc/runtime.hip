@@ -1,0 +1,964 @@
+// Host runtime of the UGKWP library: validation, device memory, the per-step
+// launch sequence of Algorithm 1, and the C ABI declared in include/ugkwp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ugkwp.h"
+#include "common.hpp"
+#include "device_math.hpp"
+#include "kernels.hpp"
+
+using namespace ugk;
+
+namespace {
+
+struct HipError {
+    hipError_t e;
+    const char* what;
+};
+
+#define HIPCHK(x)                                          \
+    do {                                                   \
+        hipError_t e_ = (x);                               \
+        if (e_ != hipSuccess) throw HipError{e_, #x};      \
+    } while (0)
+
+struct ApiError {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw ApiError{code, buf};
+}
+
+// Taylor coefficients of int_0^x t^3/(e^t-1) dt beyond x^3/3 - x^4/8:
+// c_j multiplies x^(5+2j) and equals B_{2k} / ((2k)! (2k+3)), k = j+1, with
+// B_{2k}/(2k)! = (-1)^{k+1} 2 zeta(2k) / (2 pi)^{2k}.  zeta(2k) is summed directly
+// (closed forms for k = 1, 2) in long double.
+HeadSeries make_head_series()
+{
+    HeadSeries hs;
+    hs.nterm = 24;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int j = 0; j < hs.nterm; ++j) {
+        const int k = j + 1;
+        long double zeta;
+        if (k == 1) zeta = pi * pi / 6.0L;
+        else if (k == 2) zeta = pi * pi * pi * pi / 90.0L;
+        else {
+            zeta = 0.0L;
+            const int N = 4000;
+            for (int n = N; n >= 1; --n) zeta += powl((long double)n, -2.0L * k);
+            zeta += powl((long double)N, 1.0L - 2.0L * k) / (2.0L * k - 1.0L) - 0.5L * powl((long double)N, -2.0L * k);
+        }
+        long double v = 2.0L * zeta / powl(2.0L * pi, 2.0L * k) / (2.0L * k + 3.0L);
+        if (!(k & 1)) v = -v;
+        hs.c[j] = (double)v;
+    }
+    return hs;
+}
+
+bool g_head_ready = false;
+
+void ensure_head_series()
+{
+    if (!g_head_ready) {
+        HIPCHK(set_head_series(make_head_series()));
+        g_head_ready = true;
+    }
+}
+
+struct HostInst {
+    int dim = 1, nx = 0, ny = 1;
+    double x0 = 0, x1 = 1, y0 = 0, y1 = 1;
+    int bc[4] = {0, 0, 0, 0};
+    double bcT[4] = {0, 0, 0, 0};
+    int G = 0;
+    std::vector<double> edges;
+    uint64_t seed = 0;
+    double w_ref = 0;
+};
+
+int next_pow2(int g)
+{
+    int p = 1;
+    while (p < g) p <<= 1;
+    return p;
+}
+
+int ilog2(int p)
+{
+    int l = 0;
+    while ((1 << l) < p) ++l;
+    return l;
+}
+
+template <class T>
+T* dalloc(std::vector<void*>& owned, size_t n)
+{
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) fail(UGKWP_ENOMEM, "hipMalloc of %zu bytes failed", n * sizeof(T));
+    owned.push_back(p);
+    return (T*)p;
+}
+
+}  // namespace
+
+struct ugkwp_ctx {
+    ugkwp_params P{};
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    // geometry
+    int dim = 0, n_inst = 0;
+    std::vector<HostInst> hi;
+    std::vector<Inst> inst;
+    std::vector<int64_t> inst_cg;
+    Consts K{};
+    int ncell = 0;
+    int64_t n_fx = 0, n_fy = 0, n_edges = 0;
+
+    // device state
+    std::vector<void*> owned;
+    Dev D{};
+    Pool pool[2]{};
+    int cur = 0;
+    int64_t n_alive = 0;
+    uint32_t step_idx = 0;
+    bool have_opacity = false, have_material = false;
+    int64_t* part = nullptr;
+    int64_t n_part = 0;
+    double* d_phib = nullptr;
+
+    // host staging (pinned)
+    int64_t* h_total = nullptr;
+    unsigned long long* h_counters = nullptr;
+    InstState* h_ist = nullptr;
+    double* h_diag = nullptr;
+    hipEvent_t ev[7]{};
+    int last_sweeps = 4;
+    ugkwp_diag diag{};
+
+    ~ugkwp_ctx() { release(); }
+
+    void release()
+    {
+        for (void* p : owned) (void)hipFree(p);
+        owned.clear();
+        if (h_total) (void)hipHostFree(h_total);
+        if (h_counters) (void)hipHostFree(h_counters);
+        if (h_ist) (void)hipHostFree(h_ist);
+        if (h_diag) (void)hipHostFree(h_diag);
+        h_total = nullptr; h_counters = nullptr; h_ist = nullptr; h_diag = nullptr;
+        for (auto& e : ev)
+            if (e) { (void)hipEventDestroy(e); e = nullptr; }
+        if (own_stream && st) (void)hipStreamDestroy(st);
+        st = nullptr;
+        own_stream = false;
+    }
+
+    void free_device()
+    {
+        for (void* p : owned) (void)hipFree(p);
+        owned.clear();
+        D = Dev{};
+        pool[0] = pool[1] = Pool{};
+        have_opacity = have_material = false;
+    }
+
+    // ---------------------------------------------------------------- set-up
+    void setup(const std::vector<HostInst>& in)
+    {
+        ensure_head_series();
+        if (in.empty()) fail(UGKWP_EINVAL, "no instances");
+        const int d0 = in[0].dim;
+        for (const auto& h : in) {
+            if (h.dim != 1 && h.dim != 2) fail(UGKWP_EINVAL, "dim must be 1 or 2");
+            if (h.dim != d0) fail(UGKWP_EINVAL, "all instances of a context share one dimension");
+            if (h.nx < 1 || h.ny < 1 || (h.dim == 1 && h.ny != 1)) fail(UGKWP_EINVAL, "bad cell counts");
+            if (!(h.x1 > h.x0) || (h.dim == 2 && !(h.y1 > h.y0))) fail(UGKWP_EINVAL, "empty domain");
+            if (h.G < 1 || h.G > MAX_G) fail(UGKWP_EINVAL, "G must be in 1..%d", MAX_G);
+            for (int g = 0; g < h.G; ++g)
+                if (!(h.edges[g] > 0) || !(h.edges[g + 1] > h.edges[g]) || !std::isfinite(h.edges[g + 1]))
+                    fail(UGKWP_EINVAL, "group edges must be positive, finite and ascending");
+            for (int q = 0; q < 2 * h.dim; ++q) {
+                if (h.bc[q] < 0 || h.bc[q] > 2) fail(UGKWP_EINVAL, "bad boundary type");
+                if (h.bc[q] == UGKWP_BC_PLANCK && !(h.bcT[q] > 0 && std::isfinite(h.bcT[q])))
+                    fail(UGKWP_EINVAL, "Planckian boundary temperature must be positive");
+            }
+            if (!(h.w_ref > 0)) fail(UGKWP_EINVAL, "w_ref must be positive");
+            if ((int64_t)h.nx * h.ny > (1 << 28)) fail(UGKWP_EINVAL, "too many cells");
+        }
+        {
+            // tally bins are addressed with 30-bit indices in the push's LDS table
+            int64_t cg = 0, fx = 0, fy = 0;
+            for (const auto& h : in) {
+                const int64_t gp = next_pow2(h.G);
+                cg += (int64_t)h.nx * h.ny * gp + WAVE;
+                fx += (int64_t)(h.nx + 1) * h.ny * gp;
+                if (h.dim == 2) fy += (int64_t)h.nx * (h.ny + 1) * gp;
+            }
+            if (cg >= (1ll << 30) || 2 * fx >= (1ll << 30) || 2 * fy >= (1ll << 30))
+                fail(UGKWP_EINVAL, "mesh too large for one context (more than 2^30 cell-group or face slots)");
+        }
+        free_device();
+        dim = d0;
+        n_inst = (int)in.size();
+        hi = in;
+        inst.assign(n_inst, Inst{});
+        inst_cg.assign(n_inst + 1, 0);
+        int64_t cg = 0, fx = 0, fy = 0, ed = 0;
+        int cells = 0;
+        for (int k = 0; k < n_inst; ++k) {
+            const HostInst& h = in[k];
+            Inst& I = inst[k];
+            I.dim = h.dim; I.nx = h.nx; I.ny = h.ny; I.ncell = h.nx * h.ny;
+            I.G = h.G; I.Gp = next_pow2(h.G); I.lgGp = ilog2(I.Gp);
+            I.cell_off = cells;
+            I.edge_off = (int)ed;
+            for (int q = 0; q < 4; ++q) { I.bc[q] = h.bc[q]; I.bcT[q] = h.bcT[q]; }
+            cg = (cg + WAVE - 1) / WAVE * WAVE;
+            I.cg_off = cg;
+            inst_cg[k] = cg;
+            cg += (int64_t)I.ncell * I.Gp;
+            I.fx_off = fx;
+            fx += (int64_t)(h.nx + 1) * h.ny * I.Gp;
+            I.fy_off = fy;
+            if (h.dim == 2) fy += (int64_t)h.nx * (h.ny + 1) * I.Gp;
+            I.x0 = h.x0; I.y0 = h.dim == 2 ? h.y0 : 0.0;
+            I.dx = (h.x1 - h.x0) / h.nx;
+            I.dy = h.dim == 2 ? (h.y1 - h.y0) / h.ny : 1.0;
+            I.V = I.dx * I.dy;
+            I.w_ref = h.w_ref;
+            I.seed = h.seed;
+            cells += I.ncell;
+            ed += h.G + 1;
+        }
+        const int64_t n_cg = (cg + WAVE - 1) / WAVE * WAVE;
+        inst_cg[n_inst] = n_cg;
+        ncell = cells;
+        n_fx = fx; n_fy = fy; n_edges = ed;
+
+        K.c = P.c; K.a = P.a; K.eps = P.eps; K.dt = P.dt;
+        K.e2c = P.eps * P.eps / P.c;
+        K.cv = P.c / P.eps;
+        K.lam_scale = P.c * P.dt / (P.eps * P.eps);
+        K.nu_power = P.nu_power;
+        K.si_tol = P.si_tol;
+        K.n_cap = P.n_cap;
+        K.flags = P.flags;
+        K.n_inst = n_inst;
+        K.n_cg = n_cg;
+        K.n_fx2 = 2 * fx;
+        K.ncell = ncell;
+
+        // device memory
+        std::vector<double> edges, simpson;
+        for (const auto& h : in) {
+            for (int g = 0; g <= h.G; ++g) edges.push_back(h.edges[g]);
+            for (int g = 0; g < h.G; ++g) {
+                const double nl = h.edges[g], nh = h.edges[g + 1], nm = 0.5 * (nl + nh);
+                simpson.push_back((nu_pow(nl, P.nu_power) + 4.0 * nu_pow(nm, P.nu_power) + nu_pow(nh, P.nu_power)) / 6.0);
+            }
+            simpson.push_back(0.0);
+        }
+        std::vector<int32_t> cell_inst(ncell);
+        for (int k = 0; k < n_inst; ++k)
+            for (int c = 0; c < inst[k].ncell; ++c) cell_inst[inst[k].cell_off + c] = k;
+
+        Inst* d_inst = dalloc<Inst>(owned, n_inst);
+        int64_t* d_inst_cg = dalloc<int64_t>(owned, n_inst + 1);
+        int32_t* d_cell_inst = dalloc<int32_t>(owned, ncell);
+        double* d_nu = dalloc<double>(owned, edges.size());
+        double* d_simp = dalloc<double>(owned, simpson.size());
+        d_phib = dalloc<double>(owned, (size_t)n_inst * 4 * MAX_G);
+        HIPCHK(hipMemcpy(d_inst, inst.data(), sizeof(Inst) * n_inst, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_inst_cg, inst_cg.data(), sizeof(int64_t) * (n_inst + 1), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_cell_inst, cell_inst.data(), sizeof(int32_t) * ncell, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_nu, edges.data(), sizeof(double) * edges.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_simp, simpson.data(), sizeof(double) * simpson.size(), hipMemcpyHostToDevice));
+
+        Dev& d = D;
+        d = Dev{};
+        d.inst = d_inst;
+        d.inst_cg = d_inst_cg;
+        d.cell_inst = d_cell_inst;
+        d.nu = d_nu;
+        d.simpson = d_simp;
+        d.phib = d_phib;
+        const size_t ncg = (size_t)n_cg;
+        d.kappa = dalloc<double>(owned, ncg);
+        d.sig = dalloc<double>(owned, ncg);
+        d.sv = dalloc<double>(owned, ncg);
+        d.es = dalloc<double>(owned, ncg);
+        d.c4 = dalloc<double>(owned, ncg);
+        d.wc = dalloc<double>(owned, ncg);
+        d.rho = dalloc<double>(owned, ncg);
+        d.rho_new = dalloc<double>(owned, ncg);
+        d.rhop = dalloc<double>(owned, ncg);
+        d.rhoh = dalloc<double>(owned, ncg);
+        d.Q = dalloc<double>(owned, ncg);
+        d.phi0 = dalloc<double>(owned, ncg);
+        d.phi1 = dalloc<double>(owned, ncg);
+        d.nb = dalloc<int32_t>(owned, ncg);
+        d.boff = dalloc<int64_t>(owned, ncg + 1);
+        d.wnew = dalloc<double>(owned, ncg);
+        d.beta = dalloc<double>(owned, ncg);
+        d.dep = dalloc<double>(owned, ncg);
+        d.surv = dalloc<double>(owned, ncg);
+        d.scount = dalloc<uint32_t>(owned, ncg);
+        d.soff = dalloc<int64_t>(owned, ncg + 1);
+        d.ftx = dalloc<double>(owned, (size_t)n_fx * 2);
+        d.fty = dalloc<double>(owned, (size_t)std::max<int64_t>(n_fy, 1) * 2);
+        d.Dx = dalloc<double>(owned, (size_t)n_fx);
+        d.Dy = dalloc<double>(owned, (size_t)std::max<int64_t>(n_fy, 1));
+        d.cvol = dalloc<double>(owned, ncell);
+        d.T = dalloc<double>(owned, ncell);
+        d.T_new = dalloc<double>(owned, ncell);
+        d.pinned = dalloc<uint8_t>(owned, ncell);
+        d.ist = dalloc<InstState>(owned, n_inst);
+        d.res = dalloc<Resid>(owned, (size_t)n_inst * RES_SLOTS);
+        d.diag = dalloc<double>(owned, (size_t)n_inst * 8);
+        d.counters = dalloc<unsigned long long>(owned, 8);
+        d.n_births_total = dalloc<int64_t>(owned, 2);
+        n_part = scan_partials_size(n_cg);
+        part = dalloc<int64_t>(owned, (size_t)n_part + 1);
+        HIPCHK(hipMemsetAsync(d.ist, 0, sizeof(InstState) * n_inst, st));
+        HIPCHK(hipMemsetAsync((void*)d.boff, 0, sizeof(int64_t) * (ncg + 1), st));
+        HIPCHK(hipMemsetAsync(d.ftx, 0, sizeof(double) * n_fx * 2, st));
+        HIPCHK(hipMemsetAsync(d.fty, 0, sizeof(double) * std::max<int64_t>(n_fy, 1) * 2, st));
+        HIPCHK(hipMemsetAsync(d.dep, 0, sizeof(double) * ncg, st));
+        HIPCHK(hipMemsetAsync(d.surv, 0, sizeof(double) * ncg, st));
+        HIPCHK(hipMemsetAsync(d.nb, 0, sizeof(int32_t) * ncg, st));
+        HIPCHK(hipMemsetAsync(d.wnew, 0, sizeof(double) * ncg, st));
+        HIPCHK(hipMemsetAsync(d.Q, 0, sizeof(double) * ncg, st));
+        HIPCHK(hipMemsetAsync(d.rhoh, 0, sizeof(double) * ncg, st));
+        launch_ghost_phi(D, K, d_phib, st);
+
+        const int64_t cap = std::max<int64_t>(P.pool_capacity, 1);
+        for (int b = 0; b < 2; ++b) {
+            Pool& p = pool[b];
+            p.x = dalloc<double>(owned, cap);
+            p.ox = dalloc<double>(owned, cap);
+            if (dim == 2) {
+                p.y = dalloc<double>(owned, cap);
+                p.oy = dalloc<double>(owned, cap);
+            }
+            p.nu = dalloc<double>(owned, cap);
+            p.w = dalloc<double>(owned, cap);
+            p.id = dalloc<uint64_t>(owned, cap);
+            p.cell = dalloc<int32_t>(owned, cap);
+            p.g = dalloc<int32_t>(owned, cap);
+        }
+        cur = 0;
+        n_alive = 0;
+        step_idx = 0;
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipGetLastError());
+    }
+
+    // pack a host [ncell][G] array of instance k into the padded device layout
+    void pack_cg(std::vector<double>& dst, int k, const double* src) const
+    {
+        const Inst& I = inst[k];
+        for (int c = 0; c < I.ncell; ++c)
+            for (int g = 0; g < I.G; ++g) dst[I.cg_off + ((int64_t)c << I.lgGp) + g] = src[(int64_t)c * I.G + g];
+    }
+
+    void set_opacity(const std::vector<const double*>& kap)
+    {
+        std::vector<double> h((size_t)K.n_cg, 0.0);
+        for (int k = 0; k < n_inst; ++k) {
+            const Inst& I = inst[k];
+            for (int64_t q = 0; q < (int64_t)I.ncell * I.G; ++q)
+                if (!(kap[k][q] >= 0.0) || !std::isfinite(kap[k][q])) fail(UGKWP_EINVAL, "kappa must be finite and >= 0");
+            pack_cg(h, k, kap[k]);
+        }
+        HIPCHK(hipMemcpyAsync((void*)D.kappa, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, st));
+        launch_tables(D, K, st);
+        for (int k = 0; k < n_inst; ++k) {
+            const Inst& I = inst[k];
+            launch_face_D(D, K, k, 0, (int64_t)(I.nx + 1) * I.ny * I.Gp, st);
+            if (dim == 2) launch_face_D(D, K, k, 1, (int64_t)I.nx * (I.ny + 1) * I.Gp, st);
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipGetLastError());
+        have_opacity = true;
+    }
+
+    void set_material(const std::vector<const double*>& cv, const std::vector<const double*>& T0,
+                      const std::vector<const double*>& Tr0, const std::vector<const uint8_t*>& pinned)
+    {
+        std::vector<double> hcv(ncell), hT(ncell), hTr(ncell);
+        std::vector<uint8_t> hp(ncell, 0);
+        for (int k = 0; k < n_inst; ++k) {
+            const Inst& I = inst[k];
+            for (int c = 0; c < I.ncell; ++c) {
+                const double a = cv[k][c], b = T0[k][c], r = Tr0[k][c];
+                if (!(a > 0) || !(b > 0) || !(r > 0) || !std::isfinite(a) || !std::isfinite(b) || !std::isfinite(r))
+                    fail(UGKWP_EINVAL, "cv, T0 and Tr0 must be positive and finite");
+                hcv[I.cell_off + c] = a;
+                hT[I.cell_off + c] = b;
+                hTr[I.cell_off + c] = r;
+                hp[I.cell_off + c] = pinned[k] ? (pinned[k][c] ? 1 : 0) : 0;
+            }
+        }
+        double* d_tr = nullptr;
+        HIPCHK(hipMalloc(&d_tr, sizeof(double) * ncell));
+        HIPCHK(hipMemcpyAsync((void*)D.cvol, hcv.data(), sizeof(double) * ncell, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(D.T, hT.data(), sizeof(double) * ncell, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync((void*)D.pinned, hp.data(), ncell, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(d_tr, hTr.data(), sizeof(double) * ncell, hipMemcpyHostToDevice, st));
+        launch_init_rho(D, K, d_tr, st);
+        HIPCHK(hipMemsetAsync(D.ist, 0, sizeof(InstState) * n_inst, st));
+        HIPCHK(hipStreamSynchronize(st));
+        (void)hipFree(d_tr);
+        HIPCHK(hipGetLastError());
+        n_alive = 0;
+        step_idx = 0;
+        cur = 0;
+        have_material = true;
+    }
+
+    // ---------------------------------------------------------------- one step
+    int step_once()
+    {
+        const Pool& A = pool[cur];
+        const Pool& B = pool[1 - cur];
+        HIPCHK(hipEventRecord(ev[0], st));
+        launch_count(D, K, st);
+        launch_scan(D.nb, K.n_cg, part, D.boff, D.n_births_total, st);
+        HIPCHK(hipMemcpyAsync(h_total, D.n_births_total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const int64_t births = *h_total;
+        if (n_alive + births > P.pool_capacity)
+            fail(UGKWP_EPOOL, "particle pool capacity %lld exceeded (%lld alive + %lld births)",
+                 (long long)P.pool_capacity, (long long)n_alive, (long long)births);
+        launch_sample(dim, D, K, A, n_alive, births, step_idx, st);
+        HIPCHK(hipMemsetAsync(D.ftx, 0, sizeof(double) * n_fx * 2, st));
+        if (dim == 2) HIPCHK(hipMemsetAsync(D.fty, 0, sizeof(double) * n_fy * 2, st));
+        HIPCHK(hipMemsetAsync(D.dep, 0, sizeof(double) * K.n_cg, st));
+        HIPCHK(hipMemsetAsync(D.surv, 0, sizeof(double) * K.n_cg, st));
+        HIPCHK(hipMemsetAsync(D.counters, 0, sizeof(unsigned long long) * 8, st));
+        HIPCHK(hipMemsetAsync(D.diag, 0, sizeof(double) * 8 * n_inst, st));
+        HIPCHK(hipMemsetAsync(D.scount, 0, sizeof(uint32_t) * K.n_cg, st));
+        HIPCHK(hipEventRecord(ev[1], st));
+        launch_push(dim, D, K, A, B, n_alive, n_alive + births, step_idx, st);
+        HIPCHK(hipEventRecord(ev[2], st));
+        launch_wave_source(D, K, st);
+        launch_si_init(D, K, st);
+        HIPCHK(hipEventRecord(ev[3], st));
+
+        // source iteration: sweeps are launched in chunks; the convergence test of
+        // sweep k is evaluated on the device at the start of sweep k+1
+        const int kmax = P.si_max_iters;
+        int k = 0;
+        int chunk = std::max(2, last_sweeps + 1);
+        bool done = false;
+        int status = UGKWP_OK;
+        while (!done) {
+            const int kend = std::min(k + chunk, kmax + 1);
+            for (; k < kend; ++k) launch_si_sweep(D, K, k, k == kmax, st);
+            HIPCHK(hipMemcpyAsync(h_ist, D.ist, sizeof(InstState) * n_inst, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            bool all = true, bad = false;
+            for (int q = 0; q < n_inst; ++q) {
+                if (h_ist[q].bad) bad = true;
+                if (h_ist[q].conv_sweeps == 0) all = false;
+            }
+            if (bad) { status = UGKWP_ENONFINITE; break; }
+            if (all) { done = true; break; }
+            if (k > kmax) { status = UGKWP_ENOCONV; break; }
+            chunk = 2;
+        }
+        HIPCHK(hipEventRecord(ev[4], st));
+        if (status == UGKWP_ENONFINITE) fail(status, "source iteration produced a non-positive or non-finite temperature");
+        if (status == UGKWP_ENOCONV) fail(status, "source iteration did not converge in %d sweeps", kmax);
+
+        launch_diag(D, K, st);
+        launch_commit(D, K, st);
+        // keep the pool sorted by (cell, group) slot: survivors B -> A
+        HIPCHK(hipEventRecord(ev[5], st));
+        launch_scan((const int32_t*)D.scount, K.n_cg, part, D.soff, D.n_births_total + 1, st);
+        launch_sort_scatter(dim, D, K, B, A, n_alive + births, st);
+        HIPCHK(hipEventRecord(ev[6], st));
+        HIPCHK(hipMemcpyAsync(h_counters, D.counters, sizeof(unsigned long long) * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h_diag, D.diag, sizeof(double) * 8 * n_inst, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipGetLastError());
+
+        // bookkeeping of the committed step
+        ugkwp_diag dg{};
+        dg.n_alive_in = n_alive;
+        dg.n_births = births;
+        dg.n_pushed = n_alive + births;
+        dg.n_alive_out = (int64_t)h_counters[0];
+        int smax = 0, ssum = 0;
+        for (int q = 0; q < n_inst; ++q) {
+            smax = std::max(smax, h_ist[q].conv_sweeps);
+            ssum += h_ist[q].conv_sweeps;
+            const double* g = h_diag + 8 * q;
+            dg.inflow_wave += g[0];
+            dg.inflow_eq += g[1];
+            dg.exit_particles += g[2];
+            dg.injection += g[3];
+            dg.e_start += g[4];
+            dg.e_end += g[5];
+        }
+        dg.sweeps_max = smax;
+        dg.sweeps_sum = ssum;
+        dg.residual = dg.e_end - dg.e_start - (dg.inflow_wave + dg.inflow_eq - dg.exit_particles + dg.injection);
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1])); dg.ms_sample = ms;
+        HIPCHK(hipEventElapsedTime(&ms, ev[1], ev[2])); dg.ms_push = ms;
+        HIPCHK(hipEventElapsedTime(&ms, ev[2], ev[3])); dg.ms_macro = ms;
+        HIPCHK(hipEventElapsedTime(&ms, ev[3], ev[4])); dg.ms_si = ms;
+        HIPCHK(hipEventElapsedTime(&ms, ev[5], ev[6])); dg.ms_sort = ms;
+        if (h_counters[2])
+            fail(UGKWP_EHIP, "internal error %llu: particle records or survivor counts inconsistent",
+                 (unsigned long long)h_counters[2]);
+        diag = dg;
+        last_sweeps = smax;
+
+        std::swap(D.rho, D.rho_new);
+        std::swap(D.T, D.T_new);
+        n_alive = dg.n_alive_out;
+        step_idx++;
+        return UGKWP_OK;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+namespace {
+
+template <class F>
+int guarded(ugkwp_ctx* c, F&& f)
+{
+    try {
+        f();
+        if (c) c->err.clear();
+        return UGKWP_OK;
+    } catch (const ApiError& e) {
+        if (c) c->err = e.msg;
+        return e.code;
+    } catch (const HipError& e) {
+        if (c) c->err = std::string(e.what) + ": " + hipGetErrorString(e.e);
+        return UGKWP_EHIP;
+    } catch (const std::bad_alloc&) {
+        if (c) c->err = "host allocation failed";
+        return UGKWP_ENOMEM;
+    }
+}
+
+void require_ready(const ugkwp_ctx* c)
+{
+    if (c->n_inst == 0) fail(UGKWP_EINVAL, "mesh not initialised");
+    if (!c->have_opacity) fail(UGKWP_EINVAL, "opacity not set");
+    if (!c->have_material) fail(UGKWP_EINVAL, "material not set");
+}
+
+void check_inst(const ugkwp_ctx* c, int k)
+{
+    if (c->n_inst == 0) fail(UGKWP_EINVAL, "mesh not initialised");
+    if (k < 0 || k >= c->n_inst) fail(UGKWP_EINVAL, "instance %d out of range", k);
+}
+
+void copy_rows(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width, size_t rows,
+               hipMemcpyKind kind, hipStream_t st)
+{
+    if (rows == 0 || width == 0) return;
+    HIPCHK(hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, kind, st));
+}
+
+}  // namespace
+
+namespace {
+struct Tmp {
+    std::vector<void*> p;
+    ~Tmp() { for (void* q : p) (void)hipFree(q); }
+    template <class T>
+    T* up(const T* h, size_t n)
+    {
+        void* d = nullptr;
+        HIPCHK(hipMalloc(&d, std::max<size_t>(n, 1) * sizeof(T)));
+        p.push_back(d);
+        if (h && n) HIPCHK(hipMemcpy(d, h, n * sizeof(T), hipMemcpyHostToDevice));
+        return (T*)d;
+    }
+};
+}  // namespace
+
+extern "C" {
+
+int ugkwp_create(ugkwp_ctx** out, const ugkwp_params* p, void* hip_stream)
+{
+    if (!out || !p) return UGKWP_EINVAL;
+    *out = nullptr;
+    if (!(p->c > 0) || !(p->a > 0) || !(p->eps > 0) || !(p->dt > 0) || !std::isfinite(p->dt) ||
+        !(p->si_tol >= 0) || p->si_max_iters < 1 || p->pool_capacity < 0 || p->n_cap < 0 ||
+        p->n_cap > (1 << 30) || !(p->nu_power >= 0))
+        return UGKWP_EINVAL;
+    ugkwp_ctx* c = new (std::nothrow) ugkwp_ctx();
+    if (!c) return UGKWP_ENOMEM;
+    c->P = *p;
+    int rc = guarded(c, [&] {
+        if (hip_stream) c->st = (hipStream_t)hip_stream;
+        else {
+            HIPCHK(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+        HIPCHK(hipHostMalloc((void**)&c->h_total, sizeof(int64_t), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&c->h_counters, sizeof(unsigned long long) * 8, hipHostMallocDefault));
+        for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+    });
+    if (rc) { delete c; return rc; }
+    *out = c;
+    return UGKWP_OK;
+}
+
+void ugkwp_destroy(ugkwp_ctx* ctx)
+{
+    if (!ctx) return;
+    if (ctx->st) (void)hipStreamSynchronize(ctx->st);
+    delete ctx;
+}
+
+const char* ugkwp_last_error(const ugkwp_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+static int alloc_host_status(ugkwp_ctx* c)
+{
+    if (c->h_ist) (void)hipHostFree(c->h_ist);
+    if (c->h_diag) (void)hipHostFree(c->h_diag);
+    c->h_ist = nullptr; c->h_diag = nullptr;
+    HIPCHK(hipHostMalloc((void**)&c->h_ist, sizeof(InstState) * c->n_inst, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->h_diag, sizeof(double) * 8 * c->n_inst, hipHostMallocDefault));
+    return 0;
+}
+
+int ugkwp_init_mesh(ugkwp_ctx* ctx, int dim, int nx, int ny, const double lo[2], const double hi[2],
+                    const int bc[4], const double bcT[4], int G, const double* nu_edges, uint64_t seed,
+                    double w_ref)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        if (!lo || !hi || !bc || !bcT || !nu_edges) fail(UGKWP_EINVAL, "null argument");
+        if (G < 1 || G > MAX_G) fail(UGKWP_EINVAL, "G must be in 1..%d", MAX_G);
+        HostInst h;
+        h.dim = dim; h.nx = nx; h.ny = dim == 1 ? 1 : ny;
+        if (dim == 1 && ny != 1) fail(UGKWP_EINVAL, "ny must be 1 in 1-D");
+        h.x0 = lo[0]; h.x1 = hi[0]; h.y0 = lo[1]; h.y1 = hi[1];
+        for (int q = 0; q < 4; ++q) { h.bc[q] = bc[q]; h.bcT[q] = bcT[q]; }
+        h.G = G;
+        h.edges.assign(nu_edges, nu_edges + G + 1);
+        h.seed = seed;
+        h.w_ref = w_ref;
+        ctx->setup({h});
+        alloc_host_status(ctx);
+    });
+}
+
+int ugkwp_set_opacity(ugkwp_ctx* ctx, const double* kappa)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        if (ctx->n_inst != 1) fail(UGKWP_EINVAL, "set_opacity needs a single-instance context");
+        if (!kappa) fail(UGKWP_EINVAL, "null kappa");
+        ctx->set_opacity({kappa});
+    });
+}
+
+int ugkwp_set_material(ugkwp_ctx* ctx, const double* cv, const double* T0, const double* Tr0,
+                       const uint8_t* pinned)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        if (ctx->n_inst != 1) fail(UGKWP_EINVAL, "set_material needs a single-instance context");
+        if (!cv || !T0 || !Tr0) fail(UGKWP_EINVAL, "null argument");
+        ctx->set_material({cv}, {T0}, {Tr0}, {pinned});
+    });
+}
+
+int ugkwp_init_batch(ugkwp_ctx* ctx, int n_inst, const ugkwp_instance* d)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        if (n_inst < 1 || !d) fail(UGKWP_EINVAL, "need at least one instance");
+        std::vector<HostInst> hs(n_inst);
+        std::vector<const double*> kap(n_inst), cv(n_inst), T0(n_inst), Tr0(n_inst);
+        std::vector<const uint8_t*> pin(n_inst);
+        for (int k = 0; k < n_inst; ++k) {
+            const ugkwp_instance& s = d[k];
+            if (!s.nu_edges || !s.kappa || !s.cv || !s.T0 || !s.Tr0) fail(UGKWP_EINVAL, "instance %d: null array", k);
+            if (s.G < 1 || s.G > MAX_G) fail(UGKWP_EINVAL, "instance %d: G must be in 1..%d", k, MAX_G);
+            HostInst& h = hs[k];
+            h.dim = s.dim; h.nx = s.nx; h.ny = s.dim == 1 ? 1 : s.ny;
+            if (s.dim == 1 && s.ny != 1) fail(UGKWP_EINVAL, "instance %d: ny must be 1 in 1-D", k);
+            h.x0 = s.x0; h.x1 = s.x1; h.y0 = s.y0; h.y1 = s.y1;
+            for (int q = 0; q < 4; ++q) { h.bc[q] = s.bc[q]; h.bcT[q] = s.bcT[q]; }
+            h.G = s.G;
+            h.edges.assign(s.nu_edges, s.nu_edges + s.G + 1);
+            h.seed = s.seed;
+            h.w_ref = s.w_ref;
+            kap[k] = s.kappa; cv[k] = s.cv; T0[k] = s.T0; Tr0[k] = s.Tr0; pin[k] = s.pinned;
+        }
+        ctx->setup(hs);
+        alloc_host_status(ctx);
+        ctx->set_opacity(kap);
+        ctx->set_material(cv, T0, Tr0, pin);
+    });
+}
+
+int ugkwp_step(ugkwp_ctx* ctx, int nsteps)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        require_ready(ctx);
+        if (nsteps < 0) fail(UGKWP_EINVAL, "negative step count");
+        for (int n = 0; n < nsteps; ++n) ctx->step_once();
+    });
+}
+
+int ugkwp_num_instances(const ugkwp_ctx* ctx) { return ctx ? ctx->n_inst : 0; }
+
+int ugkwp_get_fields(ugkwp_ctx* ctx, int inst, double* rho, double* T, double* rhop, int dst_is_device)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        if (ctx->n_inst == 0) fail(UGKWP_EINVAL, "mesh not initialised");
+        const hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        const int k0 = inst < 0 ? 0 : inst, k1 = inst < 0 ? ctx->n_inst : inst + 1;
+        if (inst >= ctx->n_inst) fail(UGKWP_EINVAL, "instance %d out of range", inst);
+        int64_t cg_out = 0, cell_out = 0;
+        for (int k = k0; k < k1; ++k) {
+            const Inst& I = ctx->inst[k];
+            if (rho)
+                copy_rows(rho + cg_out, sizeof(double) * I.G, ctx->D.rho + I.cg_off, sizeof(double) * I.Gp,
+                          sizeof(double) * I.G, I.ncell, kind, ctx->st);
+            if (rhop)
+                copy_rows(rhop + cg_out, sizeof(double) * I.G, ctx->D.rhop + I.cg_off, sizeof(double) * I.Gp,
+                          sizeof(double) * I.G, I.ncell, kind, ctx->st);
+            if (T)
+                HIPCHK(hipMemcpyAsync(T + cell_out, ctx->D.T + I.cell_off, sizeof(double) * I.ncell, kind, ctx->st));
+            cg_out += (int64_t)I.ncell * I.G;
+            cell_out += I.ncell;
+        }
+        HIPCHK(hipStreamSynchronize(ctx->st));
+    });
+}
+
+int ugkwp_get_tallies(ugkwp_ctx* ctx, int inst, double* fx, double* fy, double* dep, double* surv,
+                      int64_t* nbirth, double* wnew, double* Q)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        check_inst(ctx, inst);
+        const Inst& I = ctx->inst[inst];
+        const hipMemcpyKind kind = hipMemcpyDeviceToHost;
+        hipStream_t st = ctx->st;
+        const size_t G = I.G, Gp = I.Gp;
+        if (fx)
+            copy_rows(fx, sizeof(double) * 2 * G, ctx->D.ftx + 2 * I.fx_off, sizeof(double) * 2 * Gp,
+                      sizeof(double) * 2 * G, (size_t)(I.nx + 1) * I.ny, kind, st);
+        if (fy && I.dim == 2)
+            copy_rows(fy, sizeof(double) * 2 * G, ctx->D.fty + 2 * I.fy_off, sizeof(double) * 2 * Gp,
+                      sizeof(double) * 2 * G, (size_t)I.nx * (I.ny + 1), kind, st);
+        if (dep) copy_rows(dep, sizeof(double) * G, ctx->D.dep + I.cg_off, sizeof(double) * Gp, sizeof(double) * G, I.ncell, kind, st);
+        if (surv) copy_rows(surv, sizeof(double) * G, ctx->D.surv + I.cg_off, sizeof(double) * Gp, sizeof(double) * G, I.ncell, kind, st);
+        if (wnew) copy_rows(wnew, sizeof(double) * G, ctx->D.wnew + I.cg_off, sizeof(double) * Gp, sizeof(double) * G, I.ncell, kind, st);
+        if (Q) copy_rows(Q, sizeof(double) * G, ctx->D.Q + I.cg_off, sizeof(double) * Gp, sizeof(double) * G, I.ncell, kind, st);
+        std::vector<int32_t> nb;
+        if (nbirth) {
+            nb.resize((size_t)I.ncell * G);
+            copy_rows(nb.data(), sizeof(int32_t) * G, ctx->D.nb + I.cg_off, sizeof(int32_t) * Gp, sizeof(int32_t) * G,
+                      I.ncell, kind, st);
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        if (nbirth)
+            for (size_t q = 0; q < nb.size(); ++q) nbirth[q] = nb[q];
+    });
+}
+
+int ugkwp_get_diag(ugkwp_ctx* ctx, ugkwp_diag* d)
+{
+    if (!ctx || !d) return UGKWP_EINVAL;
+    *d = ctx->diag;
+    return UGKWP_OK;
+}
+
+int ugkwp_get_counters(ugkwp_ctx* ctx, int inst, uint64_t* birth_counter, int* step)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        check_inst(ctx, inst);
+        InstState s;
+        HIPCHK(hipMemcpyAsync(&s, ctx->D.ist + inst, sizeof(InstState), hipMemcpyDeviceToHost, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        if (birth_counter) *birth_counter = s.births;
+        if (step) *step = (int)ctx->step_idx;
+    });
+}
+
+int64_t ugkwp_pool_size(ugkwp_ctx* ctx) { return ctx ? ctx->n_alive : -1; }
+
+int ugkwp_get_pool(ugkwp_ctx* ctx, double* x, double* y, double* ox, double* oy, double* nu, double* w,
+                   uint64_t* id, int32_t* cell, int32_t* g)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        if (ctx->n_inst == 0) fail(UGKWP_EINVAL, "mesh not initialised");
+        const Pool& p = ctx->pool[ctx->cur];
+        const size_t n = (size_t)ctx->n_alive;
+        hipStream_t st = ctx->st;
+        auto cp = [&](void* dst, const void* src, size_t bytes) {
+            if (dst && src && bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+        };
+        cp(x, p.x, n * 8);
+        cp(ox, p.ox, n * 8);
+        if (ctx->dim == 2) { cp(y, p.y, n * 8); cp(oy, p.oy, n * 8); }
+        else {
+            if (y) std::fill(y, y + n, 0.0);
+            if (oy) std::fill(oy, oy + n, 0.0);
+        }
+        cp(nu, p.nu, n * 8);
+        cp(w, p.w, n * 8);
+        cp(id, p.id, n * 8);
+        cp(cell, p.cell, n * 4);
+        cp(g, p.g, n * 4);
+        HIPCHK(hipStreamSynchronize(st));
+    });
+}
+
+int ugkwp_set_pool(ugkwp_ctx* ctx, int64_t n, const double* x, const double* y, const double* ox,
+                   const double* oy, const double* nu, const double* w, const uint64_t* id,
+                   const int32_t* cell, const int32_t* g, uint64_t birth_counter, const double* rhop)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        require_ready(ctx);
+        if (ctx->n_inst != 1) fail(UGKWP_EINVAL, "set_pool needs a single-instance context");
+        if (n < 0 || n > ctx->P.pool_capacity) fail(UGKWP_EPOOL, "pool of %lld particles exceeds capacity", (long long)n);
+        if (n > 0 && (!x || !ox || !nu || !w || !id || !cell || !g)) fail(UGKWP_EINVAL, "null pool array");
+        if (ctx->dim == 2 && n > 0 && (!y || !oy)) fail(UGKWP_EINVAL, "2-D pool needs y and oy");
+        const Inst& I = ctx->inst[0];
+        for (int64_t q = 0; q < n; ++q)
+            if (cell[q] < 0 || cell[q] >= I.ncell || g[q] < 0 || g[q] >= I.G || !(w[q] >= 0) || !(nu[q] > 0))
+                fail(UGKWP_EINVAL, "particle %lld: cell, group, weight or frequency out of range", (long long)q);
+        const Pool& p = ctx->pool[ctx->cur];
+        hipStream_t st = ctx->st;
+        auto cp = [&](void* dst, const void* src, size_t bytes) {
+            if (bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+        };
+        const size_t nn = (size_t)n;
+        cp(p.x, x, nn * 8);
+        cp(p.ox, ox, nn * 8);
+        if (ctx->dim == 2) { cp(p.y, y, nn * 8); cp(p.oy, oy, nn * 8); }
+        cp(p.nu, nu, nn * 8);
+        cp(p.w, w, nn * 8);
+        cp(p.id, id, nn * 8);
+        cp(p.cell, cell, nn * 4);
+        cp(p.g, g, nn * 4);
+        std::vector<double> hp;
+        if (rhop) {
+            hp.assign((size_t)ctx->K.n_cg, 0.0);
+            ctx->pack_cg(hp, 0, rhop);
+            cp(ctx->D.rhop, hp.data(), hp.size() * 8);
+        }
+        InstState s{};
+        HIPCHK(hipMemcpyAsync(&s, ctx->D.ist, sizeof(InstState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        s.births = birth_counter;
+        HIPCHK(hipMemcpyAsync(ctx->D.ist, &s, sizeof(InstState), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        ctx->n_alive = n;
+    });
+}
+
+// ---- element-wise entry points ----
+
+
+int ugkwp_eval_phi(int n, const double* T, int G, const double* nu_edges, double a, double c, double* out)
+{
+    if (n < 0 || G < 1 || !T || !nu_edges || !out) return UGKWP_EINVAL;
+    return guarded(nullptr, [&] {
+        ensure_head_series();
+        Tmp t;
+        double* dT = t.up(T, n);
+        double* dnu = t.up(nu_edges, G + 1);
+        double* dout = t.up<double>(nullptr, (size_t)n * G);
+        launch_eval_phi(n, dT, G, dnu, a, c, dout, nullptr);
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(out, dout, sizeof(double) * n * G, hipMemcpyDeviceToHost));
+    });
+}
+
+int ugkwp_eval_coef(int n, const double* s, double* c4, double* w, double* c2_over_dt)
+{
+    if (n < 0 || !s || !c4 || !w || !c2_over_dt) return UGKWP_EINVAL;
+    return guarded(nullptr, [&] {
+        Tmp t;
+        double* ds = t.up(s, n);
+        double* a = t.up<double>(nullptr, n);
+        double* b = t.up<double>(nullptr, n);
+        double* cc = t.up<double>(nullptr, n);
+        launch_eval_coef(n, ds, a, b, cc, nullptr);
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(c4, a, sizeof(double) * n, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(w, b, sizeof(double) * n, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(c2_over_dt, cc, sizeof(double) * n, hipMemcpyDeviceToHost));
+    });
+}
+
+int ugkwp_eval_uniform(int n, uint64_t seed, const uint64_t* id, uint32_t step, uint32_t purpose,
+                       const uint32_t* d, double* out)
+{
+    if (n < 0 || !id || !d || !out) return UGKWP_EINVAL;
+    return guarded(nullptr, [&] {
+        Tmp t;
+        uint64_t* di = t.up(id, n);
+        uint32_t* dd = t.up(d, n);
+        double* o = t.up<double>(nullptr, n);
+        launch_eval_uniform(n, seed, di, step, purpose, dd, o, nullptr);
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(out, o, sizeof(double) * n, hipMemcpyDeviceToHost));
+    });
+}
+
+int ugkwp_eval_sample_nu(int n, const double* nl, const double* nh, const double* T, const double* U,
+                         double* beta, double* nu)
+{
+    if (n < 0 || !nl || !nh || !T || !U || !beta || !nu) return UGKWP_EINVAL;
+    return guarded(nullptr, [&] {
+        Tmp t;
+        double* a = t.up(nl, n);
+        double* b = t.up(nh, n);
+        double* c = t.up(T, n);
+        double* u = t.up(U, n);
+        double* ob = t.up<double>(nullptr, n);
+        double* on = t.up<double>(nullptr, n);
+        launch_eval_sample_nu(n, a, b, c, u, ob, on, nullptr);
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(beta, ob, sizeof(double) * n, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(nu, on, sizeof(double) * n, hipMemcpyDeviceToHost));
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,223 @@
+"""GPU (HIP, gfx950) vs FP64 oracle, element by element, on the same seeded
+inputs.  The bar: integer results (particle counts, ids, cells, groups)
+bit-exact; floating point within 1e-10 relative to the array's max-norm
+(per tally and field, gross face crossings rather than net fluxes)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_16981_amd import ugkwp
+from paper_2312_16981_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    scale = np.max(np.abs(b)) if b.size else 0.0
+    if scale == 0.0:
+        return float(np.max(np.abs(a))) if a.size else 0.0
+    return float(np.max(np.abs(a - b)) / scale)
+
+
+def compare_state(ctx, sim, prob, inst=0, what=""):
+    rho_g, T_g, rp_g = ctx.get_fields(inst)
+    rho_o, T_o, rp_o = sim.fields()
+    errs = {"rho": relerr(rho_g, rho_o), "T": relerr(T_g, T_o), "rhop": relerr(rp_g, rp_o)}
+    tg, to = ctx.get_tallies(inst), sim.tallies()
+    assert np.array_equal(tg["nbirth"], to["nbirth"]), f"{what}: birth counts differ"
+    for k in ("fx", "dep", "surv", "wnew", "Q"):
+        errs[k] = relerr(tg[k], to[k])
+    if prob.dim == 2:
+        errs["fy"] = relerr(tg["fy"], to["fy"])
+    bad = {k: v for k, v in errs.items() if not v <= TOL}
+    assert not bad, f"{what}: {bad}"
+    assert ctx.get_counters(inst)[0] == sim.counters()[0], f"{what}: birth counters differ"
+    return errs
+
+
+def compare_pool(ctx, sim, dim):
+    pg, po = ctx.get_pool(), sim.pool()
+    assert len(pg["id"]) == len(po["id"])
+    ig, io = np.argsort(pg["id"]), np.argsort(po["id"])
+    assert np.array_equal(pg["id"][ig], po["id"][io])
+    assert np.array_equal(pg["cell"][ig], po["cell"][io])
+    assert np.array_equal(pg["g"][ig], po["g"][io])
+    keys = ("x", "ox", "nu", "w") + (("y", "oy") if dim == 2 else ())
+    for k in keys:
+        a, b = pg[k][ig], po[k][io]
+        if len(a):
+            assert np.max(np.abs(a - b)) <= TOL * max(np.max(np.abs(b)), 1e-300), k
+
+
+def run_pair(prob, nsteps, every=1, pool_check=True):
+    say(f"[parity] {prob.name} dim={prob.dim} nx={prob.nx} ny={prob.ny} G={prob.G} steps={nsteps}")
+    ctx = ugkwp.from_problem(prob)
+    sim = oracle.Sim(prob)
+    for n in range(nsteps):
+        ctx.step(1)
+        sim.step(1)
+        if (n + 1) % every == 0 or n == nsteps - 1:
+            compare_state(ctx, sim, prob, what=f"{prob.name} step {n}")
+    if pool_check:
+        compare_pool(ctx, sim, prob.dim)
+    dg, do = ctx.get_diag(), sim.diag()
+    assert dg["n_births"] == do["n_births"]
+    assert dg["n_alive_out"] == do["n_alive_out"]
+    assert dg["sweeps_max"] == do["sweeps"]
+    assert abs(dg["residual"]) <= 1e-12 * abs(dg["e_end"])
+    assert relerr([dg["e_end"]], [do["e_end"]]) <= TOL
+    return ctx, sim
+
+
+# ------------------------------------------------------------ building blocks
+
+def test_uniform_stream_bit_exact():
+    rng = np.random.default_rng(1)
+    ids = rng.integers(0, 2**63, size=4096, dtype=np.uint64)
+    d = rng.integers(0, 40, size=4096).astype(np.uint32)
+    for seed, step, purpose in [(0, 0, 1), (7, 123, 2), (2**40 + 5, 2**31 + 1, 2)]:
+        g = ugkwp.eval_uniform(seed, ids, step, purpose, d)
+        o = np.array([oracle.uniform(seed, int(i), step, purpose, int(k)) for i, k in zip(ids, d)])
+        assert np.array_equal(g, o)
+
+
+def test_coefficients_match_oracle():
+    s = np.concatenate([[0.0], np.geomspace(1e-14, 1e8, 2000), [0.999999, 1.0, 1.000001, 1.999999, 2.0]])
+    c4, w, c2 = ugkwp.eval_coef(s)
+    for arr, f in ((c4, oracle.coef_c4), (w, oracle.coef_w), (c2, oracle.coef_c2_over_dt)):
+        ref = np.array([f(v) for v in s])
+        np.testing.assert_allclose(arr, ref, rtol=2e-15, atol=0)
+
+
+def test_planck_groups_match_oracle():
+    edges = np.geomspace(0.01, 10.0, 65)
+    T = np.concatenate([np.geomspace(1e-4, 30.0, 300), [1e-3, 1.0, 0.005, 2.0 / 10]])
+    g = ugkwp.eval_phi(T, edges, 1.0, 1.0)
+    o = np.array([[oracle.phi_group(t, edges[k], edges[k + 1]) for k in range(64)] for t in T])
+    rel = np.abs(g - o) / np.maximum(np.abs(o), 1e-300)
+    rel[o < 1e-290] = 0
+    assert np.max(rel) < 1e-13
+
+
+def test_frequency_sampler_matches_oracle():
+    rng = np.random.default_rng(5)
+    n = 5000
+    nl = 10 ** rng.uniform(-2, 1, n)
+    nh = nl * rng.uniform(1.01, 2.5, n)
+    T = 10 ** rng.uniform(-3.5, 0.5, n)
+    U = rng.uniform(0, 1, n)
+    beta, nu = ugkwp.eval_sample_nu(nl, nh, T, U)
+    bo = np.array([oracle.freq_slope(a, b, t) for a, b, t in zip(nl, nh, T)])
+    no = np.array([oracle.sample_nu(a, b, bb, u) for a, b, bb, u in zip(nl, nh, bo, U)])
+    np.testing.assert_allclose(beta, bo, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(nu, no, rtol=1e-13)
+
+
+# ------------------------------------------------------------ whole steps, 1-D
+
+def test_slab100_g10():
+    run_pair(W.c1_marshak_like(), 25)
+
+
+def test_two_material_slab_small():
+    run_pair(W.c2_two_material(nx=240, G=24, w_ref=2e-5, pool_cap=1 << 21), 30, every=5)
+
+
+def test_reflective_walls_and_group_sigma():
+    p = W.c1_marshak_like(flags=W.FLAG_GROUP_SIGMA)
+    p = p.with_(bc=[W.BC_PLANCK, W.BC_REFLECT, 0, 0])
+    run_pair(p, 15)
+
+
+@pytest.mark.parametrize("G", [1, 7, 33, 64])
+def test_group_counts(G):
+    p = W.slab(37, G, lambda x: np.where(x < 0.3, 0.2, 30.0), dt=2e-3, steps=0, w_ref=5e-5,
+               pool_cap=1 << 20, name=f"slab37_g{G}")
+    run_pair(p, 8)
+
+
+def test_no_particles_pure_wave():
+    run_pair(W.c1_marshak_like(w_ref=1e300), 10)
+
+
+def test_pool_capacity_error_is_transactional():
+    p = W.c1_marshak_like(pool_cap=3000)
+    ctx = ugkwp.from_problem(p)
+    for n in range(20):
+        rho0, T0, rp0 = ctx.get_fields()
+        cnt = ctx.get_counters()
+        pool_n = ctx.pool_size()
+        rc = ctx.step(1, check=False)
+        if rc:
+            break
+    assert rc == ugkwp.EPOOL
+    rho, T, rp = ctx.get_fields()
+    np.testing.assert_array_equal(rho, rho0)
+    np.testing.assert_array_equal(T, T0)
+    np.testing.assert_array_equal(rp, rp0)
+    assert ctx.get_counters() == cnt and ctx.pool_size() == pool_n
+
+
+def test_iteration_limit_reports_noconv():
+    ctx = ugkwp.from_problem(W.c1_marshak_like(si_max_iters=1))
+    assert ctx.step(1, check=False) == ugkwp.ENOCONV
+
+
+# ------------------------------------------------------------ 2-D
+
+def test_lattice_small():
+    run_pair(W.c3_lattice(n=28, G=6, w_ref=1e-3, pool_cap=1 << 21, dt=2e-2), 6)
+
+
+def test_lognormal_small_planck_wall():
+    run_pair(W.c5_lognormal(n=24, G=5, w_ref=2e-4, pool_cap=1 << 21, dt=2e-3), 6)
+
+
+# ------------------------------------------------------------ batched instances
+
+def test_batch_matches_independent_oracle_runs():
+    probs = []
+    rng = np.random.default_rng(9)
+    for k, (nx, G) in enumerate([(13, 5), (64, 16), (50, 33), (129, 64), (8, 1), (40, 12)]):
+        kl, kr = 10 ** rng.uniform(-2, 3, 2)
+        xj = rng.uniform(0.2, 0.8)
+        probs.append(W.slab(nx, G, lambda x, kl=kl, kr=kr, xj=xj: np.where(x < xj, kl, kr), dt=1e-3,
+                            steps=0, w_ref=3e-5, seed=100 + k, pool_cap=1 << 18, name=f"b{k}"))
+    say("[parity] batch of", len(probs))
+    ctx = ugkwp.from_batch(probs)
+    sims = [oracle.Sim(p) for p in probs]
+    for n in range(8):
+        ctx.step(1)
+        for s in sims:
+            s.step(1)
+    for k, (p, s) in enumerate(zip(probs, sims)):
+        compare_state(ctx, s, p, inst=k, what=f"instance {k}")
+    # pool: split by instance via the global cell index
+    pg = ctx.get_pool()
+    cell_off = np.cumsum([0] + [p.ncell for p in probs])
+    for k, s in enumerate(sims):
+        sel = (pg["cell"] >= cell_off[k]) & (pg["cell"] < cell_off[k + 1])
+        po = s.pool()
+        assert sel.sum() == len(po["id"])
+        ig, io = np.argsort(pg["id"][sel]), np.argsort(po["id"])
+        assert np.array_equal(pg["id"][sel][ig], po["id"][io])
+        assert np.array_equal(pg["cell"][sel][ig] - cell_off[k], po["cell"][io])
+        np.testing.assert_allclose(pg["x"][sel][ig], po["x"][io], rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------------ full size
+
+def test_two_material_full_size_first_steps():
+    """2000 cells x 64 groups (the benchmark workload) for its first 40 steps."""
+    p = W.c2_two_material()
+    run_pair(p, 40, every=10)
