@@ -23,8 +23,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PUSH_BYTES_READ = 48       # x, mu, nu, w, id (8 B each) + cell, group (4 B each)
-PUSH_BYTES_WRITE = 48      # survivor record written to the compacted pool
+PUSH_BYTES_READ = 48       # x, mu, nu, w, id (8 B each) + cell word, group (4 B each)
+PUSH_BYTES_WRITE = 12      # new position and cell word of a survivor (updated in place)
+PUSH_BYTES_DEAD = 4        # empty-slot mark of a particle absorbed or gone
 SPINUP = 500
 
 
@@ -52,6 +53,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--sort-interval", type=int, default=0,
+                    help="steps between counting sorts of the pool (0 = library default)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -65,7 +68,7 @@ def main():
     torch.cuda.set_device(0)
     prob = W.c2_two_material()
     stream = torch.cuda.current_stream()
-    ctx = ugkwp.from_problem(prob, stream=stream.cuda_stream)
+    ctx = ugkwp.from_problem(prob, stream=stream.cuda_stream, sort_interval=args.sort_interval)
     ncg = prob.ncell * prob.G
 
     ctx.step(SPINUP)
@@ -78,6 +81,7 @@ def main():
     sweeps = 0
     ms_push = 0.0
     ms_si = 0.0
+    ms_sort = 0.0
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ctx.step(1)
@@ -87,11 +91,13 @@ def main():
         sweeps += d["sweeps_max"]
         ms_push += d["ms_push"]
         ms_si += d["ms_si"]
+        ms_sort += d["ms_sort"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
     value = pushes / elapsed
-    algo_bytes = PUSH_BYTES_READ * pushes + PUSH_BYTES_WRITE * survivors
+    algo_bytes = (PUSH_BYTES_READ * pushes + PUSH_BYTES_WRITE * survivors
+                  + PUSH_BYTES_DEAD * (pushes - survivors))
     achieved = algo_bytes / (ms_push * 1e-3) / 1e9
     out = {
         "metric": "particle-pushes/s (whole UGKWP step, FP64, parity 1e-10 vs oracle)",
@@ -115,10 +121,13 @@ def main():
         "cell_group_updates_per_s_si_only": ncg * sweeps / (ms_si * 1e-3) if ms_si > 0 else None,
         "push_kernel_pushes_per_s": pushes / (ms_push * 1e-3),
         "sweeps_per_step": sweeps / max(args.steps, 1),
+        "ms_per_step_phases": {"push": ms_push / max(args.steps, 1), "si": ms_si / max(args.steps, 1),
+                               "sort": ms_sort / max(args.steps, 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_push<1>", "algorithmic_bytes_per_push":
-                     f"{PUSH_BYTES_READ} read + {PUSH_BYTES_WRITE} per survivor"},
+                     f"{PUSH_BYTES_READ} read + {PUSH_BYTES_WRITE} per survivor + "
+                     f"{PUSH_BYTES_DEAD} per absorbed/escaped particle"},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_budget)

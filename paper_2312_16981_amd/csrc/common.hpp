@@ -43,6 +43,7 @@ struct Consts {
     double nu_power;
     double si_tol;
     int64_t n_cap;
+    int64_t pool_cap;
     uint32_t flags;
     int n_inst;
     int64_t n_cg;          // total (cell, group) slots incl. padding
@@ -63,15 +64,45 @@ struct InstState {
     uint64_t births;       // birth counter B_n
 };
 
+// Context counters (device, unsigned 64-bit):
+enum {
+    CNT_SURV = 0,      // particles alive after this step's push
+    CNT_ERR = 2,       // ERR_* bits raised in this step
+    CNT_CONV = 3,      // instances whose source iteration has converged
+    CNT_SLOTS = 4,     // pool slots at the start of the step (live particles and holes)
+    CNT_PUSHED = 5,    // slots covered by this step's push (CNT_SLOTS + births)
+    CNT_LIVE = 6,      // live particles at the start of the step
+    N_COUNTERS = 8
+};
+enum : unsigned long long {
+    ERR_POOL = 1,      // pool capacity would be exceeded: nothing sampled, step not committed
+    ERR_RECORD = 2,    // a particle record with an out-of-range cell or group
+    ERR_COUNT = 4,     // survivor counts disagree with the pool
+    ERR_TEMP = 8       // non-positive or non-finite temperature in the source iteration
+};
+
+// The cell word of a particle: bits 0..28 the context-global cell, bit 29 a
+// pending reversal of the y direction, bit 30 of the x direction (specular
+// reflections; the stored direction is rewritten only when the pool is
+// sorted), and a negative word marks an empty slot.
+constexpr int32_t CELL_MASK = (1 << 29) - 1;
+constexpr int32_t FLIP_Y = 1 << 29;
+constexpr int32_t FLIP_X = 1 << 30;
+constexpr int32_t DEAD = -1;
+
+// A particle pool viewed as structure of arrays.  The moving fields (x, y and
+// the cell word) live in one of two buffers that alternate between steps; the
+// stable fields (direction, frequency, weight, id, group) are only appended
+// to, and move to the other buffer set when the pool is sorted.
 struct Pool {
     double* x;
     double* y;
+    int32_t* cell;
     double* ox;            // mu in 1-D
     double* oy;
     double* nu;
     double* w;
     uint64_t* id;
-    int32_t* cell;         // global cell index
     int32_t* g;
 };
 
@@ -119,8 +150,9 @@ struct Dev {
     Resid* res;                 // [n_inst][RES_SLOTS]
     double* diag;               // [n_inst][8]
     // context-wide counters
-    unsigned long long* counters;   // [0] survivors written, [1] crossings, ...
-    int64_t* n_births_total;        // scan total
+    unsigned long long* counters;   // CNT_*
+    int64_t* n_births_total;        // [0] births of the step, [1] survivors (sort scan)
+    unsigned long long* blk_surv;   // survivors counted by each push block
 };
 
 __host__ __device__ inline int find_inst(const int64_t* starts, int n, int64_t j)

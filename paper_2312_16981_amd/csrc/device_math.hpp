@@ -84,6 +84,7 @@ __host__ __device__ inline void keyed_uniform_pair(uint64_t seed, uint64_t id, u
 struct HeadSeries {
     int nterm;                 // even-power terms after x^3, x^4
     double c[40];              // coefficient of x^(5 + 2j)
+    double inv[64];            // inv[n] = 1/n (correctly rounded), n >= 1
 };
 
 __device__ inline double planck_head(double x, const HeadSeries& hs)
@@ -96,14 +97,14 @@ __device__ inline double planck_head(double x, const HeadSeries& hs)
     return x3 * (1.0 / 3.0) - x3 * x * 0.125 + acc * x3 * x2;
 }
 
-__device__ inline double planck_tail_series(double x)
+__device__ inline double planck_tail_series(double x, const HeadSeries& hs)
 {
     const double e1 = exp(-x);
     if (e1 == 0.0) return 0.0;
     const double x2 = x * x, x3 = x2 * x;
     double en = e1, sum = 0.0;
     for (int n = 1; n < 64; ++n) {
-        const double dn = (double)n, in = 1.0 / dn;
+        const double in = hs.inv[n];
         const double term = en * (((6.0 * in + 6.0 * x) * in + 3.0 * x2) * in + x3) * in;
         sum += term;
         if (term <= 1e-18 * sum) break;
@@ -115,7 +116,7 @@ __device__ inline double planck_tail_series(double x)
 // Edge value used by group bands: head(x) below 2, tail(x) from 2 on.
 __device__ inline double planck_edge_value(double x, const HeadSeries& hs)
 {
-    return x < 2.0 ? planck_head(x, hs) : planck_tail_series(x);
+    return x < 2.0 ? planck_head(x, hs) : planck_tail_series(x, hs);
 }
 
 // int_{xl}^{xh} t^3/(e^t-1) from edge values vl = edge_value(xl), vh = edge_value(xh).

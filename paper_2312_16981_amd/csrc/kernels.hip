@@ -12,11 +12,17 @@
 //   k_push         free flight with reset at interfaces (Eq. particle tf formula,
 //                  Remark 1), gross face tallies (Eq. wfrpFormula), deletion of
 //                  collided particles, stable wavefront-ballot compaction of survivors
-//   k_wave_source  wave free-transport flux (Sec. 2.2, F^{fr,wave}; Remark 3) and the
-//                  static part Q of the macroscopic update (Eq. macroSysFinal)
-//   k_si_init, k_si_sweep
-//                  source iteration (Appendix B, Eq. macroSysAppendixIte, Algorithm 2)
-//   k_commit, k_diag
+//   k_sort_scatter counting sort of the survivors by (cell, group) slot
+//   k_macro_setup  wave free-transport flux (Sec. 2.2, F^{fr,wave}; Remark 3), the
+//                  static part Q of the macroscopic update (Eq. macroSysFinal), and
+//                  the start of the source iteration
+//   k_si_sweep     source iteration (Appendix B, Eq. macroSysAppendixIte, Algorithm 2)
+//   k_finish       commit of the step and energy bookkeeping
+//
+// Counts that the host does not know without a round trip (births, survivors,
+// pool size) stay in device memory; the kernels that need them loop over the
+// device count, and every kernel that changes the committed state checks that
+// the step neither failed nor left a source iteration unconverged.
 #include "common.hpp"
 #include "device_math.hpp"
 #include "kernels.hpp"
@@ -60,6 +66,12 @@ __device__ inline double phi_group_direct(double T, double nl, double nh, double
     const double band = planck_band_from_edges(xl, planck_edge_value(xl, c_head), xh,
                                                planck_edge_value(xh, c_head));
     return phi_from_band(a, c, T, band);
+}
+
+// A step commits only when nothing failed and every instance's source iteration converged.
+__device__ inline bool step_committed(const Dev& D, const Consts& K)
+{
+    return D.counters[CNT_ERR] == 0 && D.counters[CNT_CONV] == (unsigned long long)K.n_inst;
 }
 
 __device__ inline unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
@@ -279,10 +291,18 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(const int32_t* in, 
 // A2: sample the collisionless wave particles
 
 template <int DIM>
-__global__ void k_sample(Dev D, Consts K, Pool P, int64_t base, int64_t total, uint32_t step)
+__global__ void k_sample(Dev D, Consts K, Pool P, uint32_t step)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= total) return;
+    const int64_t n_slots = (int64_t)D.counters[CNT_SLOTS];
+    const int64_t total = D.n_births_total[0];
+    if (n_slots + total > K.pool_cap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr((unsigned long long*)(D.counters + CNT_ERR), ERR_POOL);
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) D.counters[CNT_PUSHED] = (unsigned long long)(n_slots + total);
+    const int64_t base = n_slots;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
     int64_t lo = 0, hi = K.n_cg;           // boff[lo] <= j < boff[hi]
     while (hi - lo > 1) {
         const int64_t mid = (lo + hi) >> 1;
@@ -323,6 +343,7 @@ __global__ void k_sample(Dev D, Consts K, Pool P, int64_t base, int64_t total, u
     P.id[o] = id;
     P.cell[o] = I.cell_off + lcell;
     P.g[o] = g;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -336,8 +357,11 @@ __global__ void k_sample(Dev D, Consts K, Pool P, int64_t base, int64_t total, u
 // into a handful of bins.
 
 constexpr int PUSH_THREADS = 256;
-constexpr int PUSH_PPT = 4;
-constexpr int HT_BITS = 11;
+#ifndef UGK_PUSH_PPT
+#define UGK_PUSH_PPT 4
+#endif
+constexpr int PUSH_PPT = UGK_PUSH_PPT;
+constexpr int HT_BITS = 10;
 constexpr int HT_SIZE = 1 << HT_BITS;
 constexpr uint32_t HT_EMPTY = 0xFFFFFFFFu;
 constexpr int HT_PROBES = 32;
@@ -364,6 +388,7 @@ __device__ inline void lds_tally(TallyTable& T, const Dev& D, uint32_t type, uin
 {
     const uint32_t key = (index << 2) | type;
     uint32_t h = (key * 2654435761u) >> (32 - HT_BITS);
+#pragma unroll 1
     for (int probe = 0; probe < HT_PROBES; ++probe) {
         const uint32_t prev = atomicCAS(&T.key[h], HT_EMPTY, key);
         if (prev == HT_EMPTY || prev == key) {
@@ -478,159 +503,239 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Inst& I, TallyTab
     }
 }
 
+// Each block takes chunks of PUSH_THREADS * PUSH_PPT consecutive pool slots;
+// a thread handles PUSH_PPT of them.  Stable fields are only read; the new
+// position and cell word go to the other moving-field buffer at the same slot,
+// so the committed pool stays intact until the step commits.
+#ifndef UGK_PUSH_ATTR
+#define UGK_PUSH_ATTR
+#endif
 template <int DIM, bool SINGLE>
-__global__ __launch_bounds__(PUSH_THREADS) void k_push(Dev D, Consts K, Pool A, Pool B, int64_t n_alive,
-                                                       int64_t n_total, uint32_t step)
+__global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool In, Pool Out,
+                                                                     uint32_t step)
 {
     __shared__ TallyTable T;
-    __shared__ int wcount[PUSH_THREADS / WAVE];
-    __shared__ unsigned long long bbase;
-    for (int h = threadIdx.x; h < HT_SIZE; h += PUSH_THREADS) {
-        T.key[h] = HT_EMPTY;
-        T.cnt[h] = 0u;
-        T.val[h] = 0.0;
-    }
-    __syncthreads();
+    __shared__ unsigned long long bsurv[PUSH_THREADS / WAVE];
+    if (D.counters[CNT_ERR] & ERR_POOL) return;
+    const int64_t n_slots = (int64_t)D.counters[CNT_SLOTS];
+    const int64_t n_total = (int64_t)D.counters[CNT_PUSHED];
+    const int64_t chunk = PUSH_THREADS * PUSH_PPT;
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-    const int64_t base = (int64_t)blockIdx.x * (PUSH_THREADS * PUSH_PPT);
-    for (int r = 0; r < PUSH_PPT; ++r) {
-        const int64_t i = base + (int64_t)r * PUSH_THREADS + threadIdx.x;
-        const bool valid = i < n_total;
-        bool keep = false;
-        Flight f;
-        double nu = 0.0, w = 0.0;
-        uint64_t id = 0;
-        int g = 0, inst = 0;
-        const int cell = valid ? A.cell[i] : 0;
-        const bool rec_ok = cell >= 0 && cell < K.ncell;
-        if (valid && !rec_ok) atomicOr((unsigned long long*)(D.counters + 2), 4ull);   // corrupt record
-        if (valid && rec_ok) {
-            f.x = A.x[i];
-            f.ox = A.ox[i];
-            if (DIM == 2) { f.y = A.y[i]; f.oy = A.oy[i]; } else { f.y = 0.0; f.oy = 0.0; }
-            nu = A.nu[i];
-            w = A.w[i];
-            id = A.id[i];
-            g = A.g[i];
-            if (!SINGLE) inst = D.cell_inst[cell];
-            const Inst& I = D.inst[SINGLE ? 0 : inst];
+    unsigned long long nsurv = 0;
+    for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < n_total; c0 += (int64_t)gridDim.x * chunk) {
+        for (int h = threadIdx.x; h < HT_SIZE; h += PUSH_THREADS) {
+            T.key[h] = HT_EMPTY;
+            T.cnt[h] = 0u;
+            T.val[h] = 0.0;
+        }
+        __syncthreads();
+        for (int r = 0; r < PUSH_PPT; ++r) {
+            const int64_t i = c0 + (int64_t)r * PUSH_THREADS + threadIdx.x;
+            if (i >= n_total) continue;
+            const int32_t word = In.cell[i];
+            if (word < 0) {                        // empty slot stays empty
+                Out.cell[i] = DEAD;
+                continue;
+            }
+            const int cell = word & CELL_MASK;
+            const int g = In.g[i];
+            if (cell >= K.ncell) {
+                atomicOr((unsigned long long*)(D.counters + CNT_ERR), ERR_RECORD);
+                Out.cell[i] = DEAD;
+                continue;
+            }
+            const int inst = SINGLE ? 0 : D.cell_inst[cell];
+            const Inst& I = D.inst[inst];
+            Flight f;
+            f.x = In.x[i];
+            f.ox = (word & FLIP_X) ? -In.ox[i] : In.ox[i];
+            if (DIM == 2) {
+                f.y = In.y[i];
+                f.oy = (word & FLIP_Y) ? -In.oy[i] : In.oy[i];
+            } else {
+                f.y = 0.0;
+                f.oy = 0.0;
+            }
+            const double nu = In.nu[i], w = In.w[i];
+            const uint64_t id = In.id[i];
             const int lcell = cell - I.cell_off;
             f.ix = DIM == 1 ? lcell : lcell % I.nx;
             f.iy = DIM == 1 ? 0 : lcell / I.nx;
             f.t = 0.0;
             f.d = 0;
             f.sig = particle_sigma(D, K, I, I.cg_off + ((int64_t)lcell << I.lgGp) + g, nu, g);
-            if (i < n_alive) draw_flight(K, I, id, step, f);   // old particle: t_f = min(-tau ln eta, dt)
-            else { f.coll = false; f.t_rem = K.dt; }           // new collisionless particle: t_f = dt
+            if (i < n_slots) draw_flight(K, I, id, step, f);    // old particle: t_f = min(-tau ln eta, dt)
+            else { f.coll = false; f.t_rem = K.dt; }            // new collisionless particle: t_f = dt
+            const double ox0 = f.ox, oy0 = f.oy;
             const int out = fly<DIM>(D, K, I, T, id, step, nu, g, w, f);
             if (out != 2) {
                 const uint32_t cg = (uint32_t)(I.cg_off + ((int64_t)(f.iy * I.nx + f.ix) << I.lgGp) + g);
                 lds_tally(T, D, out == 0 ? TAL_SURV : TAL_DEP, cg, w);
             }
-            keep = out == 0;
+            if (out == 0) {
+                int32_t nw = I.cell_off + f.iy * I.nx + f.ix;
+                // pending reversal relative to the stored direction
+                if ((f.ox != ox0) != ((word & FLIP_X) != 0)) nw |= FLIP_X;
+                if (DIM == 2 && ((f.oy != oy0) != ((word & FLIP_Y) != 0))) nw |= FLIP_Y;
+                Out.x[i] = f.x;
+                if (DIM == 2) Out.y[i] = f.y;
+                Out.cell[i] = nw;
+                nsurv++;
+            } else {
+                Out.cell[i] = DEAD;
+            }
         }
-        // stable compaction of this round: ballot per wavefront, prefix over wavefronts
-        const unsigned long long mask = __ballot(keep);
-        const int pre = __popcll(mask & ((1ull << lane) - 1ull));
-        if (lane == 0) wcount[wid] = __popcll(mask);
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int tot = 0;
-            for (int k = 0; k < PUSH_THREADS / WAVE; ++k) tot += wcount[k];
-            bbase = tot ? atomicAdd(D.counters, (unsigned long long)tot) : 0ull;
-        }
-        __syncthreads();
-        if (keep) {
-            const Inst& I = D.inst[SINGLE ? 0 : inst];
-            int woff = 0;
-            for (int k = 0; k < wid; ++k) woff += wcount[k];
-            const int64_t o = (int64_t)bbase + woff + pre;
-            B.x[o] = f.x;
-            B.ox[o] = f.ox;
-            if (DIM == 2) { B.y[o] = f.y; B.oy[o] = f.oy; }
-            B.nu[o] = nu;
-            B.w[o] = w;
-            B.id[o] = id;
-            B.cell[o] = I.cell_off + f.iy * I.nx + f.ix;
-            B.g[o] = g;
+        // flush the chunk's tallies: one global atomic per distinct bin
+        for (int h = threadIdx.x; h < HT_SIZE; h += PUSH_THREADS) {
+            const uint32_t key = T.key[h];
+            if (key == HT_EMPTY) continue;
+            const uint32_t type = key & 3u, index = key >> 2;
+            unsafeAtomicAdd(tally_target(D, type, index), T.val[h]);
+            if (type == TAL_SURV) atomicAdd(D.scount + index, T.cnt[h]);
         }
         __syncthreads();
     }
-    // flush the block's tallies: one global atomic per distinct bin
-    for (int h = threadIdx.x; h < HT_SIZE; h += PUSH_THREADS) {
-        const uint32_t key = T.key[h];
-        if (key == HT_EMPTY) continue;
-        const uint32_t type = key & 3u, index = key >> 2;
-        unsafeAtomicAdd(tally_target(D, type, index), T.val[h]);
-        if (type == TAL_SURV) atomicAdd(D.scount + index, T.cnt[h]);
+    // survivors of this block (summed by k_pool_count)
+    for (int m = 32; m >= 1; m >>= 1) nsurv += __shfl_xor(nsurv, m, WAVE);
+    if (lane == 0) bsurv[wid] = nsurv;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < PUSH_THREADS / WAVE; ++k) t += bsurv[k];
+        D.blk_surv[blockIdx.x] = t;
     }
 }
 
-// Counting-sort scatter of the survivors (B -> A) by (cell, group) slot.  soff
-// holds the exclusive scan of the survivor counts and serves as the per-slot
-// write cursor; each run of equal slots within a wavefront reserves its range
-// with one atomic.
-template <int DIM, bool SINGLE>
-__global__ __launch_bounds__(256) void k_sort_scatter(Dev D, Consts K, Pool B, Pool A)
+// Survivor total of the push from the per-block counts.
+__global__ void k_pool_count(Dev D, int nblk)
 {
-    // survivor count written by the push's compaction
-    const int64_t n = (int64_t)D.counters[0];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int lane = threadIdx.x & (WAVE - 1);
-    bool valid = i < n;
-    int64_t key = -1;
-    int cell = 0;
-    if (valid) {
-        cell = B.cell[i];
-        const int g = B.g[i];
-        if (cell < 0 || cell >= K.ncell) {
-            valid = false;
-        } else {
-            const int inst = SINGLE ? 0 : D.cell_inst[cell];
-            const Inst& I = D.inst[inst];
-            key = I.cg_off + ((int64_t)(cell - I.cell_off) << I.lgGp) + g;
-            if (g < 0 || g >= I.G) valid = false;
-        }
-        if (!valid) {
-            key = -1;
-            atomicOr((unsigned long long*)(D.counters + 2), 2ull);   // corrupt record
-        }
+    __shared__ unsigned long long part[256 / WAVE];
+    unsigned long long t = 0;
+    for (int b = threadIdx.x; b < nblk; b += 256) t += D.blk_surv[b];
+    for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0) part[threadIdx.x / WAVE] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int k = 0; k < 256 / WAVE; ++k) s += part[k];
+        D.counters[CNT_SURV] = (D.counters[CNT_ERR] & ERR_POOL) ? 0ull : s;
     }
-    const int64_t kprev = __shfl_up(key, 1, WAVE);
-    const bool head = valid && (lane == 0 || kprev != key);
-    const unsigned long long heads = __ballot(head);
-    const unsigned long long upto = lane == WAVE - 1 ? ~0ull : ((2ull << lane) - 1ull);
-    const int hl = 63 - __clzll(heads & upto);                    // head lane of my run
-    const unsigned long long after = heads & ~upto;
-    int nexth = after ? __ffsll((long long)after) - 1 : WAVE;     // next run's head (or end)
-    const unsigned long long vmask = __ballot(valid);
-    const int nvalid = __popcll(vmask);
-    if (nexth > nvalid) nexth = nvalid;
-    int64_t rbase = 0;
-    if (head) rbase = (int64_t)atomicAdd((unsigned long long*)(D.soff + key), (unsigned long long)(nexth - lane));
-    rbase = __shfl(rbase, hl < 0 ? 0 : hl, WAVE);
-    const int64_t o = rbase + (lane - hl);
-    if (valid && (o < 0 || o >= n)) atomicOr((unsigned long long*)(D.counters + 2), 1ull);   // count mismatch
-    if (valid && o >= 0 && o < n) {
-        A.x[o] = B.x[i];
-        A.ox[o] = B.ox[i];
-        if (DIM == 2) { A.y[o] = B.y[i]; A.oy[o] = B.oy[i]; }
-        A.nu[o] = B.nu[i];
-        A.w[o] = B.w[i];
-        A.id[o] = B.id[i];
-        A.cell[o] = cell;
-        A.g[o] = B.g[i];
+}
+
+// Counting-sort scatter of the live particles (In -> Out) by (cell, group)
+// slot: compacts the pool, applies pending direction reversals, and leaves the
+// pool ordered so that the blocks of the next pushes see few tally bins.  soff
+// holds the exclusive scan of the survivor counts and serves as the per-slot
+// write cursor.  Each block ranks the particles of a chunk per key in an LDS
+// table and reserves every key's range with one global atomic; the input is
+// nearly sorted, so a chunk holds few keys.
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_PPT = 4;
+constexpr int ST_BITS = 10;
+constexpr int ST_SIZE = 1 << ST_BITS;
+
+struct RankTable {
+    uint32_t key[ST_SIZE];
+    uint32_t cnt[ST_SIZE];
+    unsigned long long base[ST_SIZE];
+};
+
+template <int DIM, bool SINGLE>
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(Dev D, Consts K, Pool In, Pool Out)
+{
+    __shared__ RankTable R;
+    if (!step_committed(D, K)) return;
+    const int64_t n = (int64_t)D.counters[CNT_PUSHED];
+    const int64_t nlive = (int64_t)D.counters[CNT_SURV];
+    if (blockIdx.x == 0 && threadIdx.x == 0) D.counters[CNT_SLOTS] = (unsigned long long)nlive;
+    const int64_t chunk = SORT_THREADS * SORT_PPT;
+    for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < n; c0 += (int64_t)gridDim.x * chunk) {
+        for (int h = threadIdx.x; h < ST_SIZE; h += SORT_THREADS) {
+            R.key[h] = HT_EMPTY;
+            R.cnt[h] = 0u;
+        }
+        __syncthreads();
+        int slot[SORT_PPT];          // table entry (>= 0), -1 empty slot, -2 ranked globally
+        int64_t pos[SORT_PPT];       // local rank, or the global position when ranked globally
+#pragma unroll
+        for (int r = 0; r < SORT_PPT; ++r) {
+            const int64_t i = c0 + (int64_t)r * SORT_THREADS + threadIdx.x;
+            slot[r] = -1;
+            pos[r] = 0;
+            if (i >= n) continue;
+            const int32_t word = In.cell[i];
+            if (word < 0) continue;
+            const int cell = word & CELL_MASK;
+            const int g = In.g[i];
+            bool ok = cell < K.ncell;
+            int64_t key = 0;
+            if (ok) {
+                const Inst& I = D.inst[SINGLE ? 0 : D.cell_inst[cell]];
+                ok = g >= 0 && g < I.G;
+                key = I.cg_off + ((int64_t)(cell - I.cell_off) << I.lgGp) + g;
+            }
+            if (!ok) {
+                atomicOr((unsigned long long*)(D.counters + CNT_ERR), ERR_RECORD);
+                continue;
+            }
+            const uint32_t k32 = (uint32_t)key;
+            uint32_t h = (k32 * 2654435761u) >> (32 - ST_BITS);
+            bool placed = false;
+#pragma unroll 1
+            for (int probe = 0; probe < HT_PROBES; ++probe) {
+                const uint32_t prev = atomicCAS(&R.key[h], HT_EMPTY, k32);
+                if (prev == HT_EMPTY || prev == k32) {
+                    slot[r] = (int)h;
+                    pos[r] = atomicAdd(&R.cnt[h], 1u);
+                    placed = true;
+                    break;
+                }
+                h = (h + 1) & (ST_SIZE - 1);
+            }
+            if (!placed) {
+                slot[r] = -2;
+                pos[r] = (int64_t)atomicAdd((unsigned long long*)(D.soff + key), 1ull);
+            }
+        }
+        __syncthreads();
+        for (int h = threadIdx.x; h < ST_SIZE; h += SORT_THREADS) {
+            const uint32_t k32 = R.key[h];
+            if (k32 != HT_EMPTY)
+                R.base[h] = atomicAdd((unsigned long long*)(D.soff + k32), (unsigned long long)R.cnt[h]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < SORT_PPT; ++r) {
+            if (slot[r] == -1) continue;
+            const int64_t i = c0 + (int64_t)r * SORT_THREADS + threadIdx.x;
+            const int64_t o = slot[r] >= 0 ? (int64_t)R.base[slot[r]] + pos[r] : pos[r];
+            if (o < 0 || o >= nlive) {
+                atomicOr((unsigned long long*)(D.counters + CNT_ERR), ERR_COUNT);
+                continue;
+            }
+            const int32_t word = In.cell[i];
+            Out.x[o] = In.x[i];
+            Out.ox[o] = (word & FLIP_X) ? -In.ox[i] : In.ox[i];
+            if (DIM == 2) {
+                Out.y[o] = In.y[i];
+                Out.oy[o] = (word & FLIP_Y) ? -In.oy[i] : In.oy[i];
+            }
+            Out.nu[o] = In.nu[i];
+            Out.w[o] = In.w[i];
+            Out.id[o] = In.id[i];
+            Out.cell[o] = word & CELL_MASK;
+            Out.g[o] = In.g[i];
+        }
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
 // A4: wave free-transport flux and the static source Q
 
-__global__ void k_wave_source(Dev D, Consts K)
+__device__ inline void wave_source(const Dev& D, const Consts& K, int64_t j, const Slot& s)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= K.n_cg) return;
-    const Slot s = decode_slot(D, K, j);
     if (!s.active) { D.Q[j] = 0.0; return; }
     const Inst& I = D.inst[s.inst];
     const int Gp = I.Gp, g = s.g, nx = I.nx;
@@ -689,11 +794,15 @@ __global__ void k_wave_source(Dev D, Consts K)
 // share one wavefront, so the group sum of the temperature update and the
 // group-edge sharing of the Planck integrals are wavefront shuffles.
 
-__global__ void k_si_init(Dev D, Consts K)
+// Wave flux and Q (A4) fused with the set-up of the source iteration:
+// phi^0 = phi(T^n), rho^0 = rho^n, T^0 = T^n, residual slot 0 and the
+// per-instance convergence state cleared.
+__global__ void k_macro_setup(Dev D, Consts K)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const Slot s = decode_slot(D, K, j);
     if (j >= K.n_cg) return;
+    const Slot s = decode_slot(D, K, j);
+    wave_source(D, K, j, s);
     if (s.cell_ok) {
         const Inst& I = D.inst[s.inst];
         const int cell = I.cell_off + s.lcell;
@@ -735,7 +844,10 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         const double drho = bitsd(r.drho), mrho = bitsd(r.rho), dT = bitsd(r.dT), mT = bitsd(r.T);
         if (drho <= K.si_tol * mrho && dT <= K.si_tol * mT) {
             run = false;
-            if (first) D.ist[s.inst].conv_sweeps = k;
+            if (first) {
+                D.ist[s.inst].conv_sweeps = k;
+                atomicAdd((unsigned long long*)(D.counters + CNT_CONV), 1ull);
+            }
         }
     }
     if (first && !check_only) {
@@ -799,7 +911,10 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         const double Tn = D.T[cell];
         Tnew = D.pinned[cell] ? Tn : Tn + (K.dt / (K.eps * K.eps * D.cvol[cell])) * contrib;
         if (!(Tnew > 0.0) || !isfinite(Tnew)) {
-            if (g == 0) atomicOr(&D.ist[s.inst].bad, 1);
+            if (g == 0) {
+                atomicOr(&D.ist[s.inst].bad, 1);
+                atomicOr((unsigned long long*)(D.counters + CNT_ERR), ERR_TEMP);
+            }
             Tnew = 1.0;
         }
         if (g == 0) {
@@ -867,19 +982,6 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
 // ---------------------------------------------------------------------------
 // commit and diagnostics
 
-__global__ void k_commit(Dev D, Consts K)
-{
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= K.n_cg) return;
-    const Slot s = decode_slot(D, K, j);
-    const Inst& I = D.inst[s.inst];
-    D.rhop[j] = s.active ? D.surv[j] / I.V : 0.0;
-    if (j == I.cg_off) {
-        const int64_t end = s.inst + 1 < K.n_inst ? D.boff[D.inst_cg[s.inst + 1]] : *D.n_births_total;
-        D.ist[s.inst].births += (uint64_t)(end - D.boff[I.cg_off]);
-    }
-}
-
 // Energy bookkeeping of the step per instance: diag[inst*8 + q],
 // q = 0 inflow_wave (written by k_wave_source), 1 inflow_eq, 2 exit, 3 injection,
 // 4 e_start, 5 e_end.  Uses the final source-iteration input phi^k.  Sums are
@@ -887,10 +989,24 @@ __global__ void k_commit(Dev D, Consts K)
 // before one atomic per quantity.
 constexpr int DIAG_THREADS = 256;
 
-__global__ __launch_bounds__(DIAG_THREADS) void k_diag(Dev D, Consts K)
+__global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K)
 {
+    if (!step_committed(D, K)) return;
     const int64_t j = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x;
     const Slot s = decode_slot(D, K, j);
+    // commit: survivor density for the next step, birth counters, pool size
+    if (j < K.n_cg) {
+        const Inst& I = D.inst[s.inst];
+        D.rhop[j] = s.active ? D.surv[j] / I.V : 0.0;
+        if (j == I.cg_off) {
+            const int64_t end = s.inst + 1 < K.n_inst ? D.boff[D.inst_cg[s.inst + 1]] : D.n_births_total[0];
+            D.ist[s.inst].births += (uint64_t)(end - D.boff[I.cg_off]);
+        }
+        if (j == 0) {
+            D.counters[CNT_SLOTS] = D.counters[CNT_PUSHED];
+            D.counters[CNT_LIVE] = D.counters[CNT_SURV];
+        }
+    }
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // inflow_eq, exit/c, injection, e0, e1
     if (s.active) {
         const Inst& I = D.inst[s.inst];
@@ -957,6 +1073,18 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag(Dev D, Consts K)
             }
             w0 = w1;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-step clearing of tallies and counters in one launch
+
+__global__ void k_zero(ZeroList Z)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int r = 0; r < Z.n; ++r) {
+        uint64_t* p = (uint64_t*)Z.ptr[r];
+        for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < Z.words[r]; j += stride) p[j] = 0ull;
     }
 }
 
@@ -1043,52 +1171,69 @@ void launch_scan(const int32_t* in, int64_t n, int64_t* part, int64_t* out, int6
     k_scan_final<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, n, part, out);
 }
 
-void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, int64_t base, int64_t total,
-                   uint32_t step, hipStream_t st)
+void launch_zero(const ZeroList& Z, hipStream_t st)
 {
-    if (total <= 0) return;
-    if (dim == 1) k_sample<1><<<blocks(total, 256), 256, 0, st>>>(D, K, P, base, total, step);
-    else k_sample<2><<<blocks(total, 256), 256, 0, st>>>(D, K, P, base, total, step);
+    k_zero<<<1024, 256, 0, st>>>(Z);
 }
 
-void launch_push(int dim, const Dev& D, const Consts& K, const Pool& A, const Pool& B, int64_t n_alive,
-                 int64_t n_total, uint32_t step, hipStream_t st)
+void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, uint32_t step, hipStream_t st)
 {
-    if (n_total <= 0) return;
-    const unsigned nb = blocks(n_total, PUSH_THREADS * PUSH_PPT);
+    if (dim == 1) k_sample<1><<<512, 256, 0, st>>>(D, K, P, step);
+    else k_sample<2><<<512, 256, 0, st>>>(D, K, P, step);
+}
+
+static int g_push_grid[2][2] = {{0, 0}, {0, 0}};
+
+int push_grid(int dim, bool single)
+{
+    int& gsz = g_push_grid[dim - 1][single ? 1 : 0];
+    if (gsz == 0) {
+        int dev = 0, ncu = 0, per = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        hipError_t e;
+        if (dim == 1) e = single ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_push<1, true>, PUSH_THREADS, 0)
+                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_push<1, false>, PUSH_THREADS, 0);
+        else e = single ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_push<2, true>, PUSH_THREADS, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_push<2, false>, PUSH_THREADS, 0);
+        if (e != hipSuccess || per < 1) per = 2;
+        if (ncu < 1) ncu = 256;
+        gsz = ncu * per;
+    }
+    return gsz;
+}
+
+void launch_push(int dim, const Dev& D, const Consts& K, const Pool& In, const Pool& Out, uint32_t step,
+                 hipStream_t st)
+{
     const bool single = K.n_inst == 1;
+    const int nb = push_grid(dim, single);
     if (dim == 1) {
-        if (single) k_push<1, true><<<nb, PUSH_THREADS, 0, st>>>(D, K, A, B, n_alive, n_total, step);
-        else k_push<1, false><<<nb, PUSH_THREADS, 0, st>>>(D, K, A, B, n_alive, n_total, step);
+        if (single) k_push<1, true><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
+        else k_push<1, false><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
     } else {
-        if (single) k_push<2, true><<<nb, PUSH_THREADS, 0, st>>>(D, K, A, B, n_alive, n_total, step);
-        else k_push<2, false><<<nb, PUSH_THREADS, 0, st>>>(D, K, A, B, n_alive, n_total, step);
+        if (single) k_push<2, true><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
+        else k_push<2, false><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
+    }
+    k_pool_count<<<1, 256, 0, st>>>(D, nb);
+}
+
+void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& In, const Pool& Out, hipStream_t st)
+{
+    const bool single = K.n_inst == 1;
+    const unsigned nb = 2048;
+    if (dim == 1) {
+        if (single) k_sort_scatter<1, true><<<nb, SORT_THREADS, 0, st>>>(D, K, In, Out);
+        else k_sort_scatter<1, false><<<nb, SORT_THREADS, 0, st>>>(D, K, In, Out);
+    } else {
+        if (single) k_sort_scatter<2, true><<<nb, SORT_THREADS, 0, st>>>(D, K, In, Out);
+        else k_sort_scatter<2, false><<<nb, SORT_THREADS, 0, st>>>(D, K, In, Out);
     }
 }
 
-void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& B, const Pool& A, int64_t n_max,
-                         hipStream_t st)
+void launch_macro_setup(const Dev& D, const Consts& K, hipStream_t st)
 {
-    if (n_max <= 0) return;
-    const unsigned nb = blocks(n_max, 256);
-    const bool single = K.n_inst == 1;
-    if (dim == 1) {
-        if (single) k_sort_scatter<1, true><<<nb, 256, 0, st>>>(D, K, B, A);
-        else k_sort_scatter<1, false><<<nb, 256, 0, st>>>(D, K, B, A);
-    } else {
-        if (single) k_sort_scatter<2, true><<<nb, 256, 0, st>>>(D, K, B, A);
-        else k_sort_scatter<2, false><<<nb, 256, 0, st>>>(D, K, B, A);
-    }
-}
-
-void launch_wave_source(const Dev& D, const Consts& K, hipStream_t st)
-{
-    k_wave_source<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K);
-}
-
-void launch_si_init(const Dev& D, const Consts& K, hipStream_t st)
-{
-    k_si_init<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K);
+    k_macro_setup<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K);
 }
 
 void launch_si_sweep(const Dev& D, const Consts& K, int k, bool check_only, hipStream_t st)
@@ -1098,14 +1243,9 @@ void launch_si_sweep(const Dev& D, const Consts& K, int k, bool check_only, hipS
     k_si_sweep<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, pin, pout, check_only ? 1 : 0);
 }
 
-void launch_commit(const Dev& D, const Consts& K, hipStream_t st)
+void launch_finish(const Dev& D, const Consts& K, hipStream_t st)
 {
-    k_commit<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K);
-}
-
-void launch_diag(const Dev& D, const Consts& K, hipStream_t st)
-{
-    k_diag<<<blocks(K.n_cg, DIAG_THREADS), DIAG_THREADS, 0, st>>>(D, K);
+    k_finish<<<blocks(K.n_cg, DIAG_THREADS), DIAG_THREADS, 0, st>>>(D, K);
 }
 
 void launch_eval_phi(int n, const double* T, int G, const double* nu, double a, double c, double* out,

@@ -5,26 +5,31 @@
 
 namespace ugk {
 
+// Up to 8 device ranges of 64-bit words cleared by one launch.
+struct ZeroList {
+    int n;
+    void* ptr[8];
+    int64_t words[8];
+};
+
 hipError_t set_head_series(const HeadSeries& hs);
 
 void launch_tables(const Dev& D, const Consts& K, hipStream_t st);
 void launch_face_D(const Dev& D, const Consts& K, int inst, int axis, int64_t nslots, hipStream_t st);
 void launch_ghost_phi(const Dev& D, const Consts& K, double* phib, hipStream_t st);
 void launch_init_rho(const Dev& D, const Consts& K, const double* Tr0, hipStream_t st);
+void launch_zero(const ZeroList& Z, hipStream_t st);
 void launch_count(const Dev& D, const Consts& K, hipStream_t st);
 int64_t scan_partials_size(int64_t n);
 void launch_scan(const int32_t* in, int64_t n, int64_t* part, int64_t* out, int64_t* total, hipStream_t st);
-void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, int64_t base, int64_t total,
-                   uint32_t step, hipStream_t st);
-void launch_push(int dim, const Dev& D, const Consts& K, const Pool& A, const Pool& B, int64_t n_alive,
-                 int64_t n_total, uint32_t step, hipStream_t st);
-void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& B, const Pool& A, int64_t n_max,
-                         hipStream_t st);
-void launch_wave_source(const Dev& D, const Consts& K, hipStream_t st);
-void launch_si_init(const Dev& D, const Consts& K, hipStream_t st);
+void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, uint32_t step, hipStream_t st);
+int push_grid(int dim, bool single);
+void launch_push(int dim, const Dev& D, const Consts& K, const Pool& A, const Pool& B, uint32_t step,
+                 hipStream_t st);
+void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& B, const Pool& A, hipStream_t st);
+void launch_macro_setup(const Dev& D, const Consts& K, hipStream_t st);
 void launch_si_sweep(const Dev& D, const Consts& K, int k, bool check_only, hipStream_t st);
-void launch_commit(const Dev& D, const Consts& K, hipStream_t st);
-void launch_diag(const Dev& D, const Consts& K, hipStream_t st);
+void launch_finish(const Dev& D, const Consts& K, hipStream_t st);
 
 void launch_eval_phi(int n, const double* T, int G, const double* nu, double a, double c, double* out,
                      hipStream_t st);

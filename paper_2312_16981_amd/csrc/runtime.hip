@@ -70,6 +70,8 @@ HeadSeries make_head_series()
         if (!(k & 1)) v = -v;
         hs.c[j] = (double)v;
     }
+    hs.inv[0] = 0.0;
+    for (int n = 1; n < 64; ++n) hs.inv[n] = 1.0 / (double)n;
     return hs;
 }
 
@@ -138,9 +140,11 @@ struct ugkwp_ctx {
     // device state
     std::vector<void*> owned;
     Dev D{};
-    Pool pool[2]{};
-    int cur = 0;
-    int64_t n_alive = 0;
+    Pool mv[2]{};          // moving fields (x, y, cell word), alternate every step
+    Pool stb[2]{};         // stable fields (direction, nu, w, id, g), switch on sorts
+    int cur_mv = 0, cur_st = 0;
+    int64_t n_alive = 0;   // live particles
+    int64_t n_slots = 0;   // pool slots incl. holes
     uint32_t step_idx = 0;
     bool have_opacity = false, have_material = false;
     int64_t* part = nullptr;
@@ -148,12 +152,18 @@ struct ugkwp_ctx {
     double* d_phib = nullptr;
 
     // host staging (pinned)
+    // status block: counters | birth totals | per-instance state | per-instance diagnostics,
+    // contiguous on the device and mirrored in pinned host memory (one copy per step)
+    void* d_status = nullptr;
+    void* h_status = nullptr;
+    size_t status_bytes = 0;
     int64_t* h_total = nullptr;
     unsigned long long* h_counters = nullptr;
     InstState* h_ist = nullptr;
     double* h_diag = nullptr;
     hipEvent_t ev[7]{};
     int last_sweeps = 4;
+    int sort_interval = 8;
     ugkwp_diag diag{};
 
     ~ugkwp_ctx() { release(); }
@@ -162,10 +172,8 @@ struct ugkwp_ctx {
     {
         for (void* p : owned) (void)hipFree(p);
         owned.clear();
-        if (h_total) (void)hipHostFree(h_total);
-        if (h_counters) (void)hipHostFree(h_counters);
-        if (h_ist) (void)hipHostFree(h_ist);
-        if (h_diag) (void)hipHostFree(h_diag);
+        if (h_status) (void)hipHostFree(h_status);
+        h_status = nullptr;
         h_total = nullptr; h_counters = nullptr; h_ist = nullptr; h_diag = nullptr;
         for (auto& e : ev)
             if (e) { (void)hipEventDestroy(e); e = nullptr; }
@@ -179,7 +187,7 @@ struct ugkwp_ctx {
         for (void* p : owned) (void)hipFree(p);
         owned.clear();
         D = Dev{};
-        pool[0] = pool[1] = Pool{};
+        mv[0] = mv[1] = stb[0] = stb[1] = Pool{};
         have_opacity = have_material = false;
     }
 
@@ -263,6 +271,7 @@ struct ugkwp_ctx {
         K.nu_power = P.nu_power;
         K.si_tol = P.si_tol;
         K.n_cap = P.n_cap;
+        K.pool_cap = P.pool_capacity;
         K.flags = P.flags;
         K.n_inst = n_inst;
         K.n_cg = n_cg;
@@ -333,11 +342,24 @@ struct ugkwp_ctx {
         d.T = dalloc<double>(owned, ncell);
         d.T_new = dalloc<double>(owned, ncell);
         d.pinned = dalloc<uint8_t>(owned, ncell);
-        d.ist = dalloc<InstState>(owned, n_inst);
+        // status block (see the member comment); offsets are multiples of 16 bytes
+        const size_t off_tot = sizeof(unsigned long long) * N_COUNTERS;
+        const size_t off_ist = off_tot + 16;
+        const size_t off_diag = off_ist + sizeof(InstState) * (size_t)n_inst;
+        status_bytes = off_diag + sizeof(double) * 8 * (size_t)n_inst;
+        d_status = dalloc<char>(owned, status_bytes);
+        HIPCHK(hipMemsetAsync(d_status, 0, status_bytes, st));
+        if (h_status) (void)hipHostFree(h_status);
+        HIPCHK(hipHostMalloc(&h_status, status_bytes, hipHostMallocDefault));
+        h_counters = (unsigned long long*)h_status;
+        h_total = (int64_t*)((char*)h_status + off_tot);
+        h_ist = (InstState*)((char*)h_status + off_ist);
+        h_diag = (double*)((char*)h_status + off_diag);
+        d.counters = (unsigned long long*)d_status;
+        d.n_births_total = (int64_t*)((char*)d_status + off_tot);
+        d.ist = (InstState*)((char*)d_status + off_ist);
+        d.diag = (double*)((char*)d_status + off_diag);
         d.res = dalloc<Resid>(owned, (size_t)n_inst * RES_SLOTS);
-        d.diag = dalloc<double>(owned, (size_t)n_inst * 8);
-        d.counters = dalloc<unsigned long long>(owned, 8);
-        d.n_births_total = dalloc<int64_t>(owned, 2);
         n_part = scan_partials_size(n_cg);
         part = dalloc<int64_t>(owned, (size_t)n_part + 1);
         HIPCHK(hipMemsetAsync(d.ist, 0, sizeof(InstState) * n_inst, st));
@@ -354,21 +376,21 @@ struct ugkwp_ctx {
 
         const int64_t cap = std::max<int64_t>(P.pool_capacity, 1);
         for (int b = 0; b < 2; ++b) {
-            Pool& p = pool[b];
-            p.x = dalloc<double>(owned, cap);
-            p.ox = dalloc<double>(owned, cap);
+            mv[b].x = dalloc<double>(owned, cap);
+            mv[b].cell = dalloc<int32_t>(owned, cap);
+            stb[b].ox = dalloc<double>(owned, cap);
             if (dim == 2) {
-                p.y = dalloc<double>(owned, cap);
-                p.oy = dalloc<double>(owned, cap);
+                mv[b].y = dalloc<double>(owned, cap);
+                stb[b].oy = dalloc<double>(owned, cap);
             }
-            p.nu = dalloc<double>(owned, cap);
-            p.w = dalloc<double>(owned, cap);
-            p.id = dalloc<uint64_t>(owned, cap);
-            p.cell = dalloc<int32_t>(owned, cap);
-            p.g = dalloc<int32_t>(owned, cap);
+            stb[b].nu = dalloc<double>(owned, cap);
+            stb[b].w = dalloc<double>(owned, cap);
+            stb[b].id = dalloc<uint64_t>(owned, cap);
+            stb[b].g = dalloc<int32_t>(owned, cap);
         }
-        cur = 0;
-        n_alive = 0;
+        d.blk_surv = dalloc<unsigned long long>(owned, 8192);
+        cur_mv = cur_st = 0;
+        n_alive = n_slots = 0;
         step_idx = 0;
         HIPCHK(hipStreamSynchronize(st));
         HIPCHK(hipGetLastError());
@@ -428,88 +450,107 @@ struct ugkwp_ctx {
         HIPCHK(hipMemcpyAsync(d_tr, hTr.data(), sizeof(double) * ncell, hipMemcpyHostToDevice, st));
         launch_init_rho(D, K, d_tr, st);
         HIPCHK(hipMemsetAsync(D.ist, 0, sizeof(InstState) * n_inst, st));
+        HIPCHK(hipMemsetAsync(D.counters, 0, sizeof(unsigned long long) * N_COUNTERS, st));
         HIPCHK(hipStreamSynchronize(st));
         (void)hipFree(d_tr);
         HIPCHK(hipGetLastError());
-        n_alive = 0;
+        n_alive = n_slots = 0;
         step_idx = 0;
-        cur = 0;
+        cur_mv = cur_st = 0;
         have_material = true;
     }
 
+    Pool view(int m, int t) const
+    {
+        Pool p = stb[t];
+        p.x = mv[m].x;
+        p.y = mv[m].y;
+        p.cell = mv[m].cell;
+        return p;
+    }
+    Pool moving(int m) const
+    {
+        Pool p{};
+        p.x = mv[m].x;
+        p.y = mv[m].y;
+        p.cell = mv[m].cell;
+        return p;
+    }
+
     // ---------------------------------------------------------------- one step
+    // Algorithm 1, enqueued without host round trips; one synchronisation at the
+    // end reads the status.  Source-iteration sweeps are launched speculatively
+    // (the previous step's count + 2; a converged instance's sweeps return at
+    // once) and more are added only if an instance has not converged.
+    void enqueue_finish(bool do_sort)
+    {
+        launch_finish(D, K, st);
+        if (do_sort) {
+            HIPCHK(hipEventRecord(ev[5], st));
+            launch_scan((const int32_t*)D.scount, K.n_cg, part, D.soff, D.n_births_total + 1, st);
+            launch_sort_scatter(dim, D, K, view(1 - cur_mv, cur_st), view(cur_mv, 1 - cur_st), st);
+            HIPCHK(hipEventRecord(ev[6], st));
+        }
+        HIPCHK(hipMemcpyAsync(h_status, d_status, status_bytes, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+
     int step_once()
     {
-        const Pool& A = pool[cur];
-        const Pool& B = pool[1 - cur];
+        // sort periodically, and whenever holes have filled half the pool
+        const bool do_sort = sort_interval <= 1 ||
+                             (step_idx % (uint32_t)sort_interval) == (uint32_t)(sort_interval - 1) ||
+                             n_slots > P.pool_capacity / 2;
+        ZeroList z{};
+        auto add = [&](void* p, int64_t words) {
+            if (words > 0) { z.ptr[z.n] = p; z.words[z.n] = words; z.n++; }
+        };
+        add(D.ftx, n_fx * 2);
+        if (dim == 2) add(D.fty, n_fy * 2);
+        add(D.dep, K.n_cg);
+        add(D.surv, K.n_cg);
+        add(D.scount, K.n_cg / 2);
+        add(D.diag, 8 * (int64_t)n_inst);
+        add(D.counters, 4);                 // CNT_SURV .. CNT_CONV; slot and live counts persist
+        launch_zero(z, st);
+
         HIPCHK(hipEventRecord(ev[0], st));
         launch_count(D, K, st);
         launch_scan(D.nb, K.n_cg, part, D.boff, D.n_births_total, st);
-        HIPCHK(hipMemcpyAsync(h_total, D.n_births_total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        const int64_t births = *h_total;
-        if (n_alive + births > P.pool_capacity)
-            fail(UGKWP_EPOOL, "particle pool capacity %lld exceeded (%lld alive + %lld births)",
-                 (long long)P.pool_capacity, (long long)n_alive, (long long)births);
-        launch_sample(dim, D, K, A, n_alive, births, step_idx, st);
-        HIPCHK(hipMemsetAsync(D.ftx, 0, sizeof(double) * n_fx * 2, st));
-        if (dim == 2) HIPCHK(hipMemsetAsync(D.fty, 0, sizeof(double) * n_fy * 2, st));
-        HIPCHK(hipMemsetAsync(D.dep, 0, sizeof(double) * K.n_cg, st));
-        HIPCHK(hipMemsetAsync(D.surv, 0, sizeof(double) * K.n_cg, st));
-        HIPCHK(hipMemsetAsync(D.counters, 0, sizeof(unsigned long long) * 8, st));
-        HIPCHK(hipMemsetAsync(D.diag, 0, sizeof(double) * 8 * n_inst, st));
-        HIPCHK(hipMemsetAsync(D.scount, 0, sizeof(uint32_t) * K.n_cg, st));
+        const Pool In = view(cur_mv, cur_st);
+        launch_sample(dim, D, K, In, step_idx, st);
         HIPCHK(hipEventRecord(ev[1], st));
-        launch_push(dim, D, K, A, B, n_alive, n_alive + births, step_idx, st);
+        launch_push(dim, D, K, In, moving(1 - cur_mv), step_idx, st);
         HIPCHK(hipEventRecord(ev[2], st));
-        launch_wave_source(D, K, st);
-        launch_si_init(D, K, st);
+        launch_macro_setup(D, K, st);
         HIPCHK(hipEventRecord(ev[3], st));
-
-        // source iteration: sweeps are launched in chunks; the convergence test of
-        // sweep k is evaluated on the device at the start of sweep k+1
         const int kmax = P.si_max_iters;
         int k = 0;
-        int chunk = std::max(2, last_sweeps + 1);
-        bool done = false;
-        int status = UGKWP_OK;
-        while (!done) {
-            const int kend = std::min(k + chunk, kmax + 1);
-            for (; k < kend; ++k) launch_si_sweep(D, K, k, k == kmax, st);
-            HIPCHK(hipMemcpyAsync(h_ist, D.ist, sizeof(InstState) * n_inst, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            bool all = true, bad = false;
-            for (int q = 0; q < n_inst; ++q) {
-                if (h_ist[q].bad) bad = true;
-                if (h_ist[q].conv_sweeps == 0) all = false;
-            }
-            if (bad) { status = UGKWP_ENONFINITE; break; }
-            if (all) { done = true; break; }
-            if (k > kmax) { status = UGKWP_ENOCONV; break; }
-            chunk = 2;
-        }
+        const int first = std::min(kmax + 1, last_sweeps + 2);
+        for (; k < first; ++k) launch_si_sweep(D, K, k, k == kmax, st);
         HIPCHK(hipEventRecord(ev[4], st));
-        if (status == UGKWP_ENONFINITE) fail(status, "source iteration produced a non-positive or non-finite temperature");
-        if (status == UGKWP_ENOCONV) fail(status, "source iteration did not converge in %d sweeps", kmax);
-
-        launch_diag(D, K, st);
-        launch_commit(D, K, st);
-        // keep the pool sorted by (cell, group) slot: survivors B -> A
-        HIPCHK(hipEventRecord(ev[5], st));
-        launch_scan((const int32_t*)D.scount, K.n_cg, part, D.soff, D.n_births_total + 1, st);
-        launch_sort_scatter(dim, D, K, B, A, n_alive + births, st);
-        HIPCHK(hipEventRecord(ev[6], st));
-        HIPCHK(hipMemcpyAsync(h_counters, D.counters, sizeof(unsigned long long) * 8, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h_diag, D.diag, sizeof(double) * 8 * n_inst, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        HIPCHK(hipGetLastError());
+        enqueue_finish(do_sort);
+        for (;;) {
+            const unsigned long long err = h_counters[CNT_ERR];
+            if (err & ERR_POOL)
+                fail(UGKWP_EPOOL, "particle pool capacity %lld exceeded (%lld alive + %lld births)",
+                     (long long)P.pool_capacity, (long long)h_counters[CNT_SLOTS], (long long)*h_total);
+            if (err & ERR_TEMP) fail(UGKWP_ENONFINITE, "source iteration produced a non-positive or non-finite temperature");
+            if (err) fail(UGKWP_EHIP, "internal error %llu: particle records or survivor counts inconsistent", err);
+            if (h_counters[CNT_CONV] == (unsigned long long)n_inst) break;
+            if (k > kmax) fail(UGKWP_ENOCONV, "source iteration did not converge in %d sweeps", kmax);
+            const int kend = std::min(k + 4, kmax + 1);
+            for (; k < kend; ++k) launch_si_sweep(D, K, k, k == kmax, st);
+            enqueue_finish(do_sort);
+        }
 
         // bookkeeping of the committed step
         ugkwp_diag dg{};
         dg.n_alive_in = n_alive;
-        dg.n_births = births;
-        dg.n_pushed = n_alive + births;
-        dg.n_alive_out = (int64_t)h_counters[0];
+        dg.n_births = *h_total;
+        dg.n_pushed = n_alive + *h_total;
+        const int64_t pushed_slots = (int64_t)h_counters[CNT_PUSHED];
+        dg.n_alive_out = (int64_t)h_counters[CNT_SURV];
         int smax = 0, ssum = 0;
         for (int q = 0; q < n_inst; ++q) {
             smax = std::max(smax, h_ist[q].conv_sweeps);
@@ -530,15 +571,20 @@ struct ugkwp_ctx {
         HIPCHK(hipEventElapsedTime(&ms, ev[1], ev[2])); dg.ms_push = ms;
         HIPCHK(hipEventElapsedTime(&ms, ev[2], ev[3])); dg.ms_macro = ms;
         HIPCHK(hipEventElapsedTime(&ms, ev[3], ev[4])); dg.ms_si = ms;
-        HIPCHK(hipEventElapsedTime(&ms, ev[5], ev[6])); dg.ms_sort = ms;
-        if (h_counters[2])
-            fail(UGKWP_EHIP, "internal error %llu: particle records or survivor counts inconsistent",
-                 (unsigned long long)h_counters[2]);
+        dg.ms_sort = 0.0;
+        if (do_sort) { HIPCHK(hipEventElapsedTime(&ms, ev[5], ev[6])); dg.ms_sort = ms; }
         diag = dg;
         last_sweeps = smax;
 
         std::swap(D.rho, D.rho_new);
         std::swap(D.T, D.T_new);
+        if (do_sort) {
+            cur_st = 1 - cur_st;           // sorted, compact pool: moving fields in mv[cur_mv]
+            n_slots = dg.n_alive_out;
+        } else {
+            cur_mv = 1 - cur_mv;           // positions of this step in the other moving buffer
+            n_slots = pushed_slots;
+        }
         n_alive = dg.n_alive_out;
         step_idx++;
         return UGKWP_OK;
@@ -615,7 +661,7 @@ int ugkwp_create(ugkwp_ctx** out, const ugkwp_params* p, void* hip_stream)
     *out = nullptr;
     if (!(p->c > 0) || !(p->a > 0) || !(p->eps > 0) || !(p->dt > 0) || !std::isfinite(p->dt) ||
         !(p->si_tol >= 0) || p->si_max_iters < 1 || p->pool_capacity < 0 || p->n_cap < 0 ||
-        p->n_cap > (1 << 30) || !(p->nu_power >= 0))
+        p->n_cap > (1 << 30) || !(p->nu_power >= 0) || p->sort_interval < 0)
         return UGKWP_EINVAL;
     ugkwp_ctx* c = new (std::nothrow) ugkwp_ctx();
     if (!c) return UGKWP_ENOMEM;
@@ -626,8 +672,7 @@ int ugkwp_create(ugkwp_ctx** out, const ugkwp_params* p, void* hip_stream)
             HIPCHK(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking));
             c->own_stream = true;
         }
-        HIPCHK(hipHostMalloc((void**)&c->h_total, sizeof(int64_t), hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void**)&c->h_counters, sizeof(unsigned long long) * 8, hipHostMallocDefault));
+        c->sort_interval = p->sort_interval > 0 ? p->sort_interval : 16;
         for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
     });
     if (rc) { delete c; return rc; }
@@ -643,16 +688,6 @@ void ugkwp_destroy(ugkwp_ctx* ctx)
 }
 
 const char* ugkwp_last_error(const ugkwp_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
-
-static int alloc_host_status(ugkwp_ctx* c)
-{
-    if (c->h_ist) (void)hipHostFree(c->h_ist);
-    if (c->h_diag) (void)hipHostFree(c->h_diag);
-    c->h_ist = nullptr; c->h_diag = nullptr;
-    HIPCHK(hipHostMalloc((void**)&c->h_ist, sizeof(InstState) * c->n_inst, hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&c->h_diag, sizeof(double) * 8 * c->n_inst, hipHostMallocDefault));
-    return 0;
-}
 
 int ugkwp_init_mesh(ugkwp_ctx* ctx, int dim, int nx, int ny, const double lo[2], const double hi[2],
                     const int bc[4], const double bcT[4], int G, const double* nu_edges, uint64_t seed,
@@ -672,7 +707,6 @@ int ugkwp_init_mesh(ugkwp_ctx* ctx, int dim, int nx, int ny, const double lo[2],
         h.seed = seed;
         h.w_ref = w_ref;
         ctx->setup({h});
-        alloc_host_status(ctx);
     });
 }
 
@@ -721,7 +755,6 @@ int ugkwp_init_batch(ugkwp_ctx* ctx, int n_inst, const ugkwp_instance* d)
             kap[k] = s.kappa; cv[k] = s.cv; T0[k] = s.T0; Tr0[k] = s.Tr0; pin[k] = s.pinned;
         }
         ctx->setup(hs);
-        alloc_host_status(ctx);
         ctx->set_opacity(kap);
         ctx->set_material(cv, T0, Tr0, pin);
     });
@@ -825,25 +858,42 @@ int ugkwp_get_pool(ugkwp_ctx* ctx, double* x, double* y, double* ox, double* oy,
     if (!ctx) return UGKWP_EINVAL;
     return guarded(ctx, [&] {
         if (ctx->n_inst == 0) fail(UGKWP_EINVAL, "mesh not initialised");
-        const Pool& p = ctx->pool[ctx->cur];
-        const size_t n = (size_t)ctx->n_alive;
+        const Pool p = ctx->view(ctx->cur_mv, ctx->cur_st);
+        const size_t ns = (size_t)ctx->n_slots;
         hipStream_t st = ctx->st;
+        std::vector<double> hx(ns), hy, hox(ns), hoy, hnu(ns), hw(ns);
+        std::vector<uint64_t> hid(ns);
+        std::vector<int32_t> hcell(ns), hg(ns);
+        if (ctx->dim == 2) { hy.resize(ns); hoy.resize(ns); }
         auto cp = [&](void* dst, const void* src, size_t bytes) {
-            if (dst && src && bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+            if (bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
         };
-        cp(x, p.x, n * 8);
-        cp(ox, p.ox, n * 8);
-        if (ctx->dim == 2) { cp(y, p.y, n * 8); cp(oy, p.oy, n * 8); }
-        else {
-            if (y) std::fill(y, y + n, 0.0);
-            if (oy) std::fill(oy, oy + n, 0.0);
-        }
-        cp(nu, p.nu, n * 8);
-        cp(w, p.w, n * 8);
-        cp(id, p.id, n * 8);
-        cp(cell, p.cell, n * 4);
-        cp(g, p.g, n * 4);
+        cp(hx.data(), p.x, ns * 8);
+        cp(hox.data(), p.ox, ns * 8);
+        if (ctx->dim == 2) { cp(hy.data(), p.y, ns * 8); cp(hoy.data(), p.oy, ns * 8); }
+        cp(hnu.data(), p.nu, ns * 8);
+        cp(hw.data(), p.w, ns * 8);
+        cp(hid.data(), p.id, ns * 8);
+        cp(hcell.data(), p.cell, ns * 4);
+        cp(hg.data(), p.g, ns * 4);
         HIPCHK(hipStreamSynchronize(st));
+        size_t o = 0;
+        for (size_t q = 0; q < ns; ++q) {
+            const int32_t word = hcell[q];
+            if (word < 0) continue;
+            if (x) x[o] = hx[q];
+            if (y) y[o] = ctx->dim == 2 ? hy[q] : 0.0;
+            if (ox) ox[o] = (word & FLIP_X) ? -hox[q] : hox[q];
+            if (oy) oy[o] = ctx->dim == 2 ? ((word & FLIP_Y) ? -hoy[q] : hoy[q]) : 0.0;
+            if (nu) nu[o] = hnu[q];
+            if (w) w[o] = hw[q];
+            if (id) id[o] = hid[q];
+            if (cell) cell[o] = word & CELL_MASK;
+            if (g) g[o] = hg[q];
+            ++o;
+        }
+        if ((int64_t)o != ctx->n_alive) fail(UGKWP_EHIP, "pool holds %zu live particles, expected %lld", o,
+                                              (long long)ctx->n_alive);
     });
 }
 
@@ -862,7 +912,7 @@ int ugkwp_set_pool(ugkwp_ctx* ctx, int64_t n, const double* x, const double* y, 
         for (int64_t q = 0; q < n; ++q)
             if (cell[q] < 0 || cell[q] >= I.ncell || g[q] < 0 || g[q] >= I.G || !(w[q] >= 0) || !(nu[q] > 0))
                 fail(UGKWP_EINVAL, "particle %lld: cell, group, weight or frequency out of range", (long long)q);
-        const Pool& p = ctx->pool[ctx->cur];
+        const Pool p = ctx->view(ctx->cur_mv, ctx->cur_st);
         hipStream_t st = ctx->st;
         auto cp = [&](void* dst, const void* src, size_t bytes) {
             if (bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
@@ -887,8 +937,11 @@ int ugkwp_set_pool(ugkwp_ctx* ctx, int64_t n, const double* x, const double* y, 
         HIPCHK(hipStreamSynchronize(st));
         s.births = birth_counter;
         HIPCHK(hipMemcpyAsync(ctx->D.ist, &s, sizeof(InstState), hipMemcpyHostToDevice, st));
+        const unsigned long long na[3] = {(unsigned long long)n, (unsigned long long)n, (unsigned long long)n};
+        HIPCHK(hipMemcpyAsync(ctx->D.counters + CNT_SLOTS, na, sizeof(na), hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
         ctx->n_alive = n;
+        ctx->n_slots = n;
     });
 }
 
