@@ -1,11 +1,19 @@
 """Throughput benchmark of the UGKWP hot path on one MI355X.
 
-Workload: the two-material slab (2000 cells x 64 log-spaced groups on
-[0.01, 10], kappa = 0.01 | 1000 jump at x = 0.5, dt = 1e-4, Planckian left
-wall at T = 1), advanced from t = 0 through a fixed 500-step spin-up that
-fills the particle pool (set-up, untimed), then `--warmup` untimed steps,
-then `--steps` timed steps.  A step is one full time step of the method
-(sampling, particle push, wave flux, source iteration) over the whole mesh.
+Workloads (--workload):
+  slab     (default) two-material slab: 2000 cells x 64 log-spaced groups on
+           [0.01, 10], kappa = 0.01 | 1000 jump at x = 0.5, dt = 1e-4,
+           Planckian left wall at T = 1
+  lattice  2-D block lattice 256 x 256 cells x 32 groups on [0,7]^2 with a
+           pinned central source, dt = 1e-3
+  batch    512 independent slabs of 64..4096 cells and 16/32/64 groups in one
+           context (one launch per kernel per step); --per-instance steps the
+           same instances in 512 separate contexts instead
+
+Each run advances from t = 0 through a fixed spin-up (set-up, untimed) that
+fills the particle pool, then `--warmup` untimed steps, then `--steps` timed
+steps.  A step is one full time step of the method (sampling, particle push,
+wave flux, source iteration) over every instance.
 
 Prints one JSON line: particle-pushes/s over the timed steps (whole step,
 inputs resident in HBM), cell-group source-iteration updates/s, the push
@@ -26,36 +34,104 @@ HBM_PEAK_GBS = 8000.0
 PUSH_BYTES_READ = 48       # x, mu, nu, w, id (8 B each) + cell word, group (4 B each)
 PUSH_BYTES_WRITE = 12      # new position and cell word of a survivor (updated in place)
 PUSH_BYTES_DEAD = 4        # empty-slot mark of a particle absorbed or gone
-SPINUP = 500
+SPINUP = {"slab": 500, "lattice": 300, "batch": 100}
+BYTES_2D = (64, 20, 4)     # 2-D: x, y, ox, oy, nu, w, id + cell word, group; writes x, y, cell word
 
 
-def cpu_baseline(prob, budget_s=15.0):
-    """The oracle as it stands, single thread, on the first steps of the same run."""
+def cpu_baseline(probs, budget_s=15.0):
+    """The oracle as it stands, single thread, on the first steps of the same run
+    (for a batch: the instances in turn, each from t = 0)."""
     import oracle
-    sim = oracle.Sim(prob)
     pushes = 0
     steps = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and steps < prob.steps:
-        sim.step(1)
-        pushes += sim.diag()["n_alive_in"] + sim.diag()["n_births"]
-        steps += 1
+    sims = []
+    done = False
+    for prob in probs:
+        sim = oracle.Sim(prob)
+        sims.append(sim)
+        for _ in range(prob.steps):
+            sim.step(1)
+            d = sim.diag()
+            pushes += d["n_alive_in"] + d["n_births"]
+            steps += 1
+            if time.perf_counter() - t0 >= budget_s:
+                done = True
+                break
+        if done:
+            break
     dt = time.perf_counter() - t0
+    what = (f"steps 0-{steps - 1} of the same run from t=0" if len(probs) == 1 else
+            f"{steps} instance-steps of the first {len(sims)} instances from t=0")
     return {"value": pushes / dt, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
-            "sample": f"steps 0-{steps - 1} of the same slab run from t=0 ({pushes} pushes, "
-                      f"{dt:.1f} s, single thread)"}
+            "sample": f"{what} ({pushes} pushes, {dt:.1f} s, single thread)"}
+
+
+def summarize_trace(csv_path, steps, push_kernel="k_push"):
+    """Text summary of a rocprofv3 kernel trace of this benchmark restricted to
+    the timed steps: the window opens at the start of the push dispatch that
+    begins the last `steps` steps.  Prints per-kernel calls, total and average
+    duration in that window."""
+    import csv
+    rows = list(csv.DictReader(open(csv_path)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    pushes = [r for r in rows if push_kernel in r["Kernel_Name"]]
+    if len(pushes) < steps:
+        raise SystemExit(f"trace holds {len(pushes)} push dispatches, fewer than {steps} steps")
+    t0 = int(pushes[-steps]["Start_Timestamp"])
+    stats = {}
+    for r in rows:
+        if int(r["Start_Timestamp"]) < t0:
+            continue
+        d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        e = stats.setdefault(r["Kernel_Name"], [0, 0, 0, 1 << 62])
+        e[0] += 1
+        e[1] += d
+        e[2] = max(e[2], d)
+        e[3] = min(e[3], d)
+    total = sum(v[1] for v in stats.values())
+    lines = [f"timed window: last {steps} steps ({len(pushes)} push dispatches in the trace)",
+             f"{'kernel':70s} {'calls':>6s} {'total_us':>10s} {'avg_us':>9s} {'min_us':>8s} {'max_us':>8s} {'pct':>6s}"]
+    for name, (n, tot, mx, mn) in sorted(stats.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"{name[:70]:70s} {n:6d} {tot / 1e3:10.1f} {tot / n / 1e3:9.2f} {mn / 1e3:8.2f} "
+                     f"{mx / 1e3:8.2f} {100.0 * tot / total:6.2f}")
+    return "\n".join(lines)
+
+
+def workload_name(wl, probs, spin, args):
+    first, last = spin + args.warmup, spin + args.warmup + args.steps - 1
+    if wl == "slab":
+        p = probs[0]
+        return (f"two-material slab {p.nx} cells x {p.G} groups, dt=1e-4, kappa 0.01|1000 jump at "
+                f"x=0.5, steps {first}-{last} of the run from t=0")
+    if wl == "lattice":
+        p = probs[0]
+        return (f"2-D lattice {p.nx}x{p.ny} cells x {p.G} groups, dt=1e-3, kappa 100|1 squares, "
+                f"pinned source, steps {first}-{last} of the run from t=0")
+    return (f"{len(probs)} independent slabs (64-4096 cells, 16/32/64 groups, kappa jump), dt=1e-4, "
+            f"steps {first}-{last} of the run from t=0")
 
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
+                    help="print the kernel summary of a rocprofv3 trace of this benchmark over the "
+                         "last --steps steps, and exit")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--workload", choices=("slab", "lattice", "batch"), default="slab")
+    ap.add_argument("--per-instance", action="store_true",
+                    help="batch workload: one context per instance instead of one batched context")
+    ap.add_argument("--spinup", type=int, default=-1, help="untimed steps from t=0 (default per workload)")
     ap.add_argument("--sort-interval", type=int, default=0,
                     help="steps between counting sorts of the pool (0 = library default)")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace, args.steps))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -66,14 +142,40 @@ def main():
     from paper_2312_16981_amd import workloads as W
 
     torch.cuda.set_device(0)
-    prob = W.c2_two_material()
     stream = torch.cuda.current_stream()
-    ctx = ugkwp.from_problem(prob, stream=stream.cuda_stream, sort_interval=args.sort_interval)
-    ncg = prob.ncell * prob.G
+    wl = args.workload
+    if wl == "slab":
+        probs = [W.c2_two_material()]
+    elif wl == "lattice":
+        probs = [W.c3_lattice()]
+    else:
+        probs = W.c4_batch()
+    ncg = sum(p.ncell * p.G for p in probs)
+    spin = SPINUP[wl] if args.spinup < 0 else args.spinup
+    if wl == "batch" and args.per_instance:
+        ctxs = [ugkwp.from_problem(p, stream=stream.cuda_stream, sort_interval=args.sort_interval)
+                for p in probs]
+    elif wl == "batch":
+        ctxs = [ugkwp.from_batch(probs, stream=stream.cuda_stream, pool_capacity=1 << 26,
+                                 sort_interval=args.sort_interval)]
+    else:
+        ctxs = [ugkwp.from_problem(probs[0], stream=stream.cuda_stream, sort_interval=args.sort_interval)]
 
-    ctx.step(SPINUP)
-    for _ in range(args.warmup):
-        ctx.step(1)
+    def one_step():
+        acc = {"n_pushed": 0, "n_alive_out": 0, "sweeps": 0, "ms_push": 0.0, "ms_si": 0.0, "ms_sort": 0.0}
+        for c in ctxs:
+            c.step(1)
+            d = c.get_diag()
+            acc["n_pushed"] += d["n_pushed"]
+            acc["n_alive_out"] += d["n_alive_out"]
+            acc["ms_push"] += d["ms_push"]
+            acc["ms_si"] += d["ms_si"]
+            acc["ms_sort"] += d["ms_sort"]
+            acc["sweeps"] += d["sweeps_sum"]
+        return acc
+
+    for _ in range(spin + args.warmup):
+        one_step()
     torch.cuda.synchronize()
 
     pushes = 0
@@ -84,20 +186,22 @@ def main():
     ms_sort = 0.0
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.step(1)
-        d = ctx.get_diag()
+        d = one_step()
         pushes += d["n_pushed"]
         survivors += d["n_alive_out"]
-        sweeps += d["sweeps_max"]
+        sweeps += d["sweeps"]
         ms_push += d["ms_push"]
         ms_si += d["ms_si"]
         ms_sort += d["ms_sort"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # cell-group updates: every instance's cell-groups times its own sweep count
+    cg_per_inst = [p.ncell * p.G for p in probs]
+    mean_cg = ncg / len(probs)
 
     value = pushes / elapsed
-    algo_bytes = (PUSH_BYTES_READ * pushes + PUSH_BYTES_WRITE * survivors
-                  + PUSH_BYTES_DEAD * (pushes - survivors))
+    br, bw, bd = (PUSH_BYTES_READ, PUSH_BYTES_WRITE, PUSH_BYTES_DEAD) if probs[0].dim == 1 else BYTES_2D
+    algo_bytes = br * pushes + bw * survivors + bd * (pushes - survivors)
     achieved = algo_bytes / (ms_push * 1e-3) / 1e9
     out = {
         "metric": "particle-pushes/s (whole UGKWP step, FP64, parity 1e-10 vs oracle)",
@@ -112,25 +216,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"two-material slab {prob.nx} cells x {prob.G} groups, dt=1e-4, "
-                               f"kappa 0.01|1000 jump at x=0.5, steps {SPINUP + args.warmup}-"
-                               f"{SPINUP + args.warmup + args.steps - 1} of the run from t=0",
+        "config": {"workload": workload_name(wl, probs, spin, args),
                    "particles_per_step": pushes / max(args.steps, 1),
-                   "parallelism": "single GPU"},
-        "cell_group_updates_per_s": ncg * sweeps / elapsed,
-        "cell_group_updates_per_s_si_only": ncg * sweeps / (ms_si * 1e-3) if ms_si > 0 else None,
+                   "cell_groups": ncg,
+                   "parallelism": "single GPU" + (", per-instance contexts" if args.per_instance else "")},
+        "cell_group_updates_per_s": mean_cg * sweeps / elapsed,
+        "cell_group_updates_per_s_si_only": mean_cg * sweeps / (ms_si * 1e-3) if ms_si > 0 else None,
         "push_kernel_pushes_per_s": pushes / (ms_push * 1e-3),
-        "sweeps_per_step": sweeps / max(args.steps, 1),
+        "push_kernel_avg_us": ms_push * 1e3 / max(args.steps, 1),
+        "sweeps_per_step": sweeps / max(args.steps, 1) / len(probs),
         "ms_per_step_phases": {"push": ms_push / max(args.steps, 1), "si": ms_si / max(args.steps, 1),
                                "sort": ms_sort / max(args.steps, 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_push<1>", "algorithmic_bytes_per_push":
-                     f"{PUSH_BYTES_READ} read + {PUSH_BYTES_WRITE} per survivor + "
-                     f"{PUSH_BYTES_DEAD} per absorbed/escaped particle"},
+                     "kernel": f"k_push<{probs[0].dim}>", "algorithmic_bytes_per_push":
+                     f"{br} read + {bw} per survivor + {bd} per absorbed/escaped particle"},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(probs, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

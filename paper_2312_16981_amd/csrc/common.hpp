@@ -15,6 +15,8 @@ namespace ugk {
 constexpr int WAVE = 64;
 constexpr int MAX_G = 64;
 constexpr int RES_SLOTS = 3;     // rotating residual slots of the source iteration
+constexpr int RES_SUB = 64;      // sub-slots per residual slot (spread the atomics of many blocks)
+constexpr int DIAG_SUB = 16;     // sub-slots of the per-instance energy sums
 
 enum { BC_VACUUM = 0, BC_PLANCK = 1, BC_REFLECT = 2 };
 enum { XLO = 0, XHI = 1, YLO = 2, YHI = 3 };
@@ -147,8 +149,9 @@ struct Dev {
     const uint8_t* pinned;
     // per instance
     InstState* ist;
-    Resid* res;                 // [n_inst][RES_SLOTS]
-    double* diag;               // [n_inst][8]
+    Resid* res;                 // [n_inst][RES_SLOTS][RES_SUB]
+    double* diag;               // [n_inst][8] (folded from diag_sub each step)
+    double* diag_sub;           // [n_inst][DIAG_SUB][8]
     // context-wide counters
     unsigned long long* counters;   // CNT_*
     int64_t* n_births_total;        // [0] births of the step, [1] survivors (sort scan)

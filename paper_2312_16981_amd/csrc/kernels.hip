@@ -786,7 +786,8 @@ __device__ inline void wave_source(const Dev& D, const Consts& K, int64_t j, con
         a_out += D.fty[fb * 2 + 1] + D.fty[ft * 2 + 0];
     }
     D.Q[j] = D.rho[j] + (K.dt / I.V) * fsum + (a_in - a_out) / I.V;
-    if (inflow != 0.0) atomicAdd(D.diag + s.inst * 8 + 0, inflow);
+    if (inflow != 0.0)
+        atomicAdd(D.diag_sub + ((int64_t)s.inst * DIAG_SUB + (blockIdx.x & (DIAG_SUB - 1))) * 8 + 0, inflow);
 }
 
 // ---------------------------------------------------------------------------
@@ -818,9 +819,12 @@ __global__ void k_macro_setup(Dev D, Consts K)
         D.phi1[j] = 0.0;
         D.rho_new[j] = 0.0;
     }
-    if (j == D.inst[s.inst].cg_off) {
+    const int64_t rel = j - D.inst[s.inst].cg_off;
+    if (rel >= 0 && rel < RES_SUB) {            // first wavefront of the instance
         Resid z = {0ull, 0ull, 0ull, 0ull};
-        D.res[s.inst * RES_SLOTS + 0] = z;
+        D.res[((int64_t)s.inst * RES_SLOTS + 0) * RES_SUB + rel] = z;
+    }
+    if (rel == 0) {
         D.ist[s.inst].conv_sweeps = 0;
         D.ist[s.inst].bad = 0;
     }
@@ -837,12 +841,14 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const bool first = j == I.cg_off;
 
-    // convergence decision from the previous sweep (identical in every thread of the instance)
+    // convergence decision from the previous sweep (identical in every thread of the
+    // instance): lane l reads sub-slot l, the wavefront takes the maxima
     bool run = D.ist[s.inst].conv_sweeps == 0 && j < K.n_cg;
-    if (run && k > 0) {
-        const Resid r = D.res[s.inst * RES_SLOTS + (k - 1) % RES_SLOTS];
-        const double drho = bitsd(r.drho), mrho = bitsd(r.rho), dT = bitsd(r.dT), mT = bitsd(r.T);
-        if (drho <= K.si_tol * mrho && dT <= K.si_tol * mT) {
+    if (k > 0) {
+        const Resid r = D.res[((int64_t)s.inst * RES_SLOTS + (k - 1) % RES_SLOTS) * RES_SUB + lane];
+        const double drho = wave_nmax(bitsd(r.drho)), mrho = wave_nmax(bitsd(r.rho));
+        const double dT = wave_nmax(bitsd(r.dT)), mT = wave_nmax(bitsd(r.T));
+        if (run && drho <= K.si_tol * mrho && dT <= K.si_tol * mT) {
             run = false;
             if (first) {
                 D.ist[s.inst].conv_sweeps = k;
@@ -850,9 +856,10 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
             }
         }
     }
-    if (first && !check_only) {
+    const int64_t rel = j - I.cg_off;
+    if (rel >= 0 && rel < RES_SUB && !check_only) {
         Resid z = {0ull, 0ull, 0ull, 0ull};
-        D.res[s.inst * RES_SLOTS + (k + 1) % RES_SLOTS] = z;
+        D.res[((int64_t)s.inst * RES_SLOTS + (k + 1) % RES_SLOTS) * RES_SUB + rel] = z;
     }
     if (check_only) run = false;
 
@@ -968,7 +975,8 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
                 ++w1;
             }
             if (any) {
-                Resid* r = D.res + winst[w0] * RES_SLOTS + k % RES_SLOTS;
+                Resid* r = D.res + ((int64_t)winst[w0] * RES_SLOTS + k % RES_SLOTS) * RES_SUB +
+                           (blockIdx.x & (RES_SUB - 1));
                 atomicMax(&r->drho, dbits(a0));
                 atomicMax(&r->rho, dbits(a1));
                 atomicMax(&r->dT, dbits(a2));
@@ -1067,12 +1075,24 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K)
                 ++w1;
             }
             if (winst[w0] >= 0) {
-                double* dg = D.diag + winst[w0] * 8;
+                double* dg = D.diag_sub + ((int64_t)winst[w0] * DIAG_SUB + (blockIdx.x & (DIAG_SUB - 1))) * 8;
                 for (int q = 0; q < 5; ++q)
                     if (acc[q] != 0.0) atomicAdd(dg + 1 + q, acc[q]);
             }
             w0 = w1;
         }
+    }
+}
+
+// Fold the energy-sum sub-slots into diag[inst][8].
+__global__ void k_diag_reduce(Dev D, Consts K)
+{
+    const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+    if (inst >= K.n_inst) return;
+    for (int q = 0; q < 8; ++q) {
+        double acc = 0.0;
+        for (int b = 0; b < DIAG_SUB; ++b) acc += D.diag_sub[((int64_t)inst * DIAG_SUB + b) * 8 + q];
+        D.diag[(int64_t)inst * 8 + q] = acc;
     }
 }
 
@@ -1215,7 +1235,11 @@ void launch_push(int dim, const Dev& D, const Consts& K, const Pool& In, const P
         if (single) k_push<2, true><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
         else k_push<2, false><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
     }
-    k_pool_count<<<1, 256, 0, st>>>(D, nb);
+}
+
+void launch_pool_count(int dim, const Dev& D, const Consts& K, hipStream_t st)
+{
+    k_pool_count<<<1, 256, 0, st>>>(D, push_grid(dim, K.n_inst == 1));
 }
 
 void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& In, const Pool& Out, hipStream_t st)
@@ -1246,6 +1270,7 @@ void launch_si_sweep(const Dev& D, const Consts& K, int k, bool check_only, hipS
 void launch_finish(const Dev& D, const Consts& K, hipStream_t st)
 {
     k_finish<<<blocks(K.n_cg, DIAG_THREADS), DIAG_THREADS, 0, st>>>(D, K);
+    k_diag_reduce<<<blocks(K.n_inst, 64), 64, 0, st>>>(D, K);
 }
 
 void launch_eval_phi(int n, const double* T, int G, const double* nu, double a, double c, double* out,

@@ -26,6 +26,7 @@ void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, uint32
 int push_grid(int dim, bool single);
 void launch_push(int dim, const Dev& D, const Consts& K, const Pool& A, const Pool& B, uint32_t step,
                  hipStream_t st);
+void launch_pool_count(int dim, const Dev& D, const Consts& K, hipStream_t st);
 void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& B, const Pool& A, hipStream_t st);
 void launch_macro_setup(const Dev& D, const Consts& K, hipStream_t st);
 void launch_si_sweep(const Dev& D, const Consts& K, int k, bool check_only, hipStream_t st);

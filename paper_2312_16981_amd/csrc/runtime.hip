@@ -359,7 +359,8 @@ struct ugkwp_ctx {
         d.n_births_total = (int64_t*)((char*)d_status + off_tot);
         d.ist = (InstState*)((char*)d_status + off_ist);
         d.diag = (double*)((char*)d_status + off_diag);
-        d.res = dalloc<Resid>(owned, (size_t)n_inst * RES_SLOTS);
+        d.res = dalloc<Resid>(owned, (size_t)n_inst * RES_SLOTS * RES_SUB);
+        d.diag_sub = dalloc<double>(owned, (size_t)n_inst * DIAG_SUB * 8);
         n_part = scan_partials_size(n_cg);
         part = dalloc<int64_t>(owned, (size_t)n_part + 1);
         HIPCHK(hipMemsetAsync(d.ist, 0, sizeof(InstState) * n_inst, st));
@@ -510,7 +511,7 @@ struct ugkwp_ctx {
         add(D.dep, K.n_cg);
         add(D.surv, K.n_cg);
         add(D.scount, K.n_cg / 2);
-        add(D.diag, 8 * (int64_t)n_inst);
+        add(D.diag_sub, (int64_t)DIAG_SUB * 8 * n_inst);
         add(D.counters, 4);                 // CNT_SURV .. CNT_CONV; slot and live counts persist
         launch_zero(z, st);
 
@@ -522,6 +523,7 @@ struct ugkwp_ctx {
         HIPCHK(hipEventRecord(ev[1], st));
         launch_push(dim, D, K, In, moving(1 - cur_mv), step_idx, st);
         HIPCHK(hipEventRecord(ev[2], st));
+        launch_pool_count(dim, D, K, st);
         launch_macro_setup(D, K, st);
         HIPCHK(hipEventRecord(ev[3], st));
         const int kmax = P.si_max_iters;

@@ -115,7 +115,7 @@ def c3_lattice(n: int = 256, G: int = 32, **kw) -> Problem:
     ncell = n * n
     T0 = np.full(ncell, 1e-3)
     T0[src] = 1.0
-    p = dict(dt=1e-3, steps=500, w_ref=2e-4, pool_cap=1 << 26, seed=0)
+    p = dict(dt=1e-3, steps=500, w_ref=1e-6, pool_cap=1 << 27, seed=0)
     p.update(kw)
     return Problem(name=f"lattice{n}x{n}_g{G}", dim=2, nx=n, ny=n, x0=0.0, x1=L, y0=0.0, y1=L,
                    bc=[BC_VACUUM] * 4, bcT=[0.0] * 4, nu_edges=log_edges(0.01, 10.0, G),
@@ -141,7 +141,7 @@ def c5_lognormal(n: int = 128, G: int = 16, **kw) -> Problem:
 
 
 def c4_batch(n_inst: int = 512, nx_range=(64, 4096), groups=(16, 32, 64), steps: int = 200,
-             dt: float = 1e-4, w_ref: float = 2e-5, key: int = 1) -> List[Problem]:
+             dt: float = 1e-4, w_ref: float = 5e-4, key: int = 1) -> List[Problem]:
     """Independent 1-D slabs with uneven sizes: nx ~ U{64..4096}, G in {16,32,64},
     kappa_L, kappa_R ~ logU[1e-2, 1e3], jump position ~ U(0,1); instance seeds 0..n-1.
     Instance parameters come from numpy's Philox bit generator with the given key."""
@@ -153,7 +153,7 @@ def c4_batch(n_inst: int = 512, nx_range=(64, 4096), groups=(16, 32, 64), steps:
         kl, kr = 10.0 ** rng.uniform(-2.0, 3.0, size=2)
         xj = float(rng.uniform(0.0, 1.0))
         pr = slab(nx, G, lambda x, kl=kl, kr=kr, xj=xj: np.where(x < xj, kl, kr),
-                  dt=dt, steps=steps, w_ref=w_ref, seed=k, pool_cap=1 << 20,
+                  dt=dt, steps=steps, w_ref=w_ref, seed=k, pool_cap=1 << 17,
                   name=f"inst{k}_nx{nx}_g{G}")
         out.append(pr)
     return out

@@ -221,3 +221,24 @@ def test_two_material_full_size_first_steps():
     """2000 cells x 64 groups (the benchmark workload) for its first 40 steps."""
     p = W.c2_two_material()
     run_pair(p, 40, every=10)
+
+
+def test_lattice_full_size_first_steps():
+    """256 x 256 cells x 32 groups with the pinned source (the 2-D benchmark workload)."""
+    run_pair(W.c3_lattice(), 3)
+
+
+def test_batch_full_size_sampled_instances():
+    """All 512 uneven slabs advance in one batched context; 8 sampled instances are
+    checked against independent oracle runs (the oracle cannot afford all 512)."""
+    probs = W.c4_batch()
+    say("[parity] batch of", len(probs), "cell-groups", sum(p.ncell * p.G for p in probs))
+    ctx = ugkwp.from_batch(probs, pool_capacity=1 << 24)
+    nsteps = 3
+    ctx.step(nsteps)
+    rng = np.random.default_rng(2)
+    sample = sorted(rng.choice(len(probs), size=8, replace=False).tolist())
+    for k in sample:
+        s = oracle.Sim(probs[k])
+        s.step(nsteps)
+        compare_state(ctx, s, probs[k], inst=k, what=f"instance {k}")
