@@ -98,6 +98,45 @@ def summarize_trace(csv_path, steps, push_kernel="k_push"):
     return "\n".join(lines)
 
 
+def summarize_counters(csv_path, steps, kernel="k_push"):
+    """Per-dispatch average of each counter in a rocprofv3 --pmc CSV over the last
+    `steps` dispatches of the kernel whose name contains `kernel` (all of its
+    dispatches if it ran fewer times), and over the largest dispatches of every
+    other kernel (for a copy-probe run)."""
+    import csv
+    rows = list(csv.DictReader(open(csv_path)))
+    by = {}
+    for r in rows:
+        key = (r["Kernel_Name"], r["Counter_Name"])
+        by.setdefault(key, []).append((int(r.get("Dispatch_Id", r.get("Correlation_Id", 0))),
+                                       float(r["Counter_Value"]), int(r.get("Grid_Size", 0))))
+    lines = [f"{'kernel':60s} {'counter':12s} {'dispatches':>10s} {'avg_KiB':>14s} {'grid':>10s}"]
+    for (name, ctr), v in sorted(by.items()):
+        v.sort()
+        if kernel in name:
+            sel = v[-steps:]
+        else:
+            gmax = max(g for _, _, g in v)
+            sel = [t for t in v if t[2] == gmax]
+        avg = sum(t[1] for t in sel) / len(sel)
+        lines.append(f"{name[:60]:60s} {ctr:12s} {len(sel):10d} {avg:14.1f} {sel[-1][2]:10d}")
+    return "\n".join(lines)
+
+
+def copy_probe(mib=1024, reps=5):
+    """A plain elementwise copy (dst = -src, float64) of `mib` MiB read and
+    `mib` MiB written, repeated: the known-size reference for HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                      "reps": reps}), flush=True)
+
+
 def workload_name(wl, probs, spin, args):
     first, last = spin + args.warmup, spin + args.warmup + args.steps - 1
     if wl == "slab":
@@ -117,6 +156,11 @@ def main():
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
                     help="print the kernel summary of a rocprofv3 trace of this benchmark over the "
                          "last --steps steps, and exit")
+    ap.add_argument("--summarize-counters", metavar="COUNTER_CSV",
+                    help="print per-dispatch counter averages of a rocprofv3 --pmc CSV of this "
+                         "benchmark over the last --steps push dispatches, and exit")
+    ap.add_argument("--copy-probe", type=int, metavar="MIB", default=0,
+                    help="run a plain device copy of MIB MiB (HBM counter reference) and exit")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
@@ -132,10 +176,17 @@ def main():
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.steps))
         return
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters, args.steps))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     import torch
     from paper_2312_16981_amd import ugkwp

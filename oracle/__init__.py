@@ -58,7 +58,8 @@ def lib():
         L.ora_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         L.ora_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
         L.ora_uniform.restype = _d
-        for f in ("ora_planck_tail", "ora_planck_head", "ora_coef_c4", "ora_coef_w", "ora_coef_c2_over_dt"):
+        for f in ("ora_planck_tail", "ora_planck_head", "ora_coef_c4", "ora_coef_w", "ora_coef_c2_over_dt",
+                  "ora_coef_c4_ds", "ora_coef_w_ds", "ora_coef_c2_over_dt_ds"):
             getattr(L, f).argtypes = [_d]
             getattr(L, f).restype = _d
         for f in ("ora_phi_group", "ora_dphi_group"):
@@ -135,6 +136,18 @@ def coef_w(s):
 
 def coef_c2_over_dt(s):
     return lib().ora_coef_c2_over_dt(s)
+
+
+def coef_c4_ds(s):
+    return lib().ora_coef_c4_ds(s)
+
+
+def coef_w_ds(s):
+    return lib().ora_coef_w_ds(s)
+
+
+def coef_c2_over_dt_ds(s):
+    return lib().ora_coef_c2_over_dt_ds(s)
 
 
 def freq_slope(nl, nh, T):

@@ -54,6 +54,10 @@ double ora_dphi_group(double T, double nl, double nh, double a, double c);
 double ora_coef_c4(double s);          /* C4 = (1 - e^{-s}) / s           */
 double ora_coef_w(double s);           /* W  = C4 - e^{-s}                 */
 double ora_coef_c2_over_dt(double s);  /* C2 / dt  (C2 of the F^eq flux)   */
+/* Their derivatives in s (adjoint of the macroscopic solve). */
+double ora_coef_c4_ds(double s);
+double ora_coef_w_ds(double s);
+double ora_coef_c2_over_dt_ds(double s);
 
 /* Linear-frequency sampling: slope beta = (B(nh) - B(nl)) / B(nmid), limited
  * to [-2, 2], at temperature T. */

@@ -171,6 +171,50 @@ double ora_coef_c2_over_dt(double s)
     return (2.0 * ora_coef_c4(s) - 1.0 - exp(-s)) / s;
 }
 
+/* Derivatives in s, needed by the adjoint of the macroscopic solve.  From the
+ * closed forms above:
+ *   dC4/ds      = (e^{-s} - C4)/s = -W/s
+ *   dW/ds       = dC4/ds + e^{-s} = e^{-s} - W/s
+ *   d(C2/dt)/ds = (2 dC4/ds + e^{-s} - C2/dt)/s
+ * W/s comes from W's series below s = 1 (it tends to 1/2 at s = 0); the last
+ * form cancels for small s, where the series of C2/dt is differentiated term
+ * by term instead:  d(C2/dt)/ds = sum_{n>=2} (-1)^{n+1} (n-1)^2 s^{n-2}/(n+1)!. */
+static double w_over_s(double s)
+{
+    if (s < 1.0) {
+        double sum = 0.0, pw = 1.0, fact = 1.0;   /* pw = s^{n-1}, fact = (n+1)! */
+        for (int n = 1; n < 60; ++n) {
+            if (n > 1) pw *= s;
+            fact *= (double)(n + 1);
+            double term = (double)n * pw / fact;
+            sum += (n & 1) ? term : -term;
+            if (term < 1e-18 * fabs(sum)) break;
+        }
+        return sum;
+    }
+    return ora_coef_w(s) / s;
+}
+
+double ora_coef_c4_ds(double s) { return -w_over_s(s); }
+
+double ora_coef_w_ds(double s) { return exp(-s) - w_over_s(s); }
+
+double ora_coef_c2_over_dt_ds(double s)
+{
+    if (s < 2.0) {
+        double sum = 0.0, pw = 1.0, fact = 2.0;    /* pw = s^{n-2}, fact = (n+1)! */
+        for (int n = 2; n < 80; ++n) {
+            if (n > 2) pw *= s;
+            fact *= (double)(n + 1);
+            double term = (double)((n - 1) * (n - 1)) * pw / fact;
+            sum += (n & 1) ? term : -term;
+            if (term < 1e-18 * fabs(sum)) break;
+        }
+        return sum;
+    }
+    return (-2.0 * w_over_s(s) + exp(-s) - ora_coef_c2_over_dt(s)) / s;
+}
+
 /* ------------------------------------------------------------------ */
 /* Linear-frequency sampling (Eqs. Blinear, kg; Appendix A).
  * B_lin(nu) = B(nmid) + k_g (nu - nmid),  k_g = (B(nh) - B(nl)) / (nh - nl).

@@ -38,16 +38,12 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
-#include "oracle.h"
+#include "oracle_internal.h"
 
 #define XLO 0
 #define XHI 1
 #define YLO 2
 #define YHI 3
-
-typedef struct {
-    double *rho, *T, *rhop, *rhoh, *wnet; unsigned char* sampled;
-} ora_rec_step;
 
 struct ora_sim {
     ora_params p;
@@ -835,13 +831,16 @@ int ora_record(ora_sim* s, int on)
     return ORA_OK;
 }
 
-/* Accessors for oracle_adjoint.c (same translation unit family, not exported in the header). */
+/* Accessors for oracle_adjoint.c (declared in oracle_internal.h). */
 int ora__nrec(const ora_sim* s) { return s->nrec; }
 const ora_rec_step* ora__rec(const ora_sim* s, int k) { return &s->rec[k]; }
 const ora_params* ora__params(const ora_sim* s) { return &s->p; }
 const double* ora__simpson(const ora_sim* s) { return s->simpson; }
 const double* ora__cv(const ora_sim* s) { return s->cv; }
 const unsigned char* ora__pinned(const ora_sim* s) { return s->pinned; }
+const double* ora__kappa_rec(const ora_sim* s) { return s->kappa0; }
+const double* ora__T(const ora_sim* s) { return s->T; }
+const double* ora__rho(const ora_sim* s) { return s->rho; }
 double ora__V(const ora_sim* s) { return s->V; }
 double ora__dx(const ora_sim* s) { return s->dx; }
 double ora__dy(const ora_sim* s) { return s->dy; }
