@@ -179,6 +179,50 @@ int ugkwp_set_pool(ugkwp_ctx* ctx, int64_t n, const double* x, const double* y,
                    const uint64_t* id, const int32_t* cell, const int32_t* g,
                    uint64_t birth_counter, const double* rhop);
 
+/* ---- adjoint of the macroscopic solve with the particle results held fixed ----
+ *
+ * The paper differentiates nothing; this is the derivative of the following
+ * map.  A recorded forward run hands three particle-phase results per step to
+ * its macroscopic solve: the net particle flux w^{fr,p} (Eq. wfrpFormula),
+ * the survivor density rho^p, and which cell-groups sampled particles (the
+ * choice between C4 - e^{-s} and C4 in the wave flux, Remark 3).  Holding them
+ * fixed, a step maps (rho^n, T^n, kappa) to the fixed point (rho^{n+1}, T^{n+1})
+ * of Eq. macroSysFinal solved by the source iteration of Appendix B, through
+ * sigma = kappa S_g, s = c sigma dt / eps^2, C4(s), W(s), the harmonic face
+ * opacity and C2 (Eq. C2Formula).  ugkwp_adjoint returns dJ/dkappa of
+ * J = sum_cells dJdT[cell] T_cell after the last recorded step (dJdT = V C_v
+ * gives the material energy) by a reverse sweep over the recorded steps, each
+ * a transposed source iteration followed by the cotangents of the coefficients.
+ *
+ * Discrete particle events (sample counts, collisions, crossings) have no
+ * derivative; a finite difference of the whole stochastic step is not what this
+ * computes. */
+
+/* Start a record with room for max_steps steps (device memory: per step about
+ * 17 bytes per (cell, group) slot and 8 per cell), discarding any earlier one;
+ * max_steps = 0 stops recording and frees it.  Each committed ugkwp_step then
+ * adds one step; a step beyond max_steps fails with UGKWP_EINVAL before it
+ * starts.  ugkwp_set_material restarts the record at the new initial state;
+ * ugkwp_set_opacity fails while a record is kept. */
+int ugkwp_record(ugkwp_ctx* ctx, int max_steps);
+int ugkwp_recorded_steps(const ugkwp_ctx* ctx);
+
+typedef struct {
+    int steps;               /* recorded steps swept                              */
+    int sweeps_launched;     /* transposed source-iteration sweeps launched, sum  */
+    int sweeps_max;          /* largest per step                                   */
+    double ms;               /* GPU time of the whole reverse sweep                */
+} ugkwp_adjoint_stats;
+
+/* dJdT [ncell] and grad_kappa [ncell][G] (all instances, concatenated as for
+ * ugkwp_get_fields), host arrays, or device pointers read and written on the
+ * context stream when ptrs_are_device = 1.  stats may be NULL.  Returns
+ * UGKWP_EINVAL without recorded steps, UGKWP_ENOCONV if a transposed iteration
+ * does not converge in 1000 sweeps (relative max-norm change 1e-15, 1e-13 after
+ * 60 sweeps), UGKWP_ENONFINITE on a non-finite cotangent. */
+int ugkwp_adjoint(ugkwp_ctx* ctx, const double* dJdT, double* grad_kappa, int ptrs_are_device,
+                  ugkwp_adjoint_stats* stats);
+
 /* ---- device building blocks, exposed for element-wise checks (host arrays) ---- */
 
 /* out[i] = phi_g(T[i]) for g < G (group equilibrium value of rho, Sec. 2.1),

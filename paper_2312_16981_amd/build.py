@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libugkwp.so")
-SOURCES = ["kernels.hip", "runtime.hip"]
+SOURCES = ["kernels.hip", "adjoint.hip", "runtime.hip"]
 ARCH = os.environ.get("UGKWP_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1,0 +1,397 @@
+// HIP kernels (gfx950) of the recording and the reverse sweep of the adjoint
+// of the frozen-tally macroscopic map; see adjoint.hpp for what is stored and
+// differentiated.  Same (cell, group) slot layout and wavefront-per-cell
+// structure as the forward source iteration (kernels.hip): the Gp group lanes
+// of a cell sit in one wavefront, group sums are shuffles, Planck edge values
+// are shared by neighbouring lanes.
+#include "adjoint.hpp"
+#include "device_common.hpp"
+
+namespace ugk {
+
+__constant__ HeadSeries c_head_adj;
+
+hipError_t set_head_series_adj(const HeadSeries& hs)
+{
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_head_adj), &hs, sizeof(HeadSeries));
+}
+
+constexpr int ADJ_THREADS = 256;
+
+// x^4 / (e^x - 1): the edge term of d phi_g / dT
+__device__ inline double planck_edge_weight(double x)
+{
+    if (x > 700.0) return 0.0;
+    const double x2 = x * x;
+    return x2 * x2 / expm1(x);
+}
+
+// Heat-capacity weight dt / (eps^2 C_v) of the temperature update; 0 in pinned cells.
+__device__ inline double temp_weight(const Dev& D, const Consts& K, int cell)
+{
+    return D.pinned[cell] ? 0.0 : K.dt / (K.eps * K.eps * D.cvol[cell]);
+}
+
+// ---------------------------------------------------------------------------
+// recording (after a committed step: D.T holds T^{n+1})
+
+__global__ void k_rec_store(Dev D, Consts K, Adj A, int r)
+{
+    const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
+    if (j >= K.n_cg) return;
+    const Slot s = decode_slot(D, K, j);
+    const int64_t o = (int64_t)r * K.n_cg + j;
+    A.rQ[o] = D.Q[j];
+    A.rRhoh[o] = D.rhoh[j];
+    A.rSamp[o] = D.nb[j] > 0 ? 1 : 0;
+    if (s.cell_ok && s.g == 0) {
+        const int cell = D.inst[s.inst].cell_off + s.lcell;
+        A.rT[(int64_t)r * K.ncell + cell] = D.T[cell];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kappa-dependent coefficients of the reverse sweep (once per adjoint)
+
+__global__ void k_adj_coef(Dev D, Consts K, Adj A)
+{
+    const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
+    if (j >= K.n_cg) return;
+    const Slot s = decode_slot(D, K, j);
+    const double sv = D.sv[j];
+    A.c4d[j] = s.active ? coef_c4_ds(sv) : 0.0;
+    A.wd[j] = s.active ? coef_w_ds(sv) : 0.0;
+}
+
+// dD_f/dsigma of the cells on either side of each face: D_f = -(c^2/3eps^2) C2(s_f)/h
+// with s_f = c sf dt/eps^2 and sf the harmonic mean of the two cells' sigma (the
+// interior cell's sigma on a domain face).
+__global__ void k_adj_face(Dev D, Consts K, Adj A, int inst, int axis)
+{
+    const Inst& I = D.inst[inst];
+    const int64_t nface = axis == 0 ? (int64_t)(I.nx + 1) * I.ny : (int64_t)I.nx * (I.ny + 1);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nface * I.Gp) return;
+    const int64_t f = j >> I.lgGp;
+    const int g = (int)(j & (I.Gp - 1));
+    double* Dl = axis == 0 ? A.Dlx + I.fx_off : A.Dly + I.fy_off;
+    double* Dh = axis == 0 ? A.Dhx + I.fx_off : A.Dhy + I.fy_off;
+    if (g >= I.G) { Dl[j] = 0.0; Dh[j] = 0.0; return; }
+    int cl, cr;
+    double h;
+    if (axis == 0) {
+        const int iy = (int)(f / (I.nx + 1)), fx = (int)(f % (I.nx + 1));
+        cl = fx > 0 ? iy * I.nx + fx - 1 : -1;
+        cr = fx < I.nx ? iy * I.nx + fx : -1;
+        h = I.dx;
+    } else {
+        const int fy = (int)(f / I.nx), ix = (int)(f % I.nx);
+        cl = fy > 0 ? (fy - 1) * I.nx + ix : -1;
+        cr = fy < I.ny ? fy * I.nx + ix : -1;
+        h = I.dy;
+    }
+    double sf, dl = 0.0, dr = 0.0;
+    if (cl >= 0 && cr >= 0) {
+        const double a = D.sig[I.cg_off + ((int64_t)cl << I.lgGp) + g];
+        const double b = D.sig[I.cg_off + ((int64_t)cr << I.lgGp) + g];
+        const double ab = a + b;
+        sf = ab > 0.0 ? 2.0 * (a * b) / ab : 0.0;
+        if (ab > 0.0) {
+            dl = 2.0 * (b * b) / (ab * ab);
+            dr = 2.0 * (a * a) / (ab * ab);
+        }
+    } else {
+        sf = D.sig[I.cg_off + ((int64_t)(cl >= 0 ? cl : cr) << I.lgGp) + g];
+        if (cl >= 0) dl = 1.0; else dr = 1.0;
+    }
+    const double ks = K.c * K.dt / (K.eps * K.eps);
+    const double dDdsf = -(K.c * K.c / (3.0 * K.eps * K.eps)) * K.dt * ks * coef_c2_over_dt_ds(ks * sf) / h;
+    Dl[j] = dDdsf * dl;
+    Dh[j] = dDdsf * dr;
+}
+
+// ---------------------------------------------------------------------------
+// per recorded step, in reverse
+
+// phi and phi' at T^{n+1}; mu^0 = Tbar; convergence state of the step reset.
+__global__ __launch_bounds__(ADJ_THREADS) void k_adj_prep(Dev D, Consts K, Adj A, int r)
+{
+    const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
+    const Slot s = decode_slot(D, K, j);
+    const Inst& I = D.inst[s.inst];
+    const int g = s.g, G = I.G, Gp = I.Gp;
+    const bool work = s.cell_ok;
+    const int cell = I.cell_off + s.lcell;
+    const double T = work ? A.rT[(int64_t)r * K.ncell + cell] : 1.0;
+    // lane g: lower edge of group g; the upper edge comes from lane g+1
+    const bool edge_lane = work && g <= G;
+    const double xe = edge_lane ? D.nu[I.edge_off + g] / T : 0.0;
+    const double ve = edge_lane ? planck_edge_value(xe, c_head_adj) : 0.0;
+    const double we = edge_lane ? planck_edge_weight(xe) : 0.0;
+    double xh = __shfl_down(xe, 1, Gp < 2 ? 2 : Gp);
+    double vh = __shfl_down(ve, 1, Gp < 2 ? 2 : Gp);
+    double wh = __shfl_down(we, 1, Gp < 2 ? 2 : Gp);
+    if (work && g == G - 1 && G == Gp) {
+        xh = D.nu[I.edge_off + G] / T;
+        vh = planck_edge_value(xh, c_head_adj);
+        wh = planck_edge_weight(xh);
+    }
+    if (j < K.n_cg) {
+        if (s.active) {
+            const double phi = phi_from_band(K.a, K.c, T, planck_band_from_edges(xe, ve, xh, vh));
+            const double T3 = T * T * T;
+            A.phi[j] = phi;
+            A.dphi[j] = 4.0 * phi / T + K.a * K.c * T3 * (we - wh) / UGK_PI4_15;
+        } else {
+            A.phi[j] = 0.0;
+            A.dphi[j] = 0.0;
+        }
+        if (work && g == 0) A.mu0[cell] = A.Tbar[cell];
+        const int64_t rel = j - I.cg_off;
+        if (rel >= 0 && rel < RES_SUB) {
+            AdjResid z = {0ull, 0ull};
+            A.res[((int64_t)s.inst * RES_SLOTS + 0) * RES_SUB + rel] = z;
+        }
+        if (rel == 0) A.conv[s.inst] = 0;
+    }
+}
+
+// bbar = w sigma/(1+lambda) mu + rbar/(1+lambda) of slot jj in cell c
+__device__ inline double bbar_of(const Dev& D, const Consts& K, const Adj& A, const double* mu, int64_t jj,
+                                 int c)
+{
+    const double lam = D.sv[jj];
+    return temp_weight(D, K, c) * D.sig[jj] / (1.0 + lam) * mu[c] + A.rbar[jj] / (1.0 + lam);
+}
+
+// Face q (XLO, XHI, YLO, YHI) of slot j: neighbour slot and cell, face slot, area.
+struct FaceRef {
+    bool inside;
+    int64_t nbj, fslot;
+    int nbcell;
+    double S;
+};
+
+__device__ inline FaceRef face_ref(const Inst& I, int64_t j, int lcell, int g, int q)
+{
+    FaceRef f;
+    const int nx = I.nx, ix = lcell % nx, iy = lcell / nx, Gp = I.Gp;
+    const bool lo = (q & 1) == 0;
+    if ((q >> 1) == 0) {
+        f.inside = lo ? ix > 0 : ix < nx - 1;
+        f.nbj = j + (lo ? -Gp : Gp);
+        f.nbcell = I.cell_off + lcell + (lo ? -1 : 1);
+        f.fslot = I.fx_off + (((int64_t)iy * (nx + 1) + ix + (lo ? 0 : 1)) << I.lgGp) + g;
+        f.S = I.dy;
+    } else {
+        f.inside = lo ? iy > 0 : iy < I.ny - 1;
+        f.nbj = j + (lo ? -(int64_t)nx * Gp : (int64_t)nx * Gp);
+        f.nbcell = I.cell_off + lcell + (lo ? -nx : nx);
+        f.fslot = I.fy_off + (((int64_t)(iy + (lo ? 0 : 1)) * nx + ix) << I.lgGp) + g;
+        f.S = I.dx;
+    }
+    return f;
+}
+
+// One sweep of the transposed source iteration:
+//   mu^{k+1} = Tbar + sum_g phi_g' [ -w sigma/(1+lambda) mu^k + lambda/(1+lambda) rbar
+//                                    + (dt/V) sum_f S_f D_f (bbar_nb - bbar) ].
+// Sweep k first decides convergence from sweep k-1's residual (relative 1e-15,
+// 1e-13 after 60 sweeps), exactly as the source iteration of the forward step.
+__global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj A, int k, const double* mu_in,
+                                                           double* mu_out, int check_only)
+{
+    const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
+    const Slot s = decode_slot(D, K, j);
+    const Inst& I = D.inst[s.inst];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const bool first = j == I.cg_off;
+
+    bool run = A.conv[s.inst] == 0 && j < K.n_cg;
+    if (k > 0) {
+        const AdjResid rr = A.res[((int64_t)s.inst * RES_SLOTS + (k - 1) % RES_SLOTS) * RES_SUB + lane];
+        const double dm = wave_nmax(bitsd(rr.dmu)), mm = wave_nmax(bitsd(rr.mu));
+        const double tol = (k - 1) >= 60 ? 1e-13 : 1e-15;
+        if (run && dm <= tol * mm) {
+            run = false;
+            if (first) {
+                A.conv[s.inst] = k;
+                atomicAdd(A.status + ADJ_CONV, 1ull);
+            }
+        }
+    }
+    const int64_t rel = j - I.cg_off;
+    if (rel >= 0 && rel < RES_SUB && !check_only) {
+        AdjResid z = {0ull, 0ull};
+        A.res[((int64_t)s.inst * RES_SLOTS + (k + 1) % RES_SLOTS) * RES_SUB + rel] = z;
+    }
+    if (check_only) run = false;
+
+    const int g = s.g, Gp = I.Gp;
+    const bool work = run && s.cell_ok;
+    const int cell = I.cell_off + s.lcell;
+    double contrib = 0.0;
+    if (work && s.active) {
+        const double lam = D.sv[j];
+        const double mui = mu_in[cell];
+        const double fac = temp_weight(D, K, cell) * D.sig[j] / (1.0 + lam);
+        const double bb = fac * mui + A.rbar[j] / (1.0 + lam);
+        double lt = 0.0;
+        for (int q = 0; q < 2 * I.dim; ++q) {
+            const FaceRef f = face_ref(I, j, s.lcell, g, q);
+            const double Df = (q >> 1) == 0 ? D.Dx[f.fslot] : D.Dy[f.fslot];
+            if (f.inside) lt += f.S * Df * (bbar_of(D, K, A, mu_in, f.nbj, f.nbcell) - bb);
+            else if (I.bc[q] != BC_REFLECT) lt -= f.S * Df * bb;
+        }
+        const double phibar = -fac * mui + lam / (1.0 + lam) * A.rbar[j] + (K.dt / I.V) * lt;
+        contrib = A.dphi[j] * phibar;
+    }
+    for (int m = 1; m < Gp; m <<= 1) contrib += __shfl_xor(contrib, m, WAVE);
+
+    double dm = 0.0, mm = 0.0;
+    if (work && g == 0) {
+        const double mun = A.Tbar[cell] + contrib;
+        if (!isfinite(mun)) atomicOr(A.status + ADJ_ERR, 1ull);
+        mu_out[cell] = mun;
+        dm = fabs(mun - mu_in[cell]);
+        mm = fabs(mun);
+    }
+    dm = wave_nmax(dm);
+    mm = wave_nmax(mm);
+    __shared__ double wres[ADJ_THREADS / WAVE][2];
+    __shared__ int winst[ADJ_THREADS / WAVE];
+    __shared__ int wrun[ADJ_THREADS / WAVE];
+    if (lane == 0) {
+        wres[wid][0] = dm; wres[wid][1] = mm;
+        winst[wid] = s.inst;
+        wrun[wid] = work ? 1 : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = ADJ_THREADS / WAVE;
+        int w0 = 0;
+        while (w0 < nw) {
+            int w1 = w0, any = 0;
+            double a0 = 0.0, a1 = 0.0;
+            while (w1 < nw && winst[w1] == winst[w0]) {
+                if (wrun[w1]) {
+                    any = 1;
+                    a0 = nmax(a0, wres[w1][0]);
+                    a1 = nmax(a1, wres[w1][1]);
+                }
+                ++w1;
+            }
+            if (any) {
+                AdjResid* rr = A.res + ((int64_t)winst[w0] * RES_SLOTS + k % RES_SLOTS) * RES_SUB +
+                               (blockIdx.x & (RES_SUB - 1));
+                atomicMax(&rr->dmu, dbits(a0));
+                atomicMax(&rr->mu, dbits(a1));
+            }
+            w0 = w1;
+        }
+    }
+}
+
+// With the converged mu: cotangents of lambda (= s), sigma, Q, A rho^h and D_f;
+// dJ/dkappa += S_g dJ/dsigma; rbar^n = bbar + A ubar; Tbar^n = mu.
+__global__ __launch_bounds__(ADJ_THREADS) void k_adj_grad(Dev D, Consts K, Adj A, int r)
+{
+    const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
+    if (j >= K.n_cg) return;
+    const Slot s = decode_slot(D, K, j);
+    if (!s.active) {
+        A.rbar_next[j] = 0.0;
+        return;
+    }
+    const Inst& I = D.inst[s.inst];
+    const int g = s.g;
+    const int cell = I.cell_off + s.lcell;
+    const double* mu = (A.conv[s.inst] & 1) ? A.mu1 : A.mu0;
+    const double mui = mu[cell];
+    const double wi = temp_weight(D, K, cell);
+    const double lam = D.sv[j], sig = D.sig[j];
+    const double bb = wi * sig / (1.0 + lam) * mui + A.rbar[j] / (1.0 + lam);
+    const double phik = A.phi[j];
+    const double dtV = K.dt / I.V;
+    const double cq = K.c / (4.0 * K.eps);
+    const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
+    double lap = 0.0, accu = 0.0, sig_face = 0.0, s_planck = 0.0;
+    for (int q = 0; q < 2 * I.dim; ++q) {
+        const FaceRef f = face_ref(I, j, s.lcell, g, q);
+        const bool xax = (q >> 1) == 0, lo = (q & 1) == 0;
+        const double Df = xax ? D.Dx[f.fslot] : D.Dy[f.fslot];
+        // this cell is the high side of its low face and the low side of its high face
+        const double dDds = xax ? (lo ? A.Dhx[f.fslot] : A.Dlx[f.fslot])
+                                : (lo ? A.Dhy[f.fslot] : A.Dly[f.fslot]);
+        if (f.inside) {
+            const double bbn = bbar_of(D, K, A, mu, f.nbj, f.nbcell);
+            const double phin = A.phi[f.nbj];
+            lap += f.S * Df * (phin - phik);
+            accu += f.S * (bbn - bb);
+            sig_face += dtV * f.S * (bb - bbn) * (phin - phik) * dDds;
+        } else {
+            const int bc = I.bc[q];
+            if (bc == BC_REFLECT) continue;
+            const double ghost = bc == BC_PLANCK ? phib[q * MAX_G + g] : 0.0;
+            lap += f.S * Df * (ghost - phik);
+            accu -= f.S * bb;
+            sig_face += dtV * f.S * bb * (ghost - phik) * dDds;
+            if (bc == BC_PLANCK) s_planck += dtV * f.S * cq * bb * ghost * A.c4d[j];
+        }
+    }
+    const int64_t o = (int64_t)r * K.n_cg + j;
+    const double b = A.rQ[o] + dtV * lap;
+    const double em = (b - phik) / (1.0 + lam);
+    const double ubar = dtV * cq * accu;
+    const bool samp = A.rSamp[o] != 0;
+    const double Af = samp ? D.wc[j] : D.c4[j];
+    const double dA = samp ? A.wd[j] : A.c4d[j];
+    double sbar = -em / (1.0 + lam) * (wi * sig * mui + A.rbar[j]);
+    sbar += ubar * A.rRhoh[o] * dA;
+    sbar += s_planck;
+    const double sigbar = wi * em * mui;
+    const double ks = K.c * K.dt / (K.eps * K.eps);
+    A.grad[j] += D.simpson[I.edge_off + g] * (sigbar + ks * sbar + sig_face);
+    A.rbar_next[j] = bb + Af * ubar;
+    if (g == 0) A.Tbar[cell] = mui;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static inline unsigned ablocks(int64_t n) { return (unsigned)((n + ADJ_THREADS - 1) / ADJ_THREADS); }
+
+void launch_rec_store(const Dev& D, const Consts& K, const Adj& A, int r, hipStream_t st)
+{
+    k_rec_store<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, r);
+}
+
+void launch_adj_coef(const Dev& D, const Consts& K, const Adj& A, hipStream_t st)
+{
+    k_adj_coef<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A);
+}
+
+void launch_adj_face(const Dev& D, const Consts& K, const Adj& A, int inst, int axis, int64_t nslots,
+                     hipStream_t st)
+{
+    if (nslots > 0) k_adj_face<<<ablocks(nslots), ADJ_THREADS, 0, st>>>(D, K, A, inst, axis);
+}
+
+void launch_adj_prep(const Dev& D, const Consts& K, const Adj& A, int r, hipStream_t st)
+{
+    k_adj_prep<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, r);
+}
+
+void launch_adj_sweep(const Dev& D, const Consts& K, const Adj& A, int k, bool check_only, hipStream_t st)
+{
+    const double* in = (k & 1) ? A.mu1 : A.mu0;
+    double* out = (k & 1) ? A.mu0 : A.mu1;
+    k_adj_sweep<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, k, in, out, check_only ? 1 : 0);
+}
+
+void launch_adj_grad(const Dev& D, const Consts& K, const Adj& A, int r, hipStream_t st)
+{
+    k_adj_grad<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, r);
+}
+
+}  // namespace ugk

@@ -110,7 +110,8 @@ struct Pool {
 
 struct Dev {
     const Inst* inst;
-    const int64_t* inst_cg;     // [n_inst+1] padded starts (for binary search)
+    const int64_t* inst_cg;     // [n_inst+1] padded starts
+    const int32_t* wave_inst;   // [n_cg/64] instance of each aligned run of 64 slots
     const int32_t* cell_inst;   // [ncell]
     const double* nu;           // edges
     const double* simpson;      // [edge_off + g]

@@ -1,0 +1,53 @@
+// Device helpers shared by the step kernels (kernels.hip) and the adjoint
+// kernels (adjoint.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "common.hpp"
+
+namespace ugk {
+
+struct Slot {
+    int inst, lcell, g;
+    bool cell_ok, active;
+};
+
+// Slot j of a thread whose wavefront covers the 64 slots j & ~63 .. (j & ~63) + 63.
+// Instance blocks start on multiples of 64, so those slots belong to one
+// instance: it is looked up once per wavefront and its record is read with
+// scalar loads.
+__device__ inline Slot decode_slot(const Dev& D, const Consts& K, int64_t j)
+{
+    Slot s;
+    const bool in = j < K.n_cg;
+    const int w = __builtin_amdgcn_readfirstlane((int)(j >> 6));
+    s.inst = ((int64_t)w << 6) < K.n_cg ? D.wave_inst[w] : K.n_inst - 1;
+    const Inst& I = D.inst[s.inst];
+    const int64_t local = j - I.cg_off;
+    s.lcell = (int)(local >> I.lgGp);
+    s.g = (int)(local & (I.Gp - 1));
+    s.cell_ok = in && local >= 0 && s.lcell < I.ncell;
+    s.active = s.cell_ok && s.g < I.G;
+    return s;
+}
+
+__device__ inline unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
+__device__ inline double bitsd(unsigned long long v) { return __longlong_as_double((long long)v); }
+
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, WAVE));
+    return v;
+}
+
+// NaN-propagating max (fmax drops NaN)
+__device__ inline double nmax(double a, double b) { return (a != a || a > b) ? a : b; }
+
+__device__ inline double wave_nmax(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = nmax(v, __shfl_xor(v, m, WAVE));
+    return v;
+}
+
+}  // namespace ugk

@@ -176,6 +176,47 @@ __host__ __device__ inline double coef_c2_over_dt(double s)
     return (2.0 * coef_c4(s) - 1.0 - exp(-s)) / s;
 }
 
+// Derivatives in s (for the adjoint of the macroscopic solve).  With
+// W/s -> 1/2 as s -> 0 taken from W's series below s = 1:
+//   C4' = -W/s,   W' = e^{-s} - W/s,   (C2/dt)' = (e^{-s} - 2 W/s - C2/dt) / s,
+// the last replaced below s = 2 by its series
+//   sum_{n>=2} (-1)^{n+1} (n-1)^2 s^{n-2} / (n+1)!   (it cancels there).
+__host__ __device__ inline double coef_w_over_s(double s)
+{
+    if (s < 1.0) {
+        double p = 1.0, inv_fact = 0.5, sum = 0.5;      // n = 1 term: 1/2
+        for (int n = 2; n < 60; ++n) {
+            p *= s;                                     // s^{n-1}
+            inv_fact /= (double)(n + 1);                // 1/(n+1)!
+            const double t = (double)n * p * inv_fact;
+            sum += (n & 1) ? t : -t;
+            if (t < 1e-18 * fabs(sum)) break;
+        }
+        return sum;
+    }
+    return coef_w(s) / s;
+}
+
+__host__ __device__ inline double coef_c4_ds(double s) { return -coef_w_over_s(s); }
+
+__host__ __device__ inline double coef_w_ds(double s) { return exp(-s) - coef_w_over_s(s); }
+
+__host__ __device__ inline double coef_c2_over_dt_ds(double s)
+{
+    if (s < 2.0) {
+        double p = 1.0, inv_fact = 1.0 / 6.0, sum = -1.0 / 6.0;   // n = 2 term
+        for (int n = 3; n < 80; ++n) {
+            p *= s;                                     // s^{n-2}
+            inv_fact /= (double)(n + 1);
+            const double t = (double)((n - 1) * (n - 1)) * p * inv_fact;
+            sum += (n & 1) ? t : -t;
+            if (t < 1e-18 * fabs(sum)) break;
+        }
+        return sum;
+    }
+    return (exp(-s) - 2.0 * coef_w_over_s(s) - coef_c2_over_dt(s)) / s;
+}
+
 // ---------------------------------------------------------------------------
 // Linear-frequency sampling.  beta = (B(nh) - B(nl)) / B(nmid) limited to [-2, 2]
 // (keeps the linear pdf non-negative on the group); evaluated as ratios of

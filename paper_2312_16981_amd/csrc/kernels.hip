@@ -26,38 +26,45 @@
 #include "common.hpp"
 #include "device_math.hpp"
 #include "kernels.hpp"
+#include "device_common.hpp"
 
 namespace ugk {
 
 __constant__ HeadSeries c_head;
 
-// ---------------------------------------------------------------------------
-// helpers
-
-struct Slot {
-    int inst, lcell, g;
-    bool cell_ok, active;
+// What a particle flight reads of its instance, copied into registers once
+// (scalar registers when the whole launch serves one instance).
+struct Geo {
+    double x0, y0, dx, dy;
+    int64_t cg_off, fx_off, fy_off;
+    uint64_t seed;
+    int nx, ny, lgGp, cell_off, edge_off;
+    int reflect;           // bit q: side q (XLO, XHI, YLO, YHI) is reflective
 };
 
-__device__ inline Slot decode_slot(const Dev& D, const Consts& K, int64_t j)
+__device__ inline Geo geo_of(const Inst& I)
 {
-    Slot s;
-    const bool in = j < K.n_cg;
-    s.inst = in ? find_inst(D.inst_cg, K.n_inst, j) : K.n_inst - 1;
-    const Inst& I = D.inst[s.inst];
-    const int64_t local = j - I.cg_off;
-    s.lcell = (int)(local >> I.lgGp);
-    s.g = (int)(local & (I.Gp - 1));
-    s.cell_ok = in && local >= 0 && s.lcell < I.ncell;
-    s.active = s.cell_ok && s.g < I.G;
-    return s;
+    Geo o;
+    o.x0 = I.x0; o.y0 = I.y0; o.dx = I.dx; o.dy = I.dy;
+    o.cg_off = I.cg_off; o.fx_off = I.fx_off; o.fy_off = I.fy_off;
+    o.seed = I.seed;
+    o.nx = I.nx; o.ny = I.ny; o.lgGp = I.lgGp; o.cell_off = I.cell_off; o.edge_off = I.edge_off;
+    o.reflect = 0;
+    for (int q = 0; q < 4; ++q) o.reflect |= (I.bc[q] == BC_REFLECT ? 1 : 0) << q;
+    return o;
 }
 
-__device__ inline double particle_sigma(const Dev& D, const Consts& K, const Inst& I, int64_t cg,
-                                        double nu, int g)
+// sigma(nu, cell) = kappa[cell][g] * f(nu): f = nu^-3 (the paper's opacities),
+// nu^-p, or the Simpson group factor S_g with the group-opacity flag.  f is
+// fixed for a particle, so the push computes it once.
+enum { SIG_NU3 = 0, SIG_POW = 1, SIG_GROUP = 2 };
+
+template <int SM>
+__device__ inline double nu_factor(const Dev& D, const Consts& K, const Geo& I, double nu, int g)
 {
-    if (K.flags & 1u) return D.kappa[cg] * D.simpson[I.edge_off + g];
-    return D.kappa[cg] * nu_pow(nu, K.nu_power);
+    if (SM == SIG_GROUP) return D.simpson[I.edge_off + g];
+    if (SM == SIG_NU3) return 1.0 / (nu * nu * nu);
+    return pow(nu, -K.nu_power);
 }
 
 __device__ inline double phi_group_direct(double T, double nl, double nh, double a, double c)
@@ -72,26 +79,6 @@ __device__ inline double phi_group_direct(double T, double nl, double nh, double
 __device__ inline bool step_committed(const Dev& D, const Consts& K)
 {
     return D.counters[CNT_ERR] == 0 && D.counters[CNT_CONV] == (unsigned long long)K.n_inst;
-}
-
-__device__ inline unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
-__device__ inline double bitsd(unsigned long long v) { return __longlong_as_double((long long)v); }
-
-__device__ inline double wave_max(double v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, WAVE));
-    return v;
-}
-
-// NaN-propagating max (fmax drops NaN)
-__device__ inline double nmax(double a, double b) { return (a != a || a > b) ? a : b; }
-
-__device__ inline double wave_nmax(double v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = nmax(v, __shfl_xor(v, m, WAVE));
-    return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -309,7 +296,7 @@ __global__ void k_sample(Dev D, Consts K, Pool P, uint32_t step)
         if (D.boff[mid] <= j) lo = mid; else hi = mid;
     }
     const int64_t cg = lo;
-    const int inst = find_inst(D.inst_cg, K.n_inst, cg);
+    const int inst = D.wave_inst[cg >> 6];
     const Inst& I = D.inst[inst];
     const int64_t local = cg - I.cg_off;
     const int lcell = (int)(local >> I.lgGp), g = (int)(local & (I.Gp - 1));
@@ -412,7 +399,7 @@ struct Flight {
     bool coll;
 };
 
-__device__ inline void draw_flight(const Consts& K, const Inst& I, uint64_t id, uint32_t step, Flight& f)
+__device__ inline void draw_flight(const Consts& K, const Geo& I, uint64_t id, uint32_t step, Flight& f)
 {
     const double u = keyed_uniform(I.seed, id, step, PURPOSE_FLIGHT, f.d++);
     const double tau = K.e2c / f.sig;
@@ -423,8 +410,8 @@ __device__ inline void draw_flight(const Consts& K, const Inst& I, uint64_t id, 
 
 // Flight of one particle through the step.  Returns 0 survives, 1 collided, 2 left the domain.
 template <int DIM>
-__device__ inline int fly(const Dev& D, const Consts& K, const Inst& I, TallyTable& T, uint64_t id,
-                          uint32_t step, double nu, int g, double w, Flight& f)
+__device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTable& T, uint64_t id,
+                          uint32_t step, double nfac, int g, double w, Flight& f)
 {
     for (;;) {
         const double vx = K.cv * f.ox;
@@ -488,7 +475,7 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Inst& I, TallyTab
             index = (uint32_t)(((I.fy_off + (face << I.lgGp) + g) << 1) + (pos ? 0 : 1));
         }
         if (boundary) {
-            if (I.bc[side] == BC_REFLECT) {
+            if ((I.reflect >> side) & 1) {
                 if (xaxis) f.ox = -f.ox; else f.oy = -f.oy;
                 f.t_rem = f.t_rem - tf;
                 continue;
@@ -498,7 +485,7 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Inst& I, TallyTab
         }
         lds_tally(T, D, type, index, w);
         if (xaxis) f.ix += pos ? 1 : -1; else f.iy += pos ? 1 : -1;
-        f.sig = particle_sigma(D, K, I, I.cg_off + ((int64_t)(f.iy * I.nx + f.ix) << I.lgGp) + g, nu, g);
+        f.sig = D.kappa[I.cg_off + ((int64_t)(f.iy * I.nx + f.ix) << I.lgGp) + g] * nfac;
         draw_flight(K, I, id, step, f);
     }
 }
@@ -510,7 +497,7 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Inst& I, TallyTab
 #ifndef UGK_PUSH_ATTR
 #define UGK_PUSH_ATTR
 #endif
-template <int DIM, bool SINGLE>
+template <int DIM, bool SINGLE, int SM>
 __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool In, Pool Out,
                                                                      uint32_t step)
 {
@@ -522,6 +509,8 @@ __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Cons
     const int64_t chunk = PUSH_THREADS * PUSH_PPT;
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     unsigned long long nsurv = 0;
+    Geo geo0{};
+    if (SINGLE) geo0 = geo_of(D.inst[0]);
     for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < n_total; c0 += (int64_t)gridDim.x * chunk) {
         for (int h = threadIdx.x; h < HT_SIZE; h += PUSH_THREADS) {
             T.key[h] = HT_EMPTY;
@@ -544,8 +533,7 @@ __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Cons
                 Out.cell[i] = DEAD;
                 continue;
             }
-            const int inst = SINGLE ? 0 : D.cell_inst[cell];
-            const Inst& I = D.inst[inst];
+            const Geo I = SINGLE ? geo0 : geo_of(D.inst[D.cell_inst[cell]]);
             Flight f;
             f.x = In.x[i];
             f.ox = (word & FLIP_X) ? -In.ox[i] : In.ox[i];
@@ -563,11 +551,12 @@ __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Cons
             f.iy = DIM == 1 ? 0 : lcell / I.nx;
             f.t = 0.0;
             f.d = 0;
-            f.sig = particle_sigma(D, K, I, I.cg_off + ((int64_t)lcell << I.lgGp) + g, nu, g);
+            const double nfac = nu_factor<SM>(D, K, I, nu, g);
+            f.sig = D.kappa[I.cg_off + ((int64_t)lcell << I.lgGp) + g] * nfac;
             if (i < n_slots) draw_flight(K, I, id, step, f);    // old particle: t_f = min(-tau ln eta, dt)
             else { f.coll = false; f.t_rem = K.dt; }            // new collisionless particle: t_f = dt
             const double ox0 = f.ox, oy0 = f.oy;
-            const int out = fly<DIM>(D, K, I, T, id, step, nu, g, w, f);
+            const int out = fly<DIM>(D, K, I, T, id, step, nfac, g, w, f);
             if (out != 2) {
                 const uint32_t cg = (uint32_t)(I.cg_off + ((int64_t)(f.iy * I.nx + f.ix) << I.lgGp) + g);
                 lds_tally(T, D, out == 0 ? TAL_SURV : TAL_DEP, cg, w);
@@ -1202,44 +1191,69 @@ void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, uint32
     else k_sample<2><<<512, 256, 0, st>>>(D, K, P, step);
 }
 
-static int g_push_grid[2][2] = {{0, 0}, {0, 0}};
+static int g_push_grid[2][2][3] = {};
 
-int push_grid(int dim, bool single)
+template <int DIM, bool SINGLE, int SM>
+static int push_blocks_per_cu()
 {
-    int& gsz = g_push_grid[dim - 1][single ? 1 : 0];
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_push<DIM, SINGLE, SM>, PUSH_THREADS, 0) != hipSuccess)
+        per = 0;
+    return per;
+}
+
+static int sig_mode(const Consts& K)
+{
+    return (K.flags & 1u) ? SIG_GROUP : (K.nu_power == 3.0 ? SIG_NU3 : SIG_POW);
+}
+
+int push_grid(int dim, bool single, int sm)
+{
+    int& gsz = g_push_grid[dim - 1][single ? 1 : 0][sm];
     if (gsz == 0) {
         int dev = 0, ncu = 0, per = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        hipError_t e;
-        if (dim == 1) e = single ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_push<1, true>, PUSH_THREADS, 0)
-                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_push<1, false>, PUSH_THREADS, 0);
-        else e = single ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_push<2, true>, PUSH_THREADS, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_push<2, false>, PUSH_THREADS, 0);
-        if (e != hipSuccess || per < 1) per = 2;
+#define UGK_PER(D_, S_, M_) if (dim == D_ && single == S_ && sm == M_) per = push_blocks_per_cu<D_, S_, M_>();
+        UGK_PER(1, true, 0) UGK_PER(1, true, 1) UGK_PER(1, true, 2)
+        UGK_PER(1, false, 0) UGK_PER(1, false, 1) UGK_PER(1, false, 2)
+        UGK_PER(2, true, 0) UGK_PER(2, true, 1) UGK_PER(2, true, 2)
+        UGK_PER(2, false, 0) UGK_PER(2, false, 1) UGK_PER(2, false, 2)
+#undef UGK_PER
+        if (per < 1) per = 2;
         if (ncu < 1) ncu = 256;
         gsz = ncu * per;
     }
     return gsz;
 }
 
+template <int DIM, bool SINGLE>
+static void push_mode(int sm, int nb, const Dev& D, const Consts& K, const Pool& In, const Pool& Out,
+                      uint32_t step, hipStream_t st)
+{
+    if (sm == SIG_NU3) k_push<DIM, SINGLE, SIG_NU3><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
+    else if (sm == SIG_POW) k_push<DIM, SINGLE, SIG_POW><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
+    else k_push<DIM, SINGLE, SIG_GROUP><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
+}
+
 void launch_push(int dim, const Dev& D, const Consts& K, const Pool& In, const Pool& Out, uint32_t step,
                  hipStream_t st)
 {
     const bool single = K.n_inst == 1;
-    const int nb = push_grid(dim, single);
+    const int sm = sig_mode(K);
+    const int nb = push_grid(dim, single, sm);
     if (dim == 1) {
-        if (single) k_push<1, true><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
-        else k_push<1, false><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
+        if (single) push_mode<1, true>(sm, nb, D, K, In, Out, step, st);
+        else push_mode<1, false>(sm, nb, D, K, In, Out, step, st);
     } else {
-        if (single) k_push<2, true><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
-        else k_push<2, false><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
+        if (single) push_mode<2, true>(sm, nb, D, K, In, Out, step, st);
+        else push_mode<2, false>(sm, nb, D, K, In, Out, step, st);
     }
 }
 
 void launch_pool_count(int dim, const Dev& D, const Consts& K, hipStream_t st)
 {
-    k_pool_count<<<1, 256, 0, st>>>(D, push_grid(dim, K.n_inst == 1));
+    k_pool_count<<<1, 256, 0, st>>>(D, push_grid(dim, K.n_inst == 1, sig_mode(K)));
 }
 
 void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& In, const Pool& Out, hipStream_t st)

@@ -23,7 +23,7 @@ void launch_count(const Dev& D, const Consts& K, hipStream_t st);
 int64_t scan_partials_size(int64_t n);
 void launch_scan(const int32_t* in, int64_t n, int64_t* part, int64_t* out, int64_t* total, hipStream_t st);
 void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, uint32_t step, hipStream_t st);
-int push_grid(int dim, bool single);
+int push_grid(int dim, bool single, int sig_mode);
 void launch_push(int dim, const Dev& D, const Consts& K, const Pool& A, const Pool& B, uint32_t step,
                  hipStream_t st);
 void launch_pool_count(int dim, const Dev& D, const Consts& K, hipStream_t st);

@@ -14,6 +14,7 @@
 #include "../../include/ugkwp.h"
 #include "common.hpp"
 #include "device_math.hpp"
+#include "adjoint.hpp"
 #include "kernels.hpp"
 
 using namespace ugk;
@@ -80,7 +81,9 @@ bool g_head_ready = false;
 void ensure_head_series()
 {
     if (!g_head_ready) {
-        HIPCHK(set_head_series(make_head_series()));
+        const HeadSeries hs = make_head_series();
+        HIPCHK(set_head_series(hs));
+        HIPCHK(set_head_series_adj(hs));
         g_head_ready = true;
     }
 }
@@ -166,10 +169,29 @@ struct ugkwp_ctx {
     int sort_interval = 8;
     ugkwp_diag diag{};
 
+    // adjoint: record of the forward run and reverse-sweep buffers
+    std::vector<void*> rec_owned;
+    Adj A{};
+    int rec_cap = 0, nrec = 0;
+    std::vector<int> rec_sweeps;      // forward source-iteration sweeps per recorded step
+    unsigned long long* h_adj = nullptr;   // pinned copy of A.status
+
     ~ugkwp_ctx() { release(); }
+
+    void free_record()
+    {
+        for (void* p : rec_owned) (void)hipFree(p);
+        rec_owned.clear();
+        A = Adj{};
+        rec_cap = nrec = 0;
+        rec_sweeps.clear();
+    }
 
     void release()
     {
+        free_record();
+        if (h_adj) (void)hipHostFree(h_adj);
+        h_adj = nullptr;
         for (void* p : owned) (void)hipFree(p);
         owned.clear();
         if (h_status) (void)hipHostFree(h_status);
@@ -184,6 +206,7 @@ struct ugkwp_ctx {
 
     void free_device()
     {
+        free_record();
         for (void* p : owned) (void)hipFree(p);
         owned.clear();
         D = Dev{};
@@ -288,6 +311,11 @@ struct ugkwp_ctx {
             }
             simpson.push_back(0.0);
         }
+        std::vector<int32_t> wave_inst((size_t)(n_cg / WAVE));
+        for (int k = 0, w = 0; w < (int)wave_inst.size(); ++w) {
+            while (k + 1 < n_inst && inst_cg[k + 1] <= (int64_t)w * WAVE) ++k;
+            wave_inst[w] = k;
+        }
         std::vector<int32_t> cell_inst(ncell);
         for (int k = 0; k < n_inst; ++k)
             for (int c = 0; c < inst[k].ncell; ++c) cell_inst[inst[k].cell_off + c] = k;
@@ -295,12 +323,14 @@ struct ugkwp_ctx {
         Inst* d_inst = dalloc<Inst>(owned, n_inst);
         int64_t* d_inst_cg = dalloc<int64_t>(owned, n_inst + 1);
         int32_t* d_cell_inst = dalloc<int32_t>(owned, ncell);
+        int32_t* d_wave_inst = dalloc<int32_t>(owned, wave_inst.size());
         double* d_nu = dalloc<double>(owned, edges.size());
         double* d_simp = dalloc<double>(owned, simpson.size());
         d_phib = dalloc<double>(owned, (size_t)n_inst * 4 * MAX_G);
         HIPCHK(hipMemcpy(d_inst, inst.data(), sizeof(Inst) * n_inst, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(d_inst_cg, inst_cg.data(), sizeof(int64_t) * (n_inst + 1), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(d_cell_inst, cell_inst.data(), sizeof(int32_t) * ncell, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_wave_inst, wave_inst.data(), sizeof(int32_t) * wave_inst.size(), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(d_nu, edges.data(), sizeof(double) * edges.size(), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(d_simp, simpson.data(), sizeof(double) * simpson.size(), hipMemcpyHostToDevice));
 
@@ -308,6 +338,7 @@ struct ugkwp_ctx {
         d = Dev{};
         d.inst = d_inst;
         d.inst_cg = d_inst_cg;
+        d.wave_inst = d_wave_inst;
         d.cell_inst = d_cell_inst;
         d.nu = d_nu;
         d.simpson = d_simp;
@@ -407,6 +438,7 @@ struct ugkwp_ctx {
 
     void set_opacity(const std::vector<const double*>& kap)
     {
+        if (rec_cap > 0) fail(UGKWP_EINVAL, "the opacity cannot change while a record is kept (ugkwp_record(ctx, 0) first)");
         std::vector<double> h((size_t)K.n_cg, 0.0);
         for (int k = 0; k < n_inst; ++k) {
             const Inst& I = inst[k];
@@ -459,6 +491,8 @@ struct ugkwp_ctx {
         step_idx = 0;
         cur_mv = cur_st = 0;
         have_material = true;
+        nrec = 0;
+        rec_sweeps.clear();
     }
 
     Pool view(int m, int t) const
@@ -498,6 +532,8 @@ struct ugkwp_ctx {
 
     int step_once()
     {
+        if (rec_cap > 0 && nrec >= rec_cap)
+            fail(UGKWP_EINVAL, "the record holds its maximum of %d steps", rec_cap);
         // sort periodically, and whenever holes have filled half the pool
         const bool do_sort = sort_interval <= 1 ||
                              (step_idx % (uint32_t)sort_interval) == (uint32_t)(sort_interval - 1) ||
@@ -589,7 +625,127 @@ struct ugkwp_ctx {
         }
         n_alive = dg.n_alive_out;
         step_idx++;
+        if (rec_cap > 0) {
+            launch_rec_store(D, K, A, nrec, st);
+            rec_sweeps.push_back(smax);
+            nrec++;
+        }
         return UGKWP_OK;
+    }
+
+    // ---------------------------------------------------------------- adjoint
+    template <class T>
+    T* ralloc(size_t n)
+    {
+        void* p = nullptr;
+        if (n == 0) n = 1;
+        if (hipMalloc(&p, n * sizeof(T)) != hipSuccess)
+            fail(UGKWP_ENOMEM, "hipMalloc of %zu bytes for the record failed", n * sizeof(T));
+        rec_owned.push_back(p);
+        return (T*)p;
+    }
+
+    void record_start(int max_steps)
+    {
+        free_record();
+        if (max_steps <= 0) return;
+        const size_t ncg = (size_t)K.n_cg, nc = (size_t)ncell;
+        const size_t nfx = (size_t)std::max<int64_t>(n_fx, 1), nfy = (size_t)std::max<int64_t>(n_fy, 1);
+        A.rQ = ralloc<double>(ncg * max_steps);
+        A.rRhoh = ralloc<double>(ncg * max_steps);
+        A.rSamp = ralloc<uint8_t>(ncg * max_steps);
+        A.rT = ralloc<double>(nc * max_steps);
+        A.phi = ralloc<double>(ncg);
+        A.dphi = ralloc<double>(ncg);
+        A.rbar = ralloc<double>(ncg);
+        A.rbar_next = ralloc<double>(ncg);
+        A.mu0 = ralloc<double>(nc);
+        A.mu1 = ralloc<double>(nc);
+        A.Tbar = ralloc<double>(nc);
+        A.grad = ralloc<double>(ncg);
+        A.c4d = ralloc<double>(ncg);
+        A.wd = ralloc<double>(ncg);
+        A.Dlx = ralloc<double>(nfx);
+        A.Dhx = ralloc<double>(nfx);
+        A.Dly = ralloc<double>(nfy);
+        A.Dhy = ralloc<double>(nfy);
+        A.res = ralloc<AdjResid>((size_t)n_inst * RES_SLOTS * RES_SUB);
+        A.conv = ralloc<int>((size_t)n_inst);
+        A.status = ralloc<unsigned long long>(ADJ_N_STATUS);
+        if (!h_adj) HIPCHK(hipHostMalloc((void**)&h_adj, sizeof(unsigned long long) * ADJ_N_STATUS, hipHostMallocDefault));
+        rec_cap = max_steps;
+        nrec = 0;
+        rec_sweeps.clear();
+    }
+
+    void adjoint(const double* dJdT, double* grad, bool dev, ugkwp_adjoint_stats* stats)
+    {
+        if (rec_cap == 0 || nrec == 0) fail(UGKWP_EINVAL, "no recorded steps (ugkwp_record before ugkwp_step)");
+        if (!dJdT || !grad) fail(UGKWP_EINVAL, "null array");
+        if (!dev)
+            for (int c = 0; c < ncell; ++c)
+                if (!std::isfinite(dJdT[c])) fail(UGKWP_EINVAL, "dJdT must be finite");
+        HIPCHK(hipEventRecord(ev[0], st));
+        HIPCHK(hipMemcpyAsync(A.Tbar, dJdT, sizeof(double) * ncell,
+                              dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemsetAsync(A.rbar, 0, sizeof(double) * K.n_cg, st));
+        HIPCHK(hipMemsetAsync(A.grad, 0, sizeof(double) * K.n_cg, st));
+        HIPCHK(hipMemsetAsync(A.conv, 0, sizeof(int) * n_inst, st));
+        launch_adj_coef(D, K, A, st);
+        for (int q = 0; q < n_inst; ++q) {
+            const Inst& I = inst[q];
+            launch_adj_face(D, K, A, q, 0, (int64_t)(I.nx + 1) * I.ny * I.Gp, st);
+            if (dim == 2) launch_adj_face(D, K, A, q, 1, (int64_t)I.nx * (I.ny + 1) * I.Gp, st);
+        }
+        const int kmax = 1000;
+        int sweeps_sum = 0, sweeps_max = 0;
+        for (int r = nrec - 1; r >= 0; --r) {
+            HIPCHK(hipMemsetAsync(A.status, 0, sizeof(unsigned long long) * ADJ_N_STATUS, st));
+            launch_adj_prep(D, K, A, r, st);
+            int k = 0;
+            const int first = std::min(kmax + 1, rec_sweeps[r] + 3);
+            for (; k < first; ++k) launch_adj_sweep(D, K, A, k, k == kmax, st);
+            for (;;) {
+                HIPCHK(hipMemcpyAsync(h_adj, A.status, sizeof(unsigned long long) * ADJ_N_STATUS,
+                                      hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                if (h_adj[ADJ_ERR]) fail(UGKWP_ENONFINITE, "adjoint of step %d produced a non-finite value", r);
+                if (h_adj[ADJ_CONV] == (unsigned long long)n_inst) break;
+                if (k > kmax) fail(UGKWP_ENOCONV, "transposed source iteration of step %d did not converge", r);
+                const int kend = std::min(k + 4, kmax + 1);
+                for (; k < kend; ++k) launch_adj_sweep(D, K, A, k, k == kmax, st);
+            }
+            launch_adj_grad(D, K, A, r, st);
+            std::swap(A.rbar, A.rbar_next);
+            sweeps_sum += k;
+            sweeps_max = std::max(sweeps_max, k);
+        }
+        const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        int64_t out = 0;
+        for (int q = 0; q < n_inst; ++q) {
+            const Inst& I = inst[q];
+            copy_rows_rt(grad + out, sizeof(double) * I.G, A.grad + I.cg_off, sizeof(double) * I.Gp,
+                         sizeof(double) * I.G, I.ncell, kind);
+            out += (int64_t)I.ncell * I.G;
+        }
+        HIPCHK(hipEventRecord(ev[1], st));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipGetLastError());
+        if (stats) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            stats->steps = nrec;
+            stats->sweeps_launched = sweeps_sum;
+            stats->sweeps_max = sweeps_max;
+            stats->ms = ms;
+        }
+    }
+
+    void copy_rows_rt(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width, size_t rows,
+                      hipMemcpyKind kind)
+    {
+        if (rows == 0 || width == 0) return;
+        HIPCHK(hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, kind, st));
     }
 };
 
@@ -769,6 +925,28 @@ int ugkwp_step(ugkwp_ctx* ctx, int nsteps)
         require_ready(ctx);
         if (nsteps < 0) fail(UGKWP_EINVAL, "negative step count");
         for (int n = 0; n < nsteps; ++n) ctx->step_once();
+    });
+}
+
+int ugkwp_record(ugkwp_ctx* ctx, int max_steps)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        if (max_steps < 0) fail(UGKWP_EINVAL, "negative record size");
+        if (max_steps > 0) require_ready(ctx);
+        ctx->record_start(max_steps);
+    });
+}
+
+int ugkwp_recorded_steps(const ugkwp_ctx* ctx) { return ctx ? ctx->nrec : 0; }
+
+int ugkwp_adjoint(ugkwp_ctx* ctx, const double* dJdT, double* grad_kappa, int ptrs_are_device,
+                  ugkwp_adjoint_stats* stats)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        require_ready(ctx);
+        ctx->adjoint(dJdT, grad_kappa, ptrs_are_device != 0, stats);
     });
 }
 

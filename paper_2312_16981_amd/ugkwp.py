@@ -25,7 +25,8 @@ EXPORTED = [
     "ugkwp_set_material", "ugkwp_init_batch", "ugkwp_step", "ugkwp_num_instances",
     "ugkwp_get_fields", "ugkwp_get_tallies", "ugkwp_get_diag", "ugkwp_get_counters",
     "ugkwp_pool_size", "ugkwp_get_pool", "ugkwp_set_pool", "ugkwp_eval_phi", "ugkwp_eval_coef",
-    "ugkwp_eval_uniform", "ugkwp_eval_sample_nu",
+    "ugkwp_eval_uniform", "ugkwp_eval_sample_nu", "ugkwp_record", "ugkwp_recorded_steps",
+    "ugkwp_adjoint",
 ]
 
 _d = C.c_double
@@ -50,6 +51,13 @@ class Instance(C.Structure):
                 ("bc", C.c_int * 4), ("bcT", _d * 4), ("G", C.c_int), ("nu_edges", _pd),
                 ("seed", C.c_uint64), ("w_ref", _d), ("kappa", _pd), ("cv", _pd), ("T0", _pd),
                 ("Tr0", _pd), ("pinned", _pu8)]
+
+
+class AdjointStats(C.Structure):
+    _fields_ = [("steps", C.c_int), ("sweeps_launched", C.c_int), ("sweeps_max", C.c_int), ("ms", _d)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Diag(C.Structure):
@@ -97,6 +105,9 @@ def load():
     L.ugkwp_get_pool.argtypes = [vp, _pd, _pd, _pd, _pd, _pd, _pd, _pu64, _pi32, _pi32]
     L.ugkwp_set_pool.argtypes = [vp, C.c_int64, _pd, _pd, _pd, _pd, _pd, _pd, _pu64, _pi32, _pi32,
                                  C.c_uint64, _pd]
+    L.ugkwp_record.argtypes = [vp, C.c_int]
+    L.ugkwp_recorded_steps.argtypes = [vp]
+    L.ugkwp_adjoint.argtypes = [vp, _pd, _pd, C.c_int, C.POINTER(AdjointStats)]
     L.ugkwp_eval_phi.argtypes = [C.c_int, _pd, C.c_int, _pd, _d, _d, _pd]
     L.ugkwp_eval_coef.argtypes = [C.c_int, _pd, _pd, _pd, _pd]
     L.ugkwp_eval_uniform.argtypes = [C.c_int, C.c_uint64, _pu64, C.c_uint32, C.c_uint32, _pu32, _pd]
@@ -180,6 +191,34 @@ class Context:
         if check:
             self._chk(rc, "step")
         return rc
+
+    # ---- adjoint of the frozen-tally macroscopic map ----
+    def record(self, max_steps):
+        """Keep a record of up to max_steps following steps (0 stops and frees it)."""
+        self._chk(load().ugkwp_record(self.h, int(max_steps)), "record")
+
+    def recorded_steps(self):
+        return int(load().ugkwp_recorded_steps(self.h))
+
+    def adjoint(self, dJdT):
+        """dJ/dkappa [all cells][G] (instances concatenated) of J = sum dJdT * T(final)."""
+        d = _f64(dJdT).reshape(-1)
+        if d.size != sum(n for n, *_ in self.layout):
+            raise ValueError("dJdT needs one value per cell of every instance")
+        total = sum(n * g for n, g, *_ in self.layout)
+        out = np.zeros(total)
+        st = AdjointStats()
+        self._chk(load().ugkwp_adjoint(self.h, _p(d), _p(out), 0, C.byref(st)), "adjoint")
+        self.last_adjoint = st.as_dict()
+        return out
+
+    def adjoint_device(self, dJdT_ptr, grad_ptr):
+        """Device-pointer variant (e.g. torch tensors' data_ptr()), on the context stream."""
+        st = AdjointStats()
+        self._chk(load().ugkwp_adjoint(self.h, C.cast(dJdT_ptr, _pd), C.cast(grad_ptr, _pd), 1,
+                                       C.byref(st)), "adjoint")
+        self.last_adjoint = st.as_dict()
+        return self.last_adjoint
 
     # ---- results ----
     def get_fields(self, inst=0):
