@@ -82,6 +82,14 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
                            "python paper_2312_16981_amd/build.py")
+    # PyTorch-ROCm ships its own HIP runtime under the same soname.  Loading it
+    # first makes the library bind to that one copy, so that torch streams and
+    # device pointers can be handed to the library; a second copy loaded after
+    # the system runtime leaves torch without a device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp = C.c_void_p
     L.ugkwp_create.argtypes = [C.POINTER(vp), C.POINTER(Params), vp]
