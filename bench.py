@@ -9,6 +9,9 @@ Workloads (--workload):
   batch    512 independent slabs of 64..4096 cells and 16/32/64 groups in one
            context (one launch per kernel per step); --per-instance steps the
            same instances in 512 separate contexts instead
+  adjoint  2-D 128 x 128 cells x 16 groups, log-normal opacity, dt = 1e-3:
+           --steps recorded steps from t = 0 (default 100), then the adjoint
+           of the frozen-tally macroscopic map (dJ/dkappa of the material energy)
 
 Each run advances from t = 0 through a fixed spin-up (set-up, untimed) that
 fills the particle pool, then `--warmup` untimed steps, then `--steps` timed
@@ -34,7 +37,8 @@ HBM_PEAK_GBS = 8000.0
 PUSH_BYTES_READ = 48       # x, mu, nu, w, id (8 B each) + cell word, group (4 B each)
 PUSH_BYTES_WRITE = 12      # new position and cell word of a survivor (updated in place)
 PUSH_BYTES_DEAD = 4        # empty-slot mark of a particle absorbed or gone
-SPINUP = {"slab": 500, "lattice": 300, "batch": 100}
+SPINUP = {"slab": 500, "lattice": 300, "batch": 100, "adjoint": 0}
+ADJ_SWEEP_BYTES = 48       # rbar, lambda, sigma, phi' and two face coefficients per (cell, group) update
 BYTES_2D = (64, 20, 4)     # 2-D: x, y, ox, oy, nu, w, id + cell word, group; writes x, y, cell word
 
 
@@ -65,6 +69,90 @@ def cpu_baseline(probs, budget_s=15.0):
             f"{steps} instance-steps of the first {len(sims)} instances from t=0")
     return {"value": pushes / dt, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
             "sample": f"{what} ({pushes} pushes, {dt:.1f} s, single thread)"}
+
+
+def cpu_baseline_adjoint(prob, budget_s=15.0):
+    """The oracle's adjoint as it stands, single thread: a forward run recorded
+    from t = 0 for as many steps as fit in half the budget, then its adjoint."""
+    import oracle
+    sim = oracle.Sim(prob)
+    sim.record(True)
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < 0.5 * budget_s and steps < prob.steps:
+        sim.step(1)
+        steps += 1
+    V = cell_volume(prob)
+    t1 = time.perf_counter()
+    sim.adjoint(V * prob.cv)
+    dt = time.perf_counter() - t1
+    upd = sim.adjoint_updates()
+    return {"value": upd / dt, "unit": "cell-group updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"adjoint of steps 0-{steps - 1} of the same run ({upd} cell-group updates of the "
+                      f"transposed iteration, {dt:.1f} s, single thread)"}
+
+
+def cell_volume(p):
+    return (p.x1 - p.x0) / p.nx * ((p.y1 - p.y0) / p.ny if p.dim == 2 else 1.0)
+
+
+def run_adjoint(args, stream):
+    """Record --steps steps from t = 0, then time the adjoint (after one untimed
+    warm-up of both on a short run)."""
+    import numpy as np
+    import torch
+    from paper_2312_16981_amd import ugkwp
+    from paper_2312_16981_amd import workloads as W
+    prob = W.c5_lognormal()
+    nsteps = args.steps
+    ctx = ugkwp.from_problem(prob, stream=stream.cuda_stream)
+    dJdT = cell_volume(prob) * np.asarray(prob.cv)
+    ctx.record(max(args.warmup, 1))
+    ctx.step(max(args.warmup, 1))
+    ctx.adjoint(dJdT)
+    ctx.set_material(prob.cv, prob.T0, prob.Tr0, prob.pinned)      # back to t = 0
+    ctx.record(nsteps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(nsteps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ctx.adjoint(dJdT)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    st = ctx.last_adjoint
+    cgu = st["cell_group_updates"]
+    ms_sw = st["ms_sweeps"]
+    achieved = ADJ_SWEEP_BYTES * cgu / (ms_sw * 1e-3) / 1e9
+    out = {
+        "metric": "cell-group updates/s (adjoint of the frozen-tally macroscopic map, FP64, parity 1e-10 vs oracle)",
+        "value": cgu / t_adj,
+        "unit": "cell-group updates/s",
+        "n_gpus": 1,
+        "steps": nsteps,
+        "warmup": args.warmup,
+        "ms_per_step": t_adj * 1e3 / nsteps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2-D log-normal opacity {prob.nx}x{prob.ny} cells x {prob.G} groups, dt=1e-3, "
+                               f"adjoint of steps 0-{nsteps - 1} (dJ/dkappa of the material energy)",
+                   "cell_groups": prob.ncell * prob.G, "parallelism": "single GPU"},
+        "forward_ms_per_step_recording": t_fwd * 1e3 / nsteps,
+        "adjoint_ms": t_adj * 1e3,
+        "adjoint_gpu_ms": st["ms"],
+        "adjoint_sweeps_per_step": cgu / (prob.ncell * prob.G) / nsteps,
+        "sweep_ms": ms_sw,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_adj_sweep",
+                     "algorithmic_bytes_per_update": ADJ_SWEEP_BYTES},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_adjoint(prob, args.cpu_budget)
+    print(json.dumps(out), flush=True)
 
 
 def summarize_trace(csv_path, steps, push_kernel="k_push"):
@@ -162,11 +250,12 @@ def main():
     ap.add_argument("--copy-probe", type=int, metavar="MIB", default=0,
                     help="run a plain device copy of MIB MiB (HBM counter reference) and exit")
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=-1,
+                    help="timed steps (default 400; for the adjoint workload the recorded steps, 100)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--workload", choices=("slab", "lattice", "batch"), default="slab")
+    ap.add_argument("--workload", choices=("slab", "lattice", "batch", "adjoint"), default="slab")
     ap.add_argument("--per-instance", action="store_true",
                     help="batch workload: one context per instance instead of one batched context")
     ap.add_argument("--spinup", type=int, default=-1, help="untimed steps from t=0 (default per workload)")
@@ -195,6 +284,11 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     wl = args.workload
+    if args.steps < 0:
+        args.steps = 100 if wl == "adjoint" else 400
+    if wl == "adjoint":
+        run_adjoint(args, stream)
+        return
     if wl == "slab":
         probs = [W.c2_two_material()]
     elif wl == "lattice":

@@ -212,6 +212,10 @@ typedef struct {
     int sweeps_launched;     /* transposed source-iteration sweeps launched, sum  */
     int sweeps_max;          /* largest per step                                   */
     double ms;               /* GPU time of the whole reverse sweep                */
+    double ms_sweeps;        /* of which the transposed source-iteration sweeps
+                                (incl. their convergence polls)                    */
+    long long cell_group_updates; /* sum over steps and instances of cells x groups
+                                x sweeps up to convergence                         */
 } ugkwp_adjoint_stats;
 
 /* dJdT [ncell] and grad_kappa [ncell][G] (all instances, concatenated as for

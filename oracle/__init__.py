@@ -88,6 +88,8 @@ def lib():
         L.ora_record.argtypes = [C.c_void_p, C.c_int]
         L.ora_adjoint.argtypes = [C.c_void_p, _pd, _pd]
         L.ora_replay_frozen.argtypes = [C.c_void_p, _pd, _pd]
+        L.ora_adjoint_updates.argtypes = []
+        L.ora_adjoint_updates.restype = C.c_longlong
         _lib = L
     return _lib
 
@@ -293,6 +295,10 @@ class Sim:
         if st:
             raise OracleError(st, "adjoint")
         return g
+
+    def adjoint_updates(self):
+        """(cell, group) updates of the transposed iterations of the last adjoint call."""
+        return int(lib().ora_adjoint_updates())
 
     def replay_frozen(self, kappa):
         p = self.prob

@@ -139,6 +139,8 @@ int ora_get_start_weights(const ora_sim* s, double* start);
 int ora_record(ora_sim* s, int on);
 int ora_adjoint(ora_sim* s, const double* dJdT, double* grad_kappa);
 int ora_replay_frozen(ora_sim* s, const double* kappa, double* T_final);
+/* (cell, group) updates done by the transposed iterations of the last ora_adjoint. */
+long long ora_adjoint_updates(void);
 
 #ifdef __cplusplus
 }

@@ -290,8 +290,13 @@ static void transposed_terms(const ora_sim* sim, const coefs* M, const double* w
     }
 }
 
+/* (cell, group) updates of the transposed iterations of the last ora_adjoint call. */
+static long long g_last_updates = 0;
+long long ora_adjoint_updates(void) { return g_last_updates; }
+
 int ora_adjoint(ora_sim* s, const double* dJdT, double* grad_kappa)
 {
+    g_last_updates = 0;
     const int nrec = ora__nrec(s);
     const double* kappa = ora__kappa_rec(s);
     if (nrec == 0 || !kappa) return ORA_EINVAL;
@@ -355,6 +360,7 @@ int ora_adjoint(ora_sim* s, const double* dJdT, double* grad_kappa)
                 if (fabs(mu1[i]) > mm) mm = fabs(mu1[i]);
             }
             memcpy(mu, mu1, sizeof(double) * nc);
+            g_last_updates += (long long)ncg;
             if (!(dm == dm)) break;
             if (dm <= (it >= 60 ? 1e-13 : 1e-15) * mm) conv = 1;
         }

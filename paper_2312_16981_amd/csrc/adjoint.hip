@@ -196,36 +196,21 @@ __device__ inline FaceRef face_ref(const Inst& I, int64_t j, int lcell, int g, i
 // One sweep of the transposed source iteration:
 //   mu^{k+1} = Tbar + sum_g phi_g' [ -w sigma/(1+lambda) mu^k + lambda/(1+lambda) rbar
 //                                    + (dt/V) sum_f S_f D_f (bbar_nb - bbar) ].
-// Sweep k first decides convergence from sweep k-1's residual (relative 1e-15,
-// 1e-13 after 60 sweeps), exactly as the source iteration of the forward step.
+// Residual maxima go to 64 sub-slots of the instance; k_adj_decide reads them.
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj A, int k, const double* mu_in,
-                                                           double* mu_out, int check_only)
+                                                           double* mu_out)
 {
     const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
     const Slot s = decode_slot(D, K, j);
     const Inst& I = D.inst[s.inst];
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-    const bool first = j == I.cg_off;
 
-    bool run = A.conv[s.inst] == 0 && j < K.n_cg;
-    if (k > 0) {
-        const AdjResid rr = A.res[((int64_t)s.inst * RES_SLOTS + (k - 1) % RES_SLOTS) * RES_SUB + lane];
-        const double dm = wave_nmax(bitsd(rr.dmu)), mm = wave_nmax(bitsd(rr.mu));
-        const double tol = (k - 1) >= 60 ? 1e-13 : 1e-15;
-        if (run && dm <= tol * mm) {
-            run = false;
-            if (first) {
-                A.conv[s.inst] = k;
-                atomicAdd(A.status + ADJ_CONV, 1ull);
-            }
-        }
-    }
+    const bool run = A.conv[s.inst] == 0 && j < K.n_cg;
     const int64_t rel = j - I.cg_off;
-    if (rel >= 0 && rel < RES_SUB && !check_only) {
+    if (run && rel >= 0 && rel < RES_SUB) {
         AdjResid z = {0ull, 0ull};
         A.res[((int64_t)s.inst * RES_SLOTS + (k + 1) % RES_SLOTS) * RES_SUB + rel] = z;
     }
-    if (check_only) run = false;
 
     const int g = s.g, Gp = I.Gp;
     const bool work = run && s.cell_ok;
@@ -264,7 +249,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
     if (lane == 0) {
         wres[wid][0] = dm; wres[wid][1] = mm;
         winst[wid] = s.inst;
-        wrun[wid] = work ? 1 : 0;
+        wrun[wid] = run ? 1 : 0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -289,6 +274,25 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
             }
             w0 = w1;
         }
+    }
+}
+
+// Convergence after sweep k, one wavefront per instance still running
+// (relative max-norm change 1e-15, 1e-13 from sweep 60 on).
+__global__ void k_adj_decide(Dev D, Consts K, Adj A, int k)
+{
+    const int inst = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (inst >= K.n_inst || A.conv[inst] != 0) return;
+    const AdjResid r = A.res[((int64_t)inst * RES_SLOTS + k % RES_SLOTS) * RES_SUB + lane];
+    const double dm = wave_nmax(bitsd(r.dmu)), mm = wave_nmax(bitsd(r.mu));
+    const double tol = k >= 60 ? 1e-13 : 1e-15;
+    if (lane == 0 && dm <= tol * mm) {
+        const Inst& I = D.inst[inst];
+        A.conv[inst] = k + 1;
+        atomicAdd(A.status + ADJ_CONV, 1ull);
+        atomicAdd(A.status + ADJ_CGU, (unsigned long long)(k + 1) * (unsigned long long)(I.ncell * I.G));
+        atomicMax(A.status + ADJ_MAXK, (unsigned long long)(k + 1));
     }
 }
 
@@ -382,11 +386,12 @@ void launch_adj_prep(const Dev& D, const Consts& K, const Adj& A, int r, hipStre
     k_adj_prep<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, r);
 }
 
-void launch_adj_sweep(const Dev& D, const Consts& K, const Adj& A, int k, bool check_only, hipStream_t st)
+void launch_adj_sweep(const Dev& D, const Consts& K, const Adj& A, int k, hipStream_t st)
 {
     const double* in = (k & 1) ? A.mu1 : A.mu0;
     double* out = (k & 1) ? A.mu0 : A.mu1;
-    k_adj_sweep<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, k, in, out, check_only ? 1 : 0);
+    k_adj_sweep<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, k, in, out);
+    k_adj_decide<<<ablocks((int64_t)K.n_inst * WAVE), ADJ_THREADS, 0, st>>>(D, K, A, k);
 }
 
 void launch_adj_grad(const Dev& D, const Consts& K, const Adj& A, int r, hipStream_t st)

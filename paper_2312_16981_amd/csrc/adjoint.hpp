@@ -21,7 +21,7 @@ struct AdjResid {
     unsigned long long dmu, mu;     // max |mu^{k+1} - mu^k|, max |mu^{k+1}| as IEEE bits
 };
 
-enum { ADJ_CONV = 0, ADJ_ERR = 1, ADJ_N_STATUS = 2 };
+enum { ADJ_CONV = 0, ADJ_ERR = 1, ADJ_CGU = 2, ADJ_MAXK = 3, ADJ_N_STATUS = 4 };
 
 struct Adj {
     // record: step r occupies [r * n_cg, (r+1) * n_cg) and [r * ncell, (r+1) * ncell)
@@ -46,7 +46,9 @@ struct Adj {
     double* Dhy;
     AdjResid* res;        // [n_inst][RES_SLOTS][RES_SUB]
     int* conv;            // [n_inst] sweeps at convergence, 0 while running
-    unsigned long long* status;   // ADJ_CONV: converged instances, ADJ_ERR: non-finite seen
+    unsigned long long* status;   // ADJ_CONV: converged instances, ADJ_ERR: non-finite seen,
+                                  // ADJ_CGU: (cell, group) updates of the converged sweeps,
+                                  // ADJ_MAXK: most sweeps an instance needed
 };
 
 hipError_t set_head_series_adj(const HeadSeries& hs);
@@ -55,7 +57,8 @@ void launch_adj_coef(const Dev& D, const Consts& K, const Adj& A, hipStream_t st
 void launch_adj_face(const Dev& D, const Consts& K, const Adj& A, int inst, int axis, int64_t nslots,
                      hipStream_t st);
 void launch_adj_prep(const Dev& D, const Consts& K, const Adj& A, int r, hipStream_t st);
-void launch_adj_sweep(const Dev& D, const Consts& K, const Adj& A, int k, bool check_only, hipStream_t st);
+// sweep k of the transposed iteration followed by its convergence decision
+void launch_adj_sweep(const Dev& D, const Consts& K, const Adj& A, int k, hipStream_t st);
 void launch_adj_grad(const Dev& D, const Consts& K, const Adj& A, int r, hipStream_t st);
 
 }  // namespace ugk

@@ -821,36 +821,23 @@ __global__ void k_macro_setup(Dev D, Consts K)
 
 constexpr int SI_THREADS = 256;
 
+// Sweep k: rho^{k+1}, T^{k+1} and phi^{k+1} from phi^k for every instance whose
+// iteration is still running.  The residual maxima of the sweep go to sub-slots
+// of the instance (spread over 64 addresses by block); k_si_decide reads them.
 __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k, const double* phi_in,
-                                                          double* phi_out, int check_only)
+                                                          double* phi_out)
 {
     const int64_t j = (int64_t)blockIdx.x * SI_THREADS + threadIdx.x;
     const Slot s = decode_slot(D, K, j);
     const Inst& I = D.inst[s.inst];
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-    const bool first = j == I.cg_off;
 
-    // convergence decision from the previous sweep (identical in every thread of the
-    // instance): lane l reads sub-slot l, the wavefront takes the maxima
-    bool run = D.ist[s.inst].conv_sweeps == 0 && j < K.n_cg;
-    if (k > 0) {
-        const Resid r = D.res[((int64_t)s.inst * RES_SLOTS + (k - 1) % RES_SLOTS) * RES_SUB + lane];
-        const double drho = wave_nmax(bitsd(r.drho)), mrho = wave_nmax(bitsd(r.rho));
-        const double dT = wave_nmax(bitsd(r.dT)), mT = wave_nmax(bitsd(r.T));
-        if (run && drho <= K.si_tol * mrho && dT <= K.si_tol * mT) {
-            run = false;
-            if (first) {
-                D.ist[s.inst].conv_sweeps = k;
-                atomicAdd((unsigned long long*)(D.counters + CNT_CONV), 1ull);
-            }
-        }
-    }
+    const bool run = D.ist[s.inst].conv_sweeps == 0 && j < K.n_cg;
     const int64_t rel = j - I.cg_off;
-    if (rel >= 0 && rel < RES_SUB && !check_only) {
+    if (run && rel >= 0 && rel < RES_SUB) {
         Resid z = {0ull, 0ull, 0ull, 0ull};
         D.res[((int64_t)s.inst * RES_SLOTS + (k + 1) % RES_SLOTS) * RES_SUB + rel] = z;
     }
-    if (check_only) run = false;
 
     double dr = 0.0, mr = 0.0, dT = 0.0, mT = 0.0;
     const int g = s.g, Gp = I.Gp, G = I.G;
@@ -945,16 +932,15 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     if (lane == 0) {
         wres[wid][0] = dr; wres[wid][1] = mr; wres[wid][2] = dT; wres[wid][3] = mT;
         winst[wid] = s.inst;
-        wrun[wid] = work ? 1 : 0;
+        wrun[wid] = run ? 1 : 0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         int w0 = 0;
         const int nw = SI_THREADS / WAVE;
         while (w0 < nw) {
-            int w1 = w0;
+            int w1 = w0, any = 0;
             double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-            int any = 0;
             while (w1 < nw && winst[w1] == winst[w0]) {
                 if (wrun[w1]) {
                     any = 1;
@@ -973,6 +959,23 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
             }
             w0 = w1;
         }
+    }
+}
+
+// Convergence after sweep k, one wavefront per instance still running: lane l
+// reads sub-slot l; converged when max|rho^{k+1} - rho^k| <= si_tol max|rho^{k+1}|
+// and max|T^{k+1} - T^k| <= si_tol max T^{k+1} (Algorithm 2's stopping test).
+__global__ void k_si_decide(Dev D, Consts K, int k)
+{
+    const int inst = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (inst >= K.n_inst || D.ist[inst].conv_sweeps != 0) return;
+    const Resid r = D.res[((int64_t)inst * RES_SLOTS + k % RES_SLOTS) * RES_SUB + lane];
+    const double drho = wave_nmax(bitsd(r.drho)), mrho = wave_nmax(bitsd(r.rho));
+    const double dT = wave_nmax(bitsd(r.dT)), mT = wave_nmax(bitsd(r.T));
+    if (lane == 0 && drho <= K.si_tol * mrho && dT <= K.si_tol * mT) {
+        D.ist[inst].conv_sweeps = k + 1;
+        atomicAdd((unsigned long long*)(D.counters + CNT_CONV), 1ull);
     }
 }
 
@@ -1274,11 +1277,12 @@ void launch_macro_setup(const Dev& D, const Consts& K, hipStream_t st)
     k_macro_setup<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K);
 }
 
-void launch_si_sweep(const Dev& D, const Consts& K, int k, bool check_only, hipStream_t st)
+void launch_si_sweep(const Dev& D, const Consts& K, int k, hipStream_t st)
 {
     const double* pin = (k & 1) ? D.phi1 : D.phi0;
     double* pout = (k & 1) ? D.phi0 : D.phi1;
-    k_si_sweep<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, pin, pout, check_only ? 1 : 0);
+    k_si_sweep<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, pin, pout);
+    k_si_decide<<<blocks((int64_t)K.n_inst * WAVE, 256), 256, 0, st>>>(D, K, k);
 }
 
 void launch_finish(const Dev& D, const Consts& K, hipStream_t st)

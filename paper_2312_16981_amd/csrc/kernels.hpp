@@ -29,7 +29,8 @@ void launch_push(int dim, const Dev& D, const Consts& K, const Pool& A, const Po
 void launch_pool_count(int dim, const Dev& D, const Consts& K, hipStream_t st);
 void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& B, const Pool& A, hipStream_t st);
 void launch_macro_setup(const Dev& D, const Consts& K, hipStream_t st);
-void launch_si_sweep(const Dev& D, const Consts& K, int k, bool check_only, hipStream_t st);
+// sweep k of the source iteration followed by its convergence decision
+void launch_si_sweep(const Dev& D, const Consts& K, int k, hipStream_t st);
 void launch_finish(const Dev& D, const Consts& K, hipStream_t st);
 
 void launch_eval_phi(int n, const double* T, int G, const double* nu, double a, double c, double* out,

@@ -123,6 +123,27 @@ T* dalloc(std::vector<void*>& owned, size_t n)
     return (T*)p;
 }
 
+// rows x width bytes from src (row pitch spitch) to dst (row pitch dpitch).  A
+// pitched copy into pageable host memory would go row by row, so it is staged
+// in one contiguous transfer and unpacked on the host (synchronously).
+void copy_rows(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width, size_t rows,
+               hipMemcpyKind kind, hipStream_t st)
+{
+    if (rows == 0 || width == 0) return;
+    if (dpitch == width && spitch == width) {
+        HIPCHK(hipMemcpyAsync(dst, src, width * rows, kind, st));
+        return;
+    }
+    if (kind == hipMemcpyDeviceToHost) {
+        std::vector<char> tmp(spitch * (rows - 1) + width);
+        HIPCHK(hipMemcpyAsync(tmp.data(), src, tmp.size(), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (size_t r = 0; r < rows; ++r) memcpy((char*)dst + r * dpitch, tmp.data() + r * spitch, width);
+        return;
+    }
+    HIPCHK(hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, kind, st));
+}
+
 }  // namespace
 
 struct ugkwp_ctx {
@@ -515,7 +536,7 @@ struct ugkwp_ctx {
     // ---------------------------------------------------------------- one step
     // Algorithm 1, enqueued without host round trips; one synchronisation at the
     // end reads the status.  Source-iteration sweeps are launched speculatively
-    // (the previous step's count + 2; a converged instance's sweeps return at
+    // (the previous step's count + 1; a converged instance's sweeps return at
     // once) and more are added only if an instance has not converged.
     void enqueue_finish(bool do_sort)
     {
@@ -564,8 +585,10 @@ struct ugkwp_ctx {
         HIPCHK(hipEventRecord(ev[3], st));
         const int kmax = P.si_max_iters;
         int k = 0;
-        const int first = std::min(kmax + 1, last_sweeps + 2);
-        for (; k < first; ++k) launch_si_sweep(D, K, k, k == kmax, st);
+        // each sweep is followed by its convergence decision, so last step's count
+        // plus one covers a step that needs one sweep more without a host round trip
+        const int first = std::min(kmax, last_sweeps + 1);
+        for (; k < first; ++k) launch_si_sweep(D, K, k, st);
         HIPCHK(hipEventRecord(ev[4], st));
         enqueue_finish(do_sort);
         for (;;) {
@@ -576,9 +599,9 @@ struct ugkwp_ctx {
             if (err & ERR_TEMP) fail(UGKWP_ENONFINITE, "source iteration produced a non-positive or non-finite temperature");
             if (err) fail(UGKWP_EHIP, "internal error %llu: particle records or survivor counts inconsistent", err);
             if (h_counters[CNT_CONV] == (unsigned long long)n_inst) break;
-            if (k > kmax) fail(UGKWP_ENOCONV, "source iteration did not converge in %d sweeps", kmax);
-            const int kend = std::min(k + 4, kmax + 1);
-            for (; k < kend; ++k) launch_si_sweep(D, K, k, k == kmax, st);
+            if (k >= kmax) fail(UGKWP_ENOCONV, "source iteration did not converge in %d sweeps", kmax);
+            const int kend = std::min(k + 4, kmax);
+            for (; k < kend; ++k) launch_si_sweep(D, K, k, st);
             enqueue_finish(do_sort);
         }
 
@@ -699,23 +722,38 @@ struct ugkwp_ctx {
         }
         const int kmax = 1000;
         int sweeps_sum = 0, sweeps_max = 0;
+        double ms_sweeps = 0.0;
+        long long cg_updates = 0;
+        int last = rec_sweeps[nrec - 1];    // sweeps the previous reverse step needed
         for (int r = nrec - 1; r >= 0; --r) {
             HIPCHK(hipMemsetAsync(A.status, 0, sizeof(unsigned long long) * ADJ_N_STATUS, st));
             launch_adj_prep(D, K, A, r, st);
+            HIPCHK(hipEventRecord(ev[2], st));
             int k = 0;
-            const int first = std::min(kmax + 1, rec_sweeps[r] + 3);
-            for (; k < first; ++k) launch_adj_sweep(D, K, A, k, k == kmax, st);
+            const int first = std::min(kmax, last + 1);
+            for (; k < first; ++k) launch_adj_sweep(D, K, A, k, st);
             for (;;) {
                 HIPCHK(hipMemcpyAsync(h_adj, A.status, sizeof(unsigned long long) * ADJ_N_STATUS,
                                       hipMemcpyDeviceToHost, st));
                 HIPCHK(hipStreamSynchronize(st));
                 if (h_adj[ADJ_ERR]) fail(UGKWP_ENONFINITE, "adjoint of step %d produced a non-finite value", r);
-                if (h_adj[ADJ_CONV] == (unsigned long long)n_inst) break;
-                if (k > kmax) fail(UGKWP_ENOCONV, "transposed source iteration of step %d did not converge", r);
-                const int kend = std::min(k + 4, kmax + 1);
-                for (; k < kend; ++k) launch_adj_sweep(D, K, A, k, k == kmax, st);
+                if (h_adj[ADJ_CONV] == (unsigned long long)n_inst) {
+                    cg_updates += (long long)h_adj[ADJ_CGU];
+                    last = (int)h_adj[ADJ_MAXK];
+                    break;
+                }
+                if (k >= kmax) fail(UGKWP_ENOCONV, "transposed source iteration of step %d did not converge", r);
+                const int kend = std::min(k + 4, kmax);
+                for (; k < kend; ++k) launch_adj_sweep(D, K, A, k, st);
             }
+            HIPCHK(hipEventRecord(ev[3], st));
             launch_adj_grad(D, K, A, r, st);
+            {
+                HIPCHK(hipEventSynchronize(ev[3]));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, ev[2], ev[3]));
+                ms_sweeps += ms;
+            }
             std::swap(A.rbar, A.rbar_next);
             sweeps_sum += k;
             sweeps_max = std::max(sweeps_max, k);
@@ -724,8 +762,8 @@ struct ugkwp_ctx {
         int64_t out = 0;
         for (int q = 0; q < n_inst; ++q) {
             const Inst& I = inst[q];
-            copy_rows_rt(grad + out, sizeof(double) * I.G, A.grad + I.cg_off, sizeof(double) * I.Gp,
-                         sizeof(double) * I.G, I.ncell, kind);
+            copy_rows(grad + out, sizeof(double) * I.G, A.grad + I.cg_off, sizeof(double) * I.Gp,
+                      sizeof(double) * I.G, I.ncell, kind, st);
             out += (int64_t)I.ncell * I.G;
         }
         HIPCHK(hipEventRecord(ev[1], st));
@@ -738,15 +776,11 @@ struct ugkwp_ctx {
             stats->sweeps_launched = sweeps_sum;
             stats->sweeps_max = sweeps_max;
             stats->ms = ms;
+            stats->ms_sweeps = ms_sweeps;
+            stats->cell_group_updates = cg_updates;
         }
     }
 
-    void copy_rows_rt(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width, size_t rows,
-                      hipMemcpyKind kind)
-    {
-        if (rows == 0 || width == 0) return;
-        HIPCHK(hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, kind, st));
-    }
 };
 
 // ---------------------------------------------------------------------------
@@ -784,13 +818,6 @@ void check_inst(const ugkwp_ctx* c, int k)
 {
     if (c->n_inst == 0) fail(UGKWP_EINVAL, "mesh not initialised");
     if (k < 0 || k >= c->n_inst) fail(UGKWP_EINVAL, "instance %d out of range", k);
-}
-
-void copy_rows(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width, size_t rows,
-               hipMemcpyKind kind, hipStream_t st)
-{
-    if (rows == 0 || width == 0) return;
-    HIPCHK(hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, kind, st));
 }
 
 }  // namespace

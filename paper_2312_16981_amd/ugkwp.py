@@ -54,7 +54,8 @@ class Instance(C.Structure):
 
 
 class AdjointStats(C.Structure):
-    _fields_ = [("steps", C.c_int), ("sweeps_launched", C.c_int), ("sweeps_max", C.c_int), ("ms", _d)]
+    _fields_ = [("steps", C.c_int), ("sweeps_launched", C.c_int), ("sweeps_max", C.c_int), ("ms", _d),
+                ("ms_sweeps", _d), ("cell_group_updates", C.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
