@@ -39,6 +39,26 @@ PUSH_BYTES_WRITE = 12      # new position and cell word of a survivor (updated i
 PUSH_BYTES_DEAD = 4        # empty-slot mark of a particle absorbed or gone
 SPINUP = {"slab": 500, "lattice": 300, "batch": 100, "adjoint": 0}
 ADJ_SWEEP_BYTES = 48       # rbar, lambda, sigma, phi' and two face coefficients per (cell, group) update
+
+# HBM bytes per push of k_push measured with rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# each scaled by its reading for a plain 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE
+# x 1.0), over the windows of the profiles under profiles/.  They hold only for
+# the push kernel sources they were taken with (SHA-256 prefix below); any change
+# to those sources makes bench.py report the traffic as unknown.
+PUSH_SOURCES = ("kernels.hip", "device_math.hpp", "device_common.hpp", "common.hpp")
+PUSH_TRAFFIC = {
+    "slab": {"sources": "ccab938fa2fb5b4e", "read_per_push": 48.80, "write_per_push": 12.65},
+    "lattice": {"sources": "ccab938fa2fb5b4e", "read_per_push": 66.66, "write_per_push": 22.11},
+}
+
+
+def push_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PUSH_SOURCES:
+        with open(os.path.join(ROOT, "paper_2312_16981_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 BYTES_2D = (64, 20, 4)     # 2-D: x, y, ox, oy, nu, w, id + cell word, group; writes x, y, cell word
 
 
@@ -348,6 +368,10 @@ def main():
     br, bw, bd = (PUSH_BYTES_READ, PUSH_BYTES_WRITE, PUSH_BYTES_DEAD) if probs[0].dim == 1 else BYTES_2D
     algo_bytes = br * pushes + bw * survivors + bd * (pushes - survivors)
     achieved = algo_bytes / (ms_push * 1e-3) / 1e9
+    traffic = None
+    tr = PUSH_TRAFFIC.get(wl)
+    if tr and not args.per_instance and tr["sources"] == push_sources_digest():
+        traffic = (tr["read_per_push"] + tr["write_per_push"]) * pushes / max(args.steps, 1)
     out = {
         "metric": "particle-pushes/s (whole UGKWP step, FP64, parity 1e-10 vs oracle)",
         "value": value,
@@ -373,7 +397,9 @@ def main():
         "ms_per_step_phases": {"push": ms_push / max(args.steps, 1), "si": ms_si / max(args.steps, 1),
                                "sort": ms_sort / max(args.steps, 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (measured bytes per push x pushes per launch)",
+                     "algorithmic_bytes_per_launch": algo_bytes / max(args.steps, 1),
                      "kernel": f"k_push<{probs[0].dim}>", "algorithmic_bytes_per_push":
                      f"{br} read + {bw} per survivor + {bd} per absorbed/escaped particle"},
     }

@@ -109,9 +109,10 @@ typedef struct {
     double inflow_wave, inflow_eq, exit_particles, injection;
     double residual;         /* e_end - e_start - (inflow_wave + inflow_eq - exit + injection) */
     /* GPU time of the phases of the step, in ms, from HIP events on the context
-     * stream: count + scan + sample (incl. one host read of the birth total and
-     * the tally clears), the push kernel alone, wave flux + source set-up, and the
-     * source iteration (incl. its host convergence polls), and the counting sort
+     * stream: tally clears + count + scan + sample, the push kernel alone (events
+     * recorded just before and after its launch, so the interval also holds its
+     * dispatch, a few microseconds), wave flux + source set-up, the
+     * source iteration (incl. any host convergence poll), and the counting sort
      * that keeps the pool ordered by (cell, group). */
     double ms_sample, ms_push, ms_macro, ms_si, ms_sort;
 } ugkwp_diag;
