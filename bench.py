@@ -281,6 +281,11 @@ def main():
     ap.add_argument("--spinup", type=int, default=-1, help="untimed steps from t=0 (default per workload)")
     ap.add_argument("--sort-interval", type=int, default=0,
                     help="steps between counting sorts of the pool (0 = library default)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default push launch shape instead of tuning it after the spin-up")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the launches before the push and the source-iteration sweeps from "
+                         "captured HIP graphs")
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.steps))
@@ -317,14 +322,16 @@ def main():
         probs = W.c4_batch()
     ncg = sum(p.ncell * p.G for p in probs)
     spin = SPINUP[wl] if args.spinup < 0 else args.spinup
+    xf = ugkwp.FLAG_GRAPH if args.graph else 0
     if wl == "batch" and args.per_instance:
-        ctxs = [ugkwp.from_problem(p, stream=stream.cuda_stream, sort_interval=args.sort_interval)
+        ctxs = [ugkwp.from_problem(p, stream=stream.cuda_stream, sort_interval=args.sort_interval, extra_flags=xf)
                 for p in probs]
     elif wl == "batch":
         ctxs = [ugkwp.from_batch(probs, stream=stream.cuda_stream, pool_capacity=1 << 26,
-                                 sort_interval=args.sort_interval)]
+                                 sort_interval=args.sort_interval, extra_flags=xf)]
     else:
-        ctxs = [ugkwp.from_problem(probs[0], stream=stream.cuda_stream, sort_interval=args.sort_interval)]
+        ctxs = [ugkwp.from_problem(probs[0], stream=stream.cuda_stream, sort_interval=args.sort_interval,
+                                   extra_flags=xf)]
 
     def one_step():
         acc = {"n_pushed": 0, "n_alive_out": 0, "sweeps": 0, "ms_push": 0.0, "ms_si": 0.0, "ms_sort": 0.0}
@@ -339,7 +346,12 @@ def main():
             acc["sweeps"] += d["sweeps_sum"]
         return acc
 
-    for _ in range(spin + args.warmup):
+    for _ in range(spin):
+        one_step()
+    tuned = None
+    if not args.no_autotune:
+        tuned = [c.autotune() for c in ctxs]
+    for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
 
@@ -388,7 +400,12 @@ def main():
         "config": {"workload": workload_name(wl, probs, spin, args),
                    "particles_per_step": pushes / max(args.steps, 1),
                    "cell_groups": ncg,
-                   "parallelism": "single GPU" + (", per-instance contexts" if args.per_instance else "")},
+                   "parallelism": "single GPU" + (", per-instance contexts" if args.per_instance else ""),
+                   "launch": "HIP graph replays" if args.graph else "kernels launched directly",
+                   "push_shape": ("default (occupancy-filled grid, 4 particles per thread)" if tuned is None else
+                                  f"autotuned: {tuned[0]['blocks']} blocks, {tuned[0]['ppt']} particles per thread "
+                                  f"({tuned[0]['us_best']:.1f} vs {tuned[0]['us_default']:.1f} us default)"
+                                  + (f", per context ({len(tuned)})" if len(tuned) > 1 else ""))},
         "cell_group_updates_per_s": mean_cg * sweeps / elapsed,
         "cell_group_updates_per_s_si_only": mean_cg * sweeps / (ms_si * 1e-3) if ms_si > 0 else None,
         "push_kernel_pushes_per_s": pushes / (ms_push * 1e-3),

@@ -56,8 +56,12 @@ enum { UGKWP_SIDE_XLO = 0, UGKWP_SIDE_XHI = 1, UGKWP_SIDE_YLO = 2, UGKWP_SIDE_YH
 
 /* Flags */
 enum {
-    UGKWP_FLAG_GROUP_SIGMA = 1   /* particle flights use the Simpson group opacity
+    UGKWP_FLAG_GROUP_SIGMA = 1,  /* particle flights use the Simpson group opacity
                                     instead of kappa * nu_k^-p (Remark 2)        */
+    UGKWP_FLAG_GRAPH = 2         /* replay the launches before the push and the
+                                    source-iteration sweeps from captured HIP
+                                    graphs (one per launch configuration) instead
+                                    of launching each kernel; same results        */
 };
 
 typedef struct ugkwp_ctx ugkwp_ctx;
@@ -179,6 +183,22 @@ int ugkwp_set_pool(ugkwp_ctx* ctx, int64_t n, const double* x, const double* y,
                    const double* ox, const double* oy, const double* nu, const double* w,
                    const uint64_t* id, const int32_t* cell, const int32_t* g,
                    uint64_t birth_counter, const double* rhop);
+
+/* ---- launch autotuner ----
+ * Times the particle push on the context's current pool for launch shapes
+ * (persistent blocks per CU: half, one and two times what fits; particles per
+ * thread: 1, 2, 4, 8) and keeps the fastest for the following steps.  Only the
+ * speed changes: the order in which the push adds to its tallies may differ,
+ * which moves floating-point sums by rounding.  The tallies and counters of the
+ * last step are restored.  Needs a non-empty pool (UGKWP_EINVAL otherwise). */
+typedef struct {
+    int ppt;                 /* particles per thread chosen                        */
+    int blocks;              /* push blocks chosen                                 */
+    int candidates;          /* shapes timed                                       */
+    double us_best;          /* push time of the chosen shape, microseconds       */
+    double us_default;       /* of the default shape (occupancy-filled grid, 4)   */
+} ugkwp_tune_result;
+int ugkwp_autotune(ugkwp_ctx* ctx, ugkwp_tune_result* res);
 
 /* ---- adjoint of the macroscopic solve with the particle results held fixed ----
  *

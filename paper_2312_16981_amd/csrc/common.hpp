@@ -154,6 +154,7 @@ struct Dev {
     double* diag;               // [n_inst][8] (folded from diag_sub each step)
     double* diag_sub;           // [n_inst][DIAG_SUB][8]
     // context-wide counters
+    uint32_t* step;                 // step index n (keys the random numbers), advanced on commit
     unsigned long long* counters;   // CNT_*
     int64_t* n_births_total;        // [0] births of the step, [1] survivors (sort scan)
     unsigned long long* blk_surv;   // survivors counted by each push block

@@ -278,8 +278,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(const int32_t* in, 
 // A2: sample the collisionless wave particles
 
 template <int DIM>
-__global__ void k_sample(Dev D, Consts K, Pool P, uint32_t step)
+__global__ void k_sample(Dev D, Consts K, Pool P)
 {
+    const uint32_t step = *D.step;
     const int64_t n_slots = (int64_t)D.counters[CNT_SLOTS];
     const int64_t total = D.n_births_total[0];
     if (n_slots + total > K.pool_cap) {
@@ -336,7 +337,8 @@ __global__ void k_sample(Dev D, Consts K, Pool P, uint32_t step)
 // ---------------------------------------------------------------------------
 // A3: free flight, reset at interfaces, tallies, deletion, compaction
 //
-// One thread per particle, PUSH_PPT particles per thread.  Tallies (survivor
+// One thread per particle, ppt particles per thread (a launch parameter chosen
+// by the autotuner, 4 by default).  Tallies (survivor
 // and deposited weight per (cell, group), gross face crossings per face, group
 // and direction, survivor counts per (cell, group)) are accumulated in a
 // per-block LDS hash table and flushed with one global atomic per distinct bin:
@@ -344,10 +346,7 @@ __global__ void k_sample(Dev D, Consts K, Pool P, uint32_t step)
 // into a handful of bins.
 
 constexpr int PUSH_THREADS = 256;
-#ifndef UGK_PUSH_PPT
-#define UGK_PUSH_PPT 4
-#endif
-constexpr int PUSH_PPT = UGK_PUSH_PPT;
+constexpr int PUSH_PPT_DEFAULT = 4;
 constexpr int HT_BITS = 10;
 constexpr int HT_SIZE = 1 << HT_BITS;
 constexpr uint32_t HT_EMPTY = 0xFFFFFFFFu;
@@ -490,23 +489,23 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTabl
     }
 }
 
-// Each block takes chunks of PUSH_THREADS * PUSH_PPT consecutive pool slots;
-// a thread handles PUSH_PPT of them.  Stable fields are only read; the new
+// Each block takes chunks of PUSH_THREADS * ppt consecutive pool slots;
+// a thread handles ppt of them.  Stable fields are only read; the new
 // position and cell word go to the other moving-field buffer at the same slot,
 // so the committed pool stays intact until the step commits.
 #ifndef UGK_PUSH_ATTR
 #define UGK_PUSH_ATTR
 #endif
 template <int DIM, bool SINGLE, int SM>
-__global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool In, Pool Out,
-                                                                     uint32_t step)
+__global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool In, Pool Out, int ppt)
 {
+    const uint32_t step = *D.step;
     __shared__ TallyTable T;
     __shared__ unsigned long long bsurv[PUSH_THREADS / WAVE];
     if (D.counters[CNT_ERR] & ERR_POOL) return;
     const int64_t n_slots = (int64_t)D.counters[CNT_SLOTS];
     const int64_t n_total = (int64_t)D.counters[CNT_PUSHED];
-    const int64_t chunk = PUSH_THREADS * PUSH_PPT;
+    const int64_t chunk = (int64_t)PUSH_THREADS * ppt;
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     unsigned long long nsurv = 0;
     Geo geo0{};
@@ -518,7 +517,8 @@ __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Cons
             T.val[h] = 0.0;
         }
         __syncthreads();
-        for (int r = 0; r < PUSH_PPT; ++r) {
+#pragma unroll 1
+        for (int r = 0; r < ppt; ++r) {
             const int64_t i = c0 + (int64_t)r * PUSH_THREADS + threadIdx.x;
             if (i >= n_total) continue;
             const int32_t word = In.cell[i];
@@ -1005,6 +1005,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K)
         if (j == 0) {
             D.counters[CNT_SLOTS] = D.counters[CNT_PUSHED];
             D.counters[CNT_LIVE] = D.counters[CNT_SURV];
+            *D.step += 1u;
         }
     }
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // inflow_eq, exit/c, injection, e0, e1
@@ -1188,10 +1189,10 @@ void launch_zero(const ZeroList& Z, hipStream_t st)
     k_zero<<<1024, 256, 0, st>>>(Z);
 }
 
-void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, uint32_t step, hipStream_t st)
+void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, hipStream_t st)
 {
-    if (dim == 1) k_sample<1><<<512, 256, 0, st>>>(D, K, P, step);
-    else k_sample<2><<<512, 256, 0, st>>>(D, K, P, step);
+    if (dim == 1) k_sample<1><<<512, 256, 0, st>>>(D, K, P);
+    else k_sample<2><<<512, 256, 0, st>>>(D, K, P);
 }
 
 static int g_push_grid[2][2][3] = {};
@@ -1231,32 +1232,49 @@ int push_grid(int dim, bool single, int sm)
 }
 
 template <int DIM, bool SINGLE>
-static void push_mode(int sm, int nb, const Dev& D, const Consts& K, const Pool& In, const Pool& Out,
-                      uint32_t step, hipStream_t st)
+static void push_mode(int sm, int nb, int ppt, const Dev& D, const Consts& K, const Pool& In, const Pool& Out,
+                      hipStream_t st)
 {
-    if (sm == SIG_NU3) k_push<DIM, SINGLE, SIG_NU3><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
-    else if (sm == SIG_POW) k_push<DIM, SINGLE, SIG_POW><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
-    else k_push<DIM, SINGLE, SIG_GROUP><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, step);
+    if (sm == SIG_NU3) k_push<DIM, SINGLE, SIG_NU3><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, ppt);
+    else if (sm == SIG_POW) k_push<DIM, SINGLE, SIG_POW><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, ppt);
+    else k_push<DIM, SINGLE, SIG_GROUP><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, ppt);
 }
 
-void launch_push(int dim, const Dev& D, const Consts& K, const Pool& In, const Pool& Out, uint32_t step,
+PushShape push_default_shape(int dim, const Consts& K)
+{
+    PushShape p;
+    p.blocks = push_grid(dim, K.n_inst == 1, sig_mode(K));
+    p.ppt = PUSH_PPT_DEFAULT;
+    return p;
+}
+
+int push_blocks_per_cu(int dim, const Consts& K)
+{
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ncu < 1) ncu = 256;
+    return push_grid(dim, K.n_inst == 1, sig_mode(K)) / ncu;
+}
+
+void launch_push(int dim, const Dev& D, const Consts& K, const Pool& In, const Pool& Out, const PushShape& sh,
                  hipStream_t st)
 {
     const bool single = K.n_inst == 1;
     const int sm = sig_mode(K);
-    const int nb = push_grid(dim, single, sm);
+    const int nb = sh.blocks, ppt = sh.ppt;
     if (dim == 1) {
-        if (single) push_mode<1, true>(sm, nb, D, K, In, Out, step, st);
-        else push_mode<1, false>(sm, nb, D, K, In, Out, step, st);
+        if (single) push_mode<1, true>(sm, nb, ppt, D, K, In, Out, st);
+        else push_mode<1, false>(sm, nb, ppt, D, K, In, Out, st);
     } else {
-        if (single) push_mode<2, true>(sm, nb, D, K, In, Out, step, st);
-        else push_mode<2, false>(sm, nb, D, K, In, Out, step, st);
+        if (single) push_mode<2, true>(sm, nb, ppt, D, K, In, Out, st);
+        else push_mode<2, false>(sm, nb, ppt, D, K, In, Out, st);
     }
 }
 
-void launch_pool_count(int dim, const Dev& D, const Consts& K, hipStream_t st)
+void launch_pool_count(const Dev& D, const PushShape& sh, hipStream_t st)
 {
-    k_pool_count<<<1, 256, 0, st>>>(D, push_grid(dim, K.n_inst == 1, sig_mode(K)));
+    k_pool_count<<<1, 256, 0, st>>>(D, sh.blocks);
 }
 
 void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& In, const Pool& Out, hipStream_t st)

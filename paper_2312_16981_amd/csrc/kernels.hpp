@@ -22,11 +22,18 @@ void launch_zero(const ZeroList& Z, hipStream_t st);
 void launch_count(const Dev& D, const Consts& K, hipStream_t st);
 int64_t scan_partials_size(int64_t n);
 void launch_scan(const int32_t* in, int64_t n, int64_t* part, int64_t* out, int64_t* total, hipStream_t st);
-void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, uint32_t step, hipStream_t st);
+void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, hipStream_t st);
+// Launch shape of the push: persistent blocks and particles per thread.
+struct PushShape {
+    int blocks;
+    int ppt;
+};
 int push_grid(int dim, bool single, int sig_mode);
-void launch_push(int dim, const Dev& D, const Consts& K, const Pool& A, const Pool& B, uint32_t step,
+PushShape push_default_shape(int dim, const Consts& K);   // occupancy-filled grid, 4 per thread
+int push_blocks_per_cu(int dim, const Consts& K);         // resident blocks per CU (occupancy)
+void launch_push(int dim, const Dev& D, const Consts& K, const Pool& A, const Pool& B, const PushShape& sh,
                  hipStream_t st);
-void launch_pool_count(int dim, const Dev& D, const Consts& K, hipStream_t st);
+void launch_pool_count(const Dev& D, const PushShape& sh, hipStream_t st);
 void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& B, const Pool& A, hipStream_t st);
 void launch_macro_setup(const Dev& D, const Consts& K, hipStream_t st);
 // sweep k of the source iteration followed by its convergence decision

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -113,6 +114,8 @@ int ilog2(int p)
     return l;
 }
 
+constexpr int MAX_PUSH_BLOCKS = 8192;     // per-block survivor counts kept by the push
+
 template <class T>
 T* dalloc(std::vector<void*>& owned, size_t n)
 {
@@ -190,6 +193,24 @@ struct ugkwp_ctx {
     int sort_interval = 8;
     ugkwp_diag diag{};
 
+    // launch shape of the push (default: occupancy-filled persistent grid, 4
+    // particles per thread; ugkwp_autotune may change it)
+    PushShape push_shape{0, 4};
+
+    // each step's launch sequence captured as a HIP graph, one per launch
+    // configuration (pool buffer parities, rho/T parity, sort, speculative sweeps)
+    bool use_graph = false;
+    hipStream_t cap_st = nullptr;
+    std::map<uint32_t, hipGraphExec_t> graphs;
+    const double* rho_buf0 = nullptr;
+    int graphs_built = 0;
+
+    void drop_graphs()
+    {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
+
     // adjoint: record of the forward run and reverse-sweep buffers
     std::vector<void*> rec_owned;
     Adj A{};
@@ -210,6 +231,9 @@ struct ugkwp_ctx {
 
     void release()
     {
+        drop_graphs();
+        if (cap_st) (void)hipStreamDestroy(cap_st);
+        cap_st = nullptr;
         free_record();
         if (h_adj) (void)hipHostFree(h_adj);
         h_adj = nullptr;
@@ -227,6 +251,7 @@ struct ugkwp_ctx {
 
     void free_device()
     {
+        drop_graphs();
         free_record();
         for (void* p : owned) (void)hipFree(p);
         owned.clear();
@@ -372,6 +397,8 @@ struct ugkwp_ctx {
         d.c4 = dalloc<double>(owned, ncg);
         d.wc = dalloc<double>(owned, ncg);
         d.rho = dalloc<double>(owned, ncg);
+        rho_buf0 = d.rho;
+        d.step = dalloc<uint32_t>(owned, 1);
         d.rho_new = dalloc<double>(owned, ncg);
         d.rhop = dalloc<double>(owned, ncg);
         d.rhoh = dalloc<double>(owned, ncg);
@@ -441,7 +468,9 @@ struct ugkwp_ctx {
             stb[b].id = dalloc<uint64_t>(owned, cap);
             stb[b].g = dalloc<int32_t>(owned, cap);
         }
-        d.blk_surv = dalloc<unsigned long long>(owned, 8192);
+        d.blk_surv = dalloc<unsigned long long>(owned, MAX_PUSH_BLOCKS);
+        push_shape = push_default_shape(dim, K);
+        push_shape.blocks = std::min(push_shape.blocks, MAX_PUSH_BLOCKS);
         cur_mv = cur_st = 0;
         n_alive = n_slots = 0;
         step_idx = 0;
@@ -505,6 +534,7 @@ struct ugkwp_ctx {
         launch_init_rho(D, K, d_tr, st);
         HIPCHK(hipMemsetAsync(D.ist, 0, sizeof(InstState) * n_inst, st));
         HIPCHK(hipMemsetAsync(D.counters, 0, sizeof(unsigned long long) * N_COUNTERS, st));
+        HIPCHK(hipMemsetAsync(D.step, 0, sizeof(uint32_t), st));
         HIPCHK(hipStreamSynchronize(st));
         (void)hipFree(d_tr);
         HIPCHK(hipGetLastError());
@@ -548,17 +578,11 @@ struct ugkwp_ctx {
             HIPCHK(hipEventRecord(ev[6], st));
         }
         HIPCHK(hipMemcpyAsync(h_status, d_status, status_bytes, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
     }
 
-    int step_once()
+    // The launches before the push: tally clears, counts, scan, sampling.
+    void enqueue_pre_push()
     {
-        if (rec_cap > 0 && nrec >= rec_cap)
-            fail(UGKWP_EINVAL, "the record holds its maximum of %d steps", rec_cap);
-        // sort periodically, and whenever holes have filled half the pool
-        const bool do_sort = sort_interval <= 1 ||
-                             (step_idx % (uint32_t)sort_interval) == (uint32_t)(sort_interval - 1) ||
-                             n_slots > P.pool_capacity / 2;
         ZeroList z{};
         auto add = [&](void* p, int64_t words) {
             if (words > 0) { z.ptr[z.n] = p; z.words[z.n] = words; z.n++; }
@@ -571,26 +595,88 @@ struct ugkwp_ctx {
         add(D.diag_sub, (int64_t)DIAG_SUB * 8 * n_inst);
         add(D.counters, 4);                 // CNT_SURV .. CNT_CONV; slot and live counts persist
         launch_zero(z, st);
-
-        HIPCHK(hipEventRecord(ev[0], st));
         launch_count(D, K, st);
         launch_scan(D.nb, K.n_cg, part, D.boff, D.n_births_total, st);
-        const Pool In = view(cur_mv, cur_st);
-        launch_sample(dim, D, K, In, step_idx, st);
-        HIPCHK(hipEventRecord(ev[1], st));
-        launch_push(dim, D, K, In, moving(1 - cur_mv), step_idx, st);
-        HIPCHK(hipEventRecord(ev[2], st));
-        launch_pool_count(dim, D, K, st);
-        launch_macro_setup(D, K, st);
-        HIPCHK(hipEventRecord(ev[3], st));
+        launch_sample(dim, D, K, view(cur_mv, cur_st), st);
+    }
+
+    void enqueue_sweeps(int k0, int k1)
+    {
+        for (int k = k0; k < k1; ++k) launch_si_sweep(D, K, k, st);
+    }
+
+    // Run `enq` on the context stream: replayed from the HIP graph captured for
+    // `key` (captured on first use), or launched directly without graphs.
+    template <class F>
+    void launch_group(uint32_t key, F&& enq)
+    {
+        if (!use_graph) {
+            enq();
+            return;
+        }
+        auto it = graphs.find(key);
+        if (it == graphs.end()) {
+            if (!cap_st) HIPCHK(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ex = nullptr;
+            std::swap(st, cap_st);
+            hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                try {
+                    enq();
+                } catch (...) {
+                    (void)hipStreamEndCapture(st, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    std::swap(st, cap_st);
+                    throw;
+                }
+                e = hipStreamEndCapture(st, &g);
+            }
+            std::swap(st, cap_st);
+            if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                // this runtime cannot capture these launches: launch directly from now on
+                (void)hipGetLastError();
+                use_graph = false;
+                enq();
+                return;
+            }
+            it = graphs.emplace(key, ex).first;
+            graphs_built++;
+        }
+        HIPCHK(hipGraphLaunch(it->second, st));
+    }
+
+    // Graph keys: what the captured kernel arguments depend on.
+    uint32_t parity() const { return D.rho == rho_buf0 ? 1u : 0u; }
+
+    int step_once()
+    {
+        if (rec_cap > 0 && nrec >= rec_cap)
+            fail(UGKWP_EINVAL, "the record holds its maximum of %d steps", rec_cap);
+        // sort periodically, and whenever holes have filled half the pool
+        const bool do_sort = sort_interval <= 1 ||
+                             (step_idx % (uint32_t)sort_interval) == (uint32_t)(sort_interval - 1) ||
+                             n_slots > P.pool_capacity / 2;
         const int kmax = P.si_max_iters;
-        int k = 0;
         // each sweep is followed by its convergence decision, so last step's count
         // plus one covers a step that needs one sweep more without a host round trip
         const int first = std::min(kmax, last_sweeps + 1);
-        for (; k < first; ++k) launch_si_sweep(D, K, k, st);
+        int k = first;
+        HIPCHK(hipEventRecord(ev[0], st));
+        launch_group(0x100000u | (uint32_t)cur_mv | ((uint32_t)cur_st << 1) | (parity() << 2),
+                     [&] { enqueue_pre_push(); });
+        HIPCHK(hipEventRecord(ev[1], st));
+        launch_push(dim, D, K, view(cur_mv, cur_st), moving(1 - cur_mv), push_shape, st);
+        HIPCHK(hipEventRecord(ev[2], st));
+        launch_pool_count(D, push_shape, st);
+        launch_macro_setup(D, K, st);
+        HIPCHK(hipEventRecord(ev[3], st));
+        launch_group(0x200000u | (uint32_t)first | (parity() << 16), [&] { enqueue_sweeps(0, first); });
         HIPCHK(hipEventRecord(ev[4], st));
         enqueue_finish(do_sort);
+        HIPCHK(hipStreamSynchronize(st));
         for (;;) {
             const unsigned long long err = h_counters[CNT_ERR];
             if (err & ERR_POOL)
@@ -603,6 +689,7 @@ struct ugkwp_ctx {
             const int kend = std::min(k + 4, kmax);
             for (; k < kend; ++k) launch_si_sweep(D, K, k, st);
             enqueue_finish(do_sort);
+            HIPCHK(hipStreamSynchronize(st));
         }
 
         // bookkeeping of the committed step
@@ -654,6 +741,93 @@ struct ugkwp_ctx {
             nrec++;
         }
         return UGKWP_OK;
+    }
+
+    // ---------------------------------------------------------------- autotuner
+    // Times the push on the committed pool for a grid of launch shapes and keeps
+    // the fastest.  The tallies and counters the trial pushes touch are saved
+    // and restored; only the launch shape (hence speed) changes.
+    void autotune(ugkwp_tune_result* res)
+    {
+        if (n_slots == 0) fail(UGKWP_EINVAL, "the particle pool is empty: step the context before tuning");
+        std::vector<unsigned long long> cnt(N_COUNTERS);
+        HIPCHK(hipMemcpyAsync(cnt.data(), D.counters, sizeof(unsigned long long) * N_COUNTERS,
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<unsigned long long> trial = cnt;
+        trial[CNT_PUSHED] = trial[CNT_SLOTS];
+        trial[CNT_ERR] = 0;
+        // save what the trial pushes add to
+        struct Saved { void* dev; void* copy; size_t bytes; };
+        std::vector<Saved> saved;
+        auto keep = [&](void* p, size_t bytes) {
+            if (!p || bytes == 0) return;
+            void* c = nullptr;
+            if (hipMalloc(&c, bytes) != hipSuccess) fail(UGKWP_ENOMEM, "autotune: no room to save the tallies");
+            saved.push_back({p, c, bytes});
+            HIPCHK(hipMemcpyAsync(c, p, bytes, hipMemcpyDeviceToDevice, st));
+        };
+        struct Release {
+            std::vector<Saved>& v;
+            ~Release() { for (auto& q : v) (void)hipFree(q.copy); }
+        } release{saved};
+        keep(D.dep, sizeof(double) * K.n_cg);
+        keep(D.surv, sizeof(double) * K.n_cg);
+        keep(D.scount, sizeof(uint32_t) * K.n_cg);
+        keep(D.ftx, sizeof(double) * 2 * n_fx);
+        if (dim == 2) keep(D.fty, sizeof(double) * 2 * n_fy);
+        HIPCHK(hipMemcpyAsync(D.counters, trial.data(), sizeof(unsigned long long) * N_COUNTERS,
+                              hipMemcpyHostToDevice, st));
+        int dev = 0, ncu = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        const int occ = std::max(1, push_blocks_per_cu(dim, K));
+        std::vector<PushShape> cand;
+        for (int ppt : {1, 2, 4, 8})
+            for (int bpc : {std::max(1, occ / 2), occ, 2 * occ}) {
+                const PushShape c{std::min(bpc * ncu, MAX_PUSH_BLOCKS), ppt};
+                bool dup = false;
+                for (const auto& q : cand) dup = dup || (q.blocks == c.blocks && q.ppt == c.ppt);
+                if (!dup) cand.push_back(c);
+            }
+        const PushShape def = {std::min(push_default_shape(dim, K).blocks, MAX_PUSH_BLOCKS), 4};
+        auto time_push = [&](const PushShape& sh) {
+            const Pool In = view(cur_mv, cur_st), Out = moving(1 - cur_mv);
+            launch_push(dim, D, K, In, Out, sh, st);           // warm-up
+            float best = 1e30f;
+            for (int r = 0; r < 3; ++r) {
+                HIPCHK(hipEventRecord(ev[0], st));
+                launch_push(dim, D, K, In, Out, sh, st);
+                HIPCHK(hipEventRecord(ev[1], st));
+                HIPCHK(hipEventSynchronize(ev[1]));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+                best = std::min(best, ms);
+            }
+            return 1e3 * (double)best;
+        };
+        const double us_def = time_push(def);
+        PushShape best = def;
+        double us_best = us_def;
+        for (const auto& c : cand) {
+            const double us = time_push(c);
+            if (us < us_best) { us_best = us; best = c; }
+        }
+        // restore
+        for (auto& q : saved) HIPCHK(hipMemcpyAsync(q.dev, q.copy, q.bytes, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(D.counters, cnt.data(), sizeof(unsigned long long) * N_COUNTERS,
+                              hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipGetLastError());
+        push_shape = best;
+        drop_graphs();
+        if (res) {
+            res->ppt = best.ppt;
+            res->blocks = best.blocks;
+            res->candidates = (int)cand.size();
+            res->us_best = us_best;
+            res->us_default = us_def;
+        }
     }
 
     // ---------------------------------------------------------------- adjoint
@@ -858,6 +1032,7 @@ int ugkwp_create(ugkwp_ctx** out, const ugkwp_params* p, void* hip_stream)
             c->own_stream = true;
         }
         c->sort_interval = p->sort_interval > 0 ? p->sort_interval : 16;
+        c->use_graph = (p->flags & UGKWP_FLAG_GRAPH) != 0;
         for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
     });
     if (rc) { delete c; return rc; }
@@ -966,6 +1141,15 @@ int ugkwp_record(ugkwp_ctx* ctx, int max_steps)
 }
 
 int ugkwp_recorded_steps(const ugkwp_ctx* ctx) { return ctx ? ctx->nrec : 0; }
+
+int ugkwp_autotune(ugkwp_ctx* ctx, ugkwp_tune_result* res)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        require_ready(ctx);
+        ctx->autotune(res);
+    });
+}
 
 int ugkwp_adjoint(ugkwp_ctx* ctx, const double* dJdT, double* grad_kappa, int ptrs_are_device,
                   ugkwp_adjoint_stats* stats)

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libugkwp.so")
 OK, EINVAL, ENOMEM, EPOOL, ENOCONV, ENONFINITE, EHIP = 0, -1, -2, -3, -4, -5, -6
 BC_VACUUM, BC_PLANCK, BC_REFLECT = 0, 1, 2
 FLAG_GROUP_SIGMA = 1
+FLAG_GRAPH = 2
 PURPOSE_BIRTH, PURPOSE_FLIGHT = 1, 2
 
 EXPORTED = [
@@ -26,7 +27,7 @@ EXPORTED = [
     "ugkwp_get_fields", "ugkwp_get_tallies", "ugkwp_get_diag", "ugkwp_get_counters",
     "ugkwp_pool_size", "ugkwp_get_pool", "ugkwp_set_pool", "ugkwp_eval_phi", "ugkwp_eval_coef",
     "ugkwp_eval_uniform", "ugkwp_eval_sample_nu", "ugkwp_record", "ugkwp_recorded_steps",
-    "ugkwp_adjoint",
+    "ugkwp_adjoint", "ugkwp_autotune",
 ]
 
 _d = C.c_double
@@ -56,6 +57,14 @@ class Instance(C.Structure):
 class AdjointStats(C.Structure):
     _fields_ = [("steps", C.c_int), ("sweeps_launched", C.c_int), ("sweeps_max", C.c_int), ("ms", _d),
                 ("ms_sweeps", _d), ("cell_group_updates", C.c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("ppt", C.c_int), ("blocks", C.c_int), ("candidates", C.c_int), ("us_best", _d),
+                ("us_default", _d)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -115,6 +124,7 @@ def load():
     L.ugkwp_set_pool.argtypes = [vp, C.c_int64, _pd, _pd, _pd, _pd, _pd, _pd, _pu64, _pi32, _pi32,
                                  C.c_uint64, _pd]
     L.ugkwp_record.argtypes = [vp, C.c_int]
+    L.ugkwp_autotune.argtypes = [vp, C.POINTER(TuneResult)]
     L.ugkwp_recorded_steps.argtypes = [vp]
     L.ugkwp_adjoint.argtypes = [vp, _pd, _pd, C.c_int, C.POINTER(AdjointStats)]
     L.ugkwp_eval_phi.argtypes = [C.c_int, _pd, C.c_int, _pd, _d, _d, _pd]
@@ -200,6 +210,12 @@ class Context:
         if check:
             self._chk(rc, "step")
         return rc
+
+    def autotune(self):
+        """Pick the push launch shape by timing it on the current pool (see ugkwp.h)."""
+        r = TuneResult()
+        self._chk(load().ugkwp_autotune(self.h, C.byref(r)), "autotune")
+        return r.as_dict()
 
     # ---- adjoint of the frozen-tally macroscopic map ----
     def record(self, max_steps):
@@ -302,11 +318,12 @@ def make_params(c=1.0, a=1.0, eps=1.0, dt=1e-3, nu_power=3.0, n_cap=1 << 20, poo
     return p
 
 
-def from_problem(prob, stream=None, pool_capacity: Optional[int] = None, sort_interval: int = 0) -> Context:
+def from_problem(prob, stream=None, pool_capacity: Optional[int] = None, sort_interval: int = 0,
+                 extra_flags: int = 0) -> Context:
     """Build a single-instance context from a workloads.Problem."""
     P = make_params(c=prob.c, a=prob.a, eps=prob.eps, dt=prob.dt, nu_power=prob.nu_power,
                     n_cap=prob.n_cap, pool_capacity=pool_capacity or prob.pool_cap,
-                    si_max_iters=prob.si_max_iters, si_tol=prob.si_tol, flags=prob.flags,
+                    si_max_iters=prob.si_max_iters, si_tol=prob.si_tol, flags=prob.flags | extra_flags,
                     sort_interval=sort_interval)
     ctx = Context(P, stream)
     ctx.init_mesh(prob.dim, prob.nx, prob.ny, [prob.x0, prob.y0], [prob.x1, prob.y1], prob.bc, prob.bcT,
@@ -316,13 +333,14 @@ def from_problem(prob, stream=None, pool_capacity: Optional[int] = None, sort_in
     return ctx
 
 
-def from_batch(probs, stream=None, pool_capacity: Optional[int] = None, sort_interval: int = 0) -> Context:
+def from_batch(probs, stream=None, pool_capacity: Optional[int] = None, sort_interval: int = 0,
+               extra_flags: int = 0) -> Context:
     """Build a batched context from a list of workloads.Problem (same dim, c, a, eps, dt)."""
     p0 = probs[0]
     cap = pool_capacity or sum(p.pool_cap for p in probs)
     P = make_params(c=p0.c, a=p0.a, eps=p0.eps, dt=p0.dt, nu_power=p0.nu_power, n_cap=p0.n_cap,
-                    pool_capacity=cap, si_max_iters=p0.si_max_iters, si_tol=p0.si_tol, flags=p0.flags,
-                    sort_interval=sort_interval)
+                    pool_capacity=cap, si_max_iters=p0.si_max_iters, si_tol=p0.si_tol,
+                    flags=p0.flags | extra_flags, sort_interval=sort_interval)
     ctx = Context(P, stream)
     keep = []
     insts = []

@@ -242,3 +242,81 @@ def test_batch_full_size_sampled_instances():
         s = oracle.Sim(probs[k])
         s.step(nsteps)
         compare_state(ctx, s, probs[k], inst=k, what=f"instance {k}")
+
+
+# ------------------------------------------------------------ launch modes
+
+def test_graph_replay_matches_direct_launches():
+    """A step replayed from its captured HIP graph gives the results of launching
+    its kernels one by one (runs across pool sorts and buffer parities)."""
+    p = W.c1_marshak_like()
+    a = ugkwp.from_problem(p, extra_flags=ugkwp.FLAG_GRAPH)
+    b = ugkwp.from_problem(p)
+    for n in range(40):
+        a.step(1)
+        b.step(1)
+    ra, Ta, pa = a.get_fields()
+    rb, Tb, pb = b.get_fields()
+    # tallies are summed with floating-point atomics, whose order is not fixed
+    assert relerr(ra, rb) <= 1e-12 and relerr(Ta, Tb) <= 1e-12 and relerr(pa, pb) <= 1e-12
+    assert a.get_counters() == b.get_counters()
+    assert a.get_diag()["n_alive_out"] == b.get_diag()["n_alive_out"]
+
+
+def test_batched_matches_separate_contexts():
+    """Instances advanced together in one batched context give what they give
+    in contexts of their own (integers exactly, floats to 1e-12)."""
+    probs = []
+    rng = np.random.default_rng(21)
+    for k, (nx, G) in enumerate([(30, 8), (77, 16), (12, 33)]):
+        kl, kr = 10 ** rng.uniform(-2, 3, 2)
+        xj = rng.uniform(0.2, 0.8)
+        probs.append(W.slab(nx, G, lambda x, kl=kl, kr=kr, xj=xj: np.where(x < xj, kl, kr), dt=1e-3,
+                            steps=0, w_ref=3e-5, seed=300 + k, pool_cap=1 << 18, name=f"sep{k}"))
+    say("[batch vs separate]", len(probs))
+    bat = ugkwp.from_batch(probs)
+    sep = [ugkwp.from_problem(p) for p in probs]
+    bat.step(12)
+    for c in sep:
+        c.step(12)
+    for k, (p, c) in enumerate(zip(probs, sep)):
+        rb, Tb, pb = bat.get_fields(k)
+        rs, Ts, ps = c.get_fields(0)
+        assert relerr(rb, rs) <= 1e-12 and relerr(Tb, Ts) <= 1e-12 and relerr(pb, ps) <= 1e-12
+        tb, ts = bat.get_tallies(k), c.get_tallies(0)
+        assert np.array_equal(tb["nbirth"], ts["nbirth"])
+        assert bat.get_counters(k) == c.get_counters(0)
+
+
+def test_autotune_keeps_results():
+    """The autotuner changes only the push's launch shape: the last step's tallies
+    and counters are restored, and later steps agree with an untuned run."""
+    p = W.c2_two_material(nx=240, G=24, w_ref=2e-5, pool_cap=1 << 21)
+    a = ugkwp.from_problem(p)
+    b = ugkwp.from_problem(p)
+    a.step(10)
+    b.step(10)
+    before = a.get_tallies()
+    cnt = a.get_counters()
+    r = a.autotune()
+    say("[autotune]", r)
+    assert r["candidates"] >= 3 and r["blocks"] >= 1 and r["ppt"] in (1, 2, 4, 8)
+    assert r["us_best"] <= r["us_default"]
+    after = a.get_tallies()
+    for k in ("fx", "dep", "surv", "nbirth", "wnew", "Q"):
+        assert np.array_equal(before[k], after[k]), k
+    assert a.get_counters() == cnt
+    a.step(10)
+    b.step(10)
+    ra, Ta, pa = a.get_fields()
+    rb, Tb, pb = b.get_fields()
+    assert relerr(ra, rb) <= 1e-12 and relerr(Ta, Tb) <= 1e-12 and relerr(pa, pb) <= 1e-12
+    assert a.get_counters() == b.get_counters()
+    assert a.pool_size() == b.pool_size()
+
+
+def test_autotune_needs_particles():
+    a = ugkwp.from_problem(W.c1_marshak_like(w_ref=1e300))
+    a.step(2)
+    with pytest.raises(ugkwp.UGKWPError):
+        a.autotune()
