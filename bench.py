@@ -333,45 +333,37 @@ def main():
         ctxs = [ugkwp.from_problem(probs[0], stream=stream.cuda_stream, sort_interval=args.sort_interval,
                                    extra_flags=xf)]
 
-    def one_step():
-        acc = {"n_pushed": 0, "n_alive_out": 0, "sweeps": 0, "ms_push": 0.0, "ms_si": 0.0, "ms_sort": 0.0}
-        for c in ctxs:
-            c.step(1)
-            d = c.get_diag()
-            acc["n_pushed"] += d["n_pushed"]
-            acc["n_alive_out"] += d["n_alive_out"]
-            acc["ms_push"] += d["ms_push"]
-            acc["ms_si"] += d["ms_si"]
-            acc["ms_sort"] += d["ms_sort"]
-            acc["sweeps"] += d["sweeps_sum"]
-        return acc
-
-    for _ in range(spin):
-        one_step()
+    for c in ctxs:
+        c.step(spin)
     tuned = None
     if not args.no_autotune:
         tuned = [c.autotune() for c in ctxs]
-    for _ in range(args.warmup):
-        one_step()
+    for c in ctxs:
+        c.step(args.warmup)
+        c.get_totals(reset=True)
     torch.cuda.synchronize()
 
-    pushes = 0
-    survivors = 0
-    sweeps = 0
-    ms_push = 0.0
-    ms_si = 0.0
-    ms_sort = 0.0
+    # the timed steps: one library call per context (steps run back to back inside it)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        d = one_step()
-        pushes += d["n_pushed"]
-        survivors += d["n_alive_out"]
-        sweeps += d["sweeps"]
-        ms_push += d["ms_push"]
-        ms_si += d["ms_si"]
-        ms_sort += d["ms_sort"]
+    for c in ctxs:
+        c.step(args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    tots = [c.get_totals() for c in ctxs]
+    pushes = sum(t["n_pushed"] for t in tots)
+    survivors = sum(t["n_survived"] for t in tots)
+    sweeps = sum(t["sweeps_sum"] for t in tots)
+    ms_push = sum(t["ms_push"] for t in tots)
+    # phase breakdown: a further stretch of steps with every phase timed (each
+    # phase event costs a few microseconds, so the timed steps above time the push only)
+    nph = min(args.steps, 50)
+    for c in ctxs:
+        c.set_phase_times(True)
+        c.get_totals(reset=True)
+        c.step(nph)
+    ptot = [c.get_totals() for c in ctxs]
+    ph = {k: sum(t[k] for t in ptot) / max(nph, 1) for k in ("ms_sample", "ms_push", "ms_macro", "ms_si", "ms_sort")}
+    ph_sweeps = sum(t["sweeps_sum"] for t in ptot)
     # cell-group updates: every instance's cell-groups times its own sweep count
     cg_per_inst = [p.ncell * p.G for p in probs]
     mean_cg = ncg / len(probs)
@@ -407,12 +399,14 @@ def main():
                                   f"({tuned[0]['us_best']:.1f} vs {tuned[0]['us_default']:.1f} us default)"
                                   + (f", per context ({len(tuned)})" if len(tuned) > 1 else ""))},
         "cell_group_updates_per_s": mean_cg * sweeps / elapsed,
-        "cell_group_updates_per_s_si_only": mean_cg * sweeps / (ms_si * 1e-3) if ms_si > 0 else None,
+        "cell_group_updates_per_s_si_only": (mean_cg * ph_sweeps / (ph["ms_si"] * nph * 1e-3)
+                                             if ph["ms_si"] > 0 else None),
         "push_kernel_pushes_per_s": pushes / (ms_push * 1e-3),
         "push_kernel_avg_us": ms_push * 1e3 / max(args.steps, 1),
         "sweeps_per_step": sweeps / max(args.steps, 1) / len(probs),
-        "ms_per_step_phases": {"push": ms_push / max(args.steps, 1), "si": ms_si / max(args.steps, 1),
-                               "sort": ms_sort / max(args.steps, 1)},
+        "ms_per_step_phases": {"sample": ph["ms_sample"], "push": ph["ms_push"], "macro": ph["ms_macro"],
+                               "si": ph["ms_si"], "sort": ph["ms_sort"],
+                               "from": f"{nph} further steps with every phase timed"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (measured bytes per push x pushes per launch)",

@@ -58,10 +58,13 @@ enum { UGKWP_SIDE_XLO = 0, UGKWP_SIDE_XHI = 1, UGKWP_SIDE_YLO = 2, UGKWP_SIDE_YH
 enum {
     UGKWP_FLAG_GROUP_SIGMA = 1,  /* particle flights use the Simpson group opacity
                                     instead of kappa * nu_k^-p (Remark 2)        */
-    UGKWP_FLAG_GRAPH = 2         /* replay the launches before the push and the
+    UGKWP_FLAG_GRAPH = 2,        /* replay the launches before the push and the
                                     source-iteration sweeps from captured HIP
                                     graphs (one per launch configuration) instead
                                     of launching each kernel; same results        */
+    UGKWP_FLAG_PHASE_TIMES = 4   /* time every phase of a step with HIP events (the
+                                    diag's ms_sample, ms_macro, ms_si, ms_sort);
+                                    otherwise only the push is timed              */
 };
 
 typedef struct ugkwp_ctx ugkwp_ctx;
@@ -115,11 +118,23 @@ typedef struct {
     /* GPU time of the phases of the step, in ms, from HIP events on the context
      * stream: tally clears + count + scan + sample, the push kernel alone (events
      * recorded just before and after its launch, so the interval also holds its
-     * dispatch, a few microseconds), wave flux + source set-up, the
-     * source iteration (incl. any host convergence poll), and the counting sort
-     * that keeps the pool ordered by (cell, group). */
+     * dispatch, a few microseconds), wave flux + source set-up, the source
+     * iteration, and the counting sort that keeps the pool ordered by (cell,
+     * group).  All but ms_push are 0 unless the context was created with
+     * UGKWP_FLAG_PHASE_TIMES (each event adds a few microseconds to a step). */
     double ms_sample, ms_push, ms_macro, ms_si, ms_sort;
 } ugkwp_diag;
+
+/* Running sums over the committed steps since the last reset, so that a caller
+ * can time many steps in one ugkwp_step call. */
+typedef struct {
+    int64_t steps;
+    int64_t n_pushed;        /* particles entering the push, summed over steps     */
+    int64_t n_survived;      /* survivors, summed over steps                       */
+    int64_t sweeps_max;      /* sum of per-step largest sweep counts               */
+    int64_t sweeps_sum;      /* sum over steps and instances of sweep counts       */
+    double ms_sample, ms_push, ms_macro, ms_si, ms_sort;   /* as in ugkwp_diag    */
+} ugkwp_totals;
 
 /* ---- context ---- */
 
@@ -170,6 +185,11 @@ int ugkwp_get_fields(ugkwp_ctx* ctx, int inst, double* rho, double* T, double* r
 int ugkwp_get_tallies(ugkwp_ctx* ctx, int inst, double* fx, double* fy, double* dep,
                       double* surv, int64_t* nbirth, double* wnew, double* Q);
 int ugkwp_get_diag(ugkwp_ctx* ctx, ugkwp_diag* d);
+/* Copy the running sums to *t (may be NULL); reset them to zero if reset != 0. */
+int ugkwp_get_totals(ugkwp_ctx* ctx, ugkwp_totals* t, int reset);
+/* Turn the timing of every phase (UGKWP_FLAG_PHASE_TIMES) on or off for the
+ * following steps. */
+int ugkwp_set_phase_times(ugkwp_ctx* ctx, int on);
 /* Birth counter and step index of instance `inst`. */
 int ugkwp_get_counters(ugkwp_ctx* ctx, int inst, uint64_t* birth_counter, int* step);
 

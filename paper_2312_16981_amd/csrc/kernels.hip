@@ -171,32 +171,55 @@ __global__ void k_init_rho(Dev D, Consts K, const double* Tr0)
 // ---------------------------------------------------------------------------
 // A1: wave split and particle counts
 
-__global__ void k_count(Dev D, Consts K)
+// Also clears the tallies and step counters the push and the commit add to
+// (grid-stride over the flat arrays), and, when part is given, writes the
+// per-block sum of N for the scan that follows.
+constexpr int COUNT_THREADS = 256;
+
+__global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroList Z, int64_t* part)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= K.n_cg) return;
-    const Slot s = decode_slot(D, K, j);
-    if (!s.active) {
-        D.nb[j] = 0;
-        D.rhoh[j] = 0.0;
-        D.wnew[j] = 0.0;
-        return;
+    const int64_t j = (int64_t)blockIdx.x * COUNT_THREADS + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * COUNT_THREADS;
+    for (int r = 0; r < Z.n; ++r) {
+        uint64_t* p = (uint64_t*)Z.ptr[r];
+        for (int64_t q = j; q < Z.words[r]; q += stride) p[q] = 0ull;
     }
-    const Inst& I = D.inst[s.inst];
-    const double rh = D.rho[j] - D.rhop[j];
-    D.rhoh[j] = rh;
-    const double eov = D.es[j] * rh;
-    const double E = eov * I.V;
     int N = 0;
-    if (E > 0.0) {
-        const double q = eov / I.w_ref;
-        N = (q >= (double)K.n_cap) ? (int)K.n_cap : (int)floor(q);
+    if (j < K.n_cg) {
+        const Slot s = decode_slot(D, K, j);
+        if (!s.active) {
+            D.nb[j] = 0;
+            D.rhoh[j] = 0.0;
+            D.wnew[j] = 0.0;
+        } else {
+            const Inst& I = D.inst[s.inst];
+            const double rh = D.rho[j] - D.rhop[j];
+            D.rhoh[j] = rh;
+            const double eov = D.es[j] * rh;
+            const double E = eov * I.V;
+            if (E > 0.0) {
+                const double q = eov / I.w_ref;
+                N = (q >= (double)K.n_cap) ? (int)K.n_cap : (int)floor(q);
+            }
+            D.nb[j] = N;
+            D.wnew[j] = N >= 1 ? E / (double)N : 0.0;
+            if (N >= 1)
+                D.beta[j] = freq_slope(D.nu[I.edge_off + s.g], D.nu[I.edge_off + s.g + 1],
+                                       D.T[I.cell_off + s.lcell]);
+        }
     }
-    D.nb[j] = N;
-    D.wnew[j] = N >= 1 ? E / (double)N : 0.0;
-    if (N >= 1)
-        D.beta[j] = freq_slope(D.nu[I.edge_off + s.g], D.nu[I.edge_off + s.g + 1],
-                               D.T[I.cell_off + s.lcell]);
+    if (part) {
+        __shared__ int64_t wsum[COUNT_THREADS / WAVE];
+        int64_t v = N;
+        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, WAVE);
+        if ((threadIdx.x & (WAVE - 1)) == 0) wsum[threadIdx.x / WAVE] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t t = 0;
+            for (int w = 0; w < COUNT_THREADS / WAVE; ++w) t += wsum[w];
+            part[blockIdx.x] = t;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -252,6 +275,53 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(int64_t* part, int64_
         carry += tot;
     }
     if (threadIdx.x == 0) *total = carry;
+}
+
+// Exclusive scan of in[0..n) (one item per thread, COUNT_THREADS per block) from
+// the per-block sums part[0..nblk) written by k_count: every block sums the
+// partials before it itself (nblk is small), block 0 also writes the total.
+__global__ __launch_bounds__(COUNT_THREADS) void k_scan_small(const int32_t* in, int64_t n, const int64_t* part,
+                                                              int nblk, int64_t* out, int64_t* total)
+{
+    __shared__ int64_t red[COUNT_THREADS / WAVE][2];
+    int64_t before = 0, all = 0;
+    for (int b = threadIdx.x; b < nblk; b += COUNT_THREADS) {
+        const int64_t v = part[b];
+        all += v;
+        if (b < (int)blockIdx.x) before += v;
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+        before += __shfl_xor(before, m, WAVE);
+        all += __shfl_xor(all, m, WAVE);
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        red[threadIdx.x / WAVE][0] = before;
+        red[threadIdx.x / WAVE][1] = all;
+    }
+    __syncthreads();
+    int64_t base = 0, tot = 0;
+    for (int w = 0; w < COUNT_THREADS / WAVE; ++w) {
+        base += red[w][0];
+        tot += red[w][1];
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) *total = tot;
+    const int64_t i = (int64_t)blockIdx.x * COUNT_THREADS + threadIdx.x;
+    const int64_t v = i < n ? in[i] : 0;
+    // block-wide exclusive scan of one item per thread
+    __shared__ int64_t wsum[COUNT_THREADS / WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    int64_t inc = v;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const int64_t o = __shfl_up(inc, d, WAVE);
+        if (lane >= d) inc += o;
+    }
+    if (lane == WAVE - 1) wsum[wid] = inc;
+    __syncthreads();
+    int64_t woff = 0;
+    for (int w = 0; w < wid; ++w) woff += wsum[w];
+    if (i < n) out[i] = base + woff + inc - v;
 }
 
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(const int32_t* in, int64_t n, const int64_t* part,
@@ -585,7 +655,7 @@ __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Cons
         }
         __syncthreads();
     }
-    // survivors of this block (summed by k_pool_count)
+    // survivors of this block (summed in k_macro_setup)
     for (int m = 32; m >= 1; m >>= 1) nsurv += __shfl_xor(nsurv, m, WAVE);
     if (lane == 0) bsurv[wid] = nsurv;
     __syncthreads();
@@ -593,22 +663,6 @@ __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Cons
         unsigned long long t = 0;
         for (int k = 0; k < PUSH_THREADS / WAVE; ++k) t += bsurv[k];
         D.blk_surv[blockIdx.x] = t;
-    }
-}
-
-// Survivor total of the push from the per-block counts.
-__global__ void k_pool_count(Dev D, int nblk)
-{
-    __shared__ unsigned long long part[256 / WAVE];
-    unsigned long long t = 0;
-    for (int b = threadIdx.x; b < nblk; b += 256) t += D.blk_surv[b];
-    for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, WAVE);
-    if ((threadIdx.x & (WAVE - 1)) == 0) part[threadIdx.x / WAVE] = t;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long s = 0;
-        for (int k = 0; k < 256 / WAVE; ++k) s += part[k];
-        D.counters[CNT_SURV] = (D.counters[CNT_ERR] & ERR_POOL) ? 0ull : s;
     }
 }
 
@@ -787,8 +841,22 @@ __device__ inline void wave_source(const Dev& D, const Consts& K, int64_t j, con
 // Wave flux and Q (A4) fused with the set-up of the source iteration:
 // phi^0 = phi(T^n), rho^0 = rho^n, T^0 = T^n, residual slot 0 and the
 // per-instance convergence state cleared.
-__global__ void k_macro_setup(Dev D, Consts K)
+__global__ void k_macro_setup(Dev D, Consts K, int push_blocks)
 {
+    if (blockIdx.x == 0) {
+        // survivors of the push: sum of its per-block counts
+        __shared__ unsigned long long part[256 / WAVE];
+        unsigned long long t = 0;
+        for (int b = threadIdx.x; b < push_blocks; b += blockDim.x) t += D.blk_surv[b];
+        for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, WAVE);
+        if ((threadIdx.x & (WAVE - 1)) == 0) part[threadIdx.x / WAVE] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long sum = 0;
+            for (int k = 0; k < (int)blockDim.x / WAVE; ++k) sum += part[k];
+            D.counters[CNT_SURV] = (D.counters[CNT_ERR] & ERR_POOL) ? 0ull : sum;
+        }
+    }
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= K.n_cg) return;
     const Slot s = decode_slot(D, K, j);
@@ -1089,21 +1157,6 @@ __global__ void k_diag_reduce(Dev D, Consts K)
     }
 }
 
-// ---------------------------------------------------------------------------
-// per-step clearing of tallies and counters in one launch
-
-__global__ void k_zero(ZeroList Z)
-{
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int r = 0; r < Z.n; ++r) {
-        uint64_t* p = (uint64_t*)Z.ptr[r];
-        for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < Z.words[r]; j += stride) p[j] = 0ull;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// element-wise entry points
-
 __global__ void k_eval_phi(int n, const double* T, int G, const double* nu, double a, double c, double* out)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1169,9 +1222,23 @@ void launch_init_rho(const Dev& D, const Consts& K, const double* Tr0, hipStream
     k_init_rho<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K, Tr0);
 }
 
-void launch_count(const Dev& D, const Consts& K, hipStream_t st)
+// Tally clears, particle counts and their exclusive scan (births per slot ->
+// first birth slot, total births): two launches while the per-block sums of
+// the count fit one scan pass, four otherwise.
+constexpr unsigned SMALL_SCAN_BLOCKS = 1024;
+
+int64_t count_partials_size() { return SMALL_SCAN_BLOCKS; }
+
+void launch_count_scan(const Dev& D, const Consts& K, const ZeroList& Z, int64_t* part, hipStream_t st)
 {
-    k_count<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K);
+    const unsigned nb = blocks(K.n_cg, COUNT_THREADS);
+    if (nb <= SMALL_SCAN_BLOCKS) {
+        k_count<<<nb, COUNT_THREADS, 0, st>>>(D, K, Z, part);
+        k_scan_small<<<nb, COUNT_THREADS, 0, st>>>(D.nb, K.n_cg, part, (int)nb, D.boff, D.n_births_total);
+    } else {
+        k_count<<<nb, COUNT_THREADS, 0, st>>>(D, K, Z, nullptr);
+        launch_scan(D.nb, K.n_cg, part, D.boff, D.n_births_total, st);
+    }
 }
 
 int64_t scan_partials_size(int64_t n) { return (n + SCAN_CHUNK - 1) / SCAN_CHUNK; }
@@ -1182,11 +1249,6 @@ void launch_scan(const int32_t* in, int64_t n, int64_t* part, int64_t* out, int6
     k_scan_partials<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, n, part);
     k_scan_top<<<1, SCAN_THREADS, 0, st>>>(part, nb, total);
     k_scan_final<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, n, part, out);
-}
-
-void launch_zero(const ZeroList& Z, hipStream_t st)
-{
-    k_zero<<<1024, 256, 0, st>>>(Z);
 }
 
 void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, hipStream_t st)
@@ -1272,11 +1334,6 @@ void launch_push(int dim, const Dev& D, const Consts& K, const Pool& In, const P
     }
 }
 
-void launch_pool_count(const Dev& D, const PushShape& sh, hipStream_t st)
-{
-    k_pool_count<<<1, 256, 0, st>>>(D, sh.blocks);
-}
-
 void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& In, const Pool& Out, hipStream_t st)
 {
     const bool single = K.n_inst == 1;
@@ -1290,9 +1347,9 @@ void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& In,
     }
 }
 
-void launch_macro_setup(const Dev& D, const Consts& K, hipStream_t st)
+void launch_macro_setup(const Dev& D, const Consts& K, const PushShape& sh, hipStream_t st)
 {
-    k_macro_setup<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K);
+    k_macro_setup<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K, sh.blocks);
 }
 
 void launch_si_sweep(const Dev& D, const Consts& K, int k, hipStream_t st)

@@ -5,7 +5,7 @@
 
 namespace ugk {
 
-// Up to 8 device ranges of 64-bit words cleared by one launch.
+// Up to 8 device ranges of 64-bit words cleared at the start of a step.
 struct ZeroList {
     int n;
     void* ptr[8];
@@ -18,8 +18,9 @@ void launch_tables(const Dev& D, const Consts& K, hipStream_t st);
 void launch_face_D(const Dev& D, const Consts& K, int inst, int axis, int64_t nslots, hipStream_t st);
 void launch_ghost_phi(const Dev& D, const Consts& K, double* phib, hipStream_t st);
 void launch_init_rho(const Dev& D, const Consts& K, const double* Tr0, hipStream_t st);
-void launch_zero(const ZeroList& Z, hipStream_t st);
-void launch_count(const Dev& D, const Consts& K, hipStream_t st);
+// clears Z, counts particles per slot and scans the counts into birth offsets
+void launch_count_scan(const Dev& D, const Consts& K, const ZeroList& Z, int64_t* part, hipStream_t st);
+int64_t count_partials_size();    // entries of `part` the small-context path needs
 int64_t scan_partials_size(int64_t n);
 void launch_scan(const int32_t* in, int64_t n, int64_t* part, int64_t* out, int64_t* total, hipStream_t st);
 void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, hipStream_t st);
@@ -33,9 +34,9 @@ PushShape push_default_shape(int dim, const Consts& K);   // occupancy-filled gr
 int push_blocks_per_cu(int dim, const Consts& K);         // resident blocks per CU (occupancy)
 void launch_push(int dim, const Dev& D, const Consts& K, const Pool& A, const Pool& B, const PushShape& sh,
                  hipStream_t st);
-void launch_pool_count(const Dev& D, const PushShape& sh, hipStream_t st);
 void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& B, const Pool& A, hipStream_t st);
-void launch_macro_setup(const Dev& D, const Consts& K, hipStream_t st);
+// wave flux, Q and the start of the source iteration; also sums the push's survivors
+void launch_macro_setup(const Dev& D, const Consts& K, const PushShape& sh, hipStream_t st);
 // sweep k of the source iteration followed by its convergence decision
 void launch_si_sweep(const Dev& D, const Consts& K, int k, hipStream_t st);
 void launch_finish(const Dev& D, const Consts& K, hipStream_t st);

@@ -192,6 +192,7 @@ struct ugkwp_ctx {
     int last_sweeps = 4;
     int sort_interval = 8;
     ugkwp_diag diag{};
+    ugkwp_totals tot{};                // running sums since the last reset
 
     // launch shape of the push (default: occupancy-filled persistent grid, 4
     // particles per thread; ugkwp_autotune may change it)
@@ -200,6 +201,7 @@ struct ugkwp_ctx {
     // each step's launch sequence captured as a HIP graph, one per launch
     // configuration (pool buffer parities, rho/T parity, sort, speculative sweeps)
     bool use_graph = false;
+    bool phase_times = false;          // time every phase of a step (else the push only)
     hipStream_t cap_st = nullptr;
     std::map<uint32_t, hipGraphExec_t> graphs;
     const double* rho_buf0 = nullptr;
@@ -440,7 +442,7 @@ struct ugkwp_ctx {
         d.diag = (double*)((char*)d_status + off_diag);
         d.res = dalloc<Resid>(owned, (size_t)n_inst * RES_SLOTS * RES_SUB);
         d.diag_sub = dalloc<double>(owned, (size_t)n_inst * DIAG_SUB * 8);
-        n_part = scan_partials_size(n_cg);
+        n_part = std::max<int64_t>(scan_partials_size(n_cg), count_partials_size());
         part = dalloc<int64_t>(owned, (size_t)n_part + 1);
         HIPCHK(hipMemsetAsync(d.ist, 0, sizeof(InstState) * n_inst, st));
         HIPCHK(hipMemsetAsync((void*)d.boff, 0, sizeof(int64_t) * (ncg + 1), st));
@@ -572,10 +574,10 @@ struct ugkwp_ctx {
     {
         launch_finish(D, K, st);
         if (do_sort) {
-            HIPCHK(hipEventRecord(ev[5], st));
+            if (phase_times) HIPCHK(hipEventRecord(ev[5], st));
             launch_scan((const int32_t*)D.scount, K.n_cg, part, D.soff, D.n_births_total + 1, st);
             launch_sort_scatter(dim, D, K, view(1 - cur_mv, cur_st), view(cur_mv, 1 - cur_st), st);
-            HIPCHK(hipEventRecord(ev[6], st));
+            if (phase_times) HIPCHK(hipEventRecord(ev[6], st));
         }
         HIPCHK(hipMemcpyAsync(h_status, d_status, status_bytes, hipMemcpyDeviceToHost, st));
     }
@@ -594,9 +596,7 @@ struct ugkwp_ctx {
         add(D.scount, K.n_cg / 2);
         add(D.diag_sub, (int64_t)DIAG_SUB * 8 * n_inst);
         add(D.counters, 4);                 // CNT_SURV .. CNT_CONV; slot and live counts persist
-        launch_zero(z, st);
-        launch_count(D, K, st);
-        launch_scan(D.nb, K.n_cg, part, D.boff, D.n_births_total, st);
+        launch_count_scan(D, K, z, part, st);
         launch_sample(dim, D, K, view(cur_mv, cur_st), st);
     }
 
@@ -664,17 +664,16 @@ struct ugkwp_ctx {
         // plus one covers a step that needs one sweep more without a host round trip
         const int first = std::min(kmax, last_sweeps + 1);
         int k = first;
-        HIPCHK(hipEventRecord(ev[0], st));
+        if (phase_times) HIPCHK(hipEventRecord(ev[0], st));
         launch_group(0x100000u | (uint32_t)cur_mv | ((uint32_t)cur_st << 1) | (parity() << 2),
                      [&] { enqueue_pre_push(); });
         HIPCHK(hipEventRecord(ev[1], st));
         launch_push(dim, D, K, view(cur_mv, cur_st), moving(1 - cur_mv), push_shape, st);
         HIPCHK(hipEventRecord(ev[2], st));
-        launch_pool_count(D, push_shape, st);
-        launch_macro_setup(D, K, st);
-        HIPCHK(hipEventRecord(ev[3], st));
+        launch_macro_setup(D, K, push_shape, st);
+        if (phase_times) HIPCHK(hipEventRecord(ev[3], st));
         launch_group(0x200000u | (uint32_t)first | (parity() << 16), [&] { enqueue_sweeps(0, first); });
-        HIPCHK(hipEventRecord(ev[4], st));
+        if (phase_times) HIPCHK(hipEventRecord(ev[4], st));
         enqueue_finish(do_sort);
         HIPCHK(hipStreamSynchronize(st));
         for (;;) {
@@ -715,13 +714,25 @@ struct ugkwp_ctx {
         dg.sweeps_sum = ssum;
         dg.residual = dg.e_end - dg.e_start - (dg.inflow_wave + dg.inflow_eq - dg.exit_particles + dg.injection);
         float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1])); dg.ms_sample = ms;
         HIPCHK(hipEventElapsedTime(&ms, ev[1], ev[2])); dg.ms_push = ms;
-        HIPCHK(hipEventElapsedTime(&ms, ev[2], ev[3])); dg.ms_macro = ms;
-        HIPCHK(hipEventElapsedTime(&ms, ev[3], ev[4])); dg.ms_si = ms;
+        if (phase_times) {
+            HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1])); dg.ms_sample = ms;
+            HIPCHK(hipEventElapsedTime(&ms, ev[2], ev[3])); dg.ms_macro = ms;
+            HIPCHK(hipEventElapsedTime(&ms, ev[3], ev[4])); dg.ms_si = ms;
+        }
         dg.ms_sort = 0.0;
-        if (do_sort) { HIPCHK(hipEventElapsedTime(&ms, ev[5], ev[6])); dg.ms_sort = ms; }
+        if (do_sort && phase_times) { HIPCHK(hipEventElapsedTime(&ms, ev[5], ev[6])); dg.ms_sort = ms; }
         diag = dg;
+        tot.steps += 1;
+        tot.n_pushed += dg.n_pushed;
+        tot.n_survived += dg.n_alive_out;
+        tot.sweeps_max += dg.sweeps_max;
+        tot.sweeps_sum += dg.sweeps_sum;
+        tot.ms_sample += dg.ms_sample;
+        tot.ms_push += dg.ms_push;
+        tot.ms_macro += dg.ms_macro;
+        tot.ms_si += dg.ms_si;
+        tot.ms_sort += dg.ms_sort;
         last_sweeps = smax;
 
         std::swap(D.rho, D.rho_new);
@@ -1033,7 +1044,9 @@ int ugkwp_create(ugkwp_ctx** out, const ugkwp_params* p, void* hip_stream)
         }
         c->sort_interval = p->sort_interval > 0 ? p->sort_interval : 16;
         c->use_graph = (p->flags & UGKWP_FLAG_GRAPH) != 0;
-        for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+        c->phase_times = (p->flags & UGKWP_FLAG_PHASE_TIMES) != 0;
+        // timing-only events: no system-scope fence (cache write-back) when recorded
+        for (auto& e : c->ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     });
     if (rc) { delete c; return rc; }
     *out = c;
@@ -1225,6 +1238,21 @@ int ugkwp_get_diag(ugkwp_ctx* ctx, ugkwp_diag* d)
 {
     if (!ctx || !d) return UGKWP_EINVAL;
     *d = ctx->diag;
+    return UGKWP_OK;
+}
+
+int ugkwp_set_phase_times(ugkwp_ctx* ctx, int on)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    ctx->phase_times = on != 0;
+    return UGKWP_OK;
+}
+
+int ugkwp_get_totals(ugkwp_ctx* ctx, ugkwp_totals* t, int reset)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    if (t) *t = ctx->tot;
+    if (reset) ctx->tot = ugkwp_totals{};
     return UGKWP_OK;
 }
 

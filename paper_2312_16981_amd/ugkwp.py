@@ -19,6 +19,7 @@ OK, EINVAL, ENOMEM, EPOOL, ENOCONV, ENONFINITE, EHIP = 0, -1, -2, -3, -4, -5, -6
 BC_VACUUM, BC_PLANCK, BC_REFLECT = 0, 1, 2
 FLAG_GROUP_SIGMA = 1
 FLAG_GRAPH = 2
+FLAG_PHASE_TIMES = 4
 PURPOSE_BIRTH, PURPOSE_FLIGHT = 1, 2
 
 EXPORTED = [
@@ -27,7 +28,7 @@ EXPORTED = [
     "ugkwp_get_fields", "ugkwp_get_tallies", "ugkwp_get_diag", "ugkwp_get_counters",
     "ugkwp_pool_size", "ugkwp_get_pool", "ugkwp_set_pool", "ugkwp_eval_phi", "ugkwp_eval_coef",
     "ugkwp_eval_uniform", "ugkwp_eval_sample_nu", "ugkwp_record", "ugkwp_recorded_steps",
-    "ugkwp_adjoint", "ugkwp_autotune",
+    "ugkwp_adjoint", "ugkwp_autotune", "ugkwp_get_totals", "ugkwp_set_phase_times",
 ]
 
 _d = C.c_double
@@ -57,6 +58,15 @@ class Instance(C.Structure):
 class AdjointStats(C.Structure):
     _fields_ = [("steps", C.c_int), ("sweeps_launched", C.c_int), ("sweeps_max", C.c_int), ("ms", _d),
                 ("ms_sweeps", _d), ("cell_group_updates", C.c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Totals(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("n_pushed", C.c_int64), ("n_survived", C.c_int64),
+                ("sweeps_max", C.c_int64), ("sweeps_sum", C.c_int64), ("ms_sample", _d), ("ms_push", _d),
+                ("ms_macro", _d), ("ms_si", _d), ("ms_sort", _d)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -125,6 +135,8 @@ def load():
                                  C.c_uint64, _pd]
     L.ugkwp_record.argtypes = [vp, C.c_int]
     L.ugkwp_autotune.argtypes = [vp, C.POINTER(TuneResult)]
+    L.ugkwp_get_totals.argtypes = [vp, C.POINTER(Totals), C.c_int]
+    L.ugkwp_set_phase_times.argtypes = [vp, C.c_int]
     L.ugkwp_recorded_steps.argtypes = [vp]
     L.ugkwp_adjoint.argtypes = [vp, _pd, _pd, C.c_int, C.POINTER(AdjointStats)]
     L.ugkwp_eval_phi.argtypes = [C.c_int, _pd, C.c_int, _pd, _d, _d, _pd]
@@ -276,6 +288,15 @@ class Context:
         d = Diag()
         self._chk(load().ugkwp_get_diag(self.h, C.byref(d)), "get_diag")
         return d.as_dict()
+
+    def get_totals(self, reset=False):
+        """Running sums over committed steps since the last reset (see ugkwp.h)."""
+        t = Totals()
+        self._chk(load().ugkwp_get_totals(self.h, C.byref(t), 1 if reset else 0), "get_totals")
+        return t.as_dict()
+
+    def set_phase_times(self, on=True):
+        self._chk(load().ugkwp_set_phase_times(self.h, 1 if on else 0), "set_phase_times")
 
     def get_counters(self, inst=0):
         b = C.c_uint64()
