@@ -892,15 +892,41 @@ constexpr int SI_THREADS = 256;
 // Sweep k: rho^{k+1}, T^{k+1} and phi^{k+1} from phi^k for every instance whose
 // iteration is still running.  The residual maxima of the sweep go to sub-slots
 // of the instance (spread over 64 addresses by block); k_si_decide reads them.
+// With decide_prev (single-instance contexts), every block first takes the
+// convergence decision of sweep k-1 itself, from the same sub-slots, so no
+// decide launch sits between sweeps; block 0 records it.
+__device__ inline bool si_converged(const Dev& D, const Consts& K, int inst, int k, int lane)
+{
+    const Resid r = D.res[((int64_t)inst * RES_SLOTS + k % RES_SLOTS) * RES_SUB + lane];
+    const double drho = wave_nmax(bitsd(r.drho)), mrho = wave_nmax(bitsd(r.rho));
+    const double dT = wave_nmax(bitsd(r.dT)), mT = wave_nmax(bitsd(r.T));
+    return drho <= K.si_tol * mrho && dT <= K.si_tol * mT;
+}
+
 __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k, const double* phi_in,
-                                                          double* phi_out)
+                                                          double* phi_out, int decide_prev)
 {
     const int64_t j = (int64_t)blockIdx.x * SI_THREADS + threadIdx.x;
     const Slot s = decode_slot(D, K, j);
     const Inst& I = D.inst[s.inst];
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
 
-    const bool run = D.ist[s.inst].conv_sweeps == 0 && j < K.n_cg;
+    bool run = D.ist[s.inst].conv_sweeps == 0 && j < K.n_cg;
+    if (decide_prev) {
+        __shared__ int stop;
+        if (wid == 0) {
+            const bool conv = D.ist[0].conv_sweeps == 0 && si_converged(D, K, 0, k - 1, lane);
+            if (lane == 0) {
+                stop = conv ? 1 : 0;
+                if (conv && blockIdx.x == 0) {
+                    D.ist[0].conv_sweeps = k;
+                    atomicAdd((unsigned long long*)(D.counters + CNT_CONV), 1ull);
+                }
+            }
+        }
+        __syncthreads();
+        run = run && !stop;
+    }
     const int64_t rel = j - I.cg_off;
     if (run && rel >= 0 && rel < RES_SUB) {
         Resid z = {0ull, 0ull, 0ull, 0ull};
@@ -1038,10 +1064,8 @@ __global__ void k_si_decide(Dev D, Consts K, int k)
     const int inst = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
     if (inst >= K.n_inst || D.ist[inst].conv_sweeps != 0) return;
-    const Resid r = D.res[((int64_t)inst * RES_SLOTS + k % RES_SLOTS) * RES_SUB + lane];
-    const double drho = wave_nmax(bitsd(r.drho)), mrho = wave_nmax(bitsd(r.rho));
-    const double dT = wave_nmax(bitsd(r.dT)), mT = wave_nmax(bitsd(r.T));
-    if (lane == 0 && drho <= K.si_tol * mrho && dT <= K.si_tol * mT) {
+    const bool conv = si_converged(D, K, inst, k, lane);
+    if (lane == 0 && conv) {
         D.ist[inst].conv_sweeps = k + 1;
         atomicAdd((unsigned long long*)(D.counters + CNT_CONV), 1ull);
     }
@@ -1352,18 +1376,21 @@ void launch_macro_setup(const Dev& D, const Consts& K, const PushShape& sh, hipS
     k_macro_setup<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K, sh.blocks);
 }
 
-void launch_si_sweep(const Dev& D, const Consts& K, int k, hipStream_t st)
+void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t st)
 {
-    const double* pin = (k & 1) ? D.phi1 : D.phi0;
-    double* pout = (k & 1) ? D.phi0 : D.phi1;
-    k_si_sweep<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, pin, pout);
-    k_si_decide<<<blocks((int64_t)K.n_inst * WAVE, 256), 256, 0, st>>>(D, K, k);
+    const bool fold = K.n_inst == 1;
+    for (int k = k0; k < k1; ++k) {
+        const double* pin = (k & 1) ? D.phi1 : D.phi0;
+        double* pout = (k & 1) ? D.phi0 : D.phi1;
+        k_si_sweep<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, pin, pout, fold && k > k0 ? 1 : 0);
+        if (!fold || k == k1 - 1) k_si_decide<<<blocks((int64_t)K.n_inst * WAVE, 256), 256, 0, st>>>(D, K, k);
+    }
 }
 
-void launch_finish(const Dev& D, const Consts& K, hipStream_t st)
+void launch_finish(const Dev& D, const Consts& K, bool reduce_diag, hipStream_t st)
 {
     k_finish<<<blocks(K.n_cg, DIAG_THREADS), DIAG_THREADS, 0, st>>>(D, K);
-    k_diag_reduce<<<blocks(K.n_inst, 64), 64, 0, st>>>(D, K);
+    if (reduce_diag) k_diag_reduce<<<blocks(K.n_inst, 64), 64, 0, st>>>(D, K);
 }
 
 void launch_eval_phi(int n, const double* T, int G, const double* nu, double a, double c, double* out,

@@ -188,6 +188,8 @@ struct ugkwp_ctx {
     unsigned long long* h_counters = nullptr;
     InstState* h_ist = nullptr;
     double* h_diag = nullptr;
+    double* h_diag_sub = nullptr;      // energy-sum sub-slots, when the host folds them
+    bool host_diag = false;
     hipEvent_t ev[7]{};
     int last_sweeps = 4;
     int sort_interval = 8;
@@ -243,7 +245,7 @@ struct ugkwp_ctx {
         owned.clear();
         if (h_status) (void)hipHostFree(h_status);
         h_status = nullptr;
-        h_total = nullptr; h_counters = nullptr; h_ist = nullptr; h_diag = nullptr;
+        h_total = nullptr; h_counters = nullptr; h_ist = nullptr; h_diag = nullptr; h_diag_sub = nullptr;
         for (auto& e : ev)
             if (e) { (void)hipEventDestroy(e); e = nullptr; }
         if (own_stream && st) (void)hipStreamDestroy(st);
@@ -427,7 +429,11 @@ struct ugkwp_ctx {
         const size_t off_tot = sizeof(unsigned long long) * N_COUNTERS;
         const size_t off_ist = off_tot + 16;
         const size_t off_diag = off_ist + sizeof(InstState) * (size_t)n_inst;
-        status_bytes = off_diag + sizeof(double) * 8 * (size_t)n_inst;
+        const size_t off_sub = off_diag + sizeof(double) * 8 * (size_t)n_inst;
+        // few instances: the energy sums' sub-slots travel with the status and
+        // the host folds them (no reduction launch)
+        host_diag = n_inst <= 16;
+        status_bytes = off_sub + (host_diag ? sizeof(double) * DIAG_SUB * 8 * (size_t)n_inst : 0);
         d_status = dalloc<char>(owned, status_bytes);
         HIPCHK(hipMemsetAsync(d_status, 0, status_bytes, st));
         if (h_status) (void)hipHostFree(h_status);
@@ -441,7 +447,9 @@ struct ugkwp_ctx {
         d.ist = (InstState*)((char*)d_status + off_ist);
         d.diag = (double*)((char*)d_status + off_diag);
         d.res = dalloc<Resid>(owned, (size_t)n_inst * RES_SLOTS * RES_SUB);
-        d.diag_sub = dalloc<double>(owned, (size_t)n_inst * DIAG_SUB * 8);
+        d.diag_sub = host_diag ? (double*)((char*)d_status + off_sub)
+                               : dalloc<double>(owned, (size_t)n_inst * DIAG_SUB * 8);
+        h_diag_sub = host_diag ? (double*)((char*)h_status + off_sub) : nullptr;
         n_part = std::max<int64_t>(scan_partials_size(n_cg), count_partials_size());
         part = dalloc<int64_t>(owned, (size_t)n_part + 1);
         HIPCHK(hipMemsetAsync(d.ist, 0, sizeof(InstState) * n_inst, st));
@@ -572,7 +580,7 @@ struct ugkwp_ctx {
     // once) and more are added only if an instance has not converged.
     void enqueue_finish(bool do_sort)
     {
-        launch_finish(D, K, st);
+        launch_finish(D, K, !host_diag, st);
         if (do_sort) {
             if (phase_times) HIPCHK(hipEventRecord(ev[5], st));
             launch_scan((const int32_t*)D.scount, K.n_cg, part, D.soff, D.n_births_total + 1, st);
@@ -600,10 +608,7 @@ struct ugkwp_ctx {
         launch_sample(dim, D, K, view(cur_mv, cur_st), st);
     }
 
-    void enqueue_sweeps(int k0, int k1)
-    {
-        for (int k = k0; k < k1; ++k) launch_si_sweep(D, K, k, st);
-    }
+    void enqueue_sweeps(int k0, int k1) { launch_si_sweeps(D, K, k0, k1, st); }
 
     // Run `enq` on the context stream: replayed from the HIP graph captured for
     // `key` (captured on first use), or launched directly without graphs.
@@ -686,7 +691,8 @@ struct ugkwp_ctx {
             if (h_counters[CNT_CONV] == (unsigned long long)n_inst) break;
             if (k >= kmax) fail(UGKWP_ENOCONV, "source iteration did not converge in %d sweeps", kmax);
             const int kend = std::min(k + 4, kmax);
-            for (; k < kend; ++k) launch_si_sweep(D, K, k, st);
+            enqueue_sweeps(k, kend);
+            k = kend;
             enqueue_finish(do_sort);
             HIPCHK(hipStreamSynchronize(st));
         }
@@ -702,7 +708,17 @@ struct ugkwp_ctx {
         for (int q = 0; q < n_inst; ++q) {
             smax = std::max(smax, h_ist[q].conv_sweeps);
             ssum += h_ist[q].conv_sweeps;
+            double fold[8];
             const double* g = h_diag + 8 * q;
+            if (host_diag) {
+                // the same order as the device reduction: sub-slot 0, 1, ...
+                for (int c = 0; c < 8; ++c) {
+                    double acc = 0.0;
+                    for (int b = 0; b < DIAG_SUB; ++b) acc += h_diag_sub[((size_t)q * DIAG_SUB + b) * 8 + c];
+                    fold[c] = acc;
+                }
+                g = fold;
+            }
             dg.inflow_wave += g[0];
             dg.inflow_eq += g[1];
             dg.exit_particles += g[2];
