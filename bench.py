@@ -177,19 +177,22 @@ def run_adjoint(args, stream):
 
 def summarize_trace(csv_path, steps, push_kernel="k_push"):
     """Text summary of a rocprofv3 kernel trace of this benchmark restricted to
-    the timed steps: the window opens at the start of the push dispatch that
-    begins the last `steps` steps.  Prints per-kernel calls, total and average
-    duration in that window."""
+    the timed steps: the window runs from the push dispatch that begins the
+    timed steps to the one that begins the phase-timed steps after them
+    (min(steps, 50) of them, the last pushes of the run).  Prints per-kernel
+    calls, total and average duration in that window."""
     import csv
     rows = list(csv.DictReader(open(csv_path)))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
     pushes = [r for r in rows if push_kernel in r["Kernel_Name"]]
-    if len(pushes) < steps:
-        raise SystemExit(f"trace holds {len(pushes)} push dispatches, fewer than {steps} steps")
-    t0 = int(pushes[-steps]["Start_Timestamp"])
+    nph = min(steps, 50)
+    if len(pushes) < steps + nph:
+        raise SystemExit(f"trace holds {len(pushes)} push dispatches, fewer than {steps} + {nph} steps")
+    t0 = int(pushes[-steps - nph]["Start_Timestamp"])
+    t1 = int(pushes[-nph]["Start_Timestamp"])
     stats = {}
     for r in rows:
-        if int(r["Start_Timestamp"]) < t0:
+        if int(r["Start_Timestamp"]) < t0 or int(r["Start_Timestamp"]) >= t1:
             continue
         d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
         e = stats.setdefault(r["Kernel_Name"], [0, 0, 0, 1 << 62])
@@ -198,7 +201,7 @@ def summarize_trace(csv_path, steps, push_kernel="k_push"):
         e[2] = max(e[2], d)
         e[3] = min(e[3], d)
     total = sum(v[1] for v in stats.values())
-    lines = [f"timed window: last {steps} steps ({len(pushes)} push dispatches in the trace)",
+    lines = [f"timed window: {steps} steps before the last {nph} ({len(pushes)} push dispatches in the trace)",
              f"{'kernel':70s} {'calls':>6s} {'total_us':>10s} {'avg_us':>9s} {'min_us':>8s} {'max_us':>8s} {'pct':>6s}"]
     for name, (n, tot, mx, mn) in sorted(stats.items(), key=lambda kv: -kv[1][1]):
         lines.append(f"{name[:70]:70s} {n:6d} {tot / 1e3:10.1f} {tot / n / 1e3:9.2f} {mn / 1e3:8.2f} "

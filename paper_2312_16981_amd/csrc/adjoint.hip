@@ -33,10 +33,12 @@ __device__ inline double temp_weight(const Dev& D, const Consts& K, int cell)
 }
 
 // ---------------------------------------------------------------------------
-// recording (after a committed step: D.T holds T^{n+1})
+// recording, launched behind the step's commit with the step's own buffers:
+// D.T_new holds T^{n+1}
 
 __global__ void k_rec_store(Dev D, Consts K, Adj A, int r)
 {
+    if (!gate_open(D, K, 1)) return;
     const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
     if (j >= K.n_cg) return;
     const Slot s = decode_slot(D, K, j);
@@ -46,7 +48,7 @@ __global__ void k_rec_store(Dev D, Consts K, Adj A, int r)
     A.rSamp[o] = D.nb[j] > 0 ? 1 : 0;
     if (s.cell_ok && s.g == 0) {
         const int cell = D.inst[s.inst].cell_off + s.lcell;
-        A.rT[(int64_t)r * K.ncell + cell] = D.T[cell];
+        A.rT[(int64_t)r * K.ncell + cell] = D.T_new[cell];
     }
 }
 

@@ -47,11 +47,14 @@ struct Consts {
     int64_t n_cap;
     int64_t pool_cap;
     uint32_t flags;
+    uint32_t gate;         // step index a launch belongs to (GATE_OFF: none), see gate_open
     int n_inst;
     int64_t n_cg;          // total (cell, group) slots incl. padding
     int64_t n_fx2;         // x-face tally entries (2 per x-face slot)
     int ncell;             // total cells
 };
+
+constexpr uint32_t GATE_OFF = 0xFFFFFFFFu;
 
 // Residual accumulators of one source-iteration sweep (non-negative doubles as
 // their IEEE bit patterns, so that integer atomicMax orders them; NaN wins).

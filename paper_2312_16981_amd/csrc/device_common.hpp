@@ -6,6 +6,17 @@
 
 namespace ugk {
 
+// The launches of step n carry K.gate = n and may be enqueued behind steps
+// that have not run yet.  A launch from before the step's commit runs only
+// when n steps have committed (after = 0), one from after it only when n + 1
+// have (after = 1).  Behind a step that did not commit, every later step's
+// launches therefore return at once and leave that step's state as its
+// failure left it.  The value read is uniform, so whole grids return together.
+__device__ inline bool gate_open(const Dev& D, const Consts& K, uint32_t after)
+{
+    return K.gate == GATE_OFF || *D.step == K.gate + after;
+}
+
 struct Slot {
     int inst, lcell, g;
     bool cell_ok, active;

@@ -178,6 +178,7 @@ constexpr int COUNT_THREADS = 256;
 
 __global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroList Z, int64_t* part)
 {
+    if (!gate_open(D, K, 0)) return;
     const int64_t j = (int64_t)blockIdx.x * COUNT_THREADS + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * COUNT_THREADS;
     for (int r = 0; r < Z.n; ++r) {
@@ -251,8 +252,12 @@ __device__ inline int64_t block_excl_scan(int64_t v, int64_t* total)
     return woff + inc - v;
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(const int32_t* in, int64_t n, int64_t* part)
+__device__ inline bool scan_open(const ScanGate& q) { return q.expect == GATE_OFF || *q.step == q.expect; }
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(ScanGate q, const int32_t* in, int64_t n,
+                                                                int64_t* part)
 {
+    if (!scan_open(q)) return;
     const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
     int64_t sum = 0;
 #pragma unroll
@@ -263,8 +268,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(const int32_t* i
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(int64_t* part, int64_t nblk, int64_t* total)
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(ScanGate q, int64_t* part, int64_t nblk, int64_t* total)
 {
+    if (!scan_open(q)) return;
     int64_t carry = 0;
     for (int64_t b0 = 0; b0 < nblk; b0 += SCAN_THREADS) {
         const int64_t b = b0 + threadIdx.x;
@@ -280,9 +286,11 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(int64_t* part, int64_
 // Exclusive scan of in[0..n) (one item per thread, COUNT_THREADS per block) from
 // the per-block sums part[0..nblk) written by k_count: every block sums the
 // partials before it itself (nblk is small), block 0 also writes the total.
-__global__ __launch_bounds__(COUNT_THREADS) void k_scan_small(const int32_t* in, int64_t n, const int64_t* part,
-                                                              int nblk, int64_t* out, int64_t* total)
+__global__ __launch_bounds__(COUNT_THREADS) void k_scan_small(ScanGate q, const int32_t* in, int64_t n,
+                                                              const int64_t* part, int nblk, int64_t* out,
+                                                              int64_t* total)
 {
+    if (!scan_open(q)) return;
     __shared__ int64_t red[COUNT_THREADS / WAVE][2];
     int64_t before = 0, all = 0;
     for (int b = threadIdx.x; b < nblk; b += COUNT_THREADS) {
@@ -324,9 +332,10 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_scan_small(const int32_t* in,
     if (i < n) out[i] = base + woff + inc - v;
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(const int32_t* in, int64_t n, const int64_t* part,
-                                                          int64_t* out)
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(ScanGate q, const int32_t* in, int64_t n,
+                                                          const int64_t* part, int64_t* out)
 {
+    if (!scan_open(q)) return;
     const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
     int32_t v[SCAN_ITEMS];
     int64_t sum = 0;
@@ -350,6 +359,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(const int32_t* in, 
 template <int DIM>
 __global__ void k_sample(Dev D, Consts K, Pool P)
 {
+    if (!gate_open(D, K, 0)) return;
     const uint32_t step = *D.step;
     const int64_t n_slots = (int64_t)D.counters[CNT_SLOTS];
     const int64_t total = D.n_births_total[0];
@@ -569,6 +579,7 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTabl
 template <int DIM, bool SINGLE, int SM>
 __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool In, Pool Out, int ppt)
 {
+    if (!gate_open(D, K, 0)) return;
     const uint32_t step = *D.step;
     __shared__ TallyTable T;
     __shared__ unsigned long long bsurv[PUSH_THREADS / WAVE];
@@ -688,7 +699,7 @@ template <int DIM, bool SINGLE>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(Dev D, Consts K, Pool In, Pool Out)
 {
     __shared__ RankTable R;
-    if (!step_committed(D, K)) return;
+    if (!gate_open(D, K, 1) || !step_committed(D, K)) return;
     const int64_t n = (int64_t)D.counters[CNT_PUSHED];
     const int64_t nlive = (int64_t)D.counters[CNT_SURV];
     if (blockIdx.x == 0 && threadIdx.x == 0) D.counters[CNT_SLOTS] = (unsigned long long)nlive;
@@ -843,6 +854,7 @@ __device__ inline void wave_source(const Dev& D, const Consts& K, int64_t j, con
 // per-instance convergence state cleared.
 __global__ void k_macro_setup(Dev D, Consts K, int push_blocks)
 {
+    if (!gate_open(D, K, 0)) return;
     if (blockIdx.x == 0) {
         // survivors of the push: sum of its per-block counts
         __shared__ unsigned long long part[256 / WAVE];
@@ -906,6 +918,7 @@ __device__ inline bool si_converged(const Dev& D, const Consts& K, int inst, int
 __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k, const double* phi_in,
                                                           double* phi_out, int decide_prev)
 {
+    if (!gate_open(D, K, 0)) return;
     const int64_t j = (int64_t)blockIdx.x * SI_THREADS + threadIdx.x;
     const Slot s = decode_slot(D, K, j);
     const Inst& I = D.inst[s.inst];
@@ -1061,6 +1074,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
 // and max|T^{k+1} - T^k| <= si_tol max T^{k+1} (Algorithm 2's stopping test).
 __global__ void k_si_decide(Dev D, Consts K, int k)
 {
+    if (!gate_open(D, K, 0)) return;
     const int inst = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
     if (inst >= K.n_inst || D.ist[inst].conv_sweeps != 0) return;
@@ -1083,6 +1097,9 @@ constexpr int DIAG_THREADS = 256;
 
 __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K)
 {
+    // the commit below advances *D.step while other blocks may still start:
+    // both the step's own value and the next one open this launch
+    if (!gate_open(D, K, 0) && !gate_open(D, K, 1)) return;
     if (!step_committed(D, K)) return;
     const int64_t j = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x;
     const Slot s = decode_slot(D, K, j);
@@ -1172,6 +1189,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K)
 // Fold the energy-sum sub-slots into diag[inst][8].
 __global__ void k_diag_reduce(Dev D, Consts K)
 {
+    if (!gate_open(D, K, 1)) return;
     const int inst = blockIdx.x * blockDim.x + threadIdx.x;
     if (inst >= K.n_inst) return;
     for (int q = 0; q < 8; ++q) {
@@ -1256,23 +1274,30 @@ int64_t count_partials_size() { return SMALL_SCAN_BLOCKS; }
 void launch_count_scan(const Dev& D, const Consts& K, const ZeroList& Z, int64_t* part, hipStream_t st)
 {
     const unsigned nb = blocks(K.n_cg, COUNT_THREADS);
+    const ScanGate q = scan_gate(D, K, 0);
     if (nb <= SMALL_SCAN_BLOCKS) {
         k_count<<<nb, COUNT_THREADS, 0, st>>>(D, K, Z, part);
-        k_scan_small<<<nb, COUNT_THREADS, 0, st>>>(D.nb, K.n_cg, part, (int)nb, D.boff, D.n_births_total);
+        k_scan_small<<<nb, COUNT_THREADS, 0, st>>>(q, D.nb, K.n_cg, part, (int)nb, D.boff, D.n_births_total);
     } else {
         k_count<<<nb, COUNT_THREADS, 0, st>>>(D, K, Z, nullptr);
-        launch_scan(D.nb, K.n_cg, part, D.boff, D.n_births_total, st);
+        launch_scan(q, D.nb, K.n_cg, part, D.boff, D.n_births_total, st);
     }
 }
 
 int64_t scan_partials_size(int64_t n) { return (n + SCAN_CHUNK - 1) / SCAN_CHUNK; }
 
-void launch_scan(const int32_t* in, int64_t n, int64_t* part, int64_t* out, int64_t* total, hipStream_t st)
+ScanGate scan_gate(const Dev& D, const Consts& K, uint32_t after)
+{
+    return ScanGate{D.step, K.gate == GATE_OFF ? GATE_OFF : K.gate + after};
+}
+
+void launch_scan(const ScanGate& q, const int32_t* in, int64_t n, int64_t* part, int64_t* out, int64_t* total,
+                 hipStream_t st)
 {
     const int64_t nb = scan_partials_size(n);
-    k_scan_partials<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, n, part);
-    k_scan_top<<<1, SCAN_THREADS, 0, st>>>(part, nb, total);
-    k_scan_final<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, n, part, out);
+    k_scan_partials<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(q, in, n, part);
+    k_scan_top<<<1, SCAN_THREADS, 0, st>>>(q, part, nb, total);
+    k_scan_final<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(q, in, n, part, out);
 }
 
 void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, hipStream_t st)

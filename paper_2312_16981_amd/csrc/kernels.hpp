@@ -22,7 +22,15 @@ void launch_init_rho(const Dev& D, const Consts& K, const double* Tr0, hipStream
 void launch_count_scan(const Dev& D, const Consts& K, const ZeroList& Z, int64_t* part, hipStream_t st);
 int64_t count_partials_size();    // entries of `part` the small-context path needs
 int64_t scan_partials_size(int64_t n);
-void launch_scan(const int32_t* in, int64_t n, int64_t* part, int64_t* out, int64_t* total, hipStream_t st);
+// Scans of a step's launch sequence return at once when their step's gate is
+// shut (see gate_open); expect = GATE_OFF runs them unconditionally.
+struct ScanGate {
+    const uint32_t* step;
+    uint32_t expect;
+};
+ScanGate scan_gate(const Dev& D, const Consts& K, uint32_t after);
+void launch_scan(const ScanGate& q, const int32_t* in, int64_t n, int64_t* part, int64_t* out, int64_t* total,
+                 hipStream_t st);
 void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, hipStream_t st);
 // Launch shape of the push: persistent blocks and particles per thread.
 struct PushShape {

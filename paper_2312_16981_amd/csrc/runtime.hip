@@ -115,6 +115,7 @@ int ilog2(int p)
 }
 
 constexpr int MAX_PUSH_BLOCKS = 8192;     // per-block survivor counts kept by the push
+constexpr int RUN_AHEAD = 16;             // steps enqueued per host synchronisation
 
 template <class T>
 T* dalloc(std::vector<void*>& owned, size_t n)
@@ -179,19 +180,21 @@ struct ugkwp_ctx {
     double* d_phib = nullptr;
 
     // host staging (pinned)
-    // status block: counters | birth totals | per-instance state | per-instance diagnostics,
-    // contiguous on the device and mirrored in pinned host memory (one copy per step)
+    // status block: counters | birth totals | step index | per-instance state |
+    // per-instance energy sums [| their sub-slots], contiguous on the device;
+    // copied after every step into a slot of the pinned ring h_ring, and into
+    // h_status when a step is taken up alone
     void* d_status = nullptr;
     void* h_status = nullptr;
-    size_t status_bytes = 0;
-    int64_t* h_total = nullptr;
-    unsigned long long* h_counters = nullptr;
-    InstState* h_ist = nullptr;
-    double* h_diag = nullptr;
-    double* h_diag_sub = nullptr;      // energy-sum sub-slots, when the host folds them
-    bool host_diag = false;
-    hipEvent_t ev[7]{};
+    char* h_ring = nullptr;
+    size_t status_bytes = 0, ring_stride = 0;
+    size_t off_tot = 0, off_step = 0, off_ist = 0, off_diag = 0, off_sub = 0;
+    bool host_diag = false;            // the host folds the energy sums' sub-slots
+    hipEvent_t ev[7]{};                // autotuner and adjoint timing
+    hipEvent_t sev[RUN_AHEAD][7]{};    // per step of a batch: phase boundaries, push
+    int cur_slot = 0;                  // ring slot / event set of the step being enqueued or read
     int last_sweeps = 4;
+    int64_t last_births = 0;
     int sort_interval = 8;
     ugkwp_diag diag{};
     ugkwp_totals tot{};                // running sums since the last reset
@@ -245,9 +248,13 @@ struct ugkwp_ctx {
         owned.clear();
         if (h_status) (void)hipHostFree(h_status);
         h_status = nullptr;
-        h_total = nullptr; h_counters = nullptr; h_ist = nullptr; h_diag = nullptr; h_diag_sub = nullptr;
+        if (h_ring) (void)hipHostFree(h_ring);
+        h_ring = nullptr;
         for (auto& e : ev)
             if (e) { (void)hipEventDestroy(e); e = nullptr; }
+        for (auto& row : sev)
+            for (auto& e : row)
+                if (e) { (void)hipEventDestroy(e); e = nullptr; }
         if (own_stream && st) (void)hipStreamDestroy(st);
         st = nullptr;
         own_stream = false;
@@ -346,6 +353,7 @@ struct ugkwp_ctx {
         K.n_cap = P.n_cap;
         K.pool_cap = P.pool_capacity;
         K.flags = P.flags;
+        K.gate = GATE_OFF;
         K.n_inst = n_inst;
         K.n_cg = n_cg;
         K.n_fx2 = 2 * fx;
@@ -402,7 +410,6 @@ struct ugkwp_ctx {
         d.wc = dalloc<double>(owned, ncg);
         d.rho = dalloc<double>(owned, ncg);
         rho_buf0 = d.rho;
-        d.step = dalloc<uint32_t>(owned, 1);
         d.rho_new = dalloc<double>(owned, ncg);
         d.rhop = dalloc<double>(owned, ncg);
         d.rhoh = dalloc<double>(owned, ncg);
@@ -426,30 +433,32 @@ struct ugkwp_ctx {
         d.T_new = dalloc<double>(owned, ncell);
         d.pinned = dalloc<uint8_t>(owned, ncell);
         // status block (see the member comment); offsets are multiples of 16 bytes
-        const size_t off_tot = sizeof(unsigned long long) * N_COUNTERS;
-        const size_t off_ist = off_tot + 16;
-        const size_t off_diag = off_ist + sizeof(InstState) * (size_t)n_inst;
-        const size_t off_sub = off_diag + sizeof(double) * 8 * (size_t)n_inst;
+        off_tot = sizeof(unsigned long long) * N_COUNTERS;
+        off_step = off_tot + 16;
+        off_ist = off_step + 16;
+        off_diag = off_ist + (sizeof(InstState) * (size_t)n_inst + 15) / 16 * 16;
+        off_sub = off_diag + sizeof(double) * 8 * (size_t)n_inst;
         // few instances: the energy sums' sub-slots travel with the status and
         // the host folds them (no reduction launch)
         host_diag = n_inst <= 16;
         status_bytes = off_sub + (host_diag ? sizeof(double) * DIAG_SUB * 8 * (size_t)n_inst : 0);
+        ring_stride = (status_bytes + 255) / 256 * 256;
         d_status = dalloc<char>(owned, status_bytes);
         HIPCHK(hipMemsetAsync(d_status, 0, status_bytes, st));
         if (h_status) (void)hipHostFree(h_status);
+        h_status = nullptr;
         HIPCHK(hipHostMalloc(&h_status, status_bytes, hipHostMallocDefault));
-        h_counters = (unsigned long long*)h_status;
-        h_total = (int64_t*)((char*)h_status + off_tot);
-        h_ist = (InstState*)((char*)h_status + off_ist);
-        h_diag = (double*)((char*)h_status + off_diag);
+        if (h_ring) (void)hipHostFree(h_ring);
+        h_ring = nullptr;
+        HIPCHK(hipHostMalloc((void**)&h_ring, ring_stride * RUN_AHEAD, hipHostMallocDefault));
         d.counters = (unsigned long long*)d_status;
         d.n_births_total = (int64_t*)((char*)d_status + off_tot);
+        d.step = (uint32_t*)((char*)d_status + off_step);
         d.ist = (InstState*)((char*)d_status + off_ist);
         d.diag = (double*)((char*)d_status + off_diag);
         d.res = dalloc<Resid>(owned, (size_t)n_inst * RES_SLOTS * RES_SUB);
         d.diag_sub = host_diag ? (double*)((char*)d_status + off_sub)
                                : dalloc<double>(owned, (size_t)n_inst * DIAG_SUB * 8);
-        h_diag_sub = host_diag ? (double*)((char*)h_status + off_sub) : nullptr;
         n_part = std::max<int64_t>(scan_partials_size(n_cg), count_partials_size());
         part = dalloc<int64_t>(owned, (size_t)n_part + 1);
         HIPCHK(hipMemsetAsync(d.ist, 0, sizeof(InstState) * n_inst, st));
@@ -550,6 +559,7 @@ struct ugkwp_ctx {
         HIPCHK(hipGetLastError());
         n_alive = n_slots = 0;
         step_idx = 0;
+        last_births = 0;
         cur_mv = cur_st = 0;
         have_material = true;
         nrec = 0;
@@ -573,21 +583,112 @@ struct ugkwp_ctx {
         return p;
     }
 
-    // ---------------------------------------------------------------- one step
-    // Algorithm 1, enqueued without host round trips; one synchronisation at the
-    // end reads the status.  Source-iteration sweeps are launched speculatively
-    // (the previous step's count + 1; a converged instance's sweeps return at
-    // once) and more are added only if an instance has not converged.
-    void enqueue_finish(bool do_sort)
+    // ---------------------------------------------------------------- stepping
+    // Algorithm 1 per step, and steps run ahead of the host.  A batch of up to
+    // RUN_AHEAD steps is enqueued without waiting: every launch of step n
+    // carries n as its gate (gate_open), and each step's status block is copied
+    // into its own slot of a pinned ring.  One synchronisation per batch reads
+    // the slots.  The host plans the batch as if every step commits; the first
+    // step that does not commit has made every later launch of the batch return
+    // at once, so it is taken up alone (more sweeps, or the error it raised)
+    // and planning resumes after it.  Source-iteration sweeps are launched
+    // speculatively (the most the last batch needed, plus one; converged
+    // sweeps return at once).
+    // Host view of the state a step's launches depend on.
+    struct Plan {
+        double* rho;
+        double* rho_new;
+        double* T;
+        double* T_new;
+        int cur_mv, cur_st;
+        uint32_t step;
+        int64_t n_slots;       // known after processing; an estimate while planned
+        int nrec;
+        bool do_sort;
+        int sweeps;            // sweeps launched
+    };
+
+    Plan state_now() const
+    {
+        Plan p{};
+        p.rho = D.rho; p.rho_new = D.rho_new; p.T = D.T; p.T_new = D.T_new;
+        p.cur_mv = cur_mv; p.cur_st = cur_st;
+        p.step = step_idx;
+        p.n_slots = n_slots;
+        p.nrec = nrec;
+        return p;
+    }
+
+    void set_state(const Plan& p)
+    {
+        D.rho = p.rho; D.rho_new = p.rho_new; D.T = p.T; D.T_new = p.T_new;
+        cur_mv = p.cur_mv; cur_st = p.cur_st;
+        step_idx = p.step;
+        n_slots = p.n_slots;
+        nrec = p.nrec;
+    }
+
+    // the state after step p commits (n_slots_after from its status, or estimated)
+    Plan after(const Plan& p, int64_t n_slots_after) const
+    {
+        Plan q = p;
+        std::swap(q.rho, q.rho_new);
+        std::swap(q.T, q.T_new);
+        if (p.do_sort) q.cur_st = 1 - p.cur_st;    // sorted, compact pool: moving fields in mv[cur_mv]
+        else q.cur_mv = 1 - p.cur_mv;              // positions of this step in the other moving buffer
+        q.n_slots = n_slots_after;
+        q.step = p.step + 1;
+        if (rec_cap > 0) q.nrec = p.nrec + 1;
+        q.do_sort = false;
+        q.sweeps = 0;
+        return q;
+    }
+
+    bool sort_due(uint32_t step, int64_t slots) const
+    {
+        // sort periodically, and whenever holes have filled half the pool
+        return sort_interval <= 1 || (step % (uint32_t)sort_interval) == (uint32_t)(sort_interval - 1) ||
+               slots > P.pool_capacity / 2;
+    }
+
+    // Status block views: the device block, its pinned mirror and the ring slots.
+    struct StatusView {
+        const unsigned long long* counters;
+        const int64_t* total;
+        uint32_t step;
+        const InstState* ist;
+        const double* diag;
+        const double* sub;
+    };
+    StatusView status_at(const char* base) const
+    {
+        StatusView v;
+        v.counters = (const unsigned long long*)base;
+        v.total = (const int64_t*)(base + off_tot);
+        v.step = *(const uint32_t*)(base + off_step);
+        v.ist = (const InstState*)(base + off_ist);
+        v.diag = (const double*)(base + off_diag);
+        v.sub = host_diag ? (const double*)(base + off_sub) : nullptr;
+        return v;
+    }
+
+    // RAII: the launches enqueued while it lives carry `step` as their gate.
+    struct GateScope {
+        Consts& k;
+        GateScope(Consts& kk, uint32_t step) : k(kk) { k.gate = step; }
+        ~GateScope() { k.gate = GATE_OFF; }
+    };
+
+    void enqueue_finish(bool do_sort, int rec)
     {
         launch_finish(D, K, !host_diag, st);
         if (do_sort) {
-            if (phase_times) HIPCHK(hipEventRecord(ev[5], st));
-            launch_scan((const int32_t*)D.scount, K.n_cg, part, D.soff, D.n_births_total + 1, st);
+            if (phase_times) HIPCHK(hipEventRecord(sev[cur_slot][5], st));
+            launch_scan(scan_gate(D, K, 1), (const int32_t*)D.scount, K.n_cg, part, D.soff, D.n_births_total + 1, st);
             launch_sort_scatter(dim, D, K, view(1 - cur_mv, cur_st), view(cur_mv, 1 - cur_st), st);
-            if (phase_times) HIPCHK(hipEventRecord(ev[6], st));
+            if (phase_times) HIPCHK(hipEventRecord(sev[cur_slot][6], st));
         }
-        HIPCHK(hipMemcpyAsync(h_status, d_status, status_bytes, hipMemcpyDeviceToHost, st));
+        if (rec >= 0) launch_rec_store(D, K, A, rec, st);
     }
 
     // The launches before the push: tally clears, counts, scan, sampling.
@@ -656,65 +757,78 @@ struct ugkwp_ctx {
     // Graph keys: what the captured kernel arguments depend on.
     uint32_t parity() const { return D.rho == rho_buf0 ? 1u : 0u; }
 
-    int step_once()
+    // Enqueue the launches of step p (the host state is p's) with its status
+    // copied to `dst`.  Graph replays carry no gate: with graphs, steps run one
+    // at a time.
+    void enqueue_step(Plan& p, void* dst)
     {
-        if (rec_cap > 0 && nrec >= rec_cap)
-            fail(UGKWP_EINVAL, "the record holds its maximum of %d steps", rec_cap);
-        // sort periodically, and whenever holes have filled half the pool
-        const bool do_sort = sort_interval <= 1 ||
-                             (step_idx % (uint32_t)sort_interval) == (uint32_t)(sort_interval - 1) ||
-                             n_slots > P.pool_capacity / 2;
-        const int kmax = P.si_max_iters;
-        // each sweep is followed by its convergence decision, so last step's count
-        // plus one covers a step that needs one sweep more without a host round trip
-        const int first = std::min(kmax, last_sweeps + 1);
-        int k = first;
-        if (phase_times) HIPCHK(hipEventRecord(ev[0], st));
+        GateScope gs(K, use_graph ? GATE_OFF : p.step);
+        hipEvent_t* e = sev[cur_slot];
+        if (phase_times) HIPCHK(hipEventRecord(e[0], st));
         launch_group(0x100000u | (uint32_t)cur_mv | ((uint32_t)cur_st << 1) | (parity() << 2),
                      [&] { enqueue_pre_push(); });
-        HIPCHK(hipEventRecord(ev[1], st));
+        HIPCHK(hipEventRecord(e[1], st));
         launch_push(dim, D, K, view(cur_mv, cur_st), moving(1 - cur_mv), push_shape, st);
-        HIPCHK(hipEventRecord(ev[2], st));
+        HIPCHK(hipEventRecord(e[2], st));
         launch_macro_setup(D, K, push_shape, st);
-        if (phase_times) HIPCHK(hipEventRecord(ev[3], st));
+        if (phase_times) HIPCHK(hipEventRecord(e[3], st));
+        const int first = p.sweeps;
         launch_group(0x200000u | (uint32_t)first | (parity() << 16), [&] { enqueue_sweeps(0, first); });
-        if (phase_times) HIPCHK(hipEventRecord(ev[4], st));
-        enqueue_finish(do_sort);
-        HIPCHK(hipStreamSynchronize(st));
+        if (phase_times) HIPCHK(hipEventRecord(e[4], st));
+        enqueue_finish(p.do_sort, rec_cap > 0 ? p.nrec : -1);
+        HIPCHK(hipMemcpyAsync(dst, d_status, status_bytes, hipMemcpyDeviceToHost, st));
+    }
+
+    // Step p did not commit: raise its error, or add sweeps until it converges.
+    // Returns the status block of the committed step (in h_status).
+    StatusView take_up(Plan& p, StatusView s)
+    {
+        const int kmax = P.si_max_iters;
         for (;;) {
-            const unsigned long long err = h_counters[CNT_ERR];
+            const unsigned long long err = s.counters[CNT_ERR];
             if (err & ERR_POOL)
                 fail(UGKWP_EPOOL, "particle pool capacity %lld exceeded (%lld alive + %lld births)",
-                     (long long)P.pool_capacity, (long long)h_counters[CNT_SLOTS], (long long)*h_total);
+                     (long long)P.pool_capacity, (long long)s.counters[CNT_SLOTS], (long long)s.total[0]);
             if (err & ERR_TEMP) fail(UGKWP_ENONFINITE, "source iteration produced a non-positive or non-finite temperature");
             if (err) fail(UGKWP_EHIP, "internal error %llu: particle records or survivor counts inconsistent", err);
-            if (h_counters[CNT_CONV] == (unsigned long long)n_inst) break;
-            if (k >= kmax) fail(UGKWP_ENOCONV, "source iteration did not converge in %d sweeps", kmax);
-            const int kend = std::min(k + 4, kmax);
-            enqueue_sweeps(k, kend);
-            k = kend;
-            enqueue_finish(do_sort);
+            if (s.step == p.step + 1) return s;
+            if (s.step != p.step) fail(UGKWP_EHIP, "internal error: step counter %u, expected %u", s.step, p.step);
+            if (s.counters[CNT_CONV] == (unsigned long long)n_inst)
+                fail(UGKWP_EHIP, "internal error: converged step %u not committed", p.step);
+            if (p.sweeps >= kmax) fail(UGKWP_ENOCONV, "source iteration did not converge in %d sweeps", kmax);
+            const int kend = std::min(p.sweeps + 4, kmax);
+            {
+                GateScope gs(K, use_graph ? GATE_OFF : p.step);
+                enqueue_sweeps(p.sweeps, kend);
+                p.sweeps = kend;
+                if (phase_times) HIPCHK(hipEventRecord(sev[cur_slot][4], st));
+                enqueue_finish(p.do_sort, rec_cap > 0 ? p.nrec : -1);
+            }
+            HIPCHK(hipMemcpyAsync(h_status, d_status, status_bytes, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
+            s = status_at((const char*)h_status);
         }
+    }
 
-        // bookkeeping of the committed step
+    // bookkeeping of committed step p from its status block
+    void account(const Plan& p, const StatusView& s)
+    {
         ugkwp_diag dg{};
         dg.n_alive_in = n_alive;
-        dg.n_births = *h_total;
-        dg.n_pushed = n_alive + *h_total;
-        const int64_t pushed_slots = (int64_t)h_counters[CNT_PUSHED];
-        dg.n_alive_out = (int64_t)h_counters[CNT_SURV];
+        dg.n_births = s.total[0];
+        dg.n_pushed = n_alive + s.total[0];
+        dg.n_alive_out = (int64_t)s.counters[CNT_SURV];
         int smax = 0, ssum = 0;
         for (int q = 0; q < n_inst; ++q) {
-            smax = std::max(smax, h_ist[q].conv_sweeps);
-            ssum += h_ist[q].conv_sweeps;
+            smax = std::max(smax, s.ist[q].conv_sweeps);
+            ssum += s.ist[q].conv_sweeps;
             double fold[8];
-            const double* g = h_diag + 8 * q;
+            const double* g = s.diag + 8 * q;
             if (host_diag) {
                 // the same order as the device reduction: sub-slot 0, 1, ...
                 for (int c = 0; c < 8; ++c) {
                     double acc = 0.0;
-                    for (int b = 0; b < DIAG_SUB; ++b) acc += h_diag_sub[((size_t)q * DIAG_SUB + b) * 8 + c];
+                    for (int b = 0; b < DIAG_SUB; ++b) acc += s.sub[((size_t)q * DIAG_SUB + b) * 8 + c];
                     fold[c] = acc;
                 }
                 g = fold;
@@ -729,15 +843,16 @@ struct ugkwp_ctx {
         dg.sweeps_max = smax;
         dg.sweeps_sum = ssum;
         dg.residual = dg.e_end - dg.e_start - (dg.inflow_wave + dg.inflow_eq - dg.exit_particles + dg.injection);
+        hipEvent_t* e = sev[cur_slot];
         float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, ev[1], ev[2])); dg.ms_push = ms;
+        HIPCHK(hipEventElapsedTime(&ms, e[1], e[2])); dg.ms_push = ms;
         if (phase_times) {
-            HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1])); dg.ms_sample = ms;
-            HIPCHK(hipEventElapsedTime(&ms, ev[2], ev[3])); dg.ms_macro = ms;
-            HIPCHK(hipEventElapsedTime(&ms, ev[3], ev[4])); dg.ms_si = ms;
+            HIPCHK(hipEventElapsedTime(&ms, e[0], e[1])); dg.ms_sample = ms;
+            HIPCHK(hipEventElapsedTime(&ms, e[2], e[3])); dg.ms_macro = ms;
+            HIPCHK(hipEventElapsedTime(&ms, e[3], e[4])); dg.ms_si = ms;
         }
         dg.ms_sort = 0.0;
-        if (do_sort && phase_times) { HIPCHK(hipEventElapsedTime(&ms, ev[5], ev[6])); dg.ms_sort = ms; }
+        if (p.do_sort && phase_times) { HIPCHK(hipEventElapsedTime(&ms, e[5], e[6])); dg.ms_sort = ms; }
         diag = dg;
         tot.steps += 1;
         tot.n_pushed += dg.n_pushed;
@@ -749,25 +864,62 @@ struct ugkwp_ctx {
         tot.ms_macro += dg.ms_macro;
         tot.ms_si += dg.ms_si;
         tot.ms_sort += dg.ms_sort;
-        last_sweeps = smax;
-
-        std::swap(D.rho, D.rho_new);
-        std::swap(D.T, D.T_new);
-        if (do_sort) {
-            cur_st = 1 - cur_st;           // sorted, compact pool: moving fields in mv[cur_mv]
-            n_slots = dg.n_alive_out;
-        } else {
-            cur_mv = 1 - cur_mv;           // positions of this step in the other moving buffer
-            n_slots = pushed_slots;
-        }
+        if (rec_cap > 0) rec_sweeps.push_back(smax);
         n_alive = dg.n_alive_out;
-        step_idx++;
-        if (rec_cap > 0) {
-            launch_rec_store(D, K, A, nrec, st);
-            rec_sweeps.push_back(smax);
-            nrec++;
+        last_births = dg.n_births;
+        // slots after the step: compacted to the survivors by a sort, else
+        // every slot the push covered
+        set_state(after(p, p.do_sort ? dg.n_alive_out : (int64_t)s.counters[CNT_PUSHED]));
+    }
+
+    void run(int nsteps)
+    {
+        int done = 0;
+        while (done < nsteps) {
+            if (rec_cap > 0 && nrec >= rec_cap)
+                fail(UGKWP_EINVAL, "the record holds its maximum of %d steps", rec_cap);
+            int m = std::min(nsteps - done, use_graph ? 1 : RUN_AHEAD);
+            if (rec_cap > 0) m = std::min(m, rec_cap - nrec);
+            const int kmax = P.si_max_iters;
+            const int spec = std::min(kmax, last_sweeps + 1);
+            // plan and enqueue
+            const Plan start = state_now();
+            std::vector<Plan> plan;
+            plan.reserve(m);
+            Plan p = start;
+            try {
+                for (int i = 0; i < m; ++i) {
+                    p.do_sort = sort_due(p.step, p.n_slots);
+                    p.sweeps = spec;
+                    set_state(p);
+                    cur_slot = i;
+                    enqueue_step(p, h_ring + (size_t)i * ring_stride);
+                    plan.push_back(p);
+                    p = after(p, p.do_sort ? n_alive : p.n_slots + last_births);
+                }
+                HIPCHK(hipStreamSynchronize(st));
+            } catch (...) {
+                (void)hipStreamSynchronize(st);
+                set_state(start);
+                throw;
+            }
+            // read the statuses in order
+            set_state(start);
+            int batch_max = 0;
+            for (int i = 0; i < m; ++i) {
+                Plan& q = plan[i];
+                cur_slot = i;
+                StatusView s = status_at(h_ring + (size_t)i * ring_stride);
+                const bool committed = s.step == q.step + 1 && s.counters[CNT_ERR] == 0;
+                if (!committed) s = take_up(q, s);
+                account(q, s);
+                step_idx = q.step + 1;
+                batch_max = std::max(batch_max, diag.sweeps_max);
+                done++;
+                if (!committed) break;      // later steps of the batch did not run: plan again
+            }
+            last_sweeps = batch_max;
         }
-        return UGKWP_OK;
     }
 
     // ---------------------------------------------------------------- autotuner
@@ -1063,6 +1215,8 @@ int ugkwp_create(ugkwp_ctx** out, const ugkwp_params* p, void* hip_stream)
         c->phase_times = (p->flags & UGKWP_FLAG_PHASE_TIMES) != 0;
         // timing-only events: no system-scope fence (cache write-back) when recorded
         for (auto& e : c->ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+        for (auto& row : c->sev)
+            for (auto& e : row) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     });
     if (rc) { delete c; return rc; }
     *out = c;
@@ -1155,7 +1309,7 @@ int ugkwp_step(ugkwp_ctx* ctx, int nsteps)
     return guarded(ctx, [&] {
         require_ready(ctx);
         if (nsteps < 0) fail(UGKWP_EINVAL, "negative step count");
-        for (int n = 0; n < nsteps; ++n) ctx->step_once();
+        ctx->run(nsteps);
     });
 }
 
