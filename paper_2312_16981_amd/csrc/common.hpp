@@ -66,12 +66,17 @@ struct Resid {
 struct InstState {
     int conv_sweeps;       // sweeps used by the converged source iteration, 0 = running
     int bad;               // non-finite / non-positive temperature seen
-    uint64_t births;       // birth counter B_n
+    uint64_t births;       // birth counter B_n (carried from step to step)
 };
 
-// Context counters (device, unsigned 64-bit):
+// Context counters (device, unsigned 64-bit).  They sit in a step record
+// together with the birth totals, the per-instance states and energy sums:
+// every step of a batch writes its own record, and its first launch carries
+// the persistent entries (CNT_SLOTS, CNT_LIVE, the birth counters) over
+// from the record of the step before.
 enum {
     CNT_SURV = 0,      // particles alive after this step's push
+    CNT_DONE = 1,      // the step count after this step's commit, 0 while not committed
     CNT_ERR = 2,       // ERR_* bits raised in this step
     CNT_CONV = 3,      // instances whose source iteration has converged
     CNT_SLOTS = 4,     // pool slots at the start of the step (live particles and holes)
@@ -161,6 +166,10 @@ struct Dev {
     unsigned long long* counters;   // CNT_*
     int64_t* n_births_total;        // [0] births of the step, [1] survivors (sort scan)
     unsigned long long* blk_surv;   // survivors counted by each push block
+    // the record of the step before (counters and instance states), read
+    // once at the start of a step for the persistent entries
+    const unsigned long long* prev_counters;
+    const InstState* prev_ist;
 };
 
 __host__ __device__ inline int find_inst(const int64_t* starts, int n, int64_t j)

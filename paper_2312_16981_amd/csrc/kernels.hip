@@ -171,9 +171,10 @@ __global__ void k_init_rho(Dev D, Consts K, const double* Tr0)
 // ---------------------------------------------------------------------------
 // A1: wave split and particle counts
 
-// Also clears the tallies and step counters the push and the commit add to
-// (grid-stride over the flat arrays), and, when part is given, writes the
-// per-block sum of N for the scan that follows.
+// Also opens the step's record (block 0: the persistent entries from the
+// record before, everything else cleared), clears the tallies the push and
+// the commit add to (grid-stride over the flat arrays), and, when part is
+// given, writes the per-block sum of N for the scan that follows.
 constexpr int COUNT_THREADS = 256;
 
 __global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroList Z, int64_t* part)
@@ -181,6 +182,21 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroLi
     if (!gate_open(D, K, 0)) return;
     const int64_t j = (int64_t)blockIdx.x * COUNT_THREADS + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * COUNT_THREADS;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < N_COUNTERS) {
+            const int q = threadIdx.x;
+            D.counters[q] = (q == CNT_SLOTS || q == CNT_LIVE) ? D.prev_counters[q] : 0ull;
+        }
+        if (threadIdx.x < 2) D.n_births_total[threadIdx.x] = 0;
+        for (int q = threadIdx.x; q < K.n_inst; q += COUNT_THREADS) {
+            InstState st;
+            st.conv_sweeps = 0;
+            st.bad = 0;
+            st.births = D.prev_ist[q].births;
+            D.ist[q] = st;
+        }
+        for (int q = threadIdx.x; q < 8 * K.n_inst; q += COUNT_THREADS) D.diag[q] = 0.0;
+    }
     for (int r = 0; r < Z.n; ++r) {
         uint64_t* p = (uint64_t*)Z.ptr[r];
         for (int64_t q = j; q < Z.words[r]; q += stride) p[q] = 0ull;
@@ -850,8 +866,8 @@ __device__ inline void wave_source(const Dev& D, const Consts& K, int64_t j, con
 // group-edge sharing of the Planck integrals are wavefront shuffles.
 
 // Wave flux and Q (A4) fused with the set-up of the source iteration:
-// phi^0 = phi(T^n), rho^0 = rho^n, T^0 = T^n, residual slot 0 and the
-// per-instance convergence state cleared.
+// phi^0 = phi(T^n), rho^0 = rho^n, T^0 = T^n, residual slot 0 cleared (the
+// per-instance convergence state starts cleared in the step's record).
 __global__ void k_macro_setup(Dev D, Consts K, int push_blocks)
 {
     if (!gate_open(D, K, 0)) return;
@@ -892,10 +908,6 @@ __global__ void k_macro_setup(Dev D, Consts K, int push_blocks)
     if (rel >= 0 && rel < RES_SUB) {            // first wavefront of the instance
         Resid z = {0ull, 0ull, 0ull, 0ull};
         D.res[((int64_t)s.inst * RES_SLOTS + 0) * RES_SUB + rel] = z;
-    }
-    if (rel == 0) {
-        D.ist[s.inst].conv_sweeps = 0;
-        D.ist[s.inst].bad = 0;
     }
 }
 
@@ -1114,7 +1126,9 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K)
         if (j == 0) {
             D.counters[CNT_SLOTS] = D.counters[CNT_PUSHED];
             D.counters[CNT_LIVE] = D.counters[CNT_SURV];
-            *D.step += 1u;
+            const uint32_t n1 = *D.step + 1u;
+            *D.step = n1;
+            D.counters[CNT_DONE] = n1;
         }
     }
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // inflow_eq, exit/c, injection, e0, e1

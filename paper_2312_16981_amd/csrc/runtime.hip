@@ -116,6 +116,7 @@ int ilog2(int p)
 
 constexpr int MAX_PUSH_BLOCKS = 8192;     // per-block survivor counts kept by the push
 constexpr int RUN_AHEAD = 16;             // steps enqueued per host synchronisation
+constexpr int N_RECORDS = RUN_AHEAD + 1;  // step records: a batch's steps and the state it starts from
 
 template <class T>
 T* dalloc(std::vector<void*>& owned, size_t n)
@@ -179,20 +180,22 @@ struct ugkwp_ctx {
     int64_t n_part = 0;
     double* d_phib = nullptr;
 
-    // host staging (pinned)
-    // status block: counters | birth totals | step index | per-instance state |
-    // per-instance energy sums [| their sub-slots], contiguous on the device;
-    // copied after every step into a slot of the pinned ring h_ring, and into
-    // h_status when a step is taken up alone
-    void* d_status = nullptr;
-    void* h_status = nullptr;
+    // step records: counters | birth totals | per-instance state | per-instance
+    // energy sums [| their sub-slots], N_RECORDS of them on the device (every
+    // step of a batch writes its own), read back together after the batch into
+    // pinned h_ring, or one of them into h_status when a step is taken up alone.
+    // cur_rec holds the committed state; D points at it between steps.
+    char* d_ring = nullptr;
     char* h_ring = nullptr;
+    void* h_status = nullptr;
     size_t status_bytes = 0, ring_stride = 0;
-    size_t off_tot = 0, off_step = 0, off_ist = 0, off_diag = 0, off_sub = 0;
+    size_t off_tot = 0, off_ist = 0, off_diag = 0, off_sub = 0;
+    int cur_rec = 0;
     bool host_diag = false;            // the host folds the energy sums' sub-slots
+    double* diag_sub_dev = nullptr;    // the sub-slots when the device folds them
     hipEvent_t ev[7]{};                // autotuner and adjoint timing
     hipEvent_t sev[RUN_AHEAD][7]{};    // per step of a batch: phase boundaries, push
-    int cur_slot = 0;                  // ring slot / event set of the step being enqueued or read
+    int cur_slot = 0;                  // event set of the step being enqueued or read
     int last_sweeps = 4;
     int64_t last_births = 0;
     int sort_interval = 8;
@@ -432,33 +435,30 @@ struct ugkwp_ctx {
         d.T = dalloc<double>(owned, ncell);
         d.T_new = dalloc<double>(owned, ncell);
         d.pinned = dalloc<uint8_t>(owned, ncell);
-        // status block (see the member comment); offsets are multiples of 16 bytes
+        // step records (see the member comment); offsets are multiples of 16 bytes
         off_tot = sizeof(unsigned long long) * N_COUNTERS;
-        off_step = off_tot + 16;
-        off_ist = off_step + 16;
+        off_ist = off_tot + 16;
         off_diag = off_ist + (sizeof(InstState) * (size_t)n_inst + 15) / 16 * 16;
         off_sub = off_diag + sizeof(double) * 8 * (size_t)n_inst;
-        // few instances: the energy sums' sub-slots travel with the status and
+        // few instances: the energy sums' sub-slots travel with the record and
         // the host folds them (no reduction launch)
         host_diag = n_inst <= 16;
         status_bytes = off_sub + (host_diag ? sizeof(double) * DIAG_SUB * 8 * (size_t)n_inst : 0);
         ring_stride = (status_bytes + 255) / 256 * 256;
-        d_status = dalloc<char>(owned, status_bytes);
-        HIPCHK(hipMemsetAsync(d_status, 0, status_bytes, st));
+        d_ring = dalloc<char>(owned, ring_stride * N_RECORDS);
+        HIPCHK(hipMemsetAsync(d_ring, 0, ring_stride * N_RECORDS, st));
         if (h_status) (void)hipHostFree(h_status);
         h_status = nullptr;
         HIPCHK(hipHostMalloc(&h_status, status_bytes, hipHostMallocDefault));
         if (h_ring) (void)hipHostFree(h_ring);
         h_ring = nullptr;
-        HIPCHK(hipHostMalloc((void**)&h_ring, ring_stride * RUN_AHEAD, hipHostMallocDefault));
-        d.counters = (unsigned long long*)d_status;
-        d.n_births_total = (int64_t*)((char*)d_status + off_tot);
-        d.step = (uint32_t*)((char*)d_status + off_step);
-        d.ist = (InstState*)((char*)d_status + off_ist);
-        d.diag = (double*)((char*)d_status + off_diag);
+        HIPCHK(hipHostMalloc((void**)&h_ring, ring_stride * N_RECORDS, hipHostMallocDefault));
+        d.step = dalloc<uint32_t>(owned, 1);
+        HIPCHK(hipMemsetAsync(d.step, 0, sizeof(uint32_t), st));
         d.res = dalloc<Resid>(owned, (size_t)n_inst * RES_SLOTS * RES_SUB);
-        d.diag_sub = host_diag ? (double*)((char*)d_status + off_sub)
-                               : dalloc<double>(owned, (size_t)n_inst * DIAG_SUB * 8);
+        diag_sub_dev = host_diag ? nullptr : dalloc<double>(owned, (size_t)n_inst * DIAG_SUB * 8);
+        cur_rec = 0;
+        point_record(d, 0, 0);
         n_part = std::max<int64_t>(scan_partials_size(n_cg), count_partials_size());
         part = dalloc<int64_t>(owned, (size_t)n_part + 1);
         HIPCHK(hipMemsetAsync(d.ist, 0, sizeof(InstState) * n_inst, st));
@@ -495,6 +495,20 @@ struct ugkwp_ctx {
         step_idx = 0;
         HIPCHK(hipStreamSynchronize(st));
         HIPCHK(hipGetLastError());
+    }
+
+    // point D's record entries at record `slot`, the record before it at `prev`
+    void point_record(Dev& d, int slot, int prev) const
+    {
+        char* r = d_ring + (size_t)slot * ring_stride;
+        const char* q = d_ring + (size_t)prev * ring_stride;
+        d.counters = (unsigned long long*)r;
+        d.n_births_total = (int64_t*)(r + off_tot);
+        d.ist = (InstState*)(r + off_ist);
+        d.diag = (double*)(r + off_diag);
+        d.diag_sub = host_diag ? (double*)(r + off_sub) : diag_sub_dev;
+        d.prev_counters = (const unsigned long long*)q;
+        d.prev_ist = (const InstState*)(q + off_ist);
     }
 
     // pack a host [ncell][G] array of instance k into the padded device layout
@@ -586,14 +600,14 @@ struct ugkwp_ctx {
     // ---------------------------------------------------------------- stepping
     // Algorithm 1 per step, and steps run ahead of the host.  A batch of up to
     // RUN_AHEAD steps is enqueued without waiting: every launch of step n
-    // carries n as its gate (gate_open), and each step's status block is copied
-    // into its own slot of a pinned ring.  One synchronisation per batch reads
-    // the slots.  The host plans the batch as if every step commits; the first
-    // step that does not commit has made every later launch of the batch return
-    // at once, so it is taken up alone (more sweeps, or the error it raised)
-    // and planning resumes after it.  Source-iteration sweeps are launched
-    // speculatively (the most the last batch needed, plus one; converged
-    // sweeps return at once).
+    // carries n as its gate (gate_open), and every step writes its own record
+    // of counters and sums.  One copy and one synchronisation per batch bring
+    // the records back.  The host plans the batch as if every step commits;
+    // the first step that does not commit has made every later launch of the
+    // batch return at once, so it is taken up alone (more sweeps, or the error
+    // it raised) and planning resumes after it.  Source-iteration sweeps are
+    // launched speculatively (the most the last batch needed, plus one;
+    // converged sweeps return at once).
     // Host view of the state a step's launches depend on.
     struct Plan {
         double* rho;
@@ -604,6 +618,8 @@ struct ugkwp_ctx {
         uint32_t step;
         int64_t n_slots;       // known after processing; an estimate while planned
         int nrec;
+        int rec;               // record holding the state the step starts from
+        int slot;              // record the step writes
         bool do_sort;
         int sweeps;            // sweeps launched
     };
@@ -616,6 +632,8 @@ struct ugkwp_ctx {
         p.step = step_idx;
         p.n_slots = n_slots;
         p.nrec = nrec;
+        p.rec = cur_rec;
+        p.slot = -1;
         return p;
     }
 
@@ -626,7 +644,13 @@ struct ugkwp_ctx {
         step_idx = p.step;
         n_slots = p.n_slots;
         nrec = p.nrec;
+        cur_rec = p.rec;
+        point_record(D, p.rec, p.rec);
     }
+
+    // the record after `r` (with graphs, two alternate: their addresses are
+    // part of the captured launches)
+    int next_record(int r) const { return use_graph ? (r ^ 1) : (r + 1) % N_RECORDS; }
 
     // the state after step p commits (n_slots_after from its status, or estimated)
     Plan after(const Plan& p, int64_t n_slots_after) const
@@ -638,6 +662,8 @@ struct ugkwp_ctx {
         else q.cur_mv = 1 - p.cur_mv;              // positions of this step in the other moving buffer
         q.n_slots = n_slots_after;
         q.step = p.step + 1;
+        q.rec = p.slot;
+        q.slot = -1;
         if (rec_cap > 0) q.nrec = p.nrec + 1;
         q.do_sort = false;
         q.sweeps = 0;
@@ -651,11 +677,10 @@ struct ugkwp_ctx {
                slots > P.pool_capacity / 2;
     }
 
-    // Status block views: the device block, its pinned mirror and the ring slots.
+    // A step record read back to the host.
     struct StatusView {
         const unsigned long long* counters;
         const int64_t* total;
-        uint32_t step;
         const InstState* ist;
         const double* diag;
         const double* sub;
@@ -665,7 +690,6 @@ struct ugkwp_ctx {
         StatusView v;
         v.counters = (const unsigned long long*)base;
         v.total = (const int64_t*)(base + off_tot);
-        v.step = *(const uint32_t*)(base + off_step);
         v.ist = (const InstState*)(base + off_ist);
         v.diag = (const double*)(base + off_diag);
         v.sub = host_diag ? (const double*)(base + off_sub) : nullptr;
@@ -704,7 +728,6 @@ struct ugkwp_ctx {
         add(D.surv, K.n_cg);
         add(D.scount, K.n_cg / 2);
         add(D.diag_sub, (int64_t)DIAG_SUB * 8 * n_inst);
-        add(D.counters, 4);                 // CNT_SURV .. CNT_CONV; slot and live counts persist
         launch_count_scan(D, K, z, part, st);
         launch_sample(dim, D, K, view(cur_mv, cur_st), st);
     }
@@ -757,15 +780,16 @@ struct ugkwp_ctx {
     // Graph keys: what the captured kernel arguments depend on.
     uint32_t parity() const { return D.rho == rho_buf0 ? 1u : 0u; }
 
-    // Enqueue the launches of step p (the host state is p's) with its status
-    // copied to `dst`.  Graph replays carry no gate: with graphs, steps run one
-    // at a time.
-    void enqueue_step(Plan& p, void* dst)
+    // Enqueue the launches of step p (the host state is p's).  Graph replays
+    // carry no gate: with graphs, steps run one at a time.
+    void enqueue_step(Plan& p)
     {
         GateScope gs(K, use_graph ? GATE_OFF : p.step);
+        point_record(D, p.slot, p.rec);
         hipEvent_t* e = sev[cur_slot];
         if (phase_times) HIPCHK(hipEventRecord(e[0], st));
-        launch_group(0x100000u | (uint32_t)cur_mv | ((uint32_t)cur_st << 1) | (parity() << 2),
+        launch_group(0x100000u | (uint32_t)cur_mv | ((uint32_t)cur_st << 1) | (parity() << 2) |
+                         ((uint32_t)p.slot << 3),
                      [&] { enqueue_pre_push(); });
         HIPCHK(hipEventRecord(e[1], st));
         launch_push(dim, D, K, view(cur_mv, cur_st), moving(1 - cur_mv), push_shape, st);
@@ -773,17 +797,18 @@ struct ugkwp_ctx {
         launch_macro_setup(D, K, push_shape, st);
         if (phase_times) HIPCHK(hipEventRecord(e[3], st));
         const int first = p.sweeps;
-        launch_group(0x200000u | (uint32_t)first | (parity() << 16), [&] { enqueue_sweeps(0, first); });
+        launch_group(0x200000u | (uint32_t)first | (parity() << 16) | ((uint32_t)p.slot << 17),
+                     [&] { enqueue_sweeps(0, first); });
         if (phase_times) HIPCHK(hipEventRecord(e[4], st));
         enqueue_finish(p.do_sort, rec_cap > 0 ? p.nrec : -1);
-        HIPCHK(hipMemcpyAsync(dst, d_status, status_bytes, hipMemcpyDeviceToHost, st));
     }
 
     // Step p did not commit: raise its error, or add sweeps until it converges.
-    // Returns the status block of the committed step (in h_status).
+    // Returns the record of the committed step (in h_status).
     StatusView take_up(Plan& p, StatusView s)
     {
         const int kmax = P.si_max_iters;
+        point_record(D, p.slot, p.rec);
         for (;;) {
             const unsigned long long err = s.counters[CNT_ERR];
             if (err & ERR_POOL)
@@ -791,8 +816,9 @@ struct ugkwp_ctx {
                      (long long)P.pool_capacity, (long long)s.counters[CNT_SLOTS], (long long)s.total[0]);
             if (err & ERR_TEMP) fail(UGKWP_ENONFINITE, "source iteration produced a non-positive or non-finite temperature");
             if (err) fail(UGKWP_EHIP, "internal error %llu: particle records or survivor counts inconsistent", err);
-            if (s.step == p.step + 1) return s;
-            if (s.step != p.step) fail(UGKWP_EHIP, "internal error: step counter %u, expected %u", s.step, p.step);
+            if (s.counters[CNT_DONE] == (unsigned long long)p.step + 1) return s;
+            if (s.counters[CNT_DONE] != 0)
+                fail(UGKWP_EHIP, "internal error: step %u recorded as step %llu", p.step, s.counters[CNT_DONE]);
             if (s.counters[CNT_CONV] == (unsigned long long)n_inst)
                 fail(UGKWP_EHIP, "internal error: converged step %u not committed", p.step);
             if (p.sweeps >= kmax) fail(UGKWP_ENOCONV, "source iteration did not converge in %d sweeps", kmax);
@@ -804,7 +830,7 @@ struct ugkwp_ctx {
                 if (phase_times) HIPCHK(hipEventRecord(sev[cur_slot][4], st));
                 enqueue_finish(p.do_sort, rec_cap > 0 ? p.nrec : -1);
             }
-            HIPCHK(hipMemcpyAsync(h_status, d_status, status_bytes, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(h_status, D.counters, status_bytes, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             s = status_at((const char*)h_status);
         }
@@ -891,29 +917,39 @@ struct ugkwp_ctx {
                 for (int i = 0; i < m; ++i) {
                     p.do_sort = sort_due(p.step, p.n_slots);
                     p.sweeps = spec;
+                    p.slot = next_record(p.rec);
                     set_state(p);
                     cur_slot = i;
-                    enqueue_step(p, h_ring + (size_t)i * ring_stride);
+                    enqueue_step(p);
                     plan.push_back(p);
                     p = after(p, p.do_sort ? n_alive : p.n_slots + last_births);
                 }
+                HIPCHK(hipMemcpyAsync(h_ring, d_ring, ring_stride * N_RECORDS, hipMemcpyDeviceToHost, st));
                 HIPCHK(hipStreamSynchronize(st));
             } catch (...) {
                 (void)hipStreamSynchronize(st);
                 set_state(start);
                 throw;
             }
-            // read the statuses in order
+            // read the records in order
             set_state(start);
             int batch_max = 0;
             for (int i = 0; i < m; ++i) {
                 Plan& q = plan[i];
                 cur_slot = i;
-                StatusView s = status_at(h_ring + (size_t)i * ring_stride);
-                const bool committed = s.step == q.step + 1 && s.counters[CNT_ERR] == 0;
-                if (!committed) s = take_up(q, s);
+                StatusView s = status_at(h_ring + (size_t)q.slot * ring_stride);
+                const bool committed =
+                    s.counters[CNT_DONE] == (unsigned long long)q.step + 1 && s.counters[CNT_ERR] == 0;
+                if (!committed) {
+                    const Plan before = state_now();
+                    try {
+                        s = take_up(q, s);
+                    } catch (...) {
+                        set_state(before);
+                        throw;
+                    }
+                }
                 account(q, s);
-                step_idx = q.step + 1;
                 batch_max = std::max(batch_max, diag.sweeps_max);
                 done++;
                 if (!committed) break;      // later steps of the batch did not run: plan again
