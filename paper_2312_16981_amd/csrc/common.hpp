@@ -136,8 +136,9 @@ struct Dev {
     double* rhop;               // survivor density from the previous step
     double* rhoh;               // rho^h = rho^n - rhop (start of step)
     double* Q;
-    double* phi0;
-    double* phi1;
+    double* phi0;               // phi(T^n): the source iteration's phi^0
+    double* phi1;               // phi^{k+1} of the even sweeps
+    double* phi2;               // phi^{k+1} of the odd sweeps
     int32_t* nb;                // births per slot
     int64_t* boff;              // exclusive scan of nb
     double* wnew;

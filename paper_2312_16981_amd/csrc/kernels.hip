@@ -152,20 +152,24 @@ __global__ void k_ghost_phi(Dev D, Consts K, double* phib)
     phib[((int64_t)inst * 4 + side) * MAX_G + g] = v;
 }
 
-// rho^0 = phi(Tr0) per (cell, group)
+// rho^0 = phi(Tr0) per (cell, group), and phi(T^0), the first step's
+// source-iteration start (later steps start from the last sweep's phi)
 __global__ void k_init_rho(Dev D, Consts K, const double* Tr0)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= K.n_cg) return;
     const Slot s = decode_slot(D, K, j);
-    double v = 0.0;
+    double v = 0.0, p = 0.0;
     if (s.active) {
         const Inst& I = D.inst[s.inst];
-        v = phi_group_direct(Tr0[I.cell_off + s.lcell], D.nu[I.edge_off + s.g],
-                             D.nu[I.edge_off + s.g + 1], K.a, K.c);
+        const int cell = I.cell_off + s.lcell;
+        const double nl = D.nu[I.edge_off + s.g], nh = D.nu[I.edge_off + s.g + 1];
+        v = phi_group_direct(Tr0[cell], nl, nh, K.a, K.c);
+        p = phi_group_direct(D.T[cell], nl, nh, K.a, K.c);
     }
     D.rho[j] = v;
     D.rhop[j] = 0.0;
+    D.phi0[j] = p;
 }
 
 // ---------------------------------------------------------------------------
@@ -866,8 +870,10 @@ __device__ inline void wave_source(const Dev& D, const Consts& K, int64_t j, con
 // group-edge sharing of the Planck integrals are wavefront shuffles.
 
 // Wave flux and Q (A4) fused with the set-up of the source iteration:
-// phi^0 = phi(T^n), rho^0 = rho^n, T^0 = T^n, residual slot 0 cleared (the
-// per-instance convergence state starts cleared in the step's record).
+// rho^0 = rho^n, T^0 = T^n, residual slot 0 cleared.  phi^0 = phi(T^n) is
+// already in phi0 (the output of the previous step's last sweep, the same
+// expression evaluated at the same T), and the per-instance convergence
+// state starts cleared in the step's record.
 __global__ void k_macro_setup(Dev D, Consts K, int push_blocks)
 {
     if (!gate_open(D, K, 0)) return;
@@ -892,16 +898,9 @@ __global__ void k_macro_setup(Dev D, Consts K, int push_blocks)
     if (s.cell_ok) {
         const Inst& I = D.inst[s.inst];
         const int cell = I.cell_off + s.lcell;
-        const double T = D.T[cell];
-        double v = 0.0;
-        if (s.active)
-            v = phi_group_direct(T, D.nu[I.edge_off + s.g], D.nu[I.edge_off + s.g + 1], K.a, K.c);
-        D.phi0[j] = v;
         D.rho_new[j] = D.rho[j];
-        if (s.g == 0) D.T_new[cell] = T;
+        if (s.g == 0) D.T_new[cell] = D.T[cell];
     } else {
-        D.phi0[j] = 0.0;
-        D.phi1[j] = 0.0;
         D.rho_new[j] = 0.0;
     }
     const int64_t rel = j - D.inst[s.inst].cg_off;
@@ -912,6 +911,14 @@ __global__ void k_macro_setup(Dev D, Consts K, int push_blocks)
 }
 
 constexpr int SI_THREADS = 256;
+
+// phi^k buffers: sweep 0 reads phi0 = phi(T^n), sweep k writes phi1 (k even)
+// or phi2 (k odd) and sweep k + 1 reads it; phi0 is only rewritten by the commit.
+__host__ __device__ inline const double* sweep_in(const Dev& D, int k)
+{
+    return k == 0 ? D.phi0 : (((k - 1) & 1) ? D.phi2 : D.phi1);
+}
+__host__ __device__ inline double* sweep_out(const Dev& D, int k) { return (k & 1) ? D.phi2 : D.phi1; }
 
 // Sweep k: rho^{k+1}, T^{k+1} and phi^{k+1} from phi^k for every instance whose
 // iteration is still running.  The residual maxima of the sweep go to sub-slots
@@ -1102,17 +1109,39 @@ __global__ void k_si_decide(Dev D, Consts K, int k)
 
 // Energy bookkeeping of the step per instance: diag[inst*8 + q],
 // q = 0 inflow_wave (written by k_wave_source), 1 inflow_eq, 2 exit, 3 injection,
-// 4 e_start, 5 e_end.  Uses the final source-iteration input phi^k.  Sums are
+// 4 e_start, 5 e_end.  Uses the final source-iteration input phi^k; the
+// commit also keeps the last sweep's phi(T^{n+1}) in phi0 for the next step.  Sums are
 // reduced per wavefront and per run of same-instance wavefronts of the block
 // before one atomic per quantity.
 constexpr int DIAG_THREADS = 256;
 
-__global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K)
+// last_sweep >= 0 (single instance): the convergence decision of that sweep
+// is taken here rather than by a decide launch; wavefront 0 of every block
+// takes it from the same residual sub-slots, and block 0 records it.
+__global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int last_sweep)
 {
     // the commit below advances *D.step while other blocks may still start:
     // both the step's own value and the next one open this launch
     if (!gate_open(D, K, 0) && !gate_open(D, K, 1)) return;
-    if (!step_committed(D, K)) return;
+    int ns_single = 0;
+    if (last_sweep >= 0) {
+        __shared__ int sh_ns;
+        if (threadIdx.x < WAVE) {
+            // a block starting after block 0's record reads that record: the same value
+            int ns = D.ist[0].conv_sweeps;
+            if (ns == 0 && si_converged(D, K, 0, last_sweep, threadIdx.x)) ns = last_sweep + 1;
+            if (threadIdx.x == 0) sh_ns = ns;
+        }
+        __syncthreads();
+        ns_single = sh_ns;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && ns_single != 0 && D.ist[0].conv_sweeps == 0) {
+            D.ist[0].conv_sweeps = ns_single;
+            atomicAdd((unsigned long long*)(D.counters + CNT_CONV), 1ull);
+        }
+        if (D.counters[CNT_ERR] != 0 || ns_single == 0) return;
+    } else if (!step_committed(D, K)) {
+        return;
+    }
     const int64_t j = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x;
     const Slot s = decode_slot(D, K, j);
     // commit: survivor density for the next step, birth counters, pool size
@@ -1134,11 +1163,11 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K)
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // inflow_eq, exit/c, injection, e0, e1
     if (s.active) {
         const Inst& I = D.inst[s.inst];
-        const int ns = D.ist[s.inst].conv_sweeps;
-        const double* phik = ((ns - 1) & 1) ? D.phi1 : D.phi0;
+        const int ns = last_sweep >= 0 ? ns_single : D.ist[s.inst].conv_sweeps;
         const int nx = I.nx, ix = s.lcell % nx, iy = s.lcell / nx, g = s.g;
         const int cell = I.cell_off + s.lcell;
-        const double phi = phik[j];
+        const double phi = sweep_in(D, ns - 1)[j];          // phi^k of the last sweep
+        D.phi0[j] = sweep_out(D, ns - 1)[j];                // phi(T^{n+1}): the next step's phi^0
         const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
         for (int q = 0; q < 2 * I.dim; ++q) {
             const int axis = q >> 1;
@@ -1419,16 +1448,15 @@ void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t
 {
     const bool fold = K.n_inst == 1;
     for (int k = k0; k < k1; ++k) {
-        const double* pin = (k & 1) ? D.phi1 : D.phi0;
-        double* pout = (k & 1) ? D.phi0 : D.phi1;
-        k_si_sweep<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, pin, pout, fold && k > k0 ? 1 : 0);
-        if (!fold || k == k1 - 1) k_si_decide<<<blocks((int64_t)K.n_inst * WAVE, 256), 256, 0, st>>>(D, K, k);
+        k_si_sweep<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, sweep_in(D, k), sweep_out(D, k),
+                                                                    fold && k > k0 ? 1 : 0);
+        if (!fold) k_si_decide<<<blocks((int64_t)K.n_inst * WAVE, 256), 256, 0, st>>>(D, K, k);
     }
 }
 
-void launch_finish(const Dev& D, const Consts& K, bool reduce_diag, hipStream_t st)
+void launch_finish(const Dev& D, const Consts& K, bool reduce_diag, int last_sweep, hipStream_t st)
 {
-    k_finish<<<blocks(K.n_cg, DIAG_THREADS), DIAG_THREADS, 0, st>>>(D, K);
+    k_finish<<<blocks(K.n_cg, DIAG_THREADS), DIAG_THREADS, 0, st>>>(D, K, K.n_inst == 1 ? last_sweep : -1);
     if (reduce_diag) k_diag_reduce<<<blocks(K.n_inst, 64), 64, 0, st>>>(D, K);
 }
 

@@ -46,11 +46,13 @@ void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& B, 
 // wave flux, Q and the start of the source iteration; also sums the push's survivors
 void launch_macro_setup(const Dev& D, const Consts& K, const PushShape& sh, hipStream_t st);
 // sweeps k0..k1-1 of the source iteration, each sweep's convergence decided
-// before the next (in the next sweep for a single instance, else by a decide
-// launch), the last one's by a decide launch
+// before the next: for a single instance in the next sweep (the last one's in
+// launch_finish), else by a decide launch after every sweep
 void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t st);
-// commit and energy sums; reduce_diag folds the sums' sub-slots on the device
-void launch_finish(const Dev& D, const Consts& K, bool reduce_diag, hipStream_t st);
+// commit and energy sums; reduce_diag folds the sums' sub-slots on the device;
+// last_sweep is the last sweep launched (a single instance's convergence
+// after it is decided by the commit launch)
+void launch_finish(const Dev& D, const Consts& K, bool reduce_diag, int last_sweep, hipStream_t st);
 
 void launch_eval_phi(int n, const double* T, int G, const double* nu, double a, double c, double* out,
                      hipStream_t st);

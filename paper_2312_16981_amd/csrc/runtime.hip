@@ -419,6 +419,8 @@ struct ugkwp_ctx {
         d.Q = dalloc<double>(owned, ncg);
         d.phi0 = dalloc<double>(owned, ncg);
         d.phi1 = dalloc<double>(owned, ncg);
+        d.phi2 = dalloc<double>(owned, ncg);
+        for (double* q : {d.phi0, d.phi1, d.phi2}) HIPCHK(hipMemsetAsync(q, 0, sizeof(double) * ncg, st));
         d.nb = dalloc<int32_t>(owned, ncg);
         d.boff = dalloc<int64_t>(owned, ncg + 1);
         d.wnew = dalloc<double>(owned, ncg);
@@ -703,9 +705,9 @@ struct ugkwp_ctx {
         ~GateScope() { k.gate = GATE_OFF; }
     };
 
-    void enqueue_finish(bool do_sort, int rec)
+    void enqueue_finish(bool do_sort, int rec, int last_sweep)
     {
-        launch_finish(D, K, !host_diag, st);
+        launch_finish(D, K, !host_diag, last_sweep, st);
         if (do_sort) {
             if (phase_times) HIPCHK(hipEventRecord(sev[cur_slot][5], st));
             launch_scan(scan_gate(D, K, 1), (const int32_t*)D.scount, K.n_cg, part, D.soff, D.n_births_total + 1, st);
@@ -800,7 +802,7 @@ struct ugkwp_ctx {
         launch_group(0x200000u | (uint32_t)first | (parity() << 16) | ((uint32_t)p.slot << 17),
                      [&] { enqueue_sweeps(0, first); });
         if (phase_times) HIPCHK(hipEventRecord(e[4], st));
-        enqueue_finish(p.do_sort, rec_cap > 0 ? p.nrec : -1);
+        enqueue_finish(p.do_sort, rec_cap > 0 ? p.nrec : -1, first - 1);
     }
 
     // Step p did not commit: raise its error, or add sweeps until it converges.
@@ -828,7 +830,7 @@ struct ugkwp_ctx {
                 enqueue_sweeps(p.sweeps, kend);
                 p.sweeps = kend;
                 if (phase_times) HIPCHK(hipEventRecord(sev[cur_slot][4], st));
-                enqueue_finish(p.do_sort, rec_cap > 0 ? p.nrec : -1);
+                enqueue_finish(p.do_sort, rec_cap > 0 ? p.nrec : -1, kend - 1);
             }
             HIPCHK(hipMemcpyAsync(h_status, D.counters, status_bytes, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
