@@ -118,10 +118,12 @@ typedef struct {
     /* GPU time of the phases of the step, in ms, from HIP events on the context
      * stream: tally clears + count + scan + sample, the push kernel alone (events
      * recorded just before and after its launch, so the interval also holds its
-     * dispatch, a few microseconds), wave flux + source set-up, the source
-     * iteration, and the counting sort that keeps the pool ordered by (cell,
-     * group).  All but ms_push are 0 unless the context was created with
-     * UGKWP_FLAG_PHASE_TIMES (each event adds a few microseconds to a step). */
+     * dispatch, a few microseconds), ms_macro (now only the event pair after
+     * the push: the wave flux and Q are evaluated by the first source-iteration
+     * sweep and counted in ms_si), the source iteration, and the counting sort
+     * that keeps the pool ordered by (cell, group).  All but ms_push are 0
+     * unless the context was created with UGKWP_FLAG_PHASE_TIMES (each event
+     * adds a few microseconds to a step). */
     double ms_sample, ms_push, ms_macro, ms_si, ms_sort;
 } ugkwp_diag;
 

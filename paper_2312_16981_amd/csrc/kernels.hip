@@ -11,12 +11,14 @@
 //                  linear-frequency nu (Appendix A), t_f = dt
 //   k_push         free flight with reset at interfaces (Eq. particle tf formula,
 //                  Remark 1), gross face tallies (Eq. wfrpFormula), deletion of
-//                  collided particles, stable wavefront-ballot compaction of survivors
-//   k_sort_scatter counting sort of the survivors by (cell, group) slot
-//   k_macro_setup  wave free-transport flux (Sec. 2.2, F^{fr,wave}; Remark 3), the
-//                  static part Q of the macroscopic update (Eq. macroSysFinal), and
-//                  the start of the source iteration
-//   k_si_sweep     source iteration (Appendix B, Eq. macroSysAppendixIte, Algorithm 2)
+//                  collided particles (their slots stay empty until the next sort)
+//   k_sort_scatter counting sort of the survivors by (cell, group) slot, which
+//                  also compacts the pool
+//   k_si_sweep     source iteration (Appendix B, Eq. macroSysAppendixIte, Algorithm 2);
+//                  sweep 0 also evaluates the wave free-transport flux (Sec. 2.2,
+//                  F^{fr,wave}; Remark 3) and the static part Q of the macroscopic
+//                  update (Eq. macroSysFinal)
+//   k_si_decide    convergence decision of a sweep (batched contexts)
 //   k_finish       commit of the step and energy bookkeeping
 //
 // Counts that the host does not know without a round trip (births, survivors,
@@ -686,7 +688,7 @@ __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Cons
         }
         __syncthreads();
     }
-    // survivors of this block (summed in k_macro_setup)
+    // survivors of this block (summed by the commit)
     for (int m = 32; m >= 1; m >>= 1) nsurv += __shfl_xor(nsurv, m, WAVE);
     if (lane == 0) bsurv[wid] = nsurv;
     __syncthreads();
@@ -808,9 +810,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(Dev D, Consts K, 
 // ---------------------------------------------------------------------------
 // A4: wave free-transport flux and the static source Q
 
-__device__ inline void wave_source(const Dev& D, const Consts& K, int64_t j, const Slot& s)
+__device__ inline double wave_source(const Dev& D, const Consts& K, int64_t j, const Slot& s)
 {
-    if (!s.active) { D.Q[j] = 0.0; return; }
     const Inst& I = D.inst[s.inst];
     const int Gp = I.Gp, g = s.g, nx = I.nx;
     const int ix = s.lcell % nx, iy = s.lcell / nx;
@@ -859,56 +860,19 @@ __device__ inline void wave_source(const Dev& D, const Consts& K, int64_t j, con
         a_in += D.fty[fb * 2 + 0] + D.fty[ft * 2 + 1];
         a_out += D.fty[fb * 2 + 1] + D.fty[ft * 2 + 0];
     }
-    D.Q[j] = D.rho[j] + (K.dt / I.V) * fsum + (a_in - a_out) / I.V;
     if (inflow != 0.0)
         atomicAdd(D.diag_sub + ((int64_t)s.inst * DIAG_SUB + (blockIdx.x & (DIAG_SUB - 1))) * 8 + 0, inflow);
+    return D.rho[j] + (K.dt / I.V) * fsum + (a_in - a_out) / I.V;
 }
 
 // ---------------------------------------------------------------------------
 // A5: source iteration.  Thread per (cell, group) slot; the Gp slots of a cell
 // share one wavefront, so the group sum of the temperature update and the
-// group-edge sharing of the Planck integrals are wavefront shuffles.
-
-// Wave flux and Q (A4) fused with the set-up of the source iteration:
-// rho^0 = rho^n, T^0 = T^n, residual slot 0 cleared.  phi^0 = phi(T^n) is
-// already in phi0 (the output of the previous step's last sweep, the same
-// expression evaluated at the same T), and the per-instance convergence
-// state starts cleared in the step's record.
-__global__ void k_macro_setup(Dev D, Consts K, int push_blocks)
-{
-    if (!gate_open(D, K, 0)) return;
-    if (blockIdx.x == 0) {
-        // survivors of the push: sum of its per-block counts
-        __shared__ unsigned long long part[256 / WAVE];
-        unsigned long long t = 0;
-        for (int b = threadIdx.x; b < push_blocks; b += blockDim.x) t += D.blk_surv[b];
-        for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, WAVE);
-        if ((threadIdx.x & (WAVE - 1)) == 0) part[threadIdx.x / WAVE] = t;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long sum = 0;
-            for (int k = 0; k < (int)blockDim.x / WAVE; ++k) sum += part[k];
-            D.counters[CNT_SURV] = (D.counters[CNT_ERR] & ERR_POOL) ? 0ull : sum;
-        }
-    }
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= K.n_cg) return;
-    const Slot s = decode_slot(D, K, j);
-    wave_source(D, K, j, s);
-    if (s.cell_ok) {
-        const Inst& I = D.inst[s.inst];
-        const int cell = I.cell_off + s.lcell;
-        D.rho_new[j] = D.rho[j];
-        if (s.g == 0) D.T_new[cell] = D.T[cell];
-    } else {
-        D.rho_new[j] = 0.0;
-    }
-    const int64_t rel = j - D.inst[s.inst].cg_off;
-    if (rel >= 0 && rel < RES_SUB) {            // first wavefront of the instance
-        Resid z = {0ull, 0ull, 0ull, 0ull};
-        D.res[((int64_t)s.inst * RES_SLOTS + 0) * RES_SUB + rel] = z;
-    }
-}
+// group-edge sharing of the Planck integrals are wavefront shuffles.  Sweep 0
+// also evaluates the wave flux and Q (A4) for its slot and keeps Q for the
+// later sweeps; it starts from rho^0 = rho^n, T^0 = T^n and phi^0 = phi(T^n),
+// which phi0 already holds (the previous commit's last sweep output, the same
+// expression at the same temperature).
 
 constexpr int SI_THREADS = 256;
 
@@ -920,6 +884,13 @@ __host__ __device__ inline const double* sweep_in(const Dev& D, int k)
 }
 __host__ __device__ inline double* sweep_out(const Dev& D, int k) { return (k & 1) ? D.phi2 : D.phi1; }
 
+// Residual sub-slots of sweep k for instance inst: [RES_SLOTS][n_inst][RES_SUB],
+// so that the slots of sweep 0 form one range cleared at the start of a step.
+__device__ inline Resid* res_slot(const Dev& D, const Consts& K, int inst, int k)
+{
+    return D.res + ((int64_t)(k % RES_SLOTS) * K.n_inst + inst) * RES_SUB;
+}
+
 // Sweep k: rho^{k+1}, T^{k+1} and phi^{k+1} from phi^k for every instance whose
 // iteration is still running.  The residual maxima of the sweep go to sub-slots
 // of the instance (spread over 64 addresses by block); k_si_decide reads them.
@@ -928,12 +899,15 @@ __host__ __device__ inline double* sweep_out(const Dev& D, int k) { return (k & 
 // decide launch sits between sweeps; block 0 records it.
 __device__ inline bool si_converged(const Dev& D, const Consts& K, int inst, int k, int lane)
 {
-    const Resid r = D.res[((int64_t)inst * RES_SLOTS + k % RES_SLOTS) * RES_SUB + lane];
+    const Resid r = res_slot(D, K, inst, k)[lane];
     const double drho = wave_nmax(bitsd(r.drho)), mrho = wave_nmax(bitsd(r.rho));
     const double dT = wave_nmax(bitsd(r.dT)), mT = wave_nmax(bitsd(r.T));
     return drho <= K.si_tol * mrho && dT <= K.si_tol * mT;
 }
 
+// FIRST: sweep 0 (its own instantiation, so that the wave-flux code does not
+// weigh on the registers of the later sweeps).
+template <bool FIRST>
 __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k, const double* phi_in,
                                                           double* phi_out, int decide_prev)
 {
@@ -962,7 +936,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     const int64_t rel = j - I.cg_off;
     if (run && rel >= 0 && rel < RES_SUB) {
         Resid z = {0ull, 0ull, 0ull, 0ull};
-        D.res[((int64_t)s.inst * RES_SLOTS + (k + 1) % RES_SLOTS) * RES_SUB + rel] = z;
+        res_slot(D, K, s.inst, k + 1)[rel] = z;
     }
 
     double dr = 0.0, mr = 0.0, dT = 0.0, mT = 0.0;
@@ -1001,12 +975,19 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
             }
             lap += S * Df * (pn - phi);
         }
+        double Qj;
+        if (FIRST) {
+            Qj = wave_source(D, K, j, s);
+            D.Q[j] = Qj;
+        } else {
+            Qj = D.Q[j];
+        }
         const double lam = D.sv[j];
-        const double b = D.Q[j] + (K.dt / I.V) * lap;
+        const double b = Qj + (K.dt / I.V) * lap;
         const double r = (b + lam * phi) / (1.0 + lam);
         const double em = (b - phi) / (1.0 + lam);
         contrib = D.sig[j] * em;
-        dr = fabs(r - D.rho_new[j]);
+        dr = fabs(r - (FIRST ? D.rho[j] : D.rho_new[j]));
         mr = fabs(r);
         D.rho_new[j] = r;
     }
@@ -1016,8 +997,8 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     double Tnew = 1.0;
     if (work) {
         const int cell = I.cell_off + s.lcell;
-        const double Tk = D.T_new[cell];
         const double Tn = D.T[cell];
+        const double Tk = FIRST ? Tn : D.T_new[cell];
         Tnew = D.pinned[cell] ? Tn : Tn + (K.dt / (K.eps * K.eps * D.cvol[cell])) * contrib;
         if (!(Tnew > 0.0) || !isfinite(Tnew)) {
             if (g == 0) {
@@ -1076,8 +1057,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
                 ++w1;
             }
             if (any) {
-                Resid* r = D.res + ((int64_t)winst[w0] * RES_SLOTS + k % RES_SLOTS) * RES_SUB +
-                           (blockIdx.x & (RES_SUB - 1));
+                Resid* r = res_slot(D, K, winst[w0], k) + (blockIdx.x & (RES_SUB - 1));
                 atomicMax(&r->drho, dbits(a0));
                 atomicMax(&r->rho, dbits(a1));
                 atomicMax(&r->dT, dbits(a2));
@@ -1118,7 +1098,7 @@ constexpr int DIAG_THREADS = 256;
 // last_sweep >= 0 (single instance): the convergence decision of that sweep
 // is taken here rather than by a decide launch; wavefront 0 of every block
 // takes it from the same residual sub-slots, and block 0 records it.
-__global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int last_sweep)
+__global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int last_sweep, int push_blocks)
 {
     // the commit below advances *D.step while other blocks may still start:
     // both the step's own value and the next one open this launch
@@ -1144,6 +1124,20 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
     }
     const int64_t j = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x;
     const Slot s = decode_slot(D, K, j);
+    if (blockIdx.x == 0) {
+        // survivors of the push: sum of its per-block counts
+        __shared__ unsigned long long part[DIAG_THREADS / WAVE];
+        unsigned long long t = 0;
+        for (int b = threadIdx.x; b < push_blocks; b += DIAG_THREADS) t += D.blk_surv[b];
+        for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, WAVE);
+        if ((threadIdx.x & (WAVE - 1)) == 0) part[threadIdx.x / WAVE] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long sum = 0;
+            for (int q = 0; q < DIAG_THREADS / WAVE; ++q) sum += part[q];
+            D.counters[CNT_SURV] = sum;
+        }
+    }
     // commit: survivor density for the next step, birth counters, pool size
     if (j < K.n_cg) {
         const Inst& I = D.inst[s.inst];
@@ -1439,24 +1433,21 @@ void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& In,
     }
 }
 
-void launch_macro_setup(const Dev& D, const Consts& K, const PushShape& sh, hipStream_t st)
-{
-    k_macro_setup<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K, sh.blocks);
-}
-
 void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t st)
 {
     const bool fold = K.n_inst == 1;
     for (int k = k0; k < k1; ++k) {
-        k_si_sweep<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, sweep_in(D, k), sweep_out(D, k),
+        auto kern = k == 0 ? k_si_sweep<true> : k_si_sweep<false>;
+        kern<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, sweep_in(D, k), sweep_out(D, k),
                                                                     fold && k > k0 ? 1 : 0);
         if (!fold) k_si_decide<<<blocks((int64_t)K.n_inst * WAVE, 256), 256, 0, st>>>(D, K, k);
     }
 }
 
-void launch_finish(const Dev& D, const Consts& K, bool reduce_diag, int last_sweep, hipStream_t st)
+void launch_finish(const Dev& D, const Consts& K, bool reduce_diag, int last_sweep, int push_blocks, hipStream_t st)
 {
-    k_finish<<<blocks(K.n_cg, DIAG_THREADS), DIAG_THREADS, 0, st>>>(D, K, K.n_inst == 1 ? last_sweep : -1);
+    k_finish<<<blocks(K.n_cg, DIAG_THREADS), DIAG_THREADS, 0, st>>>(D, K, K.n_inst == 1 ? last_sweep : -1,
+                                                                   push_blocks);
     if (reduce_diag) k_diag_reduce<<<blocks(K.n_inst, 64), 64, 0, st>>>(D, K);
 }
 

@@ -43,16 +43,16 @@ int push_blocks_per_cu(int dim, const Consts& K);         // resident blocks per
 void launch_push(int dim, const Dev& D, const Consts& K, const Pool& A, const Pool& B, const PushShape& sh,
                  hipStream_t st);
 void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& B, const Pool& A, hipStream_t st);
-// wave flux, Q and the start of the source iteration; also sums the push's survivors
-void launch_macro_setup(const Dev& D, const Consts& K, const PushShape& sh, hipStream_t st);
 // sweeps k0..k1-1 of the source iteration, each sweep's convergence decided
 // before the next: for a single instance in the next sweep (the last one's in
 // launch_finish), else by a decide launch after every sweep
 void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t st);
 // commit and energy sums; reduce_diag folds the sums' sub-slots on the device;
 // last_sweep is the last sweep launched (a single instance's convergence
-// after it is decided by the commit launch)
-void launch_finish(const Dev& D, const Consts& K, bool reduce_diag, int last_sweep, hipStream_t st);
+// after it is decided by the commit launch); the commit also sums the
+// survivor counts of the push's push_blocks blocks
+void launch_finish(const Dev& D, const Consts& K, bool reduce_diag, int last_sweep, int push_blocks,
+                   hipStream_t st);
 
 void launch_eval_phi(int n, const double* T, int G, const double* nu, double a, double c, double* out,
                      hipStream_t st);

@@ -420,7 +420,9 @@ struct ugkwp_ctx {
         d.phi0 = dalloc<double>(owned, ncg);
         d.phi1 = dalloc<double>(owned, ncg);
         d.phi2 = dalloc<double>(owned, ncg);
-        for (double* q : {d.phi0, d.phi1, d.phi2}) HIPCHK(hipMemsetAsync(q, 0, sizeof(double) * ncg, st));
+        // slots the sweeps never write (padding groups and cells) stay zero
+        for (double* q : {d.phi0, d.phi1, d.phi2, d.rho, d.rho_new})
+            HIPCHK(hipMemsetAsync(q, 0, sizeof(double) * ncg, st));
         d.nb = dalloc<int32_t>(owned, ncg);
         d.boff = dalloc<int64_t>(owned, ncg + 1);
         d.wnew = dalloc<double>(owned, ncg);
@@ -707,7 +709,7 @@ struct ugkwp_ctx {
 
     void enqueue_finish(bool do_sort, int rec, int last_sweep)
     {
-        launch_finish(D, K, !host_diag, last_sweep, st);
+        launch_finish(D, K, !host_diag, last_sweep, push_shape.blocks, st);
         if (do_sort) {
             if (phase_times) HIPCHK(hipEventRecord(sev[cur_slot][5], st));
             launch_scan(scan_gate(D, K, 1), (const int32_t*)D.scount, K.n_cg, part, D.soff, D.n_births_total + 1, st);
@@ -730,6 +732,7 @@ struct ugkwp_ctx {
         add(D.surv, K.n_cg);
         add(D.scount, K.n_cg / 2);
         add(D.diag_sub, (int64_t)DIAG_SUB * 8 * n_inst);
+        add(D.res, (int64_t)n_inst * RES_SUB * (int64_t)(sizeof(Resid) / 8));   // sweep 0's residual slots
         launch_count_scan(D, K, z, part, st);
         launch_sample(dim, D, K, view(cur_mv, cur_st), st);
     }
@@ -796,7 +799,7 @@ struct ugkwp_ctx {
         HIPCHK(hipEventRecord(e[1], st));
         launch_push(dim, D, K, view(cur_mv, cur_st), moving(1 - cur_mv), push_shape, st);
         HIPCHK(hipEventRecord(e[2], st));
-        launch_macro_setup(D, K, push_shape, st);
+        // the wave flux and Q are evaluated by the first sweep: no launch of their own
         if (phase_times) HIPCHK(hipEventRecord(e[3], st));
         const int first = p.sweeps;
         launch_group(0x200000u | (uint32_t)first | (parity() << 16) | ((uint32_t)p.slot << 17),
