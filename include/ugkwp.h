@@ -281,6 +281,11 @@ int ugkwp_eval_coef(int n, const double* s, double* c4, double* w, double* c2_ov
 /* Uniform draws u(seed, id[i], step, purpose, d[i]) of the keyed Philox4x32-10 stream. */
 int ugkwp_eval_uniform(int n, uint64_t seed, const uint64_t* id, uint32_t step,
                        uint32_t purpose, const uint32_t* d, double* out);
+/* -ln(u[i]) for u[i] in (0, 1) as the particle flights evaluate it (free-flight
+ * time t_f = -tau ln(eta), Sec. 2.2): within a few ulp of the correctly
+ * rounded value.  EINVAL for n < 0 or a null array; u outside (0, 1) gives an
+ * unspecified value. */
+int ugkwp_eval_neg_log(int n, const double* u, double* out);
 /* Linear-frequency sampling (Appendix A): slope beta at T[i] and the sampled nu
  * for U[i] in group [nl[i], nh[i]]. */
 int ugkwp_eval_sample_nu(int n, const double* nl, const double* nh, const double* T,

@@ -126,6 +126,7 @@ struct Dev {
     const double* phib;         // [inst][4][MAX_G] Planckian ghost phi
     // per (cell, group) slot
     const double* kappa;
+    double* inv_kappa;          // 1/kappa (+inf where kappa = 0), for the particle flights
     double* sig;
     double* sv;                 // s = c sigma dt / eps^2 (= lambda of the source iteration)
     double* es;                 // e^{-s}

@@ -76,6 +76,40 @@ __host__ __device__ inline void keyed_uniform_pair(uint64_t seed, uint64_t id, u
     out1 = u52(r.v[2], r.v[3]);
 }
 
+// -ln(u) for u in (0, 1), the uniforms above.  u = 2^e m with m in
+// [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s) with s = (m - 1)/(m + 1), |s| <= 0.1716,
+// summed as 2s (1 + s^2/3 + s^4/5 + ... + s^22/23): the first term left out is
+// below 2^-54 of the sum.  ln 2 is split so that e ln2_hi is exact (ln2_hi
+// keeps 32 significant bits).  The result is within a few ulp of the correctly
+// rounded value; the tests compare it with the host libm.
+__host__ __device__ inline double neg_log_unit(double u)
+{
+    int e;
+    double m = frexp(u, &e);                       // u = m 2^e, m in [1/2, 1)
+    if (m < 0.70710678118654752440) {
+        m = m + m;
+        e -= 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);        // m - 1 is exact here
+    const double z = s * s;
+    double p = 1.0 / 23.0;
+    p = fma(p, z, 1.0 / 21.0);
+    p = fma(p, z, 1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    const double t = s + s;
+    const double lnm = fma(t, z * p, t);
+    const double de = (double)e;
+    const double ln2_hi = 0x1.62e42fee00000p-1, ln2_lo = 0x1.a39ef35793c76p-33;
+    return -fma(de, ln2_hi, fma(de, ln2_lo, lnm));
+}
+
 // ---------------------------------------------------------------------------
 // Planck band integrals.  head(x) = int_0^x t^3/(e^t-1) dt by its Taylor series
 // in x (x < 2, coefficients in constant memory supplied by the host);

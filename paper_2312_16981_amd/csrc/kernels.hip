@@ -61,12 +61,16 @@ __device__ inline Geo geo_of(const Inst& I)
 // fixed for a particle, so the push computes it once.
 enum { SIG_NU3 = 0, SIG_POW = 1, SIG_GROUP = 2 };
 
+// The flight scale of a particle, tau = eps^2 / (c sigma), with sigma = kappa
+// nu^-p (Remark 2; Simpson's group factor S_g instead of nu^-p with
+// UGKWP_FLAG_GROUP_SIGMA), is evaluated as the particle's factor eps^2 nu^p
+// / c times the cell's 1/kappa: no division per particle or per crossing.
 template <int SM>
-__device__ inline double nu_factor(const Dev& D, const Consts& K, const Geo& I, double nu, int g)
+__device__ inline double tau_factor(const Dev& D, const Consts& K, const Geo& I, double nu, int g)
 {
-    if (SM == SIG_GROUP) return D.simpson[I.edge_off + g];
-    if (SM == SIG_NU3) return 1.0 / (nu * nu * nu);
-    return pow(nu, -K.nu_power);
+    if (SM == SIG_GROUP) return K.e2c / D.simpson[I.edge_off + g];
+    if (SM == SIG_NU3) return K.e2c * (nu * nu * nu);
+    return K.e2c * pow(nu, K.nu_power);
 }
 
 __device__ inline double phi_group_direct(double T, double nl, double nh, double a, double c)
@@ -92,9 +96,10 @@ __global__ void k_tables(Dev D, Consts K)
     if (j >= K.n_cg) return;
     const Slot s = decode_slot(D, K, j);
     if (!s.active) {
-        D.sig[j] = 0.0; D.sv[j] = 0.0; D.es[j] = 1.0; D.c4[j] = 1.0; D.wc[j] = 0.0;
+        D.sig[j] = 0.0; D.sv[j] = 0.0; D.es[j] = 1.0; D.c4[j] = 1.0; D.wc[j] = 0.0; D.inv_kappa[j] = 0.0;
         return;
     }
+    D.inv_kappa[j] = 1.0 / D.kappa[j];     // +inf for kappa = 0: no collision
     const Inst& I = D.inst[s.inst];
     const double sg = D.kappa[j] * D.simpson[I.edge_off + s.g];
     const double sv = K.c * sg * K.dt / (K.eps * K.eps);
@@ -494,7 +499,7 @@ __device__ inline void lds_tally(TallyTable& T, const Dev& D, uint32_t type, uin
 
 struct Flight {
     double x, y, ox, oy;   // position and direction (mu in 1-D)
-    double t, t_rem, sig;
+    double t, t_rem, tau;  // time flown, flight time left, flight scale in this cell
     uint32_t d;            // FLIGHT draws used
     int ix, iy;
     bool coll;
@@ -503,8 +508,7 @@ struct Flight {
 __device__ inline void draw_flight(const Consts& K, const Geo& I, uint64_t id, uint32_t step, Flight& f)
 {
     const double u = keyed_uniform(I.seed, id, step, PURPOSE_FLIGHT, f.d++);
-    const double tau = K.e2c / f.sig;
-    const double a = -tau * log(u);
+    const double a = f.tau * neg_log_unit(u);
     f.coll = a < K.dt - f.t;
     f.t_rem = f.coll ? a : K.dt - f.t;
 }
@@ -512,7 +516,7 @@ __device__ inline void draw_flight(const Consts& K, const Geo& I, uint64_t id, u
 // Flight of one particle through the step.  Returns 0 survives, 1 collided, 2 left the domain.
 template <int DIM>
 __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTable& T, uint64_t id,
-                          uint32_t step, double nfac, int g, double w, Flight& f)
+                          uint32_t step, double tfac, int g, double w, Flight& f)
 {
     for (;;) {
         const double vx = K.cv * f.ox;
@@ -586,7 +590,7 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTabl
         }
         lds_tally(T, D, type, index, w);
         if (xaxis) f.ix += pos ? 1 : -1; else f.iy += pos ? 1 : -1;
-        f.sig = D.kappa[I.cg_off + ((int64_t)(f.iy * I.nx + f.ix) << I.lgGp) + g] * nfac;
+        f.tau = tfac * D.inv_kappa[I.cg_off + ((int64_t)(f.iy * I.nx + f.ix) << I.lgGp) + g];
         draw_flight(K, I, id, step, f);
     }
 }
@@ -654,12 +658,12 @@ __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Cons
             f.iy = DIM == 1 ? 0 : lcell / I.nx;
             f.t = 0.0;
             f.d = 0;
-            const double nfac = nu_factor<SM>(D, K, I, nu, g);
-            f.sig = D.kappa[I.cg_off + ((int64_t)lcell << I.lgGp) + g] * nfac;
+            const double tfac = tau_factor<SM>(D, K, I, nu, g);
+            f.tau = tfac * D.inv_kappa[I.cg_off + ((int64_t)lcell << I.lgGp) + g];
             if (i < n_slots) draw_flight(K, I, id, step, f);    // old particle: t_f = min(-tau ln eta, dt)
             else { f.coll = false; f.t_rem = K.dt; }            // new collisionless particle: t_f = dt
             const double ox0 = f.ox, oy0 = f.oy;
-            const int out = fly<DIM>(D, K, I, T, id, step, nfac, g, w, f);
+            const int out = fly<DIM>(D, K, I, T, id, step, tfac, g, w, f);
             if (out != 2) {
                 const uint32_t cg = (uint32_t)(I.cg_off + ((int64_t)(f.iy * I.nx + f.ix) << I.lgGp) + g);
                 lds_tally(T, D, out == 0 ? TAL_SURV : TAL_DEP, cg, w);
@@ -1261,6 +1265,13 @@ __global__ void k_eval_uniform(int n, uint64_t seed, const uint64_t* id, uint32_
     out[j] = keyed_uniform(seed, id[j], step, purpose, d[j]);
 }
 
+__global__ void k_eval_neg_log(int n, const double* u, double* out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    out[j] = neg_log_unit(u[j]);
+}
+
 __global__ void k_eval_sample_nu(int n, const double* nl, const double* nh, const double* T, const double* U,
                                  double* beta, double* nu)
 {
@@ -1466,6 +1477,11 @@ void launch_eval_uniform(int n, uint64_t seed, const uint64_t* id, uint32_t step
                          const uint32_t* d, double* out, hipStream_t st)
 {
     k_eval_uniform<<<blocks(n, 256), 256, 0, st>>>(n, seed, id, step, purpose, d, out);
+}
+
+void launch_eval_neg_log(int n, const double* u, double* out, hipStream_t st)
+{
+    k_eval_neg_log<<<blocks(n, 256), 256, 0, st>>>(n, u, out);
 }
 
 void launch_eval_sample_nu(int n, const double* nl, const double* nh, const double* T, const double* U,

@@ -59,6 +59,7 @@ void launch_eval_phi(int n, const double* T, int G, const double* nu, double a, 
 void launch_eval_coef(int n, const double* s, double* c4, double* w, double* c2, hipStream_t st);
 void launch_eval_uniform(int n, uint64_t seed, const uint64_t* id, uint32_t step, uint32_t purpose,
                          const uint32_t* d, double* out, hipStream_t st);
+void launch_eval_neg_log(int n, const double* u, double* out, hipStream_t st);
 void launch_eval_sample_nu(int n, const double* nl, const double* nh, const double* T, const double* U,
                            double* beta, double* nu, hipStream_t st);
 

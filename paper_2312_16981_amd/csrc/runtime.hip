@@ -407,6 +407,7 @@ struct ugkwp_ctx {
         const size_t ncg = (size_t)n_cg;
         d.kappa = dalloc<double>(owned, ncg);
         d.sig = dalloc<double>(owned, ncg);
+        d.inv_kappa = dalloc<double>(owned, ncg);
         d.sv = dalloc<double>(owned, ncg);
         d.es = dalloc<double>(owned, ncg);
         d.c4 = dalloc<double>(owned, ncg);
@@ -1620,6 +1621,19 @@ int ugkwp_eval_uniform(int n, uint64_t seed, const uint64_t* id, uint32_t step, 
         uint32_t* dd = t.up(d, n);
         double* o = t.up<double>(nullptr, n);
         launch_eval_uniform(n, seed, di, step, purpose, dd, o, nullptr);
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(out, o, sizeof(double) * n, hipMemcpyDeviceToHost));
+    });
+}
+
+int ugkwp_eval_neg_log(int n, const double* u, double* out)
+{
+    if (n < 0 || !u || !out) return UGKWP_EINVAL;
+    return guarded(nullptr, [&] {
+        Tmp t;
+        double* du = t.up(u, n);
+        double* o = t.up<double>(nullptr, n);
+        launch_eval_neg_log(n, du, o, nullptr);
         HIPCHK(hipDeviceSynchronize());
         HIPCHK(hipMemcpy(out, o, sizeof(double) * n, hipMemcpyDeviceToHost));
     });

@@ -27,7 +27,7 @@ EXPORTED = [
     "ugkwp_set_material", "ugkwp_init_batch", "ugkwp_step", "ugkwp_num_instances",
     "ugkwp_get_fields", "ugkwp_get_tallies", "ugkwp_get_diag", "ugkwp_get_counters",
     "ugkwp_pool_size", "ugkwp_get_pool", "ugkwp_set_pool", "ugkwp_eval_phi", "ugkwp_eval_coef",
-    "ugkwp_eval_uniform", "ugkwp_eval_sample_nu", "ugkwp_record", "ugkwp_recorded_steps",
+    "ugkwp_eval_uniform", "ugkwp_eval_neg_log", "ugkwp_eval_sample_nu", "ugkwp_record", "ugkwp_recorded_steps",
     "ugkwp_adjoint", "ugkwp_autotune", "ugkwp_get_totals", "ugkwp_set_phase_times",
 ]
 
@@ -142,6 +142,7 @@ def load():
     L.ugkwp_eval_phi.argtypes = [C.c_int, _pd, C.c_int, _pd, _d, _d, _pd]
     L.ugkwp_eval_coef.argtypes = [C.c_int, _pd, _pd, _pd, _pd]
     L.ugkwp_eval_uniform.argtypes = [C.c_int, C.c_uint64, _pu64, C.c_uint32, C.c_uint32, _pu32, _pd]
+    L.ugkwp_eval_neg_log.argtypes = [C.c_int, _pd, _pd]
     L.ugkwp_eval_sample_nu.argtypes = [C.c_int, _pd, _pd, _pd, _pd, _pd, _pd]
     _lib = L
     return L
@@ -416,6 +417,15 @@ def eval_uniform(seed, ids, step, purpose, d):
     rc = load().ugkwp_eval_uniform(len(ids), int(seed), _p(ids, _pu64), step, purpose, _p(d, _pu32), _p(out))
     if rc:
         raise UGKWPError(rc, "eval_uniform")
+    return out
+
+
+def eval_neg_log(u):
+    u = _f64(u)
+    out = np.zeros_like(u)
+    rc = load().ugkwp_eval_neg_log(len(u), _p(u), _p(out))
+    if rc:
+        raise UGKWPError(rc, "eval_neg_log")
     return out
 
 

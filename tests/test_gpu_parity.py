@@ -91,6 +91,24 @@ def test_uniform_stream_bit_exact():
         assert np.array_equal(g, o)
 
 
+def test_neg_log_within_two_ulp():
+    """-ln(u) of the particle flights against the extended-precision host log:
+    random 52-bit uniforms as the stream produces them, both ends of (0, 1),
+    and the range around sqrt(1/2) where the reduction switches."""
+    rng = np.random.default_rng(3)
+    k = rng.integers(0, 2**52, size=1 << 20, dtype=np.uint64)
+    u = (k.astype(np.float64) + 0.5) * 2.0**-52
+    i = np.arange(1, 4097, dtype=np.float64)
+    edges = np.concatenate([i * 2.0**-53, 1.0 - i * 2.0**-53, 2.0**-np.arange(1, 60, dtype=np.float64),
+                            np.sqrt(0.5) * (1.0 + np.linspace(-1e-12, 1e-12, 4097))])
+    u = np.concatenate([u, edges])
+    got = ugkwp.eval_neg_log(u)
+    ref = -np.log(u.astype(np.longdouble))
+    ulp = np.spacing(np.abs(ref.astype(np.float64))).astype(np.longdouble)
+    err = np.abs(got.astype(np.longdouble) - ref) / ulp
+    assert float(err.max()) <= 2.5, float(err.max())
+
+
 def test_coefficients_match_oracle():
     s = np.concatenate([[0.0], np.geomspace(1e-14, 1e8, 2000), [0.999999, 1.0, 1.000001, 1.999999, 2.0]])
     c4, w, c2 = ugkwp.eval_coef(s)
