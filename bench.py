@@ -47,8 +47,8 @@ ADJ_SWEEP_BYTES = 48       # rbar, lambda, sigma, phi' and two face coefficients
 # to those sources makes bench.py report the traffic as unknown.
 PUSH_SOURCES = ("kernels.hip", "device_math.hpp", "device_common.hpp", "common.hpp")
 PUSH_TRAFFIC = {
-    "slab": {"sources": "ccab938fa2fb5b4e", "read_per_push": 48.80, "write_per_push": 12.65},
-    "lattice": {"sources": "ccab938fa2fb5b4e", "read_per_push": 66.66, "write_per_push": 22.11},
+    "slab": {"sources": "1e64927d716feb97", "read_per_push": 48.80, "write_per_push": 12.65},
+    "lattice": {"sources": "1e64927d716feb97", "read_per_push": 66.66, "write_per_push": 21.83},
 }
 
 
@@ -210,10 +210,11 @@ def summarize_trace(csv_path, steps, push_kernel="k_push"):
 
 
 def summarize_counters(csv_path, steps, kernel="k_push"):
-    """Per-dispatch average of each counter in a rocprofv3 --pmc CSV over the last
-    `steps` dispatches of the kernel whose name contains `kernel` (all of its
-    dispatches if it ran fewer times), and over the largest dispatches of every
-    other kernel (for a copy-probe run)."""
+    """Per-dispatch average of each counter in a rocprofv3 --pmc CSV over the
+    dispatches of the kernel whose name contains `kernel` in the timed steps
+    (the `steps` before the min(steps, 50) phase-timed ones at the end, as in
+    summarize_trace; the last `steps` if the run is shorter), and over the
+    largest dispatches of every other kernel (for a copy-probe run)."""
     import csv
     rows = list(csv.DictReader(open(csv_path)))
     by = {}
@@ -225,7 +226,8 @@ def summarize_counters(csv_path, steps, kernel="k_push"):
     for (name, ctr), v in sorted(by.items()):
         v.sort()
         if kernel in name:
-            sel = v[-steps:]
+            nph = min(steps, 50)
+            sel = v[-steps - nph:-nph] if len(v) >= steps + nph else v[-steps:]
         else:
             gmax = max(g for _, _, g in v)
             sel = [t for t in v if t[2] == gmax]
