@@ -500,6 +500,7 @@ __device__ inline void lds_tally(TallyTable& T, const Dev& D, uint32_t type, uin
 struct Flight {
     double x, y, ox, oy;   // position and direction (mu in 1-D)
     double t, t_rem, tau;  // time flown, flight time left, flight scale in this cell
+    double u_odd;          // the odd draw of the last Philox block (draws 2m and 2m+1 share one)
     uint32_t d;            // FLIGHT draws used
     int ix, iy;
     bool coll;
@@ -507,7 +508,10 @@ struct Flight {
 
 __device__ inline void draw_flight(const Consts& K, const Geo& I, uint64_t id, uint32_t step, Flight& f)
 {
-    const double u = keyed_uniform(I.seed, id, step, PURPOSE_FLIGHT, f.d++);
+    double u;
+    if ((f.d & 1u) == 0) keyed_uniform_pair(I.seed, id, step, PURPOSE_FLIGHT, f.d, u, f.u_odd);
+    else u = f.u_odd;                  // the first crossing's draw: no second Philox evaluation
+    f.d++;
     const double a = f.tau * neg_log_unit(u);
     f.coll = a < K.dt - f.t;
     f.t_rem = f.coll ? a : K.dt - f.t;
