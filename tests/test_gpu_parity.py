@@ -262,6 +262,58 @@ def test_batch_full_size_sampled_instances():
         compare_state(ctx, s, probs[k], inst=k, what=f"instance {k}")
 
 
+# ------------------------------------------------------------ steps enqueued ahead of the host
+
+def test_one_call_of_many_steps_matches_single_steps_and_oracle():
+    """ugkwp_step(ctx, 40) runs batches of steps without host round trips; a
+    2-D medium whose source iteration needs more sweeps than the first batch
+    speculates makes a step be taken up alone mid-batch.  The result equals
+    40 calls of one step and the oracle."""
+    p = W.c5_lognormal(n=24, G=5, w_ref=2e-4, pool_cap=1 << 21, dt=2e-2)
+    a = ugkwp.from_problem(p)
+    b = ugkwp.from_problem(p)
+    a.get_totals(reset=True)
+    say("[run-ahead] one call of 40 steps vs 40 calls")
+    assert a.step(40) == ugkwp.OK
+    smax = 0
+    for n in range(40):
+        b.step(1)
+        smax = max(smax, b.get_diag()["sweeps_max"])
+    assert smax > 5, smax                  # the first batch launches 5 sweeps per step
+    t = a.get_totals()
+    assert t["steps"] == 40
+    ra, Ta, pa = a.get_fields()
+    rb, Tb, pb = b.get_fields()
+    assert relerr(ra, rb) <= 1e-12 and relerr(Ta, Tb) <= 1e-12 and relerr(pa, pb) <= 1e-12
+    assert a.get_counters() == b.get_counters() and a.pool_size() == b.pool_size()
+    sim = oracle.Sim(p)
+    sim.step(40)
+    compare_state(a, sim, p, what="40 steps in one call")
+
+
+def test_pool_error_mid_batch_leaves_the_last_committed_step():
+    """A step that overflows the pool inside a batch: the steps before it are
+    committed, it and the steps enqueued after it leave no trace."""
+    p = W.c1_marshak_like(pool_cap=3000)
+    ref = ugkwp.from_problem(p)
+    k = 0
+    while ref.step(1, check=False) == ugkwp.OK:
+        k += 1
+        assert k < 40
+    assert k >= 2
+    good = ugkwp.from_problem(p)
+    good.step(k)
+    ctx = ugkwp.from_problem(p)
+    ctx.get_totals(reset=True)
+    assert ctx.step(k + 10, check=False) == ugkwp.EPOOL
+    assert ctx.get_totals()["steps"] == k
+    assert ctx.get_counters() == good.get_counters() and ctx.pool_size() == good.pool_size()
+    for x, y in zip(ctx.get_fields(), good.get_fields()):
+        assert relerr(x, y) <= 1e-12
+    # the context goes on from there like one that never saw the failure
+    assert ctx.step(1, check=False) == ugkwp.EPOOL
+
+
 # ------------------------------------------------------------ launch modes
 
 def test_graph_replay_matches_direct_launches():
