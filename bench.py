@@ -39,6 +39,7 @@ PUSH_BYTES_WRITE = 12      # new position and cell word of a survivor (updated i
 PUSH_BYTES_DEAD = 4        # empty-slot mark of a particle absorbed or gone
 SPINUP = {"slab": 500, "lattice": 300, "batch": 100, "adjoint": 0}
 ADJ_SWEEP_BYTES = 48       # rbar, lambda, sigma, phi' and two face coefficients per (cell, group) update
+SI_SWEEP_BYTES = 64        # Q, lambda, sigma, phi^k, rho^k, one face D read; rho^{k+1}, phi^{k+1} written
 
 # HBM bytes per push of k_push measured with rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # each scaled by its reading for a plain 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE
@@ -368,10 +369,10 @@ def main():
         c.step(nph)
     ptot = [c.get_totals() for c in ctxs]
     ph = {k: sum(t[k] for t in ptot) / max(nph, 1) for k in ("ms_sample", "ms_push", "ms_macro", "ms_si", "ms_sort")}
-    ph_sweeps = sum(t["sweeps_sum"] for t in ptot)
     # cell-group updates: every instance's cell-groups times its own sweep count
-    cg_per_inst = [p.ncell * p.G for p in probs]
-    mean_cg = ncg / len(probs)
+    cgu = sum(t["cg_updates"] for t in tots)
+    ph_cgu = sum(t["cg_updates"] for t in ptot)
+    ms_si_ph = sum(t["ms_si"] for t in ptot)
 
     value = pushes / elapsed
     br, bw, bd = (PUSH_BYTES_READ, PUSH_BYTES_WRITE, PUSH_BYTES_DEAD) if probs[0].dim == 1 else BYTES_2D
@@ -403,9 +404,8 @@ def main():
                                   f"autotuned: {tuned[0]['blocks']} blocks, {tuned[0]['ppt']} particles per thread "
                                   f"({tuned[0]['us_best']:.1f} vs {tuned[0]['us_default']:.1f} us default)"
                                   + (f", per context ({len(tuned)})" if len(tuned) > 1 else ""))},
-        "cell_group_updates_per_s": mean_cg * sweeps / elapsed,
-        "cell_group_updates_per_s_si_only": (mean_cg * ph_sweeps / (ph["ms_si"] * nph * 1e-3)
-                                             if ph["ms_si"] > 0 else None),
+        "cell_group_updates_per_s": cgu / elapsed,
+        "cell_group_updates_per_s_si_only": ph_cgu / (ms_si_ph * 1e-3) if ms_si_ph > 0 else None,
         "push_kernel_pushes_per_s": pushes / (ms_push * 1e-3),
         "push_kernel_avg_us": ms_push * 1e3 / max(args.steps, 1),
         "sweeps_per_step": sweeps / max(args.steps, 1) / len(probs),
@@ -419,6 +419,16 @@ def main():
                      "kernel": f"k_push<{probs[0].dim}>", "algorithmic_bytes_per_push":
                      f"{br} read + {bw} per survivor + {bd} per absorbed/escaped particle"},
     }
+    if wl == "batch" and ms_si_ph > 0:
+        # the source iteration dominates the batched step: its phase (every sweep and
+        # decide launch between two events) is the roofline kernel, the push is kept
+        si_ach = SI_SWEEP_BYTES * ph_cgu / (ms_si_ph * 1e-3) / 1e9
+        out["roofline_push"] = out["roofline"]
+        out["roofline"] = {"bound": "hbm", "achieved": si_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": si_ach / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "k_si_sweep (the source-iteration phase: sweeps and decides)",
+                           "algorithmic_bytes_per_update": SI_SWEEP_BYTES,
+                           "from": f"{nph} further steps with every phase timed"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(probs, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -136,6 +136,8 @@ typedef struct {
     int64_t sweeps_max;      /* sum of per-step largest sweep counts               */
     int64_t sweeps_sum;      /* sum over steps and instances of sweep counts       */
     double ms_sample, ms_push, ms_macro, ms_si, ms_sort;   /* as in ugkwp_diag    */
+    int64_t cg_updates;      /* (cell, group) updates of the source iteration: sum over
+                                steps and instances of sweeps x cells x groups      */
 } ugkwp_totals;
 
 /* ---- context ---- */

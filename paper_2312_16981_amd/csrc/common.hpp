@@ -160,7 +160,8 @@ struct Dev {
     const uint8_t* pinned;
     // per instance
     InstState* ist;
-    Resid* res;                 // [n_inst][RES_SLOTS][RES_SUB]
+    Resid* res;                 // [RES_SLOTS][n_inst][RES_SUB]
+    uint8_t* wave_run;          // [n_cg/64 rounded up to 4] 1 while the wavefront's instance iterates (batches)
     double* diag;               // [n_inst][8] (folded from diag_sub each step)
     double* diag_sub;           // [n_inst][DIAG_SUB][8]
     // context-wide counters

@@ -920,12 +920,23 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
                                                           double* phi_out, int decide_prev)
 {
     if (!gate_open(D, K, 0)) return;
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    // batches: a block whose four wavefronts all belong to converged instances
+    // returns after one load (the flags of its wavefronts, one byte each)
+    uint32_t flags = 0xFFFFFFFFu;
+    if (K.n_inst > 1) {
+        if (FIRST) {
+            if (lane == 0) D.wave_run[(int64_t)blockIdx.x * (SI_THREADS / WAVE) + wid] = 1;
+        } else {
+            flags = ((const uint32_t*)D.wave_run)[blockIdx.x];
+            if (flags == 0) return;
+        }
+    }
     const int64_t j = (int64_t)blockIdx.x * SI_THREADS + threadIdx.x;
     const Slot s = decode_slot(D, K, j);
     const Inst& I = D.inst[s.inst];
-    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
 
-    bool run = D.ist[s.inst].conv_sweeps == 0 && j < K.n_cg;
+    bool run = ((flags >> (8 * wid)) & 0xFFu) != 0 && D.ist[s.inst].conv_sweeps == 0 && j < K.n_cg;
     if (decide_prev) {
         __shared__ int stop;
         if (wid == 0) {
@@ -1086,9 +1097,13 @@ __global__ void k_si_decide(Dev D, Consts K, int k)
     const int lane = threadIdx.x & (WAVE - 1);
     if (inst >= K.n_inst || D.ist[inst].conv_sweeps != 0) return;
     const bool conv = si_converged(D, K, inst, k, lane);
-    if (lane == 0 && conv) {
-        D.ist[inst].conv_sweeps = k + 1;
-        atomicAdd((unsigned long long*)(D.counters + CNT_CONV), 1ull);
+    if (conv) {
+        // the instance's wavefronts stop running in the following sweeps
+        for (int64_t w = D.inst_cg[inst] / WAVE + lane; w < D.inst_cg[inst + 1] / WAVE; w += WAVE) D.wave_run[w] = 0;
+        if (lane == 0) {
+            D.ist[inst].conv_sweeps = k + 1;
+            atomicAdd((unsigned long long*)(D.counters + CNT_CONV), 1ull);
+        }
     }
 }
 

@@ -461,6 +461,12 @@ struct ugkwp_ctx {
         d.step = dalloc<uint32_t>(owned, 1);
         HIPCHK(hipMemsetAsync(d.step, 0, sizeof(uint32_t), st));
         d.res = dalloc<Resid>(owned, (size_t)n_inst * RES_SLOTS * RES_SUB);
+        {
+            // one flag per wavefront of slots, read four at a time by the sweeps' blocks
+            const size_t nflag = ((size_t)(n_cg / WAVE) + 3) / 4 * 4;
+            d.wave_run = dalloc<uint8_t>(owned, nflag);
+            HIPCHK(hipMemsetAsync(d.wave_run, 0, nflag, st));
+        }
         diag_sub_dev = host_diag ? nullptr : dalloc<double>(owned, (size_t)n_inst * DIAG_SUB * 8);
         cur_rec = 0;
         point_record(d, 0, 0);
@@ -851,9 +857,11 @@ struct ugkwp_ctx {
         dg.n_pushed = n_alive + s.total[0];
         dg.n_alive_out = (int64_t)s.counters[CNT_SURV];
         int smax = 0, ssum = 0;
+        int64_t cgu = 0;
         for (int q = 0; q < n_inst; ++q) {
             smax = std::max(smax, s.ist[q].conv_sweeps);
             ssum += s.ist[q].conv_sweeps;
+            cgu += (int64_t)s.ist[q].conv_sweeps * inst[q].ncell * inst[q].G;
             double fold[8];
             const double* g = s.diag + 8 * q;
             if (host_diag) {
@@ -891,6 +899,7 @@ struct ugkwp_ctx {
         tot.n_survived += dg.n_alive_out;
         tot.sweeps_max += dg.sweeps_max;
         tot.sweeps_sum += dg.sweeps_sum;
+        tot.cg_updates += cgu;
         tot.ms_sample += dg.ms_sample;
         tot.ms_push += dg.ms_push;
         tot.ms_macro += dg.ms_macro;

@@ -66,7 +66,7 @@ class AdjointStats(C.Structure):
 class Totals(C.Structure):
     _fields_ = [("steps", C.c_int64), ("n_pushed", C.c_int64), ("n_survived", C.c_int64),
                 ("sweeps_max", C.c_int64), ("sweeps_sum", C.c_int64), ("ms_sample", _d), ("ms_push", _d),
-                ("ms_macro", _d), ("ms_si", _d), ("ms_sort", _d)]
+                ("ms_macro", _d), ("ms_si", _d), ("ms_sort", _d), ("cg_updates", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
