@@ -32,6 +32,33 @@ __device__ inline double temp_weight(const Dev& D, const Consts& K, int cell)
     return D.pinned[cell] ? 0.0 : K.dt / (K.eps * K.eps * D.cvol[cell]);
 }
 
+__device__ inline bool adj_gate(const Adj& A, uint32_t gate)
+{
+    return gate == GATE_OFF || A.status[ADJ_DONE] == (unsigned long long)gate;
+}
+
+// Convergence of instance inst after sweep k, one wavefront (lane l reads
+// sub-slot l): relative max-norm change of mu at most 1e-15, 1e-13 from the
+// 61st sweep on.
+__device__ inline bool adj_converged(const Adj& A, int inst, int k, int lane)
+{
+    const AdjResid r = A.res[((int64_t)inst * RES_SLOTS + k % RES_SLOTS) * RES_SUB + lane];
+    const double dm = wave_nmax(bitsd(r.dmu)), mm = wave_nmax(bitsd(r.mu));
+    const double tol = k >= 60 ? 1e-13 : 1e-15;
+    return dm <= tol * mm;
+}
+
+// Record instance inst converged after ns sweeps of reverse step r.
+__device__ inline void adj_mark_converged(const Dev& D, const Adj& A, int inst, int ns, int r)
+{
+    const Inst& I = D.inst[inst];
+    A.conv[inst] = ns;
+    atomicAdd(A.status + ADJ_CONV, 1ull);
+    atomicAdd(A.status + ADJ_CGU, (unsigned long long)ns * (unsigned long long)(I.ncell * I.G));
+    atomicMax(A.status + ADJ_MAXK, (unsigned long long)ns);
+    atomicMax(A.stepk + r, ns);
+}
+
 // ---------------------------------------------------------------------------
 // recording, launched behind the step's commit with the step's own buffers:
 // D.T_new holds T^{n+1}
@@ -116,9 +143,14 @@ __global__ void k_adj_face(Dev D, Consts K, Adj A, int inst, int axis)
 // per recorded step, in reverse
 
 // phi and phi' at T^{n+1}; mu^0 = Tbar; convergence state of the step reset.
-__global__ __launch_bounds__(ADJ_THREADS) void k_adj_prep(Dev D, Consts K, Adj A, int r)
+__global__ __launch_bounds__(ADJ_THREADS) void k_adj_prep(Dev D, Consts K, Adj A, int r, uint32_t gate)
 {
+    if (!adj_gate(A, gate)) return;
     const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
+    if (j == 0) {
+        A.status[ADJ_CONV] = 0;
+        A.stepk[r] = 0;
+    }
     const Slot s = decode_slot(D, K, j);
     const Inst& I = D.inst[s.inst];
     const int g = s.g, G = I.G, Gp = I.Gp;
@@ -199,15 +231,32 @@ __device__ inline FaceRef face_ref(const Inst& I, int64_t j, int lcell, int g, i
 //   mu^{k+1} = Tbar + sum_g phi_g' [ -w sigma/(1+lambda) mu^k + lambda/(1+lambda) rbar
 //                                    + (dt/V) sum_f S_f D_f (bbar_nb - bbar) ].
 // Residual maxima go to 64 sub-slots of the instance; k_adj_decide reads them.
+// With decide_prev (single instance), every block first takes the decision of
+// sweep k-1 from those sub-slots itself; block 0 records it.
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj A, int k, const double* mu_in,
-                                                           double* mu_out)
+                                                           double* mu_out, int r, uint32_t gate, int decide_prev)
 {
+    if (!adj_gate(A, gate)) return;
     const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
     const Slot s = decode_slot(D, K, j);
     const Inst& I = D.inst[s.inst];
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
 
-    const bool run = A.conv[s.inst] == 0 && j < K.n_cg;
+    bool run = A.conv[s.inst] == 0 && j < K.n_cg;
+    if (decide_prev) {
+        // the whole block stops when the iteration has converged (now or before)
+        __shared__ int stop;
+        if (wid == 0) {
+            const int cs = A.conv[0];
+            const bool conv = cs == 0 && adj_converged(A, 0, k - 1, lane);
+            if (lane == 0) {
+                stop = (conv || cs != 0) ? 1 : 0;
+                if (conv && blockIdx.x == 0) adj_mark_converged(D, A, 0, k, r);
+            }
+        }
+        __syncthreads();
+        if (stop) return;
+    }
     const int64_t rel = j - I.cg_off;
     if (run && rel >= 0 && rel < RES_SUB) {
         AdjResid z = {0ull, 0ull};
@@ -279,30 +328,45 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
     }
 }
 
-// Convergence after sweep k, one wavefront per instance still running
-// (relative max-norm change 1e-15, 1e-13 from sweep 60 on).
-__global__ void k_adj_decide(Dev D, Consts K, Adj A, int k)
+// Convergence after sweep k, one wavefront per instance still running.
+__global__ void k_adj_decide(Dev D, Consts K, Adj A, int k, int r, uint32_t gate)
 {
+    if (!adj_gate(A, gate)) return;
     const int inst = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
     if (inst >= K.n_inst || A.conv[inst] != 0) return;
-    const AdjResid r = A.res[((int64_t)inst * RES_SLOTS + k % RES_SLOTS) * RES_SUB + lane];
-    const double dm = wave_nmax(bitsd(r.dmu)), mm = wave_nmax(bitsd(r.mu));
-    const double tol = k >= 60 ? 1e-13 : 1e-15;
-    if (lane == 0 && dm <= tol * mm) {
-        const Inst& I = D.inst[inst];
-        A.conv[inst] = k + 1;
-        atomicAdd(A.status + ADJ_CONV, 1ull);
-        atomicAdd(A.status + ADJ_CGU, (unsigned long long)(k + 1) * (unsigned long long)(I.ncell * I.G));
-        atomicMax(A.status + ADJ_MAXK, (unsigned long long)(k + 1));
-    }
+    if (adj_converged(A, inst, k, lane) && lane == 0) adj_mark_converged(D, A, inst, k + 1, r);
 }
 
 // With the converged mu: cotangents of lambda (= s), sigma, Q, A rho^h and D_f;
 // dJ/dkappa += S_g dJ/dsigma; rbar^n = bbar + A ubar; Tbar^n = mu.
-__global__ __launch_bounds__(ADJ_THREADS) void k_adj_grad(Dev D, Consts K, Adj A, int r)
+// last_sweep >= 0 (single instance): the convergence after that sweep is
+// decided here (wavefront 0 of every block, the same answer; block 0 records
+// it).  The step's cotangents are formed only when every instance converged
+// and nothing non-finite was seen; block 0 then counts the step done.
+__global__ __launch_bounds__(ADJ_THREADS) void k_adj_grad(Dev D, Consts K, Adj A, int r, uint32_t gate,
+                                                          int last_sweep)
 {
+    // the done count below advances while other blocks may still start
+    if (!adj_gate(A, gate) && !(gate != GATE_OFF && A.status[ADJ_DONE] == (unsigned long long)gate + 1)) return;
+    int ns_single = 0;
+    if (last_sweep >= 0) {
+        __shared__ int sh_ns;
+        if (threadIdx.x < WAVE) {
+            int ns = A.conv[0];
+            if (ns == 0 && adj_converged(A, 0, last_sweep, threadIdx.x)) ns = last_sweep + 1;
+            if (threadIdx.x == 0) sh_ns = ns;
+        }
+        __syncthreads();
+        ns_single = sh_ns;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && ns_single != 0 && A.conv[0] == 0)
+            adj_mark_converged(D, A, 0, ns_single, r);
+        if (ns_single == 0 || A.status[ADJ_ERR] != 0) return;
+    } else if (A.status[ADJ_CONV] != (unsigned long long)K.n_inst || A.status[ADJ_ERR] != 0) {
+        return;
+    }
     const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
+    if (j == 0 && gate != GATE_OFF) A.status[ADJ_DONE] = (unsigned long long)gate + 1;
     if (j >= K.n_cg) return;
     const Slot s = decode_slot(D, K, j);
     if (!s.active) {
@@ -312,7 +376,8 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_grad(Dev D, Consts K, Adj A
     const Inst& I = D.inst[s.inst];
     const int g = s.g;
     const int cell = I.cell_off + s.lcell;
-    const double* mu = (A.conv[s.inst] & 1) ? A.mu1 : A.mu0;
+    const int ns = last_sweep >= 0 ? ns_single : A.conv[s.inst];
+    const double* mu = (ns & 1) ? A.mu1 : A.mu0;
     const double mui = mu[cell];
     const double wi = temp_weight(D, K, cell);
     const double lam = D.sv[j], sig = D.sig[j];
@@ -383,22 +448,32 @@ void launch_adj_face(const Dev& D, const Consts& K, const Adj& A, int inst, int 
     if (nslots > 0) k_adj_face<<<ablocks(nslots), ADJ_THREADS, 0, st>>>(D, K, A, inst, axis);
 }
 
-void launch_adj_prep(const Dev& D, const Consts& K, const Adj& A, int r, hipStream_t st)
+void launch_adj_prep(const Dev& D, const Consts& K, const Adj& A, int r, uint32_t gate, hipStream_t st)
 {
-    k_adj_prep<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, r);
+    k_adj_prep<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, r, gate);
 }
 
-void launch_adj_sweep(const Dev& D, const Consts& K, const Adj& A, int k, hipStream_t st)
+void launch_adj_decide(const Dev& D, const Consts& K, const Adj& A, int k, int r, uint32_t gate, hipStream_t st)
 {
-    const double* in = (k & 1) ? A.mu1 : A.mu0;
-    double* out = (k & 1) ? A.mu0 : A.mu1;
-    k_adj_sweep<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, k, in, out);
-    k_adj_decide<<<ablocks((int64_t)K.n_inst * WAVE), ADJ_THREADS, 0, st>>>(D, K, A, k);
+    k_adj_decide<<<ablocks((int64_t)K.n_inst * WAVE), ADJ_THREADS, 0, st>>>(D, K, A, k, r, gate);
 }
 
-void launch_adj_grad(const Dev& D, const Consts& K, const Adj& A, int r, hipStream_t st)
+void launch_adj_sweeps(const Dev& D, const Consts& K, const Adj& A, int k0, int k1, int r, uint32_t gate,
+                       hipStream_t st)
 {
-    k_adj_grad<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, r);
+    const bool fold = K.n_inst == 1;
+    for (int k = k0; k < k1; ++k) {
+        const double* in = (k & 1) ? A.mu1 : A.mu0;
+        double* out = (k & 1) ? A.mu0 : A.mu1;
+        k_adj_sweep<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, k, in, out, r, gate, fold && k > k0 ? 1 : 0);
+        if (!fold) launch_adj_decide(D, K, A, k, r, gate, st);
+    }
+}
+
+void launch_adj_grad(const Dev& D, const Consts& K, const Adj& A, int r, uint32_t gate, int last_sweep,
+                     hipStream_t st)
+{
+    k_adj_grad<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, r, gate, K.n_inst == 1 ? last_sweep : -1);
 }
 
 }  // namespace ugk

@@ -21,7 +21,11 @@ struct AdjResid {
     unsigned long long dmu, mu;     // max |mu^{k+1} - mu^k|, max |mu^{k+1}| as IEEE bits
 };
 
-enum { ADJ_CONV = 0, ADJ_ERR = 1, ADJ_CGU = 2, ADJ_MAXK = 3, ADJ_N_STATUS = 4 };
+// Status words: ADJ_CONV converged instances of the reverse step in progress
+// (cleared by its set-up), ADJ_ERR non-finite value seen, ADJ_CGU (cell, group)
+// updates of the converged sweeps so far, ADJ_MAXK most sweeps any reverse step
+// needed so far, ADJ_DONE reverse steps completed (the gate of the next one).
+enum { ADJ_CONV = 0, ADJ_ERR = 1, ADJ_CGU = 2, ADJ_MAXK = 3, ADJ_DONE = 4, ADJ_N_STATUS = 5 };
 
 struct Adj {
     // record: step r occupies [r * n_cg, (r+1) * n_cg) and [r * ncell, (r+1) * ncell)
@@ -46,9 +50,8 @@ struct Adj {
     double* Dhy;
     AdjResid* res;        // [n_inst][RES_SLOTS][RES_SUB]
     int* conv;            // [n_inst] sweeps at convergence, 0 while running
-    unsigned long long* status;   // ADJ_CONV: converged instances, ADJ_ERR: non-finite seen,
-                                  // ADJ_CGU: (cell, group) updates of the converged sweeps,
-                                  // ADJ_MAXK: most sweeps an instance needed
+    int* stepk;           // [record steps] most sweeps an instance needed in that step
+    unsigned long long* status;   // ADJ_* words
 };
 
 hipError_t set_head_series_adj(const HeadSeries& hs);
@@ -56,9 +59,20 @@ void launch_rec_store(const Dev& D, const Consts& K, const Adj& A, int r, hipStr
 void launch_adj_coef(const Dev& D, const Consts& K, const Adj& A, hipStream_t st);
 void launch_adj_face(const Dev& D, const Consts& K, const Adj& A, int inst, int axis, int64_t nslots,
                      hipStream_t st);
-void launch_adj_prep(const Dev& D, const Consts& K, const Adj& A, int r, hipStream_t st);
-// sweep k of the transposed iteration followed by its convergence decision
-void launch_adj_sweep(const Dev& D, const Consts& K, const Adj& A, int k, hipStream_t st);
-void launch_adj_grad(const Dev& D, const Consts& K, const Adj& A, int r, hipStream_t st);
+// The launches of reverse step q (recorded step r = nrec - 1 - q) carry q as
+// their gate: they run only when q reverse steps are done (GATE_OFF: always),
+// so reverse steps can be enqueued ahead and the ones behind a step that did
+// not converge return at once.
+void launch_adj_prep(const Dev& D, const Consts& K, const Adj& A, int r, uint32_t gate, hipStream_t st);
+// sweeps k0..k1-1 of the transposed iteration, each one's convergence decided
+// before the next (in the next sweep for a single instance, else by a decide
+// launch after every sweep)
+void launch_adj_sweeps(const Dev& D, const Consts& K, const Adj& A, int k0, int k1, int r, uint32_t gate,
+                       hipStream_t st);
+void launch_adj_decide(const Dev& D, const Consts& K, const Adj& A, int k, int r, uint32_t gate, hipStream_t st);
+// the cotangents of step r once its iteration converged (a single instance's
+// convergence after last_sweep is decided here), and the step counted done
+void launch_adj_grad(const Dev& D, const Consts& K, const Adj& A, int r, uint32_t gate, int last_sweep,
+                     hipStream_t st);
 
 }  // namespace ugk

@@ -938,11 +938,14 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
 
     bool run = ((flags >> (8 * wid)) & 0xFFu) != 0 && D.ist[s.inst].conv_sweeps == 0 && j < K.n_cg;
     if (decide_prev) {
+        // the whole block stops when the iteration has converged (decided now or
+        // by an earlier sweep): a speculative sweep past convergence costs little
         __shared__ int stop;
         if (wid == 0) {
-            const bool conv = D.ist[0].conv_sweeps == 0 && si_converged(D, K, 0, k - 1, lane);
+            const int cs = D.ist[0].conv_sweeps;
+            const bool conv = cs == 0 && si_converged(D, K, 0, k - 1, lane);
             if (lane == 0) {
-                stop = conv ? 1 : 0;
+                stop = (conv || cs != 0) ? 1 : 0;
                 if (conv && blockIdx.x == 0) {
                     D.ist[0].conv_sweeps = k;
                     atomicAdd((unsigned long long*)(D.counters + CNT_CONV), 1ull);
@@ -950,7 +953,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
             }
         }
         __syncthreads();
-        run = run && !stop;
+        if (stop) return;
     }
     const int64_t rel = j - I.cg_off;
     if (run && rel >= 0 && rel < RES_SUB) {

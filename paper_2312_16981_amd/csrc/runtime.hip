@@ -1098,6 +1098,7 @@ struct ugkwp_ctx {
         A.Dhy = ralloc<double>(nfy);
         A.res = ralloc<AdjResid>((size_t)n_inst * RES_SLOTS * RES_SUB);
         A.conv = ralloc<int>((size_t)n_inst);
+        A.stepk = ralloc<int>((size_t)max_steps);
         A.status = ralloc<unsigned long long>(ADJ_N_STATUS);
         if (!h_adj) HIPCHK(hipHostMalloc((void**)&h_adj, sizeof(unsigned long long) * ADJ_N_STATUS, hipHostMallocDefault));
         rec_cap = max_steps;
@@ -1124,44 +1125,94 @@ struct ugkwp_ctx {
             launch_adj_face(D, K, A, q, 0, (int64_t)(I.nx + 1) * I.ny * I.Gp, st);
             if (dim == 2) launch_adj_face(D, K, A, q, 1, (int64_t)I.nx * (I.ny + 1) * I.Gp, st);
         }
+        // Reverse steps q = 0, 1, ... (recorded step r = nrec - 1 - q) are enqueued
+        // RUN_AHEAD at a time with q as their gate; each launches the sweeps the
+        // most demanding step so far needed plus one.  One synchronisation per
+        // batch reads how many completed; a step that did not converge is taken
+        // up alone (more sweeps) and the next batch starts after it.
         const int kmax = 1000;
+        HIPCHK(hipMemsetAsync(A.status, 0, sizeof(unsigned long long) * ADJ_N_STATUS, st));
         int sweeps_sum = 0, sweeps_max = 0;
         double ms_sweeps = 0.0;
-        long long cg_updates = 0;
-        int last = rec_sweeps[nrec - 1];    // sweeps the previous reverse step needed
-        for (int r = nrec - 1; r >= 0; --r) {
-            HIPCHK(hipMemsetAsync(A.status, 0, sizeof(unsigned long long) * ADJ_N_STATUS, st));
-            launch_adj_prep(D, K, A, r, st);
-            HIPCHK(hipEventRecord(ev[2], st));
-            int k = 0;
-            const int first = std::min(kmax, last + 1);
-            for (; k < first; ++k) launch_adj_sweep(D, K, A, k, st);
-            for (;;) {
+        int last = rec_sweeps[nrec - 1];    // first guess: the forward's last step
+        std::vector<int> hk(RUN_AHEAD);
+        auto sweep_ms = [&](hipEvent_t a, hipEvent_t b) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, a, b));
+            return (double)ms;
+        };
+        int done = 0;
+        while (done < nrec) {
+            const int m = std::min(RUN_AHEAD, nrec - done);
+            const int spec = std::min(kmax, last + 1);
+            double* const rbar0 = A.rbar;
+            double* const rbar1 = A.rbar_next;
+            for (int i = 0; i < m; ++i) {
+                const uint32_t q = (uint32_t)(done + i);
+                const int r = nrec - 1 - (int)q;
+                launch_adj_prep(D, K, A, r, q, st);
+                HIPCHK(hipEventRecord(sev[i][0], st));
+                launch_adj_sweeps(D, K, A, 0, spec, r, q, st);
+                HIPCHK(hipEventRecord(sev[i][1], st));
+                launch_adj_grad(D, K, A, r, q, spec - 1, st);
+                std::swap(A.rbar, A.rbar_next);
+            }
+            const int r_lo = nrec - done - m;    // recorded steps r_lo .. nrec-1-done
+            HIPCHK(hipMemcpyAsync(h_adj, A.status, sizeof(unsigned long long) * ADJ_N_STATUS,
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(hk.data(), A.stepk + r_lo, sizeof(int) * m, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const int committed = (int)h_adj[ADJ_DONE] - done;
+            int batch_max = 0;
+            for (int i = 0; i < committed; ++i) {
+                const int kneed = hk[m - 1 - i];
+                ms_sweeps += sweep_ms(sev[i][0], sev[i][1]);
+                sweeps_sum += spec;
+                sweeps_max = std::max(sweeps_max, kneed);
+                batch_max = std::max(batch_max, kneed);
+            }
+            done += committed;
+            if (committed < m) {
+                // reverse step q = done did not complete: its rbar parity, then more sweeps
+                const uint32_t q = (uint32_t)done;
+                const int r = nrec - 1 - done;
+                if (committed & 1) { A.rbar = rbar1; A.rbar_next = rbar0; }
+                else { A.rbar = rbar0; A.rbar_next = rbar1; }
+                double ms = sweep_ms(sev[committed][0], sev[committed][1]);
+                int k = spec;
+                for (;;) {
+                    if (h_adj[ADJ_ERR]) fail(UGKWP_ENONFINITE, "adjoint of step %d produced a non-finite value", r);
+                    if (h_adj[ADJ_CONV] == (unsigned long long)n_inst) break;
+                    if (k >= kmax) fail(UGKWP_ENOCONV, "transposed source iteration of step %d did not converge", r);
+                    const int kend = std::min(k + 4, kmax);
+                    HIPCHK(hipEventRecord(ev[2], st));
+                    launch_adj_sweeps(D, K, A, k, kend, r, q, st);
+                    launch_adj_decide(D, K, A, kend - 1, r, q, st);
+                    HIPCHK(hipEventRecord(ev[3], st));
+                    k = kend;
+                    HIPCHK(hipMemcpyAsync(h_adj, A.status, sizeof(unsigned long long) * ADJ_N_STATUS,
+                                          hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                    ms += sweep_ms(ev[2], ev[3]);
+                }
+                launch_adj_grad(D, K, A, r, q, -1, st);
+                std::swap(A.rbar, A.rbar_next);
+                int kneed = 0;
                 HIPCHK(hipMemcpyAsync(h_adj, A.status, sizeof(unsigned long long) * ADJ_N_STATUS,
                                       hipMemcpyDeviceToHost, st));
+                HIPCHK(hipMemcpyAsync(&kneed, A.stepk + r, sizeof(int), hipMemcpyDeviceToHost, st));
                 HIPCHK(hipStreamSynchronize(st));
-                if (h_adj[ADJ_ERR]) fail(UGKWP_ENONFINITE, "adjoint of step %d produced a non-finite value", r);
-                if (h_adj[ADJ_CONV] == (unsigned long long)n_inst) {
-                    cg_updates += (long long)h_adj[ADJ_CGU];
-                    last = (int)h_adj[ADJ_MAXK];
-                    break;
-                }
-                if (k >= kmax) fail(UGKWP_ENOCONV, "transposed source iteration of step %d did not converge", r);
-                const int kend = std::min(k + 4, kmax);
-                for (; k < kend; ++k) launch_adj_sweep(D, K, A, k, st);
-            }
-            HIPCHK(hipEventRecord(ev[3], st));
-            launch_adj_grad(D, K, A, r, st);
-            {
-                HIPCHK(hipEventSynchronize(ev[3]));
-                float ms = 0;
-                HIPCHK(hipEventElapsedTime(&ms, ev[2], ev[3]));
+                if (h_adj[ADJ_DONE] != (unsigned long long)done + 1)
+                    fail(UGKWP_EHIP, "internal error: reverse step %d not completed", r);
                 ms_sweeps += ms;
+                sweeps_sum += k;
+                sweeps_max = std::max(sweeps_max, kneed);
+                batch_max = std::max(batch_max, kneed);
+                done += 1;
             }
-            std::swap(A.rbar, A.rbar_next);
-            sweeps_sum += k;
-            sweeps_max = std::max(sweeps_max, k);
+            last = batch_max;
         }
+        const long long cg_updates = (long long)h_adj[ADJ_CGU];
         const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
         int64_t out = 0;
         for (int q = 0; q < n_inst; ++q) {
