@@ -359,7 +359,12 @@ def main():
     pushes = sum(t["n_pushed"] for t in tots)
     survivors = sum(t["n_survived"] for t in tots)
     sweeps = sum(t["sweeps_sum"] for t in tots)
+    # the push is timed with a HIP event pair on one step in 8 of the timed steps
+    # (each event costs a few microseconds of GPU time); its rates use those steps
     ms_push = sum(t["ms_push"] for t in tots)
+    n_timed = sum(t["push_timed"] for t in tots)
+    pushes_t = sum(t["n_pushed_timed"] for t in tots)
+    surv_t = sum(t["n_survived_timed"] for t in tots)
     # phase breakdown: a further stretch of steps with every phase timed (each
     # phase event costs a few microseconds, so the timed steps above time the push only)
     nph = min(args.steps, 50)
@@ -376,12 +381,12 @@ def main():
 
     value = pushes / elapsed
     br, bw, bd = (PUSH_BYTES_READ, PUSH_BYTES_WRITE, PUSH_BYTES_DEAD) if probs[0].dim == 1 else BYTES_2D
-    algo_bytes = br * pushes + bw * survivors + bd * (pushes - survivors)
+    algo_bytes = br * pushes_t + bw * surv_t + bd * (pushes_t - surv_t)
     achieved = algo_bytes / (ms_push * 1e-3) / 1e9
     traffic = None
     tr = PUSH_TRAFFIC.get(wl)
     if tr and not args.per_instance and tr["sources"] == push_sources_digest():
-        traffic = (tr["read_per_push"] + tr["write_per_push"]) * pushes / max(args.steps, 1)
+        traffic = (tr["read_per_push"] + tr["write_per_push"]) * pushes_t / max(n_timed, 1)
     out = {
         "metric": "particle-pushes/s (whole UGKWP step, FP64, parity 1e-10 vs oracle)",
         "value": value,
@@ -406,8 +411,9 @@ def main():
                                   + (f", per context ({len(tuned)})" if len(tuned) > 1 else ""))},
         "cell_group_updates_per_s": cgu / elapsed,
         "cell_group_updates_per_s_si_only": ph_cgu / (ms_si_ph * 1e-3) if ms_si_ph > 0 else None,
-        "push_kernel_pushes_per_s": pushes / (ms_push * 1e-3),
-        "push_kernel_avg_us": ms_push * 1e3 / max(args.steps, 1),
+        "push_kernel_pushes_per_s": pushes_t / (ms_push * 1e-3),
+        "push_kernel_avg_us": ms_push * 1e3 / max(n_timed, 1),
+        "push_timed_steps": n_timed,
         "sweeps_per_step": sweeps / max(args.steps, 1) / len(probs),
         "ms_per_step_phases": {"sample": ph["ms_sample"], "push": ph["ms_push"], "macro": ph["ms_macro"],
                                "si": ph["ms_si"], "sort": ph["ms_sort"],
@@ -415,7 +421,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (measured bytes per push x pushes per launch)",
-                     "algorithmic_bytes_per_launch": algo_bytes / max(args.steps, 1),
+                     "algorithmic_bytes_per_launch": algo_bytes / max(n_timed, 1),
                      "kernel": f"k_push<{probs[0].dim}>", "algorithmic_bytes_per_push":
                      f"{br} read + {bw} per survivor + {bd} per absorbed/escaped particle"},
     }

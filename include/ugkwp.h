@@ -121,10 +121,13 @@ typedef struct {
      * dispatch, a few microseconds), ms_macro (now only the event pair after
      * the push: the wave flux and Q are evaluated by the first source-iteration
      * sweep and counted in ms_si), the source iteration, and the counting sort
-     * that keeps the pool ordered by (cell, group).  All but ms_push are 0
-     * unless the context was created with UGKWP_FLAG_PHASE_TIMES (each event
-     * adds a few microseconds to a step). */
+     * that keeps the pool ordered by (cell, group).  Each event adds a few
+     * microseconds to a step, so without UGKWP_FLAG_PHASE_TIMES only the push
+     * of one step in 8 (step index a multiple of 8) is timed and everything
+     * else is 0; with it every phase of every step is timed.  push_timed says
+     * whether this step's ms_push holds a time. */
     double ms_sample, ms_push, ms_macro, ms_si, ms_sort;
+    int push_timed;
 } ugkwp_diag;
 
 /* Running sums over the committed steps since the last reset, so that a caller
@@ -138,6 +141,9 @@ typedef struct {
     double ms_sample, ms_push, ms_macro, ms_si, ms_sort;   /* as in ugkwp_diag    */
     int64_t cg_updates;      /* (cell, group) updates of the source iteration: sum over
                                 steps and instances of sweeps x cells x groups      */
+    int64_t push_timed;      /* steps whose push was timed (ms_push sums over them) */
+    int64_t n_pushed_timed;  /* particles entering those pushes                     */
+    int64_t n_survived_timed;/* and their survivors                                 */
 } ugkwp_totals;
 
 /* ---- context ---- */

@@ -117,6 +117,7 @@ int ilog2(int p)
 constexpr int MAX_PUSH_BLOCKS = 8192;     // per-block survivor counts kept by the push
 constexpr int RUN_AHEAD = 16;             // steps enqueued per host synchronisation
 constexpr int N_RECORDS = RUN_AHEAD + 1;  // step records: a batch's steps and the state it starts from
+constexpr uint32_t PUSH_TIME_EVERY = 8;   // without phase timing, the push of one step in 8 is timed
 
 template <class T>
 T* dalloc(std::vector<void*>& owned, size_t n)
@@ -632,6 +633,7 @@ struct ugkwp_ctx {
         int rec;               // record holding the state the step starts from
         int slot;              // record the step writes
         bool do_sort;
+        bool push_timed;       // events around the push (a few microseconds each)
         int sweeps;            // sweeps launched
     };
 
@@ -803,9 +805,9 @@ struct ugkwp_ctx {
         launch_group(0x100000u | (uint32_t)cur_mv | ((uint32_t)cur_st << 1) | (parity() << 2) |
                          ((uint32_t)p.slot << 3),
                      [&] { enqueue_pre_push(); });
-        HIPCHK(hipEventRecord(e[1], st));
+        if (p.push_timed) HIPCHK(hipEventRecord(e[1], st));
         launch_push(dim, D, K, view(cur_mv, cur_st), moving(1 - cur_mv), push_shape, st);
-        HIPCHK(hipEventRecord(e[2], st));
+        if (p.push_timed) HIPCHK(hipEventRecord(e[2], st));
         // the wave flux and Q are evaluated by the first sweep: no launch of their own
         if (phase_times) HIPCHK(hipEventRecord(e[3], st));
         const int first = p.sweeps;
@@ -885,7 +887,8 @@ struct ugkwp_ctx {
         dg.residual = dg.e_end - dg.e_start - (dg.inflow_wave + dg.inflow_eq - dg.exit_particles + dg.injection);
         hipEvent_t* e = sev[cur_slot];
         float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e[1], e[2])); dg.ms_push = ms;
+        dg.push_timed = p.push_timed ? 1 : 0;
+        if (p.push_timed) { HIPCHK(hipEventElapsedTime(&ms, e[1], e[2])); dg.ms_push = ms; }
         if (phase_times) {
             HIPCHK(hipEventElapsedTime(&ms, e[0], e[1])); dg.ms_sample = ms;
             HIPCHK(hipEventElapsedTime(&ms, e[2], e[3])); dg.ms_macro = ms;
@@ -902,6 +905,11 @@ struct ugkwp_ctx {
         tot.cg_updates += cgu;
         tot.ms_sample += dg.ms_sample;
         tot.ms_push += dg.ms_push;
+        if (p.push_timed) {
+            tot.push_timed += 1;
+            tot.n_pushed_timed += dg.n_pushed;
+            tot.n_survived_timed += dg.n_alive_out;
+        }
         tot.ms_macro += dg.ms_macro;
         tot.ms_si += dg.ms_si;
         tot.ms_sort += dg.ms_sort;
@@ -931,6 +939,7 @@ struct ugkwp_ctx {
             try {
                 for (int i = 0; i < m; ++i) {
                     p.do_sort = sort_due(p.step, p.n_slots);
+                    p.push_timed = phase_times || p.step % PUSH_TIME_EVERY == 0;
                     p.sweeps = spec;
                     p.slot = next_record(p.rec);
                     set_state(p);

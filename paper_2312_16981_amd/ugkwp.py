@@ -66,7 +66,8 @@ class AdjointStats(C.Structure):
 class Totals(C.Structure):
     _fields_ = [("steps", C.c_int64), ("n_pushed", C.c_int64), ("n_survived", C.c_int64),
                 ("sweeps_max", C.c_int64), ("sweeps_sum", C.c_int64), ("ms_sample", _d), ("ms_push", _d),
-                ("ms_macro", _d), ("ms_si", _d), ("ms_sort", _d), ("cg_updates", C.c_int64)]
+                ("ms_macro", _d), ("ms_si", _d), ("ms_sort", _d), ("cg_updates", C.c_int64),
+                ("push_timed", C.c_int64), ("n_pushed_timed", C.c_int64), ("n_survived_timed", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,7 +86,8 @@ class Diag(C.Structure):
                 ("n_pushed", C.c_int64), ("sweeps_max", C.c_int), ("sweeps_sum", C.c_int),
                 ("e_start", _d), ("e_end", _d), ("inflow_wave", _d), ("inflow_eq", _d),
                 ("exit_particles", _d), ("injection", _d), ("residual", _d),
-                ("ms_sample", _d), ("ms_push", _d), ("ms_macro", _d), ("ms_si", _d), ("ms_sort", _d)]
+                ("ms_sample", _d), ("ms_push", _d), ("ms_macro", _d), ("ms_si", _d), ("ms_sort", _d),
+                ("push_timed", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
