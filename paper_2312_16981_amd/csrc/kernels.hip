@@ -512,9 +512,17 @@ __device__ inline void draw_flight(const Consts& K, const Geo& I, uint64_t id, u
     if ((f.d & 1u) == 0) keyed_uniform_pair(I.seed, id, step, PURPOSE_FLIGHT, f.d, u, f.u_odd);
     else u = f.u_odd;                  // the first crossing's draw: no second Philox evaluation
     f.d++;
+    const double room = K.dt - f.t;
+    // -ln u >= 1 - u: when tau (1 - u) clears the time left by far more than the
+    // rounding of either side, the flight outlasts the step without the logarithm
+    if (f.tau * (1.0 - u) > room * (1.0 + 1e-9)) {
+        f.coll = false;
+        f.t_rem = room;
+        return;
+    }
     const double a = f.tau * neg_log_unit(u);
-    f.coll = a < K.dt - f.t;
-    f.t_rem = f.coll ? a : K.dt - f.t;
+    f.coll = a < room;
+    f.t_rem = f.coll ? a : room;
 }
 
 // Flight of one particle through the step.  Returns 0 survives, 1 collided, 2 left the domain.
