@@ -82,8 +82,9 @@ typedef struct {
     double si_tol;       /* relative max-norm tolerance on rho and on T            */
     uint32_t flags;      /* UGKWP_FLAG_*                                           */
     int sort_interval;   /* steps between counting sorts of the particle pool by
-                            (cell, group); 0 = library default (16).  Affects only
-                            speed and the order of the pool, not the results.     */
+                            (cell, group); 0 = library default (32 steps in 1-D,
+                            16 in 2-D, where locality decays faster).  Affects
+                            only speed and the order of the pool, not the results. */
 } ugkwp_params;
 
 /* One problem instance (a slab in 1-D, a rectangle in 2-D). */

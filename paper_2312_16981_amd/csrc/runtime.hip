@@ -199,7 +199,7 @@ struct ugkwp_ctx {
     int cur_slot = 0;                  // event set of the step being enqueued or read
     int last_sweeps = 4;
     int64_t last_births = 0;
-    int sort_interval = 8;
+    int sort_interval = 0;             // 0: 32 steps in 1-D, 16 in 2-D (measured on the benchmark media)
     ugkwp_diag diag{};
     ugkwp_totals tot{};                // running sums since the last reset
 
@@ -686,7 +686,8 @@ struct ugkwp_ctx {
     bool sort_due(uint32_t step, int64_t slots) const
     {
         // sort periodically, and whenever holes have filled half the pool
-        return sort_interval <= 1 || (step % (uint32_t)sort_interval) == (uint32_t)(sort_interval - 1) ||
+        const int si = sort_interval > 0 ? sort_interval : (dim == 1 ? 32 : 16);
+        return si <= 1 || (step % (uint32_t)si) == (uint32_t)(si - 1) ||
                slots > P.pool_capacity / 2;
     }
 
@@ -1321,7 +1322,7 @@ int ugkwp_create(ugkwp_ctx** out, const ugkwp_params* p, void* hip_stream)
             HIPCHK(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking));
             c->own_stream = true;
         }
-        c->sort_interval = p->sort_interval > 0 ? p->sort_interval : 16;
+        c->sort_interval = p->sort_interval;
         c->use_graph = (p->flags & UGKWP_FLAG_GRAPH) != 0;
         c->phase_times = (p->flags & UGKWP_FLAG_PHASE_TIMES) != 0;
         // timing-only events: no system-scope fence (cache write-back) when recorded
