@@ -38,7 +38,7 @@ __constant__ HeadSeries c_head;
 // (scalar registers when the whole launch serves one instance).
 struct Geo {
     double x0, y0, dx, dy;
-    int64_t cg_off, fx_off, fy_off;
+    uint32_t cg_off, fx_off, fy_off;   // slot indices stay below 2^30 (checked at set-up)
     uint64_t seed;
     int nx, ny, lgGp, cell_off, edge_off;
     int reflect;           // bit q: side q (XLO, XHI, YLO, YHI) is reflective
@@ -48,7 +48,7 @@ __device__ inline Geo geo_of(const Inst& I)
 {
     Geo o;
     o.x0 = I.x0; o.y0 = I.y0; o.dx = I.dx; o.dy = I.dy;
-    o.cg_off = I.cg_off; o.fx_off = I.fx_off; o.fy_off = I.fy_off;
+    o.cg_off = (uint32_t)I.cg_off; o.fx_off = (uint32_t)I.fx_off; o.fy_off = (uint32_t)I.fy_off;
     o.seed = I.seed;
     o.nx = I.nx; o.ny = I.ny; o.lgGp = I.lgGp; o.cell_off = I.cell_off; o.edge_off = I.edge_off;
     o.reflect = 0;
@@ -575,9 +575,9 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTabl
             }
             boundary = pos ? (f.ix == I.nx - 1) : (f.ix == 0);
             side = pos ? XHI : XLO;
-            const int64_t face = (int64_t)f.iy * (I.nx + 1) + (pos ? f.ix + 1 : f.ix);
+            const uint32_t face = (uint32_t)(f.iy * (I.nx + 1) + (pos ? f.ix + 1 : f.ix));
             type = TAL_FX;
-            index = (uint32_t)(((I.fx_off + (face << I.lgGp) + g) << 1) + (pos ? 0 : 1));
+            index = ((I.fx_off + (face << I.lgGp) + (uint32_t)g) << 1) + (pos ? 0u : 1u);
         } else {
             pos = vy > 0;
             f.y = pos ? yr : yl;
@@ -587,9 +587,9 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTabl
             f.x = xn;
             boundary = pos ? (f.iy == I.ny - 1) : (f.iy == 0);
             side = pos ? YHI : YLO;
-            const int64_t face = (int64_t)(pos ? f.iy + 1 : f.iy) * I.nx + f.ix;
+            const uint32_t face = (uint32_t)((pos ? f.iy + 1 : f.iy) * I.nx + f.ix);
             type = TAL_FY;
-            index = (uint32_t)(((I.fy_off + (face << I.lgGp) + g) << 1) + (pos ? 0 : 1));
+            index = ((I.fy_off + (face << I.lgGp) + (uint32_t)g) << 1) + (pos ? 0u : 1u);
         }
         if (boundary) {
             if ((I.reflect >> side) & 1) {
@@ -602,7 +602,7 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTabl
         }
         lds_tally(T, D, type, index, w);
         if (xaxis) f.ix += pos ? 1 : -1; else f.iy += pos ? 1 : -1;
-        f.tau = tfac * D.inv_kappa[I.cg_off + ((int64_t)(f.iy * I.nx + f.ix) << I.lgGp) + g];
+        f.tau = tfac * D.inv_kappa[I.cg_off + ((uint32_t)(f.iy * I.nx + f.ix) << I.lgGp) + (uint32_t)g];
         draw_flight(K, I, id, step, f);
     }
 }
@@ -671,13 +671,13 @@ __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Cons
             f.t = 0.0;
             f.d = 0;
             const double tfac = tau_factor<SM>(D, K, I, nu, g);
-            f.tau = tfac * D.inv_kappa[I.cg_off + ((int64_t)lcell << I.lgGp) + g];
+            f.tau = tfac * D.inv_kappa[I.cg_off + ((uint32_t)lcell << I.lgGp) + (uint32_t)g];
             if (i < n_slots) draw_flight(K, I, id, step, f);    // old particle: t_f = min(-tau ln eta, dt)
             else { f.coll = false; f.t_rem = K.dt; }            // new collisionless particle: t_f = dt
             const double ox0 = f.ox, oy0 = f.oy;
             const int out = fly<DIM>(D, K, I, T, id, step, tfac, g, w, f);
             if (out != 2) {
-                const uint32_t cg = (uint32_t)(I.cg_off + ((int64_t)(f.iy * I.nx + f.ix) << I.lgGp) + g);
+                const uint32_t cg = I.cg_off + ((uint32_t)(f.iy * I.nx + f.ix) << I.lgGp) + (uint32_t)g;
                 lds_tally(T, D, out == 0 ? TAL_SURV : TAL_DEP, cg, w);
             }
             if (out == 0) {
