@@ -607,6 +607,29 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTabl
     }
 }
 
+// One pool record as the push reads it (every field, also for an empty slot:
+// all slots below the capacity are allocated, and the values are then unused).
+template <int DIM>
+struct PoolRec {
+    double x, y, ox, oy, nu, w;
+    uint64_t id;
+    int32_t word, g;
+    __device__ inline void load(const Pool& P, int64_t i)
+    {
+        word = P.cell[i];
+        g = P.g[i];
+        x = P.x[i];
+        ox = P.ox[i];
+        if (DIM == 2) {
+            y = P.y[i];
+            oy = P.oy[i];
+        }
+        nu = P.nu[i];
+        w = P.w[i];
+        id = P.id[i];
+    }
+};
+
 // Each block takes chunks of PUSH_THREADS * ppt consecutive pool slots;
 // a thread handles ppt of them.  Stable fields are only read; the new
 // position and cell word go to the other moving-field buffer at the same slot,
@@ -636,35 +659,57 @@ __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Cons
             T.val[h] = 0.0;
         }
         __syncthreads();
+        // 2-D: the records of the next round are read while this round's flights
+        // run (1-D: the registers this takes would cost a wavefront per SIMD)
+        PoolRec<DIM> nxt;
+        if (DIM == 2) {
+            const int64_t i0 = c0 + threadIdx.x;
+            if (i0 < n_total) nxt.load(In, i0);
+        }
 #pragma unroll 1
         for (int r = 0; r < ppt; ++r) {
             const int64_t i = c0 + (int64_t)r * PUSH_THREADS + threadIdx.x;
             if (i >= n_total) continue;
-            const int32_t word = In.cell[i];
+            PoolRec<DIM> cur;
+            if (DIM == 2) {
+                cur = nxt;
+                if (r + 1 < ppt && i + PUSH_THREADS < n_total) nxt.load(In, i + PUSH_THREADS);
+            } else {
+                cur.word = In.cell[i];             // the rest only for a live slot
+            }
+            const int32_t word = cur.word;
             if (word < 0) {                        // empty slot stays empty
                 Out.cell[i] = DEAD;
                 continue;
             }
             const int cell = word & CELL_MASK;
-            const int g = In.g[i];
+            if (DIM == 1) cur.g = In.g[i];
+            const int g = cur.g;
             if (cell >= K.ncell) {
                 atomicOr((unsigned long long*)(D.counters + CNT_ERR), ERR_RECORD);
                 Out.cell[i] = DEAD;
                 continue;
             }
+            if (DIM == 1) {
+                cur.x = In.x[i];
+                cur.ox = In.ox[i];
+                cur.nu = In.nu[i];
+                cur.w = In.w[i];
+                cur.id = In.id[i];
+            }
             const Geo I = SINGLE ? geo0 : geo_of(D.inst[D.cell_inst[cell]]);
             Flight f;
-            f.x = In.x[i];
-            f.ox = (word & FLIP_X) ? -In.ox[i] : In.ox[i];
+            f.x = cur.x;
+            f.ox = (word & FLIP_X) ? -cur.ox : cur.ox;
             if (DIM == 2) {
-                f.y = In.y[i];
-                f.oy = (word & FLIP_Y) ? -In.oy[i] : In.oy[i];
+                f.y = cur.y;
+                f.oy = (word & FLIP_Y) ? -cur.oy : cur.oy;
             } else {
                 f.y = 0.0;
                 f.oy = 0.0;
             }
-            const double nu = In.nu[i], w = In.w[i];
-            const uint64_t id = In.id[i];
+            const double nu = cur.nu, w = cur.w;
+            const uint64_t id = cur.id;
             const int lcell = cell - I.cell_off;
             f.ix = DIM == 1 ? lcell : lcell % I.nx;
             f.iy = DIM == 1 ? 0 : lcell / I.nx;
