@@ -215,6 +215,31 @@ int ugkwp_set_pool(ugkwp_ctx* ctx, int64_t n, const double* x, const double* y,
                    const uint64_t* id, const int32_t* cell, const int32_t* g,
                    uint64_t birth_counter, const double* rhop);
 
+/* ---- checkpoint ----
+ * A step of Algorithm 1 starts from rho^n, T^n, the surviving particles, the
+ * survivor density rho^p and the birth counter; this library keys the random
+ * numbers of every particle by its id and the step index.  That is the whole
+ * state, and a run restored from it continues as
+ * the uninterrupted run would (up to the order of floating-point tally sums,
+ * which is not fixed on the GPU).
+ *
+ * ugkwp_state_bytes: size of the host buffer that ugkwp_get_state fills for the
+ * context as it is now (the pool's slots count), or a negative code.
+ * ugkwp_get_state: writes the committed state of every instance (rho, T, rho^p,
+ * phi(T), birth counters, step index, the pool's slots in device order) into
+ * buf (host, caller-owned, at least ugkwp_state_bytes bytes; UGKWP_EINVAL if
+ * smaller).  Needs a context with opacity and material set.
+ * ugkwp_set_state: restores such a buffer into a context set up with the same
+ * mesh, instances, groups, boundary conditions, seeds, weights and constants
+ * (checked through a fingerprint: UGKWP_EINVAL otherwise) and its opacity and
+ * material set (they are not part of the state).  UGKWP_EPOOL if the pool does
+ * not fit the capacity; UGKWP_EINVAL while an adjoint record is kept, or if the
+ * buffer is truncated or holds an out-of-range particle or a non-positive T.
+ * The last step's tallies read zero until the next step. */
+int64_t ugkwp_state_bytes(ugkwp_ctx* ctx);
+int ugkwp_get_state(ugkwp_ctx* ctx, void* buf, int64_t bytes);
+int ugkwp_set_state(ugkwp_ctx* ctx, const void* buf, int64_t bytes);
+
 /* ---- launch autotuner ----
  * Times the particle push on the context's current pool for launch shapes
  * (persistent blocks per CU: half, one and two times what fits; particles per

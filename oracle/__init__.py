@@ -82,6 +82,7 @@ def lib():
         L.ora_get_pool.argtypes = [C.c_void_p, _pd, _pd, _pd, _pd, _pd, _pd, _pu64, _pi32, _pi32]
         L.ora_set_pool.argtypes = [C.c_void_p, C.c_int64, _pd, _pd, _pd, _pd, _pd, _pd, _pu64,
                                    _pi32, _pi32, C.c_uint64, _pd]
+        L.ora_set_fields.argtypes = [C.c_void_p, _pd, _pd, C.c_int]
         L.ora_get_diag.argtypes = [C.c_void_p, C.POINTER(Diag)]
         L.ora_get_counters.argtypes = [C.c_void_p, _pu64, C.POINTER(C.c_int)]
         L.ora_get_start_weights.argtypes = [C.c_void_p, _pd]
@@ -272,6 +273,22 @@ class Sim:
                                 _p(np.ascontiguousarray(rhop)) if rhop is not None else None)
         if st:
             raise OracleError(st, "set_pool")
+
+    def set_fields(self, rho, T, step):
+        st = lib().ora_set_fields(self.h, _p(np.ascontiguousarray(rho, dtype=np.float64)),
+                                  _p(np.ascontiguousarray(T, dtype=np.float64)), int(step))
+        if st:
+            raise OracleError(st, "set_fields")
+
+    def state(self):
+        """The whole state a step starts from: fields, pool and counters."""
+        rho, T, rhop = self.fields()
+        births, step = self.counters()
+        return dict(rho=rho, T=T, rhop=rhop, pool=self.pool(), births=births, step=step)
+
+    def restore(self, st):
+        self.set_fields(st["rho"], st["T"], st["step"])
+        self.set_pool(st["pool"], st["births"], st["rhop"])
 
     def diag(self):
         d = Diag()

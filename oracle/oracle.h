@@ -122,6 +122,10 @@ int ora_set_pool(ora_sim* s, int64_t n, const double* x, const double* y,
                  const double* ox, const double* oy, const double* nu,
                  const double* w, const uint64_t* id, const int32_t* cell,
                  const int32_t* g, uint64_t birth_counter, const double* rhop);
+/* Restore a saved state's radiation density rho [cell][G], temperature T [cell]
+ * and step index (the pool, birth counter and survivor density go through
+ * ora_set_pool).  Together they are the whole state a step starts from. */
+int ora_set_fields(ora_sim* s, const double* rho, const double* T, int step);
 int ora_get_diag(const ora_sim* s, ora_diag* d);
 int ora_get_counters(const ora_sim* s, uint64_t* birth_counter, int* step);
 /* Per-(cell, g) particle ledger of the last step: weight present at the

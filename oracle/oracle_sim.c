@@ -809,6 +809,18 @@ int ora_set_pool(ora_sim* s, int64_t n, const double* x, const double* y, const 
     return ORA_OK;
 }
 
+int ora_set_fields(ora_sim* s, const double* rho, const double* T, int step)
+{
+    if (!rho || !T || step < 0) return ORA_EINVAL;
+    size_t ncg = (size_t)s->ncell * s->p.G;
+    for (int i = 0; i < s->ncell; ++i)
+        if (!(T[i] > 0) || !isfinite(T[i])) return ORA_EINVAL;
+    memcpy(s->rho, rho, sizeof(double) * ncg);
+    memcpy(s->T, T, sizeof(double) * s->ncell);
+    s->step = step;
+    return ORA_OK;
+}
+
 int ora_get_diag(const ora_sim* s, ora_diag* d) { *d = s->diag; return ORA_OK; }
 
 int ora_get_counters(const ora_sim* s, uint64_t* birth_counter, int* step)

@@ -1303,6 +1303,89 @@ struct Tmp {
 };
 }  // namespace
 
+// ---- checkpoint ----
+//
+// A saved state is one host buffer: a header, then in the device's padded
+// layout rho^n, the survivor density, phi(T^n) and T^n, the per-instance birth
+// counters, and the pool's slots as they sit in the device buffers (holes and
+// pending reflections included), so that the restored context continues with
+// the same particles in the same order.  Every section starts on an 8-byte
+// boundary.
+
+namespace {
+
+constexpr char STATE_MAGIC[8] = {'U', 'G', 'K', 'W', 'P', 'S', 'T', '1'};
+constexpr uint32_t STATE_VERSION = 1;
+
+struct StateHeader {
+    char magic[8];
+    uint64_t layout;       // fingerprint of mesh, groups, instances and constants
+    int32_t dim, n_inst, ncell;
+    uint32_t step;
+    int64_t n_cg, n_slots, n_alive, bytes;
+    uint32_t version, pad;
+};
+
+// FNV-1a over the values that fix the meaning of every saved array
+struct Fnv {
+    uint64_t h = 1469598103934665603ull;
+    template <class T>
+    void add(const T& v)
+    {
+        const unsigned char* b = reinterpret_cast<const unsigned char*>(&v);
+        for (size_t i = 0; i < sizeof(T); ++i) h = (h ^ b[i]) * 1099511628211ull;
+    }
+};
+
+uint64_t state_layout(const ugkwp_ctx* c)
+{
+    Fnv f;
+    f.add(c->dim);
+    f.add(c->n_inst);
+    f.add(c->K.c); f.add(c->K.a); f.add(c->K.eps); f.add(c->K.dt); f.add(c->K.nu_power);
+    f.add(c->K.flags);
+    for (const HostInst& h : c->hi) {
+        f.add(h.nx); f.add(h.ny); f.add(h.G);
+        f.add(h.x0); f.add(h.x1); f.add(h.y0); f.add(h.y1);
+        for (int q = 0; q < 4; ++q) { f.add(h.bc[q]); f.add(h.bcT[q]); }
+        for (double e : h.edges) f.add(e);
+        f.add(h.seed); f.add(h.w_ref);
+    }
+    return f.h;
+}
+
+// byte offsets of the sections of a saved state
+struct StateLayout {
+    size_t rho, rhop, phi0, T, births, x, y, ox, oy, nu, w, id, cell, g, end;
+};
+
+size_t up8(size_t b) { return (b + 7) / 8 * 8; }
+
+StateLayout state_sections(const ugkwp_ctx* c, int64_t n_slots)
+{
+    StateLayout L{};
+    const size_t ncg = (size_t)c->K.n_cg, ns = (size_t)n_slots, d2 = c->dim == 2 ? 1 : 0;
+    size_t o = up8(sizeof(StateHeader));
+    L.rho = o;    o += 8 * ncg;
+    L.rhop = o;   o += 8 * ncg;
+    L.phi0 = o;   o += 8 * ncg;
+    L.T = o;      o += 8 * (size_t)c->ncell;
+    L.births = o; o += 8 * (size_t)c->n_inst;
+    L.x = o;      o += 8 * ns;
+    L.y = o;      o += 8 * ns * d2;
+    L.ox = o;     o += 8 * ns;
+    L.oy = o;     o += 8 * ns * d2;
+    L.nu = o;     o += 8 * ns;
+    L.w = o;      o += 8 * ns;
+    L.id = o;     o += 8 * ns;
+    L.cell = o;   o += up8(4 * ns);
+    L.g = o;      o += up8(4 * ns);
+    L.end = o;
+    return L;
+}
+
+}  // namespace
+
 extern "C" {
 
 int ugkwp_create(ugkwp_ctx** out, const ugkwp_params* p, void* hip_stream)
@@ -1643,6 +1726,146 @@ int ugkwp_set_pool(ugkwp_ctx* ctx, int64_t n, const double* x, const double* y, 
         HIPCHK(hipStreamSynchronize(st));
         ctx->n_alive = n;
         ctx->n_slots = n;
+    });
+}
+
+// ---- checkpoint (saved layout: StateHeader and state_sections) ----
+
+int64_t ugkwp_state_bytes(ugkwp_ctx* ctx)
+{
+    if (!ctx || ctx->n_inst == 0) return UGKWP_EINVAL;
+    return (int64_t)state_sections(ctx, ctx->n_slots).end;
+}
+
+int ugkwp_get_state(ugkwp_ctx* ctx, void* buf, int64_t bytes)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        require_ready(ctx);
+        const StateLayout L = state_sections(ctx, ctx->n_slots);
+        if (!buf || bytes < (int64_t)L.end)
+            fail(UGKWP_EINVAL, "state buffer of %lld bytes, %zu needed", (long long)bytes, L.end);
+        char* b = static_cast<char*>(buf);
+        StateHeader h{};
+        std::memcpy(h.magic, STATE_MAGIC, sizeof(h.magic));
+        h.layout = state_layout(ctx);
+        h.dim = ctx->dim;
+        h.n_inst = ctx->n_inst;
+        h.ncell = ctx->ncell;
+        h.step = ctx->step_idx;
+        h.n_cg = ctx->K.n_cg;
+        h.n_slots = ctx->n_slots;
+        h.n_alive = ctx->n_alive;
+        h.bytes = (int64_t)L.end;
+        h.version = STATE_VERSION;
+        std::memcpy(b, &h, sizeof(h));
+        hipStream_t st = ctx->st;
+        auto cp = [&](size_t off, const void* src, size_t n) {
+            if (n) HIPCHK(hipMemcpyAsync(b + off, src, n, hipMemcpyDeviceToHost, st));
+        };
+        const size_t ncg = (size_t)ctx->K.n_cg, ns = (size_t)ctx->n_slots;
+        cp(L.rho, ctx->D.rho, 8 * ncg);
+        cp(L.rhop, ctx->D.rhop, 8 * ncg);
+        cp(L.phi0, ctx->D.phi0, 8 * ncg);
+        cp(L.T, ctx->D.T, 8 * (size_t)ctx->ncell);
+        std::vector<InstState> is((size_t)ctx->n_inst);
+        HIPCHK(hipMemcpyAsync(is.data(), ctx->D.ist, sizeof(InstState) * is.size(), hipMemcpyDeviceToHost, st));
+        const Pool p = ctx->view(ctx->cur_mv, ctx->cur_st);
+        cp(L.x, p.x, 8 * ns);
+        cp(L.ox, p.ox, 8 * ns);
+        if (ctx->dim == 2) { cp(L.y, p.y, 8 * ns); cp(L.oy, p.oy, 8 * ns); }
+        cp(L.nu, p.nu, 8 * ns);
+        cp(L.w, p.w, 8 * ns);
+        cp(L.id, p.id, 8 * ns);
+        cp(L.cell, p.cell, 4 * ns);
+        cp(L.g, p.g, 4 * ns);
+        HIPCHK(hipStreamSynchronize(st));
+        for (int k = 0; k < ctx->n_inst; ++k) std::memcpy(b + L.births + 8 * (size_t)k, &is[k].births, 8);
+    });
+}
+
+int ugkwp_set_state(ugkwp_ctx* ctx, const void* buf, int64_t bytes)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        require_ready(ctx);
+        if (ctx->rec_cap > 0) fail(UGKWP_EINVAL, "a state cannot be restored while a record is kept (ugkwp_record(ctx, 0) first)");
+        if (!buf || bytes < (int64_t)sizeof(StateHeader)) fail(UGKWP_EINVAL, "state buffer too short");
+        const char* b = static_cast<const char*>(buf);
+        StateHeader h;
+        std::memcpy(&h, b, sizeof(h));
+        if (std::memcmp(h.magic, STATE_MAGIC, sizeof(h.magic)) != 0 || h.version != STATE_VERSION)
+            fail(UGKWP_EINVAL, "not a saved state of this library version");
+        if (h.layout != state_layout(ctx) || h.dim != ctx->dim || h.n_inst != ctx->n_inst ||
+            h.ncell != ctx->ncell || h.n_cg != ctx->K.n_cg)
+            fail(UGKWP_EINVAL, "the state was saved from a context with another mesh, groups or constants");
+        if (h.n_slots < 0 || h.n_slots > ctx->P.pool_capacity || h.n_alive < 0 || h.n_alive > h.n_slots)
+            fail(UGKWP_EPOOL, "the saved pool of %lld slots does not fit a capacity of %lld",
+                 (long long)h.n_slots, (long long)ctx->P.pool_capacity);
+        const StateLayout L = state_sections(ctx, h.n_slots);
+        if (h.bytes != (int64_t)L.end || bytes < (int64_t)L.end) fail(UGKWP_EINVAL, "state buffer truncated");
+        // the pool: every live slot names a cell and a group of its instance
+        const size_t ns = (size_t)h.n_slots;
+        const int32_t* cw = reinterpret_cast<const int32_t*>(b + L.cell);
+        const int32_t* gw = reinterpret_cast<const int32_t*>(b + L.g);
+        std::vector<int> first(ctx->n_inst);
+        for (int k = 0; k < ctx->n_inst; ++k) first[k] = ctx->inst[k].cell_off;
+        int64_t live = 0;
+        for (size_t q = 0; q < ns; ++q) {
+            if (cw[q] < 0) continue;
+            const int cell = cw[q] & CELL_MASK;
+            if (cell >= ctx->ncell) fail(UGKWP_EINVAL, "saved particle %zu: cell out of range", q);
+            const int k = (int)(std::upper_bound(first.begin(), first.end(), cell) - first.begin()) - 1;
+            if (gw[q] < 0 || gw[q] >= ctx->inst[k].G) fail(UGKWP_EINVAL, "saved particle %zu: group out of range", q);
+            ++live;
+        }
+        if (live != h.n_alive) fail(UGKWP_EINVAL, "saved pool holds %lld live particles, header says %lld",
+                                    (long long)live, (long long)h.n_alive);
+        const double* T = reinterpret_cast<const double*>(b + L.T);
+        for (int i = 0; i < ctx->ncell; ++i)
+            if (!(T[i] > 0) || !std::isfinite(T[i])) fail(UGKWP_EINVAL, "saved temperature not positive and finite");
+
+        hipStream_t st = ctx->st;
+        auto cp = [&](void* dst, size_t off, size_t n) {
+            if (n) HIPCHK(hipMemcpyAsync(dst, b + off, n, hipMemcpyHostToDevice, st));
+        };
+        const size_t ncg = (size_t)ctx->K.n_cg;
+        cp(ctx->D.rho, L.rho, 8 * ncg);
+        cp(ctx->D.rhop, L.rhop, 8 * ncg);
+        cp(ctx->D.phi0, L.phi0, 8 * ncg);
+        cp(ctx->D.T, L.T, 8 * (size_t)ctx->ncell);
+        const Pool p = ctx->view(ctx->cur_mv, ctx->cur_st);
+        cp(p.x, L.x, 8 * ns);
+        cp(p.ox, L.ox, 8 * ns);
+        if (ctx->dim == 2) { cp(p.y, L.y, 8 * ns); cp(p.oy, L.oy, 8 * ns); }
+        cp(p.nu, L.nu, 8 * ns);
+        cp(p.w, L.w, 8 * ns);
+        cp(p.id, L.id, 8 * ns);
+        cp(p.cell, L.cell, 4 * ns);
+        cp(p.g, L.g, 4 * ns);
+        // the committed record: birth counters, pool size, step count
+        std::vector<InstState> is((size_t)ctx->n_inst);
+        for (int k = 0; k < ctx->n_inst; ++k) std::memcpy(&is[k].births, b + L.births + 8 * (size_t)k, 8);
+        HIPCHK(hipMemcpyAsync(ctx->D.ist, is.data(), sizeof(InstState) * is.size(), hipMemcpyHostToDevice, st));
+        std::vector<unsigned long long> cnt(N_COUNTERS, 0ull);
+        cnt[CNT_SLOTS] = (unsigned long long)h.n_slots;
+        cnt[CNT_LIVE] = (unsigned long long)h.n_alive;
+        cnt[CNT_DONE] = h.step;
+        HIPCHK(hipMemcpyAsync(ctx->D.counters, cnt.data(), sizeof(unsigned long long) * N_COUNTERS,
+                              hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(ctx->D.step, &h.step, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        // the last step's tallies belong to the run the state came from
+        HIPCHK(hipMemsetAsync(ctx->D.ftx, 0, sizeof(double) * ctx->n_fx * 2, st));
+        HIPCHK(hipMemsetAsync(ctx->D.fty, 0, sizeof(double) * std::max<int64_t>(ctx->n_fy, 1) * 2, st));
+        for (double* q : {ctx->D.dep, ctx->D.surv, ctx->D.wnew, ctx->D.Q})
+            HIPCHK(hipMemsetAsync(q, 0, sizeof(double) * ncg, st));
+        HIPCHK(hipMemsetAsync(ctx->D.nb, 0, sizeof(int32_t) * ncg, st));
+        HIPCHK(hipStreamSynchronize(st));
+        ctx->step_idx = h.step;
+        ctx->n_alive = h.n_alive;
+        ctx->n_slots = h.n_slots;
+        ctx->last_births = 0;
+        ctx->diag = ugkwp_diag{};
     });
 }
 

@@ -29,6 +29,7 @@ EXPORTED = [
     "ugkwp_pool_size", "ugkwp_get_pool", "ugkwp_set_pool", "ugkwp_eval_phi", "ugkwp_eval_coef",
     "ugkwp_eval_uniform", "ugkwp_eval_neg_log", "ugkwp_eval_sample_nu", "ugkwp_record", "ugkwp_recorded_steps",
     "ugkwp_adjoint", "ugkwp_autotune", "ugkwp_get_totals", "ugkwp_set_phase_times",
+    "ugkwp_state_bytes", "ugkwp_get_state", "ugkwp_set_state",
 ]
 
 _d = C.c_double
@@ -135,6 +136,10 @@ def load():
     L.ugkwp_get_pool.argtypes = [vp, _pd, _pd, _pd, _pd, _pd, _pd, _pu64, _pi32, _pi32]
     L.ugkwp_set_pool.argtypes = [vp, C.c_int64, _pd, _pd, _pd, _pd, _pd, _pd, _pu64, _pi32, _pi32,
                                  C.c_uint64, _pd]
+    L.ugkwp_state_bytes.argtypes = [vp]
+    L.ugkwp_state_bytes.restype = C.c_int64
+    L.ugkwp_get_state.argtypes = [vp, vp, C.c_int64]
+    L.ugkwp_set_state.argtypes = [vp, vp, C.c_int64]
     L.ugkwp_record.argtypes = [vp, C.c_int]
     L.ugkwp_autotune.argtypes = [vp, C.POINTER(TuneResult)]
     L.ugkwp_get_totals.argtypes = [vp, C.POINTER(Totals), C.c_int]
@@ -331,6 +336,18 @@ class Context:
                                         _p(a["cell"].astype(np.int32), _pi32),
                                         _p(a["g"].astype(np.int32), _pi32), int(birth_counter),
                                         _p(_f64(rhop)) if rhop is not None else None), "set_pool")
+
+    def get_state(self):
+        """The committed state as a byte array (ugkwp_get_state)."""
+        n = load().ugkwp_state_bytes(self.h)
+        self._chk(n if n < 0 else 0, "state_bytes")
+        buf = np.zeros(n, np.uint8)
+        self._chk(load().ugkwp_get_state(self.h, buf.ctypes.data, n), "get_state")
+        return buf
+
+    def set_state(self, buf):
+        b = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._chk(load().ugkwp_set_state(self.h, b.ctypes.data, b.size), "set_state")
 
 
 def make_params(c=1.0, a=1.0, eps=1.0, dt=1e-3, nu_power=3.0, n_cap=1 << 20, pool_capacity=1 << 20,

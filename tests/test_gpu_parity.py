@@ -390,3 +390,89 @@ def test_autotune_needs_particles():
     a.step(2)
     with pytest.raises(ugkwp.UGKWPError):
         a.autotune()
+
+
+# ------------------------------------------------------------ checkpoint
+
+def _restart(make, n):
+    """Run n steps, save, restore into a fresh context, run n more on both."""
+    a = make()
+    a.step(n)
+    buf = a.get_state()
+    b = make()
+    b.set_state(buf)
+    a.step(n)
+    b.step(n)
+    return a, b
+
+
+@pytest.mark.parametrize("which", ["slab", "lognormal"])
+def test_checkpoint_restart_matches_uninterrupted_run_and_oracle(which):
+    """Steps 0..n-1, a saved state restored into a new context, steps n..2n-1:
+    against the context that ran on (the tallies' floating-point sums may add
+    in another order on the GPU, so 1e-10; particle counts and ids bit-exact)
+    and against 2n oracle steps.  The slab's restart spans a pool sort (every
+    32 steps in 1-D)."""
+    if which == "slab":
+        p, n = W.c1_marshak_like(), 20
+    else:
+        p, n = W.c5_lognormal(n=24, G=5, dt=2e-2), 4
+    say(f"[checkpoint] {p.name} steps {n} + {n}")
+    a, b = _restart(lambda: ugkwp.from_problem(p), n)
+    sim = oracle.Sim(p)
+    sim.step(2 * n)
+    compare_state(b, sim, p, what=f"{p.name} restored")
+    compare_pool(b, sim, p.dim)
+    ra, ta, _ = a.get_fields()
+    rb, tb, _ = b.get_fields()
+    assert relerr(rb, ra) <= TOL and relerr(tb, ta) <= TOL
+    assert b.get_counters() == a.get_counters() == (sim.counters()[0], 2 * n)
+    assert b.pool_size() == a.pool_size()
+
+
+def test_checkpoint_restart_of_a_batch():
+    probs = []
+    rng = np.random.default_rng(11)
+    for k, (nx, G) in enumerate([(13, 5), (64, 16), (50, 33), (40, 12)]):
+        kl, kr = 10 ** rng.uniform(-2, 3, 2)
+        xj = rng.uniform(0.2, 0.8)
+        probs.append(W.slab(nx, G, lambda x, kl=kl, kr=kr, xj=xj: np.where(x < xj, kl, kr), dt=1e-3,
+                            steps=0, w_ref=3e-5, seed=200 + k, pool_cap=1 << 18, name=f"c{k}"))
+    say("[checkpoint] batch of", len(probs))
+    a, b = _restart(lambda: ugkwp.from_batch(probs), 5)
+    for k, p in enumerate(probs):
+        sim = oracle.Sim(p)
+        sim.step(10)
+        compare_state(b, sim, p, inst=k, what=f"restored instance {k}")
+        assert b.get_counters(k) == a.get_counters(k)
+
+
+def test_checkpoint_rejects_what_does_not_fit():
+    p = W.c1_marshak_like()
+    a = ugkwp.from_problem(p)
+    a.step(3)
+    buf = a.get_state()
+    cases = [
+        ("another seed", lambda: ugkwp.from_problem(p.with_(seed=1)), buf, ugkwp.EINVAL),
+        ("another mesh", lambda: ugkwp.from_problem(W.c1_marshak_like().with_(dt=2e-3)), buf, ugkwp.EINVAL),
+        ("truncated", lambda: ugkwp.from_problem(p), buf[:-8], ugkwp.EINVAL),
+        ("small pool", lambda: ugkwp.from_problem(p, pool_capacity=a.pool_size() // 2), buf, ugkwp.EPOOL),
+    ]
+    for what, make, b, code in cases:
+        c = make()
+        with pytest.raises(ugkwp.UGKWPError) as e:
+            c.set_state(b)
+        assert e.value.code == code, what
+        assert c.get_counters() == (0, 0), what
+    bad = buf.copy()
+    bad[:8] = 0
+    c = ugkwp.from_problem(p)
+    with pytest.raises(ugkwp.UGKWPError):
+        c.set_state(bad)
+    c.record(2)
+    with pytest.raises(ugkwp.UGKWPError) as e:
+        c.set_state(buf)
+    assert e.value.code == ugkwp.EINVAL
+    c.record(0)
+    c.set_state(buf)
+    assert c.get_counters() == a.get_counters()
