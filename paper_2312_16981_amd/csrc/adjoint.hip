@@ -239,7 +239,9 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
     if (!adj_gate(A, gate)) return;
     const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
     const Slot s = decode_slot(D, K, j);
-    const Inst& I = D.inst[s.inst];
+    // the wavefront's instance record, copied before the kernel's first store
+    // (scalar loads, read once)
+    const Inst I = D.inst[s.inst];
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
 
     bool run = A.conv[s.inst] == 0 && j < K.n_cg;
@@ -257,39 +259,78 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
         __syncthreads();
         if (stop) return;
     }
+
+    const int g = s.g, Gp = I.Gp;
+    const bool work = run && s.cell_ok;
+    const int cell = I.cell_off + s.lcell;
+    const int nf = 2 * I.dim;
+    // every load of the sweep before the first wait
+    const bool act = s.cell_ok && s.active;
+    double lam = 0.0, mui = 0.0, tw = 0.0, sg = 0.0, rb = 0.0, dphi = 0.0, tbar = 0.0;
+    FaceRef fr[4];
+    double Df[4], nlam[4], ntw[4], nsig[4], nmu[4], nrb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        fr[q] = face_ref(I, j, s.lcell, g, q);
+        Df[q] = nlam[q] = ntw[q] = nsig[q] = nmu[q] = nrb[q] = 0.0;
+    }
+    if (act) {
+        lam = D.sv[j];
+        mui = mu_in[cell];
+        tw = temp_weight(D, K, cell);
+        sg = D.sig[j];
+        rb = A.rbar[j];
+        dphi = A.dphi[j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= nf) continue;
+            Df[q] = (q >> 1) == 0 ? D.Dx[fr[q].fslot] : D.Dy[fr[q].fslot];
+            if (fr[q].inside) {
+                nlam[q] = D.sv[fr[q].nbj];
+                ntw[q] = temp_weight(D, K, fr[q].nbcell);
+                nsig[q] = D.sig[fr[q].nbj];
+                nmu[q] = mu_in[fr[q].nbcell];
+                nrb[q] = A.rbar[fr[q].nbj];
+            }
+        }
+    }
+    if (s.cell_ok && g == 0) {
+        tbar = A.Tbar[cell];
+        if (!act) mui = mu_in[cell];
+    }
+
     const int64_t rel = j - I.cg_off;
     if (run && rel >= 0 && rel < RES_SUB) {
         AdjResid z = {0ull, 0ull};
         A.res[((int64_t)s.inst * RES_SLOTS + (k + 1) % RES_SLOTS) * RES_SUB + rel] = z;
     }
 
-    const int g = s.g, Gp = I.Gp;
-    const bool work = run && s.cell_ok;
-    const int cell = I.cell_off + s.lcell;
     double contrib = 0.0;
     if (work && s.active) {
-        const double lam = D.sv[j];
-        const double mui = mu_in[cell];
-        const double fac = temp_weight(D, K, cell) * D.sig[j] / (1.0 + lam);
-        const double bb = fac * mui + A.rbar[j] / (1.0 + lam);
+        const double fac = tw * sg / (1.0 + lam);
+        const double bb = fac * mui + rb / (1.0 + lam);
         double lt = 0.0;
-        for (int q = 0; q < 2 * I.dim; ++q) {
-            const FaceRef f = face_ref(I, j, s.lcell, g, q);
-            const double Df = (q >> 1) == 0 ? D.Dx[f.fslot] : D.Dy[f.fslot];
-            if (f.inside) lt += f.S * Df * (bbar_of(D, K, A, mu_in, f.nbj, f.nbcell) - bb);
-            else if (I.bc[q] != BC_REFLECT) lt -= f.S * Df * bb;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= nf) continue;
+            if (fr[q].inside) {
+                const double bn = ntw[q] * nsig[q] / (1.0 + nlam[q]) * nmu[q] + nrb[q] / (1.0 + nlam[q]);
+                lt += fr[q].S * Df[q] * (bn - bb);
+            } else if (I.bc[q] != BC_REFLECT) {
+                lt -= fr[q].S * Df[q] * bb;
+            }
         }
-        const double phibar = -fac * mui + lam / (1.0 + lam) * A.rbar[j] + (K.dt / I.V) * lt;
-        contrib = A.dphi[j] * phibar;
+        const double phibar = -fac * mui + lam / (1.0 + lam) * rb + (K.dt / I.V) * lt;
+        contrib = dphi * phibar;
     }
     for (int m = 1; m < Gp; m <<= 1) contrib += __shfl_xor(contrib, m, WAVE);
 
     double dm = 0.0, mm = 0.0;
     if (work && g == 0) {
-        const double mun = A.Tbar[cell] + contrib;
+        const double mun = tbar + contrib;
         if (!isfinite(mun)) atomicOr(A.status + ADJ_ERR, 1ull);
         mu_out[cell] = mun;
-        dm = fabs(mun - mu_in[cell]);
+        dm = fabs(mun - mui);
         mm = fabs(mun);
     }
     dm = wave_nmax(dm);

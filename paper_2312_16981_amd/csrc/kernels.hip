@@ -193,6 +193,19 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroLi
     if (!gate_open(D, K, 0)) return;
     const int64_t j = (int64_t)blockIdx.x * COUNT_THREADS + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * COUNT_THREADS;
+    // the slot's loads (and its wavefront's instance record) before any store
+    const bool in = j < K.n_cg;
+    const Slot s = decode_slot(D, K, j);
+    const Inst I = D.inst[s.inst];
+    double rho = 0.0, rhop = 0.0, es = 0.0, nl = 0.0, nh = 0.0, T = 0.0;
+    if (in && s.active) {
+        rho = D.rho[j];
+        rhop = D.rhop[j];
+        es = D.es[j];
+        nl = D.nu[I.edge_off + s.g];
+        nh = D.nu[I.edge_off + s.g + 1];
+        T = D.T[I.cell_off + s.lcell];
+    }
     if (blockIdx.x == 0) {
         if (threadIdx.x < N_COUNTERS) {
             const int q = threadIdx.x;
@@ -213,17 +226,15 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroLi
         for (int64_t q = j; q < Z.words[r]; q += stride) p[q] = 0ull;
     }
     int N = 0;
-    if (j < K.n_cg) {
-        const Slot s = decode_slot(D, K, j);
+    if (in) {
         if (!s.active) {
             D.nb[j] = 0;
             D.rhoh[j] = 0.0;
             D.wnew[j] = 0.0;
         } else {
-            const Inst& I = D.inst[s.inst];
-            const double rh = D.rho[j] - D.rhop[j];
+            const double rh = rho - rhop;
             D.rhoh[j] = rh;
-            const double eov = D.es[j] * rh;
+            const double eov = es * rh;
             const double E = eov * I.V;
             if (E > 0.0) {
                 const double q = eov / I.w_ref;
@@ -231,9 +242,7 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroLi
             }
             D.nb[j] = N;
             D.wnew[j] = N >= 1 ? E / (double)N : 0.0;
-            if (N >= 1)
-                D.beta[j] = freq_slope(D.nu[I.edge_off + s.g], D.nu[I.edge_off + s.g + 1],
-                                       D.T[I.cell_off + s.lcell]);
+            if (N >= 1) D.beta[j] = freq_slope(nl, nh, T);
         }
     }
     if (part) {
@@ -281,15 +290,35 @@ __device__ inline int64_t block_excl_scan(int64_t v, int64_t* total)
 
 __device__ inline bool scan_open(const ScanGate& q) { return q.expect == GATE_OFF || *q.step == q.expect; }
 
+// A chunk of SCAN_CHUNK items is read in SCAN_ITEMS / 4 passes; in pass r,
+// thread t holds the four consecutive items from 4 (t + SCAN_THREADS r), so
+// that a wavefront's loads and stores cover contiguous memory.  The last chunk
+// (possibly partial) takes the same path with a bounds test per item.
+constexpr int SCAN_PASSES = SCAN_ITEMS / 4;
+
+__device__ inline int4 scan_load4(const int32_t* in, int64_t i, int64_t n, bool full)
+{
+    if (full) return *reinterpret_cast<const int4*>(in + i);
+    int4 v;
+    v.x = i + 0 < n ? in[i + 0] : 0;
+    v.y = i + 1 < n ? in[i + 1] : 0;
+    v.z = i + 2 < n ? in[i + 2] : 0;
+    v.w = i + 3 < n ? in[i + 3] : 0;
+    return v;
+}
+
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(ScanGate q, const int32_t* in, int64_t n,
                                                                 int64_t* part)
 {
     if (!scan_open(q)) return;
-    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    const int64_t c0 = (int64_t)blockIdx.x * SCAN_CHUNK;
+    const bool full = c0 + SCAN_CHUNK <= n;
+    int4 v[SCAN_PASSES];
+#pragma unroll
+    for (int r = 0; r < SCAN_PASSES; ++r) v[r] = scan_load4(in, c0 + 4 * ((int64_t)threadIdx.x + SCAN_THREADS * r), n, full);
     int64_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k)
-        if (base + k < n) sum += in[base + k];
+    for (int r = 0; r < SCAN_PASSES; ++r) sum += (int64_t)v[r].x + v[r].y + v[r].z + v[r].w;
     int64_t tot;
     block_excl_scan(sum, &tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
@@ -363,20 +392,30 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(ScanGate q, const i
                                                           const int64_t* part, int64_t* out)
 {
     if (!scan_open(q)) return;
-    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
-    int32_t v[SCAN_ITEMS];
-    int64_t sum = 0;
+    const int64_t c0 = (int64_t)blockIdx.x * SCAN_CHUNK;
+    const bool full = c0 + SCAN_CHUNK <= n;
+    int4 v[SCAN_PASSES];
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        v[k] = base + k < n ? in[base + k] : 0;
-        sum += v[k];
-    }
-    int64_t tot;
-    int64_t run = part[blockIdx.x] + block_excl_scan(sum, &tot);
+    for (int r = 0; r < SCAN_PASSES; ++r) v[r] = scan_load4(in, c0 + 4 * ((int64_t)threadIdx.x + SCAN_THREADS * r), n, full);
+    int64_t carry = part[blockIdx.x];
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        if (base + k < n) out[base + k] = run;
-        run += v[k];
+    for (int r = 0; r < SCAN_PASSES; ++r) {
+        const int64_t sum = (int64_t)v[r].x + v[r].y + v[r].z + v[r].w;
+        int64_t tot;
+        const int64_t ex = carry + block_excl_scan(sum, &tot);
+        carry += tot;
+        const int64_t i = c0 + 4 * ((int64_t)threadIdx.x + SCAN_THREADS * r);
+        const int64_t o0 = ex, o1 = o0 + v[r].x, o2 = o1 + v[r].y, o3 = o2 + v[r].z;
+        if (full) {
+            longlong2* p = reinterpret_cast<longlong2*>(out + i);
+            p[0] = make_longlong2(o0, o1);
+            p[1] = make_longlong2(o2, o3);
+        } else {
+            if (i + 0 < n) out[i + 0] = o0;
+            if (i + 1 < n) out[i + 1] = o1;
+            if (i + 2 < n) out[i + 2] = o2;
+            if (i + 3 < n) out[i + 3] = o3;
+        }
     }
 }
 
@@ -871,59 +910,110 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(Dev D, Consts K, 
 // ---------------------------------------------------------------------------
 // A4: wave free-transport flux and the static source Q
 
-__device__ inline double wave_source(const Dev& D, const Consts& K, int64_t j, const Slot& s)
+// The faces of a slot's cell in the order XLO, XHI, YLO, YHI (the first two in
+// 1-D): whether the neighbour across lies in the instance, its slot, the face's
+// tally slot and area.  Index arithmetic only, so that a kernel can issue every
+// load of the stencil before it waits for the first.
+struct CellFaces {
+    bool inside[4];
+    int64_t nbj[4], fslot[4];
+    double S[4];
+};
+
+__device__ inline CellFaces cell_faces(const Inst& I, int64_t j, int ix, int iy, int g)
 {
-    const Inst& I = D.inst[s.inst];
-    const int Gp = I.Gp, g = s.g, nx = I.nx;
+    CellFaces F;
+    const int Gp = I.Gp, nx = I.nx;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool lo = (q & 1) == 0;
+        if (q < 2) {
+            F.inside[q] = lo ? ix > 0 : ix < nx - 1;
+            F.nbj[q] = j + (lo ? -Gp : Gp);
+            F.fslot[q] = I.fx_off + (((int64_t)iy * (nx + 1) + ix + (lo ? 0 : 1)) << I.lgGp) + g;
+            F.S[q] = I.dy;
+        } else {
+            F.inside[q] = lo ? iy > 0 : iy < I.ny - 1;
+            F.nbj[q] = j + (lo ? -(int64_t)nx * Gp : (int64_t)nx * Gp);
+            F.fslot[q] = I.fy_off + (((int64_t)(iy + (lo ? 0 : 1)) * nx + ix) << I.lgGp) + g;
+            F.S[q] = I.dx;
+        }
+    }
+    return F;
+}
+
+// Wave flux through the faces of slot j and its static source Q (Remark 3:
+// coefficient C4 - e^{-s} where the cell sampled particles, C4 where it did
+// not).  *inflow gets the energy the wave flux brings in through the domain
+// boundary.
+__device__ inline double wave_source(const Dev& D, const Consts& K, const Inst& I, int64_t j, const Slot& s,
+                                     const CellFaces& F, double* inflow_out)
+{
+    const int g = s.g, nx = I.nx;
     const int ix = s.lcell % nx, iy = s.lcell / nx;
     const double cq = K.c / (4.0 * K.eps);
-    const double Ah = D.nb[j] > 0 ? D.wc[j] : D.c4[j];
-    const double here = Ah * D.rhoh[j];
     const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
-    double fsum = 0.0, inflow = 0.0;
-    // faces in the order XLO, XHI, YLO, YHI; flux through a face along +axis is
-    // cq (A_low rho^h_low - A_high rho^h_high)
-    for (int q = 0; q < 2 * I.dim; ++q) {
-        const int axis = q >> 1;
-        const bool lo = (q & 1) == 0;
-        bool inside;
-        int64_t nbj = 0;
-        if (axis == 0) {
-            inside = lo ? ix > 0 : ix < nx - 1;
-            nbj = j + (lo ? -Gp : Gp);
-        } else {
-            inside = lo ? iy > 0 : iy < I.ny - 1;
-            nbj = j + (lo ? -(int64_t)nx * Gp : (int64_t)nx * Gp);
+    const int nf = 2 * I.dim;
+    // every load first
+    const int nb_here = D.nb[j];
+    const double wc_here = D.wc[j], c4_here = D.c4[j], rhoh_here = D.rhoh[j], rho_here = D.rho[j];
+    int nb_n[4];
+    double wc_n[4], c4_n[4], rhoh_n[4], pb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        nb_n[q] = 0;
+        wc_n[q] = c4_n[q] = rhoh_n[q] = pb[q] = 0.0;
+        if (q >= nf) continue;
+        if (F.inside[q]) {
+            nb_n[q] = D.nb[F.nbj[q]];
+            wc_n[q] = D.wc[F.nbj[q]];
+            c4_n[q] = D.c4[F.nbj[q]];
+            rhoh_n[q] = D.rhoh[F.nbj[q]];
+        } else if (I.bc[q] == BC_PLANCK) {
+            pb[q] = phib[q * MAX_G + g];
         }
-        const double S = axis == 0 ? I.dy : I.dx;
-        double there;
-        if (inside) {
-            const double An = D.nb[nbj] > 0 ? D.wc[nbj] : D.c4[nbj];
-            there = An * D.rhoh[nbj];
-        } else {
-            const int bc = I.bc[q];
-            if (bc == BC_REFLECT) continue;
-            there = bc == BC_PLANCK ? D.c4[j] * phib[q * MAX_G + g] : 0.0;
-        }
-        const double Fpos = lo ? cq * (there - here) : cq * (here - there);
-        const double Fin = lo ? Fpos : -Fpos;
-        fsum += S * Fin;
-        if (!inside) inflow += K.dt * S * Fin / K.c;
     }
     // gross particle crossings into / out of the cell
     const int64_t fl = I.fx_off + (((int64_t)iy * (nx + 1) + ix) << I.lgGp) + g;
-    const int64_t fr = fl + Gp;
-    double a_in = D.ftx[fl * 2 + 0] + D.ftx[fr * 2 + 1];
-    double a_out = D.ftx[fl * 2 + 1] + D.ftx[fr * 2 + 0];
+    const int64_t fr = fl + I.Gp;
+    const double tx0 = D.ftx[fl * 2 + 0], tx1 = D.ftx[fr * 2 + 1], tx2 = D.ftx[fl * 2 + 1], tx3 = D.ftx[fr * 2 + 0];
+    double ty0 = 0.0, ty1 = 0.0, ty2 = 0.0, ty3 = 0.0;
     if (I.dim == 2) {
         const int64_t fb = I.fy_off + (((int64_t)iy * nx + ix) << I.lgGp) + g;
         const int64_t ft = fb + ((int64_t)nx << I.lgGp);
-        a_in += D.fty[fb * 2 + 0] + D.fty[ft * 2 + 1];
-        a_out += D.fty[fb * 2 + 1] + D.fty[ft * 2 + 0];
+        ty0 = D.fty[fb * 2 + 0]; ty1 = D.fty[ft * 2 + 1];
+        ty2 = D.fty[fb * 2 + 1]; ty3 = D.fty[ft * 2 + 0];
     }
-    if (inflow != 0.0)
-        atomicAdd(D.diag_sub + ((int64_t)s.inst * DIAG_SUB + (blockIdx.x & (DIAG_SUB - 1))) * 8 + 0, inflow);
-    return D.rho[j] + (K.dt / I.V) * fsum + (a_in - a_out) / I.V;
+    const double Ah = nb_here > 0 ? wc_here : c4_here;
+    const double here = Ah * rhoh_here;
+    double fsum = 0.0, inflow = 0.0;
+    // flux through a face along +axis is cq (A_low rho^h_low - A_high rho^h_high)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q >= nf) continue;
+        const bool lo = (q & 1) == 0;
+        double there;
+        if (F.inside[q]) {
+            const double An = nb_n[q] > 0 ? wc_n[q] : c4_n[q];
+            there = An * rhoh_n[q];
+        } else {
+            const int bc = I.bc[q];
+            if (bc == BC_REFLECT) continue;
+            there = bc == BC_PLANCK ? c4_here * pb[q] : 0.0;
+        }
+        const double Fpos = lo ? cq * (there - here) : cq * (here - there);
+        const double Fin = lo ? Fpos : -Fpos;
+        fsum += F.S[q] * Fin;
+        if (!F.inside[q]) inflow += K.dt * F.S[q] * Fin / K.c;
+    }
+    double a_in = tx0 + tx1;
+    double a_out = tx2 + tx3;
+    if (I.dim == 2) {
+        a_in += ty0 + ty1;
+        a_out += ty2 + ty3;
+    }
+    *inflow_out = inflow;
+    return rho_here + (K.dt / I.V) * fsum + (a_in - a_out) / I.V;
 }
 
 // ---------------------------------------------------------------------------
@@ -977,19 +1067,17 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     // batches: a block whose four wavefronts all belong to converged instances
     // returns after one load (the flags of its wavefronts, one byte each)
     uint32_t flags = 0xFFFFFFFFu;
-    if (K.n_inst > 1) {
-        if (FIRST) {
-            if (lane == 0) D.wave_run[(int64_t)blockIdx.x * (SI_THREADS / WAVE) + wid] = 1;
-        } else {
-            flags = ((const uint32_t*)D.wave_run)[blockIdx.x];
-            if (flags == 0) return;
-        }
+    if (K.n_inst > 1 && !FIRST) {
+        flags = ((const uint32_t*)D.wave_run)[blockIdx.x];
+        if (flags == 0) return;
     }
     const int64_t j = (int64_t)blockIdx.x * SI_THREADS + threadIdx.x;
     const Slot s = decode_slot(D, K, j);
-    const Inst& I = D.inst[s.inst];
+    // the wavefront's instance record, copied before the kernel's first store:
+    // its loads can then go through the scalar cache, and nothing below has to
+    // read it again from memory
+    const Inst I = D.inst[s.inst];
 
-    bool run = ((flags >> (8 * wid)) & 0xFFu) != 0 && D.ist[s.inst].conv_sweeps == 0 && j < K.n_cg;
     if (decide_prev) {
         // the whole block stops when the iteration has converged (decided now or
         // by an earlier sweep): a speculative sweep past convergence costs little
@@ -1008,100 +1096,118 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         __syncthreads();
         if (stop) return;
     }
-    const int64_t rel = j - I.cg_off;
-    if (run && rel >= 0 && rel < RES_SUB) {
-        Resid z = {0ull, 0ull, 0ull, 0ull};
-        res_slot(D, K, s.inst, k + 1)[rel] = z;
-    }
-
-    double dr = 0.0, mr = 0.0, dT = 0.0, mT = 0.0;
+    const bool wave_on = ((flags >> (8 * wid)) & 0xFFu) != 0;
     const int g = s.g, Gp = I.Gp, G = I.G;
+    const bool load = wave_on && s.cell_ok;       // the slot's cell is updated (every group lane)
+    const bool act = load && s.active;            // and the slot is a group of it
+
+    // every load of the sweep is issued here, before the first wait
+    const int nx = I.nx;
+    const int ix = s.lcell % nx, iy = s.lcell / nx;
+    const int cell = I.cell_off + s.lcell;
+    const CellFaces F = cell_faces(I, j, ix, iy, g);
+    const int nf = 2 * I.dim;
+    const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
+    double phi = 0.0, Qj = 0.0, lam = 0.0, sig = 0.0, rho_prev = 0.0;
+    double Df[4] = {0.0, 0.0, 0.0, 0.0}, pn[4] = {0.0, 0.0, 0.0, 0.0};
+    if (act) {
+        phi = phi_in[j];
+        if (!FIRST) Qj = D.Q[j];
+        lam = D.sv[j];
+        sig = D.sig[j];
+        rho_prev = FIRST ? D.rho[j] : D.rho_new[j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= nf) continue;
+            Df[q] = q < 2 ? D.Dx[F.fslot[q]] : D.Dy[F.fslot[q]];
+            if (F.inside[q]) pn[q] = phi_in[F.nbj[q]];
+            else if (I.bc[q] == BC_PLANCK) pn[q] = phib[q * MAX_G + g];
+        }
+    }
+    double Tn = 1.0, Tk = 1.0, cvol = 1.0;
+    uint8_t pinned = 0;
+    double nu_lo = 0.0, nu_top = 0.0;
+    if (load) {
+        Tn = D.T[cell];
+        Tk = FIRST ? Tn : D.T_new[cell];
+        pinned = D.pinned[cell];
+        cvol = D.cvol[cell];
+        if (g <= G) nu_lo = D.nu[I.edge_off + g];
+        if (g == G - 1 && G == Gp) nu_top = D.nu[I.edge_off + G];
+    }
+    double inflow = 0.0;
+    if (FIRST && act) Qj = wave_source(D, K, I, j, s, F, &inflow);
+
+    const bool run = wave_on && D.ist[s.inst].conv_sweeps == 0 && j < K.n_cg;
+    double dr = 0.0, mr = 0.0, dT = 0.0, mT = 0.0;
     const bool work = run && s.cell_ok;
-    double contrib = 0.0;
+    double contrib = 0.0, r = 0.0;
     if (work && s.active) {
-        const int nx = I.nx;
-        const int ix = s.lcell % nx, iy = s.lcell / nx;
-        const double phi = phi_in[j];
-        const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
         double lap = 0.0;
-        for (int q = 0; q < 2 * I.dim; ++q) {
-            const int axis = q >> 1;
-            const bool lo = (q & 1) == 0;
-            bool inside;
-            int64_t nbj, fslot;
-            double S;
-            if (axis == 0) {
-                inside = lo ? ix > 0 : ix < nx - 1;
-                nbj = j + (lo ? -Gp : Gp);
-                fslot = I.fx_off + (((int64_t)iy * (nx + 1) + ix + (lo ? 0 : 1)) << I.lgGp) + g;
-                S = I.dy;
-            } else {
-                inside = lo ? iy > 0 : iy < I.ny - 1;
-                nbj = j + (lo ? -(int64_t)nx * Gp : (int64_t)nx * Gp);
-                fslot = I.fy_off + (((int64_t)(iy + (lo ? 0 : 1)) * nx + ix) << I.lgGp) + g;
-                S = I.dx;
-            }
-            const double Df = axis == 0 ? D.Dx[fslot] : D.Dy[fslot];
-            double pn;
-            if (inside) pn = phi_in[nbj];
-            else {
-                const int bc = I.bc[q];
-                pn = bc == BC_PLANCK ? phib[q * MAX_G + g] : (bc == BC_REFLECT ? phi : 0.0);
-            }
-            lap += S * Df * (pn - phi);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= nf) continue;
+            const double p = F.inside[q] ? pn[q] : (I.bc[q] == BC_REFLECT ? phi : pn[q]);
+            lap += F.S[q] * Df[q] * (p - phi);
         }
-        double Qj;
-        if (FIRST) {
-            Qj = wave_source(D, K, j, s);
-            D.Q[j] = Qj;
-        } else {
-            Qj = D.Q[j];
-        }
-        const double lam = D.sv[j];
         const double b = Qj + (K.dt / I.V) * lap;
-        const double r = (b + lam * phi) / (1.0 + lam);
+        r = (b + lam * phi) / (1.0 + lam);
         const double em = (b - phi) / (1.0 + lam);
-        contrib = D.sig[j] * em;
-        dr = fabs(r - (FIRST ? D.rho[j] : D.rho_new[j]));
+        contrib = sig * em;
+        dr = fabs(r - rho_prev);
         mr = fabs(r);
-        D.rho_new[j] = r;
     }
     // group sum over the Gp lanes of the cell (butterfly: every lane gets the same bits)
     for (int m = 1; m < Gp; m <<= 1) contrib += __shfl_xor(contrib, m, WAVE);
 
     double Tnew = 1.0;
+    bool bad = false;
     if (work) {
-        const int cell = I.cell_off + s.lcell;
-        const double Tn = D.T[cell];
-        const double Tk = FIRST ? Tn : D.T_new[cell];
-        Tnew = D.pinned[cell] ? Tn : Tn + (K.dt / (K.eps * K.eps * D.cvol[cell])) * contrib;
+        Tnew = pinned ? Tn : Tn + (K.dt / (K.eps * K.eps * cvol)) * contrib;
         if (!(Tnew > 0.0) || !isfinite(Tnew)) {
-            if (g == 0) {
-                atomicOr(&D.ist[s.inst].bad, 1);
-                atomicOr((unsigned long long*)(D.counters + CNT_ERR), ERR_TEMP);
-            }
+            bad = true;
             Tnew = 1.0;
         }
         if (g == 0) {
-            D.T_new[cell] = Tnew;
             dT = fabs(Tnew - Tk);
             mT = Tnew;
         }
     }
     // phi^{k+1}: lane g evaluates the Planck edge value at its lower edge nu_g / T,
     // takes the upper one from lane g+1 (lane G-1 evaluates it itself when G = Gp)
+    double phi_new = 0.0;
     {
         const bool edge_lane = work && g <= G;
-        const double xe = edge_lane ? D.nu[I.edge_off + g] / Tnew : 0.0;
+        const double xe = edge_lane ? nu_lo / Tnew : 0.0;
         const double ve = edge_lane ? planck_edge_value(xe, c_head) : 0.0;
         double xh = __shfl_down(xe, 1, Gp < 2 ? 2 : Gp);
         double vh = __shfl_down(ve, 1, Gp < 2 ? 2 : Gp);
         if (work && g == G - 1 && (G == Gp)) {
-            xh = D.nu[I.edge_off + G] / Tnew;
+            xh = nu_top / Tnew;
             vh = planck_edge_value(xh, c_head);
         }
-        if (work && s.active)
-            phi_out[j] = phi_from_band(K.a, K.c, Tnew, planck_band_from_edges(xe, ve, xh, vh));
+        if (work && s.active) phi_new = phi_from_band(K.a, K.c, Tnew, planck_band_from_edges(xe, ve, xh, vh));
+    }
+    // stores
+    if (FIRST && K.n_inst > 1 && lane == 0) D.wave_run[(int64_t)blockIdx.x * (SI_THREADS / WAVE) + wid] = 1;
+    const int64_t rel = j - I.cg_off;
+    if (run && rel >= 0 && rel < RES_SUB) {
+        Resid z = {0ull, 0ull, 0ull, 0ull};
+        res_slot(D, K, s.inst, k + 1)[rel] = z;
+    }
+    if (work && s.active) {
+        if (FIRST) D.Q[j] = Qj;
+        D.rho_new[j] = r;
+        phi_out[j] = phi_new;
+        if (inflow != 0.0)
+            atomicAdd(D.diag_sub + ((int64_t)s.inst * DIAG_SUB + (blockIdx.x & (DIAG_SUB - 1))) * 8 + 0, inflow);
+    }
+    if (work && g == 0) {
+        if (bad) {
+            atomicOr(&D.ist[s.inst].bad, 1);
+            atomicOr((unsigned long long*)(D.counters + CNT_ERR), ERR_TEMP);
+        }
+        D.T_new[cell] = Tnew;
     }
     // residual maxima: wavefront, then runs of wavefronts of one instance in the block
     dr = wave_nmax(dr);
@@ -1182,6 +1288,10 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
     // the commit below advances *D.step while other blocks may still start:
     // both the step's own value and the next one open this launch
     if (!gate_open(D, K, 0) && !gate_open(D, K, 1)) return;
+    const int64_t j = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x;
+    const Slot s = decode_slot(D, K, j);
+    // the wavefront's instance record, copied before the kernel's first store
+    const Inst I = D.inst[s.inst];
     int ns_single = 0;
     if (last_sweep >= 0) {
         __shared__ int sh_ns;
@@ -1201,8 +1311,43 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
     } else if (!step_committed(D, K)) {
         return;
     }
-    const int64_t j = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x;
-    const Slot s = decode_slot(D, K, j);
+    // the slot's loads, before the stores of the commit
+    const bool in = j < K.n_cg;
+    const int g = s.g, nx = I.nx, ix = s.lcell % nx, iy = s.lcell / nx;
+    const int cell = I.cell_off + s.lcell;
+    double surv = 0.0, rho = 0.0, rho_new = 0.0, phi = 0.0, phi_next = 0.0, cv = 0.0, T0 = 0.0, T1 = 0.0;
+    uint8_t pin = 0;
+    bool bnd[4] = {false, false, false, false};
+    int64_t fs[4] = {0, 0, 0, 0};
+    double Df[4] = {0.0, 0.0, 0.0, 0.0}, tal[4] = {0.0, 0.0, 0.0, 0.0}, pb[4] = {0.0, 0.0, 0.0, 0.0};
+    if (in && s.active) {
+        const int ns = last_sweep >= 0 ? ns_single : D.ist[s.inst].conv_sweeps;
+        surv = D.surv[j];
+        rho = D.rho[j];
+        rho_new = D.rho_new[j];
+        pin = D.pinned[cell];
+        phi = sweep_in(D, ns - 1)[j];          // phi^k of the last sweep
+        phi_next = sweep_out(D, ns - 1)[j];    // phi(T^{n+1}): the next step's phi^0
+        if (g == 0) {
+            cv = D.cvol[cell];
+            T0 = D.T[cell];
+            T1 = D.T_new[cell];
+        }
+        const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= 2 * I.dim) continue;
+            const int axis = q >> 1;
+            const bool lo = (q & 1) == 0;
+            bnd[q] = axis == 0 ? (lo ? ix == 0 : ix == nx - 1) : (lo ? iy == 0 : iy == I.ny - 1);
+            if (!bnd[q]) continue;
+            fs[q] = axis == 0 ? I.fx_off + (((int64_t)iy * (nx + 1) + ix + (lo ? 0 : 1)) << I.lgGp) + g
+                              : I.fy_off + (((int64_t)(iy + (lo ? 0 : 1)) * nx + ix) << I.lgGp) + g;
+            Df[q] = axis == 0 ? D.Dx[fs[q]] : D.Dy[fs[q]];
+            tal[q] = (axis == 0 ? D.ftx : D.fty)[fs[q] * 2 + (lo ? 1 : 0)];
+            if (I.bc[q] == BC_PLANCK) pb[q] = phib[q * MAX_G + g];
+        }
+    }
     if (blockIdx.x == 0) {
         // survivors of the push: sum of its per-block counts
         __shared__ unsigned long long part[DIAG_THREADS / WAVE];
@@ -1218,9 +1363,8 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
         }
     }
     // commit: survivor density for the next step, birth counters, pool size
-    if (j < K.n_cg) {
-        const Inst& I = D.inst[s.inst];
-        D.rhop[j] = s.active ? D.surv[j] / I.V : 0.0;
+    if (in) {
+        D.rhop[j] = s.active ? surv / I.V : 0.0;
         if (j == I.cg_off) {
             const int64_t end = s.inst + 1 < K.n_inst ? D.boff[D.inst_cg[s.inst + 1]] : D.n_births_total[0];
             D.ist[s.inst].births += (uint64_t)(end - D.boff[I.cg_off]);
@@ -1234,41 +1378,23 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
         }
     }
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // inflow_eq, exit/c, injection, e0, e1
-    if (s.active) {
-        const Inst& I = D.inst[s.inst];
-        const int ns = last_sweep >= 0 ? ns_single : D.ist[s.inst].conv_sweeps;
-        const int nx = I.nx, ix = s.lcell % nx, iy = s.lcell / nx, g = s.g;
-        const int cell = I.cell_off + s.lcell;
-        const double phi = sweep_in(D, ns - 1)[j];          // phi^k of the last sweep
-        D.phi0[j] = sweep_out(D, ns - 1)[j];                // phi(T^{n+1}): the next step's phi^0
-        const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
-        for (int q = 0; q < 2 * I.dim; ++q) {
-            const int axis = q >> 1;
-            const bool lo = (q & 1) == 0;
-            const bool boundary = axis == 0 ? (lo ? ix == 0 : ix == nx - 1) : (lo ? iy == 0 : iy == I.ny - 1);
-            if (!boundary) continue;
-            int64_t fslot;
-            double S;
-            if (axis == 0) {
-                fslot = I.fx_off + (((int64_t)iy * (nx + 1) + ix + (lo ? 0 : 1)) << I.lgGp) + g;
-                S = I.dy;
-            } else {
-                fslot = I.fy_off + (((int64_t)(iy + (lo ? 0 : 1)) * nx + ix) << I.lgGp) + g;
-                S = I.dx;
-            }
-            const double Df = axis == 0 ? D.Dx[fslot] : D.Dy[fslot];
+    if (in && s.active) {
+        D.phi0[j] = phi_next;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= 2 * I.dim || !bnd[q]) continue;
+            const double S = (q >> 1) == 0 ? I.dy : I.dx;
             const int bc = I.bc[q];
-            const double pn = bc == BC_PLANCK ? phib[q * MAX_G + g] : (bc == BC_REFLECT ? phi : 0.0);
-            v[0] += K.dt * S * Df * (pn - phi) / K.c;
-            const double* tal = axis == 0 ? D.ftx : D.fty;
-            v[1] += tal[fslot * 2 + (lo ? 1 : 0)] / K.c;
+            const double pn = bc == BC_PLANCK ? pb[q] : (bc == BC_REFLECT ? phi : 0.0);
+            v[0] += K.dt * S * Df[q] * (pn - phi) / K.c;
+            v[1] += tal[q] / K.c;
         }
-        if (D.pinned[cell]) v[2] = I.V * (K.dt * D.sig[j] / (K.eps * K.eps)) * (phi - D.rho_new[j]);
-        v[3] = I.V * D.rho[j] / K.c;
-        v[4] = I.V * D.rho_new[j] / K.c;
+        if (pin) v[2] = I.V * (K.dt * D.sig[j] / (K.eps * K.eps)) * (phi - rho_new);
+        v[3] = I.V * rho / K.c;
+        v[4] = I.V * rho_new / K.c;
         if (g == 0) {
-            v[3] += I.V * D.cvol[cell] * D.T[cell];
-            v[4] += I.V * D.cvol[cell] * D.T_new[cell];
+            v[3] += I.V * cv * T0;
+            v[4] += I.V * cv * T1;
         }
     }
 #pragma unroll
