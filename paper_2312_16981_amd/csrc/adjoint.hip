@@ -29,7 +29,7 @@ __device__ inline double planck_edge_weight(double x)
 // Heat-capacity weight dt / (eps^2 C_v) of the temperature update; 0 in pinned cells.
 __device__ inline double temp_weight(const Dev& D, const Consts& K, int cell)
 {
-    return D.pinned[cell] ? 0.0 : K.dt / (K.eps * K.eps * D.cvol[cell]);
+    return D.pinned[cell] ? 0.0 : D.dtcv[cell];
 }
 
 __device__ inline bool adj_gate(const Adj& A, uint32_t gate)
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
                 lt -= fr[q].S * Df[q] * bb;
             }
         }
-        const double phibar = -fac * mui + lam / (1.0 + lam) * rb + (K.dt / I.V) * lt;
+        const double phibar = -fac * mui + lam / (1.0 + lam) * rb + I.dt_V * lt;
         contrib = dphi * phibar;
     }
     for (int m = 1; m < Gp; m <<= 1) contrib += __shfl_xor(contrib, m, WAVE);
@@ -424,8 +424,8 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_grad(Dev D, Consts K, Adj A
     const double lam = D.sv[j], sig = D.sig[j];
     const double bb = wi * sig / (1.0 + lam) * mui + A.rbar[j] / (1.0 + lam);
     const double phik = A.phi[j];
-    const double dtV = K.dt / I.V;
-    const double cq = K.c / (4.0 * K.eps);
+    const double dtV = I.dt_V;
+    const double cq = K.cq;
     const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
     double lap = 0.0, accu = 0.0, sig_face = 0.0, s_planck = 0.0;
     for (int q = 0; q < 2 * I.dim; ++q) {

@@ -31,6 +31,7 @@ struct Inst {
     int64_t fx_off;        // first x-face slot ((nx+1)*ny faces, stride Gp)
     int64_t fy_off;        // first y-face slot (nx*(ny+1) faces, stride Gp)
     double x0, y0, dx, dy, V;
+    double dt_V;           // dt / V
     double bcT[4];
     double w_ref;
     uint64_t seed;
@@ -42,6 +43,7 @@ struct Consts {
     double e2c;            // eps^2 / c   (tau = e2c / sigma)
     double cv;             // c / eps     (particle speed)
     double lam_scale;      // c dt / eps^2
+    double cq;             // c / (4 eps)   (wave flux factor)
     double nu_power;
     double si_tol;
     int64_t n_cap;
@@ -155,6 +157,7 @@ struct Dev {
     double* Dy;
     // per cell
     const double* cvol;         // heat capacity
+    const double* dtcv;         // dt / (eps^2 C_v): the temperature update's weight
     double* T;
     double* T_new;
     const uint8_t* pinned;

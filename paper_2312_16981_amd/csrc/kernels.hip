@@ -951,7 +951,7 @@ __device__ inline double wave_source(const Dev& D, const Consts& K, const Inst& 
 {
     const int g = s.g, nx = I.nx;
     const int ix = s.lcell % nx, iy = s.lcell / nx;
-    const double cq = K.c / (4.0 * K.eps);
+    const double cq = K.cq;
     const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
     const int nf = 2 * I.dim;
     // every load first
@@ -1013,7 +1013,7 @@ __device__ inline double wave_source(const Dev& D, const Consts& K, const Inst& 
         a_out += ty2 + ty3;
     }
     *inflow_out = inflow;
-    return rho_here + (K.dt / I.V) * fsum + (a_in - a_out) / I.V;
+    return rho_here + I.dt_V * fsum + (a_in - a_out) / I.V;
 }
 
 // ---------------------------------------------------------------------------
@@ -1124,14 +1124,14 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
             else if (I.bc[q] == BC_PLANCK) pn[q] = phib[q * MAX_G + g];
         }
     }
-    double Tn = 1.0, Tk = 1.0, cvol = 1.0;
+    double Tn = 1.0, Tk = 1.0, dtcv = 0.0;
     uint8_t pinned = 0;
     double nu_lo = 0.0, nu_top = 0.0;
     if (load) {
         Tn = D.T[cell];
         Tk = FIRST ? Tn : D.T_new[cell];
         pinned = D.pinned[cell];
-        cvol = D.cvol[cell];
+        dtcv = D.dtcv[cell];
         if (g <= G) nu_lo = D.nu[I.edge_off + g];
         if (g == G - 1 && G == Gp) nu_top = D.nu[I.edge_off + G];
     }
@@ -1150,7 +1150,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
             const double p = F.inside[q] ? pn[q] : (I.bc[q] == BC_REFLECT ? phi : pn[q]);
             lap += F.S[q] * Df[q] * (p - phi);
         }
-        const double b = Qj + (K.dt / I.V) * lap;
+        const double b = Qj + I.dt_V * lap;
         r = (b + lam * phi) / (1.0 + lam);
         const double em = (b - phi) / (1.0 + lam);
         contrib = sig * em;
@@ -1163,7 +1163,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     double Tnew = 1.0;
     bool bad = false;
     if (work) {
-        Tnew = pinned ? Tn : Tn + (K.dt / (K.eps * K.eps * cvol)) * contrib;
+        Tnew = pinned ? Tn : Tn + dtcv * contrib;
         if (!(Tnew > 0.0) || !isfinite(Tnew)) {
             bad = true;
             Tnew = 1.0;

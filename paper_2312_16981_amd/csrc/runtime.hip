@@ -55,7 +55,7 @@ struct ApiError {
 HeadSeries make_head_series()
 {
     HeadSeries hs;
-    hs.nterm = 24;
+    hs.nterm = HEAD_TERMS;
     const long double pi = 3.141592653589793238462643383279502884L;
     for (int j = 0; j < hs.nterm; ++j) {
         const int k = j + 1;
@@ -338,6 +338,7 @@ struct ugkwp_ctx {
             I.dx = (h.x1 - h.x0) / h.nx;
             I.dy = h.dim == 2 ? (h.y1 - h.y0) / h.ny : 1.0;
             I.V = I.dx * I.dy;
+            I.dt_V = P.dt / I.V;
             I.w_ref = h.w_ref;
             I.seed = h.seed;
             cells += I.ncell;
@@ -352,6 +353,7 @@ struct ugkwp_ctx {
         K.e2c = P.eps * P.eps / P.c;
         K.cv = P.c / P.eps;
         K.lam_scale = P.c * P.dt / (P.eps * P.eps);
+        K.cq = P.c / (4.0 * P.eps);
         K.nu_power = P.nu_power;
         K.si_tol = P.si_tol;
         K.n_cap = P.n_cap;
@@ -438,6 +440,7 @@ struct ugkwp_ctx {
         d.Dx = dalloc<double>(owned, (size_t)n_fx);
         d.Dy = dalloc<double>(owned, (size_t)std::max<int64_t>(n_fy, 1));
         d.cvol = dalloc<double>(owned, ncell);
+        d.dtcv = dalloc<double>(owned, ncell);
         d.T = dalloc<double>(owned, ncell);
         d.T_new = dalloc<double>(owned, ncell);
         d.pinned = dalloc<uint8_t>(owned, ncell);
@@ -556,7 +559,7 @@ struct ugkwp_ctx {
     void set_material(const std::vector<const double*>& cv, const std::vector<const double*>& T0,
                       const std::vector<const double*>& Tr0, const std::vector<const uint8_t*>& pinned)
     {
-        std::vector<double> hcv(ncell), hT(ncell), hTr(ncell);
+        std::vector<double> hcv(ncell), hT(ncell), hTr(ncell), hw(ncell);
         std::vector<uint8_t> hp(ncell, 0);
         for (int k = 0; k < n_inst; ++k) {
             const Inst& I = inst[k];
@@ -565,6 +568,7 @@ struct ugkwp_ctx {
                 if (!(a > 0) || !(b > 0) || !(r > 0) || !std::isfinite(a) || !std::isfinite(b) || !std::isfinite(r))
                     fail(UGKWP_EINVAL, "cv, T0 and Tr0 must be positive and finite");
                 hcv[I.cell_off + c] = a;
+                hw[I.cell_off + c] = P.dt / (P.eps * P.eps * a);
                 hT[I.cell_off + c] = b;
                 hTr[I.cell_off + c] = r;
                 hp[I.cell_off + c] = pinned[k] ? (pinned[k][c] ? 1 : 0) : 0;
@@ -573,6 +577,7 @@ struct ugkwp_ctx {
         double* d_tr = nullptr;
         HIPCHK(hipMalloc(&d_tr, sizeof(double) * ncell));
         HIPCHK(hipMemcpyAsync((void*)D.cvol, hcv.data(), sizeof(double) * ncell, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync((void*)D.dtcv, hw.data(), sizeof(double) * ncell, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(D.T, hT.data(), sizeof(double) * ncell, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync((void*)D.pinned, hp.data(), ncell, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(d_tr, hTr.data(), sizeof(double) * ncell, hipMemcpyHostToDevice, st));
