@@ -333,13 +333,13 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
         dm = fabs(mun - mui);
         mm = fabs(mun);
     }
-    dm = wave_nmax(dm);
-    mm = wave_nmax(mm);
-    __shared__ double wres[ADJ_THREADS / WAVE][2];
+    // both maxima are non-negative (or NaN): reduced as bit patterns
+    const unsigned long long bdm = wave_max_bits(dm), bmm = wave_max_bits(mm);
+    __shared__ unsigned long long wres[ADJ_THREADS / WAVE][2];
     __shared__ int winst[ADJ_THREADS / WAVE];
     __shared__ int wrun[ADJ_THREADS / WAVE];
     if (lane == 0) {
-        wres[wid][0] = dm; wres[wid][1] = mm;
+        wres[wid][0] = bdm; wres[wid][1] = bmm;
         winst[wid] = s.inst;
         wrun[wid] = run ? 1 : 0;
     }
@@ -349,20 +349,20 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
         int w0 = 0;
         while (w0 < nw) {
             int w1 = w0, any = 0;
-            double a0 = 0.0, a1 = 0.0;
+            unsigned long long a0 = 0, a1 = 0;
             while (w1 < nw && winst[w1] == winst[w0]) {
                 if (wrun[w1]) {
                     any = 1;
-                    a0 = nmax(a0, wres[w1][0]);
-                    a1 = nmax(a1, wres[w1][1]);
+                    a0 = max(a0, wres[w1][0]);
+                    a1 = max(a1, wres[w1][1]);
                 }
                 ++w1;
             }
             if (any) {
                 AdjResid* rr = A.res + ((int64_t)winst[w0] * RES_SLOTS + k % RES_SLOTS) * RES_SUB +
                                (blockIdx.x & (RES_SUB - 1));
-                atomicMax(&rr->dmu, dbits(a0));
-                atomicMax(&rr->mu, dbits(a1));
+                atomicMax(&rr->dmu, a0);
+                atomicMax(&rr->mu, a1);
             }
             w0 = w1;
         }

@@ -61,4 +61,30 @@ __device__ inline double wave_nmax(double v)
     return v;
 }
 
+// Largest value over the wavefront by DPP row steps: within quads, half rows,
+// rows, then across rows (row broadcasts 15 and 31); lane 63 ends with the
+// maximum, which is returned to every lane.
+__device__ inline uint32_t wave_max_u32(uint32_t v)
+{
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast15
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Largest of non-negative doubles (NaN allowed) over the wavefront, as IEEE bit
+// patterns: for these the unsigned order of the bits is the numeric order, and
+// every NaN lies above +inf, so a NaN anywhere wins.  The high words are
+// reduced first, then the low words of the lanes that hold the largest high word.
+__device__ inline unsigned long long wave_max_bits(double x)
+{
+    const unsigned long long b = dbits(x);
+    const uint32_t hi = wave_max_u32((uint32_t)(b >> 32));
+    const uint32_t lo = wave_max_u32((uint32_t)(b >> 32) == hi ? (uint32_t)b : 0u);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 }  // namespace ugk

@@ -1210,15 +1210,14 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         D.T_new[cell] = Tnew;
     }
     // residual maxima: wavefront, then runs of wavefronts of one instance in the block
-    dr = wave_nmax(dr);
-    mr = wave_nmax(mr);
-    dT = wave_nmax(dT);
-    mT = wave_nmax(mT);
-    __shared__ double wres[SI_THREADS / WAVE][4];
+    // the four maxima are non-negative (or NaN): reduced as bit patterns
+    const unsigned long long bdr = wave_max_bits(dr), bmr = wave_max_bits(mr);
+    const unsigned long long bdT = wave_max_bits(dT), bmT = wave_max_bits(mT);
+    __shared__ unsigned long long wres[SI_THREADS / WAVE][4];
     __shared__ int winst[SI_THREADS / WAVE];
     __shared__ int wrun[SI_THREADS / WAVE];
     if (lane == 0) {
-        wres[wid][0] = dr; wres[wid][1] = mr; wres[wid][2] = dT; wres[wid][3] = mT;
+        wres[wid][0] = bdr; wres[wid][1] = bmr; wres[wid][2] = bdT; wres[wid][3] = bmT;
         winst[wid] = s.inst;
         wrun[wid] = run ? 1 : 0;
     }
@@ -1228,21 +1227,21 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         const int nw = SI_THREADS / WAVE;
         while (w0 < nw) {
             int w1 = w0, any = 0;
-            double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            unsigned long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
             while (w1 < nw && winst[w1] == winst[w0]) {
                 if (wrun[w1]) {
                     any = 1;
-                    a0 = nmax(a0, wres[w1][0]); a1 = nmax(a1, wres[w1][1]);
-                    a2 = nmax(a2, wres[w1][2]); a3 = nmax(a3, wres[w1][3]);
+                    a0 = max(a0, wres[w1][0]); a1 = max(a1, wres[w1][1]);
+                    a2 = max(a2, wres[w1][2]); a3 = max(a3, wres[w1][3]);
                 }
                 ++w1;
             }
             if (any) {
                 Resid* r = res_slot(D, K, winst[w0], k) + (blockIdx.x & (RES_SUB - 1));
-                atomicMax(&r->drho, dbits(a0));
-                atomicMax(&r->rho, dbits(a1));
-                atomicMax(&r->dT, dbits(a2));
-                atomicMax(&r->T, dbits(a3));
+                atomicMax(&r->drho, a0);
+                atomicMax(&r->rho, a1);
+                atomicMax(&r->dT, a2);
+                atomicMax(&r->T, a3);
             }
             w0 = w1;
         }
