@@ -323,7 +323,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
         const double phibar = -fac * mui + lam / (1.0 + lam) * rb + I.dt_V * lt;
         contrib = dphi * phibar;
     }
-    for (int m = 1; m < Gp; m <<= 1) contrib += __shfl_xor(contrib, m, WAVE);
+    contrib = group_sum(contrib, Gp);
 
     double dm = 0.0, mm = 0.0;
     if (work && g == 0) {

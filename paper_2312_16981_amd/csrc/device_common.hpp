@@ -75,6 +75,56 @@ __device__ inline uint32_t wave_max_u32(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// A double moved across lanes by one DPP step; lanes of rows outside ROW_MASK,
+// and lanes whose source is outside the row, read 0.0.
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    int lo, hi;
+    if (ROW_MASK == 0xF) {
+        // every lane is written: no old value to set up
+        lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+        hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xF, false);
+        hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+    }
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over aligned groups of n lanes (n a power of two up to 64, the same in
+// every lane).  Each step adds two partial sums that every lane of a group
+// holds with the same bits, so all lanes of a group end with the same bits:
+// pairs and quads (quad permutes), 8 and 16 lanes (half-row and row mirrors),
+// then 32 and 64 lanes by shuffles.
+__device__ inline double group_sum(double v, int n)
+{
+    if (n > 1) v += dpp_f64<0xB1, 0xF>(v);     // quad_perm 1,0,3,2
+    if (n > 2) v += dpp_f64<0x4E, 0xF>(v);     // quad_perm 2,3,0,1
+    if (n > 4) v += dpp_f64<0x141, 0xF>(v);    // row_half_mirror
+    if (n > 8) v += dpp_f64<0x140, 0xF>(v);    // row_mirror
+    if (n > 16) v += __shfl_xor(v, 16, WAVE);
+    if (n > 32) v += __shfl_xor(v, 32, WAVE);
+    return v;
+}
+
+// Sum over the wavefront, returned to every lane: the group steps up to rows,
+// then the row broadcasts 15 and 31 gather the four row sums into lane 63.
+__device__ inline double wave_sum(double v)
+{
+    v += dpp_f64<0xB1, 0xF>(v);
+    v += dpp_f64<0x4E, 0xF>(v);
+    v += dpp_f64<0x141, 0xF>(v);
+    v += dpp_f64<0x140, 0xF>(v);
+    v += dpp_f64<0x142, 0xA>(v);               // row_bcast15 into rows 1, 3
+    v += dpp_f64<0x143, 0xC>(v);               // row_bcast31 into rows 2, 3
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Largest of non-negative doubles (NaN allowed) over the wavefront, as IEEE bit
 // patterns: for these the unsigned order of the bits is the numeric order, and
 // every NaN lies above +inf, so a NaN anywhere wins.  The high words are

@@ -1157,8 +1157,8 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         dr = fabs(r - rho_prev);
         mr = fabs(r);
     }
-    // group sum over the Gp lanes of the cell (butterfly: every lane gets the same bits)
-    for (int m = 1; m < Gp; m <<= 1) contrib += __shfl_xor(contrib, m, WAVE);
+    // group sum over the Gp lanes of the cell (every lane gets the same bits)
+    contrib = group_sum(contrib, Gp);
 
     double Tnew = 1.0;
     bool bad = false;
@@ -1397,8 +1397,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
         }
     }
 #pragma unroll
-    for (int q = 0; q < 5; ++q)
-        for (int m = 32; m >= 1; m >>= 1) v[q] += __shfl_xor(v[q], m, WAVE);
+    for (int q = 0; q < 5; ++q) v[q] = wave_sum(v[q]);
     __shared__ double wsum[DIAG_THREADS / WAVE][5];
     __shared__ int winst[DIAG_THREADS / WAVE];
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
