@@ -233,35 +233,43 @@ __device__ inline FaceRef face_ref(const Inst& I, int64_t j, int lcell, int g, i
 // Residual maxima go to 64 sub-slots of the instance; k_adj_decide reads them.
 // With decide_prev (single instance), every block first takes the decision of
 // sweep k-1 from those sub-slots itself; block 0 records it.
+template <bool SINGLE>
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj A, int k, const double* mu_in,
                                                            double* mu_out, int r, uint32_t gate, int decide_prev)
 {
-    if (!adj_gate(A, gate)) return;
     const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
-    const Slot s = decode_slot(D, K, j);
-    // the wavefront's instance record, copied before the kernel's first store
-    // (scalar loads, read once)
-    const Inst I = D.inst[s.inst];
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-
-    bool run = A.conv[s.inst] == 0 && j < K.n_cg;
+    // the gate (done count) and, for one instance, the state and residuals of
+    // the sweep before (the stopping test) are requested together; the slot's
+    // data once the block is known to run
+    const unsigned long long done = A.status[ADJ_DONE];
+    const int cs_prev = decide_prev ? A.conv[0] : 0;
+    AdjResid res_prev = {0ull, 0ull};
+    if (decide_prev && wid == 0) res_prev = A.res[((int64_t)0 * RES_SLOTS + (k - 1) % RES_SLOTS) * RES_SUB + lane];
+    if (!(gate == GATE_OFF || done == (unsigned long long)gate)) return;
+    Inst I;
+    const Slot s = decode_slot_rec<SINGLE>(D, K, j, I);
     if (decide_prev) {
         // the whole block stops when the iteration has converged (now or before)
         __shared__ int stop;
         if (wid == 0) {
-            const int cs = A.conv[0];
-            const bool conv = cs == 0 && adj_converged(A, 0, k - 1, lane);
+            bool conv = false;
+            if (cs_prev == 0) {
+                const double dm = bitsd(wave_max_bits(bitsd(res_prev.dmu)));
+                const double mm = bitsd(wave_max_bits(bitsd(res_prev.mu)));
+                conv = dm <= ((k - 1) >= 60 ? 1e-13 : 1e-15) * mm;
+            }
             if (lane == 0) {
-                stop = (conv || cs != 0) ? 1 : 0;
+                stop = (conv || cs_prev != 0) ? 1 : 0;
                 if (conv && blockIdx.x == 0) adj_mark_converged(D, A, 0, k, r);
             }
         }
         __syncthreads();
         if (stop) return;
     }
+    const int cs_inst = A.conv[s.inst];
 
     const int g = s.g, Gp = I.Gp;
-    const bool work = run && s.cell_ok;
     const int cell = I.cell_off + s.lcell;
     const int nf = 2 * I.dim;
     // every load of the sweep before the first wait
@@ -298,6 +306,9 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
         tbar = A.Tbar[cell];
         if (!act) mui = mu_in[cell];
     }
+
+    const bool run = cs_inst == 0 && j < K.n_cg;
+    const bool work = run && s.cell_ok;
 
     const int64_t rel = j - I.cg_off;
     if (run && rel >= 0 && rel < RES_SUB) {
@@ -506,7 +517,8 @@ void launch_adj_sweeps(const Dev& D, const Consts& K, const Adj& A, int k0, int 
     for (int k = k0; k < k1; ++k) {
         const double* in = (k & 1) ? A.mu1 : A.mu0;
         double* out = (k & 1) ? A.mu0 : A.mu1;
-        k_adj_sweep<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, k, in, out, r, gate, fold && k > k0 ? 1 : 0);
+        (fold ? k_adj_sweep<true> : k_adj_sweep<false>)<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, k, in, out, r,
+                                                                                    gate, fold && k > k0 ? 1 : 0);
         if (!fold) launch_adj_decide(D, K, A, k, r, gate, st);
     }
 }

@@ -54,6 +54,7 @@ struct Consts {
     int64_t n_cg;          // total (cell, group) slots incl. padding
     int64_t n_fx2;         // x-face tally entries (2 per x-face slot)
     int ncell;             // total cells
+    Inst inst0;            // instance 0's record (read from here when it is the only one)
 };
 
 constexpr uint32_t GATE_OFF = 0xFFFFFFFFu;

@@ -41,6 +41,30 @@ __device__ inline Slot decode_slot(const Dev& D, const Consts& K, int64_t j)
     return s;
 }
 
+// decode_slot, also handing out the slot's instance record: SINGLE (a context
+// of one instance) takes it from the kernel arguments, with no memory read on
+// the critical path; otherwise it comes from the instance table.
+template <bool SINGLE>
+__device__ inline Slot decode_slot_rec(const Dev& D, const Consts& K, int64_t j, Inst& I)
+{
+    Slot s;
+    const bool in = j < K.n_cg;
+    if (SINGLE) {
+        s.inst = 0;
+        I = K.inst0;
+    } else {
+        const int w = __builtin_amdgcn_readfirstlane((int)(j >> 6));
+        s.inst = ((int64_t)w << 6) < K.n_cg ? D.wave_inst[w] : K.n_inst - 1;
+        I = D.inst[s.inst];
+    }
+    const int64_t local = j - I.cg_off;
+    s.lcell = (int)(local >> I.lgGp);
+    s.g = (int)(local & (I.Gp - 1));
+    s.cell_ok = in && local >= 0 && s.lcell < I.ncell;
+    s.active = s.cell_ok && s.g < I.G;
+    return s;
+}
+
 __device__ inline unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 __device__ inline double bitsd(unsigned long long v) { return __longlong_as_double((long long)v); }
 

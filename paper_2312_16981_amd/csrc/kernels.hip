@@ -188,15 +188,17 @@ __global__ void k_init_rho(Dev D, Consts K, const double* Tr0)
 // given, writes the per-block sum of N for the scan that follows.
 constexpr int COUNT_THREADS = 256;
 
+template <bool SINGLE>
 __global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroList Z, int64_t* part)
 {
-    if (!gate_open(D, K, 0)) return;
     const int64_t j = (int64_t)blockIdx.x * COUNT_THREADS + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * COUNT_THREADS;
-    // the slot's loads (and its wavefront's instance record) before any store
+    // the step count (the gate), the slot's loads and its wavefront's instance
+    // record are requested together, before any store
+    const uint32_t now = *D.step;
     const bool in = j < K.n_cg;
-    const Slot s = decode_slot(D, K, j);
-    const Inst I = D.inst[s.inst];
+    Inst I;
+    const Slot s = decode_slot_rec<SINGLE>(D, K, j, I);
     double rho = 0.0, rhop = 0.0, es = 0.0, nl = 0.0, nh = 0.0, T = 0.0;
     if (in && s.active) {
         rho = D.rho[j];
@@ -206,6 +208,7 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroLi
         nh = D.nu[I.edge_off + s.g + 1];
         T = D.T[I.cell_off + s.lcell];
     }
+    if (!(K.gate == GATE_OFF || now == K.gate)) return;
     if (blockIdx.x == 0) {
         if (threadIdx.x < N_COUNTERS) {
             const int q = threadIdx.x;
@@ -1058,35 +1061,45 @@ __device__ inline bool si_converged(const Dev& D, const Consts& K, int inst, int
 
 // FIRST: sweep 0 (its own instantiation, so that the wave-flux code does not
 // weigh on the registers of the later sweeps).
-template <bool FIRST>
+template <bool FIRST, bool SINGLE>
 __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k, const double* phi_in,
                                                           double* phi_out, int decide_prev)
 {
-    if (!gate_open(D, K, 0)) return;
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-    // batches: a block whose four wavefronts all belong to converged instances
-    // returns after one load (the flags of its wavefronts, one byte each)
-    uint32_t flags = 0xFFFFFFFFu;
-    if (K.n_inst > 1 && !FIRST) {
-        flags = ((const uint32_t*)D.wave_run)[blockIdx.x];
-        if (flags == 0) return;
-    }
     const int64_t j = (int64_t)blockIdx.x * SI_THREADS + threadIdx.x;
-    const Slot s = decode_slot(D, K, j);
-    // the wavefront's instance record, copied before the kernel's first store:
-    // its loads can then go through the scalar cache, and nothing below has to
-    // read it again from memory
-    const Inst I = D.inst[s.inst];
-
+    // The gate (step count), for batches the flags of the block's wavefronts
+    // (a block whose four wavefronts all belong to converged instances returns
+    // after them) and for one instance the state and residuals of the sweep
+    // before (the stopping test) are requested together; the slot's data only
+    // once the block is known to run.
+    const uint32_t now = *D.step;
+    uint32_t flags = 0xFFFFFFFFu;
+    if (K.n_inst > 1 && !FIRST) flags = ((const uint32_t*)D.wave_run)[blockIdx.x];
+    int cs_prev = 0;
+    Resid res_prev = {0ull, 0ull, 0ull, 0ull};
     if (decide_prev) {
-        // the whole block stops when the iteration has converged (decided now or
-        // by an earlier sweep): a speculative sweep past convergence costs little
+        cs_prev = D.ist[0].conv_sweeps;
+        if (wid == 0) res_prev = res_slot(D, K, 0, k - 1)[lane];
+    }
+    if (!(K.gate == GATE_OFF || now == K.gate) || flags == 0) return;
+    Inst I;
+    const Slot s = decode_slot_rec<SINGLE>(D, K, j, I);
+    if (decide_prev) {
+        // the whole block stops when the iteration has converged (decided now
+        // or by an earlier sweep): a speculative sweep past convergence costs
+        // little
         __shared__ int stop;
         if (wid == 0) {
-            const int cs = D.ist[0].conv_sweeps;
-            const bool conv = cs == 0 && si_converged(D, K, 0, k - 1, lane);
+            bool conv = false;
+            if (cs_prev == 0) {
+                const double drho = bitsd(wave_max_bits(bitsd(res_prev.drho)));
+                const double mrho = bitsd(wave_max_bits(bitsd(res_prev.rho)));
+                const double dTm = bitsd(wave_max_bits(bitsd(res_prev.dT)));
+                const double mTm = bitsd(wave_max_bits(bitsd(res_prev.T)));
+                conv = drho <= K.si_tol * mrho && dTm <= K.si_tol * mTm;
+            }
             if (lane == 0) {
-                stop = (conv || cs != 0) ? 1 : 0;
+                stop = (conv || cs_prev != 0) ? 1 : 0;
                 if (conv && blockIdx.x == 0) {
                     D.ist[0].conv_sweeps = k;
                     atomicAdd((unsigned long long*)(D.counters + CNT_CONV), 1ull);
@@ -1096,6 +1109,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         __syncthreads();
         if (stop) return;
     }
+    const int cs_inst = D.ist[s.inst].conv_sweeps;
     const bool wave_on = ((flags >> (8 * wid)) & 0xFFu) != 0;
     const int g = s.g, Gp = I.Gp, G = I.G;
     const bool load = wave_on && s.cell_ok;       // the slot's cell is updated (every group lane)
@@ -1138,7 +1152,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     double inflow = 0.0;
     if (FIRST && act) Qj = wave_source(D, K, I, j, s, F, &inflow);
 
-    const bool run = wave_on && D.ist[s.inst].conv_sweeps == 0 && j < K.n_cg;
+    const bool run = wave_on && cs_inst == 0 && j < K.n_cg;
     double dr = 0.0, mr = 0.0, dT = 0.0, mT = 0.0;
     const bool work = run && s.cell_ok;
     double contrib = 0.0, r = 0.0;
@@ -1282,35 +1296,19 @@ constexpr int DIAG_THREADS = 256;
 // last_sweep >= 0 (single instance): the convergence decision of that sweep
 // is taken here rather than by a decide launch; wavefront 0 of every block
 // takes it from the same residual sub-slots, and block 0 records it.
+template <bool SINGLE>
 __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int last_sweep, int push_blocks)
 {
-    // the commit below advances *D.step while other blocks may still start:
-    // both the step's own value and the next one open this launch
-    if (!gate_open(D, K, 0) && !gate_open(D, K, 1)) return;
     const int64_t j = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x;
-    const Slot s = decode_slot(D, K, j);
-    // the wavefront's instance record, copied before the kernel's first store
-    const Inst I = D.inst[s.inst];
-    int ns_single = 0;
-    if (last_sweep >= 0) {
-        __shared__ int sh_ns;
-        if (threadIdx.x < WAVE) {
-            // a block starting after block 0's record reads that record: the same value
-            int ns = D.ist[0].conv_sweeps;
-            if (ns == 0 && si_converged(D, K, 0, last_sweep, threadIdx.x)) ns = last_sweep + 1;
-            if (threadIdx.x == 0) sh_ns = ns;
-        }
-        __syncthreads();
-        ns_single = sh_ns;
-        if (blockIdx.x == 0 && threadIdx.x == 0 && ns_single != 0 && D.ist[0].conv_sweeps == 0) {
-            D.ist[0].conv_sweeps = ns_single;
-            atomicAdd((unsigned long long*)(D.counters + CNT_CONV), 1ull);
-        }
-        if (D.counters[CNT_ERR] != 0 || ns_single == 0) return;
-    } else if (!step_committed(D, K)) {
-        return;
-    }
-    // the slot's loads, before the stores of the commit
+    // the loads come first (nothing is stored before the gate): step count,
+    // the stopping state of the last sweep (one instance), the slot's data
+    const uint32_t now = *D.step;
+    Inst I;
+    const Slot s = decode_slot_rec<SINGLE>(D, K, j, I);
+    const int cs0 = last_sweep >= 0 ? D.ist[0].conv_sweeps : 0;
+    Resid rl = {0ull, 0ull, 0ull, 0ull};
+    if (last_sweep >= 0 && threadIdx.x < WAVE) rl = res_slot(D, K, 0, last_sweep)[threadIdx.x];
+    const int cs_inst = D.ist[s.inst].conv_sweeps;
     const bool in = j < K.n_cg;
     const int g = s.g, nx = I.nx, ix = s.lcell % nx, iy = s.lcell / nx;
     const int cell = I.cell_off + s.lcell;
@@ -1320,13 +1318,10 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
     int64_t fs[4] = {0, 0, 0, 0};
     double Df[4] = {0.0, 0.0, 0.0, 0.0}, tal[4] = {0.0, 0.0, 0.0, 0.0}, pb[4] = {0.0, 0.0, 0.0, 0.0};
     if (in && s.active) {
-        const int ns = last_sweep >= 0 ? ns_single : D.ist[s.inst].conv_sweeps;
         surv = D.surv[j];
         rho = D.rho[j];
         rho_new = D.rho_new[j];
         pin = D.pinned[cell];
-        phi = sweep_in(D, ns - 1)[j];          // phi^k of the last sweep
-        phi_next = sweep_out(D, ns - 1)[j];    // phi(T^{n+1}): the next step's phi^0
         if (g == 0) {
             cv = D.cvol[cell];
             T0 = D.T[cell];
@@ -1346,6 +1341,40 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
             tal[q] = (axis == 0 ? D.ftx : D.fty)[fs[q] * 2 + (lo ? 1 : 0)];
             if (I.bc[q] == BC_PLANCK) pb[q] = phib[q * MAX_G + g];
         }
+    }
+    // the commit below advances *D.step while other blocks may still start:
+    // both the step's own value and the next one open this launch
+    if (!(K.gate == GATE_OFF || now == K.gate || now == K.gate + 1)) return;
+    // the sweeps the iteration took: a converged single instance has it in its
+    // state, or converged at the last sweep (decided below); batches have it
+    // per instance
+    const int ns_guess = last_sweep >= 0 ? (cs0 != 0 ? cs0 : last_sweep + 1) : cs_inst;
+    if (in && s.active && ns_guess >= 1) {
+        phi = sweep_in(D, ns_guess - 1)[j];          // phi^k of the last sweep
+        phi_next = sweep_out(D, ns_guess - 1)[j];    // phi(T^{n+1}): the next step's phi^0
+    }
+    int ns_single = 0;
+    if (last_sweep >= 0) {
+        __shared__ int sh_ns;
+        if (threadIdx.x < WAVE) {
+            // a block starting after block 0's record reads that record: the same value
+            int ns = cs0;
+            if (ns == 0) {
+                const double drho = bitsd(wave_max_bits(bitsd(rl.drho))), mrho = bitsd(wave_max_bits(bitsd(rl.rho)));
+                const double dTm = bitsd(wave_max_bits(bitsd(rl.dT))), mTm = bitsd(wave_max_bits(bitsd(rl.T)));
+                if (drho <= K.si_tol * mrho && dTm <= K.si_tol * mTm) ns = last_sweep + 1;
+            }
+            if (threadIdx.x == 0) sh_ns = ns;
+        }
+        __syncthreads();
+        ns_single = sh_ns;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && ns_single != 0 && cs0 == 0) {
+            D.ist[0].conv_sweeps = ns_single;
+            atomicAdd((unsigned long long*)(D.counters + CNT_CONV), 1ull);
+        }
+        if (D.counters[CNT_ERR] != 0 || ns_single == 0) return;
+    } else if (!step_committed(D, K)) {
+        return;
     }
     if (blockIdx.x == 0) {
         // survivors of the push: sum of its per-block counts
@@ -1523,10 +1552,12 @@ void launch_count_scan(const Dev& D, const Consts& K, const ZeroList& Z, int64_t
     const unsigned nb = blocks(K.n_cg, COUNT_THREADS);
     const ScanGate q = scan_gate(D, K, 0);
     if (nb <= SMALL_SCAN_BLOCKS) {
-        k_count<<<nb, COUNT_THREADS, 0, st>>>(D, K, Z, part);
+        if (K.n_inst == 1) k_count<true><<<nb, COUNT_THREADS, 0, st>>>(D, K, Z, part);
+        else k_count<false><<<nb, COUNT_THREADS, 0, st>>>(D, K, Z, part);
         k_scan_small<<<nb, COUNT_THREADS, 0, st>>>(q, D.nb, K.n_cg, part, (int)nb, D.boff, D.n_births_total);
     } else {
-        k_count<<<nb, COUNT_THREADS, 0, st>>>(D, K, Z, nullptr);
+        if (K.n_inst == 1) k_count<true><<<nb, COUNT_THREADS, 0, st>>>(D, K, Z, nullptr);
+        else k_count<false><<<nb, COUNT_THREADS, 0, st>>>(D, K, Z, nullptr);
         launch_scan(q, D.nb, K.n_cg, part, D.boff, D.n_births_total, st);
     }
 }
@@ -1647,7 +1678,8 @@ void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t
 {
     const bool fold = K.n_inst == 1;
     for (int k = k0; k < k1; ++k) {
-        auto kern = k == 0 ? k_si_sweep<true> : k_si_sweep<false>;
+        auto kern = fold ? (k == 0 ? k_si_sweep<true, true> : k_si_sweep<false, true>)
+                         : (k == 0 ? k_si_sweep<true, false> : k_si_sweep<false, false>);
         kern<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, sweep_in(D, k), sweep_out(D, k),
                                                                     fold && k > k0 ? 1 : 0);
         if (!fold) k_si_decide<<<blocks((int64_t)K.n_inst * WAVE, 256), 256, 0, st>>>(D, K, k);
@@ -1656,7 +1688,7 @@ void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t
 
 void launch_finish(const Dev& D, const Consts& K, bool reduce_diag, int last_sweep, int push_blocks, hipStream_t st)
 {
-    k_finish<<<blocks(K.n_cg, DIAG_THREADS), DIAG_THREADS, 0, st>>>(D, K, K.n_inst == 1 ? last_sweep : -1,
+    (K.n_inst == 1 ? k_finish<true> : k_finish<false>)<<<blocks(K.n_cg, DIAG_THREADS), DIAG_THREADS, 0, st>>>(D, K, K.n_inst == 1 ? last_sweep : -1,
                                                                    push_blocks);
     if (reduce_diag) k_diag_reduce<<<blocks(K.n_inst, 64), 64, 0, st>>>(D, K);
 }

@@ -364,6 +364,7 @@ struct ugkwp_ctx {
         K.n_cg = n_cg;
         K.n_fx2 = 2 * fx;
         K.ncell = ncell;
+        K.inst0 = inst[0];
 
         // device memory
         std::vector<double> edges, simpson;
