@@ -438,9 +438,29 @@ __global__ void k_sample(Dev D, Consts K, Pool P)
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) D.counters[CNT_PUSHED] = (unsigned long long)(n_slots + total);
     const int64_t base = n_slots;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total;
-         j += (int64_t)gridDim.x * blockDim.x) {
-    int64_t lo = 0, hi = K.n_cg;           // boff[lo] <= j < boff[hi]
+    // A wavefront takes 64 consecutive births.  Their slots lie between the
+    // slot of its first birth and that of its last, both found by a search in
+    // which every lane probes one of 64 pivots per round (a few rounds instead
+    // of a dependent load per halving); each lane then bisects that range.
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / WAVE;
+    for (int64_t j0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE * WAVE; j0 < total; j0 += nw * WAVE) {
+    const int64_t j = j0 + lane;
+    const int64_t jl = min(j0 + WAVE - 1, total - 1);
+    int64_t lo0 = 0, hi0 = K.n_cg, lo1 = 0, hi1 = K.n_cg;   // boff[lo] <= target, answer < hi
+    while (hi0 - lo0 > 1 || hi1 - lo1 > 1) {
+        const int64_t st0 = (hi0 - lo0 + WAVE - 1) / WAVE, st1 = (hi1 - lo1 + WAVE - 1) / WAVE;
+        const int64_t p0 = lo0 + lane * st0, p1 = lo1 + lane * st1;
+        const bool ok0 = p0 < hi0 && D.boff[p0] <= j0;
+        const bool ok1 = p1 < hi1 && D.boff[p1] <= jl;
+        const int n0 = __popcll(__ballot(ok0)) - 1, n1 = __popcll(__ballot(ok1)) - 1;
+        lo0 += n0 * st0;
+        hi0 = min(hi0, lo0 + st0);
+        lo1 += n1 * st1;
+        hi1 = min(hi1, lo1 + st1);
+    }
+    if (j >= total) continue;
+    int64_t lo = lo0, hi = lo1 + 1;        // boff[lo] <= j, slot(j) < hi
     while (hi - lo > 1) {
         const int64_t mid = (lo + hi) >> 1;
         if (D.boff[mid] <= j) lo = mid; else hi = mid;
