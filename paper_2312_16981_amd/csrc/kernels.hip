@@ -943,12 +943,13 @@ struct CellFaces {
     double S[4];
 };
 
+template <int DIM>
 __device__ inline CellFaces cell_faces(const Inst& I, int64_t j, int ix, int iy, int g)
 {
     CellFaces F;
     const int Gp = I.Gp, nx = I.nx;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 2 * DIM; ++q) {
         const bool lo = (q & 1) == 0;
         if (q < 2) {
             F.inside[q] = lo ? ix > 0 : ix < nx - 1;
@@ -969,14 +970,15 @@ __device__ inline CellFaces cell_faces(const Inst& I, int64_t j, int ix, int iy,
 // coefficient C4 - e^{-s} where the cell sampled particles, C4 where it did
 // not).  *inflow gets the energy the wave flux brings in through the domain
 // boundary.
+template <int DIM>
 __device__ inline double wave_source(const Dev& D, const Consts& K, const Inst& I, int64_t j, const Slot& s,
                                      const CellFaces& F, double* inflow_out)
 {
     const int g = s.g, nx = I.nx;
-    const int ix = s.lcell % nx, iy = s.lcell / nx;
+    const int ix = DIM == 1 ? s.lcell : s.lcell % nx, iy = DIM == 1 ? 0 : s.lcell / nx;
     const double cq = K.cq;
     const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
-    const int nf = 2 * I.dim;
+    constexpr int nf = 2 * DIM;
     // every load first
     const int nb_here = D.nb[j];
     const double wc_here = D.wc[j], c4_here = D.c4[j], rhoh_here = D.rhoh[j], rho_here = D.rho[j];
@@ -1001,7 +1003,7 @@ __device__ inline double wave_source(const Dev& D, const Consts& K, const Inst& 
     const int64_t fr = fl + I.Gp;
     const double tx0 = D.ftx[fl * 2 + 0], tx1 = D.ftx[fr * 2 + 1], tx2 = D.ftx[fl * 2 + 1], tx3 = D.ftx[fr * 2 + 0];
     double ty0 = 0.0, ty1 = 0.0, ty2 = 0.0, ty3 = 0.0;
-    if (I.dim == 2) {
+    if (DIM == 2) {
         const int64_t fb = I.fy_off + (((int64_t)iy * nx + ix) << I.lgGp) + g;
         const int64_t ft = fb + ((int64_t)nx << I.lgGp);
         ty0 = D.fty[fb * 2 + 0]; ty1 = D.fty[ft * 2 + 1];
@@ -1031,7 +1033,7 @@ __device__ inline double wave_source(const Dev& D, const Consts& K, const Inst& 
     }
     double a_in = tx0 + tx1;
     double a_out = tx2 + tx3;
-    if (I.dim == 2) {
+    if (DIM == 2) {
         a_in += ty0 + ty1;
         a_out += ty2 + ty3;
     }
@@ -1081,7 +1083,7 @@ __device__ inline bool si_converged(const Dev& D, const Consts& K, int inst, int
 
 // FIRST: sweep 0 (its own instantiation, so that the wave-flux code does not
 // weigh on the registers of the later sweeps).
-template <bool FIRST, bool SINGLE>
+template <bool FIRST, bool SINGLE, int DIM>
 __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k, const double* phi_in,
                                                           double* phi_out, int decide_prev)
 {
@@ -1137,10 +1139,10 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
 
     // every load of the sweep is issued here, before the first wait
     const int nx = I.nx;
-    const int ix = s.lcell % nx, iy = s.lcell / nx;
+    const int ix = DIM == 1 ? s.lcell : s.lcell % nx, iy = DIM == 1 ? 0 : s.lcell / nx;
     const int cell = I.cell_off + s.lcell;
-    const CellFaces F = cell_faces(I, j, ix, iy, g);
-    const int nf = 2 * I.dim;
+    const CellFaces F = cell_faces<DIM>(I, j, ix, iy, g);
+    constexpr int nf = 2 * DIM;
     const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
     double phi = 0.0, Qj = 0.0, lam = 0.0, sig = 0.0, rho_prev = 0.0;
     double Df[4] = {0.0, 0.0, 0.0, 0.0}, pn[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1170,7 +1172,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         if (g == G - 1 && G == Gp) nu_top = D.nu[I.edge_off + G];
     }
     double inflow = 0.0;
-    if (FIRST && act) Qj = wave_source(D, K, I, j, s, F, &inflow);
+    if (FIRST && act) Qj = wave_source<DIM>(D, K, I, j, s, F, &inflow);
 
     const bool run = wave_on && cs_inst == 0 && j < K.n_cg;
     double dr = 0.0, mr = 0.0, dT = 0.0, mT = 0.0;
@@ -1698,8 +1700,12 @@ void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t
 {
     const bool fold = K.n_inst == 1;
     for (int k = k0; k < k1; ++k) {
-        auto kern = fold ? (k == 0 ? k_si_sweep<true, true> : k_si_sweep<false, true>)
-                         : (k == 0 ? k_si_sweep<true, false> : k_si_sweep<false, false>);
+        // every instance of a context has the same dimension
+        auto kern = K.inst0.dim == 1
+                        ? (fold ? (k == 0 ? k_si_sweep<true, true, 1> : k_si_sweep<false, true, 1>)
+                                : (k == 0 ? k_si_sweep<true, false, 1> : k_si_sweep<false, false, 1>))
+                        : (fold ? (k == 0 ? k_si_sweep<true, true, 2> : k_si_sweep<false, true, 2>)
+                                : (k == 0 ? k_si_sweep<true, false, 2> : k_si_sweep<false, false, 2>));
         kern<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, sweep_in(D, k), sweep_out(D, k),
                                                                     fold && k > k0 ? 1 : 0);
         if (!fold) k_si_decide<<<blocks((int64_t)K.n_inst * WAVE, 256), 256, 0, st>>>(D, K, k);
