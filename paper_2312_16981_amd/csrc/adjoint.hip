@@ -206,10 +206,11 @@ struct FaceRef {
     double S;
 };
 
+template <int DIM>
 __device__ inline FaceRef face_ref(const Inst& I, int64_t j, int lcell, int g, int q)
 {
     FaceRef f;
-    const int nx = I.nx, ix = lcell % nx, iy = lcell / nx, Gp = I.Gp;
+    const int nx = I.nx, ix = DIM == 1 ? lcell : lcell % nx, iy = DIM == 1 ? 0 : lcell / nx, Gp = I.Gp;
     const bool lo = (q & 1) == 0;
     if ((q >> 1) == 0) {
         f.inside = lo ? ix > 0 : ix < nx - 1;
@@ -233,7 +234,7 @@ __device__ inline FaceRef face_ref(const Inst& I, int64_t j, int lcell, int g, i
 // Residual maxima go to 64 sub-slots of the instance; k_adj_decide reads them.
 // With decide_prev (single instance), every block first takes the decision of
 // sweep k-1 from those sub-slots itself; block 0 records it.
-template <bool SINGLE>
+template <bool SINGLE, int DIM>
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj A, int k, const double* mu_in,
                                                            double* mu_out, int r, uint32_t gate, int decide_prev)
 {
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
 
     const int g = s.g, Gp = I.Gp;
     const int cell = I.cell_off + s.lcell;
-    const int nf = 2 * I.dim;
+    constexpr int nf = 2 * DIM;
     // every load of the sweep before the first wait
     const bool act = s.cell_ok && s.active;
     double lam = 0.0, mui = 0.0, tw = 0.0, sg = 0.0, rb = 0.0, dphi = 0.0, tbar = 0.0;
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
     double Df[4], nlam[4], ntw[4], nsig[4], nmu[4], nrb[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        fr[q] = face_ref(I, j, s.lcell, g, q);
+        if (q < nf) fr[q] = face_ref<DIM>(I, j, s.lcell, g, q);
         Df[q] = nlam[q] = ntw[q] = nsig[q] = nmu[q] = nrb[q] = 0.0;
     }
     if (act) {
@@ -440,7 +441,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_grad(Dev D, Consts K, Adj A
     const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
     double lap = 0.0, accu = 0.0, sig_face = 0.0, s_planck = 0.0;
     for (int q = 0; q < 2 * I.dim; ++q) {
-        const FaceRef f = face_ref(I, j, s.lcell, g, q);
+        const FaceRef f = face_ref<2>(I, j, s.lcell, g, q);   // the general form: lcell split by nx
         const bool xax = (q >> 1) == 0, lo = (q & 1) == 0;
         const double Df = xax ? D.Dx[f.fslot] : D.Dy[f.fslot];
         // this cell is the high side of its low face and the low side of its high face
@@ -517,7 +518,9 @@ void launch_adj_sweeps(const Dev& D, const Consts& K, const Adj& A, int k0, int 
     for (int k = k0; k < k1; ++k) {
         const double* in = (k & 1) ? A.mu1 : A.mu0;
         double* out = (k & 1) ? A.mu0 : A.mu1;
-        (fold ? k_adj_sweep<true> : k_adj_sweep<false>)<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, k, in, out, r,
+        auto sw = K.inst0.dim == 1 ? (fold ? k_adj_sweep<true, 1> : k_adj_sweep<false, 1>)
+                                   : (fold ? k_adj_sweep<true, 2> : k_adj_sweep<false, 2>);
+        sw<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, k, in, out, r,
                                                                                     gate, fold && k > k0 ? 1 : 0);
         if (!fold) launch_adj_decide(D, K, A, k, r, gate, st);
     }

@@ -1318,7 +1318,7 @@ constexpr int DIAG_THREADS = 256;
 // last_sweep >= 0 (single instance): the convergence decision of that sweep
 // is taken here rather than by a decide launch; wavefront 0 of every block
 // takes it from the same residual sub-slots, and block 0 records it.
-template <bool SINGLE>
+template <bool SINGLE, int DIM>
 __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int last_sweep, int push_blocks)
 {
     const int64_t j = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x;
@@ -1332,7 +1332,8 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
     if (last_sweep >= 0 && threadIdx.x < WAVE) rl = res_slot(D, K, 0, last_sweep)[threadIdx.x];
     const int cs_inst = D.ist[s.inst].conv_sweeps;
     const bool in = j < K.n_cg;
-    const int g = s.g, nx = I.nx, ix = s.lcell % nx, iy = s.lcell / nx;
+    const int g = s.g, nx = I.nx;
+    const int ix = DIM == 1 ? s.lcell : s.lcell % nx, iy = DIM == 1 ? 0 : s.lcell / nx;
     const int cell = I.cell_off + s.lcell;
     double surv = 0.0, rho = 0.0, rho_new = 0.0, phi = 0.0, phi_next = 0.0, cv = 0.0, T0 = 0.0, T1 = 0.0;
     uint8_t pin = 0;
@@ -1351,8 +1352,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
         }
         const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (q >= 2 * I.dim) continue;
+        for (int q = 0; q < 2 * DIM; ++q) {
             const int axis = q >> 1;
             const bool lo = (q & 1) == 0;
             bnd[q] = axis == 0 ? (lo ? ix == 0 : ix == nx - 1) : (lo ? iy == 0 : iy == I.ny - 1);
@@ -1431,8 +1431,8 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
     if (in && s.active) {
         D.phi0[j] = phi_next;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (q >= 2 * I.dim || !bnd[q]) continue;
+        for (int q = 0; q < 2 * DIM; ++q) {
+            if (!bnd[q]) continue;
             const double S = (q >> 1) == 0 ? I.dy : I.dx;
             const int bc = I.bc[q];
             const double pn = bc == BC_PLANCK ? pb[q] : (bc == BC_REFLECT ? phi : 0.0);
@@ -1714,7 +1714,9 @@ void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t
 
 void launch_finish(const Dev& D, const Consts& K, bool reduce_diag, int last_sweep, int push_blocks, hipStream_t st)
 {
-    (K.n_inst == 1 ? k_finish<true> : k_finish<false>)<<<blocks(K.n_cg, DIAG_THREADS), DIAG_THREADS, 0, st>>>(D, K, K.n_inst == 1 ? last_sweep : -1,
+    auto fin = K.inst0.dim == 1 ? (K.n_inst == 1 ? k_finish<true, 1> : k_finish<false, 1>)
+                                    : (K.n_inst == 1 ? k_finish<true, 2> : k_finish<false, 2>);
+    fin<<<blocks(K.n_cg, DIAG_THREADS), DIAG_THREADS, 0, st>>>(D, K, K.n_inst == 1 ? last_sweep : -1,
                                                                    push_blocks);
     if (reduce_diag) k_diag_reduce<<<blocks(K.n_inst, 64), 64, 0, st>>>(D, K);
 }
