@@ -43,7 +43,7 @@ __device__ inline bool adj_gate(const Adj& A, uint32_t gate)
 __device__ inline bool adj_converged(const Adj& A, int inst, int k, int lane)
 {
     const AdjResid r = A.res[((int64_t)inst * RES_SLOTS + k % RES_SLOTS) * RES_SUB + lane];
-    const double dm = wave_nmax(bitsd(r.dmu)), mm = wave_nmax(bitsd(r.mu));
+    const double dm = bitsd(wave_max_bits(bitsd(r.dmu))), mm = bitsd(wave_max_bits(bitsd(r.mu)));
     const double tol = k >= 60 ? 1e-13 : 1e-15;
     return dm <= tol * mm;
 }

@@ -68,22 +68,6 @@ __device__ inline Slot decode_slot_rec(const Dev& D, const Consts& K, int64_t j,
 __device__ inline unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 __device__ inline double bitsd(unsigned long long v) { return __longlong_as_double((long long)v); }
 
-__device__ inline double wave_max(double v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, WAVE));
-    return v;
-}
-
-// NaN-propagating max (fmax drops NaN)
-__device__ inline double nmax(double a, double b) { return (a != a || a > b) ? a : b; }
-
-__device__ inline double wave_nmax(double v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = nmax(v, __shfl_xor(v, m, WAVE));
-    return v;
-}
 
 // Largest value over the wavefront by DPP row steps: within quads, half rows,
 // rows, then across rows (row broadcasts 15 and 31); lane 63 ends with the

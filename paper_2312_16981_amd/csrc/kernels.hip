@@ -1067,22 +1067,25 @@ __device__ inline Resid* res_slot(const Dev& D, const Consts& K, int inst, int k
     return D.res + ((int64_t)(k % RES_SLOTS) * K.n_inst + inst) * RES_SUB;
 }
 
+// The stopping test after sweep k for instance inst, taken by one wavefront
+// from the instance's 64 residual sub-slots (lane l reads sub-slot l).
+__device__ inline bool si_converged(const Dev& D, const Consts& K, int inst, int k, int lane)
+{
+    const Resid r = res_slot(D, K, inst, k)[lane];
+    const double drho = bitsd(wave_max_bits(bitsd(r.drho))), mrho = bitsd(wave_max_bits(bitsd(r.rho)));
+    const double dT = bitsd(wave_max_bits(bitsd(r.dT))), mT = bitsd(wave_max_bits(bitsd(r.T)));
+    return drho <= K.si_tol * mrho && dT <= K.si_tol * mT;
+}
+
 // Sweep k: rho^{k+1}, T^{k+1} and phi^{k+1} from phi^k for every instance whose
 // iteration is still running.  The residual maxima of the sweep go to sub-slots
 // of the instance (spread over 64 addresses by block); k_si_decide reads them.
 // With decide_prev (single-instance contexts), every block first takes the
 // convergence decision of sweep k-1 itself, from the same sub-slots, so no
 // decide launch sits between sweeps; block 0 records it.
-__device__ inline bool si_converged(const Dev& D, const Consts& K, int inst, int k, int lane)
-{
-    const Resid r = res_slot(D, K, inst, k)[lane];
-    const double drho = wave_nmax(bitsd(r.drho)), mrho = wave_nmax(bitsd(r.rho));
-    const double dT = wave_nmax(bitsd(r.dT)), mT = wave_nmax(bitsd(r.T));
-    return drho <= K.si_tol * mrho && dT <= K.si_tol * mT;
-}
-
 // FIRST: sweep 0 (its own instantiation, so that the wave-flux code does not
-// weigh on the registers of the later sweeps).
+// weigh on the registers of the later sweeps); SINGLE: a context of one
+// instance; DIM: the dimension of every instance of the context.
 template <bool FIRST, bool SINGLE, int DIM>
 __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k, const double* phi_in,
                                                           double* phi_out, int decide_prev)
