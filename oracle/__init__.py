@@ -33,7 +33,8 @@ class Params(C.Structure):
                 ("G", C.c_int), ("nu", _pd), ("nu_power", _d),
                 ("c", _d), ("a", _d), ("eps", _d), ("dt", _d), ("w_ref", _d),
                 ("n_cap", C.c_int64), ("seed", C.c_uint64), ("pool_cap", C.c_int64),
-                ("si_max_iters", C.c_int), ("si_tol", _d), ("flags", C.c_int)]
+                ("si_max_iters", C.c_int), ("si_tol", _d), ("flags", C.c_int),
+                ("tau_num_C", _d), ("tau_num_jump", _d)]
 
 
 class Diag(C.Structure):
@@ -188,6 +189,7 @@ class Sim:
         P.c, P.a, P.eps, P.dt, P.w_ref = prob.c, prob.a, prob.eps, prob.dt, prob.w_ref
         P.n_cap, P.seed, P.pool_cap = prob.n_cap, prob.seed, prob.pool_cap
         P.si_max_iters, P.si_tol, P.flags = prob.si_max_iters, prob.si_tol, prob.flags
+        P.tau_num_C, P.tau_num_jump = prob.tau_num_C, prob.tau_num_jump
         self._P = P
         h = L.ora_create(C.byref(P))
         if not h:
@@ -302,7 +304,9 @@ class Sim:
         return int(b.value), int(s.value)
 
     def record(self, on=True):
-        lib().ora_record(self.h, 1 if on else 0)
+        st = lib().ora_record(self.h, 1 if on else 0)
+        if st:
+            raise OracleError(st, "record")
 
     def adjoint(self, dJdT):
         p = self.prob

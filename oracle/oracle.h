@@ -89,6 +89,12 @@ typedef struct {
     int si_max_iters;
     double si_tol;
     int flags;
+    /* numerical collision time of thin-thick-joint cells (Sec. 3.2, second
+     * case): tau_num = eps^2/(c sigma) + C |T^l - T^r|/(T^l + T^r) dt replaces
+     * tau in the sampling fraction e^{-dt/tau} when C > 0, in the cells that
+     * share a face across which sigma changes by a factor >= jump. */
+    double tau_num_C;
+    double tau_num_jump;
 } ora_params;
 
 typedef struct ora_sim ora_sim;

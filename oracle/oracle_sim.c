@@ -460,13 +460,49 @@ static int step_once(ora_sim* s)
     double* A = (double*)malloc(sizeof(double) * ncg);
     double* wnet = (double*)malloc(sizeof(double) * ncg);
     unsigned char* sampled = (unsigned char*)malloc(ncg);
+    double* wsamp = (double*)malloc(sizeof(double) * ncg);
     for (int i = 0; i < nc; ++i)
         for (int g = 0; g < G; ++g) {
             size_t k = (size_t)i * G + g;
             sig[k] = s->kappa[k] * s->simpson[g];
             sv[k] = c * sig[k] * dt / (eps * eps);
             es[k] = exp(-sv[k]);
+            wsamp[k] = ora_coef_w(sv[k]);
         }
+    /* Thin-thick-joint cells (Sec. 3.2, second case): the sampling fraction
+     * e^{-dt/tau_num} with tau_num = tau + C * delta * dt, delta the largest
+     * |T^l - T^r| / (T^l + T^r) over the cell's faces across which sigma_g
+     * jumps by a factor >= jump (T^n, the temperatures the step starts from).
+     * dt/tau_num = s / (1 + s C delta); the wave part of a sampled cell keeps
+     * C4(s) - e^{-dt/tau_num} = W(s) - (e^{-dt/tau_num} - e^{-s}) (Remark 3
+     * with the larger sampled share). */
+    if (P->tau_num_C > 0.0) {
+        for (int i = 0; i < nc; ++i) {
+            nbface f[4];
+            int nf = cell_faces(s, i, f);
+            for (int g = 0; g < G; ++g) {
+                size_t k = (size_t)i * G + g;
+                double delta = -1.0;
+                for (int q = 0; q < nf; ++q) {
+                    if (f[q].nb < 0) continue;
+                    size_t kn = (size_t)f[q].nb * G + g;
+                    double hi = sig[k] > sig[kn] ? sig[k] : sig[kn];
+                    double lo = sig[k] > sig[kn] ? sig[kn] : sig[k];
+                    if (!(hi > 0.0) || hi < P->tau_num_jump * lo) continue;
+                    double Tl = s->T[i], Tr = s->T[f[q].nb];
+                    double d = fabs(Tl - Tr) / (Tl + Tr);
+                    if (d > delta) delta = d;
+                }
+                if (delta < 0.0) continue;
+                double snum = sv[k] / (1.0 + sv[k] * P->tau_num_C * delta);
+                es[k] = exp(-snum);
+                /* e^{-snum} - e^{-s}: by expm1 where the two are close */
+                double d = sv[k] - snum;
+                double diff = d < 0.5 ? exp(-sv[k]) * expm1(d) : exp(-snum) - exp(-sv[k]);
+                wsamp[k] = ora_coef_w(sv[k]) - diff;
+            }
+        }
+    }
 
     /* ---- wave split and sample counts (A1) ---- */
     int64_t total = 0;
@@ -487,7 +523,7 @@ static int step_once(ora_sim* s)
     }
     int64_t n_old = s->np;
     if (n_old + total > P->pool_cap) {
-        free(sig); free(sv); free(es); free(rhoh); free(A); free(wnet); free(sampled);
+        free(sig); free(sv); free(es); free(wsamp); free(rhoh); free(A); free(wnet); free(sampled);
         return ORA_EPOOL;
     }
     dg.n_alive_in = n_old;
@@ -563,7 +599,7 @@ static int step_once(ora_sim* s)
 
     /* ---- wave free-transport flux and the static source Q (A4) ---- */
     const double cq = c / (4.0 * eps);
-    for (size_t k = 0; k < ncg; ++k) A[k] = sampled[k] ? ora_coef_w(sv[k]) : ora_coef_c4(sv[k]);
+    for (size_t k = 0; k < ncg; ++k) A[k] = sampled[k] ? wsamp[k] : ora_coef_c4(sv[k]);
     double inflow_wave = 0.0;
     for (int i = 0; i < nc; ++i) {
         nbface f[4];
@@ -724,7 +760,7 @@ static int step_once(ora_sim* s)
         s->step++;
         s->diag = dg;
     }
-    free(sig); free(sv); free(es); free(rhoh); free(A); free(wnet); free(sampled);
+    free(sig); free(sv); free(es); free(wsamp); free(rhoh); free(A); free(wnet); free(sampled);
     free(phi); free(phin); free(rk); free(Tk); free(Tn1); free(rn1); free(em); free(Df);
     return status;
 }
@@ -833,6 +869,9 @@ int ora_get_counters(const ora_sim* s, uint64_t* birth_counter, int* step)
 /* Recording hooks used by the adjoint (oracle_adjoint.c). */
 int ora_record(ora_sim* s, int on)
 {
+    /* the frozen-tally map has no derivative through the joint cells' tau_num
+     * (it depends on T^n through a maximum): not recorded */
+    if (on && s->p.tau_num_C > 0.0) return ORA_EINVAL;
     free_rec(s);
     s->recording = on ? 1 : 0;
     if (on) {

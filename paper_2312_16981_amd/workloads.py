@@ -51,6 +51,8 @@ class Problem:
     si_max_iters: int = 200
     si_tol: float = 1e-13
     flags: int = 0
+    tau_num_C: float = 0.0       # > 0: numerical collision time in thin-thick-joint cells
+    tau_num_jump: float = 10.0   # opacity ratio across a face that makes its cells joint
 
     @property
     def G(self) -> int:
