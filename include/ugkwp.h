@@ -85,6 +85,16 @@ typedef struct {
                             (cell, group); 0 = library default (32 steps in 1-D,
                             16 in 2-D, where locality decays faster).  Affects
                             only speed and the order of the pool, not the results. */
+    double tau_num_C;    /* numerical collision time of thin-thick-joint cells (Sec. 3.2,
+                            second case): when > 0, a cell that shares a face across
+                            which its group opacity changes by a factor of at least
+                            tau_num_jump samples the fraction e^{-dt/tau_num} of its
+                            wave part, tau_num = eps^2/(c sigma) + tau_num_C
+                            |T^l - T^r|/(T^l + T^r) dt (largest over those faces,
+                            temperatures at the start of the step), and its wave
+                            flux keeps C4(s) - e^{-dt/tau_num} (Remark 3).  0 = off.
+                            Not recordable for ugkwp_adjoint.                        */
+    double tau_num_jump; /* opacity ratio that makes a face joint (<= 1: every face)   */
 } ugkwp_params;
 
 /* One problem instance (a slab in 1-D, a rectangle in 2-D). */

@@ -44,6 +44,8 @@ struct Consts {
     double cv;             // c / eps     (particle speed)
     double lam_scale;      // c dt / eps^2
     double cq;             // c / (4 eps)   (wave flux factor)
+    double tau_C;          // numerical collision time of joint cells: C (0 = off)
+    double tau_jump;       // opacity ratio across a face that makes its cells joint
     double nu_power;
     double si_tol;
     int64_t n_cap;
@@ -146,6 +148,7 @@ struct Dev {
     int32_t* nb;                // births per slot
     int64_t* boff;              // exclusive scan of nb
     double* wnew;
+    double* wsn;                // wave coefficient of a sampled slot this step (joint cells' tau_num)
     double* beta;
     double* dep;
     double* surv;

@@ -182,6 +182,43 @@ __global__ void k_init_rho(Dev D, Consts K, const double* Tr0)
 // ---------------------------------------------------------------------------
 // A1: wave split and particle counts
 
+// The sampling fraction of a slot when the numerical collision time of
+// thin-thick-joint cells is on (Sec. 3.2, second case): a face is joint when
+// the group opacity changes across it by a factor >= tau_jump; over the joint
+// faces of the cell, delta = max |T^l - T^r| / (T^l + T^r) (T^n), and
+// dt/tau_num = s / (1 + s C delta) replaces s = dt/tau in e^{-s}.  The wave
+// coefficient of the slot when it samples, C4(s) - e^{-dt/tau_num} =
+// W(s) - (e^{-dt/tau_num} - e^{-s}), goes to wsn (W(s) outside joint cells).
+__device__ inline double joint_fraction(const Dev& D, const Consts& K, const Inst& I, const Slot& s, int64_t j,
+                                        double es, double T)
+{
+    const int nx = I.nx, ix = s.lcell % nx, iy = s.lcell / nx, Gp = I.Gp;
+    const double sg = D.sig[j];
+    double delta = -1.0;
+    for (int q = 0; q < 2 * I.dim; ++q) {
+        const bool lo = (q & 1) == 0;
+        const bool inside = q < 2 ? (lo ? ix > 0 : ix < nx - 1) : (lo ? iy > 0 : iy < I.ny - 1);
+        if (!inside) continue;
+        const int dc = q < 2 ? (lo ? -1 : 1) : (lo ? -nx : nx);
+        const double sn = D.sig[j + (int64_t)dc * Gp];
+        const double hi = sg > sn ? sg : sn, lw = sg > sn ? sn : sg;
+        if (!(hi > 0.0) || hi < K.tau_jump * lw) continue;
+        const double Tn = D.T[I.cell_off + s.lcell + dc];
+        const double d = fabs(T - Tn) / (T + Tn);
+        if (d > delta) delta = d;
+    }
+    double frac = es, w = D.wc[j];
+    if (delta >= 0.0) {
+        const double sv = D.sv[j];
+        const double snum = sv / (1.0 + sv * K.tau_C * delta);
+        frac = exp(-snum);
+        const double dd = sv - snum;
+        w -= dd < 0.5 ? es * expm1(dd) : frac - es;
+    }
+    D.wsn[j] = w;
+    return frac;
+}
+
 // Also opens the step's record (block 0: the persistent entries from the
 // record before, everything else cleared), clears the tallies the push and
 // the commit add to (grid-stride over the flat arrays), and, when part is
@@ -237,7 +274,9 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroLi
         } else {
             const double rh = rho - rhop;
             D.rhoh[j] = rh;
-            const double eov = es * rh;
+            double frac = es;
+            if (K.tau_C > 0.0) frac = joint_fraction(D, K, I, s, j, es, T);
+            const double eov = frac * rh;
             const double E = eov * I.V;
             if (E > 0.0) {
                 const double q = eov / I.w_ref;
@@ -980,8 +1019,10 @@ __device__ inline double wave_source(const Dev& D, const Consts& K, const Inst& 
     const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
     constexpr int nf = 2 * DIM;
     // every load first
+    // the wave coefficient of a sampled slot: W(s), or this step's joint-cell value
+    const double* wsamp = K.tau_C > 0.0 ? D.wsn : D.wc;
     const int nb_here = D.nb[j];
-    const double wc_here = D.wc[j], c4_here = D.c4[j], rhoh_here = D.rhoh[j], rho_here = D.rho[j];
+    const double wc_here = wsamp[j], c4_here = D.c4[j], rhoh_here = D.rhoh[j], rho_here = D.rho[j];
     int nb_n[4];
     double wc_n[4], c4_n[4], rhoh_n[4], pb[4];
 #pragma unroll
@@ -991,7 +1032,7 @@ __device__ inline double wave_source(const Dev& D, const Consts& K, const Inst& 
         if (q >= nf) continue;
         if (F.inside[q]) {
             nb_n[q] = D.nb[F.nbj[q]];
-            wc_n[q] = D.wc[F.nbj[q]];
+            wc_n[q] = wsamp[F.nbj[q]];
             c4_n[q] = D.c4[F.nbj[q]];
             rhoh_n[q] = D.rhoh[F.nbj[q]];
         } else if (I.bc[q] == BC_PLANCK) {

@@ -354,6 +354,8 @@ struct ugkwp_ctx {
         K.cv = P.c / P.eps;
         K.lam_scale = P.c * P.dt / (P.eps * P.eps);
         K.cq = P.c / (4.0 * P.eps);
+        K.tau_C = P.tau_num_C;
+        K.tau_jump = P.tau_num_jump;
         K.nu_power = P.nu_power;
         K.si_tol = P.si_tol;
         K.n_cap = P.n_cap;
@@ -431,6 +433,7 @@ struct ugkwp_ctx {
         d.nb = dalloc<int32_t>(owned, ncg);
         d.boff = dalloc<int64_t>(owned, ncg + 1);
         d.wnew = dalloc<double>(owned, ncg);
+        d.wsn = dalloc<double>(owned, ncg);
         d.beta = dalloc<double>(owned, ncg);
         d.dep = dalloc<double>(owned, ncg);
         d.surv = dalloc<double>(owned, ncg);
@@ -1350,6 +1353,7 @@ uint64_t state_layout(const ugkwp_ctx* c)
     f.add(c->n_inst);
     f.add(c->K.c); f.add(c->K.a); f.add(c->K.eps); f.add(c->K.dt); f.add(c->K.nu_power);
     f.add(c->K.flags);
+    f.add(c->K.tau_C); f.add(c->K.tau_jump);
     for (const HostInst& h : c->hi) {
         f.add(h.nx); f.add(h.ny); f.add(h.G);
         f.add(h.x0); f.add(h.x1); f.add(h.y0); f.add(h.y1);
@@ -1400,7 +1404,8 @@ int ugkwp_create(ugkwp_ctx** out, const ugkwp_params* p, void* hip_stream)
     *out = nullptr;
     if (!(p->c > 0) || !(p->a > 0) || !(p->eps > 0) || !(p->dt > 0) || !std::isfinite(p->dt) ||
         !(p->si_tol >= 0) || p->si_max_iters < 1 || p->pool_capacity < 0 || p->n_cap < 0 ||
-        p->n_cap > (1 << 30) || !(p->nu_power >= 0) || p->sort_interval < 0)
+        p->n_cap > (1 << 30) || !(p->nu_power >= 0) || p->sort_interval < 0 ||
+        !(p->tau_num_C >= 0) || !std::isfinite(p->tau_num_C) || !(p->tau_num_jump >= 0))
         return UGKWP_EINVAL;
     ugkwp_ctx* c = new (std::nothrow) ugkwp_ctx();
     if (!c) return UGKWP_ENOMEM;
@@ -1520,6 +1525,8 @@ int ugkwp_record(ugkwp_ctx* ctx, int max_steps)
     return guarded(ctx, [&] {
         if (max_steps < 0) fail(UGKWP_EINVAL, "negative record size");
         if (max_steps > 0) require_ready(ctx);
+        if (max_steps > 0 && ctx->P.tau_num_C > 0)
+            fail(UGKWP_EINVAL, "the adjoint does not cover the numerical collision time of joint cells (tau_num_C > 0)");
         ctx->record_start(max_steps);
     });
 }

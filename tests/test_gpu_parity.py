@@ -476,3 +476,42 @@ def test_checkpoint_rejects_what_does_not_fit():
     c.record(0)
     c.set_state(buf)
     assert c.get_counters() == a.get_counters()
+
+
+# ------------------------------------------------------------ numerical collision time (joint cells)
+
+def _thick_thin(C=1e5, jump=10.0, nx=80, G=8):
+    p = W.slab(nx, G, lambda x: np.where(x <= 0.3, 1000.0, 10.0), dt=2e-3, steps=0,
+               w_ref=2e-5, pool_cap=1 << 20, tau_num_C=C, tau_num_jump=jump, name="thick_thin_taunum")
+    xc = (np.arange(nx) + 0.5) / nx
+    T0 = np.where(xc <= 0.3, 0.5, 1e-3)
+    return p.with_(T0=T0.copy(), Tr0=T0.copy())
+
+
+def test_tau_num_thick_thin_slab_matches_oracle():
+    run_pair(_thick_thin(), 12)
+
+
+def test_tau_num_lognormal_medium_matches_oracle():
+    p = W.c5_lognormal(n=24, G=5, dt=2e-2).with_(tau_num_C=1e3, tau_num_jump=4.0)
+    run_pair(p, 5)
+
+
+def test_tau_num_batch_matches_independent_oracle_runs():
+    probs = [_thick_thin(nx=40 + 16 * k, G=5 + 3 * k).with_(seed=300 + k) for k in range(3)]
+    say("[parity] tau_num batch of", len(probs))
+    ctx = ugkwp.from_batch(probs)
+    sims = [oracle.Sim(p) for p in probs]
+    for n in range(6):
+        ctx.step(1)
+        for s in sims:
+            s.step(1)
+    for k, (p, s) in enumerate(zip(probs, sims)):
+        compare_state(ctx, s, p, inst=k, what=f"tau_num instance {k}")
+
+
+def test_tau_num_is_not_recordable():
+    ctx = ugkwp.from_problem(_thick_thin())
+    with pytest.raises(ugkwp.UGKWPError) as e:
+        ctx.record(4)
+    assert e.value.code == ugkwp.EINVAL
