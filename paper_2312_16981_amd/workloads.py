@@ -104,6 +104,18 @@ def c2_two_material(nx: int = 2000, G: int = 64, **kw) -> Problem:
     return slab(nx, G, lambda x: np.where(x < 0.5, 0.01, 1000.0), **p)
 
 
+def thick_thin_joint(nx: int = 300, G: int = 24, **kw) -> Problem:
+    """Thick-to-thin slab on [0, 1.5] with the numerical collision time of the
+    joint cells on (Sec. 3.2, second case): kappa = 1000 for x <= 0.5 and 10
+    beyond (cell-centre rule; the paper's 1/sqrt(T) factor dropped), 24 log
+    groups on [0.01, 100], dt = dx / c, C = 1e5, reflective right wall."""
+    p = dict(dt=1.5 / nx, steps=600, w_ref=4e-6, pool_cap=1 << 24, name=f"thick_thin{nx}_g{G}",
+             numin=0.01, numax=100.0, bc_right=BC_REFLECT, tau_num_C=1e5, tau_num_jump=10.0)
+    p.update(kw)
+    q = slab(nx, G, lambda x: np.where(x <= 0.5 / 1.5, 1000.0, 10.0), **p)
+    return q.with_(x1=1.5)
+
+
 def c3_lattice(n: int = 256, G: int = 32, **kw) -> Problem:
     """2-D lattice on [0,7]^2: unit squares (a,b), absorber kappa=100 iff a+b odd,
     background kappa=1; cells with centres in [3,4]^2 pinned at T = 1; vacuum walls."""
