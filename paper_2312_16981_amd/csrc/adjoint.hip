@@ -143,30 +143,36 @@ __global__ void k_adj_face(Dev D, Consts K, Adj A, int inst, int axis)
 // per recorded step, in reverse
 
 // phi and phi' at T^{n+1}; mu^0 = Tbar; convergence state of the step reset.
+template <bool SINGLE>
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj_prep(Dev D, Consts K, Adj A, int r, uint32_t gate)
 {
-    if (!adj_gate(A, gate)) return;
     const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
-    if (j == 0) {
-        A.status[ADJ_CONV] = 0;
-        A.stepk[r] = 0;
-    }
-    const Slot s = decode_slot(D, K, j);
-    const Inst& I = D.inst[s.inst];
+    // the loads first (nothing is stored before the gate)
+    const unsigned long long done = A.status[ADJ_DONE];
+    Inst I;
+    const Slot s = decode_slot_rec<SINGLE>(D, K, j, I);
     const int g = s.g, G = I.G, Gp = I.Gp;
     const bool work = s.cell_ok;
     const int cell = I.cell_off + s.lcell;
     const double T = work ? A.rT[(int64_t)r * K.ncell + cell] : 1.0;
-    // lane g: lower edge of group g; the upper edge comes from lane g+1
     const bool edge_lane = work && g <= G;
-    const double xe = edge_lane ? D.nu[I.edge_off + g] / T : 0.0;
+    const double nu_lo = edge_lane ? D.nu[I.edge_off + g] : 0.0;
+    const double nu_top = work && g == G - 1 && G == Gp ? D.nu[I.edge_off + G] : 0.0;
+    const double tbar = work && g == 0 ? A.Tbar[cell] : 0.0;
+    if (!(gate == GATE_OFF || done == (unsigned long long)gate)) return;
+    if (j == 0) {
+        A.status[ADJ_CONV] = 0;
+        A.stepk[r] = 0;
+    }
+    // lane g: lower edge of group g; the upper edge comes from lane g+1
+    const double xe = edge_lane ? nu_lo / T : 0.0;
     const double ve = edge_lane ? planck_edge_value(xe, c_head_adj) : 0.0;
     const double we = edge_lane ? planck_edge_weight(xe) : 0.0;
     double xh = __shfl_down(xe, 1, Gp < 2 ? 2 : Gp);
     double vh = __shfl_down(ve, 1, Gp < 2 ? 2 : Gp);
     double wh = __shfl_down(we, 1, Gp < 2 ? 2 : Gp);
     if (work && g == G - 1 && G == Gp) {
-        xh = D.nu[I.edge_off + G] / T;
+        xh = nu_top / T;
         vh = planck_edge_value(xh, c_head_adj);
         wh = planck_edge_weight(xh);
     }
@@ -180,7 +186,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_prep(Dev D, Consts K, Adj A
             A.phi[j] = 0.0;
             A.dphi[j] = 0.0;
         }
-        if (work && g == 0) A.mu0[cell] = A.Tbar[cell];
+        if (work && g == 0) A.mu0[cell] = tbar;
         const int64_t rel = j - I.cg_off;
         if (rel >= 0 && rel < RES_SUB) {
             AdjResid z = {0ull, 0ull};
@@ -397,85 +403,133 @@ __global__ void k_adj_decide(Dev D, Consts K, Adj A, int k, int r, uint32_t gate
 // decided here (wavefront 0 of every block, the same answer; block 0 records
 // it).  The step's cotangents are formed only when every instance converged
 // and nothing non-finite was seen; block 0 then counts the step done.
+template <bool SINGLE, int DIM>
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj_grad(Dev D, Consts K, Adj A, int r, uint32_t gate,
                                                           int last_sweep)
 {
+    const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
+    // every load that does not need the sweep count goes out before the first
+    // wait (nothing is stored before the gate): the done count, the stopping
+    // state of the last sweep (one instance), the slot's and its neighbours' data
+    const unsigned long long done = A.status[ADJ_DONE];
+    const int cs0 = last_sweep >= 0 ? A.conv[0] : 0;
+    AdjResid rl = {0ull, 0ull};
+    if (last_sweep >= 0 && threadIdx.x < WAVE)
+        rl = A.res[((int64_t)0 * RES_SLOTS + last_sweep % RES_SLOTS) * RES_SUB + threadIdx.x];
+    Inst I;
+    const Slot s = decode_slot_rec<SINGLE>(D, K, j, I);
+    const int cs_inst = A.conv[s.inst];
+    const bool act = s.active;                    // implies j < n_cg
+    const int g = s.g;
+    const int cell = I.cell_off + s.lcell;
+    const int64_t o = (int64_t)r * K.n_cg + j;
+    constexpr int nf = 2 * DIM;
+    double wi = 0.0, lam = 0.0, sig = 0.0, rb = 0.0, phik = 0.0, rQ = 0.0, rRhoh = 0.0, c4d = 0.0, Af = 0.0,
+           dA = 0.0, simp = 0.0;
+    uint8_t samp = 0;
+    FaceRef fr[4];
+    double Df[4], dDds[4], phin[4], ghost[4], nw[4], nsig[4], nlam[4], nrb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        Df[q] = dDds[q] = phin[q] = ghost[q] = nw[q] = nsig[q] = nlam[q] = nrb[q] = 0.0;
+        if (q < nf) fr[q] = face_ref<DIM>(I, j, s.lcell, g, q);
+    }
+    if (act) {
+        wi = temp_weight(D, K, cell);
+        lam = D.sv[j];
+        sig = D.sig[j];
+        rb = A.rbar[j];
+        phik = A.phi[j];
+        rQ = A.rQ[o];
+        samp = A.rSamp[o];
+        rRhoh = A.rRhoh[o];
+        c4d = A.c4d[j];
+        Af = samp ? D.wc[j] : D.c4[j];
+        dA = samp ? A.wd[j] : c4d;
+        simp = D.simpson[I.edge_off + g];
+        const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
+#pragma unroll
+        for (int q = 0; q < nf; ++q) {
+            const bool xax = (q >> 1) == 0, lo = (q & 1) == 0;
+            const int64_t fs = fr[q].fslot;
+            Df[q] = xax ? D.Dx[fs] : D.Dy[fs];
+            // this cell is the high side of its low face and the low side of its high face
+            dDds[q] = xax ? (lo ? A.Dhx[fs] : A.Dlx[fs]) : (lo ? A.Dhy[fs] : A.Dly[fs]);
+            if (fr[q].inside) {
+                phin[q] = A.phi[fr[q].nbj];
+                nw[q] = temp_weight(D, K, fr[q].nbcell);
+                nsig[q] = D.sig[fr[q].nbj];
+                nlam[q] = D.sv[fr[q].nbj];
+                nrb[q] = A.rbar[fr[q].nbj];
+            } else if (I.bc[q] == BC_PLANCK) {
+                ghost[q] = phib[q * MAX_G + g];
+            }
+        }
+    }
     // the done count below advances while other blocks may still start
-    if (!adj_gate(A, gate) && !(gate != GATE_OFF && A.status[ADJ_DONE] == (unsigned long long)gate + 1)) return;
+    if (!(gate == GATE_OFF || done == (unsigned long long)gate || done == (unsigned long long)gate + 1)) return;
     int ns_single = 0;
     if (last_sweep >= 0) {
         __shared__ int sh_ns;
         if (threadIdx.x < WAVE) {
-            int ns = A.conv[0];
-            if (ns == 0 && adj_converged(A, 0, last_sweep, threadIdx.x)) ns = last_sweep + 1;
+            int ns = cs0;
+            if (ns == 0) {
+                const double dm = bitsd(wave_max_bits(bitsd(rl.dmu))), mm = bitsd(wave_max_bits(bitsd(rl.mu)));
+                if (dm <= (last_sweep >= 60 ? 1e-13 : 1e-15) * mm) ns = last_sweep + 1;
+            }
             if (threadIdx.x == 0) sh_ns = ns;
         }
         __syncthreads();
         ns_single = sh_ns;
-        if (blockIdx.x == 0 && threadIdx.x == 0 && ns_single != 0 && A.conv[0] == 0)
+        if (blockIdx.x == 0 && threadIdx.x == 0 && ns_single != 0 && cs0 == 0)
             adj_mark_converged(D, A, 0, ns_single, r);
         if (ns_single == 0 || A.status[ADJ_ERR] != 0) return;
     } else if (A.status[ADJ_CONV] != (unsigned long long)K.n_inst || A.status[ADJ_ERR] != 0) {
         return;
     }
-    const int64_t j = (int64_t)blockIdx.x * ADJ_THREADS + threadIdx.x;
     if (j == 0 && gate != GATE_OFF) A.status[ADJ_DONE] = (unsigned long long)gate + 1;
     if (j >= K.n_cg) return;
-    const Slot s = decode_slot(D, K, j);
-    if (!s.active) {
+    if (!act) {
         A.rbar_next[j] = 0.0;
         return;
     }
-    const Inst& I = D.inst[s.inst];
-    const int g = s.g;
-    const int cell = I.cell_off + s.lcell;
-    const int ns = last_sweep >= 0 ? ns_single : A.conv[s.inst];
+    // the converged mu of the step: the buffer the last sweep wrote
+    const int ns = last_sweep >= 0 ? ns_single : cs_inst;
     const double* mu = (ns & 1) ? A.mu1 : A.mu0;
     const double mui = mu[cell];
-    const double wi = temp_weight(D, K, cell);
-    const double lam = D.sv[j], sig = D.sig[j];
-    const double bb = wi * sig / (1.0 + lam) * mui + A.rbar[j] / (1.0 + lam);
-    const double phik = A.phi[j];
+    double nmu[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < nf; ++q)
+        if (fr[q].inside) nmu[q] = mu[fr[q].nbcell];
+    const double bb = wi * sig / (1.0 + lam) * mui + rb / (1.0 + lam);
     const double dtV = I.dt_V;
     const double cq = K.cq;
-    const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
     double lap = 0.0, accu = 0.0, sig_face = 0.0, s_planck = 0.0;
-    for (int q = 0; q < 2 * I.dim; ++q) {
-        const FaceRef f = face_ref<2>(I, j, s.lcell, g, q);   // the general form: lcell split by nx
-        const bool xax = (q >> 1) == 0, lo = (q & 1) == 0;
-        const double Df = xax ? D.Dx[f.fslot] : D.Dy[f.fslot];
-        // this cell is the high side of its low face and the low side of its high face
-        const double dDds = xax ? (lo ? A.Dhx[f.fslot] : A.Dlx[f.fslot])
-                                : (lo ? A.Dhy[f.fslot] : A.Dly[f.fslot]);
-        if (f.inside) {
-            const double bbn = bbar_of(D, K, A, mu, f.nbj, f.nbcell);
-            const double phin = A.phi[f.nbj];
-            lap += f.S * Df * (phin - phik);
-            accu += f.S * (bbn - bb);
-            sig_face += dtV * f.S * (bb - bbn) * (phin - phik) * dDds;
+#pragma unroll
+    for (int q = 0; q < nf; ++q) {
+        if (fr[q].inside) {
+            const double bbn = nw[q] * nsig[q] / (1.0 + nlam[q]) * nmu[q] + nrb[q] / (1.0 + nlam[q]);
+            lap += fr[q].S * Df[q] * (phin[q] - phik);
+            accu += fr[q].S * (bbn - bb);
+            sig_face += dtV * fr[q].S * (bb - bbn) * (phin[q] - phik) * dDds[q];
         } else {
             const int bc = I.bc[q];
             if (bc == BC_REFLECT) continue;
-            const double ghost = bc == BC_PLANCK ? phib[q * MAX_G + g] : 0.0;
-            lap += f.S * Df * (ghost - phik);
-            accu -= f.S * bb;
-            sig_face += dtV * f.S * bb * (ghost - phik) * dDds;
-            if (bc == BC_PLANCK) s_planck += dtV * f.S * cq * bb * ghost * A.c4d[j];
+            lap += fr[q].S * Df[q] * (ghost[q] - phik);
+            accu -= fr[q].S * bb;
+            sig_face += dtV * fr[q].S * bb * (ghost[q] - phik) * dDds[q];
+            if (bc == BC_PLANCK) s_planck += dtV * fr[q].S * cq * bb * ghost[q] * c4d;
         }
     }
-    const int64_t o = (int64_t)r * K.n_cg + j;
-    const double b = A.rQ[o] + dtV * lap;
+    const double b = rQ + dtV * lap;
     const double em = (b - phik) / (1.0 + lam);
     const double ubar = dtV * cq * accu;
-    const bool samp = A.rSamp[o] != 0;
-    const double Af = samp ? D.wc[j] : D.c4[j];
-    const double dA = samp ? A.wd[j] : A.c4d[j];
-    double sbar = -em / (1.0 + lam) * (wi * sig * mui + A.rbar[j]);
-    sbar += ubar * A.rRhoh[o] * dA;
+    double sbar = -em / (1.0 + lam) * (wi * sig * mui + rb);
+    sbar += ubar * rRhoh * dA;
     sbar += s_planck;
     const double sigbar = wi * em * mui;
     const double ks = K.c * K.dt / (K.eps * K.eps);
-    A.grad[j] += D.simpson[I.edge_off + g] * (sigbar + ks * sbar + sig_face);
+    A.grad[j] += simp * (sigbar + ks * sbar + sig_face);
     A.rbar_next[j] = bb + Af * ubar;
     if (g == 0) A.Tbar[cell] = mui;
 }
@@ -503,7 +557,7 @@ void launch_adj_face(const Dev& D, const Consts& K, const Adj& A, int inst, int 
 
 void launch_adj_prep(const Dev& D, const Consts& K, const Adj& A, int r, uint32_t gate, hipStream_t st)
 {
-    k_adj_prep<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, r, gate);
+    (K.n_inst == 1 ? k_adj_prep<true> : k_adj_prep<false>)<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, r, gate);
 }
 
 void launch_adj_decide(const Dev& D, const Consts& K, const Adj& A, int k, int r, uint32_t gate, hipStream_t st)
@@ -529,7 +583,10 @@ void launch_adj_sweeps(const Dev& D, const Consts& K, const Adj& A, int k0, int 
 void launch_adj_grad(const Dev& D, const Consts& K, const Adj& A, int r, uint32_t gate, int last_sweep,
                      hipStream_t st)
 {
-    k_adj_grad<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, r, gate, K.n_inst == 1 ? last_sweep : -1);
+    const bool single = K.n_inst == 1;
+    auto gr = K.inst0.dim == 1 ? (single ? k_adj_grad<true, 1> : k_adj_grad<false, 1>)
+                               : (single ? k_adj_grad<true, 2> : k_adj_grad<false, 2>);
+    gr<<<ablocks(K.n_cg), ADJ_THREADS, 0, st>>>(D, K, A, r, gate, single ? last_sweep : -1);
 }
 
 }  // namespace ugk
