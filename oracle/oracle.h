@@ -95,6 +95,11 @@ typedef struct {
      * share a face across which sigma changes by a factor >= jump. */
     double tau_num_C;
     double tau_num_jump;
+    /* temperature-dependent opacity sigma(nu, T) = kappa nu^-p T^-q (Sec. 3.1):
+     * q = T_power.  The particles and the wave split of a step take T^n; the
+     * source iteration re-evaluates sigma, lambda and the face coefficients
+     * from its own iterate T^k in every sweep (Algorithm 2). */
+    double T_power;
 } ora_params;
 
 typedef struct ora_sim ora_sim;

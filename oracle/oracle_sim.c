@@ -184,11 +184,20 @@ int ora_set_material(ora_sim* s, const double* cv, const double* T0, const doubl
     return ORA_OK;
 }
 
-/* Opacity seen by a particle of frequency nu in (cell, g). */
+/* kappa of (cell, g) at temperature T: kappa T^-q (Sec. 3.1's sigma0/sqrt(T) for
+ * q = 1/2); kappa itself when q = 0. */
+static double kappa_at(const ora_sim* s, size_t cg, double T)
+{
+    return s->p.T_power != 0.0 ? s->kappa[cg] * pow(T, -s->p.T_power) : s->kappa[cg];
+}
+
+/* Opacity seen by a particle of frequency nu in (cell, g) during a step: the
+ * cell's temperature T^n. */
 static double particle_sigma(const ora_sim* s, size_t cg, double nu, int g)
 {
-    if (s->p.flags & ORA_FLAG_GROUP_SIGMA) return s->kappa[cg] * s->simpson[g];
-    return s->kappa[cg] * nupow(nu, s->p.nu_power);
+    const double k = kappa_at(s, cg, s->T[cg / (size_t)s->p.G]);
+    if (s->p.flags & ORA_FLAG_GROUP_SIGMA) return k * s->simpson[g];
+    return k * nupow(nu, s->p.nu_power);
 }
 
 /* Harmonic mean face opacity (Appendix B); zero if either side is zero.
@@ -464,7 +473,7 @@ static int step_once(ora_sim* s)
     for (int i = 0; i < nc; ++i)
         for (int g = 0; g < G; ++g) {
             size_t k = (size_t)i * G + g;
-            sig[k] = s->kappa[k] * s->simpson[g];
+            sig[k] = kappa_at(s, k, s->T[i]) * s->simpson[g];
             sv[k] = c * sig[k] * dt / (eps * eps);
             es[k] = exp(-sv[k]);
             wsamp[k] = ora_coef_w(sv[k]);
@@ -637,7 +646,12 @@ static int step_once(ora_sim* s)
     dg.inflow_wave = inflow_wave;
 
     /* ---- source iteration for Eq. macroSysFinal (A5; Appendix B, Algorithm 2) ---- */
-    double* lam = sv;    /* c sigma dt / eps^2 */
+    /* With a temperature-dependent opacity every sweep first recomputes sigma,
+     * lambda = c sigma dt / eps^2 and the face coefficients from its iterate
+     * T^k (the coefficient step of Algorithm 2); otherwise they are the step's. */
+    const int tdep = P->T_power != 0.0;
+    double* sigk = tdep ? (double*)malloc(sizeof(double) * ncg) : sig;
+    double* lam = tdep ? (double*)malloc(sizeof(double) * ncg) : sv;    /* c sigma dt / eps^2 */
     double* phi = (double*)malloc(sizeof(double) * ncg);
     double* phin = (double*)malloc(sizeof(double) * ncg);
     double* rk = (double*)malloc(sizeof(double) * ncg);
@@ -667,6 +681,25 @@ static int step_once(ora_sim* s)
     int converged = 0, sweeps = 0, bad = 0;
     double drho = 0, mrho = 0, dT = 0, mT = 0;
     for (int it = 0; it < P->si_max_iters; ++it) {
+        if (tdep) {
+            for (int i = 0; i < nc; ++i)
+                for (int g = 0; g < G; ++g) {
+                    size_t k = (size_t)i * G + g;
+                    sigk[k] = kappa_at(s, k, Tk[i]) * s->simpson[g];
+                    lam[k] = c * sigk[k] * dt / (eps * eps);
+                }
+            for (int i = 0; i < nc; ++i) {
+                nbface f[4];
+                int nf = cell_faces(s, i, f);
+                for (int g = 0; g < G; ++g) {
+                    size_t k = (size_t)i * G + g;
+                    for (int q = 0; q < nf; ++q) {
+                        double sf = f[q].nb >= 0 ? harmonic(sigk[k], sigk[(size_t)f[q].nb * G + g]) : sigk[k];
+                        Df[k * 4 + q] = face_D(s, sf, f[q].h);
+                    }
+                }
+            }
+        }
         drho = mrho = dT = mT = 0.0;
         for (int i = 0; i < nc; ++i) {
             nbface f[4];
@@ -688,7 +721,7 @@ static int step_once(ora_sim* s)
                 double r = (b + lam[k] * phi[k]) / (1.0 + lam[k]);
                 rn1[k] = r;
                 em[k] = (b - phi[k]) / (1.0 + lam[k]);
-                sum += sig[k] * em[k];
+                sum += sigk[k] * em[k];
                 double dr = fabs(r - rk[k]);
                 if (dr > drho || dr != dr) drho = dr;
                 if (fabs(r) > mrho) mrho = fabs(r);
@@ -731,7 +764,7 @@ static int step_once(ora_sim* s)
                     double pn = ghost_phi(s, f[q].side, g, phi[k]);
                     inflow_eq += dt * f[q].S * Df[k * 4 + q] * (pn - phi[k]) / c;
                 }
-                if (s->pinned[i]) inj -= V * (dt * sig[k] / (eps * eps)) * em[k];
+                if (s->pinned[i]) inj -= V * (dt * sigk[k] / (eps * eps)) * em[k];
             }
         }
         double e0 = 0.0, e1 = 0.0;
@@ -762,6 +795,7 @@ static int step_once(ora_sim* s)
     }
     free(sig); free(sv); free(es); free(wsamp); free(rhoh); free(A); free(wnet); free(sampled);
     free(phi); free(phin); free(rk); free(Tk); free(Tn1); free(rn1); free(em); free(Df);
+    if (tdep) { free(sigk); free(lam); }
     return status;
 }
 
@@ -869,9 +903,9 @@ int ora_get_counters(const ora_sim* s, uint64_t* birth_counter, int* step)
 /* Recording hooks used by the adjoint (oracle_adjoint.c). */
 int ora_record(ora_sim* s, int on)
 {
-    /* the frozen-tally map has no derivative through the joint cells' tau_num
-     * (it depends on T^n through a maximum): not recorded */
-    if (on && s->p.tau_num_C > 0.0) return ORA_EINVAL;
+    /* the frozen-tally map covers neither the joint cells' tau_num (a maximum
+     * over T^n) nor a temperature-dependent opacity: not recorded */
+    if (on && (s->p.tau_num_C > 0.0 || s->p.T_power != 0.0)) return ORA_EINVAL;
     free_rec(s);
     s->recording = on ? 1 : 0;
     if (on) {

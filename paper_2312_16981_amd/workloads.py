@@ -53,6 +53,7 @@ class Problem:
     flags: int = 0
     tau_num_C: float = 0.0       # > 0: numerical collision time in thin-thick-joint cells
     tau_num_jump: float = 10.0   # opacity ratio across a face that makes its cells joint
+    T_power: float = 0.0         # sigma(nu, T) = kappa nu^-p T^-T_power
 
     @property
     def G(self) -> int:
