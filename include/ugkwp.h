@@ -95,6 +95,12 @@ typedef struct {
                             flux keeps C4(s) - e^{-dt/tau_num} (Remark 3).  0 = off.
                             Not recordable for ugkwp_adjoint.                        */
     double tau_num_jump; /* opacity ratio that makes a face joint (<= 1: every face)   */
+    double opacity_T_power; /* q of a temperature-dependent opacity sigma(nu, T) =
+                            kappa nu^-p T^-q (Sec. 3.1 takes q = 1/2); 0 = none.
+                            The particles and the wave split of a step take the
+                            temperature T^n; every source-iteration sweep recomputes
+                            sigma, lambda and the face coefficients from its iterate
+                            (Algorithm 2).  Not recordable for ugkwp_adjoint.        */
 } ugkwp_params;
 
 /* One problem instance (a slab in 1-D, a rectangle in 2-D). */

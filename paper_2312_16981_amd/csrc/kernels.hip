@@ -90,8 +90,12 @@ __device__ inline bool step_committed(const Dev& D, const Consts& K)
 // ---------------------------------------------------------------------------
 // set-up kernels
 
+// With a temperature-dependent opacity (K.t_power != 0) the tables are those
+// of the cells' temperature T^n, and the step launches this kernel again at
+// its start (gated like the step's other launches).
 __global__ void k_tables(Dev D, Consts K)
 {
+    if (!gate_open(D, K, 0)) return;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= K.n_cg) return;
     const Slot s = decode_slot(D, K, j);
@@ -99,15 +103,24 @@ __global__ void k_tables(Dev D, Consts K)
         D.sig[j] = 0.0; D.sv[j] = 0.0; D.es[j] = 1.0; D.c4[j] = 1.0; D.wc[j] = 0.0; D.inv_kappa[j] = 0.0;
         return;
     }
-    D.inv_kappa[j] = 1.0 / D.kappa[j];     // +inf for kappa = 0: no collision
     const Inst& I = D.inst[s.inst];
-    const double sg = D.kappa[j] * D.simpson[I.edge_off + s.g];
+    const double kap = K.t_power != 0.0 ? D.kappa[j] * pow(D.T[I.cell_off + s.lcell], -K.t_power) : D.kappa[j];
+    D.inv_kappa[j] = 1.0 / kap;            // +inf for kappa = 0: no collision
+    const double sg = kap * D.simpson[I.edge_off + s.g];
     const double sv = K.c * sg * K.dt / (K.eps * K.eps);
     D.sig[j] = sg;
     D.sv[j] = sv;
     D.es[j] = exp(-sv);
     D.c4[j] = coef_c4(sv);
     D.wc[j] = coef_w(sv);
+}
+
+// D of a face with face opacity sf and centre distance h (Appendix B, Eq. C2Formula).
+__device__ inline double face_coef(const Consts& K, double sf, double h)
+{
+    const double s = K.c * sf * K.dt / (K.eps * K.eps);
+    const double c2 = K.dt * coef_c2_over_dt(s);
+    return -(K.c * K.c / (3.0 * K.eps * K.eps)) * c2 / h;
 }
 
 // One instance, one axis: faces (nx+1)*ny (axis 0) or nx*(ny+1) (axis 1), Gp groups each.
@@ -142,9 +155,7 @@ __global__ void k_face_D(Dev D, Consts K, int inst, int axis)
     } else {
         sf = D.sig[I.cg_off + ((int64_t)(cl >= 0 ? cl : cr) << I.lgGp) + g];
     }
-    const double s = K.c * sf * K.dt / (K.eps * K.eps);
-    const double c2 = K.dt * coef_c2_over_dt(s);
-    Dout[j] = -(K.c * K.c / (3.0 * K.eps * K.eps)) * c2 / h;
+    Dout[j] = face_coef(K, sf, h);
 }
 
 // Planckian ghost values phi_g(T_b) per instance and side.
@@ -1127,7 +1138,7 @@ __device__ inline bool si_converged(const Dev& D, const Consts& K, int inst, int
 // FIRST: sweep 0 (its own instantiation, so that the wave-flux code does not
 // weigh on the registers of the later sweeps); SINGLE: a context of one
 // instance; DIM: the dimension of every instance of the context.
-template <bool FIRST, bool SINGLE, int DIM>
+template <bool FIRST, bool SINGLE, int DIM, bool TDEP>
 __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k, const double* phi_in,
                                                           double* phi_out, int decide_prev)
 {
@@ -1199,9 +1210,25 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q >= nf) continue;
-            Df[q] = q < 2 ? D.Dx[F.fslot[q]] : D.Dy[F.fslot[q]];
+            if (!TDEP) Df[q] = q < 2 ? D.Dx[F.fslot[q]] : D.Dy[F.fslot[q]];
             if (F.inside[q]) pn[q] = phi_in[F.nbj[q]];
             else if (I.bc[q] == BC_PLANCK) pn[q] = phib[q * MAX_G + g];
+        }
+    }
+    // temperature-dependent opacity: kappa of the slot and of the neighbours
+    // across each face, and the neighbours' iterate T^k
+    double kap_j = 0.0, Sg = 0.0;
+    double kap_n[4] = {0.0, 0.0, 0.0, 0.0}, T_nb[4] = {1.0, 1.0, 1.0, 1.0};
+    if (TDEP && act) {
+        kap_j = D.kappa[j];
+        Sg = D.simpson[I.edge_off + g];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= nf || !F.inside[q]) continue;
+            const bool lo = (q & 1) == 0;
+            const int nbc = cell + (q < 2 ? (lo ? -1 : 1) : (lo ? -nx : nx));
+            kap_n[q] = D.kappa[F.nbj[q]];
+            T_nb[q] = FIRST ? D.T[nbc] : D.T_new[nbc];
         }
     }
     double Tn = 1.0, Tk = 1.0, dtcv = 0.0;
@@ -1223,6 +1250,23 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     const bool work = run && s.cell_ok;
     double contrib = 0.0, r = 0.0;
     if (work && s.active) {
+        if (TDEP) {
+            // the coefficient step of Algorithm 2: sigma, lambda and the face
+            // coefficients of this sweep from the iterate T^k
+            const double sk = kap_j * pow(Tk, -K.t_power) * Sg;
+            sig = sk;
+            lam = K.c * sk * K.dt / (K.eps * K.eps);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q >= nf) continue;
+                double sf = sk;
+                if (F.inside[q]) {
+                    const double sn = kap_n[q] * pow(T_nb[q], -K.t_power) * Sg;
+                    sf = (sk + sn > 0.0) ? 2.0 * (sk * sn) / (sk + sn) : 0.0;
+                }
+                Df[q] = face_coef(K, sf, q < 2 ? I.dx : I.dy);
+            }
+        }
         double lap = 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -1472,6 +1516,14 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
         }
     }
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // inflow_eq, exit/c, injection, e0, e1
+    if (in && s.active && K.t_power != 0.0 && (bnd[0] || bnd[1] || bnd[2] || bnd[3])) {
+        // temperature-dependent opacity: the boundary faces' coefficients at the
+        // step's final temperature (the iteration has converged on it)
+        const double sk = D.kappa[j] * pow(D.T_new[cell], -K.t_power) * D.simpson[I.edge_off + g];
+#pragma unroll
+        for (int q = 0; q < 2 * DIM; ++q)
+            if (bnd[q]) Df[q] = face_coef(K, sk, (q >> 1) == 0 ? I.dx : I.dy);
+    }
     if (in && s.active) {
         D.phi0[j] = phi_next;
 #pragma unroll
@@ -1740,16 +1792,22 @@ void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& In,
     }
 }
 
+template <bool TDEP>
+static auto sweep_kernel(const Consts& K, bool fold, int k)
+{
+    return K.inst0.dim == 1
+               ? (fold ? (k == 0 ? k_si_sweep<true, true, 1, TDEP> : k_si_sweep<false, true, 1, TDEP>)
+                       : (k == 0 ? k_si_sweep<true, false, 1, TDEP> : k_si_sweep<false, false, 1, TDEP>))
+               : (fold ? (k == 0 ? k_si_sweep<true, true, 2, TDEP> : k_si_sweep<false, true, 2, TDEP>)
+                       : (k == 0 ? k_si_sweep<true, false, 2, TDEP> : k_si_sweep<false, false, 2, TDEP>));
+}
+
 void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t st)
 {
     const bool fold = K.n_inst == 1;
     for (int k = k0; k < k1; ++k) {
         // every instance of a context has the same dimension
-        auto kern = K.inst0.dim == 1
-                        ? (fold ? (k == 0 ? k_si_sweep<true, true, 1> : k_si_sweep<false, true, 1>)
-                                : (k == 0 ? k_si_sweep<true, false, 1> : k_si_sweep<false, false, 1>))
-                        : (fold ? (k == 0 ? k_si_sweep<true, true, 2> : k_si_sweep<false, true, 2>)
-                                : (k == 0 ? k_si_sweep<true, false, 2> : k_si_sweep<false, false, 2>));
+        auto kern = K.t_power != 0.0 ? sweep_kernel<true>(K, fold, k) : sweep_kernel<false>(K, fold, k);
         kern<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, sweep_in(D, k), sweep_out(D, k),
                                                                     fold && k > k0 ? 1 : 0);
         if (!fold) k_si_decide<<<blocks((int64_t)K.n_inst * WAVE, 256), 256, 0, st>>>(D, K, k);

@@ -515,3 +515,44 @@ def test_tau_num_is_not_recordable():
     with pytest.raises(ugkwp.UGKWPError) as e:
         ctx.record(4)
     assert e.value.code == ugkwp.EINVAL
+
+
+# ------------------------------------------------------------ temperature-dependent opacity
+
+def _marshak_like(q=0.5, nx=60, G=8, **kw):
+    p = dict(dt=2e-3, steps=0, w_ref=2e-5, pool_cap=1 << 20, name="marshak_like", T_power=q)
+    p.update(kw)
+    return W.slab(nx, G, lambda x: np.full_like(x, 0.3), **p)
+
+
+def test_temperature_dependent_opacity_slab_matches_oracle():
+    run_pair(_marshak_like(), 12)
+
+
+def test_temperature_dependent_opacity_2d_and_reflective_wall():
+    p = W.c5_lognormal(n=20, G=5, dt=2e-2).with_(T_power=0.5)
+    run_pair(p, 5)
+    q = _marshak_like(nx=40, G=6, bc_right=W.BC_REFLECT)
+    run_pair(q, 8)
+
+
+def test_temperature_dependent_opacity_with_tau_num_and_batch():
+    """Sec. 3.2's second case combines both: a thick-to-thin slab with sigma
+    ~ T^-1/2 and the joint cells' numerical collision time."""
+    run_pair(_thick_thin().with_(T_power=0.5), 10)
+    probs = [_marshak_like(nx=30 + 10 * k, G=4 + 2 * k).with_(seed=400 + k) for k in range(3)]
+    ctx = ugkwp.from_batch(probs)
+    sims = [oracle.Sim(p) for p in probs]
+    for n in range(6):
+        ctx.step(1)
+        for s in sims:
+            s.step(1)
+    for k, (p, s) in enumerate(zip(probs, sims)):
+        compare_state(ctx, s, p, inst=k, what=f"T-dependent instance {k}")
+
+
+def test_temperature_dependent_opacity_is_not_recordable():
+    ctx = ugkwp.from_problem(_marshak_like())
+    with pytest.raises(ugkwp.UGKWPError) as e:
+        ctx.record(4)
+    assert e.value.code == ugkwp.EINVAL
