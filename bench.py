@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 PUSH_BYTES_READ = 48       # x, mu, nu, w, id (8 B each) + cell word, group (4 B each)
 PUSH_BYTES_WRITE = 12      # new position and cell word of a survivor (updated in place)
 PUSH_BYTES_DEAD = 4        # empty-slot mark of a particle absorbed or gone
-SPINUP = {"slab": 500, "lattice": 300, "batch": 100, "adjoint": 0, "thickthin": 200}
+SPINUP = {"slab": 500, "lattice": 300, "batch": 100, "adjoint": 0, "thickthin": 200, "marshak": 100}
 ADJ_SWEEP_BYTES = 48       # rbar, lambda, sigma, phi' and two face coefficients per (cell, group) update
 SI_SWEEP_BYTES = 64        # Q, lambda, sigma, phi^k, rho^k, one face D read; rho^{k+1}, phi^{k+1} written
 
@@ -257,6 +257,10 @@ def workload_name(wl, probs, spin, args):
         p = probs[0]
         return (f"two-material slab {p.nx} cells x {p.G} groups, dt=1e-4, kappa 0.01|1000 jump at "
                 f"x=0.5, steps {first}-{last} of the run from t=0")
+    if wl == "marshak":
+        p = probs[0]
+        return (f"homogeneous Marshak wave {p.nx} cells x {p.G} groups on [0,5], sigma = 10/(nu^3 sqrt(T)), "
+                f"C_v = 0.1, reflective right wall, dt=dx/c, steps {first}-{last} of the run from t=0")
     if wl == "thickthin":
         p = probs[0]
         return (f"thick-to-thin slab {p.nx} cells x {p.G} groups on [0,1.5], kappa 1000|10 jump at x=0.5, "
@@ -286,7 +290,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--workload", choices=("slab", "lattice", "batch", "adjoint", "thickthin"), default="slab")
+    ap.add_argument("--workload", choices=("slab", "lattice", "batch", "adjoint", "thickthin", "marshak"), default="slab")
     ap.add_argument("--per-instance", action="store_true",
                     help="batch workload: one context per instance instead of one batched context")
     ap.add_argument("--spinup", type=int, default=-1, help="untimed steps from t=0 (default per workload)")
@@ -331,6 +335,8 @@ def main():
         probs = [W.c3_lattice()]
     elif wl == "thickthin":
         probs = [W.thick_thin_joint()]
+    elif wl == "marshak":
+        probs = [W.marshak()]
     else:
         probs = W.c4_batch()
     ncg = sum(p.ncell * p.G for p in probs)

@@ -105,6 +105,17 @@ def c2_two_material(nx: int = 2000, G: int = 64, **kw) -> Problem:
     return slab(nx, G, lambda x: np.where(x < 0.5, 0.01, 1000.0), **p)
 
 
+def marshak(nx: int = 1000, G: int = 24, sigma0: float = 10.0, **kw) -> Problem:
+    """Homogeneous Marshak wave stand-in (Sec. 3.1): [0, 5], sigma = sigma0 /
+    (nu^3 sqrt(T)), C_v = 0.1, 24 log groups on [0.01, 100], Planckian wall at
+    T = 1, reflective right wall, T0 = Tr0 = 1e-3, dt = dx / c."""
+    p = dict(dt=5.0 / nx, steps=400, w_ref=1e-5, pool_cap=1 << 24, name=f"marshak{nx}_g{G}_s{sigma0:g}",
+             numin=0.01, numax=100.0, bc_right=BC_REFLECT, T_power=0.5)
+    p.update(kw)
+    q = slab(nx, G, lambda x: np.full_like(x, sigma0), **p)
+    return q.with_(x1=5.0, cv=np.full(nx, 0.1))
+
+
 def thick_thin_joint(nx: int = 300, G: int = 24, **kw) -> Problem:
     """Thick-to-thin slab on [0, 1.5] with the numerical collision time of the
     joint cells on (Sec. 3.2, second case): kappa = 1000 for x <= 0.5 and 10
