@@ -70,7 +70,9 @@ double ora_sample_nu(double nl, double nh, double beta, double U);
 enum { ORA_BC_VACUUM = 0, ORA_BC_PLANCK = 1, ORA_BC_REFLECT = 2 };
 enum { ORA_OK = 0, ORA_EINVAL = -1, ORA_ENOMEM = -2, ORA_EPOOL = -3,
        ORA_ENOCONV = -4, ORA_ENONFINITE = -5 };
-enum { ORA_FLAG_GROUP_SIGMA = 1 };  /* flights use the group (Simpson) sigma */
+enum { ORA_FLAG_GROUP_SIGMA = 1,    /* flights use the group (Simpson) sigma */
+       ORA_FLAG_SI_LINEARIZED = 8   /* source iteration with the emission linearized
+                                       about T^k (a local Newton step) */ };
 
 typedef struct {
     int dim;              /* 1 or 2 */

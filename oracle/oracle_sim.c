@@ -650,6 +650,13 @@ static int step_once(ora_sim* s)
      * lambda = c sigma dt / eps^2 and the face coefficients from its iterate
      * T^k (the coefficient step of Algorithm 2); otherwise they are the step's. */
     const int tdep = P->T_power != 0.0;
+    /* Linearized variant: the emission of the new temperature is taken as
+     * phi^k + phi'(T^k) (T^{k+1} - T^k), so each cell's energy balance is solved
+     * for T^{k+1} as one local Newton step; its fixed point is that of the
+     * literal iteration (Eq. macroSysFinal). */
+    const int lin = (P->flags & ORA_FLAG_SI_LINEARIZED) != 0;
+    double* dph = lin ? (double*)malloc(sizeof(double) * ncg) : NULL;
+    double* bk = (double*)malloc(sizeof(double) * G);
     double* sigk = tdep ? (double*)malloc(sizeof(double) * ncg) : sig;
     double* lam = tdep ? (double*)malloc(sizeof(double) * ncg) : sv;    /* c sigma dt / eps^2 */
     double* phi = (double*)malloc(sizeof(double) * ncg);
@@ -700,11 +707,15 @@ static int step_once(ora_sim* s)
                 }
             }
         }
+        if (lin)
+            for (int i = 0; i < nc; ++i)
+                for (int g = 0; g < G; ++g)
+                    dph[(size_t)i * G + g] = ora_dphi_group(Tk[i], s->nu[g], s->nu[g + 1], P->a, c);
         drho = mrho = dT = mT = 0.0;
         for (int i = 0; i < nc; ++i) {
             nbface f[4];
             int nf = cell_faces(s, i, f);
-            double sum = 0.0;
+            double sum = 0.0, dsum = 0.0;
             for (int g = 0; g < G; ++g) {
                 size_t k = (size_t)i * G + g;
                 double lap = 0.0;
@@ -718,15 +729,27 @@ static int step_once(ora_sim* s)
                  * identical expression sigma (b - phi^k)/(1 + lam), which does not cancel
                  * when lam = c sigma dt / eps^2 is large. */
                 double b = s->Q[k] + (dt / V) * lap;
-                double r = (b + lam[k] * phi[k]) / (1.0 + lam[k]);
+                bk[g] = b;
+                sum += sigk[k] * (b - phi[k]) / (1.0 + lam[k]);
+                if (lin) dsum += sigk[k] * dph[k] / (1.0 + lam[k]);
+            }
+            const double w = dt / (eps * eps * s->cv[i]);
+            double Tnew;
+            if (s->pinned[i]) Tnew = s->T[i];
+            else if (lin) Tnew = Tk[i] + (s->T[i] - Tk[i] + w * sum) / (1.0 + w * dsum);
+            else Tnew = s->T[i] + w * sum;
+            /* the new temperature's emission: phi^k, or its linearization */
+            const double dTi = lin && !s->pinned[i] ? Tnew - Tk[i] : 0.0;
+            for (int g = 0; g < G; ++g) {
+                size_t k = (size_t)i * G + g;
+                const double pe = lin ? phi[k] + dph[k] * dTi : phi[k];
+                double r = (bk[g] + lam[k] * pe) / (1.0 + lam[k]);
                 rn1[k] = r;
-                em[k] = (b - phi[k]) / (1.0 + lam[k]);
-                sum += sigk[k] * em[k];
+                em[k] = (bk[g] - pe) / (1.0 + lam[k]);
                 double dr = fabs(r - rk[k]);
                 if (dr > drho || dr != dr) drho = dr;
                 if (fabs(r) > mrho) mrho = fabs(r);
             }
-            double Tnew = s->pinned[i] ? s->T[i] : s->T[i] + (dt / (eps * eps * s->cv[i])) * sum;
             if (!(Tnew > 0.0) || !isfinite(Tnew)) bad = 1;
             Tn1[i] = Tnew;
             double dd = fabs(Tnew - Tk[i]);
@@ -796,6 +819,7 @@ static int step_once(ora_sim* s)
     free(sig); free(sv); free(es); free(wsamp); free(rhoh); free(A); free(wnet); free(sampled);
     free(phi); free(phin); free(rk); free(Tk); free(Tn1); free(rn1); free(em); free(Df);
     if (tdep) { free(sigk); free(lam); }
+    free(dph); free(bk);
     return status;
 }
 
