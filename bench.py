@@ -298,6 +298,8 @@ def main():
                     help="steps between counting sorts of the pool (0 = library default)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default push launch shape instead of tuning it after the spin-up")
+    ap.add_argument("--si-linearized", action="store_true",
+                    help="linearized source iteration (a local Newton step per sweep; same fixed point)")
     ap.add_argument("--graph", action="store_true",
                     help="replay the launches before the push and the source-iteration sweeps from "
                          "captured HIP graphs")
@@ -339,6 +341,8 @@ def main():
         probs = [W.marshak()]
     else:
         probs = W.c4_batch()
+    if args.si_linearized:
+        probs = [p.with_(flags=p.flags | W.FLAG_SI_LINEARIZED) for p in probs]
     ncg = sum(p.ncell * p.G for p in probs)
     spin = SPINUP[wl] if args.spinup < 0 else args.spinup
     xf = ugkwp.FLAG_GRAPH if args.graph else 0
@@ -418,6 +422,7 @@ def main():
                    "cell_groups": ncg,
                    "parallelism": "single GPU" + (", per-instance contexts" if args.per_instance else ""),
                    "launch": "HIP graph replays" if args.graph else "kernels launched directly",
+                   "source_iteration": "linearized (Newton step per sweep)" if args.si_linearized else "literal",
                    "push_shape": ("default (occupancy-filled grid, 4 particles per thread)" if tuned is None else
                                   f"autotuned: {tuned[0]['blocks']} blocks, {tuned[0]['ppt']} particles per thread "
                                   f"({tuned[0]['us_best']:.1f} vs {tuned[0]['us_default']:.1f} us default)"

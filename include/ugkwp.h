@@ -62,9 +62,17 @@ enum {
                                     source-iteration sweeps from captured HIP
                                     graphs (one per launch configuration) instead
                                     of launching each kernel; same results        */
-    UGKWP_FLAG_PHASE_TIMES = 4   /* time every phase of a step with HIP events (the
+    UGKWP_FLAG_PHASE_TIMES = 4,  /* time every phase of a step with HIP events (the
                                     diag's ms_sample, ms_macro, ms_si, ms_sort);
                                     otherwise only the push is timed              */
+    UGKWP_FLAG_SI_LINEARIZED = 8 /* source iteration (Appendix B) with the emission
+                                    of T^{k+1} linearized about T^k, each sweep a
+                                    local Newton step of every cell's energy
+                                    balance: the same fixed point (Eq.
+                                    macroSysFinal), and convergence also where
+                                    sum_g dt sigma_g phi'_g / (eps^2 C_v
+                                    (1 + lambda_g)) exceeds 1 (stiff material
+                                    coupling, where the literal sweep diverges)   */
 };
 
 typedef struct ugkwp_ctx ugkwp_ctx;

@@ -18,14 +18,6 @@ hipError_t set_head_series_adj(const HeadSeries& hs)
 
 constexpr int ADJ_THREADS = 256;
 
-// x^4 / (e^x - 1): the edge term of d phi_g / dT
-__device__ inline double planck_edge_weight(double x)
-{
-    if (x > 700.0) return 0.0;
-    const double x2 = x * x;
-    return x2 * x2 / expm1(x);
-}
-
 // Heat-capacity weight dt / (eps^2 C_v) of the temperature update; 0 in pinned cells.
 __device__ inline double temp_weight(const Dev& D, const Consts& K, int cell)
 {

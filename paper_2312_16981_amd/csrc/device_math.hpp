@@ -158,6 +158,15 @@ __device__ inline double planck_tail_series(double x, const HeadSeries& hs)
     return sum;
 }
 
+// x^4 / (e^x - 1): the edge term of d phi_g / dT (the band integral of a
+// group differentiated through its limits nu / T)
+__device__ inline double planck_edge_weight(double x)
+{
+    if (x > 700.0) return 0.0;
+    const double x2 = x * x;
+    return x2 * x2 / expm1(x);
+}
+
 // Edge value used by group bands: head(x) below 2, tail(x) from 2 on.
 __device__ inline double planck_edge_value(double x, const HeadSeries& hs)
 {

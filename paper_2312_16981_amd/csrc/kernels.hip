@@ -29,6 +29,7 @@
 #include "device_math.hpp"
 #include "kernels.hpp"
 #include "device_common.hpp"
+#include "../../include/ugkwp.h"
 
 namespace ugk {
 
@@ -1138,7 +1139,11 @@ __device__ inline bool si_converged(const Dev& D, const Consts& K, int inst, int
 // FIRST: sweep 0 (its own instantiation, so that the wave-flux code does not
 // weigh on the registers of the later sweeps); SINGLE: a context of one
 // instance; DIM: the dimension of every instance of the context.
-template <bool FIRST, bool SINGLE, int DIM, bool TDEP>
+// LIN: the linearized iteration. A sweep takes the new temperature's emission
+// as phi^k + phi'(T^k) (T^{k+1} - T^k) and solves each cell's energy balance
+// for T^{k+1}, a local Newton step with the literal iteration's fixed point
+// (Eq. macroSysFinal) that also converges under stiff material coupling.
+template <bool FIRST, bool SINGLE, int DIM, bool TDEP, bool LIN>
 __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k, const double* phi_in,
                                                           double* phi_out, int decide_prev)
 {
@@ -1248,7 +1253,16 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     const bool run = wave_on && cs_inst == 0 && j < K.n_cg;
     double dr = 0.0, mr = 0.0, dT = 0.0, mT = 0.0;
     const bool work = run && s.cell_ok;
-    double contrib = 0.0, r = 0.0;
+    // linearized iteration: d phi_g / dT at T^k, its upper-edge term from lane g+1
+    double dph = 0.0;
+    if (LIN) {
+        const bool edge_lane = work && g <= G;
+        const double we = edge_lane ? planck_edge_weight(nu_lo / Tk) : 0.0;
+        double wh = __shfl_down(we, 1, Gp < 2 ? 2 : Gp);
+        if (work && g == G - 1 && G == Gp) wh = planck_edge_weight(nu_top / Tk);
+        if (work && s.active) dph = 4.0 * phi / Tk + K.a * K.c * (Tk * Tk * Tk) * (we - wh) / UGK_PI4_15;
+    }
+    double contrib = 0.0, dcon = 0.0, r = 0.0, b = 0.0;
     if (work && s.active) {
         if (TDEP) {
             // the coefficient step of Algorithm 2: sigma, lambda and the face
@@ -1274,20 +1288,33 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
             const double p = F.inside[q] ? pn[q] : (I.bc[q] == BC_REFLECT ? phi : pn[q]);
             lap += F.S[q] * Df[q] * (p - phi);
         }
-        const double b = Qj + I.dt_V * lap;
-        r = (b + lam * phi) / (1.0 + lam);
+        b = Qj + I.dt_V * lap;
         const double em = (b - phi) / (1.0 + lam);
         contrib = sig * em;
-        dr = fabs(r - rho_prev);
-        mr = fabs(r);
+        if (LIN) {
+            dcon = sig * dph / (1.0 + lam);
+        } else {
+            r = (b + lam * phi) / (1.0 + lam);
+            dr = fabs(r - rho_prev);
+            mr = fabs(r);
+        }
     }
     // group sum over the Gp lanes of the cell (every lane gets the same bits)
     contrib = group_sum(contrib, Gp);
+    if (LIN) dcon = group_sum(dcon, Gp);
 
     double Tnew = 1.0;
     bool bad = false;
     if (work) {
-        Tnew = pinned ? Tn : Tn + dtcv * contrib;
+        if (LIN) Tnew = pinned ? Tn : Tk + (Tn - Tk + dtcv * contrib) / (1.0 + dtcv * dcon);
+        else Tnew = pinned ? Tn : Tn + dtcv * contrib;
+        if (LIN && s.active) {
+            // rho^{k+1} with the linearized emission of T^{k+1}
+            const double pe = pinned ? phi : phi + dph * (Tnew - Tk);
+            r = (b + lam * pe) / (1.0 + lam);
+            dr = fabs(r - rho_prev);
+            mr = fabs(r);
+        }
         if (!(Tnew > 0.0) || !isfinite(Tnew)) {
             bad = true;
             Tnew = 1.0;
@@ -1792,14 +1819,14 @@ void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& In,
     }
 }
 
-template <bool TDEP>
+template <bool TDEP, bool LIN>
 static auto sweep_kernel(const Consts& K, bool fold, int k)
 {
     return K.inst0.dim == 1
-               ? (fold ? (k == 0 ? k_si_sweep<true, true, 1, TDEP> : k_si_sweep<false, true, 1, TDEP>)
-                       : (k == 0 ? k_si_sweep<true, false, 1, TDEP> : k_si_sweep<false, false, 1, TDEP>))
-               : (fold ? (k == 0 ? k_si_sweep<true, true, 2, TDEP> : k_si_sweep<false, true, 2, TDEP>)
-                       : (k == 0 ? k_si_sweep<true, false, 2, TDEP> : k_si_sweep<false, false, 2, TDEP>));
+               ? (fold ? (k == 0 ? k_si_sweep<true, true, 1, TDEP, LIN> : k_si_sweep<false, true, 1, TDEP, LIN>)
+                       : (k == 0 ? k_si_sweep<true, false, 1, TDEP, LIN> : k_si_sweep<false, false, 1, TDEP, LIN>))
+               : (fold ? (k == 0 ? k_si_sweep<true, true, 2, TDEP, LIN> : k_si_sweep<false, true, 2, TDEP, LIN>)
+                       : (k == 0 ? k_si_sweep<true, false, 2, TDEP, LIN> : k_si_sweep<false, false, 2, TDEP, LIN>));
 }
 
 void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t st)
@@ -1807,7 +1834,9 @@ void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t
     const bool fold = K.n_inst == 1;
     for (int k = k0; k < k1; ++k) {
         // every instance of a context has the same dimension
-        auto kern = K.t_power != 0.0 ? sweep_kernel<true>(K, fold, k) : sweep_kernel<false>(K, fold, k);
+        const bool lin = (K.flags & UGKWP_FLAG_SI_LINEARIZED) != 0;
+        auto kern = K.t_power != 0.0 ? (lin ? sweep_kernel<true, true>(K, fold, k) : sweep_kernel<true, false>(K, fold, k))
+                                     : (lin ? sweep_kernel<false, true>(K, fold, k) : sweep_kernel<false, false>(K, fold, k));
         kern<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, sweep_in(D, k), sweep_out(D, k),
                                                                     fold && k > k0 ? 1 : 0);
         if (!fold) k_si_decide<<<blocks((int64_t)K.n_inst * WAVE, 256), 256, 0, st>>>(D, K, k);

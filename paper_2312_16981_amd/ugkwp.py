@@ -20,6 +20,7 @@ BC_VACUUM, BC_PLANCK, BC_REFLECT = 0, 1, 2
 FLAG_GROUP_SIGMA = 1
 FLAG_GRAPH = 2
 FLAG_PHASE_TIMES = 4
+FLAG_SI_LINEARIZED = 8
 PURPOSE_BIRTH, PURPOSE_FLIGHT = 1, 2
 
 EXPORTED = [

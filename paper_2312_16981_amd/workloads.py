@@ -18,6 +18,7 @@ import numpy as np
 
 BC_VACUUM, BC_PLANCK, BC_REFLECT = 0, 1, 2
 FLAG_GROUP_SIGMA = 1
+FLAG_SI_LINEARIZED = 8
 
 
 @dataclass

@@ -556,3 +556,37 @@ def test_temperature_dependent_opacity_is_not_recordable():
     with pytest.raises(ugkwp.UGKWPError) as e:
         ctx.record(4)
     assert e.value.code == ugkwp.EINVAL
+
+
+def _stiff_slab(nx=40, G=6, **kw):
+    """Small heat capacity: the literal source iteration diverges on this slab."""
+    p = dict(dt=0.02, steps=0, w_ref=2e-5, pool_cap=1 << 20, name="stiff_slab",
+             flags=W.FLAG_SI_LINEARIZED)
+    p.update(kw)
+    q = W.slab(nx, G, lambda x: np.full_like(x, 50.0), **p)
+    return q.with_(cv=np.full(nx, 0.01), T0=np.full(nx, 0.05), Tr0=np.full(nx, 0.05))
+
+
+def test_linearized_iteration_stiff_slab_matches_oracle():
+    with pytest.raises(oracle.OracleError):            # the literal sweep fails here
+        oracle.Sim(_stiff_slab(flags=0)).step(1)
+    run_pair(_stiff_slab(), 8)
+
+
+def test_linearized_iteration_2d_pinned_and_temperature_dependent():
+    p = W.c3_lattice(n=24, G=5, dt=2e-2, w_ref=1e-5, pool_cap=1 << 21)
+    run_pair(p.with_(flags=p.flags | W.FLAG_SI_LINEARIZED), 5)
+    run_pair(_marshak_like().with_(flags=W.FLAG_SI_LINEARIZED), 10)
+    run_pair(_stiff_slab(nx=30, G=5, T_power=0.5), 6)
+
+
+def test_linearized_iteration_batch():
+    probs = [_stiff_slab(nx=20 + 15 * k, G=3 + 2 * k).with_(seed=500 + k) for k in range(3)]
+    ctx = ugkwp.from_batch(probs)
+    sims = [oracle.Sim(p) for p in probs]
+    for n in range(5):
+        ctx.step(1)
+        for s in sims:
+            s.step(1)
+    for k, (p, s) in enumerate(zip(probs, sims)):
+        compare_state(ctx, s, p, inst=k, what=f"linearized instance {k}")
