@@ -34,7 +34,8 @@ class Params(C.Structure):
                 ("c", _d), ("a", _d), ("eps", _d), ("dt", _d), ("w_ref", _d),
                 ("n_cap", C.c_int64), ("seed", C.c_uint64), ("pool_cap", C.c_int64),
                 ("si_max_iters", C.c_int), ("si_tol", _d), ("flags", C.c_int),
-                ("tau_num_C", _d), ("tau_num_jump", _d), ("T_power", _d)]
+                ("tau_num_C", _d), ("tau_num_jump", _d), ("T_power", _d),
+                ("opacity_stim", C.c_int)]
 
 
 class Diag(C.Structure):
@@ -191,6 +192,7 @@ class Sim:
         P.si_max_iters, P.si_tol, P.flags = prob.si_max_iters, prob.si_tol, prob.flags
         P.tau_num_C, P.tau_num_jump = prob.tau_num_C, prob.tau_num_jump
         P.T_power = prob.T_power
+        P.opacity_stim = prob.opacity_stim
         self._P = P
         h = L.ora_create(C.byref(P))
         if not h:

@@ -102,6 +102,10 @@ typedef struct {
      * source iteration re-evaluates sigma, lambda and the face coefficients
      * from its own iterate T^k in every sweep (Algorithm 2). */
     double T_power;
+    /* 1: the stimulated-emission factor (1 - e^{-nu/T}) multiplies sigma, as in
+     * Sec. 3.3's gamma0 (1 - e^{-h nu / kT}) / (h nu)^3; the group opacity is
+     * then Simpson's mean of nu^-p (1 - e^{-nu/T}) over the group.  0: none. */
+    int opacity_stim;
 } ora_params;
 
 typedef struct ora_sim ora_sim;

@@ -83,6 +83,7 @@ ora_sim* ora_create(const ora_params* p)
     if (!p || (p->dim != 1 && p->dim != 2) || p->nx < 1 || p->ny < 1) return NULL;
     if (p->dim == 1 && p->ny != 1) return NULL;
     if (p->G < 1 || !p->nu) return NULL;
+    if (p->opacity_stim != 0 && p->opacity_stim != 1) return NULL;
     if (!(p->dt > 0) || !(p->c > 0) || !(p->eps > 0) || !(p->a > 0) || !(p->w_ref > 0)) return NULL;
     if (!(p->x1 > p->x0)) return NULL;
     if (p->dim == 2 && !(p->y1 > p->y0)) return NULL;
@@ -191,13 +192,30 @@ static double kappa_at(const ora_sim* s, size_t cg, double T)
     return s->p.T_power != 0.0 ? s->kappa[cg] * pow(T, -s->p.T_power) : s->kappa[cg];
 }
 
+/* Stimulated-emission factor 1 - e^{-nu/T} (Sec. 3.3), or 1 without it. */
+static double stim(const ora_sim* s, double nu, double T)
+{
+    return s->p.opacity_stim ? -expm1(-nu / T) : 1.0;
+}
+
+/* Frequency factor of group g at temperature T: Simpson's mean over the group
+ * of nu^-p, times the stimulated-emission factor when that is on. */
+static double group_factor(const ora_sim* s, int g, double T)
+{
+    if (!s->p.opacity_stim) return s->simpson[g];
+    const double p = s->p.nu_power, nl = s->nu[g], nh = s->nu[g + 1], nm = 0.5 * (nl + nh);
+    return (nupow(nl, p) * stim(s, nl, T) + 4.0 * nupow(nm, p) * stim(s, nm, T)
+            + nupow(nh, p) * stim(s, nh, T)) / 6.0;
+}
+
 /* Opacity seen by a particle of frequency nu in (cell, g) during a step: the
  * cell's temperature T^n. */
 static double particle_sigma(const ora_sim* s, size_t cg, double nu, int g)
 {
-    const double k = kappa_at(s, cg, s->T[cg / (size_t)s->p.G]);
-    if (s->p.flags & ORA_FLAG_GROUP_SIGMA) return k * s->simpson[g];
-    return k * nupow(nu, s->p.nu_power);
+    const double T = s->T[cg / (size_t)s->p.G];
+    const double k = kappa_at(s, cg, T);
+    if (s->p.flags & ORA_FLAG_GROUP_SIGMA) return k * group_factor(s, g, T);
+    return k * nupow(nu, s->p.nu_power) * stim(s, nu, T);
 }
 
 /* Harmonic mean face opacity (Appendix B); zero if either side is zero.
@@ -473,7 +491,7 @@ static int step_once(ora_sim* s)
     for (int i = 0; i < nc; ++i)
         for (int g = 0; g < G; ++g) {
             size_t k = (size_t)i * G + g;
-            sig[k] = kappa_at(s, k, s->T[i]) * s->simpson[g];
+            sig[k] = kappa_at(s, k, s->T[i]) * group_factor(s, g, s->T[i]);
             sv[k] = c * sig[k] * dt / (eps * eps);
             es[k] = exp(-sv[k]);
             wsamp[k] = ora_coef_w(sv[k]);
@@ -649,7 +667,7 @@ static int step_once(ora_sim* s)
     /* With a temperature-dependent opacity every sweep first recomputes sigma,
      * lambda = c sigma dt / eps^2 and the face coefficients from its iterate
      * T^k (the coefficient step of Algorithm 2); otherwise they are the step's. */
-    const int tdep = P->T_power != 0.0;
+    const int tdep = P->T_power != 0.0 || P->opacity_stim;
     /* Linearized variant: the emission of the new temperature is taken as
      * phi^k + phi'(T^k) (T^{k+1} - T^k), so each cell's energy balance is solved
      * for T^{k+1} as one local Newton step; its fixed point is that of the
@@ -692,7 +710,7 @@ static int step_once(ora_sim* s)
             for (int i = 0; i < nc; ++i)
                 for (int g = 0; g < G; ++g) {
                     size_t k = (size_t)i * G + g;
-                    sigk[k] = kappa_at(s, k, Tk[i]) * s->simpson[g];
+                    sigk[k] = kappa_at(s, k, Tk[i]) * group_factor(s, g, Tk[i]);
                     lam[k] = c * sigk[k] * dt / (eps * eps);
                 }
             for (int i = 0; i < nc; ++i) {
@@ -929,7 +947,7 @@ int ora_record(ora_sim* s, int on)
 {
     /* the frozen-tally map covers neither the joint cells' tau_num (a maximum
      * over T^n) nor a temperature-dependent opacity: not recorded */
-    if (on && (s->p.tau_num_C > 0.0 || s->p.T_power != 0.0)) return ORA_EINVAL;
+    if (on && (s->p.tau_num_C > 0.0 || s->p.T_power != 0.0 || s->p.opacity_stim)) return ORA_EINVAL;
     free_rec(s);
     s->recording = on ? 1 : 0;
     if (on) {

@@ -55,6 +55,7 @@ class Problem:
     tau_num_C: float = 0.0       # > 0: numerical collision time in thin-thick-joint cells
     tau_num_jump: float = 10.0   # opacity ratio across a face that makes its cells joint
     T_power: float = 0.0         # sigma(nu, T) = kappa nu^-p T^-T_power
+    opacity_stim: int = 0        # 1: sigma also carries (1 - e^{-nu/T})
 
     @property
     def G(self) -> int:
