@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 PUSH_BYTES_READ = 48       # x, mu, nu, w, id (8 B each) + cell word, group (4 B each)
 PUSH_BYTES_WRITE = 12      # new position and cell word of a survivor (updated in place)
 PUSH_BYTES_DEAD = 4        # empty-slot mark of a particle absorbed or gone
-SPINUP = {"slab": 500, "lattice": 300, "batch": 100, "adjoint": 0, "thickthin": 200, "marshak": 100}
+SPINUP = {"slab": 500, "lattice": 300, "batch": 100, "adjoint": 0, "thickthin": 200, "marshak": 100, "larsen": 100}
 ADJ_SWEEP_BYTES = 48       # rbar, lambda, sigma, phi' and two face coefficients per (cell, group) update
 SI_SWEEP_BYTES = 64        # Q, lambda, sigma, phi^k, rho^k, one face D read; rho^{k+1}, phi^{k+1} written
 
@@ -261,6 +261,10 @@ def workload_name(wl, probs, spin, args):
         p = probs[0]
         return (f"homogeneous Marshak wave {p.nx} cells x {p.G} groups on [0,5], sigma = 10/(nu^3 sqrt(T)), "
                 f"C_v = 0.1, reflective right wall, dt=dx/c, steps {first}-{last} of the run from t=0")
+    if wl == "larsen":
+        p = probs[0]
+        return (f"Larsen three-region slab {p.nx} cells x {p.G} groups on [0,4], sigma = gamma0 (1 - e^(-nu/T))/nu^3, "
+                f"gamma0 1|1000|1, C_v = 0.05109, tau_num C = 1e3, dt=dx/c, steps {first}-{last} of the run from t=0")
     if wl == "thickthin":
         p = probs[0]
         return (f"thick-to-thin slab {p.nx} cells x {p.G} groups on [0,1.5], kappa 1000|10 jump at x=0.5, "
@@ -290,7 +294,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--workload", choices=("slab", "lattice", "batch", "adjoint", "thickthin", "marshak"), default="slab")
+    ap.add_argument("--workload", choices=("slab", "lattice", "batch", "adjoint", "thickthin", "marshak", "larsen"), default="slab")
     ap.add_argument("--per-instance", action="store_true",
                     help="batch workload: one context per instance instead of one batched context")
     ap.add_argument("--spinup", type=int, default=-1, help="untimed steps from t=0 (default per workload)")
@@ -339,6 +343,8 @@ def main():
         probs = [W.thick_thin_joint()]
     elif wl == "marshak":
         probs = [W.marshak()]
+    elif wl == "larsen":
+        probs = [W.larsen()]
     else:
         probs = W.c4_batch()
     if args.si_linearized:
@@ -422,7 +428,8 @@ def main():
                    "cell_groups": ncg,
                    "parallelism": "single GPU" + (", per-instance contexts" if args.per_instance else ""),
                    "launch": "HIP graph replays" if args.graph else "kernels launched directly",
-                   "source_iteration": "linearized (Newton step per sweep)" if args.si_linearized else "literal",
+                   "source_iteration": ("linearized (Newton step per sweep)" if probs[0].flags & W.FLAG_SI_LINEARIZED
+                                        else "literal"),
                    "push_shape": ("default (occupancy-filled grid, 4 particles per thread)" if tuned is None else
                                   f"autotuned: {tuned[0]['blocks']} blocks, {tuned[0]['ppt']} particles per thread "
                                   f"({tuned[0]['us_best']:.1f} vs {tuned[0]['us_default']:.1f} us default)"

@@ -109,6 +109,12 @@ typedef struct {
                             temperature T^n; every source-iteration sweep recomputes
                             sigma, lambda and the face coefficients from its iterate
                             (Algorithm 2).  Not recordable for ugkwp_adjoint.        */
+    int32_t opacity_stim; /* 1: sigma also carries the stimulated-emission factor
+                            (1 - e^{-nu/T}) of Sec. 3.3's gamma0 (1 - e^{-h nu/kT})
+                            / (h nu)^3, at the same temperatures as the T^-q factor;
+                            a group's opacity is then Simpson's mean of
+                            nu^-p (1 - e^{-nu/T}) over the group.  0 = none; other
+                            values are rejected.  Not recordable for ugkwp_adjoint. */
 } ugkwp_params;
 
 /* One problem instance (a slab in 1-D, a rectangle in 2-D). */

@@ -47,6 +47,7 @@ struct Consts {
     double tau_C;          // numerical collision time of joint cells: C (0 = off)
     double tau_jump;       // opacity ratio across a face that makes its cells joint
     double t_power;        // q of sigma(nu, T) = kappa nu^-p T^-q (0: no T dependence)
+    int stim;              // 1: sigma also carries 1 - e^{-nu/T}
     double nu_power;
     double si_tol;
     int64_t n_cap;

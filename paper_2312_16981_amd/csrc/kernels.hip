@@ -59,8 +59,26 @@ __device__ inline Geo geo_of(const Inst& I)
 
 // sigma(nu, cell) = kappa[cell][g] * f(nu): f = nu^-3 (the paper's opacities),
 // nu^-p, or the Simpson group factor S_g with the group-opacity flag.  f is
-// fixed for a particle, so the push computes it once.
-enum { SIG_NU3 = 0, SIG_POW = 1, SIG_GROUP = 2 };
+// fixed for a particle, so the push computes it once.  SIG_STIM: nu^-p times
+// the stimulated-emission factor 1 - e^{-nu/T} of the cell the particle is in
+// (Sec. 3.3), evaluated at every cell entry.
+enum { SIG_NU3 = 0, SIG_POW = 1, SIG_GROUP = 2, SIG_STIM = 3 };
+
+// Stimulated-emission factor 1 - e^{-nu/T} (Sec. 3.3's opacity), or 1 without it.
+__device__ inline double stim_factor(const Consts& K, double nu, double T)
+{
+    return K.stim ? -expm1(-nu / T) : 1.0;
+}
+
+// Frequency factor of group g at temperature T: Simpson's mean of nu^-p over
+// the group, times the stimulated-emission factor when that is on.
+__device__ inline double group_factor(const Dev& D, const Consts& K, int edge_off, int g, double T)
+{
+    if (!K.stim) return D.simpson[edge_off + g];
+    const double nl = D.nu[edge_off + g], nh = D.nu[edge_off + g + 1], nm = 0.5 * (nl + nh);
+    return (nu_pow(nl, K.nu_power) * stim_factor(K, nl, T) + 4.0 * nu_pow(nm, K.nu_power) * stim_factor(K, nm, T)
+            + nu_pow(nh, K.nu_power) * stim_factor(K, nh, T)) / 6.0;
+}
 
 // The flight scale of a particle, tau = eps^2 / (c sigma), with sigma = kappa
 // nu^-p (Remark 2; Simpson's group factor S_g instead of nu^-p with
@@ -71,6 +89,7 @@ __device__ inline double tau_factor(const Dev& D, const Consts& K, const Geo& I,
 {
     if (SM == SIG_GROUP) return K.e2c / D.simpson[I.edge_off + g];
     if (SM == SIG_NU3) return K.e2c * (nu * nu * nu);
+    if (SM == SIG_STIM && K.nu_power == 3.0) return K.e2c * (nu * nu * nu);
     return K.e2c * pow(nu, K.nu_power);
 }
 
@@ -91,7 +110,7 @@ __device__ inline bool step_committed(const Dev& D, const Consts& K)
 // ---------------------------------------------------------------------------
 // set-up kernels
 
-// With a temperature-dependent opacity (K.t_power != 0) the tables are those
+// With a temperature-dependent opacity (K.t_power != 0 or K.stim) the tables are those
 // of the cells' temperature T^n, and the step launches this kernel again at
 // its start (gated like the step's other launches).
 __global__ void k_tables(Dev D, Consts K)
@@ -105,9 +124,14 @@ __global__ void k_tables(Dev D, Consts K)
         return;
     }
     const Inst& I = D.inst[s.inst];
-    const double kap = K.t_power != 0.0 ? D.kappa[j] * pow(D.T[I.cell_off + s.lcell], -K.t_power) : D.kappa[j];
-    D.inv_kappa[j] = 1.0 / kap;            // +inf for kappa = 0: no collision
-    const double sg = kap * D.simpson[I.edge_off + s.g];
+    const double Tc = D.T[I.cell_off + s.lcell];
+    const double kap = K.t_power != 0.0 ? D.kappa[j] * pow(Tc, -K.t_power) : D.kappa[j];
+    const double sg = kap * group_factor(D, K, I.edge_off, s.g, Tc);
+    // flights: tau = (eps^2/c) f(nu)^-1 / kappa; with the stimulated-emission
+    // factor and group opacities the group factor's T dependence goes here
+    // (the push divides by S_g), per particle the push applies it itself
+    D.inv_kappa[j] = (K.stim && (K.flags & 1u)) ? D.simpson[I.edge_off + s.g] / sg
+                                                : 1.0 / kap;   // +inf for kappa = 0: no collision
     const double sv = K.c * sg * K.dt / (K.eps * K.eps);
     D.sig[j] = sg;
     D.sv[j] = sv;
@@ -639,9 +663,9 @@ __device__ inline void draw_flight(const Consts& K, const Geo& I, uint64_t id, u
 }
 
 // Flight of one particle through the step.  Returns 0 survives, 1 collided, 2 left the domain.
-template <int DIM>
+template <int DIM, int SM>
 __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTable& T, uint64_t id,
-                          uint32_t step, double tfac, int g, double w, Flight& f)
+                          uint32_t step, double tfac, int g, double nu, double w, Flight& f)
 {
     for (;;) {
         const double vx = K.cv * f.ox;
@@ -716,6 +740,7 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTabl
         lds_tally(T, D, type, index, w);
         if (xaxis) f.ix += pos ? 1 : -1; else f.iy += pos ? 1 : -1;
         f.tau = tfac * D.inv_kappa[I.cg_off + ((uint32_t)(f.iy * I.nx + f.ix) << I.lgGp) + (uint32_t)g];
+        if (SM == SIG_STIM) f.tau = f.tau / stim_factor(K, nu, D.T[I.cell_off + f.iy * I.nx + f.ix]);
         draw_flight(K, I, id, step, f);
     }
 }
@@ -830,10 +855,11 @@ __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Cons
             f.d = 0;
             const double tfac = tau_factor<SM>(D, K, I, nu, g);
             f.tau = tfac * D.inv_kappa[I.cg_off + ((uint32_t)lcell << I.lgGp) + (uint32_t)g];
+            if (SM == SIG_STIM) f.tau = f.tau / stim_factor(K, nu, D.T[cell]);
             if (i < n_slots) draw_flight(K, I, id, step, f);    // old particle: t_f = min(-tau ln eta, dt)
             else { f.coll = false; f.t_rem = K.dt; }            // new collisionless particle: t_f = dt
             const double ox0 = f.ox, oy0 = f.oy;
-            const int out = fly<DIM>(D, K, I, T, id, step, tfac, g, w, f);
+            const int out = fly<DIM, SM>(D, K, I, T, id, step, tfac, g, nu, w, f);
             if (out != 2) {
                 const uint32_t cg = I.cg_off + ((uint32_t)(f.iy * I.nx + f.ix) << I.lgGp) + (uint32_t)g;
                 lds_tally(T, D, out == 0 ? TAL_SURV : TAL_DEP, cg, w);
@@ -1222,11 +1248,11 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     }
     // temperature-dependent opacity: kappa of the slot and of the neighbours
     // across each face, and the neighbours' iterate T^k
-    double kap_j = 0.0, Sg = 0.0;
+    double kap_j = 0.0, Sg = 0.0, Sn[4] = {0.0, 0.0, 0.0, 0.0};
     double kap_n[4] = {0.0, 0.0, 0.0, 0.0}, T_nb[4] = {1.0, 1.0, 1.0, 1.0};
     if (TDEP && act) {
         kap_j = D.kappa[j];
-        Sg = D.simpson[I.edge_off + g];
+        Sg = group_factor(D, K, I.edge_off, g, FIRST ? D.T[cell] : D.T_new[cell]);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q >= nf || !F.inside[q]) continue;
@@ -1234,6 +1260,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
             const int nbc = cell + (q < 2 ? (lo ? -1 : 1) : (lo ? -nx : nx));
             kap_n[q] = D.kappa[F.nbj[q]];
             T_nb[q] = FIRST ? D.T[nbc] : D.T_new[nbc];
+            Sn[q] = K.stim ? group_factor(D, K, I.edge_off, g, T_nb[q]) : Sg;
         }
     }
     double Tn = 1.0, Tk = 1.0, dtcv = 0.0;
@@ -1275,7 +1302,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
                 if (q >= nf) continue;
                 double sf = sk;
                 if (F.inside[q]) {
-                    const double sn = kap_n[q] * pow(T_nb[q], -K.t_power) * Sg;
+                    const double sn = kap_n[q] * pow(T_nb[q], -K.t_power) * Sn[q];
                     sf = (sk + sn > 0.0) ? 2.0 * (sk * sn) / (sk + sn) : 0.0;
                 }
                 Df[q] = face_coef(K, sf, q < 2 ? I.dx : I.dy);
@@ -1543,10 +1570,10 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
         }
     }
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // inflow_eq, exit/c, injection, e0, e1
-    if (in && s.active && K.t_power != 0.0 && (bnd[0] || bnd[1] || bnd[2] || bnd[3])) {
+    if (in && s.active && (K.t_power != 0.0 || K.stim) && (bnd[0] || bnd[1] || bnd[2] || bnd[3])) {
         // temperature-dependent opacity: the boundary faces' coefficients at the
         // step's final temperature (the iteration has converged on it)
-        const double sk = D.kappa[j] * pow(D.T_new[cell], -K.t_power) * D.simpson[I.edge_off + g];
+        const double sk = D.kappa[j] * pow(D.T_new[cell], -K.t_power) * group_factor(D, K, I.edge_off, g, D.T_new[cell]);
 #pragma unroll
         for (int q = 0; q < 2 * DIM; ++q)
             if (bnd[q]) Df[q] = face_coef(K, sk, (q >> 1) == 0 ? I.dx : I.dy);
@@ -1729,7 +1756,7 @@ void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, hipStr
     else k_sample<2><<<512, 256, 0, st>>>(D, K, P);
 }
 
-static int g_push_grid[2][2][3] = {};
+static int g_push_grid[2][2][4] = {};
 
 template <int DIM, bool SINGLE, int SM>
 static int push_blocks_per_cu()
@@ -1742,7 +1769,9 @@ static int push_blocks_per_cu()
 
 static int sig_mode(const Consts& K)
 {
-    return (K.flags & 1u) ? SIG_GROUP : (K.nu_power == 3.0 ? SIG_NU3 : SIG_POW);
+    if (K.flags & 1u) return SIG_GROUP;
+    if (K.stim) return SIG_STIM;
+    return K.nu_power == 3.0 ? SIG_NU3 : SIG_POW;
 }
 
 int push_grid(int dim, bool single, int sm)
@@ -1771,7 +1800,8 @@ static void push_mode(int sm, int nb, int ppt, const Dev& D, const Consts& K, co
 {
     if (sm == SIG_NU3) k_push<DIM, SINGLE, SIG_NU3><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, ppt);
     else if (sm == SIG_POW) k_push<DIM, SINGLE, SIG_POW><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, ppt);
-    else k_push<DIM, SINGLE, SIG_GROUP><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, ppt);
+    else if (sm == SIG_GROUP) k_push<DIM, SINGLE, SIG_GROUP><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, ppt);
+    else k_push<DIM, SINGLE, SIG_STIM><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, ppt);
 }
 
 PushShape push_default_shape(int dim, const Consts& K)
@@ -1835,7 +1865,7 @@ void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t
     for (int k = k0; k < k1; ++k) {
         // every instance of a context has the same dimension
         const bool lin = (K.flags & UGKWP_FLAG_SI_LINEARIZED) != 0;
-        auto kern = K.t_power != 0.0 ? (lin ? sweep_kernel<true, true>(K, fold, k) : sweep_kernel<true, false>(K, fold, k))
+        auto kern = (K.t_power != 0.0 || K.stim) ? (lin ? sweep_kernel<true, true>(K, fold, k) : sweep_kernel<true, false>(K, fold, k))
                                      : (lin ? sweep_kernel<false, true>(K, fold, k) : sweep_kernel<false, false>(K, fold, k));
         kern<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, sweep_in(D, k), sweep_out(D, k),
                                                                     fold && k > k0 ? 1 : 0);

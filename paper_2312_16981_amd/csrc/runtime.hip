@@ -357,6 +357,7 @@ struct ugkwp_ctx {
         K.tau_C = P.tau_num_C;
         K.tau_jump = P.tau_num_jump;
         K.t_power = P.opacity_T_power;
+        K.stim = P.opacity_stim;
         K.nu_power = P.nu_power;
         K.si_tol = P.si_tol;
         K.n_cap = P.n_cap;
@@ -754,7 +755,7 @@ struct ugkwp_ctx {
         add(D.diag_sub, (int64_t)DIAG_SUB * 8 * n_inst);
         add(D.res, (int64_t)n_inst * RES_SUB * (int64_t)(sizeof(Resid) / 8));   // sweep 0's residual slots
         // a temperature-dependent opacity: the step's tables at its T^n
-        if (K.t_power != 0.0) launch_tables(D, K, st);
+        if (K.t_power != 0.0 || K.stim) launch_tables(D, K, st);
         launch_count_scan(D, K, z, part, st);
         launch_sample(dim, D, K, view(cur_mv, cur_st), st);
     }
@@ -1356,7 +1357,7 @@ uint64_t state_layout(const ugkwp_ctx* c)
     f.add(c->n_inst);
     f.add(c->K.c); f.add(c->K.a); f.add(c->K.eps); f.add(c->K.dt); f.add(c->K.nu_power);
     f.add(c->K.flags);
-    f.add(c->K.tau_C); f.add(c->K.tau_jump); f.add(c->K.t_power);
+    f.add(c->K.tau_C); f.add(c->K.tau_jump); f.add(c->K.t_power); f.add(c->K.stim);
     for (const HostInst& h : c->hi) {
         f.add(h.nx); f.add(h.ny); f.add(h.G);
         f.add(h.x0); f.add(h.x1); f.add(h.y0); f.add(h.y1);
@@ -1409,7 +1410,7 @@ int ugkwp_create(ugkwp_ctx** out, const ugkwp_params* p, void* hip_stream)
         !(p->si_tol >= 0) || p->si_max_iters < 1 || p->pool_capacity < 0 || p->n_cap < 0 ||
         p->n_cap > (1 << 30) || !(p->nu_power >= 0) || p->sort_interval < 0 ||
         !(p->tau_num_C >= 0) || !std::isfinite(p->tau_num_C) || !(p->tau_num_jump >= 0) ||
-        !std::isfinite(p->opacity_T_power))
+        !std::isfinite(p->opacity_T_power) || (p->opacity_stim != 0 && p->opacity_stim != 1))
         return UGKWP_EINVAL;
     ugkwp_ctx* c = new (std::nothrow) ugkwp_ctx();
     if (!c) return UGKWP_ENOMEM;
@@ -1531,7 +1532,7 @@ int ugkwp_record(ugkwp_ctx* ctx, int max_steps)
         if (max_steps > 0) require_ready(ctx);
         if (max_steps > 0 && ctx->P.tau_num_C > 0)
             fail(UGKWP_EINVAL, "the adjoint does not cover the numerical collision time of joint cells (tau_num_C > 0)");
-        if (max_steps > 0 && ctx->P.opacity_T_power != 0)
+        if (max_steps > 0 && (ctx->P.opacity_T_power != 0 || ctx->P.opacity_stim))
             fail(UGKWP_EINVAL, "the adjoint does not cover a temperature-dependent opacity");
         ctx->record_start(max_steps);
     });

@@ -47,7 +47,8 @@ class Params(C.Structure):
     _fields_ = [("c", _d), ("a", _d), ("eps", _d), ("dt", _d), ("nu_power", _d),
                 ("n_cap", C.c_int64), ("pool_capacity", C.c_int64), ("si_max_iters", C.c_int),
                 ("si_tol", _d), ("flags", C.c_uint32), ("sort_interval", C.c_int),
-                ("tau_num_C", _d), ("tau_num_jump", _d), ("opacity_T_power", _d)]
+                ("tau_num_C", _d), ("tau_num_jump", _d), ("opacity_T_power", _d),
+                ("opacity_stim", C.c_int32)]
 
 
 class Instance(C.Structure):
@@ -354,11 +355,12 @@ class Context:
 
 def make_params(c=1.0, a=1.0, eps=1.0, dt=1e-3, nu_power=3.0, n_cap=1 << 20, pool_capacity=1 << 20,
                 si_max_iters=200, si_tol=1e-13, flags=0, sort_interval=0, tau_num_C=0.0,
-                tau_num_jump=10.0, opacity_T_power=0.0) -> Params:
+                tau_num_jump=10.0, opacity_T_power=0.0, opacity_stim=0) -> Params:
     p = Params()
     p.sort_interval = sort_interval
     p.tau_num_C, p.tau_num_jump = tau_num_C, tau_num_jump
     p.opacity_T_power = opacity_T_power
+    p.opacity_stim = opacity_stim
     p.c, p.a, p.eps, p.dt, p.nu_power = c, a, eps, dt, nu_power
     p.n_cap, p.pool_capacity, p.si_max_iters, p.si_tol, p.flags = n_cap, pool_capacity, si_max_iters, si_tol, flags
     return p
@@ -371,7 +373,7 @@ def from_problem(prob, stream=None, pool_capacity: Optional[int] = None, sort_in
                     n_cap=prob.n_cap, pool_capacity=pool_capacity or prob.pool_cap,
                     si_max_iters=prob.si_max_iters, si_tol=prob.si_tol, flags=prob.flags | extra_flags,
                     sort_interval=sort_interval, tau_num_C=prob.tau_num_C, tau_num_jump=prob.tau_num_jump,
-                    opacity_T_power=prob.T_power)
+                    opacity_T_power=prob.T_power, opacity_stim=prob.opacity_stim)
     ctx = Context(P, stream)
     ctx.init_mesh(prob.dim, prob.nx, prob.ny, [prob.x0, prob.y0], [prob.x1, prob.y1], prob.bc, prob.bcT,
                   prob.nu_edges, prob.seed, prob.w_ref)
@@ -382,13 +384,22 @@ def from_problem(prob, stream=None, pool_capacity: Optional[int] = None, sort_in
 
 def from_batch(probs, stream=None, pool_capacity: Optional[int] = None, sort_interval: int = 0,
                extra_flags: int = 0) -> Context:
-    """Build a batched context from a list of workloads.Problem (same dim, c, a, eps, dt)."""
+    """Build a batched context from a list of workloads.Problem.  The parameters
+    a context shares (dimension, c, a, eps, dt, opacity law, flags, iteration
+    limits, tau_num) must agree across the list: ValueError otherwise."""
     p0 = probs[0]
+    shared = ("dim", "c", "a", "eps", "dt", "nu_power", "n_cap", "si_max_iters", "si_tol", "flags",
+              "tau_num_C", "tau_num_jump", "T_power", "opacity_stim")
+    for k, pr in enumerate(probs):
+        diff = [f for f in shared if getattr(pr, f) != getattr(p0, f)]
+        if diff:
+            raise ValueError(f"instance {k} differs from instance 0 in the shared parameters {diff}")
     cap = pool_capacity or sum(p.pool_cap for p in probs)
     P = make_params(c=p0.c, a=p0.a, eps=p0.eps, dt=p0.dt, nu_power=p0.nu_power, n_cap=p0.n_cap,
                     pool_capacity=cap, si_max_iters=p0.si_max_iters, si_tol=p0.si_tol,
                     flags=p0.flags | extra_flags, sort_interval=sort_interval, tau_num_C=p0.tau_num_C,
-                    tau_num_jump=p0.tau_num_jump, opacity_T_power=p0.T_power)
+                    tau_num_jump=p0.tau_num_jump, opacity_T_power=p0.T_power,
+                    opacity_stim=p0.opacity_stim)
     ctx = Context(P, stream)
     keep = []
     insts = []

@@ -52,3 +52,14 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(ugkwp, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         ugkwp.load()
+
+
+def test_batch_rejects_instances_that_differ_in_shared_parameters():
+    """A context shares dt, the opacity law and the flags: a batch whose
+    instances differ there is refused before any device call."""
+    from paper_2312_16981_amd import ugkwp, workloads as W
+    probs = [W.larsen(nx=40), W.larsen(nx=60)]             # dt = dx / c differs
+    with pytest.raises(ValueError, match="dt"):
+        ugkwp.from_batch(probs)
+    with pytest.raises(ValueError, match="opacity_stim"):
+        ugkwp.from_batch([W.larsen(nx=40), W.larsen(nx=40, opacity_stim=0)])

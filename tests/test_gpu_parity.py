@@ -590,3 +590,39 @@ def test_linearized_iteration_batch():
             s.step(1)
     for k, (p, s) in enumerate(zip(probs, sims)):
         compare_state(ctx, s, p, inst=k, what=f"linearized instance {k}")
+
+
+def _hot(stim=1, **kw):
+    p = dict(dt=2e-3, steps=0, w_ref=2e-5, pool_cap=1 << 20, name="hot_stim", T0=0.5, Tb=1.0,
+             opacity_stim=stim)
+    p.update(kw)
+    return W.slab(50, 8, lambda x: np.full_like(x, 5.0), **p)
+
+
+def test_stimulated_emission_factor_slab_and_group_opacity():
+    run_pair(_hot(), 8)                                   # per-particle factor in the push
+    run_pair(_hot(flags=W.FLAG_GROUP_SIGMA), 8)           # group factor folded into the tables
+    run_pair(_hot(T_power=0.5, bc_right=W.BC_REFLECT), 6)
+
+
+def test_stimulated_emission_factor_2d_and_larsen():
+    run_pair(W.c5_lognormal(n=20, G=5, dt=2e-2).with_(opacity_stim=1, T0=np.full(400, 0.3)), 5)
+    run_pair(W.larsen(nx=80, G=8, w_ref=2e-4, pool_cap=1 << 21, linearized=False), 12)
+    run_pair(W.larsen(nx=80, G=8, w_ref=2e-4, pool_cap=1 << 21, linearized=True), 12)
+
+
+def test_stimulated_emission_factor_batch_and_refused_record():
+    probs = [W.larsen(nx=40 + 20 * k, G=4 + 2 * k, w_ref=2e-4, pool_cap=1 << 21, linearized=True, dt=0.05).with_(seed=600 + k)
+             for k in range(3)]
+    ctx = ugkwp.from_batch(probs)
+    sims = [oracle.Sim(p) for p in probs]
+    for n in range(6):
+        ctx.step(1)
+        for s in sims:
+            s.step(1)
+    for k, (p, s) in enumerate(zip(probs, sims)):
+        compare_state(ctx, s, p, inst=k, what=f"stimulated-emission instance {k}")
+    ctx = ugkwp.from_problem(_hot())
+    with pytest.raises(ugkwp.UGKWPError) as e:
+        ctx.record(4)
+    assert e.value.code == ugkwp.EINVAL
