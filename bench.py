@@ -48,8 +48,8 @@ SI_SWEEP_BYTES = 64        # Q, lambda, sigma, phi^k, rho^k, one face D read; rh
 # to those sources makes bench.py report the traffic as unknown.
 PUSH_SOURCES = ("kernels.hip", "device_math.hpp", "device_common.hpp", "common.hpp")
 PUSH_TRAFFIC = {
-    "slab": {"sources": "f50d4e74a195e5fb", "read_per_push": 49.46, "write_per_push": 12.97},
-    "lattice": {"sources": "f50d4e74a195e5fb", "read_per_push": 67.22, "write_per_push": 22.05},
+    "slab": {"sources": "a77b237b0f30d25c", "read_per_push": 49.46, "write_per_push": 12.98},
+    "lattice": {"sources": "a77b237b0f30d25c", "read_per_push": 67.25, "write_per_push": 22.05},
 }
 
 
