@@ -165,3 +165,13 @@ def test_torch_autograd_binding():
     assert relerr(kappa.grad.cpu().numpy(), o) <= TOL
     T = sim.fields()[1]
     assert abs(J.item() - float(np.sum(cell_volume(p) * p.cv * T))) <= 1e-10 * abs(J.item())
+
+
+def test_adjoint_of_a_linearized_run_matches_oracle():
+    """Recording works with the linearized source iteration (the adjoint
+    differentiates the fixed point both iterations share)."""
+    make, nsteps = CASES["lognormal"]
+    p = make()
+    p = p.with_(flags=p.flags | W.FLAG_SI_LINEARIZED)
+    _, g, o = pair(p, nsteps, cell_volume(p) * p.cv)
+    assert relerr(g, o) <= TOL

@@ -83,3 +83,20 @@ def test_energy_conservation():
         s.step(1)
         d = s.diag()
         assert abs(d["residual"]) <= 1e-12 * abs(d["e_end"]), n
+
+
+def test_adjoint_of_a_linearized_run_matches_the_literal_one():
+    """The adjoint differentiates the fixed point, which both iterations share:
+    recording a run made with the linearized sweep gives the literal run's
+    gradient (to the iterations' tolerance)."""
+    p = W.c5_lognormal(n=10, G=4, w_ref=2e-4, pool_cap=1 << 20, dt=2e-3)
+    V = (p.x1 - p.x0) / p.nx * (p.y1 - p.y0) / p.ny
+    grads = []
+    for fl in (0, LIN):
+        s = oracle.Sim(p.with_(flags=fl))
+        s.record(True)
+        s.step(6)
+        grads.append(s.adjoint(V * p.cv))
+    ga, gb = grads
+    assert np.abs(ga).max() > 0
+    np.testing.assert_allclose(gb, ga, rtol=1e-8, atol=1e-10 * np.abs(ga).max())
