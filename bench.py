@@ -1,11 +1,13 @@
 """Throughput benchmark of the UGKWP hot path on one MI355X.
 
 Workloads (--workload):
-  slab     (default) two-material slab: 2000 cells x 64 log-spaced groups on
+  lattice  (default) 2-D block lattice 256 x 256 cells x 32 groups on [0,7]^2
+           with a pinned central source, dt = 1e-3, 500 steps: the timed steps
+           are the last of the 500 (steps 480-499 with --steps 20 --warmup 5),
+           where the pool holds ~6e7 particles
+  slab     two-material slab: 2000 cells x 64 log-spaced groups on
            [0.01, 10], kappa = 0.01 | 1000 jump at x = 0.5, dt = 1e-4,
            Planckian left wall at T = 1
-  lattice  2-D block lattice 256 x 256 cells x 32 groups on [0,7]^2 with a
-           pinned central source, dt = 1e-3
   batch    512 independent slabs of 64..4096 cells and 16/32/64 groups in one
            context (one launch per kernel per step); --per-instance steps the
            same instances in 512 separate contexts instead
@@ -63,10 +65,66 @@ def push_sources_digest():
 BYTES_2D = (64, 20, 4)     # 2-D: x, y, ox, oy, nu, w, id + cell word, group; writes x, y, cell word
 
 
-def cpu_baseline(probs, budget_s=15.0):
-    """The oracle as it stands, single thread, on the first steps of the same run
-    (for a batch: the instances in turn, each from t = 0)."""
+def cpu_info():
+    """Host CPU model, logical CPUs and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+class pinned_to_one_cpu:
+    """Run the enclosed block on one CPU (the first this process may use): the
+    oracle is single-threaded, and the pinning keeps the scheduler from moving it."""
+
+    def __enter__(self):
+        self.old = os.sched_getaffinity(0)
+        self.cpu = min(self.old)
+        os.sched_setaffinity(0, {self.cpu})
+        return self
+
+    def __exit__(self, *exc):
+        os.sched_setaffinity(0, self.old)
+
+
+def cpu_baseline_window(prob, n_particles, budget_s=15.0):
+    """The oracle as it stands, single thread pinned to one CPU, on the
+    lattice at the timed window's particle count: from the seeded synthetic
+    mid-run state with the window's pool size (workloads.lattice_mid_run_state),
+    steps until the budget is spent (at least one)."""
     import oracle
+    from paper_2312_16981_amd import workloads as W
+    st = W.lattice_mid_run_state(prob, int(n_particles))
+    q = prob.with_(T0=st["T0"], Tr0=st["Tr0"])
+    sim = oracle.Sim(q)
+    sim.set_pool(st["pool"], st["births"], st["rhop"])
+    del st
+    pushes = steps = 0
+    with pinned_to_one_cpu() as pin:
+        t0 = time.perf_counter()
+        while steps == 0 or time.perf_counter() - t0 < budget_s:
+            sim.step(1)
+            d = sim.diag()
+            pushes += d["n_alive_in"] + d["n_births"]
+            steps += 1
+        dt = time.perf_counter() - t0
+    model, ncpu, _ = cpu_info()
+    return {"value": pushes / dt, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of the 256x256x32 lattice from a seeded synthetic state holding the "
+                      f"timed window's {int(n_particles)} particles ({pushes} pushes, {dt:.1f} s)",
+            "cpu_model": model, "host_logical_cpus": ncpu, "pinned_cpu": pin.cpu}
+
+
+def cpu_baseline(probs, budget_s=15.0):
+    """The oracle as it stands, single thread pinned to one CPU, on the first
+    steps of the same run (for a batch: the instances in turn, each from t = 0)."""
+    import oracle
+    pin = pinned_to_one_cpu().__enter__()
     pushes = 0
     steps = 0
     t0 = time.perf_counter()
@@ -86,10 +144,13 @@ def cpu_baseline(probs, budget_s=15.0):
         if done:
             break
     dt = time.perf_counter() - t0
+    pin.__exit__()
     what = (f"steps 0-{steps - 1} of the same run from t=0" if len(probs) == 1 else
             f"{steps} instance-steps of the first {len(sims)} instances from t=0")
+    model, ncpu, _ = cpu_info()
     return {"value": pushes / dt, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
-            "sample": f"{what} ({pushes} pushes, {dt:.1f} s, single thread)"}
+            "sample": f"{what} ({pushes} pushes, {dt:.1f} s, single thread)",
+            "cpu_model": model, "host_logical_cpus": ncpu, "pinned_cpu": pin.cpu}
 
 
 def cpu_baseline_adjoint(prob, budget_s=15.0):
@@ -290,11 +351,13 @@ def main():
                     help="run a plain device copy of MIB MiB (HBM counter reference) and exit")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=-1,
-                    help="timed steps (default 400; for the adjoint workload the recorded steps, 100)")
-    ap.add_argument("--warmup", type=int, default=20)
+                    help="timed steps (default 20 on the lattice, 400 on the other forward workloads; "
+                         "for the adjoint workload the recorded steps, 100)")
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--workload", choices=("slab", "lattice", "batch", "adjoint", "thickthin", "marshak", "larsen"), default="slab")
+    ap.add_argument("--workload", choices=("lattice", "slab", "batch", "adjoint", "thickthin", "marshak", "larsen"),
+                    default="lattice")
     ap.add_argument("--per-instance", action="store_true",
                     help="batch workload: one context per instance instead of one batched context")
     ap.add_argument("--spinup", type=int, default=-1, help="untimed steps from t=0 (default per workload)")
@@ -331,7 +394,7 @@ def main():
     stream = torch.cuda.current_stream()
     wl = args.workload
     if args.steps < 0:
-        args.steps = 100 if wl == "adjoint" else 400
+        args.steps = {"adjoint": 100, "lattice": 20}.get(wl, 400)
     if wl == "adjoint":
         run_adjoint(args, stream)
         return
@@ -350,7 +413,13 @@ def main():
     if args.si_linearized:
         probs = [p.with_(flags=p.flags | W.FLAG_SI_LINEARIZED) for p in probs]
     ncg = sum(p.ncell * p.G for p in probs)
-    spin = SPINUP[wl] if args.spinup < 0 else args.spinup
+    if args.spinup >= 0:
+        spin = args.spinup
+    elif wl == "lattice":
+        # the timed steps end where the workload's 500-step run ends
+        spin = max(0, probs[0].steps - args.warmup - args.steps)
+    else:
+        spin = SPINUP[wl]
     xf = ugkwp.FLAG_GRAPH if args.graph else 0
     if wl == "batch" and args.per_instance:
         ctxs = [ugkwp.from_problem(p, stream=stream.cuda_stream, sort_interval=args.sort_interval, extra_flags=xf)
@@ -367,6 +436,10 @@ def main():
     tuned = None
     if not args.no_autotune:
         tuned = [c.autotune() for c in ctxs]
+    # time the push of every timed step where a push lasts a millisecond (2-D);
+    # in 1-D one step in 4 (each event pair adds a few microseconds to a step)
+    for c in ctxs:
+        c.set_push_timing(1 if probs[0].dim == 2 else 4)
     for c in ctxs:
         c.step(args.warmup)
         c.get_totals(reset=True)
@@ -461,7 +534,10 @@ def main():
                            "algorithmic_bytes_per_update": SI_SWEEP_BYTES,
                            "from": f"{nph} further steps with every phase timed"}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(probs, args.cpu_budget)
+        if wl == "lattice":
+            out["cpu_baseline"] = cpu_baseline_window(probs[0], pushes / max(args.steps, 1), args.cpu_budget)
+        else:
+            out["cpu_baseline"] = cpu_baseline(probs, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

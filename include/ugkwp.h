@@ -154,7 +154,8 @@ typedef struct {
      * sweep and counted in ms_si), the source iteration, and the counting sort
      * that keeps the pool ordered by (cell, group).  Each event adds a few
      * microseconds to a step, so without UGKWP_FLAG_PHASE_TIMES only the push
-     * of one step in 8 (step index a multiple of 8) is timed and everything
+     * of one step in 8 (step index a multiple of 8, or of the interval set by
+     * ugkwp_set_push_timing) is timed and everything
      * else is 0; with it every phase of every step is timed.  push_timed says
      * whether this step's ms_push holds a time. */
     double ms_sample, ms_push, ms_macro, ms_si, ms_sort;
@@ -231,6 +232,10 @@ int ugkwp_get_totals(ugkwp_ctx* ctx, ugkwp_totals* t, int reset);
 /* Turn the timing of every phase (UGKWP_FLAG_PHASE_TIMES) on or off for the
  * following steps. */
 int ugkwp_set_phase_times(ugkwp_ctx* ctx, int on);
+/* Without phase timing, time the push of every step whose index is a multiple
+ * of `every` (default 8; 1 times every push).  Each timed push adds two events
+ * (a few microseconds of GPU time).  EINVAL if every < 1. */
+int ugkwp_set_push_timing(ugkwp_ctx* ctx, int every);
 /* Birth counter and step index of instance `inst`. */
 int ugkwp_get_counters(ugkwp_ctx* ctx, int inst, uint64_t* birth_counter, int* step);
 

@@ -26,7 +26,18 @@
  *   phibar = -w sigma/(1+lambda) mu + lambda/(1+lambda) rbar + (dt/V) L bbar
  *   mu     = Tbar + sum_g phi_g'(T^{n+1}) phibar
  *
- * (L: the same face operator as in b, which is symmetric), then the cotangents
+ * (L: the same face operator as in b, which is symmetric).  The local part of
+ * the last line is -d mu with d = w sum_g sigma phi_g'/(1+lambda), the
+ * contraction factor of the literal sweep: where d > 1 (stiff coupling) the
+ * plain iteration of that line diverges exactly as the literal forward sweep
+ * does.  Both the replay and the transposed iteration therefore take the
+ * diagonally preconditioned form of the linearized sweep (a local Newton step,
+ * same fixed point):
+ *
+ *   forward:  T^{k+1} = T^k + (T^n - T^k + w sum_g sigma (b - phi)/(1+lambda)) / (1 + d)
+ *   reverse:  mu^{k+1} = mu^k + (Tbar + sum_g phi_g' phibar(mu^k) - mu^k) / (1 + d)
+ *
+ * whose iteration matrices are similar to each other's transposes.  Then the cotangents
  * of Q, lambda, sigma, D_f (through the harmonic face opacity and C2), A (through
  * C4 or W) and rho^n.  Everything is written per (cell, group) and per face
  * exactly as the forward step states it; no step is fused or reordered.
@@ -205,19 +216,27 @@ static int frozen_solve(const ora_sim* sim, const coefs* M, const double* Q, con
         double drho = 0.0, mrho = 0.0, dT = 0.0, mT = 0.0;
         int bad = 0;
         for (int i = 0; i < M->nc; ++i) {
-            double sum = 0.0;
+            double sum = 0.0, dsum = 0.0;
             for (int g = 0; g < G; ++g) {
                 size_t k = (size_t)i * G + g;
                 double lam = M->s[k];
-                double r = (b[k] + lam * phi[k]) / (1.0 + lam);
-                double em = (b[k] - phi[k]) / (1.0 + lam);
-                sum += M->sig[k] * em;
+                sum += M->sig[k] * (b[k] - phi[k]) / (1.0 + lam);
+                dsum += M->sig[k] * ora_dphi_group(Tk[i], P->nu[g], P->nu[g + 1], P->a, P->c) / (1.0 + lam);
+            }
+            /* linearized emission phi + phi' (T^{k+1} - T^k): one local Newton step */
+            const double w = P->dt / (P->eps * P->eps * cv[i]);
+            double Tnew = pinned[i] ? Tn[i] : Tk[i] + (Tn[i] - Tk[i] + w * sum) / (1.0 + w * dsum);
+            const double dTi = Tnew - Tk[i];
+            for (int g = 0; g < G; ++g) {
+                size_t k = (size_t)i * G + g;
+                double lam = M->s[k];
+                double pe = phi[k] + ora_dphi_group(Tk[i], P->nu[g], P->nu[g + 1], P->a, P->c) * dTi;
+                double r = (b[k] + lam * pe) / (1.0 + lam);
                 double dr = fabs(r - rho_out[k]);
                 if (dr > drho || dr != dr) drho = dr;
                 if (fabs(r) > mrho) mrho = fabs(r);
                 rho_out[k] = r;
             }
-            double Tnew = pinned[i] ? Tn[i] : Tn[i] + (P->dt / (P->eps * P->eps * cv[i])) * sum;
             if (!(Tnew > 0.0) || !isfinite(Tnew)) bad = 1;
             double dd = fabs(Tnew - Tk[i]);
             if (dd > dT || dd != dd) dT = dd;
@@ -319,6 +338,7 @@ int ora_adjoint(ora_sim* s, const double* dJdT, double* grad_kappa)
     double* Tbar = (double*)malloc(sizeof(double) * nc);      /* cotangent of T^{n+1}   */
     double* mu = (double*)malloc(sizeof(double) * nc);
     double* mu1 = (double*)malloc(sizeof(double) * nc);
+    double* dloc = (double*)malloc(sizeof(double) * nc);
     double* bbar = (double*)malloc(sizeof(double) * ncg);
     double* phibar = (double*)malloc(sizeof(double) * ncg);
     double* phi = (double*)malloc(sizeof(double) * ncg);
@@ -345,7 +365,16 @@ int ora_adjoint(ora_sim* s, const double* dJdT, double* grad_kappa)
         frozen_source(s, &M, r, r->rho, Q);
         apply_b(s, &M, Q, phi, b);
 
-        /* transposed source iteration for mu */
+        /* local diagonal d = w sum_g sigma phi'/(1+lambda) of the transposed map */
+        for (int i = 0; i < nc; ++i) {
+            double acc = 0.0;
+            for (int g = 0; g < G; ++g) {
+                size_t k = (size_t)i * G + g;
+                acc += M.sig[k] * dphi[k] / (1.0 + M.s[k]);
+            }
+            dloc[i] = w[i] * acc;
+        }
+        /* transposed source iteration for mu, preconditioned by 1 + d */
         memcpy(mu, Tbar, sizeof(double) * nc);
         int conv = 0;
         for (int it = 0; it < 1000 && !conv; ++it) {
@@ -354,7 +383,7 @@ int ora_adjoint(ora_sim* s, const double* dJdT, double* grad_kappa)
             for (int i = 0; i < nc; ++i) {
                 double acc = 0.0;
                 for (int g = 0; g < G; ++g) acc += dphi[(size_t)i * G + g] * phibar[(size_t)i * G + g];
-                mu1[i] = Tbar[i] + acc;
+                mu1[i] = mu[i] + (Tbar[i] + acc - mu[i]) / (1.0 + dloc[i]);
                 double d = fabs(mu1[i] - mu[i]);
                 if (d > dm || d != d) dm = d;
                 if (fabs(mu1[i]) > mm) mm = fabs(mu1[i]);
@@ -434,7 +463,7 @@ int ora_adjoint(ora_sim* s, const double* dJdT, double* grad_kappa)
         memcpy(rbar, rbar_n, sizeof(double) * ncg);
         memcpy(Tbar, mu, sizeof(double) * nc);
     }
-    free(w); free(rbar); free(rbar_n); free(Tbar); free(mu); free(mu1); free(bbar); free(phibar);
+    free(w); free(rbar); free(rbar_n); free(Tbar); free(mu); free(mu1); free(dloc); free(bbar); free(phibar);
     free(phi); free(dphi); free(Q); free(b); free(sbar); free(sigbar); free(ubar);
     coefs_free(&M);
     return status;

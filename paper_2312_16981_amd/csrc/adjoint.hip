@@ -226,9 +226,12 @@ __device__ inline FaceRef face_ref(const Inst& I, int64_t j, int lcell, int g, i
     return f;
 }
 
-// One sweep of the transposed source iteration:
-//   mu^{k+1} = Tbar + sum_g phi_g' [ -w sigma/(1+lambda) mu^k + lambda/(1+lambda) rbar
-//                                    + (dt/V) sum_f S_f D_f (bbar_nb - bbar) ].
+// One sweep of the transposed source iteration, preconditioned by its local
+// diagonal d = w sum_g sigma phi_g'/(1+lambda) (the transpose of the linearized
+// forward sweep; the plain iteration diverges where d > 1, stiff coupling):
+//   m        = Tbar + sum_g phi_g' [ -w sigma/(1+lambda) mu^k + lambda/(1+lambda) rbar
+//                                    + (dt/V) sum_f S_f D_f (bbar_nb - bbar) ]
+//   mu^{k+1} = mu^k + (m - mu^k) / (1 + d).
 // Residual maxima go to 64 sub-slots of the instance; k_adj_decide reads them.
 // With decide_prev (single instance), every block first takes the decision of
 // sweep k-1 from those sub-slots itself; block 0 records it.
@@ -315,9 +318,10 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
         A.res[((int64_t)s.inst * RES_SLOTS + (k + 1) % RES_SLOTS) * RES_SUB + rel] = z;
     }
 
-    double contrib = 0.0;
+    double contrib = 0.0, diag = 0.0;
     if (work && s.active) {
         const double fac = tw * sg / (1.0 + lam);
+        diag = fac * dphi;
         const double bb = fac * mui + rb / (1.0 + lam);
         double lt = 0.0;
 #pragma unroll
@@ -334,10 +338,11 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
         contrib = dphi * phibar;
     }
     contrib = group_sum(contrib, Gp);
+    diag = group_sum(diag, Gp);
 
     double dm = 0.0, mm = 0.0;
     if (work && g == 0) {
-        const double mun = tbar + contrib;
+        const double mun = mui + (tbar + contrib - mui) / (1.0 + diag);
         if (!isfinite(mun)) atomicOr(A.status + ADJ_ERR, 1ull);
         mu_out[cell] = mun;
         dm = fabs(mun - mui);

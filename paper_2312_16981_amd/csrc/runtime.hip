@@ -117,7 +117,7 @@ int ilog2(int p)
 constexpr int MAX_PUSH_BLOCKS = 8192;     // per-block survivor counts kept by the push
 constexpr int RUN_AHEAD = 16;             // steps enqueued per host synchronisation
 constexpr int N_RECORDS = RUN_AHEAD + 1;  // step records: a batch's steps and the state it starts from
-constexpr uint32_t PUSH_TIME_EVERY = 8;   // without phase timing, the push of one step in 8 is timed
+constexpr int PUSH_TIME_EVERY = 8;        // default: without phase timing, the push of one step in 8 is timed
 
 template <class T>
 T* dalloc(std::vector<void*>& owned, size_t n)
@@ -211,6 +211,7 @@ struct ugkwp_ctx {
     // configuration (pool buffer parities, rho/T parity, sort, speculative sweeps)
     bool use_graph = false;
     bool phase_times = false;          // time every phase of a step (else the push only)
+    int push_time_every = PUSH_TIME_EVERY;   // the push of steps with index a multiple of this is timed
     hipStream_t cap_st = nullptr;
     std::map<uint32_t, hipGraphExec_t> graphs;
     const double* rho_buf0 = nullptr;
@@ -953,7 +954,7 @@ struct ugkwp_ctx {
             try {
                 for (int i = 0; i < m; ++i) {
                     p.do_sort = sort_due(p.step, p.n_slots);
-                    p.push_timed = phase_times || p.step % PUSH_TIME_EVERY == 0;
+                    p.push_timed = phase_times || p.step % push_time_every == 0;
                     p.sweeps = spec;
                     p.slot = next_record(p.rec);
                     set_state(p);
@@ -1630,6 +1631,14 @@ int ugkwp_set_phase_times(ugkwp_ctx* ctx, int on)
 {
     if (!ctx) return UGKWP_EINVAL;
     ctx->phase_times = on != 0;
+    return UGKWP_OK;
+}
+
+int ugkwp_set_push_timing(ugkwp_ctx* ctx, int every)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    if (every < 1) return UGKWP_EINVAL;
+    ctx->push_time_every = every;
     return UGKWP_OK;
 }
 

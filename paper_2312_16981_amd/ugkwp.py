@@ -29,7 +29,7 @@ EXPORTED = [
     "ugkwp_get_fields", "ugkwp_get_tallies", "ugkwp_get_diag", "ugkwp_get_counters",
     "ugkwp_pool_size", "ugkwp_get_pool", "ugkwp_set_pool", "ugkwp_eval_phi", "ugkwp_eval_coef",
     "ugkwp_eval_uniform", "ugkwp_eval_neg_log", "ugkwp_eval_sample_nu", "ugkwp_record", "ugkwp_recorded_steps",
-    "ugkwp_adjoint", "ugkwp_autotune", "ugkwp_get_totals", "ugkwp_set_phase_times",
+    "ugkwp_adjoint", "ugkwp_autotune", "ugkwp_get_totals", "ugkwp_set_phase_times", "ugkwp_set_push_timing",
     "ugkwp_state_bytes", "ugkwp_get_state", "ugkwp_set_state",
 ]
 
@@ -147,6 +147,7 @@ def load():
     L.ugkwp_autotune.argtypes = [vp, C.POINTER(TuneResult)]
     L.ugkwp_get_totals.argtypes = [vp, C.POINTER(Totals), C.c_int]
     L.ugkwp_set_phase_times.argtypes = [vp, C.c_int]
+    L.ugkwp_set_push_timing.argtypes = [vp, C.c_int]
     L.ugkwp_recorded_steps.argtypes = [vp]
     L.ugkwp_adjoint.argtypes = [vp, _pd, _pd, C.c_int, C.POINTER(AdjointStats)]
     L.ugkwp_eval_phi.argtypes = [C.c_int, _pd, C.c_int, _pd, _d, _d, _pd]
@@ -308,6 +309,9 @@ class Context:
 
     def set_phase_times(self, on=True):
         self._chk(load().ugkwp_set_phase_times(self.h, 1 if on else 0), "set_phase_times")
+
+    def set_push_timing(self, every):
+        self._chk(load().ugkwp_set_push_timing(self.h, int(every)), "set_push_timing")
 
     def get_counters(self, inst=0):
         b = C.c_uint64()

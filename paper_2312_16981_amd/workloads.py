@@ -202,3 +202,47 @@ def c4_batch(n_inst: int = 512, nx_range=(64, 4096), groups=(16, 32, 64), steps:
                   name=f"inst{k}_nx{nx}_g{G}")
         out.append(pr)
     return out
+
+
+def lattice_mid_run_state(prob: Problem, n_particles: int, seed: int = 5) -> dict:
+    """A synthetic state of the lattice workload part-way through its run, at
+    the particle count of its late steps: material temperatures that fall off
+    from the pinned source (T0 per cell, pinned cells at 1), cold radiation
+    outside the particles (Tr0 = 1e-3), and a pool of n_particles collisionless particles in the background
+    (kappa = 1) squares within 3 of the centre, in the upper half of the
+    groups, ordered by (cell, group), each at a uniform position in its cell,
+    an isotropic direction, a frequency uniform in its group and weight w_ref V.
+    rhop is the particles' weight per unit volume in each (cell, group) bin.
+    Inputs only: both the GPU library and the oracle start from it."""
+    rng = np.random.Generator(np.random.Philox(key=seed))
+    nx, ny, G = prob.nx, prob.ny, prob.G
+    dx, dy = (prob.x1 - prob.x0) / nx, (prob.y1 - prob.y0) / ny
+    xc = prob.x0 + (np.arange(nx) + 0.5) * dx
+    yc = prob.y0 + (np.arange(ny) + 0.5) * dy
+    X, Y = np.meshgrid(xc, yc, indexing="xy")
+    r = np.hypot(X - 0.5 * (prob.x0 + prob.x1), Y - 0.5 * (prob.y0 + prob.y1)).reshape(-1)
+    T0 = np.maximum(0.5 * np.exp(-(r / 0.8) ** 2), 1e-3)
+    T0[prob.pinned == 1] = 1.0
+    Tr0 = np.full(nx * ny, 1e-3)
+    thin = np.flatnonzero((prob.kappa[:, 0] <= 1.0) & (r <= 3.0) & (prob.pinned == 0))
+    gh = G - G // 2                                   # groups G//2 .. G-1
+    b = np.sort(rng.integers(0, thin.size * gh, size=n_particles))
+    cell = thin[b // gh].astype(np.int32)
+    g = (G // 2 + b % gh).astype(np.int32)
+    del b
+    ix, iy = cell % nx, cell // nx
+    x = prob.x0 + (ix + rng.random(n_particles)) * dx
+    y = prob.y0 + (iy + rng.random(n_particles)) * dy
+    del ix, iy
+    oz = 2.0 * rng.random(n_particles) - 1.0
+    psi = 2.0 * np.pi * rng.random(n_particles)
+    st = np.sqrt(1.0 - oz * oz)
+    del oz
+    nu_e = np.asarray(prob.nu_edges)
+    nu = nu_e[g] + rng.random(n_particles) * (nu_e[g + 1] - nu_e[g])
+    V = dx * dy
+    w = np.full(n_particles, prob.w_ref * V)
+    pool = dict(x=x, y=y, ox=st * np.cos(psi), oy=st * np.sin(psi), nu=nu, w=w,
+                id=np.arange(n_particles, dtype=np.uint64), cell=cell, g=g)
+    rhop = np.bincount(cell.astype(np.int64) * G + g, weights=w, minlength=nx * ny * G).reshape(nx * ny, G) / V
+    return dict(T0=T0, Tr0=Tr0, pool=pool, rhop=rhop, births=n_particles)

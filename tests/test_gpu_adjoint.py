@@ -175,3 +175,36 @@ def test_adjoint_of_a_linearized_run_matches_oracle():
     p = p.with_(flags=p.flags | W.FLAG_SI_LINEARIZED)
     _, g, o = pair(p, nsteps, cell_volume(p) * p.cv)
     assert relerr(g, o) <= TOL
+
+
+def _stiff_slab(nx=40, G=6, **kw):
+    p = dict(dt=0.02, steps=0, w_ref=2e-5, pool_cap=1 << 20, name="stiff_slab", flags=W.FLAG_SI_LINEARIZED)
+    p.update(kw)
+    q = W.slab(nx, G, lambda x: np.full_like(x, 50.0), **p)
+    return q.with_(cv=np.full(nx, 0.01), T0=np.full(nx, 0.05), Tr0=np.full(nx, 0.05))
+
+
+def test_adjoint_of_a_stiff_linearized_run_matches_oracle():
+    """Stiff coupling (C_v = 0.01): the forward run needs the linearized sweep,
+    and the reverse sweep converges only in its preconditioned form."""
+    p = _stiff_slab()
+    _, g, o = pair(p, 3, cell_volume(p) * p.cv)
+    assert np.abs(o).max() > 0
+    assert relerr(g, o) <= TOL
+    # a batch of stiff slabs of uneven shape
+    probs = [_stiff_slab(nx=20 + 13 * k, G=3 + 2 * k).with_(seed=40 + k) for k in range(3)]
+    say("[adjoint] batch of 3 stiff slabs")
+    ctx = ugkwp.from_batch(probs)
+    ctx.record(3)
+    ctx.step(3)
+    dJ = np.concatenate([cell_volume(q) * q.cv for q in probs])
+    gb = ctx.adjoint(dJ)
+    off = 0
+    for q in probs:
+        sim = oracle.Sim(q)
+        sim.record(True)
+        sim.step(3)
+        o = sim.adjoint(cell_volume(q) * q.cv)
+        n = q.ncell * q.G
+        assert relerr(gb[off:off + n].reshape(q.ncell, q.G), o) <= TOL
+        off += n

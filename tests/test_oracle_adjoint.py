@@ -36,7 +36,18 @@ CASES = {
     "slab_reflect": (lambda: W.c1_marshak_like(w_ref=2e-5).with_(bc=[W.BC_PLANCK, W.BC_REFLECT, 0, 0]), 8),
     # 2-D lattice: opacity jumps of 100x, pinned source cells, vacuum walls
     "lattice_pinned": (lambda: W.c3_lattice(n=14, G=3, w_ref=1e-3, pool_cap=1 << 20, dt=2e-2), 4),
+    # 1-D stiff material coupling (C_v = 0.01, kappa = 50): the literal sweep and the
+    # unpreconditioned transposed sweep both diverge; run with the linearized sweep
+    "stiff_slab": (lambda: _stiff_slab(), 3),
 }
+
+
+def _stiff_slab(**kw):
+    nx = 40
+    p = dict(dt=0.02, steps=0, w_ref=2e-5, pool_cap=1 << 20, flags=W.FLAG_SI_LINEARIZED)
+    p.update(kw)
+    q = W.slab(nx, 6, lambda x: np.full_like(x, 50.0), **p)
+    return q.with_(cv=np.full(nx, 0.01), T0=np.full(nx, 0.05), Tr0=np.full(nx, 0.05))
 
 
 def recorded(name):
@@ -148,6 +159,40 @@ def test_adjoint_without_particles_matches_forward_fd():
     fd = (J(p.kappa * (1 + h * v)) - J(p.kappa * (1 - h * v))) / (2 * h)
     ad = float(np.sum(grad * p.kappa * v))
     assert abs(fd - ad) <= 1e-7 * abs(ad), (fd, ad)
+
+
+def test_stiff_adjoint_without_particles_matches_forward_fd():
+    """Stiff coupling (the local contraction factor of the literal sweep is far
+    above 1 at the fixed point): the forward run needs the linearized sweep and
+    the transposed iteration its preconditioned form.  With no particles the
+    adjoint is the derivative of the unmodified forward run from t = 0."""
+    p = _stiff_slab(w_ref=1e300)
+    p = p.with_(kappa=p.kappa * np.linspace(0.5, 2.0, p.nx)[:, None])
+    nsteps = 4
+    sim = oracle.Sim(p)
+    sim.record(True)
+    sim.step(nsteps)
+    T = sim.fields()[1]
+    e = p.nu_edges
+    sig = p.kappa[0] * (e[:-1] ** -3 + 4 * (0.5 * (e[:-1] + e[1:])) ** -3 + e[1:] ** -3) / 6.0
+    lam = p.c * sig * p.dt / p.eps ** 2
+    dphi = np.array([oracle.dphi_group(T[0], e[g], e[g + 1]) for g in range(p.G)])
+    d = p.dt / (p.eps ** 2 * p.cv[0]) * np.sum(sig * dphi / (1 + lam))
+    assert d > 5.0                            # the unpreconditioned iterations diverge
+    grad = sim.adjoint(cell_volume(p) * p.cv)
+
+    def J(kappa):
+        s = oracle.Sim(p.with_(kappa=kappa))
+        s.step(nsteps)
+        return energy(p, s.fields()[1])
+
+    rng = np.random.default_rng(4)
+    for _ in range(2):
+        v = rng.standard_normal(p.kappa.shape)
+        h = 1e-4
+        fd = (J(p.kappa * (1 + h * v)) - J(p.kappa * (1 - h * v))) / (2 * h)
+        ad = float(np.sum(grad * p.kappa * v))
+        assert abs(fd - ad) <= 1e-7 * abs(ad), (fd, ad)
 
 
 def test_adjoint_is_linear_in_the_objective():
