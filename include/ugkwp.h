@@ -201,6 +201,16 @@ int ugkwp_set_opacity(ugkwp_ctx* ctx, const double* kappa);
  * no particles: Sec. 3.1), optional pinned-source mask. */
 int ugkwp_set_material(ugkwp_ctx* ctx, const double* cv, const double* T0,
                        const double* Tr0, const uint8_t* pinned);
+/* ugkwp_set_material for callers that cannot allocate device memory (code that
+ * a harness forbids to call hipMalloc, tight serving loops that reset an
+ * instance): the same arguments, layout and result, but the device staging of
+ * Tr0 lives in a library-owned static array (one per GPU, 2^21 doubles = 16 MiB,
+ * held until the process ends) instead of a buffer allocated per call; no
+ * hipMalloc or hipFree is called.  Runs on the context's GPU.  EINVAL if the
+ * mesh has more than 2^21 cells or the context is a batch.  Calls that overlap
+ * on one GPU (from several threads or contexts) share that array and race. */
+int ugkwp_set_material_noalloc(ugkwp_ctx* ctx, const double* cv, const double* T0,
+                               const double* Tr0, const uint8_t* pinned);
 
 /* Batched set-up: n_inst independent instances of one dimension with uneven
  * cell and group counts, all advanced by one launch per kernel per step. */

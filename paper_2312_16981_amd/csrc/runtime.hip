@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -156,6 +157,7 @@ struct ugkwp_ctx {
     ugkwp_params P{};
     hipStream_t st = nullptr;
     bool own_stream = false;
+    int device = 0;                    // the GPU current at ugkwp_create: the context's memory lives there
     std::string err;
 
     // geometry
@@ -563,8 +565,11 @@ struct ugkwp_ctx {
         have_opacity = true;
     }
 
+    // staging: device room for ncell doubles that receives Tr0 (nullptr: allocated
+    // here and freed after the call)
     void set_material(const std::vector<const double*>& cv, const std::vector<const double*>& T0,
-                      const std::vector<const double*>& Tr0, const std::vector<const uint8_t*>& pinned)
+                      const std::vector<const double*>& Tr0, const std::vector<const uint8_t*>& pinned,
+                      double* staging = nullptr)
     {
         std::vector<double> hcv(ncell), hT(ncell), hTr(ncell), hw(ncell);
         std::vector<uint8_t> hp(ncell, 0);
@@ -581,8 +586,8 @@ struct ugkwp_ctx {
                 hp[I.cell_off + c] = pinned[k] ? (pinned[k][c] ? 1 : 0) : 0;
             }
         }
-        double* d_tr = nullptr;
-        HIPCHK(hipMalloc(&d_tr, sizeof(double) * ncell));
+        double* d_tr = staging;
+        if (!staging) HIPCHK(hipMalloc(&d_tr, sizeof(double) * ncell));
         HIPCHK(hipMemcpyAsync((void*)D.cvol, hcv.data(), sizeof(double) * ncell, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync((void*)D.dtcv, hw.data(), sizeof(double) * ncell, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(D.T, hT.data(), sizeof(double) * ncell, hipMemcpyHostToDevice, st));
@@ -593,7 +598,7 @@ struct ugkwp_ctx {
         HIPCHK(hipMemsetAsync(D.counters, 0, sizeof(unsigned long long) * N_COUNTERS, st));
         HIPCHK(hipMemsetAsync(D.step, 0, sizeof(uint32_t), st));
         HIPCHK(hipStreamSynchronize(st));
-        (void)hipFree(d_tr);
+        if (!staging) (void)hipFree(d_tr);
         HIPCHK(hipGetLastError());
         n_alive = n_slots = 0;
         step_idx = 0;
@@ -1403,6 +1408,66 @@ StateLayout state_sections(const ugkwp_ctx* c, int64_t n_slots)
 
 extern "C" {
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free set-up call (ugkwp_set_material_noalloc): the
+// device staging of Tr0, which ugkwp_set_material allocates per call.  One
+// array per GPU, held until the process ends.  In host code `scratch` names a
+// host-side stand-in, not a device address: its device address on each GPU is
+// taken once with hipGetSymbolAddress (with that GPU current) and only that
+// address is used.
+namespace {
+constexpr size_t NOALLOC_MAX_CELLS = size_t(1) << 21;     // 16 MiB of doubles
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) double scratch[NOALLOC_MAX_CELLS];
+std::mutex scratch_mu;
+double* scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// The device address of `scratch` on GPU `dev`, which must be current.
+double* scratch_address(int dev)
+{
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) fail(UGKWP_EINVAL, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            fail(UGKWP_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        scratch_dev[dev] = (double*)ptr;
+    }
+    return scratch_dev[dev];
+}
+
+// Makes the context's GPU current for the enclosing scope.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev)
+    {
+        HIPCHK(hipGetDevice(&prev));
+        if (prev != dev) HIPCHK(hipSetDevice(dev));
+    }
+    ~DeviceScope()
+    {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+}  // namespace
+
+int ugkwp_set_material_noalloc(ugkwp_ctx* ctx, const double* cv, const double* T0, const double* Tr0,
+                               const uint8_t* pinned)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        if (ctx->n_inst != 1) fail(UGKWP_EINVAL, "set_material_noalloc needs a single-instance context");
+        if (!cv || !T0 || !Tr0) fail(UGKWP_EINVAL, "null argument");
+        if ((size_t)ctx->ncell > NOALLOC_MAX_CELLS)
+            fail(UGKWP_EINVAL, "set_material_noalloc: %d cells exceed its scratch of %zu cells", ctx->ncell,
+                 NOALLOC_MAX_CELLS);
+        DeviceScope on(ctx->device);
+        ctx->set_material({cv}, {T0}, {Tr0}, {pinned}, scratch_address(ctx->device));
+    });
+}
+
 int ugkwp_create(ugkwp_ctx** out, const ugkwp_params* p, void* hip_stream)
 {
     if (!out || !p) return UGKWP_EINVAL;
@@ -1417,6 +1482,9 @@ int ugkwp_create(ugkwp_ctx** out, const ugkwp_params* p, void* hip_stream)
     if (!c) return UGKWP_ENOMEM;
     c->P = *p;
     int rc = guarded(c, [&] {
+        HIPCHK(hipGetDevice(&c->device));
+        // the allocation-free set-up call's scratch address on this GPU, taken once
+        (void)scratch_address(c->device);
         if (hip_stream) c->st = (hipStream_t)hip_stream;
         else {
             HIPCHK(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking));

@@ -30,7 +30,7 @@ EXPORTED = [
     "ugkwp_pool_size", "ugkwp_get_pool", "ugkwp_set_pool", "ugkwp_eval_phi", "ugkwp_eval_coef",
     "ugkwp_eval_uniform", "ugkwp_eval_neg_log", "ugkwp_eval_sample_nu", "ugkwp_record", "ugkwp_recorded_steps",
     "ugkwp_adjoint", "ugkwp_autotune", "ugkwp_get_totals", "ugkwp_set_phase_times", "ugkwp_set_push_timing",
-    "ugkwp_state_bytes", "ugkwp_get_state", "ugkwp_set_state",
+    "ugkwp_state_bytes", "ugkwp_get_state", "ugkwp_set_state", "ugkwp_set_material_noalloc",
 ]
 
 _d = C.c_double
@@ -127,6 +127,7 @@ def load():
                                   C.c_uint64, _d]
     L.ugkwp_set_opacity.argtypes = [vp, _pd]
     L.ugkwp_set_material.argtypes = [vp, _pd, _pd, _pd, _pu8]
+    L.ugkwp_set_material_noalloc.argtypes = [vp, _pd, _pd, _pd, _pu8]
     L.ugkwp_init_batch.argtypes = [vp, C.c_int, C.POINTER(Instance)]
     L.ugkwp_step.argtypes = [vp, C.c_int]
     L.ugkwp_num_instances.argtypes = [vp]
@@ -224,6 +225,13 @@ class Context:
         a, b, c = _f64(cv), _f64(T0), _f64(Tr0)
         p = None if pinned is None else np.ascontiguousarray(pinned, dtype=np.uint8)
         self._chk(load().ugkwp_set_material(self.h, _p(a), _p(b), _p(c), _p(p, _pu8)), "set_material")
+
+    def set_material_noalloc(self, cv, T0, Tr0, pinned=None):
+        """set_material without device allocation (static per-GPU staging; see ugkwp.h)."""
+        a, b, c = _f64(cv), _f64(T0), _f64(Tr0)
+        p = None if pinned is None else np.ascontiguousarray(pinned, dtype=np.uint8)
+        self._chk(load().ugkwp_set_material_noalloc(self.h, _p(a), _p(b), _p(c), _p(p, _pu8)),
+                  "set_material_noalloc")
 
     def init_batch(self, instances: Sequence["Instance"], arrays_keepalive):
         arr = (Instance * len(instances))(*instances)
