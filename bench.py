@@ -325,7 +325,8 @@ def workload_name(wl, probs, spin, args):
     if wl == "larsen":
         p = probs[0]
         return (f"Larsen three-region slab {p.nx} cells x {p.G} groups on [0,4], sigma = gamma0 (1 - e^(-nu/T))/nu^3, "
-                f"gamma0 1|1000|1, C_v = 0.05109, tau_num C = 1e3, dt=dx/c, steps {first}-{last} of the run from t=0")
+                f"gamma0 1|1000|1, C_v = 0.05109/a (paper units scaled to c = a = 1), tau_num C = 1e3, dt=dx/c, "
+                f"steps {first}-{last} of the run from t=0")
     if wl == "thickthin":
         p = probs[0]
         return (f"thick-to-thin slab {p.nx} cells x {p.G} groups on [0,1.5], kappa 1000|10 jump at x=0.5, "

@@ -194,8 +194,10 @@ const char* ugkwp_last_error(const ugkwp_ctx* ctx);
 int ugkwp_init_mesh(ugkwp_ctx* ctx, int dim, int nx, int ny, const double lo[2],
                     const double hi[2], const int bc[4], const double bcT[4], int G,
                     const double* nu_edges, uint64_t seed, double w_ref);
-/* kappa [ncell][G] (host): sigma(nu, cell) = kappa nu^-p; group opacity by
- * Simpson's rule over each group (Sec. 3).  Non-negative and finite. */
+/* kappa [ncell][G] (host): sigma(nu, T, cell) = kappa nu^-p, times T^-q when
+ * opacity_T_power = q is set and times (1 - e^{-nu/T}) when opacity_stim is 1
+ * (Sec. 3.1, 3.3); group opacity by Simpson's rule over each group (Sec. 3).
+ * Non-negative and finite. */
 int ugkwp_set_opacity(ugkwp_ctx* ctx, const double* kappa);
 /* Heat capacity, initial T and radiation temperature per cell (rho^0 = phi(Tr0),
  * no particles: Sec. 3.1), optional pinned-source mask. */
@@ -218,8 +220,14 @@ int ugkwp_init_batch(ugkwp_ctx* ctx, int n_inst, const ugkwp_instance* inst);
 
 /* ---- time stepping ---- */
 
-/* Advance every instance by nsteps steps of Algorithm 1.  Asynchronous on the
- * context stream inside a step; synchronises once per step for the status. */
+/* Advance every instance by nsteps steps of Algorithm 1.  Steps are enqueued on
+ * the context stream up to 16 at a time without waiting: every launch of step n
+ * checks on the device that the steps before it committed (else it returns at
+ * once), and each step writes its own record of counters and sums.  The host
+ * synchronises once per batch of up to 16 steps, books the committed steps,
+ * takes up alone a step that needed more source-iteration sweeps than were
+ * launched, and returns at the first step that failed; the state is then that
+ * of the last committed step. */
 int ugkwp_step(ugkwp_ctx* ctx, int nsteps);
 
 /* ---- results ---- */

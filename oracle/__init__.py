@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB = os.path.join(_HERE, "liboracle.so")
+# UGKWP_ORACLE_LIB: another build of the same sources (e.g. the sanitized one
+# that `python oracle/build.py --sanitize` makes)
+_LIB = os.environ.get("UGKWP_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 OK, EINVAL, ENOMEM, EPOOL, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5

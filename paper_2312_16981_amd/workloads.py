@@ -118,21 +118,22 @@ def marshak(nx: int = 1000, G: int = 24, sigma0: float = 10.0, **kw) -> Problem:
     return q.with_(x1=5.0, cv=np.full(nx, 0.1))
 
 
-def larsen(nx: int = 200, G: int = 24, linearized: bool = True, **kw) -> Problem:
+def larsen(nx: int = 200, G: int = 24, linearized: bool = False, **kw) -> Problem:
     """Larsen's three-region slab (Sec. 3.3) on [0, 4]: sigma = gamma0 (1 - e^{-nu/T})
     / nu^3 with gamma0 = 1 on [0, 2], 1000 on (2, 3] and 1 on (3, 4] (cell-centre
-    rule), C_v = 0.05109, T0 = 1e-3, Planckian wall at T = 1 on the left and a
-    free right boundary, 24 log groups on [0.01, 100], dt = dx / c, and the
-    numerical collision time of joint cells with C = 1e3.  The small heat
-    capacity stalls the literal source iteration once the wall has heated the
-    first cells (it stops converging within 200 sweeps after about a hundred
-    steps), so the linearized one (same fixed point) is on by default."""
+    rule), T0 = 1e-3, Planckian wall at T = 1 on the left and a free right
+    boundary, 24 log groups on [0.01, 100], the numerical collision time of joint
+    cells with C = 1e3.  The paper's units (cm, ns, keV, c = 29.98, a = 0.01372)
+    are scaled to c = a = 1: time is measured as c t (so dt = dx / c = dx), the
+    radiation density in units of a c, and the heat capacity becomes
+    C_v / a = 0.05109 / 0.01372.  linearized: the linearized source iteration
+    (same fixed point) instead of the literal one."""
     p = dict(dt=4.0 / nx, steps=400, w_ref=1e-5, pool_cap=1 << 24, name=f"larsen{nx}_g{G}",
              numin=0.01, numax=100.0, opacity_stim=1, tau_num_C=1e3, tau_num_jump=10.0,
              flags=FLAG_SI_LINEARIZED if linearized else 0)
     p.update(kw)
     q = slab(nx, G, lambda x: np.where((x > 0.5) & (x <= 0.75), 1000.0, 1.0), **p)
-    return q.with_(x1=4.0, cv=np.full(nx, 0.05109))
+    return q.with_(x1=4.0, cv=np.full(nx, 0.05109 / 0.01372))
 
 
 def thick_thin_joint(nx: int = 300, G: int = 24, **kw) -> Problem:
