@@ -504,8 +504,10 @@ def main():
                    "launch": "HIP graph replays" if args.graph else "kernels launched directly",
                    "source_iteration": ("linearized (Newton step per sweep)" if probs[0].flags & W.FLAG_SI_LINEARIZED
                                         else "literal"),
-                   "push_shape": ("default (occupancy-filled grid, 4 particles per thread)" if tuned is None else
-                                  f"autotuned: {tuned[0]['blocks']} blocks, {tuned[0]['ppt']} particles per thread "
+                   "push_shape": ("default (occupancy-filled grid of 256-thread blocks, 4 particles per thread)"
+                                  if tuned is None else
+                                  f"autotuned: {tuned[0]['blocks']} blocks of {tuned[0]['threads']} threads, "
+                                  f"{tuned[0]['ppt']} particles per thread "
                                   f"({tuned[0]['us_best']:.1f} vs {tuned[0]['us_default']:.1f} us default)"
                                   + (f", per context ({len(tuned)})" if len(tuned) > 1 else ""))},
         "cell_group_updates_per_s": cgu / elapsed,

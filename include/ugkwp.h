@@ -85,7 +85,7 @@ typedef struct {
     double dt;           /* time step                                              */
     double nu_power;     /* p in sigma(nu) = kappa * nu^-p (3 for the paper's tests) */
     int64_t n_cap;       /* max particles sampled per (cell, group) and step       */
-    int64_t pool_capacity; /* particle slots of the context (all instances)        */
+    int64_t pool_capacity; /* particle slots of the context (all instances), at most 2^29 */
     int si_max_iters;    /* source-iteration limit (Algorithm 2)                   */
     double si_tol;       /* relative max-norm tolerance on rho and on T            */
     uint32_t flags;      /* UGKWP_FLAG_*                                           */
@@ -295,8 +295,9 @@ int ugkwp_set_state(ugkwp_ctx* ctx, const void* buf, int64_t bytes);
 
 /* ---- launch autotuner ----
  * Times the particle push on the context's current pool for launch shapes
- * (persistent blocks per CU: half, one and two times what fits; particles per
- * thread: 1, 2, 4, 8) and keeps the fastest for the following steps.  Only the
+ * (threads per block: 256, 512; persistent blocks per CU: half, one and
+ * two times what fits at that block size; particles per thread: 1, 2, 4, 8)
+ * and keeps the fastest for the following steps.  Only the
  * speed changes: the order in which the push adds to its tallies may differ,
  * which moves floating-point sums by rounding.  The tallies and counters of the
  * last step are restored.  Needs a non-empty pool (UGKWP_EINVAL otherwise). */
@@ -305,7 +306,9 @@ typedef struct {
     int blocks;              /* push blocks chosen                                 */
     int candidates;          /* shapes timed                                       */
     double us_best;          /* push time of the chosen shape, microseconds       */
-    double us_default;       /* of the default shape (occupancy-filled grid, 4)   */
+    double us_default;       /* of the default shape (occupancy-filled grid of
+                                256-thread blocks, 4 per thread)                  */
+    int threads;             /* threads per push block chosen                     */
 } ugkwp_tune_result;
 int ugkwp_autotune(ugkwp_ctx* ctx, ugkwp_tune_result* res);
 

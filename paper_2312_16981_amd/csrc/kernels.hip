@@ -634,12 +634,34 @@ __device__ inline void lds_tally(TallyTable& T, const Dev& D, uint32_t type, uin
     if (type == TAL_SURV) atomicAdd(D.scount + index, 1u);
 }
 
+// Add a value (and a survivor count) to the bin of `key` in the LDS table;
+// with the table crowded, straight to memory.
+__device__ inline void lds_add(TallyTable& T, const Dev& D, uint32_t key, double w, uint32_t n)
+{
+    const uint32_t type = key & 3u;
+    uint32_t h = (key * 2654435761u) >> (32 - HT_BITS);
+#pragma unroll 1
+    for (int probe = 0; probe < HT_PROBES; ++probe) {
+        const uint32_t prev = atomicCAS(&T.key[h], HT_EMPTY, key);
+        if (prev == HT_EMPTY || prev == key) {
+            __hip_atomic_fetch_add(&T.val[h], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (type == TAL_SURV)
+                __hip_atomic_fetch_add(&T.cnt[h], n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return;
+        }
+        h = (h + 1) & (HT_SIZE - 1);
+    }
+    unsafeAtomicAdd(tally_target(D, type, key >> 2), w);
+    if (type == TAL_SURV) atomicAdd(D.scount + (key >> 2), n);
+}
+
 struct Flight {
     double x, y, ox, oy;   // position and direction (mu in 1-D)
     double t, t_rem, tau;  // time flown, flight time left, flight scale in this cell
     double u_odd;          // the odd draw of the last Philox block (draws 2m and 2m+1 share one)
     uint32_t d;            // FLIGHT draws used
     int ix, iy;
+    int32_t flips;         // FLIP_X / FLIP_Y toggled by each reflection during this step
     bool coll;
 };
 
@@ -730,7 +752,7 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTabl
         }
         if (boundary) {
             if ((I.reflect >> side) & 1) {
-                if (xaxis) f.ox = -f.ox; else f.oy = -f.oy;
+                if (xaxis) { f.ox = -f.ox; f.flips ^= FLIP_X; } else { f.oy = -f.oy; f.flips ^= FLIP_Y; }
                 f.t_rem = f.t_rem - tf;
                 continue;
             }
@@ -747,24 +769,33 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTabl
 
 // One pool record as the push reads it (every field, also for an empty slot:
 // all slots below the capacity are allocated, and the values are then unused).
+// Element i of a pool array by a 32-bit byte offset from the array's base (the
+// capacity is at most 2^29 slots), so that the load can take the base in
+// scalar registers and the offset in one vector register.
+template <class T>
+__device__ inline T& at(T* base, uint32_t i)
+{
+    return *(T*)((char*)base + (size_t)(i * (uint32_t)sizeof(T)));
+}
+
 template <int DIM>
 struct PoolRec {
     double x, y, ox, oy, nu, w;
     uint64_t id;
     int32_t word, g;
-    __device__ inline void load(const Pool& P, int64_t i)
+    __device__ inline void load(const Pool& P, uint32_t i)
     {
-        word = P.cell[i];
-        g = P.g[i];
-        x = P.x[i];
-        ox = P.ox[i];
+        word = at(P.cell, i);
+        g = at(P.g, i);
+        x = at(P.x, i);
+        ox = at(P.ox, i);
         if (DIM == 2) {
-            y = P.y[i];
-            oy = P.oy[i];
+            y = at(P.y, i);
+            oy = at(P.oy, i);
         }
-        nu = P.nu[i];
-        w = P.w[i];
-        id = P.id[i];
+        nu = at(P.nu, i);
+        w = at(P.w, i);
+        id = at(P.id, i);
     }
 };
 
@@ -775,23 +806,27 @@ struct PoolRec {
 #ifndef UGK_PUSH_ATTR
 #define UGK_PUSH_ATTR
 #endif
-template <int DIM, bool SINGLE, int SM>
-__global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool In, Pool Out, int ppt)
+#ifndef UGK_PUSH_PREFETCH_2D
+#define UGK_PUSH_PREFETCH_2D 1
+#endif
+template <int DIM, bool SINGLE, int SM, int BS>
+__global__ __launch_bounds__(BS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool In, Pool Out, int ppt)
 {
+    constexpr bool PUSH_PREFETCH = DIM == 2 && UGK_PUSH_PREFETCH_2D;
     if (!gate_open(D, K, 0)) return;
     const uint32_t step = *D.step;
     __shared__ TallyTable T;
-    __shared__ unsigned long long bsurv[PUSH_THREADS / WAVE];
+    __shared__ unsigned long long bsurv[BS / WAVE];
     if (D.counters[CNT_ERR] & ERR_POOL) return;
     const int64_t n_slots = (int64_t)D.counters[CNT_SLOTS];
     const int64_t n_total = (int64_t)D.counters[CNT_PUSHED];
-    const int64_t chunk = (int64_t)PUSH_THREADS * ppt;
+    const int64_t chunk = (int64_t)BS * ppt;
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     unsigned long long nsurv = 0;
     Geo geo0{};
     if (SINGLE) geo0 = geo_of(D.inst[0]);
     for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < n_total; c0 += (int64_t)gridDim.x * chunk) {
-        for (int h = threadIdx.x; h < HT_SIZE; h += PUSH_THREADS) {
+        for (int h = threadIdx.x; h < HT_SIZE; h += BS) {
             T.key[h] = HT_EMPTY;
             T.cnt[h] = 0u;
             T.val[h] = 0.0;
@@ -800,86 +835,96 @@ __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Cons
         // 2-D: the records of the next round are read while this round's flights
         // run (1-D: the registers this takes would cost a wavefront per SIMD)
         PoolRec<DIM> nxt;
-        if (DIM == 2) {
+        if (PUSH_PREFETCH) {
             const int64_t i0 = c0 + threadIdx.x;
-            if (i0 < n_total) nxt.load(In, i0);
+            if (i0 < n_total) nxt.load(In, (uint32_t)i0);
         }
 #pragma unroll 1
         for (int r = 0; r < ppt; ++r) {
-            const int64_t i = c0 + (int64_t)r * PUSH_THREADS + threadIdx.x;
-            if (i >= n_total) continue;
+            const int64_t i = c0 + (int64_t)r * BS + threadIdx.x;
+            const uint32_t iu = (uint32_t)i;
+            // the outcome tally of this lane's particle (survival or deposition)
+            bool has = false;
+            uint32_t tkey = 0u;
+            double tw = 0.0;
             PoolRec<DIM> cur;
-            if (DIM == 2) {
+            if (PUSH_PREFETCH) {
                 cur = nxt;
-                if (r + 1 < ppt && i + PUSH_THREADS < n_total) nxt.load(In, i + PUSH_THREADS);
-            } else {
-                cur.word = In.cell[i];             // the rest only for a live slot
+                if (r + 1 < ppt && i + BS < n_total) nxt.load(In, iu + BS);
+            } else if (i < n_total) {
+                cur.word = at(In.cell, iu);        // the rest only for a live slot
             }
             const int32_t word = cur.word;
-            if (word < 0) {                        // empty slot stays empty
-                Out.cell[i] = DEAD;
-                continue;
-            }
             const int cell = word & CELL_MASK;
-            if (DIM == 1) cur.g = In.g[i];
-            const int g = cur.g;
-            if (cell >= K.ncell) {
+            if (i >= n_total) {
+                // past the end of the pool: nothing
+            } else if (word < 0) {                 // empty slot stays empty
+                at(Out.cell, iu) = DEAD;
+            } else if (cell >= K.ncell) {
                 atomicOr((unsigned long long*)(D.counters + CNT_ERR), ERR_RECORD);
-                Out.cell[i] = DEAD;
-                continue;
-            }
-            if (DIM == 1) {
-                cur.x = In.x[i];
-                cur.ox = In.ox[i];
-                cur.nu = In.nu[i];
-                cur.w = In.w[i];
-                cur.id = In.id[i];
-            }
-            const Geo I = SINGLE ? geo0 : geo_of(D.inst[D.cell_inst[cell]]);
-            Flight f;
-            f.x = cur.x;
-            f.ox = (word & FLIP_X) ? -cur.ox : cur.ox;
-            if (DIM == 2) {
-                f.y = cur.y;
-                f.oy = (word & FLIP_Y) ? -cur.oy : cur.oy;
+                at(Out.cell, iu) = DEAD;
             } else {
-                f.y = 0.0;
-                f.oy = 0.0;
+                if (!PUSH_PREFETCH) {
+                    cur.g = at(In.g, iu);
+                    cur.x = at(In.x, iu);
+                    cur.ox = at(In.ox, iu);
+                    if (DIM == 2) {
+                        cur.y = at(In.y, iu);
+                        cur.oy = at(In.oy, iu);
+                    }
+                    cur.nu = at(In.nu, iu);
+                    cur.w = at(In.w, iu);
+                    cur.id = at(In.id, iu);
+                }
+                const int g = cur.g;
+                const Geo I = SINGLE ? geo0 : geo_of(D.inst[D.cell_inst[cell]]);
+                Flight f;
+                f.x = cur.x;
+                f.ox = (word & FLIP_X) ? -cur.ox : cur.ox;
+                if (DIM == 2) {
+                    f.y = cur.y;
+                    f.oy = (word & FLIP_Y) ? -cur.oy : cur.oy;
+                } else {
+                    f.y = 0.0;
+                    f.oy = 0.0;
+                }
+                const double nu = cur.nu, w = cur.w;
+                const uint64_t id = cur.id;
+                const int lcell = cell - I.cell_off;
+                f.ix = DIM == 1 ? lcell : lcell % I.nx;
+                f.iy = DIM == 1 ? 0 : lcell / I.nx;
+                f.t = 0.0;
+                f.d = 0;
+                f.flips = 0;
+                const double tfac = tau_factor<SM>(D, K, I, nu, g);
+                f.tau = tfac * D.inv_kappa[I.cg_off + ((uint32_t)lcell << I.lgGp) + (uint32_t)g];
+                if (SM == SIG_STIM) f.tau = f.tau / stim_factor(K, nu, D.T[cell]);
+                if (i < n_slots) draw_flight(K, I, id, step, f);    // old particle: t_f = min(-tau ln eta, dt)
+                else { f.coll = false; f.t_rem = K.dt; }            // new collisionless particle: t_f = dt
+                const int out = fly<DIM, SM>(D, K, I, T, id, step, tfac, g, nu, w, f);
+                if (out != 2) {
+                    const uint32_t cg = I.cg_off + ((uint32_t)(f.iy * I.nx + f.ix) << I.lgGp) + (uint32_t)g;
+                    has = true;
+                    tkey = (cg << 2) | (out == 0 ? TAL_SURV : TAL_DEP);
+                    tw = w;
+                }
+                if (out == 0) {
+                    // pending reversals relative to the stored direction: those
+                    // carried in, toggled by this step's reflections
+                    const int32_t nw = (I.cell_off + f.iy * I.nx + f.ix) | ((word ^ f.flips) & (FLIP_X | FLIP_Y));
+                    at(Out.x, iu) = f.x;
+                    if (DIM == 2) at(Out.y, iu) = f.y;
+                    at(Out.cell, iu) = nw;
+                    nsurv++;
+                } else {
+                    at(Out.cell, iu) = DEAD;
+                }
             }
-            const double nu = cur.nu, w = cur.w;
-            const uint64_t id = cur.id;
-            const int lcell = cell - I.cell_off;
-            f.ix = DIM == 1 ? lcell : lcell % I.nx;
-            f.iy = DIM == 1 ? 0 : lcell / I.nx;
-            f.t = 0.0;
-            f.d = 0;
-            const double tfac = tau_factor<SM>(D, K, I, nu, g);
-            f.tau = tfac * D.inv_kappa[I.cg_off + ((uint32_t)lcell << I.lgGp) + (uint32_t)g];
-            if (SM == SIG_STIM) f.tau = f.tau / stim_factor(K, nu, D.T[cell]);
-            if (i < n_slots) draw_flight(K, I, id, step, f);    // old particle: t_f = min(-tau ln eta, dt)
-            else { f.coll = false; f.t_rem = K.dt; }            // new collisionless particle: t_f = dt
-            const double ox0 = f.ox, oy0 = f.oy;
-            const int out = fly<DIM, SM>(D, K, I, T, id, step, tfac, g, nu, w, f);
-            if (out != 2) {
-                const uint32_t cg = I.cg_off + ((uint32_t)(f.iy * I.nx + f.ix) << I.lgGp) + (uint32_t)g;
-                lds_tally(T, D, out == 0 ? TAL_SURV : TAL_DEP, cg, w);
-            }
-            if (out == 0) {
-                int32_t nw = I.cell_off + f.iy * I.nx + f.ix;
-                // pending reversal relative to the stored direction
-                if ((f.ox != ox0) != ((word & FLIP_X) != 0)) nw |= FLIP_X;
-                if (DIM == 2 && ((f.oy != oy0) != ((word & FLIP_Y) != 0))) nw |= FLIP_Y;
-                Out.x[i] = f.x;
-                if (DIM == 2) Out.y[i] = f.y;
-                Out.cell[i] = nw;
-                nsurv++;
-            } else {
-                Out.cell[i] = DEAD;
-            }
+            if (has) lds_add(T, D, tkey, tw, 1u);
         }
         __syncthreads();
         // flush the chunk's tallies: one global atomic per distinct bin
-        for (int h = threadIdx.x; h < HT_SIZE; h += PUSH_THREADS) {
+        for (int h = threadIdx.x; h < HT_SIZE; h += BS) {
             const uint32_t key = T.key[h];
             if (key == HT_EMPTY) continue;
             const uint32_t type = key & 3u, index = key >> 2;
@@ -894,7 +939,7 @@ __global__ __launch_bounds__(PUSH_THREADS) UGK_PUSH_ATTR void k_push(Dev D, Cons
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
-        for (int k = 0; k < PUSH_THREADS / WAVE; ++k) t += bsurv[k];
+        for (int k = 0; k < BS / WAVE; ++k) t += bsurv[k];
         D.blk_surv[blockIdx.x] = t;
     }
 }
@@ -1756,15 +1801,12 @@ void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, hipStr
     else k_sample<2><<<512, 256, 0, st>>>(D, K, P);
 }
 
-static int g_push_grid[2][2][4] = {};
+// Push block sizes the launch shape may take (threads per block).
+constexpr int PUSH_BS[2] = {256, 512};
 
-template <int DIM, bool SINGLE, int SM>
-static int push_blocks_per_cu()
+static int push_bs_index(int threads)
 {
-    int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_push<DIM, SINGLE, SM>, PUSH_THREADS, 0) != hipSuccess)
-        per = 0;
-    return per;
+    return threads == PUSH_BS[1] ? 1 : 0;
 }
 
 static int sig_mode(const Consts& K)
@@ -1774,65 +1816,97 @@ static int sig_mode(const Consts& K)
     return K.nu_power == 3.0 ? SIG_NU3 : SIG_POW;
 }
 
-int push_grid(int dim, bool single, int sm)
+template <int DIM, bool SINGLE, int SM, int BS>
+static int push_occupancy()
 {
-    int& gsz = g_push_grid[dim - 1][single ? 1 : 0][sm];
-    if (gsz == 0) {
-        int dev = 0, ncu = 0, per = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-#define UGK_PER(D_, S_, M_) if (dim == D_ && single == S_ && sm == M_) per = push_blocks_per_cu<D_, S_, M_>();
-        UGK_PER(1, true, 0) UGK_PER(1, true, 1) UGK_PER(1, true, 2)
-        UGK_PER(1, false, 0) UGK_PER(1, false, 1) UGK_PER(1, false, 2)
-        UGK_PER(2, true, 0) UGK_PER(2, true, 1) UGK_PER(2, true, 2)
-        UGK_PER(2, false, 0) UGK_PER(2, false, 1) UGK_PER(2, false, 2)
-#undef UGK_PER
-        if (per < 1) per = 2;
-        if (ncu < 1) ncu = 256;
-        gsz = ncu * per;
-    }
-    return gsz;
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_push<DIM, SINGLE, SM, BS>, BS, 0) != hipSuccess)
+        per = 0;
+    return per;
+}
+
+template <int DIM, bool SINGLE, int SM>
+static int push_occupancy_bs(int threads)
+{
+    if (threads == 512) return push_occupancy<DIM, SINGLE, SM, 512>();
+    return push_occupancy<DIM, SINGLE, SM, 256>();
 }
 
 template <int DIM, bool SINGLE>
-static void push_mode(int sm, int nb, int ppt, const Dev& D, const Consts& K, const Pool& In, const Pool& Out,
+static int push_occupancy_sm(int sm, int threads)
+{
+    switch (sm) {
+        case SIG_NU3: return push_occupancy_bs<DIM, SINGLE, SIG_NU3>(threads);
+        case SIG_POW: return push_occupancy_bs<DIM, SINGLE, SIG_POW>(threads);
+        case SIG_GROUP: return push_occupancy_bs<DIM, SINGLE, SIG_GROUP>(threads);
+        default: return push_occupancy_bs<DIM, SINGLE, SIG_STIM>(threads);
+    }
+}
+
+// Resident push blocks per CU of the given block size (cached per kernel).
+static int g_push_occ[2][2][4][2] = {};
+
+int push_blocks_per_cu(int dim, const Consts& K, int threads)
+{
+    const bool single = K.n_inst == 1;
+    const int sm = sig_mode(K);
+    int& per = g_push_occ[dim - 1][single ? 1 : 0][sm][push_bs_index(threads)];
+    if (per == 0) {
+        if (dim == 1) per = single ? push_occupancy_sm<1, true>(sm, threads) : push_occupancy_sm<1, false>(sm, threads);
+        else per = single ? push_occupancy_sm<2, true>(sm, threads) : push_occupancy_sm<2, false>(sm, threads);
+        if (per < 1) per = 2;
+    }
+    return per;
+}
+
+static int num_cus()
+{
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    return ncu < 1 ? 256 : ncu;
+}
+
+template <int DIM, bool SINGLE, int SM>
+static void push_bs(const PushShape& sh, const Dev& D, const Consts& K, const Pool& In, const Pool& Out,
+                    hipStream_t st)
+{
+    if (sh.threads == 512) k_push<DIM, SINGLE, SM, 512><<<sh.blocks, 512, 0, st>>>(D, K, In, Out, sh.ppt);
+    else k_push<DIM, SINGLE, SM, 256><<<sh.blocks, 256, 0, st>>>(D, K, In, Out, sh.ppt);
+}
+
+template <int DIM, bool SINGLE>
+static void push_mode(int sm, const PushShape& sh, const Dev& D, const Consts& K, const Pool& In, const Pool& Out,
                       hipStream_t st)
 {
-    if (sm == SIG_NU3) k_push<DIM, SINGLE, SIG_NU3><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, ppt);
-    else if (sm == SIG_POW) k_push<DIM, SINGLE, SIG_POW><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, ppt);
-    else if (sm == SIG_GROUP) k_push<DIM, SINGLE, SIG_GROUP><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, ppt);
-    else k_push<DIM, SINGLE, SIG_STIM><<<nb, PUSH_THREADS, 0, st>>>(D, K, In, Out, ppt);
+    if (sm == SIG_NU3) push_bs<DIM, SINGLE, SIG_NU3>(sh, D, K, In, Out, st);
+    else if (sm == SIG_POW) push_bs<DIM, SINGLE, SIG_POW>(sh, D, K, In, Out, st);
+    else if (sm == SIG_GROUP) push_bs<DIM, SINGLE, SIG_GROUP>(sh, D, K, In, Out, st);
+    else push_bs<DIM, SINGLE, SIG_STIM>(sh, D, K, In, Out, st);
 }
 
 PushShape push_default_shape(int dim, const Consts& K)
 {
     PushShape p;
-    p.blocks = push_grid(dim, K.n_inst == 1, sig_mode(K));
+    p.threads = PUSH_THREADS;
+    p.blocks = num_cus() * push_blocks_per_cu(dim, K, PUSH_THREADS);
     p.ppt = PUSH_PPT_DEFAULT;
     return p;
 }
 
-int push_blocks_per_cu(int dim, const Consts& K)
-{
-    int dev = 0, ncu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (ncu < 1) ncu = 256;
-    return push_grid(dim, K.n_inst == 1, sig_mode(K)) / ncu;
-}
+int push_num_cus() { return num_cus(); }
 
 void launch_push(int dim, const Dev& D, const Consts& K, const Pool& In, const Pool& Out, const PushShape& sh,
                  hipStream_t st)
 {
     const bool single = K.n_inst == 1;
     const int sm = sig_mode(K);
-    const int nb = sh.blocks, ppt = sh.ppt;
     if (dim == 1) {
-        if (single) push_mode<1, true>(sm, nb, ppt, D, K, In, Out, st);
-        else push_mode<1, false>(sm, nb, ppt, D, K, In, Out, st);
+        if (single) push_mode<1, true>(sm, sh, D, K, In, Out, st);
+        else push_mode<1, false>(sm, sh, D, K, In, Out, st);
     } else {
-        if (single) push_mode<2, true>(sm, nb, ppt, D, K, In, Out, st);
-        else push_mode<2, false>(sm, nb, ppt, D, K, In, Out, st);
+        if (single) push_mode<2, true>(sm, sh, D, K, In, Out, st);
+        else push_mode<2, false>(sm, sh, D, K, In, Out, st);
     }
 }
 

@@ -32,14 +32,16 @@ ScanGate scan_gate(const Dev& D, const Consts& K, uint32_t after);
 void launch_scan(const ScanGate& q, const int32_t* in, int64_t n, int64_t* part, int64_t* out, int64_t* total,
                  hipStream_t st);
 void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, hipStream_t st);
-// Launch shape of the push: persistent blocks and particles per thread.
+// Launch shape of the push: persistent blocks, threads per block (256 or 512)
+// and particles per thread.
 struct PushShape {
     int blocks;
     int ppt;
+    int threads;
 };
-int push_grid(int dim, bool single, int sig_mode);
-PushShape push_default_shape(int dim, const Consts& K);   // occupancy-filled grid, 4 per thread
-int push_blocks_per_cu(int dim, const Consts& K);         // resident blocks per CU (occupancy)
+PushShape push_default_shape(int dim, const Consts& K);   // occupancy-filled grid of 256-thread blocks, 4 per thread
+int push_blocks_per_cu(int dim, const Consts& K, int threads);   // resident blocks per CU (occupancy)
+int push_num_cus();
 void launch_push(int dim, const Dev& D, const Consts& K, const Pool& A, const Pool& B, const PushShape& sh,
                  hipStream_t st);
 void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& B, const Pool& A, hipStream_t st);

@@ -207,7 +207,7 @@ struct ugkwp_ctx {
 
     // launch shape of the push (default: occupancy-filled persistent grid, 4
     // particles per thread; ugkwp_autotune may change it)
-    PushShape push_shape{0, 4};
+    PushShape push_shape{0, 4, 256};
 
     // each step's launch sequence captured as a HIP graph, one per launch
     // configuration (pool buffer parities, rho/T parity, sort, speculative sweeps)
@@ -1037,19 +1037,23 @@ struct ugkwp_ctx {
         if (dim == 2) keep(D.fty, sizeof(double) * 2 * n_fy);
         HIPCHK(hipMemcpyAsync(D.counters, trial.data(), sizeof(unsigned long long) * N_COUNTERS,
                               hipMemcpyHostToDevice, st));
-        int dev = 0, ncu = 0;
-        HIPCHK(hipGetDevice(&dev));
-        HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        const int occ = std::max(1, push_blocks_per_cu(dim, K));
+        const int ncu = push_num_cus();
         std::vector<PushShape> cand;
-        for (int ppt : {1, 2, 4, 8})
-            for (int bpc : {std::max(1, occ / 2), occ, 2 * occ}) {
-                const PushShape c{std::min(bpc * ncu, MAX_PUSH_BLOCKS), ppt};
-                bool dup = false;
-                for (const auto& q : cand) dup = dup || (q.blocks == c.blocks && q.ppt == c.ppt);
-                if (!dup) cand.push_back(c);
-            }
-        const PushShape def = {std::min(push_default_shape(dim, K).blocks, MAX_PUSH_BLOCKS), 4};
+        // 256 and 512 threads per block: blocks of 128 tuned well on one pool but
+        // ran ~10% slower than their tuning time over the following steps
+        for (int threads : {256, 512}) {
+            const int occ = std::max(1, push_blocks_per_cu(dim, K, threads));
+            for (int ppt : {1, 2, 4, 8})
+                for (int bpc : {std::max(1, occ / 2), occ, 2 * occ}) {
+                    const PushShape c{std::min(bpc * ncu, MAX_PUSH_BLOCKS), ppt, threads};
+                    bool dup = false;
+                    for (const auto& q : cand)
+                        dup = dup || (q.blocks == c.blocks && q.ppt == c.ppt && q.threads == c.threads);
+                    if (!dup) cand.push_back(c);
+                }
+        }
+        PushShape def = push_default_shape(dim, K);
+        def.blocks = std::min(def.blocks, MAX_PUSH_BLOCKS);
         auto time_push = [&](const PushShape& sh) {
             const Pool In = view(cur_mv, cur_st), Out = moving(1 - cur_mv);
             launch_push(dim, D, K, In, Out, sh, st);           // warm-up
@@ -1082,6 +1086,7 @@ struct ugkwp_ctx {
         drop_graphs();
         if (res) {
             res->ppt = best.ppt;
+            res->threads = best.threads;
             res->blocks = best.blocks;
             res->candidates = (int)cand.size();
             res->us_best = us_best;
@@ -1473,7 +1478,8 @@ int ugkwp_create(ugkwp_ctx** out, const ugkwp_params* p, void* hip_stream)
     if (!out || !p) return UGKWP_EINVAL;
     *out = nullptr;
     if (!(p->c > 0) || !(p->a > 0) || !(p->eps > 0) || !(p->dt > 0) || !std::isfinite(p->dt) ||
-        !(p->si_tol >= 0) || p->si_max_iters < 1 || p->pool_capacity < 0 || p->n_cap < 0 ||
+        !(p->si_tol >= 0) || p->si_max_iters < 1 || p->pool_capacity < 0 || p->pool_capacity > (1ll << 29) ||
+        p->n_cap < 0 ||
         p->n_cap > (1 << 30) || !(p->nu_power >= 0) || p->sort_interval < 0 ||
         !(p->tau_num_C >= 0) || !std::isfinite(p->tau_num_C) || !(p->tau_num_jump >= 0) ||
         !std::isfinite(p->opacity_T_power) || (p->opacity_stim != 0 && p->opacity_stim != 1))

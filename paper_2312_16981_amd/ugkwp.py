@@ -79,7 +79,7 @@ class Totals(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("ppt", C.c_int), ("blocks", C.c_int), ("candidates", C.c_int), ("us_best", _d),
-                ("us_default", _d)]
+                ("us_default", _d), ("threads", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
