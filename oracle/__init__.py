@@ -46,7 +46,8 @@ class Diag(C.Structure):
                 ("sweeps", C.c_int),
                 ("e_start", _d), ("e_end", _d), ("inflow_wave", _d), ("inflow_eq", _d),
                 ("exit_particles", _d), ("injection", _d), ("residual", _d),
-                ("si_drho", _d), ("si_rho", _d), ("si_dT", _d), ("si_T", _d)]
+                ("si_drho", _d), ("si_rho", _d), ("si_dT", _d), ("si_T", _d),
+                ("inflow_particles", _d), ("n_ghost_births", C.c_int64), ("n_ghost_entered", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -63,7 +64,8 @@ def lib():
         L.ora_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
         L.ora_uniform.restype = _d
         for f in ("ora_planck_tail", "ora_planck_head", "ora_coef_c4", "ora_coef_w", "ora_coef_c2_over_dt",
-                  "ora_coef_c4_ds", "ora_coef_w_ds", "ora_coef_c2_over_dt_ds"):
+                  "ora_coef_c4_ds", "ora_coef_w_ds", "ora_coef_c2_over_dt_ds", "ora_coef_c5_over_dt",
+                  "ora_coef_w5_over_dt"):
             getattr(L, f).argtypes = [_d]
             getattr(L, f).restype = _d
         for f in ("ora_phi_group", "ora_dphi_group"):
@@ -71,6 +73,8 @@ def lib():
             getattr(L, f).restype = _d
         L.ora_freq_slope.argtypes = [_d, _d, _d]
         L.ora_freq_slope.restype = _d
+        L.ora_linear_offset.argtypes = [_d, _d]
+        L.ora_linear_offset.restype = _d
         L.ora_sample_nu.argtypes = [_d, _d, _d, _d]
         L.ora_sample_nu.restype = _d
         L.ora_create.argtypes = [C.POINTER(Params)]
@@ -143,6 +147,18 @@ def coef_w(s):
 
 def coef_c2_over_dt(s):
     return lib().ora_coef_c2_over_dt(s)
+
+
+def coef_c5_over_dt(s):
+    return lib().ora_coef_c5_over_dt(s)
+
+
+def coef_w5_over_dt(s):
+    return lib().ora_coef_w5_over_dt(s)
+
+
+def linear_offset(beta, U):
+    return lib().ora_linear_offset(beta, U)
 
 
 def coef_c4_ds(s):

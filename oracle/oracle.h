@@ -54,6 +54,8 @@ double ora_dphi_group(double T, double nl, double nh, double a, double c);
 double ora_coef_c4(double s);          /* C4 = (1 - e^{-s}) / s           */
 double ora_coef_w(double s);           /* W  = C4 - e^{-s}                 */
 double ora_coef_c2_over_dt(double s);  /* C2 / dt  (C2 of the F^eq flux)   */
+double ora_coef_c5_over_dt(double s); /* C5/dt (slope term of F^{fr,UGKS})     */
+double ora_coef_w5_over_dt(double s); /* (C5 + (dt/2) e^{-s})/dt (F^{fr,wave})  */
 /* Their derivatives in s (adjoint of the macroscopic solve). */
 double ora_coef_c4_ds(double s);
 double ora_coef_w_ds(double s);
@@ -62,6 +64,9 @@ double ora_coef_c2_over_dt_ds(double s);
 /* Linear-frequency sampling: slope beta = (B(nh) - B(nl)) / B(nmid), limited
  * to [-2, 2], at temperature T. */
 double ora_freq_slope(double nl, double nh, double T);
+/* Offset u' in [-1/2, 1/2] with CDF of the density 1 + beta u' (|beta| <= 2)
+ * equal to U. */
+double ora_linear_offset(double beta, double U);
 /* Inverse of the linear CDF on [nl, nh] with slope beta for a uniform U. */
 double ora_sample_nu(double nl, double nh, double beta, double U);
 
@@ -71,8 +76,14 @@ enum { ORA_BC_VACUUM = 0, ORA_BC_PLANCK = 1, ORA_BC_REFLECT = 2 };
 enum { ORA_OK = 0, ORA_EINVAL = -1, ORA_ENOMEM = -2, ORA_EPOOL = -3,
        ORA_ENOCONV = -4, ORA_ENONFINITE = -5 };
 enum { ORA_FLAG_GROUP_SIGMA = 1,    /* flights use the group (Simpson) sigma */
-       ORA_FLAG_SI_LINEARIZED = 8   /* source iteration with the emission linearized
-                                       about T^k (a local Newton step) */ };
+       ORA_FLAG_SI_LINEARIZED = 8,  /* source iteration with the emission linearized
+                                       about T^k (a local Newton step) */
+       ORA_FLAG_SLOPES = 16,        /* MINMOD slopes of the wave part: the C5 terms of the
+                                       wave flux, new particles placed along the slope */
+       ORA_FLAG_WAVE_ITER = 32,     /* wave flux from each sweep's iterate rho^k
+                                       (Algorithm 2) instead of the start of the step */
+       ORA_FLAG_BOUNDARY_PARTICLES = 64 /* Planckian boundaries also emit collisionless
+                                       particles from their ghost cells */ };
 
 typedef struct {
     int dim;              /* 1 or 2 */
@@ -116,8 +127,11 @@ typedef struct {
     int sweeps;
     double e_start, e_end;      /* total energy (radiation rho/c + material) */
     double inflow_wave, inflow_eq, exit_particles, injection;
-    double residual;            /* e_end - e_start - (inflow_wave + inflow_eq - exit + injection) */
+    double residual;            /* e_end - e_start - (inflow_wave + inflow_eq + inflow_particles
+                                   - exit + injection) */
     double si_drho, si_rho, si_dT, si_T;
+    double inflow_particles;    /* boundary-source particles that entered the domain */
+    int64_t n_ghost_births, n_ghost_entered;
 } ora_diag;
 
 ora_sim* ora_create(const ora_params* p);

@@ -171,6 +171,46 @@ double ora_coef_c2_over_dt(double s)
     return (2.0 * ora_coef_c4(s) - 1.0 - exp(-s)) / s;
 }
 
+/* C5 / dt, the slope coefficient of the UGKS free-transport flux (Sec. 2.2):
+ * C5 = tau e^{-s} - (tau^2/dt)(1 - e^{-s}) with tau = dt/s, i.e. the time
+ * average of -t e^{-t/tau} over the step:
+ *   C5/dt = -int_0^1 u e^{-s u} du = ((1 + s) e^{-s} - 1) / s^2,
+ * by its series -sum_{n>=0} (-s)^n / (n! (n+2)) below s = 2. */
+double ora_coef_c5_over_dt(double s)
+{
+    if (s < 2.0) {
+        double sum = 0.0, pw = 1.0, fact = 1.0;    /* pw = s^n, fact = n! */
+        for (int n = 0; n < 80; ++n) {
+            if (n > 0) { pw *= s; fact *= (double)n; }
+            double term = pw / (fact * (double)(n + 2));
+            sum += (n & 1) ? term : -term;
+            if (n > 0 && term < 1e-18 * fabs(sum)) break;
+        }
+        return sum;
+    }
+    return ((1.0 + s) * exp(-s) - 1.0) / (s * s);
+}
+
+/* (C5 + (dt/2) e^{-s}) / dt, the slope coefficient of the wave flux of a cell
+ * whose collisionless part was sampled (Sec. 2.2, F^{fr,wave}): the two terms
+ * cancel as s -> 0, so below s = 2 it is summed as
+ *   sum_{n>=1} (-s)^n n / (2 n! (n+2)). */
+double ora_coef_w5_over_dt(double s)
+{
+    if (s < 2.0) {
+        double sum = 0.0, pw = 1.0, fact = 1.0;    /* pw = s^n, fact = n! */
+        for (int n = 1; n < 80; ++n) {
+            pw *= s;
+            fact *= (double)n;
+            double term = (double)n * pw / (2.0 * fact * (double)(n + 2));
+            sum += (n & 1) ? -term : term;
+            if (term < 1e-18 * fabs(sum)) break;
+        }
+        return sum;
+    }
+    return ora_coef_c5_over_dt(s) + 0.5 * exp(-s);
+}
+
 /* Derivatives in s, needed by the adjoint of the macroscopic solve.  From the
  * closed forms above:
  *   dC4/ds      = (e^{-s} - C4)/s = -W/s
@@ -242,14 +282,19 @@ double ora_freq_slope(double nl, double nh, double T)
  * which is what its printed a, b, c coefficients encode).  In u':
  *   (beta/2) u'^2 + u' + q = 0,  q = 1/2 - beta/8 - U,
  * root with non-negative density: u' = -2q / (1 + sqrt(1 - 2 beta q)). */
+double ora_linear_offset(double beta, double U)
+{
+    double q = 0.5 - 0.125 * beta - U;
+    double disc = 1.0 - 2.0 * beta * q;
+    if (disc < 0.0) disc = 0.0;
+    return -2.0 * q / (1.0 + sqrt(disc));
+}
+
 double ora_sample_nu(double nl, double nh, double beta, double U)
 {
     double nm = 0.5 * (nl + nh);
     double dnu = nh - nl;
-    double q = 0.5 - 0.125 * beta - U;
-    double disc = 1.0 - 2.0 * beta * q;
-    if (disc < 0.0) disc = 0.0;
-    double up = -2.0 * q / (1.0 + sqrt(disc));
+    double up = ora_linear_offset(beta, U);
     double nu = nm + up * dnu;
     if (nu < nl) nu = nl;
     if (nu > nh) nu = nh;

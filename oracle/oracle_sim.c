@@ -239,8 +239,16 @@ static double ghost_phi(const ora_sim* s, int side, int g, double interior)
 
 typedef struct { double x, y, ox, oy, nu, w; uint64_t id; int32_t cell, g; } particle;
 
-/* Outcome: 0 survives, 1 collided (absorbed), 2 exited through the domain boundary. */
-static int push_1d(ora_sim* s, particle* pp, int is_new, double* exit_w, int64_t* ncross)
+/* Outcome: 0 survives, 1 collided (absorbed), 2 exited through the domain
+ * boundary, 3 a boundary-source particle that never entered the domain.
+ * ghost: 0, or 1 + the side beyond which a boundary-source particle was born
+ * (in the ghost cell of that side, one cell width deep).  It flies straight and
+ * without collisions (it is a new particle) until it reaches the domain face;
+ * if that happens within the step, the crossing is tallied like any other and
+ * its flight time is drawn in the cell it enters (Remark 1), otherwise it is
+ * dropped. */
+static int push_1d(ora_sim* s, particle* pp, int is_new, int ghost, double* exit_w, double* in_w,
+                   int64_t* ncross)
 {
     const ora_params* P = &s->p;
     const int G = P->G, nx = P->nx;
@@ -249,10 +257,33 @@ static int push_1d(ora_sim* s, particle* pp, int is_new, double* exit_w, int64_t
     int g = pp->g;
     double x = pp->x, mu = pp->ox;
     uint32_t d = 0;
-    double t = 0.0, t_rem;
-    int coll;
+    double t = 0.0, t_rem = dt;
+    int coll = 0;
+    if (ghost) {
+        const int right = ghost - 1 == XLO;       /* entering through the low face moves right */
+        const double v = cv * mu;
+        if (right ? !(v > 0) : !(v < 0)) return 3;
+        const double xf = right ? P->x0 : P->x1;
+        const double te = (xf - x) / v;
+        if (!(te < dt)) return 3;
+        x = xf;
+        t = te;
+        ix = right ? 0 : nx - 1;
+        const int face = right ? 0 : nx;
+        s->ftx[((size_t)face * G + g) * 2 + (right ? 0 : 1)] += pp->w;
+        *in_w += pp->w;
+        (*ncross)++;
+        double sg = particle_sigma(s, (size_t)ix * G + g, pp->nu, g);
+        double u = ora_uniform(P->seed, pp->id, (uint32_t)s->step, ORA_PURPOSE_FLIGHT, d++);
+        double a = -(e2c / sg) * log(u);
+        coll = a < dt - t;
+        t_rem = coll ? a : dt - t;
+        is_new = 2;                               /* flight already drawn */
+    }
     double sig = particle_sigma(s, (size_t)ix * G + g, pp->nu, g);
-    if (!is_new) {
+    if (is_new == 2) {
+        /* a boundary-source particle inside the domain: flight set above */
+    } else if (!is_new) {
         double u = ora_uniform(P->seed, pp->id, (uint32_t)s->step, ORA_PURPOSE_FLIGHT, d++);
         double tau = e2c / sig;
         double a = -tau * log(u);
@@ -311,7 +342,8 @@ static int push_1d(ora_sim* s, particle* pp, int is_new, double* exit_w, int64_t
     return coll ? 1 : 0;
 }
 
-static int push_2d(ora_sim* s, particle* pp, int is_new, double* exit_w, int64_t* ncross)
+static int push_2d(ora_sim* s, particle* pp, int is_new, int ghost, double* exit_w, double* in_w,
+                   int64_t* ncross)
 {
     const ora_params* P = &s->p;
     const int G = P->G, nx = P->nx, ny = P->ny;
@@ -320,10 +352,60 @@ static int push_2d(ora_sim* s, particle* pp, int is_new, double* exit_w, int64_t
     int g = pp->g;
     double x = pp->x, y = pp->y, ox = pp->ox, oy = pp->oy;
     uint32_t d = 0;
-    double t = 0.0, t_rem;
-    int coll;
+    double t = 0.0, t_rem = dt;
+    int coll = 0;
+    if (ghost) {
+        /* the straight line from the ghost cell meets the domain's face plane at
+         * time te; it enters if te < dt and the meeting point lies on the domain's
+         * side (the cell it enters holds that point) */
+        const int side = ghost - 1;
+        const double vx = cv * ox, vy = cv * oy;
+        const int xside = side == XLO || side == XHI;
+        const int lo = side == XLO || side == YLO;
+        const double vn = xside ? vx : vy;
+        if (lo ? !(vn > 0) : !(vn < 0)) return 3;
+        const double pf = xside ? (lo ? P->x0 : P->x1) : (lo ? P->y0 : P->y1);
+        const double te = (pf - (xside ? x : y)) / vn;
+        if (!(te < dt)) return 3;
+        if (xside) {
+            double ye = y + vy * te;
+            if (ye < P->y0 || ye > P->y1) return 3;
+            iy = (int)floor((ye - P->y0) / s->dy);
+            if (iy > ny - 1) iy = ny - 1;
+            if (iy < 0) iy = 0;
+            const double yl = P->y0 + (double)iy * s->dy, yr = P->y0 + (double)(iy + 1) * s->dy;
+            y = ye < yl ? yl : (ye > yr ? yr : ye);
+            x = pf;
+            ix = lo ? 0 : nx - 1;
+            const int face = iy * (nx + 1) + (lo ? 0 : nx);
+            s->ftx[((size_t)face * G + g) * 2 + (lo ? 0 : 1)] += pp->w;
+        } else {
+            double xe = x + vx * te;
+            if (xe < P->x0 || xe > P->x1) return 3;
+            ix = (int)floor((xe - P->x0) / s->dx);
+            if (ix > nx - 1) ix = nx - 1;
+            if (ix < 0) ix = 0;
+            const double xl = P->x0 + (double)ix * s->dx, xr = P->x0 + (double)(ix + 1) * s->dx;
+            x = xe < xl ? xl : (xe > xr ? xr : xe);
+            y = pf;
+            iy = lo ? 0 : ny - 1;
+            const int face = (lo ? 0 : ny) * nx + ix;
+            s->fty[((size_t)face * G + g) * 2 + (lo ? 0 : 1)] += pp->w;
+        }
+        t = te;
+        *in_w += pp->w;
+        (*ncross)++;
+        double sg = particle_sigma(s, ((size_t)iy * nx + ix) * G + g, pp->nu, g);
+        double u = ora_uniform(P->seed, pp->id, (uint32_t)s->step, ORA_PURPOSE_FLIGHT, d++);
+        double a = -(e2c / sg) * log(u);
+        coll = a < dt - t;
+        t_rem = coll ? a : dt - t;
+        is_new = 2;
+    }
     double sig = particle_sigma(s, ((size_t)iy * nx + ix) * G + g, pp->nu, g);
-    if (!is_new) {
+    if (is_new == 2) {
+        /* a boundary-source particle inside the domain: flight set above */
+    } else if (!is_new) {
         double u = ora_uniform(P->seed, pp->id, (uint32_t)s->step, ORA_PURPOSE_FLIGHT, d++);
         double tau = e2c / sig;
         double a = -tau * log(u);
@@ -470,6 +552,152 @@ static void rec_push(ora_sim* s, const double* rhoh, const double* wnet, const u
     r->sampled = (unsigned char*)malloc(ncg); memcpy(r->sampled, sampled, ncg);
 }
 
+/* ---------------- second-order wave part (Sec. 2.2, the C5 terms) ---------------- */
+
+/* minmod of two undivided differences: 0 when they differ in sign, else the
+ * one of smaller magnitude. */
+static double minmod(double a, double b)
+{
+    if (!(a * b > 0.0)) return 0.0;
+    return fabs(a) < fabs(b) ? a : b;
+}
+
+/* Slopes of the wave part rho^h per cell and group along x (and y): MINMOD of
+ * the differences to the two neighbours, with the boundary ghost one cell width
+ * away (Planckian phi(T_b), vacuum 0, reflective the mirror image), then scaled
+ * down where needed so that the linear profile stays non-negative over the
+ * cell (|s_x| dx + |s_y| dy <= 2 rho^h); zero where rho^h <= 0. */
+static void wave_slopes(const ora_sim* s, const double* rhoh, double* sx, double* sy)
+{
+    const ora_params* P = &s->p;
+    const int G = P->G, nx = P->nx, ny = P->ny;
+    for (int i = 0; i < s->ncell; ++i) {
+        const int ix = i % nx, iy = i / nx;
+        for (int g = 0; g < G; ++g) {
+            const size_t k = (size_t)i * G + g;
+            const double c0 = rhoh[k];
+            double l = ix > 0 ? rhoh[k - G] : ghost_phi(s, XLO, g, c0);
+            double r = ix < nx - 1 ? rhoh[k + G] : ghost_phi(s, XHI, g, c0);
+            double ax = minmod(c0 - l, r - c0) / s->dx, ay = 0.0;
+            if (P->dim == 2) {
+                double b = iy > 0 ? rhoh[k - (size_t)nx * G] : ghost_phi(s, YLO, g, c0);
+                double t = iy < ny - 1 ? rhoh[k + (size_t)nx * G] : ghost_phi(s, YHI, g, c0);
+                ay = minmod(c0 - b, t - c0) / s->dy;
+            }
+            if (!(c0 > 0.0)) {
+                ax = 0.0;
+                ay = 0.0;
+            } else {
+                const double tot = fabs(ax) * s->dx + fabs(ay) * s->dy;
+                if (tot > 2.0 * c0) {
+                    const double f = 2.0 * c0 / tot;
+                    ax = ax * f;
+                    ay = ay * f;
+                }
+            }
+            sx[k] = ax;
+            if (sy) sy[k] = ay;
+        }
+    }
+}
+
+/* The wave part's free-transport flux (Sec. 2.2, F^{fr,wave}, with Remark 3's
+ * choice of coefficient) and the static source Q = rho^n + (dt/V) sum_f S_f F_in
+ * + w^{fr,p}/V of every cell and group, from the wave part rhoh.  Through a face
+ * with normal +axis between cells L and R:
+ *   F = (c/4eps) [A_L rho^h_L(face) - A_R rho^h_R(face)] + (c^2/6eps^2) [B_L s_L + B_R s_R]
+ * where rho^h(face) is the upwind cell's linear profile at the face and s its
+ * slope along the axis (angular moments 1/4 and 1/6 of an isotropic intensity
+ * over a half sphere), A = C4 - e^{-s} (or C4 unsampled), B = C5 + (dt/2) e^{-s}
+ * (or C5 unsampled).  Without slopes the second term and the profile vanish.
+ * A Planckian ghost holds phi(T_b) with the interior cell's s, coefficient C4
+ * (W when it emitted boundary particles); vacuum 0; a mirror no flux.
+ * Returns the energy flowing in through the domain boundary over the step. */
+static double wave_source(ora_sim* s, const double* rhoh, const double* sx, const double* sy,
+                          const double* A, const double* Bw, const double* sv,
+                          const unsigned char* gsamp, const double* wnet, double* Q)
+{
+    const ora_params* P = &s->p;
+    const int G = P->G, nc = s->ncell;
+    const double c = P->c, eps = P->eps, dt = P->dt, V = s->V;
+    const double cq = c / (4.0 * eps);
+    const double cs = c * c * dt / (6.0 * eps * eps);
+    double inflow = 0.0;
+    for (int i = 0; i < nc; ++i) {
+        nbface f[4];
+        int nf = cell_faces(s, i, f);
+        for (int g = 0; g < G; ++g) {
+            size_t k = (size_t)i * G + g;
+            double fsum = 0.0;   /* sum over faces of S * (flux into the cell) */
+            for (int q = 0; q < nf; ++q) {
+                /* outward sign: the LO faces have inward normal +axis */
+                int lo = (f[q].side == XLO || f[q].side == YLO);
+                double Fpos;
+                if (!sx) {
+                    double here = A[k] * rhoh[k];
+                    double there;
+                    if (f[q].nb >= 0) {
+                        size_t kn = (size_t)f[q].nb * G + g;
+                        there = A[kn] * rhoh[kn];
+                    } else {
+                        int bc = P->bc[f[q].side];
+                        if (bc == ORA_BC_REFLECT) continue;
+                        double Ag = gsamp && gsamp[k * 4 + f[q].side] ? ora_coef_w(sv[k]) : ora_coef_c4(sv[k]);
+                        there = (bc == ORA_BC_PLANCK) ? Ag * ghost_phi(s, f[q].side, g, 0.0) : 0.0;
+                    }
+                    /* flux along +axis through the face: cq (A_left rho^h_left - A_right rho^h_right) */
+                    Fpos = lo ? cq * (there - here) : cq * (here - there);
+                } else {
+                    const int xaxis = f[q].side == XLO || f[q].side == XHI;
+                    const double* sl = xaxis ? sx : sy;
+                    /* this cell is the right cell of a LO face and the left cell of a HI face */
+                    double here = A[k] * (rhoh[k] + (lo ? -0.5 : 0.5) * f[q].h * sl[k]);
+                    double hs = Bw[k] * sl[k];
+                    double there, ts = 0.0;
+                    if (f[q].nb >= 0) {
+                        size_t kn = (size_t)f[q].nb * G + g;
+                        there = A[kn] * (rhoh[kn] + (lo ? 0.5 : -0.5) * f[q].h * sl[kn]);
+                        ts = Bw[kn] * sl[kn];
+                    } else {
+                        int bc = P->bc[f[q].side];
+                        if (bc == ORA_BC_REFLECT) continue;
+                        double Ag = gsamp && gsamp[k * 4 + f[q].side] ? ora_coef_w(sv[k]) : ora_coef_c4(sv[k]);
+                        there = (bc == ORA_BC_PLANCK) ? Ag * ghost_phi(s, f[q].side, g, 0.0) : 0.0;
+                    }
+                    Fpos = lo ? cq * (there - here) + cs * (ts + hs) : cq * (here - there) + cs * (hs + ts);
+                }
+                double Fin = lo ? Fpos : -Fpos;
+                fsum += f[q].S * Fin;
+                if (f[q].nb < 0) inflow += dt * f[q].S * Fin / c;
+            }
+            Q[k] = s->rho[k] + (dt / V) * fsum + wnet[k] / V;
+        }
+    }
+    return inflow;
+}
+
+/* Place a new particle's position along the slope of its cell's wave part:
+ * density 1 + bx u + by v over the cell (u, v the offsets from the centre in
+ * cell widths), x from its marginal, y from its conditional given x; the same
+ * uniform draws as the uniform placement, which a zero slope reproduces. */
+static void place_on_slope(double xl, double dx, double yl, double dy, double bx, double by,
+                           double U0, double U1, int dim, double* x, double* y)
+{
+    double ux = 0.0;
+    if (bx == 0.0) {
+        *x = xl + U0 * dx;
+        ux = U0 - 0.5;
+    } else {
+        ux = ora_linear_offset(bx, U0);
+        *x = (xl + 0.5 * dx) + ux * dx;
+    }
+    if (dim == 2) {
+        const double bc = by / (1.0 + bx * ux);
+        if (bc == 0.0) *y = yl + U1 * dy;
+        else *y = (yl + 0.5 * dy) + ora_linear_offset(bc, U1) * dy;
+    }
+}
+
 static int step_once(ora_sim* s)
 {
     const ora_params* P = &s->p;
@@ -488,6 +716,18 @@ static int step_once(ora_sim* s)
     double* wnet = (double*)malloc(sizeof(double) * ncg);
     unsigned char* sampled = (unsigned char*)malloc(ncg);
     double* wsamp = (double*)malloc(sizeof(double) * ncg);
+    const int slopes = (P->flags & ORA_FLAG_SLOPES) != 0;
+    const int wave_iter = (P->flags & ORA_FLAG_WAVE_ITER) != 0;
+    const int bpart = (P->flags & ORA_FLAG_BOUNDARY_PARTICLES) != 0;
+    /* slope coefficient B of a sampled cell / 1 (Bw), slopes of rho^h (sx, sy) */
+    double* w5samp = slopes ? (double*)malloc(sizeof(double) * ncg) : NULL;
+    double* Bw = slopes ? (double*)malloc(sizeof(double) * ncg) : NULL;
+    double* sx = slopes ? (double*)malloc(sizeof(double) * ncg) : NULL;
+    double* sy = slopes && P->dim == 2 ? (double*)calloc(ncg, sizeof(double)) : NULL;
+    /* boundary-source particles: births per (cell, group) and side, and whether
+     * the ghost beyond that side sampled any */
+    int64_t* ngh = bpart ? (int64_t*)calloc(ncg * 4, sizeof(int64_t)) : NULL;
+    unsigned char* gsamp = bpart ? (unsigned char*)calloc(ncg * 4, 1) : NULL;
     for (int i = 0; i < nc; ++i)
         for (int g = 0; g < G; ++g) {
             size_t k = (size_t)i * G + g;
@@ -495,6 +735,7 @@ static int step_once(ora_sim* s)
             sv[k] = c * sig[k] * dt / (eps * eps);
             es[k] = exp(-sv[k]);
             wsamp[k] = ora_coef_w(sv[k]);
+            if (slopes) w5samp[k] = ora_coef_w5_over_dt(sv[k]);
         }
     /* Thin-thick-joint cells (Sec. 3.2, second case): the sampling fraction
      * e^{-dt/tau_num} with tau_num = tau + C * delta * dt, delta the largest
@@ -527,6 +768,8 @@ static int step_once(ora_sim* s)
                 double d = sv[k] - snum;
                 double diff = d < 0.5 ? exp(-sv[k]) * expm1(d) : exp(-snum) - exp(-sv[k]);
                 wsamp[k] = ora_coef_w(sv[k]) - diff;
+                /* the slope coefficient C5 + (dt/2) e^{-dt/tau_num} likewise */
+                if (slopes) w5samp[k] = ora_coef_w5_over_dt(sv[k]) + 0.5 * diff;
             }
         }
     }
@@ -548,17 +791,54 @@ static int step_once(ora_sim* s)
         sampled[k] = N >= 1;
         total += N;
     }
+    /* Boundary-source particles: the ghost cell beyond a Planckian side holds
+     * rho^h = phi(T_b) and the interior cell's opacity (the ghost of the wave
+     * flux), so its collisionless part e^{-s} phi(T_b) V is sampled like an
+     * interior cell's (same count rule and weight E/N).  Its births follow the
+     * interior births of the adjacent (cell, group), side by side. */
+    int64_t total_ghost = 0;
+    if (bpart) {
+        for (int i = 0; i < nc; ++i) {
+            int ix = i % P->nx, iy = i / P->nx;
+            for (int side = 0; side < 4; ++side) {
+                if (P->bc[side] != ORA_BC_PLANCK) continue;
+                int adj = side == XLO ? ix == 0 : side == XHI ? ix == P->nx - 1
+                        : side == YLO ? (P->dim == 2 && iy == 0) : (P->dim == 2 && iy == P->ny - 1);
+                if (!adj) continue;
+                for (int g = 0; g < G; ++g) {
+                    size_t k = (size_t)i * G + g;
+                    double e_over_v = exp(-sv[k]) * ghost_phi(s, side, g, 0.0);
+                    int64_t N = 0;
+                    if (e_over_v * V > 0.0) {
+                        double q = e_over_v / P->w_ref;
+                        if (q >= (double)P->n_cap) N = P->n_cap;
+                        else N = (int64_t)floor(q);
+                    }
+                    ngh[k * 4 + side] = N;
+                    gsamp[k * 4 + side] = N >= 1;
+                    s->nb[k] += N;
+                    total_ghost += N;
+                }
+            }
+        }
+    }
     int64_t n_old = s->np;
-    if (n_old + total > P->pool_cap) {
+    if (n_old + total + total_ghost > P->pool_cap) {
         free(sig); free(sv); free(es); free(wsamp); free(rhoh); free(A); free(wnet); free(sampled);
+        free(w5samp); free(Bw); free(sx); free(sy); free(ngh); free(gsamp);
         return ORA_EPOOL;
     }
     dg.n_alive_in = n_old;
-    dg.n_births = total;
+    dg.n_births = total + total_ghost;
+    dg.n_ghost_births = total_ghost;
+    if (slopes) wave_slopes(s, rhoh, sx, sy);
 
     /* ---- sample the collisionless wave particles (A2) ---- */
     int64_t slot = n_old;
     uint64_t id = s->nbirth;
+    int64_t n_all = n_old + total + total_ghost;
+    /* ghost side + 1 of every boundary-source particle of this step (0: not one) */
+    unsigned char* gside = bpart ? (unsigned char*)calloc((size_t)(n_all > 0 ? n_all : 1), 1) : NULL;
     for (int i = 0; i < nc; ++i) {
         int ix = i % P->nx, iy = i / P->nx;
         double xl = P->x0 + (double)ix * s->dx;
@@ -567,32 +847,64 @@ static int step_once(ora_sim* s)
             size_t k = (size_t)i * G + g;
             if (s->nb[k] == 0) continue;
             double nl = s->nu[g], nh = s->nu[g + 1];
-            double beta = ora_freq_slope(nl, nh, s->T[i]);
-            for (int64_t j = 0; j < s->nb[k]; ++j, ++id, ++slot) {
-                uint32_t st = (uint32_t)s->step;
-                s->px[slot] = xl + ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 0) * s->dx;
-                if (P->dim == 1) {
-                    s->pox[slot] = 2.0 * ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 1) - 1.0;
-                    s->py[slot] = 0.0;
-                    s->poy[slot] = 0.0;
-                    s->pnu[slot] = ora_sample_nu(nl, nh, beta, ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 2));
-                } else {
-                    s->py[slot] = yl + ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 1) * s->dy;
-                    double oz = 2.0 * ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 2) - 1.0;
-                    double psi = 6.283185307179586 * ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 3);
-                    double sn = sqrt(1.0 - oz * oz);
-                    s->pox[slot] = sn * cos(psi);
-                    s->poy[slot] = sn * sin(psi);
-                    s->pnu[slot] = ora_sample_nu(nl, nh, beta, ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 4));
+            /* the slopes of the wave part, in cell widths per rho^h */
+            double bx = 0.0, by = 0.0;
+            if (slopes && rhoh[k] > 0.0) {
+                bx = sx[k] * s->dx / rhoh[k];
+                if (P->dim == 2) by = sy[k] * s->dy / rhoh[k];
+            }
+            /* the interior births of (i, g), then those of the ghosts beyond
+             * its Planckian sides */
+            int64_t nint = s->nb[k];
+            if (bpart) for (int side = 0; side < 4; ++side) nint -= ngh[k * 4 + side];
+            for (int part = -1; part < 4; ++part) {
+                int64_t n = part < 0 ? nint : (bpart ? ngh[k * 4 + part] : 0);
+                if (n == 0) continue;
+                double Tq = part < 0 ? s->T[i] : P->bcT[part];
+                double beta = ora_freq_slope(nl, nh, Tq);
+                double wq = part < 0 ? s->wnew[k] : exp(-sv[k]) * ghost_phi(s, part, g, 0.0) * V / (double)n;
+                /* the cell the particles are placed in: the interior cell, or its
+                 * ghost one cell width beyond the side */
+                double cxl = xl, cyl = yl;
+                if (part == XLO) cxl = xl - s->dx;
+                if (part == XHI) cxl = xl + s->dx;
+                if (part == YLO) cyl = yl - s->dy;
+                if (part == YHI) cyl = yl + s->dy;
+                for (int64_t j = 0; j < n; ++j, ++id, ++slot) {
+                    uint32_t st = (uint32_t)s->step;
+                    double U0 = ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 0);
+                    double U1 = ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 1);
+                    double px, py = 0.0;
+                    if (part < 0 && (bx != 0.0 || by != 0.0)) {
+                        place_on_slope(cxl, s->dx, cyl, s->dy, bx, by, U0, U1, P->dim, &px, &py);
+                    } else {
+                        px = cxl + U0 * s->dx;
+                        if (P->dim == 2) py = cyl + U1 * s->dy;
+                    }
+                    s->px[slot] = px;
+                    if (P->dim == 1) {
+                        s->pox[slot] = 2.0 * U1 - 1.0;
+                        s->py[slot] = 0.0;
+                        s->poy[slot] = 0.0;
+                        s->pnu[slot] = ora_sample_nu(nl, nh, beta, ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 2));
+                    } else {
+                        s->py[slot] = py;
+                        double oz = 2.0 * ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 2) - 1.0;
+                        double psi = 6.283185307179586 * ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 3);
+                        double sn = sqrt(1.0 - oz * oz);
+                        s->pox[slot] = sn * cos(psi);
+                        s->poy[slot] = sn * sin(psi);
+                        s->pnu[slot] = ora_sample_nu(nl, nh, beta, ora_uniform(P->seed, id, st, ORA_PURPOSE_BIRTH, 4));
+                    }
+                    s->pw[slot] = wq;
+                    s->pid[slot] = id;
+                    s->pcell[slot] = i;
+                    s->pg[slot] = g;
+                    if (part >= 0) gside[slot] = (unsigned char)(part + 1);
                 }
-                s->pw[slot] = s->wnew[k];
-                s->pid[slot] = id;
-                s->pcell[slot] = i;
-                s->pg[slot] = g;
             }
         }
     }
-    int64_t n_all = n_old + total;
 
     /* ---- free transport of every particle (A3) ---- */
     size_t nfx = (size_t)(P->nx + 1) * P->ny, nfy = (size_t)P->nx * (P->ny + 1);
@@ -601,16 +913,19 @@ static int step_once(ora_sim* s)
     memset(s->dep, 0, sizeof(double) * ncg);
     memset(s->surv, 0, sizeof(double) * ncg);
     memset(s->start, 0, sizeof(double) * ncg);
-    double exit_w = 0.0;
+    double exit_w = 0.0, in_w = 0.0;
     int64_t ncross = 0, keep = 0;
     for (int64_t k = 0; k < n_all; ++k) {
         particle pp = { s->px[k], s->py[k], s->pox[k], s->poy[k], s->pnu[k], s->pw[k],
                         s->pid[k], s->pcell[k], s->pg[k] };
-        s->start[(size_t)pp.cell * G + pp.g] += pp.w;
-        int out = (P->dim == 1) ? push_1d(s, &pp, k >= n_old, &exit_w, &ncross)
-                                : push_2d(s, &pp, k >= n_old, &exit_w, &ncross);
+        const int gk = gside ? gside[k] : 0;
+        if (!gk) s->start[(size_t)pp.cell * G + pp.g] += pp.w;
+        int out = (P->dim == 1) ? push_1d(s, &pp, k >= n_old, gk, &exit_w, &in_w, &ncross)
+                                : push_2d(s, &pp, k >= n_old, gk, &exit_w, &in_w, &ncross);
+        if (gk && out != 3) dg.n_ghost_entered++;
         size_t kk = (size_t)pp.cell * G + pp.g;
-        if (out == 1) { s->dep[kk] += pp.w; dg.n_collided++; }
+        if (out == 3) { /* never entered */ }
+        else if (out == 1) { s->dep[kk] += pp.w; dg.n_collided++; }
         else if (out == 2) { dg.n_exited++; }
         else {
             s->surv[kk] += pp.w;
@@ -623,45 +938,22 @@ static int step_once(ora_sim* s)
     dg.n_alive_out = keep;
     dg.n_crossings = ncross;
     dg.exit_particles = exit_w / c;
+    dg.inflow_particles = in_w / c;
 
     /* ---- wave free-transport flux and the static source Q (A4) ---- */
-    const double cq = c / (4.0 * eps);
     for (size_t k = 0; k < ncg; ++k) A[k] = sampled[k] ? wsamp[k] : ora_coef_c4(sv[k]);
-    double inflow_wave = 0.0;
-    for (int i = 0; i < nc; ++i) {
-        nbface f[4];
-        int nf = cell_faces(s, i, f);
+    if (slopes)
+        for (size_t k = 0; k < ncg; ++k) Bw[k] = sampled[k] ? w5samp[k] : ora_coef_c5_over_dt(sv[k]);
+    for (int i = 0; i < nc; ++i)
         for (int g = 0; g < G; ++g) {
-            size_t k = (size_t)i * G + g;
-            double fsum = 0.0;   /* sum over faces of S * (flux into the cell) */
-            for (int q = 0; q < nf; ++q) {
-                /* outward sign: the LO faces have inward normal +axis */
-                int lo = (f[q].side == XLO || f[q].side == YLO);
-                double here = A[k] * rhoh[k];
-                double there;
-                if (f[q].nb >= 0) {
-                    size_t kn = (size_t)f[q].nb * G + g;
-                    there = A[kn] * rhoh[kn];
-                } else {
-                    int bc = P->bc[f[q].side];
-                    if (bc == ORA_BC_REFLECT) continue;
-                    there = (bc == ORA_BC_PLANCK)
-                                ? ora_coef_c4(sv[k]) * ghost_phi(s, f[q].side, g, 0.0)
-                                : 0.0;
-                }
-                /* flux along +axis through the face: cq (A_left rho^h_left - A_right rho^h_right) */
-                double Fpos = lo ? cq * (there - here) : cq * (here - there);
-                double Fin = lo ? Fpos : -Fpos;
-                fsum += f[q].S * Fin;
-                if (f[q].nb < 0) inflow_wave += dt * f[q].S * Fin / c;
-            }
             double in, out;
             cell_particle_flux(s, i, g, &in, &out);
-            wnet[k] = in - out;
-            s->Q[k] = s->rho[k] + (dt / V) * fsum + wnet[k] / V;
+            wnet[(size_t)i * G + g] = in - out;
         }
-    }
-    dg.inflow_wave = inflow_wave;
+    dg.inflow_wave = wave_source(s, rhoh, sx, sy, A, Bw, sv, gsamp, wnet, s->Q);
+    /* with the wave flux taken from the iterate (Algorithm 2), each sweep forms
+     * Q again from rho^{h,k} = rho^k - rho^p (k = 0: the above) */
+    double* rhk = wave_iter ? (double*)malloc(sizeof(double) * ncg) : NULL;
 
     /* ---- source iteration for Eq. macroSysFinal (A5; Appendix B, Algorithm 2) ---- */
     /* With a temperature-dependent opacity every sweep first recomputes sigma,
@@ -706,6 +998,11 @@ static int step_once(ora_sim* s)
     int converged = 0, sweeps = 0, bad = 0;
     double drho = 0, mrho = 0, dT = 0, mT = 0;
     for (int it = 0; it < P->si_max_iters; ++it) {
+        if (wave_iter && it > 0) {
+            for (size_t k = 0; k < ncg; ++k) rhk[k] = rk[k] - s->rhop[k];
+            if (slopes) wave_slopes(s, rhk, sx, sy);
+            dg.inflow_wave = wave_source(s, rhk, sx, sy, A, Bw, sv, gsamp, wnet, s->Q);
+        }
         if (tdep) {
             for (int i = 0; i < nc; ++i)
                 for (int g = 0; g < G; ++g) {
@@ -819,7 +1116,7 @@ static int step_once(ora_sim* s)
         dg.injection = inj;
         dg.e_start = e0;
         dg.e_end = e1;
-        dg.residual = e1 - e0 - (dg.inflow_wave + inflow_eq - dg.exit_particles + inj);
+        dg.residual = e1 - e0 - (dg.inflow_wave + inflow_eq + dg.inflow_particles - dg.exit_particles + inj);
         dg.sweeps = sweeps;
         dg.si_drho = drho; dg.si_rho = mrho; dg.si_dT = dT; dg.si_T = mT;
 
@@ -836,6 +1133,7 @@ static int step_once(ora_sim* s)
     }
     free(sig); free(sv); free(es); free(wsamp); free(rhoh); free(A); free(wnet); free(sampled);
     free(phi); free(phin); free(rk); free(Tk); free(Tn1); free(rn1); free(em); free(Df);
+    free(w5samp); free(Bw); free(sx); free(sy); free(ngh); free(gsamp); free(gside); free(rhk);
     if (tdep) { free(sigk); free(lam); }
     free(dph); free(bk);
     return status;
