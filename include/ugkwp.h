@@ -65,7 +65,7 @@ enum {
     UGKWP_FLAG_PHASE_TIMES = 4,  /* time every phase of a step with HIP events (the
                                     diag's ms_sample, ms_macro, ms_si, ms_sort);
                                     otherwise only the push is timed              */
-    UGKWP_FLAG_SI_LINEARIZED = 8 /* source iteration (Appendix B) with the emission
+    UGKWP_FLAG_SI_LINEARIZED = 8, /* source iteration (Appendix B) with the emission
                                     of T^{k+1} linearized about T^k, each sweep a
                                     local Newton step of every cell's energy
                                     balance: the same fixed point (Eq.
@@ -73,6 +73,23 @@ enum {
                                     sum_g dt sigma_g phi'_g / (eps^2 C_v
                                     (1 + lambda_g)) exceeds 1 (stiff material
                                     coupling, where the literal sweep diverges)   */
+    UGKWP_FLAG_SLOPES = 16,      /* second-order wave part (Sec. 2.2, the C5 terms):
+                                    MINMOD slopes of rho^h per axis (limited so the
+                                    linear profile stays non-negative in the cell),
+                                    the upwind profile's face value and the slope
+                                    term (C5, or C5 + dt/2 e^{-s} where sampled) in
+                                    the wave flux, new particles placed along the
+                                    slope                                          */
+    UGKWP_FLAG_WAVE_ITER = 32,   /* wave flux of each source-iteration sweep from
+                                    its iterate, rho^h = rho^k - rho^p (Algorithm 2),
+                                    instead of the start of the step                */
+    UGKWP_FLAG_BOUNDARY_PARTICLES = 64 /* a Planckian boundary's ghost cell samples its
+                                    collisionless share e^{-s} phi(T_b) V as
+                                    particles (count and weight as an interior
+                                    cell's), which fly straight to the domain face
+                                    and enter there within the step or are dropped;
+                                    the ghost's wave coefficient becomes
+                                    C4 - e^{-s}                                      */
 };
 
 typedef struct ugkwp_ctx ugkwp_ctx;
@@ -145,7 +162,8 @@ typedef struct {
     int sweeps_sum;          /* sum over instances                              */
     double e_start, e_end;   /* total energy sum V (sum_g rho/c + Cv T)        */
     double inflow_wave, inflow_eq, exit_particles, injection;
-    double residual;         /* e_end - e_start - (inflow_wave + inflow_eq - exit + injection) */
+    double residual;         /* e_end - e_start - (inflow_wave + inflow_eq + inflow_particles
+                                - exit + injection) */
     /* GPU time of the phases of the step, in ms, from HIP events on the context
      * stream: tally clears + count + scan + sample, the push kernel alone (events
      * recorded just before and after its launch, so the interval also holds its
@@ -160,6 +178,9 @@ typedef struct {
      * whether this step's ms_push holds a time. */
     double ms_sample, ms_push, ms_macro, ms_si, ms_sort;
     int push_timed;
+    double inflow_particles; /* energy of boundary-source particles that entered the
+                                domain (UGKWP_FLAG_BOUNDARY_PARTICLES); the residual
+                                adds it to the inflows                              */
 } ugkwp_diag;
 
 /* Running sums over the committed steps since the last reset, so that a caller

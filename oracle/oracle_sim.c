@@ -263,7 +263,7 @@ static int push_1d(ora_sim* s, particle* pp, int is_new, int ghost, double* exit
         const int right = ghost - 1 == XLO;       /* entering through the low face moves right */
         const double v = cv * mu;
         if (right ? !(v > 0) : !(v < 0)) return 3;
-        const double xf = right ? P->x0 : P->x1;
+        const double xf = right ? P->x0 : P->x0 + (double)nx * s->dx;   /* the domain faces as the cells' */
         const double te = (xf - x) / v;
         if (!(te < dt)) return 3;
         x = xf;
@@ -364,12 +364,14 @@ static int push_2d(ora_sim* s, particle* pp, int is_new, int ghost, double* exit
         const int lo = side == XLO || side == YLO;
         const double vn = xside ? vx : vy;
         if (lo ? !(vn > 0) : !(vn < 0)) return 3;
-        const double pf = xside ? (lo ? P->x0 : P->x1) : (lo ? P->y0 : P->y1);
+        /* the domain's faces and extent as the cells' faces are computed */
+        const double xend = P->x0 + (double)nx * s->dx, yend = P->y0 + (double)ny * s->dy;
+        const double pf = xside ? (lo ? P->x0 : xend) : (lo ? P->y0 : yend);
         const double te = (pf - (xside ? x : y)) / vn;
         if (!(te < dt)) return 3;
         if (xside) {
             double ye = y + vy * te;
-            if (ye < P->y0 || ye > P->y1) return 3;
+            if (ye < P->y0 || ye > yend) return 3;
             iy = (int)floor((ye - P->y0) / s->dy);
             if (iy > ny - 1) iy = ny - 1;
             if (iy < 0) iy = 0;
@@ -381,7 +383,7 @@ static int push_2d(ora_sim* s, particle* pp, int is_new, int ghost, double* exit
             s->ftx[((size_t)face * G + g) * 2 + (lo ? 0 : 1)] += pp->w;
         } else {
             double xe = x + vx * te;
-            if (xe < P->x0 || xe > P->x1) return 3;
+            if (xe < P->x0 || xe > xend) return 3;
             ix = (int)floor((xe - P->x0) / s->dx);
             if (ix > nx - 1) ix = nx - 1;
             if (ix < 0) ix = 0;
@@ -1127,7 +1129,7 @@ static int step_once(ora_sim* s)
         memcpy(s->T, Tn1, sizeof(double) * nc);
         for (size_t k = 0; k < ncg; ++k) s->rhop[k] = s->surv[k] / V;
         s->np = keep;
-        s->nbirth += (uint64_t)total;
+        s->nbirth += (uint64_t)(total + total_ghost);   /* every birth takes an id, entered or not */
         s->step++;
         s->diag = dg;
     }
@@ -1246,6 +1248,8 @@ int ora_record(ora_sim* s, int on)
     /* the frozen-tally map covers neither the joint cells' tau_num (a maximum
      * over T^n) nor a temperature-dependent opacity: not recorded */
     if (on && (s->p.tau_num_C > 0.0 || s->p.T_power != 0.0 || s->p.opacity_stim)) return ORA_EINVAL;
+    /* nor the slopes, the iterate's wave flux or boundary-source particles */
+    if (on && (s->p.flags & (ORA_FLAG_SLOPES | ORA_FLAG_WAVE_ITER | ORA_FLAG_BOUNDARY_PARTICLES))) return ORA_EINVAL;
     free_rec(s);
     s->recording = on ? 1 : 0;
     if (on) {

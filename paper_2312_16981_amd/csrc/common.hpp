@@ -107,6 +107,12 @@ constexpr int32_t FLIP_Y = 1 << 29;
 constexpr int32_t FLIP_X = 1 << 30;
 constexpr int32_t DEAD = -1;
 
+// The group word of a particle: the group in the low bits; a boundary-source
+// particle of this step (UGKWP_FLAG_BOUNDARY_PARTICLES) carries 1 + the side
+// of the ghost it was born in from bit GHOST_SHIFT until the push clears it.
+constexpr int GHOST_SHIFT = 8;
+constexpr int32_t GROUP_MASK = (1 << GHOST_SHIFT) - 1;
+
 // A particle pool viewed as structure of arrays.  The moving fields (x, y and
 // the cell word) live in one of two buffers that alternate between steps; the
 // stable fields (direction, frequency, weight, id, group) are only appended
@@ -151,6 +157,12 @@ struct Dev {
     int64_t* boff;              // exclusive scan of nb
     double* wnew;
     double* wsn;                // wave coefficient of a sampled slot this step (joint cells' tau_num)
+    double* sx;                 // slopes of rho^h along x and y (UGKWP_FLAG_SLOPES)
+    double* sy;
+    double* bcoef;              // slope coefficient of the wave flux: C5 or C5 + dt/2 e^{-s}, over dt
+    double* rho_alt;            // rho^k of the even sweeps with UGKWP_FLAG_WAVE_ITER
+    double* winflow;            // [2][slot] boundary wave inflow of the last even / odd sweep (WAVE_ITER)
+    int32_t* nbi;               // interior births per slot (nb adds the boundary-source births)
     double* beta;
     double* dep;
     double* surv;

@@ -230,6 +230,44 @@ __host__ __device__ inline double coef_c2_over_dt(double s)
     return (2.0 * coef_c4(s) - 1.0 - exp(-s)) / s;
 }
 
+// C5/dt of the slope term of the UGKS free-transport flux (Sec. 2.2):
+// -int_0^1 u e^{-s u} du = ((1 + s) e^{-s} - 1) / s^2.  Below s = 2 the
+// expansion -1/2 + s/3 - s^2/8 + ... = sum_n (-1)^{n+1} s^n / (n! (n+2)).
+__host__ __device__ inline double coef_c5(double s)
+{
+    if (s < 2.0) {
+        double p = 1.0, inv_fact = 1.0, sum = -0.5;      // n = 0 term
+        for (int n = 1; n < 80; ++n) {
+            p *= s;
+            inv_fact /= (double)n;
+            const double t = p * inv_fact / (double)(n + 2);
+            sum += (n & 1) ? t : -t;
+            if (t < 1e-18 * fabs(sum)) break;
+        }
+        return sum;
+    }
+    return ((1.0 + s) * exp(-s) - 1.0) / (s * s);
+}
+
+// (C5 + (dt/2) e^{-s}) / dt, the slope coefficient of the wave flux of a
+// sampled cell; below s = 2, sum_{n>=1} (-1)^n n s^n / (2 n! (n+2)) (the two
+// terms of the closed form cancel as s -> 0).
+__host__ __device__ inline double coef_w5(double s)
+{
+    if (s < 2.0) {
+        double p = 1.0, inv_fact = 1.0, sum = 0.0;
+        for (int n = 1; n < 80; ++n) {
+            p *= s;
+            inv_fact /= (double)n;
+            const double t = 0.5 * (double)n * p * inv_fact / (double)(n + 2);
+            sum += (n & 1) ? -t : t;
+            if (t < 1e-18 * fabs(sum)) break;
+        }
+        return sum;
+    }
+    return coef_c5(s) + 0.5 * exp(-s);
+}
+
 // Derivatives in s (for the adjoint of the macroscopic solve).  With
 // W/s -> 1/2 as s -> 0 taken from W's series below s = 1:
 //   C4' = -W/s,   W' = e^{-s} - W/s,   (C2/dt)' = (e^{-s} - 2 W/s - C2/dt) / s,
@@ -302,6 +340,17 @@ __host__ __device__ inline double sample_nu(double nl, double nh, double beta, d
     nu = nu < nl ? nl : nu;
     nu = nu > nh ? nh : nu;
     return nu;
+}
+
+// Offset u' in [-1/2, 1/2] whose CDF under the density 1 + beta u' is U
+// (the same quadratic as sample_nu); places new particles along the slope of
+// their cell's wave part.
+__host__ __device__ inline double linear_offset(double beta, double U)
+{
+    const double q = 0.5 - 0.125 * beta - U;
+    double disc = 1.0 - 2.0 * beta * q;
+    disc = disc < 0.0 ? 0.0 : disc;
+    return -2.0 * q / (1.0 + sqrt(disc));
 }
 
 // nu^-p with the exact cube for the paper's p = 3.

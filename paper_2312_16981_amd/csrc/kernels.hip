@@ -226,7 +226,7 @@ __global__ void k_init_rho(Dev D, Consts K, const double* Tr0)
 // coefficient of the slot when it samples, C4(s) - e^{-dt/tau_num} =
 // W(s) - (e^{-dt/tau_num} - e^{-s}), goes to wsn (W(s) outside joint cells).
 __device__ inline double joint_fraction(const Dev& D, const Consts& K, const Inst& I, const Slot& s, int64_t j,
-                                        double es, double T)
+                                        double es, double T, double* diff_out)
 {
     const int nx = I.nx, ix = s.lcell % nx, iy = s.lcell / nx, Gp = I.Gp;
     const double sg = D.sig[j];
@@ -243,16 +243,34 @@ __device__ inline double joint_fraction(const Dev& D, const Consts& K, const Ins
         const double d = fabs(T - Tn) / (T + Tn);
         if (d > delta) delta = d;
     }
-    double frac = es, w = D.wc[j];
+    double frac = es, w = D.wc[j], diff = 0.0;
     if (delta >= 0.0) {
         const double sv = D.sv[j];
         const double snum = sv / (1.0 + sv * K.tau_C * delta);
         frac = exp(-snum);
         const double dd = sv - snum;
-        w -= dd < 0.5 ? es * expm1(dd) : frac - es;
+        diff = dd < 0.5 ? es * expm1(dd) : frac - es;
+        w -= diff;
     }
     D.wsn[j] = w;
+    *diff_out = diff;
     return frac;
+}
+
+// Boundary-source particles: the ghost cell beyond Planckian side q of the
+// slot's cell (if the cell touches that side) holds rho^h = phi(T_b) with the
+// interior cell's opacity, and samples e^{-s} phi(T_b) V as an interior cell
+// would (the same count rule).  Returns its births (0 elsewhere).
+__device__ inline int ghost_births(const Dev& D, const Consts& K, const Inst& I, const Slot& s, int q, double es)
+{
+    if (I.bc[q] != BC_PLANCK) return 0;
+    const int nx = I.nx, ix = s.lcell % nx, iy = s.lcell / nx;
+    const bool adj = q == XLO ? ix == 0 : q == XHI ? ix == nx - 1 : q == YLO ? iy == 0 : iy == I.ny - 1;
+    if (!adj) return 0;
+    const double eov = es * D.phib[((int64_t)s.inst * 4 + q) * MAX_G + s.g];
+    if (!(eov * I.V > 0.0)) return 0;
+    const double qn = eov / I.w_ref;
+    return (qn >= (double)K.n_cap) ? (int)K.n_cap : (int)floor(qn);
 }
 
 // Also opens the step's record (block 0: the persistent entries from the
@@ -272,11 +290,12 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroLi
     const bool in = j < K.n_cg;
     Inst I;
     const Slot s = decode_slot_rec<SINGLE>(D, K, j, I);
-    double rho = 0.0, rhop = 0.0, es = 0.0, nl = 0.0, nh = 0.0, T = 0.0;
+    double rho = 0.0, rhop = 0.0, es = 0.0, nl = 0.0, nh = 0.0, T = 0.0, sv = 0.0;
     if (in && s.active) {
         rho = D.rho[j];
         rhop = D.rhop[j];
         es = D.es[j];
+        sv = D.sv[j];
         nl = D.nu[I.edge_off + s.g];
         nh = D.nu[I.edge_off + s.g + 1];
         T = D.T[I.cell_off + s.lcell];
@@ -305,22 +324,30 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroLi
     if (in) {
         if (!s.active) {
             D.nb[j] = 0;
+            D.nbi[j] = 0;
             D.rhoh[j] = 0.0;
             D.wnew[j] = 0.0;
         } else {
             const double rh = rho - rhop;
             D.rhoh[j] = rh;
-            double frac = es;
-            if (K.tau_C > 0.0) frac = joint_fraction(D, K, I, s, j, es, T);
+            double frac = es, diff = 0.0;
+            if (K.tau_C > 0.0) frac = joint_fraction(D, K, I, s, j, es, T, &diff);
             const double eov = frac * rh;
             const double E = eov * I.V;
             if (E > 0.0) {
                 const double q = eov / I.w_ref;
                 N = (q >= (double)K.n_cap) ? (int)K.n_cap : (int)floor(q);
             }
-            D.nb[j] = N;
+            D.nbi[j] = N;
             D.wnew[j] = N >= 1 ? E / (double)N : 0.0;
             if (N >= 1) D.beta[j] = freq_slope(nl, nh, T);
+            // slope coefficient of the wave flux (over dt): C5 + dt/2 e^{-dt/tau}
+            // where the slot samples (tau_num in joint cells), else C5
+            if (K.flags & UGKWP_FLAG_SLOPES) D.bcoef[j] = N >= 1 ? coef_w5(sv) + 0.5 * diff : coef_c5(sv);
+            // boundary-source particles of the ghosts beyond this cell's Planckian sides
+            if (K.flags & UGKWP_FLAG_BOUNDARY_PARTICLES)
+                for (int q = 0; q < 2 * I.dim; ++q) N += ghost_births(D, K, I, s, q, es);
+            D.nb[j] = N;
         }
     }
     if (part) {
@@ -547,23 +574,78 @@ __global__ void k_sample(Dev D, Consts K, Pool P)
     const int lcell = (int)(local >> I.lgGp), g = (int)(local & (I.Gp - 1));
     const uint64_t id = D.ist[inst].births + (uint64_t)(j - D.boff[I.cg_off]);
     const double nl = D.nu[I.edge_off + g], nh = D.nu[I.edge_off + g + 1];
-    const double beta = D.beta[cg];
     const int ix = lcell % I.nx, iy = lcell / I.nx;
-    const double xl = I.x0 + (double)ix * I.dx;
+    double xl = I.x0 + (double)ix * I.dx;
+    double yl = I.y0 + (double)iy * I.dy;
     const int64_t o = base + j;
+    // the slot's interior births come first, then those of the ghosts beyond
+    // its Planckian sides, side by side (boundary-source particles)
+    int part = -1;
+    double beta, w = D.wnew[cg];
+    const int64_t m = j - D.boff[cg];
+    if ((K.flags & UGKWP_FLAG_BOUNDARY_PARTICLES) && m >= D.nbi[cg]) {
+        int64_t rest = m - D.nbi[cg];
+        const double es = D.es[cg];
+        const Slot sl = {inst, lcell, g, true, true};
+        for (int q = 0; q < 2 * DIM; ++q) {
+            const int nq = ghost_births(D, K, I, sl, q, es);
+            if (rest < nq) {
+                part = q;
+                const double pb = D.phib[((int64_t)inst * 4 + q) * MAX_G + g];
+                w = es * pb * I.V / (double)nq;
+                break;
+            }
+            rest -= nq;
+        }
+        beta = freq_slope(nl, nh, I.bcT[part]);
+        if (part == XLO) xl = xl - I.dx;
+        if (part == XHI) xl = xl + I.dx;
+        if (part == YLO) yl = yl - I.dy;
+        if (part == YHI) yl = yl + I.dy;
+    } else {
+        beta = D.beta[cg];
+    }
+    // slopes of the wave part in cell widths per rho^h: the linear density the
+    // interior births are placed along (uniform where both are zero)
+    double bx = 0.0, by = 0.0;
+    if ((K.flags & UGKWP_FLAG_SLOPES) && part < 0) {
+        const double rh = D.rhoh[cg];
+        if (rh > 0.0) {
+            bx = D.sx[cg] * I.dx / rh;
+            if (DIM == 2) by = D.sy[cg] * I.dy / rh;
+        }
+    }
     double u0, u1, u2, u3;
     keyed_uniform_pair(I.seed, id, step, PURPOSE_BIRTH, 0, u0, u1);
+    double px, py = 0.0;
+    if (bx == 0.0 && by == 0.0) {
+        px = xl + u0 * I.dx;
+        if (DIM == 2) py = yl + u1 * I.dy;
+    } else {
+        // x from the marginal density 1 + bx u, y from its conditional given x
+        double ux;
+        if (bx == 0.0) {
+            px = xl + u0 * I.dx;
+            ux = u0 - 0.5;
+        } else {
+            ux = linear_offset(bx, u0);
+            px = (xl + 0.5 * I.dx) + ux * I.dx;
+        }
+        if (DIM == 2) {
+            const double bc = by / (1.0 + bx * ux);
+            py = bc == 0.0 ? yl + u1 * I.dy : (yl + 0.5 * I.dy) + linear_offset(bc, u1) * I.dy;
+        }
+    }
     if (DIM == 1) {
         u2 = keyed_uniform(I.seed, id, step, PURPOSE_BIRTH, 2);
-        P.x[o] = xl + u0 * I.dx;
+        P.x[o] = px;
         P.ox[o] = 2.0 * u1 - 1.0;
         P.nu[o] = sample_nu(nl, nh, beta, u2);
     } else {
-        const double yl = I.y0 + (double)iy * I.dy;
         keyed_uniform_pair(I.seed, id, step, PURPOSE_BIRTH, 2, u2, u3);
         const double u4 = keyed_uniform(I.seed, id, step, PURPOSE_BIRTH, 4);
-        P.x[o] = xl + u0 * I.dx;
-        P.y[o] = yl + u1 * I.dy;
+        P.x[o] = px;
+        P.y[o] = py;
         const double oz = 2.0 * u2 - 1.0;
         const double psi = 6.283185307179586 * u3;
         const double sn = sqrt(1.0 - oz * oz);
@@ -571,11 +653,70 @@ __global__ void k_sample(Dev D, Consts K, Pool P)
         P.oy[o] = sn * sin(psi);
         P.nu[o] = sample_nu(nl, nh, beta, u4);
     }
-    P.w[o] = D.wnew[cg];
+    P.w[o] = w;
     P.id[o] = id;
     P.cell[o] = I.cell_off + lcell;
-    P.g[o] = g;
+    // a boundary-source particle carries its ghost side + 1 above the group bits
+    P.g[o] = part < 0 ? g : (g | ((part + 1) << GHOST_SHIFT));
     }
+}
+
+// ---------------------------------------------------------------------------
+// Slopes of the wave part (UGKWP_FLAG_SLOPES): MINMOD of the differences of
+// rho^h to the two neighbours along each axis, with the boundary ghost one cell
+// width away (Planckian phi(T_b), vacuum 0, reflective the mirror image), then
+// scaled so that the linear profile stays non-negative over the cell
+// (|s_x| dx + |s_y| dy <= 2 rho^h); zero where rho^h <= 0.  rho^h of a slot is
+// src[j], minus rhop[j] when sub_rhop (the iterate's wave part, Algorithm 2).
+__device__ inline double minmod_diff(double a, double b)
+{
+    if (!(a * b > 0.0)) return 0.0;
+    return fabs(a) < fabs(b) ? a : b;
+}
+
+template <int DIM>
+__global__ void k_slopes(Dev D, Consts K, const double* src, int sub_rhop)
+{
+    if (!gate_open(D, K, 0)) return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= K.n_cg) return;
+    const Slot s = decode_slot(D, K, j);
+    if (!s.active) {
+        D.sx[j] = 0.0;
+        D.sy[j] = 0.0;
+        return;
+    }
+    const Inst& I = D.inst[s.inst];
+    if (sub_rhop && D.ist[s.inst].conv_sweeps != 0) return;     // converged: not used
+    const int nx = I.nx, ix = s.lcell % nx, iy = s.lcell / nx, Gp = I.Gp, g = s.g;
+    const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
+    auto rh = [&](int64_t k) { return sub_rhop ? src[k] - D.rhop[k] : src[k]; };
+    auto ghost = [&](int q, double c0) {
+        return I.bc[q] == BC_PLANCK ? phib[q * MAX_G + g] : (I.bc[q] == BC_REFLECT ? c0 : 0.0);
+    };
+    const double c0 = rh(j);
+    const double l = ix > 0 ? rh(j - Gp) : ghost(XLO, c0);
+    const double r = ix < nx - 1 ? rh(j + Gp) : ghost(XHI, c0);
+    double ax = minmod_diff(c0 - l, r - c0) / I.dx, ay = 0.0;
+    if (DIM == 2) {
+        const int64_t row = (int64_t)nx * Gp;
+        const double b = iy > 0 ? rh(j - row) : ghost(YLO, c0);
+        const double t = iy < I.ny - 1 ? rh(j + row) : ghost(YHI, c0);
+        ay = minmod_diff(c0 - b, t - c0) / I.dy;
+    }
+    if (!(c0 > 0.0)) {
+        ax = 0.0;
+        ay = 0.0;
+    } else {
+        const double tot = fabs(ax) * I.dx + fabs(ay) * I.dy;
+        if (tot > 2.0 * c0) {
+            const double f = 2.0 * c0 / tot;
+            ax = ax * f;
+            ay = ay * f;
+        }
+    }
+    D.sx[j] = ax;
+    D.sy[j] = ay;
 }
 
 // ---------------------------------------------------------------------------
@@ -767,6 +908,67 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTabl
     }
 }
 
+// A boundary-source particle born in the ghost cell beyond `side`: it flies
+// straight (a new particle: no collision in the ghost) to the domain face;
+// if it meets the face within the step at a point of the domain's extent, the
+// crossing is tallied there, it stands in the cell it enters at the time it
+// entered, and its flight is drawn in that cell (Remark 1).  Returns false for
+// a particle that never enters (dropped without a tally).  The domain's faces
+// are computed as the cells' faces are.
+template <int DIM, int SM>
+__device__ inline bool enter_from_ghost(const Dev& D, const Consts& K, const Geo& I, TallyTable& T, uint64_t id,
+                                        uint32_t step, double tfac, int g, double nu, double w, int side,
+                                        Flight& f)
+{
+    const bool xside = side == XLO || side == XHI;
+    const bool lo = side == XLO || side == YLO;
+    const double vx = K.cv * f.ox, vy = DIM == 2 ? K.cv * f.oy : 0.0;
+    const double vn = xside ? vx : vy;
+    if (lo ? !(vn > 0) : !(vn < 0)) return false;
+    const double xend = I.x0 + (double)I.nx * I.dx;
+    const double yend = DIM == 2 ? I.y0 + (double)I.ny * I.dy : 0.0;
+    const double pf = xside ? (lo ? I.x0 : xend) : (lo ? I.y0 : yend);
+    const double te = (pf - (xside ? f.x : f.y)) / vn;
+    if (!(te < K.dt)) return false;
+    uint32_t type, index;
+    if (xside) {
+        if (DIM == 2) {
+            const double ye = f.y + vy * te;
+            if (ye < I.y0 || ye > yend) return false;
+            int iy = (int)floor((ye - I.y0) / I.dy);
+            iy = iy > I.ny - 1 ? I.ny - 1 : (iy < 0 ? 0 : iy);
+            const double yl = I.y0 + (double)iy * I.dy, yr = I.y0 + (double)(iy + 1) * I.dy;
+            f.y = ye < yl ? yl : (ye > yr ? yr : ye);
+            f.iy = iy;
+        }
+        f.x = pf;
+        f.ix = lo ? 0 : I.nx - 1;
+        const uint32_t face = (uint32_t)(f.iy * (I.nx + 1) + (lo ? 0 : I.nx));
+        type = TAL_FX;
+        index = ((I.fx_off + (face << I.lgGp) + (uint32_t)g) << 1) + (lo ? 0u : 1u);
+    } else {
+        const double xe = f.x + vx * te;
+        if (xe < I.x0 || xe > xend) return false;
+        int ix = (int)floor((xe - I.x0) / I.dx);
+        ix = ix > I.nx - 1 ? I.nx - 1 : (ix < 0 ? 0 : ix);
+        const double xl = I.x0 + (double)ix * I.dx, xr = I.x0 + (double)(ix + 1) * I.dx;
+        f.x = xe < xl ? xl : (xe > xr ? xr : xe);
+        f.ix = ix;
+        f.y = pf;
+        f.iy = lo ? 0 : I.ny - 1;
+        const uint32_t face = (uint32_t)((lo ? 0 : I.ny) * I.nx + f.ix);
+        type = TAL_FY;
+        index = ((I.fy_off + (face << I.lgGp) + (uint32_t)g) << 1) + (lo ? 0u : 1u);
+    }
+    lds_tally(T, D, type, index, w);
+    f.t = te;
+    const int lcell = f.iy * I.nx + f.ix;
+    f.tau = tfac * D.inv_kappa[I.cg_off + ((uint32_t)lcell << I.lgGp) + (uint32_t)g];
+    if (SM == SIG_STIM) f.tau = f.tau / stim_factor(K, nu, D.T[I.cell_off + lcell]);
+    draw_flight(K, I, id, step, f);
+    return true;
+}
+
 // One pool record as the push reads it (every field, also for an empty slot:
 // all slots below the capacity are allocated, and the values are then unused).
 // Element i of a pool array by a 32-bit byte offset from the array's base (the
@@ -876,7 +1078,8 @@ __global__ __launch_bounds__(BS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool
                     cur.w = at(In.w, iu);
                     cur.id = at(In.id, iu);
                 }
-                const int g = cur.g;
+                const int g = cur.g & GROUP_MASK;
+                const int gside = cur.g >> GHOST_SHIFT;    // boundary-source particle: 1 + ghost side
                 const Geo I = SINGLE ? geo0 : geo_of(D.inst[D.cell_inst[cell]]);
                 Flight f;
                 f.x = cur.x;
@@ -899,10 +1102,22 @@ __global__ __launch_bounds__(BS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool
                 const double tfac = tau_factor<SM>(D, K, I, nu, g);
                 f.tau = tfac * D.inv_kappa[I.cg_off + ((uint32_t)lcell << I.lgGp) + (uint32_t)g];
                 if (SM == SIG_STIM) f.tau = f.tau / stim_factor(K, nu, D.T[cell]);
-                if (i < n_slots) draw_flight(K, I, id, step, f);    // old particle: t_f = min(-tau ln eta, dt)
-                else { f.coll = false; f.t_rem = K.dt; }            // new collisionless particle: t_f = dt
-                const int out = fly<DIM, SM>(D, K, I, T, id, step, tfac, g, nu, w, f);
-                if (out != 2) {
+                int out;
+                if (gside && !enter_from_ghost<DIM, SM>(D, K, I, T, id, step, tfac, g, nu, w, gside - 1, f)) {
+                    out = 3;                                        // never entered the domain
+                } else {
+                    if (gside) {
+                        // entered: its flight is drawn; the group word loses the ghost mark
+                        at(In.g, iu) = g;
+                    } else if (i < n_slots) {
+                        draw_flight(K, I, id, step, f);             // old particle: t_f = min(-tau ln eta, dt)
+                    } else {
+                        f.coll = false;                             // new collisionless particle: t_f = dt
+                        f.t_rem = K.dt;
+                    }
+                    out = fly<DIM, SM>(D, K, I, T, id, step, tfac, g, nu, w, f);
+                }
+                if (out < 2) {
                     const uint32_t cg = I.cg_off + ((uint32_t)(f.iy * I.nx + f.ix) << I.lgGp) + (uint32_t)g;
                     has = true;
                     tkey = (cg << 2) | (out == 0 ? TAL_SURV : TAL_DEP);
@@ -1092,32 +1307,52 @@ __device__ inline CellFaces cell_faces(const Inst& I, int64_t j, int ix, int iy,
 // coefficient C4 - e^{-s} where the cell sampled particles, C4 where it did
 // not).  *inflow gets the energy the wave flux brings in through the domain
 // boundary.
-template <int DIM>
+// EXT: compiled with the slope terms and the boundary-source ghosts (which the
+// flags then switch); without it the base flux only, at fewer registers.
+template <int DIM, bool EXT>
 __device__ inline double wave_source(const Dev& D, const Consts& K, const Inst& I, int64_t j, const Slot& s,
-                                     const CellFaces& F, double* inflow_out)
+                                     const CellFaces& F, double* inflow_out, const double* src, bool sub_rhop)
 {
     const int g = s.g, nx = I.nx;
     const int ix = DIM == 1 ? s.lcell : s.lcell % nx, iy = DIM == 1 ? 0 : s.lcell / nx;
     const double cq = K.cq;
     const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
     constexpr int nf = 2 * DIM;
+    const bool slopes = EXT && (K.flags & UGKWP_FLAG_SLOPES) != 0;
+    const bool bpart = EXT && (K.flags & UGKWP_FLAG_BOUNDARY_PARTICLES) != 0;
     // every load first
     // the wave coefficient of a sampled slot: W(s), or this step's joint-cell value
     const double* wsamp = K.tau_C > 0.0 ? D.wsn : D.wc;
-    const int nb_here = D.nb[j];
-    const double wc_here = wsamp[j], c4_here = D.c4[j], rhoh_here = D.rhoh[j], rho_here = D.rho[j];
+    const int nb_here = D.nbi[j];
+    const double wc_here = wsamp[j], c4_here = D.c4[j], rho_here = D.rho[j];
+    const double rhoh_here = sub_rhop ? src[j] - D.rhop[j] : src[j];
+    double sl_here[2] = {0.0, 0.0}, b_here = 0.0, es_here = 0.0, wphys_here = 0.0;
+    if (slopes) {
+        sl_here[0] = D.sx[j];
+        if (DIM == 2) sl_here[1] = D.sy[j];
+        b_here = D.bcoef[j];
+    }
+    if (bpart) {
+        es_here = D.es[j];
+        wphys_here = D.wc[j];
+    }
     int nb_n[4];
-    double wc_n[4], c4_n[4], rhoh_n[4], pb[4];
+    double wc_n[4], c4_n[4], rhoh_n[4], pb[4], sl_n[4], b_n[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         nb_n[q] = 0;
-        wc_n[q] = c4_n[q] = rhoh_n[q] = pb[q] = 0.0;
+        wc_n[q] = c4_n[q] = rhoh_n[q] = pb[q] = sl_n[q] = b_n[q] = 0.0;
         if (q >= nf) continue;
         if (F.inside[q]) {
-            nb_n[q] = D.nb[F.nbj[q]];
-            wc_n[q] = wsamp[F.nbj[q]];
-            c4_n[q] = D.c4[F.nbj[q]];
-            rhoh_n[q] = D.rhoh[F.nbj[q]];
+            const int64_t n = F.nbj[q];
+            nb_n[q] = D.nbi[n];
+            wc_n[q] = wsamp[n];
+            c4_n[q] = D.c4[n];
+            rhoh_n[q] = sub_rhop ? src[n] - D.rhop[n] : src[n];
+            if (slopes) {
+                sl_n[q] = q < 2 ? D.sx[n] : D.sy[n];
+                b_n[q] = D.bcoef[n];
+            }
         } else if (I.bc[q] == BC_PLANCK) {
             pb[q] = phib[q * MAX_G + g];
         }
@@ -1135,22 +1370,46 @@ __device__ inline double wave_source(const Dev& D, const Consts& K, const Inst& 
     }
     const double Ah = nb_here > 0 ? wc_here : c4_here;
     const double here = Ah * rhoh_here;
+    const double cs = K.c * K.c * K.dt / (6.0 * K.eps * K.eps);
     double fsum = 0.0, inflow = 0.0;
-    // flux through a face along +axis is cq (A_low rho^h_low - A_high rho^h_high)
+    // flux through a face along +axis: cq (A_low rho^h_low - A_high rho^h_high), with
+    // slopes the upwind profiles at the face and cs (B_low s_low + B_high s_high)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (q >= nf) continue;
         const bool lo = (q & 1) == 0;
+        double Fpos;
         double there;
-        if (F.inside[q]) {
-            const double An = nb_n[q] > 0 ? wc_n[q] : c4_n[q];
-            there = An * rhoh_n[q];
-        } else {
+        if (!F.inside[q]) {
             const int bc = I.bc[q];
             if (bc == BC_REFLECT) continue;
-            there = bc == BC_PLANCK ? c4_here * pb[q] : 0.0;
+            // a Planckian ghost that emitted boundary-source particles keeps C4 - e^{-s}
+            double Ag = c4_here;
+            if (bpart && bc == BC_PLANCK) {
+                const double eov = es_here * pb[q];
+                if (eov * I.V > 0.0 && K.n_cap >= 1 && eov / I.w_ref >= 1.0) Ag = wphys_here;
+            }
+            there = bc == BC_PLANCK ? Ag * pb[q] : 0.0;
         }
-        const double Fpos = lo ? cq * (there - here) : cq * (here - there);
+        if (!slopes) {
+            if (F.inside[q]) {
+                const double An = nb_n[q] > 0 ? wc_n[q] : c4_n[q];
+                there = An * rhoh_n[q];
+            }
+            Fpos = lo ? cq * (there - here) : cq * (here - there);
+        } else {
+            const double slh = sl_here[q >> 1], h = q < 2 ? I.dx : I.dy;
+            // this cell is the high cell of a LO face and the low cell of a HI face
+            const double hv = Ah * (rhoh_here + (lo ? -0.5 : 0.5) * h * slh);
+            const double hs = b_here * slh;
+            double ts = 0.0;
+            if (F.inside[q]) {
+                const double An = nb_n[q] > 0 ? wc_n[q] : c4_n[q];
+                there = An * (rhoh_n[q] + (lo ? 0.5 : -0.5) * h * sl_n[q]);
+                ts = b_n[q] * sl_n[q];
+            }
+            Fpos = lo ? cq * (there - hv) + cs * (ts + hs) : cq * (hv - there) + cs * (hs + ts);
+        }
         const double Fin = lo ? Fpos : -Fpos;
         fsum += F.S[q] * Fin;
         if (!F.inside[q]) inflow += K.dt * F.S[q] * Fin / K.c;
@@ -1163,6 +1422,28 @@ __device__ inline double wave_source(const Dev& D, const Consts& K, const Inst& 
     }
     *inflow_out = inflow;
     return rho_here + I.dt_V * fsum + (a_in - a_out) / I.V;
+}
+
+// Q of sweep k >= 1 with UGKWP_FLAG_WAVE_ITER: the wave flux from the iterate
+// rho^k (src) less rho^p (Algorithm 2), and the boundary wave inflow of the
+// sweep into winflow[k & 1] (the commit takes that of the last sweep).
+// Instances whose iteration has converged are left alone.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_wave_q(Dev D, Consts K, int k, const double* src)
+{
+    if (!gate_open(D, K, 0)) return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= K.n_cg) return;
+    const Slot s = decode_slot(D, K, j);
+    if (!s.cell_ok || !s.active) return;
+    if (D.ist[s.inst].conv_sweeps != 0) return;
+    const Inst& I = D.inst[s.inst];
+    const int nx = I.nx;
+    const int ix = DIM == 1 ? s.lcell : s.lcell % nx, iy = DIM == 1 ? 0 : s.lcell / nx;
+    const CellFaces F = cell_faces<DIM>(I, j, ix, iy, s.g);
+    double inflow = 0.0;
+    D.Q[j] = wave_source<DIM, true>(D, K, I, j, s, F, &inflow, src, true);
+    D.winflow[(int64_t)(k & 1) * K.n_cg + j] = inflow;
 }
 
 // ---------------------------------------------------------------------------
@@ -1214,9 +1495,10 @@ __device__ inline bool si_converged(const Dev& D, const Consts& K, int inst, int
 // as phi^k + phi'(T^k) (T^{k+1} - T^k) and solves each cell's energy balance
 // for T^{k+1}, a local Newton step with the literal iteration's fixed point
 // (Eq. macroSysFinal) that also converges under stiff material coupling.
-template <bool FIRST, bool SINGLE, int DIM, bool TDEP, bool LIN>
+template <bool FIRST, bool SINGLE, int DIM, bool TDEP, bool LIN, bool EXT>
 __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k, const double* phi_in,
-                                                          double* phi_out, int decide_prev)
+                                                          double* phi_out, int decide_prev, const double* rho_in,
+                                                          double* rho_out)
 {
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const int64_t j = (int64_t)blockIdx.x * SI_THREADS + threadIdx.x;
@@ -1282,7 +1564,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         if (!FIRST) Qj = D.Q[j];
         lam = D.sv[j];
         sig = D.sig[j];
-        rho_prev = FIRST ? D.rho[j] : D.rho_new[j];
+        rho_prev = rho_in[j];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q >= nf) continue;
@@ -1320,7 +1602,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         if (g == G - 1 && G == Gp) nu_top = D.nu[I.edge_off + G];
     }
     double inflow = 0.0;
-    if (FIRST && act) Qj = wave_source<DIM>(D, K, I, j, s, F, &inflow);
+    if (FIRST && act) Qj = wave_source<DIM, EXT>(D, K, I, j, s, F, &inflow, D.rhoh, false);
 
     const bool run = wave_on && cs_inst == 0 && j < K.n_cg;
     double dr = 0.0, mr = 0.0, dT = 0.0, mT = 0.0;
@@ -1420,9 +1702,12 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     }
     if (work && s.active) {
         if (FIRST) D.Q[j] = Qj;
-        D.rho_new[j] = r;
+        rho_out[j] = r;
         phi_out[j] = phi_new;
-        if (inflow != 0.0)
+        // the boundary wave inflow: summed here, or with the wave flux of every
+        // sweep from its iterate kept per slot for the commit (that of the last sweep)
+        if (FIRST && (K.flags & UGKWP_FLAG_WAVE_ITER)) D.winflow[j] = inflow;
+        else if (inflow != 0.0)
             atomicAdd(D.diag_sub + ((int64_t)s.inst * DIAG_SUB + (blockIdx.x & (DIAG_SUB - 1))) * 8 + 0, inflow);
     }
     if (work && g == 0) {
@@ -1527,10 +1812,12 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
     bool bnd[4] = {false, false, false, false};
     int64_t fs[4] = {0, 0, 0, 0};
     double Df[4] = {0.0, 0.0, 0.0, 0.0}, tal[4] = {0.0, 0.0, 0.0, 0.0}, pb[4] = {0.0, 0.0, 0.0, 0.0};
+    double tal_in[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool witer = (K.flags & UGKWP_FLAG_WAVE_ITER) != 0;
     if (in && s.active) {
         surv = D.surv[j];
         rho = D.rho[j];
-        rho_new = D.rho_new[j];
+        if (!witer) rho_new = D.rho_new[j];
         pin = D.pinned[cell];
         if (g == 0) {
             cv = D.cvol[cell];
@@ -1548,6 +1835,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
                               : I.fy_off + (((int64_t)(iy + (lo ? 0 : 1)) * nx + ix) << I.lgGp) + g;
             Df[q] = axis == 0 ? D.Dx[fs[q]] : D.Dy[fs[q]];
             tal[q] = (axis == 0 ? D.ftx : D.fty)[fs[q] * 2 + (lo ? 1 : 0)];
+            tal_in[q] = (axis == 0 ? D.ftx : D.fty)[fs[q] * 2 + (lo ? 0 : 1)];
             if (I.bc[q] == BC_PLANCK) pb[q] = phib[q * MAX_G + g];
         }
     }
@@ -1558,9 +1846,15 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
     // state, or converged at the last sweep (decided below); batches have it
     // per instance
     const int ns_guess = last_sweep >= 0 ? (cs0 != 0 ? cs0 : last_sweep + 1) : cs_inst;
+    double winf = 0.0;
     if (in && s.active && ns_guess >= 1) {
         phi = sweep_in(D, ns_guess - 1)[j];          // phi^k of the last sweep
         phi_next = sweep_out(D, ns_guess - 1)[j];    // phi(T^{n+1}): the next step's phi^0
+        if (witer) {
+            // the last sweep's output and the boundary wave inflow of its wave flux
+            rho_new = ((ns_guess & 1) ? D.rho_new : D.rho_alt)[j];
+            winf = D.winflow[(int64_t)((ns_guess - 1) & 1) * K.n_cg + j];
+        }
     }
     int ns_single = 0;
     if (last_sweep >= 0) {
@@ -1614,7 +1908,10 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
             D.counters[CNT_DONE] = n1;
         }
     }
-    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // inflow_eq, exit/c, injection, e0, e1
+    // the commit's rho^{n+1} lives in rho_new
+    if (witer && in && s.active && !(ns_guess & 1)) D.rho_new[j] = rho_new;
+    double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // inflow_eq, exit/c, injection, e0, e1,
+                                                         // inflow_wave (WAVE_ITER), inflow_particles
     if (in && s.active && (K.t_power != 0.0 || K.stim) && (bnd[0] || bnd[1] || bnd[2] || bnd[3])) {
         // temperature-dependent opacity: the boundary faces' coefficients at the
         // step's final temperature (the iteration has converged on it)
@@ -1633,7 +1930,9 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
             const double pn = bc == BC_PLANCK ? pb[q] : (bc == BC_REFLECT ? phi : 0.0);
             v[0] += K.dt * S * Df[q] * (pn - phi) / K.c;
             v[1] += tal[q] / K.c;
+            v[6] += tal_in[q] / K.c;
         }
+        v[5] = winf;
         if (pin) v[2] = I.V * (K.dt * D.sig[j] / (K.eps * K.eps)) * (phi - rho_new);
         v[3] = I.V * rho / K.c;
         v[4] = I.V * rho_new / K.c;
@@ -1642,13 +1941,17 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
             v[4] += I.V * cv * T1;
         }
     }
+    // the diag entry of each sum: inflow_eq 1, exit 2, injection 3, e_start 4,
+    // e_end 5, inflow_wave 0, inflow_particles 6
+    constexpr int NV = 7;
+    const int dst[NV] = {1, 2, 3, 4, 5, 0, 6};
 #pragma unroll
-    for (int q = 0; q < 5; ++q) v[q] = wave_sum(v[q]);
-    __shared__ double wsum[DIAG_THREADS / WAVE][5];
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+    __shared__ double wsum[DIAG_THREADS / WAVE][NV];
     __shared__ int winst[DIAG_THREADS / WAVE];
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     if (lane == 0) {
-        for (int q = 0; q < 5; ++q) wsum[wid][q] = v[q];
+        for (int q = 0; q < NV; ++q) wsum[wid][q] = v[q];
         winst[wid] = j < K.n_cg ? s.inst : -1;
     }
     __syncthreads();
@@ -1657,15 +1960,15 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
         int w0 = 0;
         while (w0 < nw) {
             int w1 = w0;
-            double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            double acc[NV] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             while (w1 < nw && winst[w1] == winst[w0]) {
-                for (int q = 0; q < 5; ++q) acc[q] += wsum[w1][q];
+                for (int q = 0; q < NV; ++q) acc[q] += wsum[w1][q];
                 ++w1;
             }
             if (winst[w0] >= 0) {
                 double* dg = D.diag_sub + ((int64_t)winst[w0] * DIAG_SUB + (blockIdx.x & (DIAG_SUB - 1))) * 8;
-                for (int q = 0; q < 5; ++q)
-                    if (acc[q] != 0.0) atomicAdd(dg + 1 + q, acc[q]);
+                for (int q = 0; q < NV; ++q)
+                    if (acc[q] != 0.0) atomicAdd(dg + dst[q], acc[q]);
             }
             w0 = w1;
         }
@@ -1793,6 +2096,12 @@ void launch_scan(const ScanGate& q, const int32_t* in, int64_t n, int64_t* part,
     k_scan_partials<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(q, in, n, part);
     k_scan_top<<<1, SCAN_THREADS, 0, st>>>(q, part, nb, total);
     k_scan_final<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(q, in, n, part, out);
+}
+
+void launch_slopes(int dim, const Dev& D, const Consts& K, const double* src, bool sub_rhop, hipStream_t st)
+{
+    if (dim == 1) k_slopes<1><<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K, src, sub_rhop ? 1 : 0);
+    else k_slopes<2><<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K, src, sub_rhop ? 1 : 0);
 }
 
 void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, hipStream_t st)
@@ -1923,26 +2232,55 @@ void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& In,
     }
 }
 
+template <bool TDEP, bool LIN, bool EXT>
+static auto sweep_kernel_ext(const Consts& K, bool fold, int k)
+{
+    return K.inst0.dim == 1
+               ? (fold ? (k == 0 ? k_si_sweep<true, true, 1, TDEP, LIN, EXT> : k_si_sweep<false, true, 1, TDEP, LIN, false>)
+                       : (k == 0 ? k_si_sweep<true, false, 1, TDEP, LIN, EXT> : k_si_sweep<false, false, 1, TDEP, LIN, false>))
+               : (fold ? (k == 0 ? k_si_sweep<true, true, 2, TDEP, LIN, EXT> : k_si_sweep<false, true, 2, TDEP, LIN, false>)
+                       : (k == 0 ? k_si_sweep<true, false, 2, TDEP, LIN, EXT> : k_si_sweep<false, false, 2, TDEP, LIN, false>));
+}
+
+// the first sweep evaluates the wave flux: with slope terms or boundary-source
+// ghosts, its extended instantiation
 template <bool TDEP, bool LIN>
 static auto sweep_kernel(const Consts& K, bool fold, int k)
 {
-    return K.inst0.dim == 1
-               ? (fold ? (k == 0 ? k_si_sweep<true, true, 1, TDEP, LIN> : k_si_sweep<false, true, 1, TDEP, LIN>)
-                       : (k == 0 ? k_si_sweep<true, false, 1, TDEP, LIN> : k_si_sweep<false, false, 1, TDEP, LIN>))
-               : (fold ? (k == 0 ? k_si_sweep<true, true, 2, TDEP, LIN> : k_si_sweep<false, true, 2, TDEP, LIN>)
-                       : (k == 0 ? k_si_sweep<true, false, 2, TDEP, LIN> : k_si_sweep<false, false, 2, TDEP, LIN>));
+    return (K.flags & (UGKWP_FLAG_SLOPES | UGKWP_FLAG_BOUNDARY_PARTICLES)) ? sweep_kernel_ext<TDEP, LIN, true>(K, fold, k)
+                                                                           : sweep_kernel_ext<TDEP, LIN, false>(K, fold, k);
+}
+
+// rho^m of the source iteration: rho^n for m = 0; from the wave flux of each
+// sweep's iterate on (UGKWP_FLAG_WAVE_ITER), whose sweeps read their
+// neighbours' rho^k, rho^m alternates between rho_new (m odd) and rho_alt
+// (m even); otherwise every sweep keeps its iterate in rho_new.
+const double* sweep_rho(const Dev& D, const Consts& K, int m)
+{
+    if (m == 0) return D.rho;
+    if (!(K.flags & UGKWP_FLAG_WAVE_ITER)) return D.rho_new;
+    return (m & 1) ? D.rho_new : D.rho_alt;
 }
 
 void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t st)
 {
     const bool fold = K.n_inst == 1;
+    const bool witer = (K.flags & UGKWP_FLAG_WAVE_ITER) != 0;
+    const int dim = K.inst0.dim;
     for (int k = k0; k < k1; ++k) {
+        if (witer && k > 0) {
+            // the wave flux of this sweep from its iterate: slopes, then Q
+            if (K.flags & UGKWP_FLAG_SLOPES) launch_slopes(dim, D, K, sweep_rho(D, K, k), true, st);
+            if (dim == 1) k_wave_q<1><<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K, k, sweep_rho(D, K, k));
+            else k_wave_q<2><<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K, k, sweep_rho(D, K, k));
+        }
         // every instance of a context has the same dimension
         const bool lin = (K.flags & UGKWP_FLAG_SI_LINEARIZED) != 0;
         auto kern = (K.t_power != 0.0 || K.stim) ? (lin ? sweep_kernel<true, true>(K, fold, k) : sweep_kernel<true, false>(K, fold, k))
                                      : (lin ? sweep_kernel<false, true>(K, fold, k) : sweep_kernel<false, false>(K, fold, k));
         kern<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, sweep_in(D, k), sweep_out(D, k),
-                                                                    fold && k > k0 ? 1 : 0);
+                                                                    fold && k > k0 ? 1 : 0, sweep_rho(D, K, k),
+                                                                    const_cast<double*>(sweep_rho(D, K, k + 1)));
         if (!fold) k_si_decide<<<blocks((int64_t)K.n_inst * WAVE, 256), 256, 0, st>>>(D, K, k);
     }
 }

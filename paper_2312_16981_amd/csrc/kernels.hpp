@@ -32,6 +32,8 @@ ScanGate scan_gate(const Dev& D, const Consts& K, uint32_t after);
 void launch_scan(const ScanGate& q, const int32_t* in, int64_t n, int64_t* part, int64_t* out, int64_t* total,
                  hipStream_t st);
 void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, hipStream_t st);
+// slopes of the wave part (UGKWP_FLAG_SLOPES) from rho^h = src (minus rhop when sub_rhop)
+void launch_slopes(int dim, const Dev& D, const Consts& K, const double* src, bool sub_rhop, hipStream_t st);
 // Launch shape of the push: persistent blocks, threads per block (256 or 512)
 // and particles per thread.
 struct PushShape {

@@ -439,6 +439,12 @@ struct ugkwp_ctx {
         d.boff = dalloc<int64_t>(owned, ncg + 1);
         d.wnew = dalloc<double>(owned, ncg);
         d.wsn = dalloc<double>(owned, ncg);
+        d.sx = dalloc<double>(owned, ncg);
+        d.sy = dalloc<double>(owned, ncg);
+        d.bcoef = dalloc<double>(owned, ncg);
+        d.rho_alt = dalloc<double>(owned, ncg);
+        d.winflow = dalloc<double>(owned, 2 * ncg);
+        d.nbi = dalloc<int32_t>(owned, ncg);
         d.beta = dalloc<double>(owned, ncg);
         d.dep = dalloc<double>(owned, ncg);
         d.surv = dalloc<double>(owned, ncg);
@@ -492,6 +498,11 @@ struct ugkwp_ctx {
         HIPCHK(hipMemsetAsync(d.dep, 0, sizeof(double) * ncg, st));
         HIPCHK(hipMemsetAsync(d.surv, 0, sizeof(double) * ncg, st));
         HIPCHK(hipMemsetAsync(d.nb, 0, sizeof(int32_t) * ncg, st));
+        HIPCHK(hipMemsetAsync(d.nbi, 0, sizeof(int32_t) * ncg, st));
+        HIPCHK(hipMemsetAsync(d.sx, 0, sizeof(double) * ncg, st));
+        HIPCHK(hipMemsetAsync(d.sy, 0, sizeof(double) * ncg, st));
+        HIPCHK(hipMemsetAsync(d.bcoef, 0, sizeof(double) * ncg, st));
+        HIPCHK(hipMemsetAsync(d.winflow, 0, sizeof(double) * 2 * ncg, st));
         HIPCHK(hipMemsetAsync(d.wnew, 0, sizeof(double) * ncg, st));
         HIPCHK(hipMemsetAsync(d.Q, 0, sizeof(double) * ncg, st));
         HIPCHK(hipMemsetAsync(d.rhoh, 0, sizeof(double) * ncg, st));
@@ -763,6 +774,7 @@ struct ugkwp_ctx {
         // a temperature-dependent opacity: the step's tables at its T^n
         if (K.t_power != 0.0 || K.stim) launch_tables(D, K, st);
         launch_count_scan(D, K, z, part, st);
+        if (K.flags & UGKWP_FLAG_SLOPES) launch_slopes(dim, D, K, D.rhoh, false, st);
         launch_sample(dim, D, K, view(cur_mv, cur_st), st);
     }
 
@@ -901,10 +913,12 @@ struct ugkwp_ctx {
             dg.injection += g[3];
             dg.e_start += g[4];
             dg.e_end += g[5];
+            dg.inflow_particles += g[6];
         }
         dg.sweeps_max = smax;
         dg.sweeps_sum = ssum;
-        dg.residual = dg.e_end - dg.e_start - (dg.inflow_wave + dg.inflow_eq - dg.exit_particles + dg.injection);
+        dg.residual = dg.e_end - dg.e_start -
+                      (dg.inflow_wave + dg.inflow_eq + dg.inflow_particles - dg.exit_particles + dg.injection);
         hipEvent_t* e = sev[cur_slot];
         float ms = 0;
         dg.push_timed = p.push_timed ? 1 : 0;
@@ -1609,6 +1623,9 @@ int ugkwp_record(ugkwp_ctx* ctx, int max_steps)
             fail(UGKWP_EINVAL, "the adjoint does not cover the numerical collision time of joint cells (tau_num_C > 0)");
         if (max_steps > 0 && (ctx->P.opacity_T_power != 0 || ctx->P.opacity_stim))
             fail(UGKWP_EINVAL, "the adjoint does not cover a temperature-dependent opacity");
+        if (max_steps > 0 && (ctx->P.flags & (UGKWP_FLAG_SLOPES | UGKWP_FLAG_WAVE_ITER | UGKWP_FLAG_BOUNDARY_PARTICLES)))
+            fail(UGKWP_EINVAL, "the adjoint covers neither the slopes of the wave part, its flux from the iterate, "
+                               "nor boundary-source particles");
         ctx->record_start(max_steps);
     });
 }

@@ -21,6 +21,9 @@ FLAG_GROUP_SIGMA = 1
 FLAG_GRAPH = 2
 FLAG_PHASE_TIMES = 4
 FLAG_SI_LINEARIZED = 8
+FLAG_SLOPES = 16
+FLAG_WAVE_ITER = 32
+FLAG_BOUNDARY_PARTICLES = 64
 PURPOSE_BIRTH, PURPOSE_FLIGHT = 1, 2
 
 EXPORTED = [
@@ -91,7 +94,7 @@ class Diag(C.Structure):
                 ("e_start", _d), ("e_end", _d), ("inflow_wave", _d), ("inflow_eq", _d),
                 ("exit_particles", _d), ("injection", _d), ("residual", _d),
                 ("ms_sample", _d), ("ms_push", _d), ("ms_macro", _d), ("ms_si", _d), ("ms_sort", _d),
-                ("push_timed", C.c_int)]
+                ("push_timed", C.c_int), ("inflow_particles", _d)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

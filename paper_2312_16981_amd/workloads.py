@@ -19,6 +19,9 @@ import numpy as np
 BC_VACUUM, BC_PLANCK, BC_REFLECT = 0, 1, 2
 FLAG_GROUP_SIGMA = 1
 FLAG_SI_LINEARIZED = 8
+FLAG_SLOPES = 16
+FLAG_WAVE_ITER = 32
+FLAG_BOUNDARY_PARTICLES = 64
 
 
 @dataclass

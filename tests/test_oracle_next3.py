@@ -275,6 +275,10 @@ def test_boundary_particles_conserve_energy_and_balance_the_ledger(which):
         d = s.diag()
         assert abs(d["residual"]) <= 1e-12 * d["e_end"], d
     assert d["n_ghost_entered"] > 0 and d["inflow_particles"] > 0
+    # every birth, entered or not, takes its own id: ids stay unique across steps
+    pool = s.pool()
+    births, _ = s.counters()
+    assert len(np.unique(pool["id"])) == len(pool["id"]) and np.all(pool["id"] < births)
     t = s.tallies()
     start = s.start_weights()
     nx, ny, G = p.nx, p.ny, p.G
