@@ -95,6 +95,18 @@ def lib():
         L.ora_get_counters.argtypes = [C.c_void_p, _pu64, C.POINTER(C.c_int)]
         L.ora_get_start_weights.argtypes = [C.c_void_p, _pd]
         L.ora_record.argtypes = [C.c_void_p, C.c_int]
+        L.ora_set_source.argtypes = [C.c_void_p, _pd, _d]
+        L.ora_set_heat_capacity.argtypes = [C.c_void_p, _pd, _pd]
+        L.ora_set_source_planck.argtypes = [C.c_void_p, _pd, _d, _d]
+        L.ora_set_opacity_table.argtypes = [C.c_void_p, C.c_int, _pi32, C.c_int, _pd, C.c_int, _pd, _pd]
+        L.ora_table_sigma.argtypes = [C.c_void_p, C.c_int, _d, _d]
+        L.ora_table_sigma.restype = _d
+        L.ora_olson_alpha.argtypes = [_d, _d, _pd]
+        L.ora_olson_alpha.restype = _d
+        L.ora_heat_capacity.argtypes = [C.c_void_p, C.c_int, _d]
+        L.ora_heat_capacity.restype = _d
+        L.ora_material_energy.argtypes = [C.c_void_p, C.c_int, _d]
+        L.ora_material_energy.restype = _d
         L.ora_adjoint.argtypes = [C.c_void_p, _pd, _pd]
         L.ora_replay_frozen.argtypes = [C.c_void_p, _pd, _pd]
         L.ora_adjoint_updates.argtypes = []
@@ -119,6 +131,12 @@ def philox(ctr, key):
 
 def uniform(seed, pid, step, purpose, d):
     return lib().ora_uniform(seed, pid, step, purpose, d)
+
+
+def olson_alpha(T, chi):
+    d = C.c_double()
+    a = lib().ora_olson_alpha(T, chi, C.byref(d))
+    return a, d.value
 
 
 def planck_tail(x):
@@ -220,6 +238,30 @@ class Sim:
         st = L.ora_set_opacity(h, _p(kap))
         if st:
             raise OracleError(st, "set_opacity")
+        if prob.opacity_table is not None:
+            t = prob.opacity_table
+            self._tab = (np.ascontiguousarray(t["mat"], dtype=np.int32), np.ascontiguousarray(t["nu"], dtype=np.float64),
+                         np.ascontiguousarray(t["T"], dtype=np.float64), np.ascontiguousarray(t["sigma"], dtype=np.float64))
+            m, nu, T, sg = self._tab
+            st = L.ora_set_opacity_table(h, int(sg.shape[0]), _p(m, _pi32), len(nu), _p(nu), len(T), _p(T), _p(sg))
+            if st:
+                raise OracleError(st, "set_opacity_table")
+        if prob.olson_H is not None:
+            self._ol = (np.ascontiguousarray(prob.olson_H, dtype=np.float64),
+                        np.ascontiguousarray(prob.olson_chi, dtype=np.float64))
+            st = L.ora_set_heat_capacity(h, _p(self._ol[0]), _p(self._ol[1]))
+            if st:
+                raise OracleError(st, "set_heat_capacity")
+        if prob.source_shape is not None:
+            self._qf = np.ascontiguousarray(prob.source_shape, dtype=np.float64)
+            st = L.ora_set_source_planck(h, _p(self._qf), float(prob.source_T), float(prob.source_t_off))
+            if st:
+                raise OracleError(st, "set_source_planck")
+        if prob.source is not None:
+            q = np.ascontiguousarray(prob.source, dtype=np.float64)
+            st = L.ora_set_source(h, _p(q), float(prob.source_t_off))
+            if st:
+                raise OracleError(st, "set_source")
         cv = np.ascontiguousarray(prob.cv, dtype=np.float64)
         T0 = np.ascontiguousarray(prob.T0, dtype=np.float64)
         Tr0 = np.ascontiguousarray(prob.Tr0, dtype=np.float64)
@@ -235,6 +277,15 @@ class Sim:
 
     def __del__(self):
         self.close()
+
+    def table_sigma(self, m, nu, T):
+        return lib().ora_table_sigma(self.h, int(m), float(nu), float(T))
+
+    def heat_capacity(self, cell, T):
+        return lib().ora_heat_capacity(self.h, int(cell), float(T))
+
+    def material_energy(self, cell, T):
+        return lib().ora_material_energy(self.h, int(cell), float(T))
 
     def step(self, n=1, check=True):
         st = lib().ora_step(self.h, n)

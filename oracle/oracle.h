@@ -139,6 +139,32 @@ void ora_destroy(ora_sim* s);
 int ora_set_opacity(ora_sim* s, const double* kappa);            /* [ncell][G] */
 int ora_set_material(ora_sim* s, const double* cv, const double* T0,
                      const double* Tr0, const unsigned char* pinned);
+/* A volumetric radiation source (Sec. 3.4: Q(x), switched off at a time):
+ * q [cell][G] adds dt q to rho of every step that starts before t_off. */
+int ora_set_source(ora_sim* s, const double* q, double t_off);
+/* The source Q(x) = B(nu, Ts) f(x) of Sec. 3.4-3.5 added to the transport
+ * equation's right side: its rate in rho is q = (c/eps^2) f_i phi_g(Ts). */
+int ora_set_source_planck(ora_sim* s, const double* f, double Ts, double t_off);
+/* A tabulated opacity sigma(nu, T) per material (Sec. 3.4-3.5), in place of
+ * kappa nu^-p T^-q: mat [cell] in 0..nmat-1, nodes nu[nnu], T[nT] ascending,
+ * sig [nmat][nT][nnu] > 0, interpolated bilinearly in (ln nu, ln T) on ln sigma
+ * and held constant beyond the end nodes. */
+int ora_set_opacity_table(ora_sim* s, int nmat, const int32_t* mat, int nnu, const double* nu,
+                          int nT, const double* T, const double* sig);
+/* Olson's heat capacity (Sec. 3.4, Eq. cvolson) in the cells with H[i] > 0: the
+ * volumetric heat capacity of cell i at T becomes H_i [1 + alpha + (T + chi_i)
+ * dalpha/dT] in place of its constant C_v (the printed a T_keV^3 is the unit
+ * a (1 keV)^3, folded into H), and the material energy U(T) = H_i [T (1 + alpha)
+ * + chi_i alpha], whose derivative that is.  The source iteration then solves
+ * U(T^{n+1}) = U(T^n) + exchange, the energy form of Eq. macroEquImplicit's
+ * material line: the literal iteration inverts U for T^{k+1}, the linearized one
+ * takes one Newton step at T^k.  NULL H: off. */
+int ora_set_heat_capacity(ora_sim* s, const double* H, const double* chi);
+/* The table's sigma of material m at (nu, T), and Olson's alpha and its derivative. */
+double ora_table_sigma(const ora_sim* s, int m, double nu, double T);
+double ora_olson_alpha(double T, double chi, double* dalpha);
+double ora_heat_capacity(const ora_sim* s, int cell, double T);
+double ora_material_energy(const ora_sim* s, int cell, double T);
 int ora_step(ora_sim* s, int nsteps);
 int ora_get_fields(const ora_sim* s, double* rho, double* T, double* rhop);
 /* Tallies of the last step: face gross crossings [face][G][2] (x-faces, then

@@ -68,6 +68,14 @@ struct ora_sim {
     int nrec, caprec;
     ora_rec_step* rec;
     double *kappa0, *T0rec, *rho0rec;
+    /* volumetric source and its switch-off time */
+    double *olH, *olchi;          /* Olson's heat capacity per cell (NULL: constant C_v) */
+    double* qsrc;
+    double q_toff;
+    /* tabulated opacity */
+    int tab_nmat, tab_nnu, tab_nT;
+    int32_t* tab_mat;
+    double *tab_lnu, *tab_lT, *tab_lsig;
 };
 
 static void* zalloc(size_t n) { void* q = calloc(n ? n : 1, 1); return q; }
@@ -150,7 +158,8 @@ void ora_destroy(ora_sim* s)
     free(s->rhop); free(s->pinned); free(s->px); free(s->py); free(s->pox); free(s->poy);
     free(s->pnu); free(s->pw); free(s->pid); free(s->pcell); free(s->pg); free(s->ftx);
     free(s->fty); free(s->dep); free(s->surv); free(s->start); free(s->wnew); free(s->Q);
-    free(s->nb); free(s);
+    free(s->nb); free(s->olH); free(s->olchi); free(s->qsrc); free(s->tab_mat); free(s->tab_lnu); free(s->tab_lT); free(s->tab_lsig);
+    free(s);
 }
 
 int ora_set_opacity(ora_sim* s, const double* kappa)
@@ -185,6 +194,166 @@ int ora_set_material(ora_sim* s, const double* cv, const double* T0, const doubl
     return ORA_OK;
 }
 
+int ora_set_source(ora_sim* s, const double* q, double t_off)
+{
+    size_t ncg = (size_t)s->ncell * s->p.G;
+    if (!q) { free(s->qsrc); s->qsrc = NULL; return ORA_OK; }
+    for (size_t k = 0; k < ncg; ++k) if (!(q[k] >= 0) || !isfinite(q[k])) return ORA_EINVAL;
+    if (!(t_off >= 0)) return ORA_EINVAL;
+    if (!s->qsrc) s->qsrc = (double*)malloc(sizeof(double) * ncg);
+    memcpy(s->qsrc, q, sizeof(double) * ncg);
+    s->q_toff = t_off;
+    return ORA_OK;
+}
+
+int ora_set_source_planck(ora_sim* s, const double* f, double Ts, double t_off)
+{
+    if (!f) return ora_set_source(s, NULL, t_off);
+    if (!(Ts > 0.0) || !isfinite(Ts)) return ORA_EINVAL;
+    const int G = s->p.G;
+    const double rate = s->p.c / (s->p.eps * s->p.eps);
+    double* q = (double*)malloc(sizeof(double) * (size_t)s->ncell * G);
+    if (!q) return ORA_ENOMEM;
+    int st = ORA_OK;
+    for (int i = 0; i < s->ncell && st == ORA_OK; ++i) {
+        if (!(f[i] >= 0.0) || !isfinite(f[i])) st = ORA_EINVAL;
+        for (int g = 0; g < G; ++g)
+            q[(size_t)i * G + g] = rate * f[i] * ora_phi_group(Ts, s->nu[g], s->nu[g + 1], s->p.a, s->p.c);
+    }
+    if (st == ORA_OK) st = ora_set_source(s, q, t_off);
+    free(q);
+    return st;
+}
+
+int ora_set_opacity_table(ora_sim* s, int nmat, const int32_t* mat, int nnu, const double* nu, int nT,
+                          const double* T, const double* sig)
+{
+    if (nmat < 1 || nnu < 2 || nT < 2 || !mat || !nu || !T || !sig) return ORA_EINVAL;
+    for (int i = 0; i < s->ncell; ++i) if (mat[i] < 0 || mat[i] >= nmat) return ORA_EINVAL;
+    for (int k = 0; k + 1 < nnu; ++k) if (!(nu[k] > 0) || !(nu[k + 1] > nu[k])) return ORA_EINVAL;
+    for (int k = 0; k + 1 < nT; ++k) if (!(T[k] > 0) || !(T[k + 1] > T[k])) return ORA_EINVAL;
+    size_t nt = (size_t)nmat * nT * nnu;
+    for (size_t k = 0; k < nt; ++k) if (!(sig[k] > 0) || !isfinite(sig[k])) return ORA_EINVAL;
+    free(s->tab_mat); free(s->tab_lnu); free(s->tab_lT); free(s->tab_lsig);
+    s->tab_nmat = nmat; s->tab_nnu = nnu; s->tab_nT = nT;
+    s->tab_mat = (int32_t*)malloc(sizeof(int32_t) * s->ncell);
+    memcpy(s->tab_mat, mat, sizeof(int32_t) * s->ncell);
+    s->tab_lnu = (double*)malloc(sizeof(double) * nnu);
+    s->tab_lT = (double*)malloc(sizeof(double) * nT);
+    s->tab_lsig = (double*)malloc(sizeof(double) * nt);
+    for (int k = 0; k < nnu; ++k) s->tab_lnu[k] = log(nu[k]);
+    for (int k = 0; k < nT; ++k) s->tab_lT[k] = log(T[k]);
+    for (size_t k = 0; k < nt; ++k) s->tab_lsig[k] = log(sig[k]);
+    s->have_opacity = 1;
+    return ORA_OK;
+}
+
+/* Node interval and weight of x among n ascending nodes (clamped at the ends). */
+static int tab_locate(const double* nodes, int n, double x, double* frac)
+{
+    if (x <= nodes[0]) { *frac = 0.0; return 0; }
+    if (x >= nodes[n - 1]) { *frac = 1.0; return n - 2; }
+    int lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (nodes[mid] <= x) lo = mid; else hi = mid;
+    }
+    *frac = (x - nodes[lo]) / (nodes[lo + 1] - nodes[lo]);
+    return lo;
+}
+
+double ora_table_sigma(const ora_sim* s, int m, double nu, double T)
+{
+    double a, b;
+    const int i = tab_locate(s->tab_lnu, s->tab_nnu, log(nu), &a);
+    const int j = tab_locate(s->tab_lT, s->tab_nT, log(T), &b);
+    const double* L = s->tab_lsig + (size_t)m * s->tab_nT * s->tab_nnu;
+    const int n = s->tab_nnu;
+    const double l00 = L[(size_t)j * n + i], l10 = L[(size_t)j * n + i + 1];
+    const double l01 = L[(size_t)(j + 1) * n + i], l11 = L[(size_t)(j + 1) * n + i + 1];
+    const double lo = (1.0 - a) * l00 + a * l10, hi = (1.0 - a) * l01 + a * l11;
+    return exp((1.0 - b) * lo + b * hi);
+}
+
+/* Olson's ionisation fraction (Sec. 3.4): alpha = e^{-chi/T} (sqrt(1 + 4 e^{chi/T})
+ * - 1)/2 and dalpha/dT = (chi/T^2)(alpha - 1/sqrt(1 + 4 e^{chi/T})), written with
+ * h = e^{-chi/(2T)} (alpha = h (sqrt(h^2 + 4) - h)/2) so that nothing overflows. */
+double ora_olson_alpha(double T, double chi, double* dalpha)
+{
+    const double h = exp(-0.5 * chi / T);
+    const double r = sqrt(h * h + 4.0);
+    const double alpha = 0.5 * h * (r - h);
+    if (dalpha) *dalpha = (chi / (T * T)) * (alpha - h / r);
+    return alpha;
+}
+
+int ora_set_heat_capacity(ora_sim* s, const double* H, const double* chi)
+{
+    if (!H) { free(s->olH); free(s->olchi); s->olH = s->olchi = NULL; return ORA_OK; }
+    if (!chi) return ORA_EINVAL;
+    for (int i = 0; i < s->ncell; ++i)
+        if (!(H[i] >= 0.0) || !(chi[i] >= 0.0) || !isfinite(H[i]) || !isfinite(chi[i])) return ORA_EINVAL;
+    if (!s->olH) {
+        s->olH = (double*)malloc(sizeof(double) * s->ncell);
+        s->olchi = (double*)malloc(sizeof(double) * s->ncell);
+    }
+    memcpy(s->olH, H, sizeof(double) * s->ncell);
+    memcpy(s->olchi, chi, sizeof(double) * s->ncell);
+    return ORA_OK;
+}
+
+/* Heat capacity of cell i at T: the constant C_v of the cell, or Olson's
+ * rho C_v = H [1 + alpha + (T + chi) dalpha/dT] (Eq. cvolson, whose a T_keV^3
+ * factor is the unit a (1 keV)^3 and is folded into H) where H > 0. */
+double ora_heat_capacity(const ora_sim* s, int i, double T)
+{
+    if (!s->olH || !(s->olH[i] > 0.0)) return s->cv[i];
+    double da;
+    const double chi = s->olchi[i];
+    const double al = ora_olson_alpha(T, chi, &da);
+    return s->olH[i] * (1.0 + al + (T + chi) * da);
+}
+
+/* Material energy U(T) with dU/dT = C_v (Sec. 2.1's U): C_v T, or for Olson's
+ * heat capacity H [T (1 + alpha) + chi alpha], whose derivative is the bracket
+ * of Eq. cvolson. */
+double ora_material_energy(const ora_sim* s, int i, double T)
+{
+    if (!s->olH || !(s->olH[i] > 0.0)) return s->cv[i] * T;
+    const double chi = s->olchi[i];
+    const double al = ora_olson_alpha(T, chi, NULL);
+    return s->olH[i] * (T * (1.0 + al) + chi * al);
+}
+
+static int olson_cell(const ora_sim* s, int i)
+{
+    return s->olH != NULL && s->olH[i] > 0.0;
+}
+
+/* The temperature of an Olson cell whose material energy is u > 0: U is strictly
+ * increasing, so Newton's method from T0 kept inside a bracket [lo, hi] with
+ * U(lo) <= u <= U(hi) (bisection when a step leaves it) finds the root; it stops
+ * once a step changes T by at most 1e-15 T.  Returns a non-positive value when
+ * u <= 0. */
+static double olson_temperature(const ora_sim* s, int i, double u, double T0)
+{
+    if (!(u > 0.0) || !isfinite(u)) return -1.0;
+    double lo = 0.0, hi = T0 > 0.0 ? T0 : 1.0;
+    for (int n = 0; n < 2100 && ora_material_energy(s, i, hi) < u; ++n) { lo = hi; hi = 2.0 * hi; }
+    double T = T0 > lo && T0 < hi ? T0 : 0.5 * (lo + hi);
+    for (int n = 0; n < 200; ++n) {
+        const double f = ora_material_energy(s, i, T) - u;
+        if (f == 0.0) break;
+        if (f < 0.0) lo = T; else hi = T;
+        double Tn = T - f / ora_heat_capacity(s, i, T);
+        if (!(Tn > lo && Tn < hi)) Tn = 0.5 * (lo + hi);
+        const double d = fabs(Tn - T);
+        T = Tn;
+        if (d <= 1e-15 * T) break;
+    }
+    return T;
+}
+
 /* kappa of (cell, g) at temperature T: kappa T^-q (Sec. 3.1's sigma0/sqrt(T) for
  * q = 1/2); kappa itself when q = 0. */
 static double kappa_at(const ora_sim* s, size_t cg, double T)
@@ -208,11 +377,27 @@ static double group_factor(const ora_sim* s, int g, double T)
             + nupow(nh, p) * stim(s, nh, T)) / 6.0;
 }
 
+/* Group opacity of (cell, g) at T: Simpson's rule over the group of the
+ * tabulated sigma, or kappa(T) times the group factor. */
+static double group_sigma(const ora_sim* s, size_t cg, int g, double T)
+{
+    if (s->tab_lsig) {
+        const int m = s->tab_mat[cg / (size_t)s->p.G];
+        const double nl = s->nu[g], nh = s->nu[g + 1], nm = 0.5 * (nl + nh);
+        return (ora_table_sigma(s, m, nl, T) + 4.0 * ora_table_sigma(s, m, nm, T) + ora_table_sigma(s, m, nh, T)) / 6.0;
+    }
+    return kappa_at(s, cg, T) * group_factor(s, g, T);
+}
+
 /* Opacity seen by a particle of frequency nu in (cell, g) during a step: the
  * cell's temperature T^n. */
 static double particle_sigma(const ora_sim* s, size_t cg, double nu, int g)
 {
     const double T = s->T[cg / (size_t)s->p.G];
+    if (s->tab_lsig) {
+        if (s->p.flags & ORA_FLAG_GROUP_SIGMA) return group_sigma(s, cg, g, T);
+        return ora_table_sigma(s, s->tab_mat[cg / (size_t)s->p.G], nu, T);
+    }
     const double k = kappa_at(s, cg, T);
     if (s->p.flags & ORA_FLAG_GROUP_SIGMA) return k * group_factor(s, g, T);
     return k * nupow(nu, s->p.nu_power) * stim(s, nu, T);
@@ -603,6 +788,12 @@ static void wave_slopes(const ora_sim* s, const double* rhoh, double* sx, double
     }
 }
 
+/* The volumetric source adds to this step (it starts before the switch-off time). */
+static int src_on(const ora_sim* s)
+{
+    return s->qsrc != NULL && (double)s->step * s->p.dt < s->q_toff;
+}
+
 /* The wave part's free-transport flux (Sec. 2.2, F^{fr,wave}, with Remark 3's
  * choice of coefficient) and the static source Q = rho^n + (dt/V) sum_f S_f F_in
  * + w^{fr,p}/V of every cell and group, from the wave part rhoh.  Through a face
@@ -673,6 +864,7 @@ static double wave_source(ora_sim* s, const double* rhoh, const double* sx, cons
                 if (f[q].nb < 0) inflow += dt * f[q].S * Fin / c;
             }
             Q[k] = s->rho[k] + (dt / V) * fsum + wnet[k] / V;
+            if (src_on(s)) Q[k] = Q[k] + dt * s->qsrc[k];
         }
     }
     return inflow;
@@ -733,7 +925,7 @@ static int step_once(ora_sim* s)
     for (int i = 0; i < nc; ++i)
         for (int g = 0; g < G; ++g) {
             size_t k = (size_t)i * G + g;
-            sig[k] = kappa_at(s, k, s->T[i]) * group_factor(s, g, s->T[i]);
+            sig[k] = group_sigma(s, k, g, s->T[i]);
             sv[k] = c * sig[k] * dt / (eps * eps);
             es[k] = exp(-sv[k]);
             wsamp[k] = ora_coef_w(sv[k]);
@@ -961,7 +1153,7 @@ static int step_once(ora_sim* s)
     /* With a temperature-dependent opacity every sweep first recomputes sigma,
      * lambda = c sigma dt / eps^2 and the face coefficients from its iterate
      * T^k (the coefficient step of Algorithm 2); otherwise they are the step's. */
-    const int tdep = P->T_power != 0.0 || P->opacity_stim;
+    const int tdep = P->T_power != 0.0 || P->opacity_stim || s->tab_lsig != NULL;
     /* Linearized variant: the emission of the new temperature is taken as
      * phi^k + phi'(T^k) (T^{k+1} - T^k), so each cell's energy balance is solved
      * for T^{k+1} as one local Newton step; its fixed point is that of the
@@ -976,6 +1168,7 @@ static int step_once(ora_sim* s)
     double* rk = (double*)malloc(sizeof(double) * ncg);
     double* Tk = (double*)malloc(sizeof(double) * nc);
     double* Tn1 = (double*)malloc(sizeof(double) * nc);
+    double* uend = (double*)malloc(sizeof(double) * nc);      /* material energy the last sweep gave */
     double* rn1 = (double*)malloc(sizeof(double) * ncg);
     double* em = (double*)malloc(sizeof(double) * ncg);
     /* face coefficients D for the 2*dim faces of every cell */
@@ -1009,7 +1202,7 @@ static int step_once(ora_sim* s)
             for (int i = 0; i < nc; ++i)
                 for (int g = 0; g < G; ++g) {
                     size_t k = (size_t)i * G + g;
-                    sigk[k] = kappa_at(s, k, Tk[i]) * group_factor(s, g, Tk[i]);
+                    sigk[k] = group_sigma(s, k, g, Tk[i]);
                     lam[k] = c * sigk[k] * dt / (eps * eps);
                 }
             for (int i = 0; i < nc; ++i) {
@@ -1050,11 +1243,32 @@ static int step_once(ora_sim* s)
                 sum += sigk[k] * (b - phi[k]) / (1.0 + lam[k]);
                 if (lin) dsum += sigk[k] * dph[k] / (1.0 + lam[k]);
             }
-            const double w = dt / (eps * eps * s->cv[i]);
             double Tnew;
-            if (s->pinned[i]) Tnew = s->T[i];
-            else if (lin) Tnew = Tk[i] + (s->T[i] - Tk[i] + w * sum) / (1.0 + w * dsum);
-            else Tnew = s->T[i] + w * sum;
+            if (s->pinned[i]) {
+                Tnew = s->T[i];
+                uend[i] = ora_material_energy(s, i, Tnew);
+            } else if (!olson_cell(s, i)) {
+                const double w = dt / (eps * eps * s->cv[i]);
+                Tnew = lin ? Tk[i] + (s->T[i] - Tk[i] + w * sum) / (1.0 + w * dsum) : s->T[i] + w * sum;
+                uend[i] = s->cv[i] * Tnew;
+            } else {
+                /* Olson's heat capacity: the energy equation in U, U(T^{n+1}) = U(T^n) +
+                 * exchange.  Literal: U(T^{k+1}) = U(T^n) + exchange(phi^k), solved for
+                 * T^{k+1}.  Linearized: one Newton step at T^k, U and the emission both
+                 * linearized, T^{k+1} = T^k + (U(T^n) - U(T^k) + exchange(phi^k)) /
+                 * (C_v(T^k) + (dt/eps^2) sum_g sigma phi'/(1 + lam)); its material
+                 * energy is U(T^k) + C_v(T^k)(T^{k+1} - T^k). */
+                const double ex = dt / (eps * eps) * sum;
+                const double un = ora_material_energy(s, i, s->T[i]);
+                if (lin) {
+                    const double uk = ora_material_energy(s, i, Tk[i]), ck = ora_heat_capacity(s, i, Tk[i]);
+                    Tnew = Tk[i] + (un - uk + ex) / (ck + dt / (eps * eps) * dsum);
+                    uend[i] = uk + ck * (Tnew - Tk[i]);
+                } else {
+                    uend[i] = un + ex;
+                    Tnew = olson_temperature(s, i, uend[i], Tk[i]);
+                }
+            }
             /* the new temperature's emission: phi^k, or its linearization */
             const double dTi = lin && !s->pinned[i] ? Tnew - Tk[i] : 0.0;
             for (int g = 0; g < G; ++g) {
@@ -1105,14 +1319,15 @@ static int step_once(ora_sim* s)
                     inflow_eq += dt * f[q].S * Df[k * 4 + q] * (pn - phi[k]) / c;
                 }
                 if (s->pinned[i]) inj -= V * (dt * sigk[k] / (eps * eps)) * em[k];
+                if (src_on(s)) inj += V * dt * s->qsrc[k] / c;
             }
         }
         double e0 = 0.0, e1 = 0.0;
         for (int i = 0; i < nc; ++i) {
             double r0 = 0.0, r1 = 0.0;
             for (int g = 0; g < G; ++g) { r0 += s->rho[(size_t)i * G + g]; r1 += rn1[(size_t)i * G + g]; }
-            e0 += V * (r0 / c + s->cv[i] * s->T[i]);
-            e1 += V * (r1 / c + s->cv[i] * Tn1[i]);
+            e0 += V * (r0 / c + ora_material_energy(s, i, s->T[i]));
+            e1 += V * (r1 / c + uend[i]);
         }
         dg.inflow_eq = inflow_eq;
         dg.injection = inj;
@@ -1134,7 +1349,7 @@ static int step_once(ora_sim* s)
         s->diag = dg;
     }
     free(sig); free(sv); free(es); free(wsamp); free(rhoh); free(A); free(wnet); free(sampled);
-    free(phi); free(phin); free(rk); free(Tk); free(Tn1); free(rn1); free(em); free(Df);
+    free(phi); free(phin); free(rk); free(Tk); free(Tn1); free(rn1); free(em); free(Df); free(uend);
     free(w5samp); free(Bw); free(sx); free(sy); free(ngh); free(gsamp); free(gside); free(rhk);
     if (tdep) { free(sigk); free(lam); }
     free(dph); free(bk);
@@ -1250,6 +1465,8 @@ int ora_record(ora_sim* s, int on)
     if (on && (s->p.tau_num_C > 0.0 || s->p.T_power != 0.0 || s->p.opacity_stim)) return ORA_EINVAL;
     /* nor the slopes, the iterate's wave flux or boundary-source particles */
     if (on && (s->p.flags & (ORA_FLAG_SLOPES | ORA_FLAG_WAVE_ITER | ORA_FLAG_BOUNDARY_PARTICLES))) return ORA_EINVAL;
+    /* nor Olson's heat capacity, a volumetric source or a tabulated opacity */
+    if (on && (s->olH || s->qsrc || s->tab_lsig)) return ORA_EINVAL;
     free_rec(s);
     s->recording = on ? 1 : 0;
     if (on) {

@@ -59,6 +59,13 @@ class Problem:
     tau_num_jump: float = 10.0   # opacity ratio across a face that makes its cells joint
     T_power: float = 0.0         # sigma(nu, T) = kappa nu^-p T^-T_power
     opacity_stim: int = 0        # 1: sigma also carries (1 - e^{-nu/T})
+    olson_H: Optional[np.ndarray] = None    # [ncell]: H > 0 gives a T^3 H [1 + alpha + (T + chi) alpha']
+    olson_chi: Optional[np.ndarray] = None  # [ncell]
+    source: Optional[np.ndarray] = None     # [ncell, G] volumetric source rate (rho units per unit time)
+    source_shape: Optional[np.ndarray] = None   # [ncell] f(x): a Planckian source (c/eps^2) f(x) phi_g(source_T)
+    source_T: float = 0.0
+    source_t_off: float = float("inf")      # the source acts in steps starting before this time
+    opacity_table: Optional[dict] = None    # {"mat": [ncell], "nu": [nnu], "T": [nT], "sigma": [nmat, nT, nnu]}
 
     @property
     def G(self) -> int:
@@ -206,6 +213,61 @@ def c4_batch(n_inst: int = 512, nx_range=(64, 4096), groups=(16, 32, 64), steps:
                   name=f"inst{k}_nx{nx}_g{G}")
         out.append(pr)
     return out
+
+
+def foam_kappa(nu: np.ndarray, T: np.ndarray) -> np.ndarray:
+    """Mass opacity (cm^2/g) of the carbon-hydrogen foam of Sec. 3.4 at photon
+    energies nu and temperatures T (both keV), as printed: kappa[..., T, nu]."""
+    n, t = np.meshgrid(np.asarray(nu, float), np.asarray(T, float), indexing="xy")
+    k = np.minimum(1e7, 1e9 * t ** 2)
+    mid = 3e6 * (0.008 / n) ** 2 / (1.0 + 200.0 * t ** 1.5)
+    hi = (3e6 * (0.008 / n) ** 2 * (0.3 / n) ** 0.5 / (1.0 + 200.0 * t ** 1.5)
+          + 4e4 * (0.3 / n) ** 2.5 / (1.0 + 8000.0 * t ** 2))
+    return np.where(n <= 0.008, k, np.where(n <= 0.3, mid, hi))
+
+
+def aluminium_kappa(nu: np.ndarray, T: np.ndarray) -> np.ndarray:
+    """Mass opacity (cm^2/g) of the aluminium blocks of Sec. 3.5, as printed."""
+    n, t = np.meshgrid(np.asarray(nu, float), np.asarray(T, float), indexing="xy")
+    low = np.minimum(1e7, 1e8 * t ** 2)
+    a = 1e7 * (0.01 / n) ** 2 / (1.0 + 20.0 * t ** 1.5)
+    b = 1e6 * (0.1 / n) ** 2 / (1.0 + 200.0 * t ** 2)
+    c = 1e7 * (0.01 / n) ** 2 * (1.5 / n) ** 0.5 / (1.0 + 20.0 * t ** 1.5) + 1e5 * (1.5 / n) ** 2.5 / (1.0 + 1000.0 * t ** 2)
+    return np.where(n <= 0.01, low, np.where(n <= 0.1, a, np.where(n <= 1.5, a + b, c)))
+
+
+def opacity_nodes(breaks=(0.008, 0.01, 0.1, 0.3, 1.5), numin: float = 1e-3, numax: float = 200.0,
+                  Tmin: float = 1e-3, Tmax: float = 2.0):
+    """Table nodes: 24 per decade in nu, with a node just below and at every
+    breakpoint of the printed piecewise opacities so that their jumps stay sharp,
+    and 16 per decade in T."""
+    nu = np.geomspace(numin, numax, int(round(24 * np.log10(numax / numin))) + 1)
+    nu = np.unique(np.concatenate([nu, np.asarray(breaks), np.asarray(breaks) * (1.0 - 1e-9)]))
+    T = np.geomspace(Tmin, Tmax, int(round(16 * np.log10(Tmax / Tmin))) + 1)
+    return nu, T
+
+
+def olson1d(nx: int = 128, G: int = 24, **kw) -> Problem:
+    """Olson's 1-D foam problem (Sec. 3.4) on [0, 4.8] cm with a = c = 1: the
+    foam's printed opacity times its density 0.001 g/cm^3, tabulated on
+    opacity_nodes(); Olson's heat capacity with H = 0.1, chi = 0.1 (keV); T0 =
+    Tr0 = 0.01 keV; reflecting walls; the source B(0.5 keV) e^{-693 x^3} (cell
+    centres) on while c t < 2; 24 log groups on [0.01, 100] keV; dt = dx / c;
+    the particle weight 1e-4 V; the linearized source iteration."""
+    L = 4.8
+    nu_n, T_n = opacity_nodes()
+    p = dict(dt=L / nx, steps=int(round(4.0 / (L / nx))), w_ref=1e-4, pool_cap=1 << 24,
+             name=f"olson1d_{nx}_g{G}", numin=0.01, numax=100.0, bc_right=BC_REFLECT,
+             flags=FLAG_SI_LINEARIZED, si_max_iters=500)
+    p.update(kw)
+    q = slab(nx, G, lambda x: np.ones_like(x), T0=0.01, **p)
+    xc = (np.arange(nx) + 0.5) * (L / nx)
+    table = {"mat": np.zeros(nx, np.int32), "nu": nu_n, "T": T_n,
+             "sigma": (1e-3 * foam_kappa(nu_n, T_n))[None, :, :].copy()}
+    return q.with_(x1=L, bc=[BC_REFLECT, BC_REFLECT, BC_VACUUM, BC_VACUUM], bcT=[0.0] * 4,
+                   kappa=np.zeros((nx, G)), cv=np.ones(nx), olson_H=np.full(nx, 0.1),
+                   olson_chi=np.full(nx, 0.1), opacity_table=table,
+                   source_shape=np.exp(-693.0 * xc ** 3), source_T=0.5, source_t_off=2.0)
 
 
 def lattice_mid_run_state(prob: Problem, n_particles: int, seed: int = 5) -> dict:
