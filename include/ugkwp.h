@@ -235,6 +235,45 @@ int ugkwp_set_material(ugkwp_ctx* ctx, const double* cv, const double* T0,
 int ugkwp_set_material_noalloc(ugkwp_ctx* ctx, const double* cv, const double* T0,
                                const double* Tr0, const uint8_t* pinned);
 
+/* ---- material models of Olson's problems (Sec. 3.4-3.5) ----
+ * Each takes per-cell (or per-(cell, group)) arrays of every instance of the
+ * context, concatenated in instance order, and is called after the material
+ * (ugkwp_set_material or ugkwp_init_batch).  They turn on the source iteration
+ * that re-evaluates the material from its iterate, and none is recordable for
+ * ugkwp_adjoint.  EINVAL for invalid values; a null first array turns the model
+ * off again. */
+
+/* Olson's heat capacity (Eq. cvolson): where H[cell] > 0 the cell's volumetric heat
+ * capacity at T is H [1 + alpha + (T + chi) dalpha/dT], alpha = e^{-chi/T}
+ * (sqrt(1 + 4 e^{chi/T}) - 1)/2 (the printed factor a T_keV^3 is the unit
+ * a (1 keV)^3, to be folded into H by the caller), in place of its constant C_v;
+ * its material energy is U(T) = H [T (1 + alpha) + chi alpha], and the source
+ * iteration solves U(T^{n+1}) = U(T^n) + exchange (the energy form of Eq.
+ * macroEquImplicit's material line): the literal sweep inverts U for T^{k+1}
+ * (Newton inside a bracket, to 1e-15 T), the linearized one takes one Newton step
+ * at T^k.  The ledger's material energy of such a cell is U.  H [ncell] >= 0,
+ * chi [ncell] >= 0, finite; cells with H = 0 keep their C_v. */
+int ugkwp_set_heat_capacity(ugkwp_ctx* ctx, const double* H, const double* chi);
+/* A volumetric radiation source (Sec. 3.4-3.5's Q(x)): q [ncell][G] >= 0, finite, the
+ * rate of rho; every step that starts before t_off (step index n with n dt < t_off)
+ * adds dt q to the right side of the macroscopic solve, and the ledger counts
+ * V dt q / c as injection.  t_off >= 0 (+inf: always on). */
+int ugkwp_set_source(ugkwp_ctx* ctx, const double* q, double t_off);
+/* The source Q(x) = B(nu, Ts) f(x) added to the transport equation's right side, as
+ * printed for Olson's problems: q = (c/eps^2) f[cell] phi_g(Ts) computed on the
+ * device; f [ncell] >= 0, finite; Ts > 0. */
+int ugkwp_set_source_planck(ugkwp_ctx* ctx, const double* f, double Ts, double t_off);
+/* A tabulated opacity sigma(nu, T) per material in place of kappa nu^-p T^-q (the
+ * piecewise opacities of Sec. 3.4-3.5, tabulated by the caller): mat [ncell] in
+ * 0..nmat-1, nodes nu [nnu >= 2] and T [nT >= 2] positive, finite, strictly
+ * ascending, sig [nmat][nT][nnu] > 0, finite.  sigma is bilinear in (ln nu, ln T) on
+ * ln sigma and constant beyond the end nodes; a group's opacity is Simpson's rule
+ * over the group (Sec. 3); particle flights use sigma at their own nu and the cell's
+ * T^n (the group opacity with UGKWP_FLAG_GROUP_SIGMA).  kappa is then unused.  The
+ * device copies of an earlier table are kept until the context is destroyed. */
+int ugkwp_set_opacity_table(ugkwp_ctx* ctx, int nmat, const int32_t* mat, int nnu, const double* nu, int nT,
+                            const double* T, const double* sig);
+
 /* Batched set-up: n_inst independent instances of one dimension with uneven
  * cell and group counts, all advanced by one launch per kernel per step. */
 int ugkwp_init_batch(ugkwp_ctx* ctx, int n_inst, const ugkwp_instance* inst);

@@ -49,6 +49,12 @@ struct Consts {
     double t_power;        // q of sigma(nu, T) = kappa nu^-p T^-q (0: no T dependence)
     int stim;              // 1: sigma also carries 1 - e^{-nu/T}
     double nu_power;
+    // material models of Olson's problems (Sec. 3.4-3.5), all off when 0
+    int olson;             // 1: per-cell Olson heat capacity (D.olH, D.olchi) in some cells
+    int table;             // 1: tabulated sigma(nu, T) per material replaces kappa nu^-p T^-q
+    int tab_nnu, tab_nT;   // table nodes in nu and T
+    int has_src;           // 1: a volumetric source D.qsrc
+    double q_toff;         // the source acts in steps that start before this time
     double si_tol;
     int64_t n_cap;
     int64_t pool_cap;
@@ -179,6 +185,21 @@ struct Dev {
     double* T;
     double* T_new;
     const uint8_t* pinned;
+    // Olson's heat capacity H [1 + alpha + (T + chi) alpha'] where olH > 0 (else the
+    // constant cvol), and the material energy the last sweep gave those cells
+    const double* olH;
+    const double* olchi;
+    double* uend;
+    // volumetric source: rate per (cell, group) slot, and whether the step's source is on
+    const double* qsrc;
+    int* src_on;
+    // tabulated opacity: material per cell, ln of the nodes and of sigma [mat][T][nu],
+    // and per cell the ln sigma along the nu nodes at the cell's T^n (the push's rows)
+    const int32_t* tab_mat;
+    double* tab_lnu;
+    double* tab_lT;
+    double* tab_lsig;
+    double* tab_row;
     // per instance
     InstState* ist;
     Resid* res;                 // [RES_SLOTS][n_inst][RES_SUB]

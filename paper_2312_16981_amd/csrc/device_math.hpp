@@ -353,6 +353,78 @@ __host__ __device__ inline double linear_offset(double beta, double U)
     return -2.0 * q / (1.0 + sqrt(disc));
 }
 
+// ---------------------------------------------------------------------------
+// Olson's material (Sec. 3.4, Eq. cvolson).  The ionisation fraction alpha solves
+// alpha^2 = e^{-chi/T} (1 - alpha); with h = e^{-chi/(2T)} and r = sqrt(h^2 + 4) it is
+// h (r - h)/2 (no overflow for cold material), and dalpha/dT = (chi/T^2)(alpha - h/r).
+__host__ __device__ inline double olson_alpha(double T, double chi, double* dalpha)
+{
+    const double h = exp(-0.5 * chi / T);
+    const double r = sqrt(h * h + 4.0);
+    const double al = 0.5 * h * (r - h);
+    if (dalpha) *dalpha = (chi / (T * T)) * (al - h / r);
+    return al;
+}
+
+// Heat capacity H [1 + alpha + (T + chi) alpha'] (the printed a T_keV^3 is the unit
+// a (1 keV)^3, folded into H) and the material energy H [T (1 + alpha) + chi alpha]
+// whose derivative it is.
+__host__ __device__ inline double olson_cv(double H, double chi, double T)
+{
+    double da;
+    const double al = olson_alpha(T, chi, &da);
+    return H * (1.0 + al + (T + chi) * da);
+}
+
+__host__ __device__ inline double olson_energy(double H, double chi, double T)
+{
+    const double al = olson_alpha(T, chi, nullptr);
+    return H * (T * (1.0 + al) + chi * al);
+}
+
+// The temperature whose Olson material energy is u > 0.  The energy rises
+// strictly with T: a bracket [lo, hi] with energy(lo) <= u <= energy(hi) is found
+// by doubling from T0, then Newton steps from T0 that stay inside the bracket
+// (else its midpoint), until a step moves T by at most 1e-15 T.  Returns -1 for
+// u <= 0 (no temperature).
+__host__ __device__ inline double olson_temperature(double H, double chi, double u, double T0)
+{
+    if (!(u > 0.0) || !isfinite(u)) return -1.0;
+    double lo = 0.0, hi = T0 > 0.0 ? T0 : 1.0;
+    for (int n = 0; n < 2100 && olson_energy(H, chi, hi) < u; ++n) {
+        lo = hi;
+        hi = 2.0 * hi;
+    }
+    double T = (T0 > lo && T0 < hi) ? T0 : 0.5 * (lo + hi);
+    for (int n = 0; n < 200; ++n) {
+        const double f = olson_energy(H, chi, T) - u;
+        if (f == 0.0) break;
+        if (f < 0.0) lo = T; else hi = T;
+        double Tn = T - f / olson_cv(H, chi, T);
+        if (!(Tn > lo && Tn < hi)) Tn = 0.5 * (lo + hi);
+        const double d = fabs(Tn - T);
+        T = Tn;
+        if (d <= 1e-15 * T) break;
+    }
+    return T;
+}
+
+// ---------------------------------------------------------------------------
+// Tabulated opacity: the interval [i, i+1] of n ascending nodes holding x and the
+// weight of node i+1 (clamped to the end intervals: weight 0 or 1 beyond them).
+__host__ __device__ inline int table_locate(const double* nodes, int n, double x, double* frac)
+{
+    if (x <= nodes[0]) { *frac = 0.0; return 0; }
+    if (x >= nodes[n - 1]) { *frac = 1.0; return n - 2; }
+    int lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (nodes[mid] <= x) lo = mid; else hi = mid;
+    }
+    *frac = (x - nodes[lo]) / (nodes[lo + 1] - nodes[lo]);
+    return lo;
+}
+
 // nu^-p with the exact cube for the paper's p = 3.
 __host__ __device__ inline double nu_pow(double nu, double p)
 {

@@ -62,7 +62,10 @@ __device__ inline Geo geo_of(const Inst& I)
 // fixed for a particle, so the push computes it once.  SIG_STIM: nu^-p times
 // the stimulated-emission factor 1 - e^{-nu/T} of the cell the particle is in
 // (Sec. 3.3), evaluated at every cell entry.
-enum { SIG_NU3 = 0, SIG_POW = 1, SIG_GROUP = 2, SIG_STIM = 3 };
+// SIG_TAB: a tabulated sigma(nu, T) (Sec. 3.4-3.5), from the row of the cell the
+// particle is in (ln sigma along the table's nu nodes at the cell's T^n) at the
+// particle's own nu interval, evaluated at every cell entry.
+enum { SIG_NU3 = 0, SIG_POW = 1, SIG_GROUP = 2, SIG_STIM = 3, SIG_TAB = 4 };
 
 // Stimulated-emission factor 1 - e^{-nu/T} (Sec. 3.3's opacity), or 1 without it.
 __device__ inline double stim_factor(const Consts& K, double nu, double T)
@@ -80,6 +83,34 @@ __device__ inline double group_factor(const Dev& D, const Consts& K, int edge_of
             + nu_pow(nh, K.nu_power) * stim_factor(K, nh, T)) / 6.0;
 }
 
+// sigma of material m at (nu, T) from the table: bilinear in (ln nu, ln T) on
+// ln sigma, constant beyond the end nodes (Sec. 3.4-3.5's printed opacities,
+// tabulated by the caller).
+__device__ inline double table_sigma(const Dev& D, const Consts& K, int m, double nu, double T)
+{
+    double a, b;
+    const int i = table_locate(D.tab_lnu, K.tab_nnu, log(nu), &a);
+    const int jt = table_locate(D.tab_lT, K.tab_nT, log(T), &b);
+    const int n = K.tab_nnu;
+    const double* L = D.tab_lsig + ((int64_t)m * K.tab_nT + jt) * n + i;
+    const double l00 = L[0], l10 = L[1], l01 = L[n], l11 = L[n + 1];
+    const double lo = (1.0 - a) * l00 + a * l10, hi = (1.0 - a) * l01 + a * l11;
+    return exp((1.0 - b) * lo + b * hi);
+}
+
+// Group opacity of material m at T from the table: Simpson's rule over the group.
+__device__ inline double table_group_sigma(const Dev& D, const Consts& K, int m, int edge_off, int g, double T)
+{
+    const double nl = D.nu[edge_off + g], nh = D.nu[edge_off + g + 1], nm = 0.5 * (nl + nh);
+    return (table_sigma(D, K, m, nl, T) + 4.0 * table_sigma(D, K, m, nm, T) + table_sigma(D, K, m, nh, T)) / 6.0;
+}
+
+// The volumetric source acts in the steps that start before its switch-off time.
+__device__ inline bool source_on(const Consts& K, uint32_t step)
+{
+    return K.has_src && (double)step * K.dt < K.q_toff;
+}
+
 // The flight scale of a particle, tau = eps^2 / (c sigma), with sigma = kappa
 // nu^-p (Remark 2; Simpson's group factor S_g instead of nu^-p with
 // UGKWP_FLAG_GROUP_SIGMA), is evaluated as the particle's factor eps^2 nu^p
@@ -90,6 +121,7 @@ __device__ inline double tau_factor(const Dev& D, const Consts& K, const Geo& I,
     if (SM == SIG_GROUP) return K.e2c / D.simpson[I.edge_off + g];
     if (SM == SIG_NU3) return K.e2c * (nu * nu * nu);
     if (SM == SIG_STIM && K.nu_power == 3.0) return K.e2c * (nu * nu * nu);
+    if (SM == SIG_TAB) return K.e2c;
     return K.e2c * pow(nu, K.nu_power);
 }
 
@@ -126,18 +158,43 @@ __global__ void k_tables(Dev D, Consts K)
     const Inst& I = D.inst[s.inst];
     const double Tc = D.T[I.cell_off + s.lcell];
     const double kap = K.t_power != 0.0 ? D.kappa[j] * pow(Tc, -K.t_power) : D.kappa[j];
-    const double sg = kap * group_factor(D, K, I.edge_off, s.g, Tc);
+    const double sg = K.table ? table_group_sigma(D, K, D.tab_mat[I.cell_off + s.lcell], I.edge_off, s.g, Tc)
+                              : kap * group_factor(D, K, I.edge_off, s.g, Tc);
     // flights: tau = (eps^2/c) f(nu)^-1 / kappa; with the stimulated-emission
-    // factor and group opacities the group factor's T dependence goes here
-    // (the push divides by S_g), per particle the push applies it itself
-    D.inv_kappa[j] = (K.stim && (K.flags & 1u)) ? D.simpson[I.edge_off + s.g] / sg
-                                                : 1.0 / kap;   // +inf for kappa = 0: no collision
+    // factor or a table and group opacities the group opacity's T dependence goes
+    // here (the push divides by S_g), per particle the push applies it itself
+    // (a table's per-particle flights read the cell rows instead)
+    D.inv_kappa[j] = ((K.stim || K.table) && (K.flags & 1u)) ? D.simpson[I.edge_off + s.g] / sg
+                     : K.table ? 1.0 / sg
+                               : 1.0 / kap;   // +inf for kappa = 0: no collision
     const double sv = K.c * sg * K.dt / (K.eps * K.eps);
     D.sig[j] = sg;
     D.sv[j] = sv;
     D.es[j] = exp(-sv);
     D.c4[j] = coef_c4(sv);
     D.wc[j] = coef_w(sv);
+}
+
+// The push's rows of a tabulated opacity: for every cell and nu node, ln sigma of
+// the cell's material interpolated to the cell's T^n (launched with the tables at
+// the start of each step).
+__global__ void k_tab_rows(Dev D, Consts K)
+{
+    if (!gate_open(D, K, 0)) return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= (int64_t)K.ncell * K.tab_nnu) return;
+    const int cell = (int)(j / K.tab_nnu), i = (int)(j % K.tab_nnu);
+    double b;
+    const int jt = table_locate(D.tab_lT, K.tab_nT, log(D.T[cell]), &b);
+    const double* L = D.tab_lsig + ((int64_t)D.tab_mat[cell] * K.tab_nT + jt) * K.tab_nnu + i;
+    D.tab_row[j] = (1.0 - b) * L[0] + b * L[K.tab_nnu];
+}
+
+// ln of the table's nodes and values, once at set-up (n entries of each array).
+__global__ void k_tab_logs(double* v, int64_t n)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) v[j] = log(v[j]);
 }
 
 // D of a face with face opacity sf and centre distance h (Appendix B, Eq. C2Formula).
@@ -213,6 +270,22 @@ __global__ void k_init_rho(Dev D, Consts K, const double* Tr0)
     D.rho[j] = v;
     D.rhop[j] = 0.0;
     D.phi0[j] = p;
+}
+
+// The source Q(x) = B(nu, Ts) f(x) of Sec. 3.4-3.5 on the transport equation's
+// right side, as the rate of rho per (cell, group) slot: (c/eps^2) f_cell phi_g(Ts).
+__global__ void k_source_planck(Dev D, Consts K, double* q, const double* f, double Ts)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= K.n_cg) return;
+    const Slot s = decode_slot(D, K, j);
+    double v = 0.0;
+    if (s.active) {
+        const Inst& I = D.inst[s.inst];
+        const double nl = D.nu[I.edge_off + s.g], nh = D.nu[I.edge_off + s.g + 1];
+        v = K.c / (K.eps * K.eps) * f[I.cell_off + s.lcell] * phi_group_direct(Ts, nl, nh, K.a, K.c);
+    }
+    q[j] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -804,7 +877,23 @@ struct Flight {
     int ix, iy;
     int32_t flips;         // FLIP_X / FLIP_Y toggled by each reflection during this step
     bool coll;
+    int ti;                // SIG_TAB: the particle's nu interval among the table nodes
+    double ta;             // and the weight of its upper node
 };
+
+// The flight scale of a particle in local cell lcell of its instance.
+template <int SM>
+__device__ inline double cell_tau(const Dev& D, const Consts& K, const Geo& I, double tfac, int lcell, int g,
+                                  double nu, const Flight& f)
+{
+    if (SM == SIG_TAB) {
+        const double* row = D.tab_row + (int64_t)(I.cell_off + lcell) * K.tab_nnu + f.ti;
+        return tfac * exp(-((1.0 - f.ta) * row[0] + f.ta * row[1]));
+    }
+    double t = tfac * D.inv_kappa[I.cg_off + ((uint32_t)lcell << I.lgGp) + (uint32_t)g];
+    if (SM == SIG_STIM) t = t / stim_factor(K, nu, D.T[I.cell_off + lcell]);
+    return t;
+}
 
 __device__ inline void draw_flight(const Consts& K, const Geo& I, uint64_t id, uint32_t step, Flight& f)
 {
@@ -902,8 +991,7 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTabl
         }
         lds_tally(T, D, type, index, w);
         if (xaxis) f.ix += pos ? 1 : -1; else f.iy += pos ? 1 : -1;
-        f.tau = tfac * D.inv_kappa[I.cg_off + ((uint32_t)(f.iy * I.nx + f.ix) << I.lgGp) + (uint32_t)g];
-        if (SM == SIG_STIM) f.tau = f.tau / stim_factor(K, nu, D.T[I.cell_off + f.iy * I.nx + f.ix]);
+        f.tau = cell_tau<SM>(D, K, I, tfac, f.iy * I.nx + f.ix, g, nu, f);
         draw_flight(K, I, id, step, f);
     }
 }
@@ -962,9 +1050,7 @@ __device__ inline bool enter_from_ghost(const Dev& D, const Consts& K, const Geo
     }
     lds_tally(T, D, type, index, w);
     f.t = te;
-    const int lcell = f.iy * I.nx + f.ix;
-    f.tau = tfac * D.inv_kappa[I.cg_off + ((uint32_t)lcell << I.lgGp) + (uint32_t)g];
-    if (SM == SIG_STIM) f.tau = f.tau / stim_factor(K, nu, D.T[I.cell_off + lcell]);
+    f.tau = cell_tau<SM>(D, K, I, tfac, f.iy * I.nx + f.ix, g, nu, f);
     draw_flight(K, I, id, step, f);
     return true;
 }
@@ -1100,8 +1186,10 @@ __global__ __launch_bounds__(BS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool
                 f.d = 0;
                 f.flips = 0;
                 const double tfac = tau_factor<SM>(D, K, I, nu, g);
-                f.tau = tfac * D.inv_kappa[I.cg_off + ((uint32_t)lcell << I.lgGp) + (uint32_t)g];
-                if (SM == SIG_STIM) f.tau = f.tau / stim_factor(K, nu, D.T[cell]);
+                f.ti = 0;
+                f.ta = 0.0;
+                if (SM == SIG_TAB) f.ti = table_locate(D.tab_lnu, K.tab_nnu, log(nu), &f.ta);
+                f.tau = cell_tau<SM>(D, K, I, tfac, lcell, g, nu, f);
                 int out;
                 if (gside && !enter_from_ghost<DIM, SM>(D, K, I, T, id, step, tfac, g, nu, w, gside - 1, f)) {
                     out = 3;                                        // never entered the domain
@@ -1421,7 +1509,9 @@ __device__ inline double wave_source(const Dev& D, const Consts& K, const Inst& 
         a_out += ty2 + ty3;
     }
     *inflow_out = inflow;
-    return rho_here + I.dt_V * fsum + (a_in - a_out) / I.V;
+    const double Q = rho_here + I.dt_V * fsum + (a_in - a_out) / I.V;
+    // a volumetric source adds dt q in the steps it is on
+    return source_on(K, *D.step) ? Q + K.dt * D.qsrc[j] : Q;
 }
 
 // Q of sweep k >= 1 with UGKWP_FLAG_WAVE_ITER: the wave flux from the iterate
@@ -1517,6 +1607,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         if (wid == 0) res_prev = res_slot(D, K, 0, k - 1)[lane];
     }
     if (!(K.gate == GATE_OFF || now == K.gate) || flags == 0) return;
+    if (FIRST && j == 0 && K.has_src) *D.src_on = source_on(K, now) ? 1 : 0;   // for the commit's ledger
     Inst I;
     const Slot s = decode_slot_rec<SINGLE>(D, K, j, I);
     if (decide_prev) {
@@ -1575,22 +1666,30 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     }
     // temperature-dependent opacity: kappa of the slot and of the neighbours
     // across each face, and the neighbours' iterate T^k
+    // (a tabulated opacity: the materials of the slot's cell and of the neighbours)
     double kap_j = 0.0, Sg = 0.0, Sn[4] = {0.0, 0.0, 0.0, 0.0};
     double kap_n[4] = {0.0, 0.0, 0.0, 0.0}, T_nb[4] = {1.0, 1.0, 1.0, 1.0};
+    int mat_j = 0, mat_n[4] = {0, 0, 0, 0};
     if (TDEP && act) {
-        kap_j = D.kappa[j];
-        Sg = group_factor(D, K, I.edge_off, g, FIRST ? D.T[cell] : D.T_new[cell]);
+        if (K.table) mat_j = D.tab_mat[cell];
+        else {
+            kap_j = D.kappa[j];
+            Sg = group_factor(D, K, I.edge_off, g, FIRST ? D.T[cell] : D.T_new[cell]);
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q >= nf || !F.inside[q]) continue;
             const bool lo = (q & 1) == 0;
             const int nbc = cell + (q < 2 ? (lo ? -1 : 1) : (lo ? -nx : nx));
-            kap_n[q] = D.kappa[F.nbj[q]];
             T_nb[q] = FIRST ? D.T[nbc] : D.T_new[nbc];
-            Sn[q] = K.stim ? group_factor(D, K, I.edge_off, g, T_nb[q]) : Sg;
+            if (K.table) mat_n[q] = D.tab_mat[nbc];
+            else {
+                kap_n[q] = D.kappa[F.nbj[q]];
+                Sn[q] = K.stim ? group_factor(D, K, I.edge_off, g, T_nb[q]) : Sg;
+            }
         }
     }
-    double Tn = 1.0, Tk = 1.0, dtcv = 0.0;
+    double Tn = 1.0, Tk = 1.0, dtcv = 0.0, olH = 0.0, olchi = 0.0;
     uint8_t pinned = 0;
     double nu_lo = 0.0, nu_top = 0.0;
     if (load) {
@@ -1598,6 +1697,10 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         Tk = FIRST ? Tn : D.T_new[cell];
         pinned = D.pinned[cell];
         dtcv = D.dtcv[cell];
+        if (TDEP && K.olson) {
+            olH = D.olH[cell];
+            olchi = D.olchi[cell];
+        }
         if (g <= G) nu_lo = D.nu[I.edge_off + g];
         if (g == G - 1 && G == Gp) nu_top = D.nu[I.edge_off + G];
     }
@@ -1621,7 +1724,8 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         if (TDEP) {
             // the coefficient step of Algorithm 2: sigma, lambda and the face
             // coefficients of this sweep from the iterate T^k
-            const double sk = kap_j * pow(Tk, -K.t_power) * Sg;
+            const double sk = K.table ? table_group_sigma(D, K, mat_j, I.edge_off, g, Tk)
+                                      : kap_j * pow(Tk, -K.t_power) * Sg;
             sig = sk;
             lam = K.c * sk * K.dt / (K.eps * K.eps);
 #pragma unroll
@@ -1629,7 +1733,8 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
                 if (q >= nf) continue;
                 double sf = sk;
                 if (F.inside[q]) {
-                    const double sn = kap_n[q] * pow(T_nb[q], -K.t_power) * Sn[q];
+                    const double sn = K.table ? table_group_sigma(D, K, mat_n[q], I.edge_off, g, T_nb[q])
+                                              : kap_n[q] * pow(T_nb[q], -K.t_power) * Sn[q];
                     sf = (sk + sn > 0.0) ? 2.0 * (sk * sn) / (sk + sn) : 0.0;
                 }
                 Df[q] = face_coef(K, sf, q < 2 ? I.dx : I.dy);
@@ -1657,10 +1762,28 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     contrib = group_sum(contrib, Gp);
     if (LIN) dcon = group_sum(dcon, Gp);
 
-    double Tnew = 1.0;
+    double Tnew = 1.0, uend = 0.0;
     bool bad = false;
     if (work) {
-        if (LIN) Tnew = pinned ? Tn : Tk + (Tn - Tk + dtcv * contrib) / (1.0 + dtcv * dcon);
+        if (TDEP && olH > 0.0) {
+            // Olson's heat capacity: the energy equation in the material energy U,
+            // U(T^{n+1}) = U(T^n) + exchange.  Literal: U(T^{k+1}) = U(T^n) +
+            // exchange(phi^k), solved for T^{k+1}; linearized: one Newton step at
+            // T^k with U and the emission linearized, whose material energy is
+            // U(T^k) + C_v(T^k)(T^{k+1} - T^k).
+            const double un = olson_energy(olH, olchi, Tn);
+            if (pinned) {
+                Tnew = Tn;
+                uend = un;
+            } else if (LIN) {
+                const double uk = olson_energy(olH, olchi, Tk), ck = olson_cv(olH, olchi, Tk);
+                Tnew = Tk + (un - uk + K.dt / (K.eps * K.eps) * contrib) / (ck + K.dt / (K.eps * K.eps) * dcon);
+                uend = uk + ck * (Tnew - Tk);
+            } else {
+                uend = un + K.dt / (K.eps * K.eps) * contrib;
+                Tnew = olson_temperature(olH, olchi, uend, Tk);
+            }
+        } else if (LIN) Tnew = pinned ? Tn : Tk + (Tn - Tk + dtcv * contrib) / (1.0 + dtcv * dcon);
         else Tnew = pinned ? Tn : Tn + dtcv * contrib;
         if (LIN && s.active) {
             // rho^{k+1} with the linearized emission of T^{k+1}
@@ -1716,6 +1839,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
             atomicOr((unsigned long long*)(D.counters + CNT_ERR), ERR_TEMP);
         }
         D.T_new[cell] = Tnew;
+        if (TDEP && olH > 0.0) D.uend[cell] = uend;
     }
     // residual maxima: wavefront, then runs of wavefronts of one instance in the block
     // the four maxima are non-negative (or NaN): reduced as bit patterns
@@ -1808,6 +1932,8 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
     const int ix = DIM == 1 ? s.lcell : s.lcell % nx, iy = DIM == 1 ? 0 : s.lcell / nx;
     const int cell = I.cell_off + s.lcell;
     double surv = 0.0, rho = 0.0, rho_new = 0.0, phi = 0.0, phi_next = 0.0, cv = 0.0, T0 = 0.0, T1 = 0.0;
+    double olH = 0.0, olchi = 0.0, uend = 0.0, qs = 0.0;
+    int src = 0;
     uint8_t pin = 0;
     bool bnd[4] = {false, false, false, false};
     int64_t fs[4] = {0, 0, 0, 0};
@@ -1823,6 +1949,15 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
             cv = D.cvol[cell];
             T0 = D.T[cell];
             T1 = D.T_new[cell];
+            if (K.olson) {
+                olH = D.olH[cell];
+                olchi = D.olchi[cell];
+                if (olH > 0.0) uend = D.uend[cell];
+            }
+        }
+        if (K.has_src) {
+            src = *D.src_on;
+            qs = D.qsrc[j];
         }
         const double* phib = D.phib + (int64_t)s.inst * 4 * MAX_G;
 #pragma unroll
@@ -1912,10 +2047,12 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
     if (witer && in && s.active && !(ns_guess & 1)) D.rho_new[j] = rho_new;
     double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // inflow_eq, exit/c, injection, e0, e1,
                                                          // inflow_wave (WAVE_ITER), inflow_particles
-    if (in && s.active && (K.t_power != 0.0 || K.stim) && (bnd[0] || bnd[1] || bnd[2] || bnd[3])) {
+    if (in && s.active && (K.t_power != 0.0 || K.stim || K.table) && (bnd[0] || bnd[1] || bnd[2] || bnd[3])) {
         // temperature-dependent opacity: the boundary faces' coefficients at the
         // step's final temperature (the iteration has converged on it)
-        const double sk = D.kappa[j] * pow(D.T_new[cell], -K.t_power) * group_factor(D, K, I.edge_off, g, D.T_new[cell]);
+        const double Tf = D.T_new[cell];
+        const double sk = K.table ? table_group_sigma(D, K, D.tab_mat[cell], I.edge_off, g, Tf)
+                                  : D.kappa[j] * pow(Tf, -K.t_power) * group_factor(D, K, I.edge_off, g, Tf);
 #pragma unroll
         for (int q = 0; q < 2 * DIM; ++q)
             if (bnd[q]) Df[q] = face_coef(K, sk, (q >> 1) == 0 ? I.dx : I.dy);
@@ -1934,9 +2071,14 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
         }
         v[5] = winf;
         if (pin) v[2] = I.V * (K.dt * D.sig[j] / (K.eps * K.eps)) * (phi - rho_new);
+        if (src) v[2] += I.V * K.dt * qs / K.c;
         v[3] = I.V * rho / K.c;
         v[4] = I.V * rho_new / K.c;
-        if (g == 0) {
+        if (g == 0 && olH > 0.0) {
+            // Olson's material energy, and the one the last sweep gave
+            v[3] += I.V * olson_energy(olH, olchi, T0);
+            v[4] += I.V * uend;
+        } else if (g == 0) {
             v[3] += I.V * cv * T0;
             v[4] += I.V * cv * T1;
         }
@@ -2043,6 +2185,12 @@ hipError_t set_head_series(const HeadSeries& hs)
 void launch_tables(const Dev& D, const Consts& K, hipStream_t st)
 {
     k_tables<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K);
+    if (K.table) k_tab_rows<<<blocks((int64_t)K.ncell * K.tab_nnu, 256), 256, 0, st>>>(D, K);
+}
+
+void launch_tab_logs(double* v, int64_t n, hipStream_t st)
+{
+    if (n > 0) k_tab_logs<<<blocks(n, 256), 256, 0, st>>>(v, n);
 }
 
 void launch_face_D(const Dev& D, const Consts& K, int inst, int axis, int64_t nslots, hipStream_t st)
@@ -2058,6 +2206,11 @@ void launch_ghost_phi(const Dev& D, const Consts& K, double* phib, hipStream_t s
 void launch_init_rho(const Dev& D, const Consts& K, const double* Tr0, hipStream_t st)
 {
     k_init_rho<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K, Tr0);
+}
+
+void launch_source_planck(const Dev& D, const Consts& K, double* q, const double* f, double Ts, hipStream_t st)
+{
+    k_source_planck<<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K, q, f, Ts);
 }
 
 // Tally clears, particle counts and their exclusive scan (births per slot ->
@@ -2121,6 +2274,7 @@ static int push_bs_index(int threads)
 static int sig_mode(const Consts& K)
 {
     if (K.flags & 1u) return SIG_GROUP;
+    if (K.table) return SIG_TAB;
     if (K.stim) return SIG_STIM;
     return K.nu_power == 3.0 ? SIG_NU3 : SIG_POW;
 }
@@ -2148,12 +2302,13 @@ static int push_occupancy_sm(int sm, int threads)
         case SIG_NU3: return push_occupancy_bs<DIM, SINGLE, SIG_NU3>(threads);
         case SIG_POW: return push_occupancy_bs<DIM, SINGLE, SIG_POW>(threads);
         case SIG_GROUP: return push_occupancy_bs<DIM, SINGLE, SIG_GROUP>(threads);
+        case SIG_TAB: return push_occupancy_bs<DIM, SINGLE, SIG_TAB>(threads);
         default: return push_occupancy_bs<DIM, SINGLE, SIG_STIM>(threads);
     }
 }
 
 // Resident push blocks per CU of the given block size (cached per kernel).
-static int g_push_occ[2][2][4][2] = {};
+static int g_push_occ[2][2][5][2] = {};
 
 int push_blocks_per_cu(int dim, const Consts& K, int threads)
 {
@@ -2191,6 +2346,7 @@ static void push_mode(int sm, const PushShape& sh, const Dev& D, const Consts& K
     if (sm == SIG_NU3) push_bs<DIM, SINGLE, SIG_NU3>(sh, D, K, In, Out, st);
     else if (sm == SIG_POW) push_bs<DIM, SINGLE, SIG_POW>(sh, D, K, In, Out, st);
     else if (sm == SIG_GROUP) push_bs<DIM, SINGLE, SIG_GROUP>(sh, D, K, In, Out, st);
+    else if (sm == SIG_TAB) push_bs<DIM, SINGLE, SIG_TAB>(sh, D, K, In, Out, st);
     else push_bs<DIM, SINGLE, SIG_STIM>(sh, D, K, In, Out, st);
 }
 
@@ -2276,7 +2432,9 @@ void launch_si_sweeps(const Dev& D, const Consts& K, int k0, int k1, hipStream_t
         }
         // every instance of a context has the same dimension
         const bool lin = (K.flags & UGKWP_FLAG_SI_LINEARIZED) != 0;
-        auto kern = (K.t_power != 0.0 || K.stim) ? (lin ? sweep_kernel<true, true>(K, fold, k) : sweep_kernel<true, false>(K, fold, k))
+        // a temperature-dependent or tabulated opacity and Olson's heat capacity take
+        // the sweeps that re-evaluate the material from the iterate
+        auto kern = (K.t_power != 0.0 || K.stim || K.table || K.olson) ? (lin ? sweep_kernel<true, true>(K, fold, k) : sweep_kernel<true, false>(K, fold, k))
                                      : (lin ? sweep_kernel<false, true>(K, fold, k) : sweep_kernel<false, false>(K, fold, k));
         kern<<<blocks(K.n_cg, SI_THREADS), SI_THREADS, 0, st>>>(D, K, k, sweep_in(D, k), sweep_out(D, k),
                                                                     fold && k > k0 ? 1 : 0, sweep_rho(D, K, k),

@@ -15,9 +15,13 @@ struct ZeroList {
 hipError_t set_head_series(const HeadSeries& hs);
 
 void launch_tables(const Dev& D, const Consts& K, hipStream_t st);
+// ln of n doubles in place (the opacity table's nodes and values at set-up).
+void launch_tab_logs(double* v, int64_t n, hipStream_t st);
 void launch_face_D(const Dev& D, const Consts& K, int inst, int axis, int64_t nslots, hipStream_t st);
 void launch_ghost_phi(const Dev& D, const Consts& K, double* phib, hipStream_t st);
 void launch_init_rho(const Dev& D, const Consts& K, const double* Tr0, hipStream_t st);
+// q[slot] = (c/eps^2) f[cell] phi_g(Ts): a Planckian volumetric source's rate
+void launch_source_planck(const Dev& D, const Consts& K, double* q, const double* f, double Ts, hipStream_t st);
 // clears Z, counts particles per slot and scans the counts into birth offsets
 void launch_count_scan(const Dev& D, const Consts& K, const ZeroList& Z, int64_t* part, hipStream_t st);
 int64_t count_partials_size();    // entries of `part` the small-context path needs

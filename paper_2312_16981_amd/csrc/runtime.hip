@@ -182,6 +182,13 @@ struct ugkwp_ctx {
     int64_t* part = nullptr;
     int64_t n_part = 0;
     double* d_phib = nullptr;
+    // Olson's material models (allocated on first use)
+    double* olH_buf = nullptr;
+    double* olchi_buf = nullptr;
+    double* uend_buf = nullptr;
+    double* qsrc_buf = nullptr;
+    int* src_on_buf = nullptr;
+    int32_t* tab_mat_buf = nullptr;
 
     // step records: counters | birth totals | per-instance state | per-instance
     // energy sums [| their sub-slots], N_RECORDS of them on the device (every
@@ -276,6 +283,10 @@ struct ugkwp_ctx {
         D = Dev{};
         mv[0] = mv[1] = stb[0] = stb[1] = Pool{};
         have_opacity = have_material = false;
+        olH_buf = olchi_buf = uend_buf = qsrc_buf = nullptr;
+        src_on_buf = nullptr;
+        tab_mat_buf = nullptr;
+        K.olson = K.table = K.has_src = 0;
     }
 
     // ---------------------------------------------------------------- set-up
@@ -620,6 +631,143 @@ struct ugkwp_ctx {
         rec_sweeps.clear();
     }
 
+    // ---------------------------------------------------------------- Olson's material models
+    // The device arrays of a model, allocated on its first set-up call and kept.
+    template <class T>
+    T* model_array(T*& p, size_t n)
+    {
+        if (!p) p = dalloc<T>(owned, n);
+        return p;
+    }
+
+    // H and chi per cell (all instances); NULL H: off
+    void set_heat_capacity(const double* H, const double* chi)
+    {
+        if (rec_cap > 0) fail(UGKWP_EINVAL, "the material cannot change while a record is kept (ugkwp_record(ctx, 0) first)");
+        drop_graphs();
+        if (!H) {
+            K.olson = 0;
+            return;
+        }
+        if (!chi) fail(UGKWP_EINVAL, "null chi");
+        for (int c = 0; c < ncell; ++c)
+            if (!(H[c] >= 0.0) || !std::isfinite(H[c]) || !(chi[c] >= 0.0) || !std::isfinite(chi[c]))
+                fail(UGKWP_EINVAL, "H and chi must be finite and >= 0");
+        double* dH = model_array(olH_buf, (size_t)ncell);
+        double* dchi = model_array(olchi_buf, (size_t)ncell);
+        model_array(uend_buf, (size_t)ncell);
+        HIPCHK(hipMemcpyAsync(dH, H, sizeof(double) * ncell, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(dchi, chi, sizeof(double) * ncell, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemsetAsync(uend_buf, 0, sizeof(double) * ncell, st));
+        HIPCHK(hipStreamSynchronize(st));
+        D.olH = dH;
+        D.olchi = dchi;
+        D.uend = uend_buf;
+        K.olson = 1;
+    }
+
+    // q [cell][G] of every instance, or (f != nullptr) the Planckian source
+    // (c/eps^2) f phi_g(Ts); both null: off
+    void set_source(const double* q, const double* f, double Ts, double t_off)
+    {
+        if (rec_cap > 0) fail(UGKWP_EINVAL, "the source cannot change while a record is kept (ugkwp_record(ctx, 0) first)");
+        drop_graphs();
+        if (!q && !f) {
+            K.has_src = 0;
+            return;
+        }
+        if (!(t_off >= 0.0)) fail(UGKWP_EINVAL, "t_off must be >= 0");
+        double* dq = model_array(qsrc_buf, (size_t)K.n_cg);
+        model_array(src_on_buf, 1);
+        if (q) {
+            std::vector<double> h((size_t)K.n_cg, 0.0);
+            int64_t off = 0;
+            for (int k = 0; k < n_inst; ++k) {
+                const Inst& I = inst[k];
+                for (int64_t e = 0; e < (int64_t)I.ncell * I.G; ++e)
+                    if (!(q[off + e] >= 0.0) || !std::isfinite(q[off + e])) fail(UGKWP_EINVAL, "q must be finite and >= 0");
+                pack_cg(h, k, q + off);
+                off += (int64_t)I.ncell * I.G;
+            }
+            HIPCHK(hipMemcpyAsync(dq, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+        } else {
+            if (!(Ts > 0.0) || !std::isfinite(Ts)) fail(UGKWP_EINVAL, "the source temperature must be positive and finite");
+            for (int c = 0; c < ncell; ++c)
+                if (!(f[c] >= 0.0) || !std::isfinite(f[c])) fail(UGKWP_EINVAL, "f must be finite and >= 0");
+            double* df = nullptr;
+            HIPCHK(hipMalloc(&df, sizeof(double) * ncell));
+            hipError_t e = hipMemcpyAsync(df, f, sizeof(double) * ncell, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) {
+                launch_source_planck(D, K, dq, df, Ts, st);
+                e = hipStreamSynchronize(st);
+            }
+            (void)hipFree(df);
+            if (e != hipSuccess) fail(UGKWP_EHIP, "set_source_planck: %s", hipGetErrorString(e));
+        }
+        HIPCHK(hipMemsetAsync(src_on_buf, 0, sizeof(int), st));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipGetLastError());
+        D.qsrc = dq;
+        D.src_on = src_on_buf;
+        K.has_src = 1;
+        K.q_toff = t_off;
+    }
+
+    void set_opacity_table(int nmat, const int32_t* mat, int nnu, const double* nu, int nT, const double* T,
+                           const double* sig)
+    {
+        if (rec_cap > 0) fail(UGKWP_EINVAL, "the opacity cannot change while a record is kept (ugkwp_record(ctx, 0) first)");
+        if (nmat < 1 || nnu < 2 || nT < 2 || !mat || !nu || !T || !sig) fail(UGKWP_EINVAL, "bad table sizes or null arrays");
+        for (int c = 0; c < ncell; ++c)
+            if (mat[c] < 0 || mat[c] >= nmat) fail(UGKWP_EINVAL, "material index out of range");
+        for (int k = 0; k < nnu; ++k)
+            if (!(nu[k] > 0) || !std::isfinite(nu[k]) || (k > 0 && !(nu[k] > nu[k - 1])))
+                fail(UGKWP_EINVAL, "nu nodes must be positive, finite and ascending");
+        for (int k = 0; k < nT; ++k)
+            if (!(T[k] > 0) || !std::isfinite(T[k]) || (k > 0 && !(T[k] > T[k - 1])))
+                fail(UGKWP_EINVAL, "T nodes must be positive, finite and ascending");
+        const size_t nt = (size_t)nmat * nT * nnu;
+        for (size_t k = 0; k < nt; ++k)
+            if (!(sig[k] > 0) || !std::isfinite(sig[k])) fail(UGKWP_EINVAL, "table values must be positive and finite");
+        drop_graphs();
+        // the arrays of an earlier table are kept in `owned` until the context ends
+        int32_t* dmat = model_array(tab_mat_buf, (size_t)ncell);
+        double* dnu = dalloc<double>(owned, (size_t)nnu);
+        double* dT = dalloc<double>(owned, (size_t)nT);
+        double* dsig = dalloc<double>(owned, nt);
+        double* drow = dalloc<double>(owned, (size_t)ncell * nnu);
+        HIPCHK(hipMemcpyAsync(dmat, mat, sizeof(int32_t) * ncell, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(dnu, nu, sizeof(double) * nnu, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(dT, T, sizeof(double) * nT, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(dsig, sig, sizeof(double) * nt, hipMemcpyHostToDevice, st));
+        launch_tab_logs(dnu, nnu, st);
+        launch_tab_logs(dT, nT, st);
+        launch_tab_logs(dsig, (int64_t)nt, st);
+        D.tab_mat = dmat;
+        D.tab_lnu = dnu;
+        D.tab_lT = dT;
+        D.tab_lsig = dsig;
+        D.tab_row = drow;
+        K.table = 1;
+        K.tab_nnu = nnu;
+        K.tab_nT = nT;
+        // the push now runs the table's flights: its default launch shape follows
+        push_shape = push_default_shape(dim, K);
+        push_shape.blocks = std::min(push_shape.blocks, MAX_PUSH_BLOCKS);
+        if (have_material) {
+            launch_tables(D, K, st);
+            for (int k = 0; k < n_inst; ++k) {
+                const Inst& I = inst[k];
+                launch_face_D(D, K, k, 0, (int64_t)(I.nx + 1) * I.ny * I.Gp, st);
+                if (dim == 2) launch_face_D(D, K, k, 1, (int64_t)I.nx * (I.ny + 1) * I.Gp, st);
+            }
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipGetLastError());
+        have_opacity = true;
+    }
+
     Pool view(int m, int t) const
     {
         Pool p = stb[t];
@@ -772,7 +920,7 @@ struct ugkwp_ctx {
         add(D.diag_sub, (int64_t)DIAG_SUB * 8 * n_inst);
         add(D.res, (int64_t)n_inst * RES_SUB * (int64_t)(sizeof(Resid) / 8));   // sweep 0's residual slots
         // a temperature-dependent opacity: the step's tables at its T^n
-        if (K.t_power != 0.0 || K.stim) launch_tables(D, K, st);
+        if (K.t_power != 0.0 || K.stim || K.table) launch_tables(D, K, st);
         launch_count_scan(D, K, z, part, st);
         if (K.flags & UGKWP_FLAG_SLOPES) launch_slopes(dim, D, K, D.rhoh, false, st);
         launch_sample(dim, D, K, view(cur_mv, cur_st), st);
@@ -1383,6 +1531,7 @@ uint64_t state_layout(const ugkwp_ctx* c)
     f.add(c->K.c); f.add(c->K.a); f.add(c->K.eps); f.add(c->K.dt); f.add(c->K.nu_power);
     f.add(c->K.flags);
     f.add(c->K.tau_C); f.add(c->K.tau_jump); f.add(c->K.t_power); f.add(c->K.stim);
+    f.add(c->K.olson); f.add(c->K.table); f.add(c->K.has_src);
     for (const HostInst& h : c->hi) {
         f.add(h.nx); f.add(h.ny); f.add(h.G);
         f.add(h.x0); f.add(h.x1); f.add(h.y0); f.add(h.y1);
@@ -1574,6 +1723,43 @@ int ugkwp_set_material(ugkwp_ctx* ctx, const double* cv, const double* T0, const
     });
 }
 
+int ugkwp_set_heat_capacity(ugkwp_ctx* ctx, const double* H, const double* chi)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        if (!ctx->have_material) fail(UGKWP_EINVAL, "set_heat_capacity needs the mesh and material first");
+        ctx->set_heat_capacity(H, chi);
+    });
+}
+
+int ugkwp_set_source(ugkwp_ctx* ctx, const double* q, double t_off)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        if (!ctx->have_material) fail(UGKWP_EINVAL, "set_source needs the mesh and material first");
+        ctx->set_source(q, nullptr, 0.0, t_off);
+    });
+}
+
+int ugkwp_set_source_planck(ugkwp_ctx* ctx, const double* f, double Ts, double t_off)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        if (!ctx->have_material) fail(UGKWP_EINVAL, "set_source_planck needs the mesh and material first");
+        ctx->set_source(nullptr, f, Ts, t_off);
+    });
+}
+
+int ugkwp_set_opacity_table(ugkwp_ctx* ctx, int nmat, const int32_t* mat, int nnu, const double* nu, int nT,
+                            const double* T, const double* sig)
+{
+    if (!ctx) return UGKWP_EINVAL;
+    return guarded(ctx, [&] {
+        if (!ctx->have_material) fail(UGKWP_EINVAL, "set_opacity_table needs the mesh and material first");
+        ctx->set_opacity_table(nmat, mat, nnu, nu, nT, T, sig);
+    });
+}
+
 int ugkwp_init_batch(ugkwp_ctx* ctx, int n_inst, const ugkwp_instance* d)
 {
     if (!ctx) return UGKWP_EINVAL;
@@ -1626,6 +1812,8 @@ int ugkwp_record(ugkwp_ctx* ctx, int max_steps)
         if (max_steps > 0 && (ctx->P.flags & (UGKWP_FLAG_SLOPES | UGKWP_FLAG_WAVE_ITER | UGKWP_FLAG_BOUNDARY_PARTICLES)))
             fail(UGKWP_EINVAL, "the adjoint covers neither the slopes of the wave part, its flux from the iterate, "
                                "nor boundary-source particles");
+        if (max_steps > 0 && (ctx->K.olson || ctx->K.table || ctx->K.has_src))
+            fail(UGKWP_EINVAL, "the adjoint covers neither Olson's heat capacity, a tabulated opacity nor a volumetric source");
         ctx->record_start(max_steps);
     });
 }

@@ -34,6 +34,7 @@ EXPORTED = [
     "ugkwp_eval_uniform", "ugkwp_eval_neg_log", "ugkwp_eval_sample_nu", "ugkwp_record", "ugkwp_recorded_steps",
     "ugkwp_adjoint", "ugkwp_autotune", "ugkwp_get_totals", "ugkwp_set_phase_times", "ugkwp_set_push_timing",
     "ugkwp_state_bytes", "ugkwp_get_state", "ugkwp_set_state", "ugkwp_set_material_noalloc",
+    "ugkwp_set_heat_capacity", "ugkwp_set_source", "ugkwp_set_source_planck", "ugkwp_set_opacity_table",
 ]
 
 _d = C.c_double
@@ -132,6 +133,10 @@ def load():
     L.ugkwp_set_material.argtypes = [vp, _pd, _pd, _pd, _pu8]
     L.ugkwp_set_material_noalloc.argtypes = [vp, _pd, _pd, _pd, _pu8]
     L.ugkwp_init_batch.argtypes = [vp, C.c_int, C.POINTER(Instance)]
+    L.ugkwp_set_heat_capacity.argtypes = [vp, _pd, _pd]
+    L.ugkwp_set_source.argtypes = [vp, _pd, _d]
+    L.ugkwp_set_source_planck.argtypes = [vp, _pd, _d, _d]
+    L.ugkwp_set_opacity_table.argtypes = [vp, C.c_int, _pi32, C.c_int, _pd, C.c_int, _pd, _pd]
     L.ugkwp_step.argtypes = [vp, C.c_int]
     L.ugkwp_num_instances.argtypes = [vp]
     L.ugkwp_get_fields.argtypes = [vp, C.c_int, _pd, _pd, _pd, C.c_int]
@@ -235,6 +240,31 @@ class Context:
         p = None if pinned is None else np.ascontiguousarray(pinned, dtype=np.uint8)
         self._chk(load().ugkwp_set_material_noalloc(self.h, _p(a), _p(b), _p(c), _p(p, _pu8)),
                   "set_material_noalloc")
+
+    def set_heat_capacity(self, H, chi):
+        """Olson's heat capacity per cell (H = 0: the cell keeps its C_v); H None: off."""
+        if H is None:
+            self._chk(load().ugkwp_set_heat_capacity(self.h, None, None), "set_heat_capacity")
+            return
+        a, b = _f64(H), _f64(chi)
+        self._chk(load().ugkwp_set_heat_capacity(self.h, _p(a), _p(b)), "set_heat_capacity")
+
+    def set_source(self, q, t_off=float("inf")):
+        """Volumetric source rate q [ncell][G]; None: off."""
+        a = None if q is None else _f64(q)
+        self._chk(load().ugkwp_set_source(self.h, _p(a), float(t_off)), "set_source")
+
+    def set_source_planck(self, f, Ts, t_off=float("inf")):
+        """The source B(nu, Ts) f(x) (rate (c/eps^2) f phi_g(Ts), computed on the device)."""
+        a = _f64(f)
+        self._chk(load().ugkwp_set_source_planck(self.h, _p(a), float(Ts), float(t_off)), "set_source_planck")
+
+    def set_opacity_table(self, mat, nu, T, sigma):
+        """Tabulated sigma [nmat][nT][nnu] on nodes nu, T; mat [ncell]."""
+        m = np.ascontiguousarray(mat, dtype=np.int32)
+        n, t, sg = _f64(nu), _f64(T), _f64(sigma)
+        self._chk(load().ugkwp_set_opacity_table(self.h, int(sg.shape[0]), _p(m, _pi32), len(n), _p(n), len(t),
+                                                 _p(t), _p(sg)), "set_opacity_table")
 
     def init_batch(self, instances: Sequence["Instance"], arrays_keepalive):
         arr = (Instance * len(instances))(*instances)
@@ -394,7 +424,46 @@ def from_problem(prob, stream=None, pool_capacity: Optional[int] = None, sort_in
                   prob.nu_edges, prob.seed, prob.w_ref)
     ctx.set_opacity(prob.kappa)
     ctx.set_material(prob.cv, prob.T0, prob.Tr0, prob.pinned)
+    _set_models(ctx, [prob])
     return ctx
+
+
+def _set_models(ctx, probs):
+    """Olson's material models of the problems (heat capacity, source, opacity
+    table), concatenated over the instances: instances without a model get its
+    neutral value (H = 0, q = 0, their own material numbers after the others')."""
+    if any(p.olson_H is not None for p in probs):
+        H = np.concatenate([np.zeros(p.ncell) if p.olson_H is None else np.asarray(p.olson_H, float) for p in probs])
+        chi = np.concatenate([np.zeros(p.ncell) if p.olson_chi is None else np.asarray(p.olson_chi, float)
+                              for p in probs])
+        ctx.set_heat_capacity(H, chi)
+    srcs = [p for p in probs if p.source is not None or p.source_shape is not None]
+    if srcs:
+        if len({p.source_t_off for p in srcs}) != 1:
+            raise ValueError("the instances' sources must share their switch-off time")
+        t_off = srcs[0].source_t_off
+        if all(p.source is None for p in probs) and len({p.source_T for p in srcs}) == 1:
+            f = np.concatenate([np.zeros(p.ncell) if p.source_shape is None else np.asarray(p.source_shape, float)
+                                for p in probs])
+            ctx.set_source_planck(f, srcs[0].source_T, t_off)
+        elif all(p.source_shape is None for p in probs):
+            ctx.set_source(np.concatenate([np.zeros(p.ncell * p.G) if p.source is None
+                                           else np.asarray(p.source, float).reshape(-1) for p in probs]), t_off)
+        else:
+            raise ValueError("a batch takes either rate sources or Planckian sources of one temperature")
+    tabs = [p.opacity_table for p in probs if p.opacity_table is not None]
+    if tabs:
+        if len(tabs) != len(probs):
+            raise ValueError("a tabulated opacity must be given for every instance of a batch or none")
+        t0 = tabs[0]
+        if any(not (np.array_equal(t["nu"], t0["nu"]) and np.array_equal(t["T"], t0["T"])) for t in tabs):
+            raise ValueError("the instances' opacity tables must share their nodes")
+        mats, sig, off = [], [], 0
+        for t in tabs:
+            mats.append(np.asarray(t["mat"], np.int64) + off)
+            sig.append(np.asarray(t["sigma"], float))
+            off += sig[-1].shape[0]
+        ctx.set_opacity_table(np.concatenate(mats), t0["nu"], t0["T"], np.concatenate(sig, axis=0))
 
 
 def from_batch(probs, stream=None, pool_capacity: Optional[int] = None, sort_interval: int = 0,
@@ -438,6 +507,7 @@ def from_batch(probs, stream=None, pool_capacity: Optional[int] = None, sort_int
     ctx.init_batch(insts, keep)
     ctx.layout = [(p.ncell, p.G, p.nx, p.ny, p.dim) for p in probs]
     ctx._keep = keep
+    _set_models(ctx, probs)
     return ctx
 
 

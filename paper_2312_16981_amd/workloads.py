@@ -270,6 +270,44 @@ def olson1d(nx: int = 128, G: int = 24, **kw) -> Problem:
                    source_shape=np.exp(-693.0 * xc ** 3), source_T=0.5, source_t_off=2.0)
 
 
+# Aluminium blocks of the 2-D Olson stand-in (lower-left corners, side 0.5 cm): the
+# paper's layout exists only as a figure, so a layout symmetric about y = x of the
+# same kind (blocks around the source corner and along the diagonal) stands in.
+OLSON2D_BLOCKS = ((1.0, 0.0), (0.0, 1.0), (1.5, 1.0), (1.0, 1.5), (2.5, 0.5), (0.5, 2.5), (2.5, 2.5))
+
+
+def olson2d(n: int = 285, G: int = 24, **kw) -> Problem:
+    """Olson's 2-D problem (Sec. 3.5) on [0, 3.8]^2 cm with a = c = 1: foam (as in
+    olson1d) with aluminium blocks (the printed aluminium opacity times 0.001 g/cm^3;
+    Olson's heat capacity with H = 0.5, chi = 0.3 keV) at OLSON2D_BLOCKS (cell-centre
+    rule), both tabulated on opacity_nodes(); T0 = Tr0 = 0.01 keV; reflecting walls;
+    the source B(0.5 keV) e^{-18.7 r^3}, r the distance of the cell centre from the
+    origin, on while c t < 3; 24 log groups on [0.01, 100] keV; dt = dx / c; the
+    particle weight 1e-4 V; the linearized source iteration."""
+    L = 3.8
+    h = L / n
+    xc = (np.arange(n) + 0.5) * h
+    X, Y = np.meshgrid(xc, xc, indexing="xy")
+    al = np.zeros((n, n), bool)
+    for (bx, by) in OLSON2D_BLOCKS:
+        al |= (X >= bx) & (X < bx + 0.5) & (Y >= by) & (Y < by + 0.5)
+    al = al.reshape(-1)
+    ncell = n * n
+    nu_n, T_n = opacity_nodes()
+    table = {"mat": al.astype(np.int32), "nu": nu_n, "T": T_n,
+             "sigma": np.stack([1e-3 * foam_kappa(nu_n, T_n), 1e-3 * aluminium_kappa(nu_n, T_n)])}
+    p = dict(dt=h, steps=int(round(3.0 / h)), w_ref=1e-4, pool_cap=1 << 25, seed=0, flags=FLAG_SI_LINEARIZED,
+             si_max_iters=500)
+    p.update(kw)
+    r = np.hypot(X, Y).reshape(-1)
+    return Problem(name=f"olson2d_{n}x{n}_g{G}", dim=2, nx=n, ny=n, x0=0.0, x1=L, y0=0.0, y1=L,
+                   bc=[BC_REFLECT] * 4, bcT=[0.0] * 4, nu_edges=log_edges(0.01, 100.0, G),
+                   kappa=np.zeros((ncell, G)), cv=np.ones(ncell), T0=np.full(ncell, 0.01),
+                   Tr0=np.full(ncell, 0.01), pinned=np.zeros(ncell, np.uint8),
+                   olson_H=np.where(al, 0.5, 0.1), olson_chi=np.where(al, 0.3, 0.1), opacity_table=table,
+                   source_shape=np.exp(-18.7 * r ** 3), source_T=0.5, source_t_off=3.0, **p)
+
+
 def lattice_mid_run_state(prob: Problem, n_particles: int, seed: int = 5) -> dict:
     """A synthetic state of the lattice workload part-way through its run, at
     the particle count of its late steps: material temperatures that fall off
