@@ -43,10 +43,12 @@ def test_rate_source_switching_off(flags):
     assert ctx.get_diag()["injection"] == 0.0 and sim.diag()["injection"] == 0.0   # switched off by step 5
 
 
-@pytest.mark.parametrize("flags", [LIN, 0, LIN | SL | WI, LIN | GS])
+@pytest.mark.parametrize("flags", [LIN, 0, LIN | SL, LIN | GS])
 def test_olson_1d(flags):
     """The Olson foam problem: tabulated opacity (per-particle flights through the
-    cell rows, or group opacities), Olson's heat capacity, Planckian source."""
+    cell rows, or group opacities), Olson's heat capacity, Planckian source.  (The
+    wave flux from the iterate, UGKWP_FLAG_WAVE_ITER, does not converge here at
+    dt = dx / c, on either side.)"""
     p = W.olson1d(flags=flags)
     run_pair(p.with_(name=f"olson1d_f{flags}"), 12, every=4)
 
@@ -84,7 +86,7 @@ def test_olson_2d_full_mesh_first_steps():
 def test_batch_of_olson_instances():
     probs = []
     for k, (nx, H) in enumerate([(40, 0.1), (96, 0.3), (17, 0.05)]):
-        p = W.olson1d(nx=nx, G=6, seed=900 + k, pool_cap=1 << 18)
+        p = W.olson1d(nx=nx, G=6, seed=900 + k, pool_cap=1 << 18, dt=0.04)
         probs.append(p.with_(olson_H=np.full(nx, H), name=f"olson_b{k}"))
     say("[olson] batch of", len(probs))
     ctx = ugkwp.from_batch(probs)
