@@ -298,6 +298,33 @@ def summarize_counters(csv_path, steps, kernel="k_push"):
     return "\n".join(lines)
 
 
+def batched_vs_per_instance(probs, stream, spin, nsteps=20, sort_interval=0):
+    """The batch's instances as one batched context and as one context each,
+    both fresh from t = 0 and stepped to `spin`, then `nsteps` steps timed on
+    each (same work: the same seeds give the same particles)."""
+    import torch
+    from paper_2312_16981_amd import ugkwp
+    out = {}
+    for mode in ("batched", "per_instance"):
+        if mode == "batched":
+            ctxs = [ugkwp.from_batch(probs, stream=stream.cuda_stream, pool_capacity=1 << 26,
+                                     sort_interval=sort_interval)]
+        else:
+            ctxs = [ugkwp.from_problem(p, stream=stream.cuda_stream, sort_interval=sort_interval) for p in probs]
+        for c in ctxs:
+            c.step(spin)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in ctxs:
+            c.step(nsteps)
+        torch.cuda.synchronize()
+        out[mode] = (time.perf_counter() - t0) * 1e3 / nsteps
+        del ctxs
+    return {"steps": f"{spin}-{spin + nsteps - 1} of fresh runs from t=0",
+            "batched_ms_per_step": out["batched"], "per_instance_ms_per_step": out["per_instance"],
+            "speedup": out["per_instance"] / out["batched"]}
+
+
 def copy_probe(mib=1024, reps=5):
     """A plain elementwise copy (dst = -src, float64) of `mib` MiB read and
     `mib` MiB written, repeated: the known-size reference for HBM byte counters."""
@@ -536,6 +563,9 @@ def main():
                            "kernel": "k_si_sweep (the source-iteration phase: sweeps and decides)",
                            "algorithmic_bytes_per_update": SI_SWEEP_BYTES,
                            "from": f"{nph} further steps with every phase timed"}
+    if wl == "batch" and not args.per_instance:
+        del ctxs
+        out["batched_vs_per_instance"] = batched_vs_per_instance(probs, stream, spin, 20, args.sort_interval)
     if not args.no_cpu_baseline:
         if wl == "lattice":
             out["cpu_baseline"] = cpu_baseline_window(probs[0], pushes / max(args.steps, 1), args.cpu_budget)

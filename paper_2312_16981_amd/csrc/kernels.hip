@@ -45,6 +45,23 @@ struct Geo {
     int reflect;           // bit q: side q (XLO, XHI, YLO, YHI) is reflective
 };
 
+// Column and row of local cell lcell of an nx-wide instance: the quotient from the
+// double reciprocal of nx (off by at most one for lcell < 2^29), corrected.
+__device__ inline void cell_col_row(int lcell, int nx, double inv_nx, int& ix, int& iy)
+{
+    int q = (int)((double)lcell * inv_nx);
+    int r = lcell - q * nx;
+    if (r < 0) {
+        q -= 1;
+        r += nx;
+    } else if (r >= nx) {
+        q += 1;
+        r -= nx;
+    }
+    ix = r;
+    iy = q;
+}
+
 __device__ inline Geo geo_of(const Inst& I)
 {
     Geo o;
@@ -418,8 +435,13 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroLi
             // where the slot samples (tau_num in joint cells), else C5
             if (K.flags & UGKWP_FLAG_SLOPES) D.bcoef[j] = N >= 1 ? coef_w5(sv) + 0.5 * diff : coef_c5(sv);
             // boundary-source particles of the ghosts beyond this cell's Planckian sides
-            if (K.flags & UGKWP_FLAG_BOUNDARY_PARTICLES)
-                for (int q = 0; q < 2 * I.dim; ++q) N += ghost_births(D, K, I, s, q, es);
+            // (sides unrolled: a side indexed at run time would put the instance
+            // record in scratch memory)
+            if (K.flags & UGKWP_FLAG_BOUNDARY_PARTICLES) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q < 2 * I.dim) N += ghost_births(D, K, I, s, q, es);
+            }
             D.nb[j] = N;
         }
     }
@@ -1112,7 +1134,11 @@ __global__ __launch_bounds__(BS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     unsigned long long nsurv = 0;
     Geo geo0{};
-    if (SINGLE) geo0 = geo_of(D.inst[0]);
+    double inv_nx0 = 0.0;
+    if (SINGLE) {
+        geo0 = geo_of(D.inst[0]);
+        inv_nx0 = 1.0 / (double)geo0.nx;
+    }
     for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < n_total; c0 += (int64_t)gridDim.x * chunk) {
         for (int h = threadIdx.x; h < HT_SIZE; h += BS) {
             T.key[h] = HT_EMPTY;
@@ -1180,8 +1206,15 @@ __global__ __launch_bounds__(BS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool
                 const double nu = cur.nu, w = cur.w;
                 const uint64_t id = cur.id;
                 const int lcell = cell - I.cell_off;
-                f.ix = DIM == 1 ? lcell : lcell % I.nx;
-                f.iy = DIM == 1 ? 0 : lcell / I.nx;
+                if (DIM == 1) {
+                    f.ix = lcell;
+                    f.iy = 0;
+                } else if (SINGLE) {
+                    cell_col_row(lcell, I.nx, inv_nx0, f.ix, f.iy);
+                } else {
+                    f.ix = lcell % I.nx;
+                    f.iy = lcell / I.nx;
+                }
                 f.t = 0.0;
                 f.d = 0;
                 f.flips = 0;
