@@ -39,7 +39,8 @@ HBM_PEAK_GBS = 8000.0
 PUSH_BYTES_READ = 48       # x, mu, nu, w, id (8 B each) + cell word, group (4 B each)
 PUSH_BYTES_WRITE = 12      # new position and cell word of a survivor (updated in place)
 PUSH_BYTES_DEAD = 4        # empty-slot mark of a particle absorbed or gone
-SPINUP = {"slab": 500, "lattice": 300, "batch": 100, "adjoint": 0, "thickthin": 200, "marshak": 100, "larsen": 100}
+SPINUP = {"slab": 500, "lattice": 300, "batch": 100, "adjoint": 0, "thickthin": 200, "marshak": 100, "larsen": 100,
+          "olson1d": 0, "olson2d": 0}
 ADJ_SWEEP_BYTES = 48       # rbar, lambda, sigma, phi' and two face coefficients per (cell, group) update
 SI_SWEEP_BYTES = 64        # Q, lambda, sigma, phi^k, rho^k, one face D read; rho^{k+1}, phi^{k+1} written
 
@@ -50,10 +51,9 @@ SI_SWEEP_BYTES = 64        # Q, lambda, sigma, phi^k, rho^k, one face D read; rh
 # to those sources makes bench.py report the traffic as unknown.
 PUSH_SOURCES = ("kernels.hip", "device_math.hpp", "device_common.hpp", "common.hpp")
 PUSH_TRAFFIC = {
-    "slab": {"sources": "a77b237b0f30d25c", "read_per_push": 49.46, "write_per_push": 12.98},
-    "lattice": {"sources": "a77b237b0f30d25c", "read_per_push": 67.25, "write_per_push": 22.05},
+    "slab": {"sources": "c4a69605aaa7f2e7", "read_per_push": 49.13, "write_per_push": 12.88},
+    "lattice": {"sources": "c4a69605aaa7f2e7", "read_per_push": 66.53, "write_per_push": 21.53},
 }
-
 
 def push_sources_digest():
     import hashlib
@@ -359,6 +359,11 @@ def workload_name(wl, probs, spin, args):
         return (f"thick-to-thin slab {p.nx} cells x {p.G} groups on [0,1.5], kappa 1000|10 jump at x=0.5, "
                 f"dt=dx/c, numerical collision time of the joint cells C=1e5, steps {first}-{last} of the run "
                 f"from t=0")
+    if wl in ("olson1d", "olson2d"):
+        p = probs[0]
+        return (f"Olson {p.dim}-D foam problem {p.nx}x{p.ny} cells x {p.G} groups (tabulated foam"
+                f"{' and aluminium' if p.dim == 2 else ''} opacity, Olson heat capacity, Planckian source), "
+                f"dt=dx/c, linearized source iteration, steps {first}-{last} of the run from t=0")
     if wl == "lattice":
         p = probs[0]
         return (f"2-D lattice {p.nx}x{p.ny} cells x {p.G} groups, dt=1e-3, kappa 100|1 squares, "
@@ -384,7 +389,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--workload", choices=("lattice", "slab", "batch", "adjoint", "thickthin", "marshak", "larsen"),
+    ap.add_argument("--workload", choices=("lattice", "slab", "batch", "adjoint", "thickthin", "marshak", "larsen",
+                                           "olson1d", "olson2d"),
                     default="lattice")
     ap.add_argument("--per-instance", action="store_true",
                     help="batch workload: one context per instance instead of one batched context")
@@ -422,7 +428,8 @@ def main():
     stream = torch.cuda.current_stream()
     wl = args.workload
     if args.steps < 0:
-        args.steps = {"adjoint": 100, "lattice": 20}.get(wl, 400)
+        # the Olson problems: their whole runs (c t = 4 in 1-D, 3 in 2-D) after the warm-up
+        args.steps = {"adjoint": 100, "lattice": 20, "olson1d": 102, "olson2d": 220}.get(wl, 400)
     if wl == "adjoint":
         run_adjoint(args, stream)
         return
@@ -436,6 +443,10 @@ def main():
         probs = [W.marshak()]
     elif wl == "larsen":
         probs = [W.larsen()]
+    elif wl == "olson1d":
+        probs = [W.olson1d()]
+    elif wl == "olson2d":
+        probs = [W.olson2d()]
     else:
         probs = W.c4_batch()
     if args.si_linearized:
@@ -462,7 +473,8 @@ def main():
     for c in ctxs:
         c.step(spin)
     tuned = None
-    if not args.no_autotune:
+    # (the Olson runs start without particles: nothing to tune on)
+    if not args.no_autotune and not wl.startswith("olson"):
         tuned = [c.autotune() for c in ctxs]
     # time the push of every timed step where a push lasts a millisecond (2-D);
     # in 1-D one step in 4 (each event pair adds a few microseconds to a step)
