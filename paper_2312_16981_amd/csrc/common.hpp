@@ -200,6 +200,9 @@ struct Dev {
     double* tab_lT;
     double* tab_lsig;
     double* tab_row;
+    int32_t* tab_gi;            // [edge][3] nu interval of each group's Simpson points
+    double* tab_ga;             // [edge][3] and the weight of its upper node
+    double* tab_sig;            // [2][slot] group sigma at the iterate written by sweep k for sweep k+1
     // per instance
     InstState* ist;
     Resid* res;                 // [RES_SLOTS][n_inst][RES_SUB]

@@ -100,26 +100,28 @@ __device__ inline double group_factor(const Dev& D, const Consts& K, int edge_of
             + nu_pow(nh, K.nu_power) * stim_factor(K, nh, T)) / 6.0;
 }
 
-// sigma of material m at (nu, T) from the table: bilinear in (ln nu, ln T) on
-// ln sigma, constant beyond the end nodes (Sec. 3.4-3.5's printed opacities,
-// tabulated by the caller).
-__device__ inline double table_sigma(const Dev& D, const Consts& K, int m, double nu, double T)
+// Group opacity of material m at T from the table (Sec. 3.4-3.5's printed
+// opacities, tabulated by the caller): sigma is bilinear in (ln nu, ln T) on
+// ln sigma, constant beyond the end nodes, and the group value is Simpson's rule
+// over the group (edge index e = edge_off + g).  The nu intervals and weights of the group's
+// three Simpson points are fixed by the edges and read from tab_gi / tab_ga
+// (k_tab_groups at set-up); only T is located here.
+__device__ inline double table_group_sigma(const Dev& D, const Consts& K, int m, int e, double T)
 {
-    double a, b;
-    const int i = table_locate(D.tab_lnu, K.tab_nnu, log(nu), &a);
+    double b;
     const int jt = table_locate(D.tab_lT, K.tab_nT, log(T), &b);
     const int n = K.tab_nnu;
-    const double* L = D.tab_lsig + ((int64_t)m * K.tab_nT + jt) * n + i;
-    const double l00 = L[0], l10 = L[1], l01 = L[n], l11 = L[n + 1];
-    const double lo = (1.0 - a) * l00 + a * l10, hi = (1.0 - a) * l01 + a * l11;
-    return exp((1.0 - b) * lo + b * hi);
-}
-
-// Group opacity of material m at T from the table: Simpson's rule over the group.
-__device__ inline double table_group_sigma(const Dev& D, const Consts& K, int m, int edge_off, int g, double T)
-{
-    const double nl = D.nu[edge_off + g], nh = D.nu[edge_off + g + 1], nm = 0.5 * (nl + nh);
-    return (table_sigma(D, K, m, nl, T) + 4.0 * table_sigma(D, K, m, nm, T) + table_sigma(D, K, m, nh, T)) / 6.0;
+    const double* L0 = D.tab_lsig + ((int64_t)m * K.tab_nT + jt) * n;
+    double v[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const int i = D.tab_gi[3 * e + p];
+        const double a = D.tab_ga[3 * e + p];
+        const double* L = L0 + i;
+        const double lo = (1.0 - a) * L[0] + a * L[1], hi = (1.0 - a) * L[n] + a * L[n + 1];
+        v[p] = exp((1.0 - b) * lo + b * hi);
+    }
+    return (v[0] + 4.0 * v[1] + v[2]) / 6.0;
 }
 
 // The volumetric source acts in the steps that start before its switch-off time.
@@ -175,7 +177,7 @@ __global__ void k_tables(Dev D, Consts K)
     const Inst& I = D.inst[s.inst];
     const double Tc = D.T[I.cell_off + s.lcell];
     const double kap = K.t_power != 0.0 ? D.kappa[j] * pow(Tc, -K.t_power) : D.kappa[j];
-    const double sg = K.table ? table_group_sigma(D, K, D.tab_mat[I.cell_off + s.lcell], I.edge_off, s.g, Tc)
+    const double sg = K.table ? table_group_sigma(D, K, D.tab_mat[I.cell_off + s.lcell], I.edge_off + s.g, Tc)
                               : kap * group_factor(D, K, I.edge_off, s.g, Tc);
     // flights: tau = (eps^2/c) f(nu)^-1 / kappa; with the stimulated-emission
     // factor or a table and group opacities the group opacity's T dependence goes
@@ -205,6 +207,24 @@ __global__ void k_tab_rows(Dev D, Consts K)
     const int jt = table_locate(D.tab_lT, K.tab_nT, log(D.T[cell]), &b);
     const double* L = D.tab_lsig + ((int64_t)D.tab_mat[cell] * K.tab_nT + jt) * K.tab_nnu + i;
     D.tab_row[j] = (1.0 - b) * L[0] + b * L[K.tab_nnu];
+}
+
+// The nu intervals and upper-node weights of the three Simpson points (lower
+// edge, midpoint, upper edge) of the group starting at every edge e < n_edges - 1,
+// once at set-up (after the logs of the nodes).
+__global__ void k_tab_groups(Dev D, Consts K, int64_t n_edges)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e + 1 >= n_edges) return;
+    const double nl = D.nu[e], nh = D.nu[e + 1], nm = 0.5 * (nl + nh);
+    const double pts[3] = {nl, nm, nh};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        double a;
+        const int i = table_locate(D.tab_lnu, K.tab_nnu, log(pts[p]), &a);
+        D.tab_gi[3 * e + p] = i;
+        D.tab_ga[3 * e + p] = a;
+    }
 }
 
 // ln of the table's nodes and values, once at set-up (n entries of each array).
@@ -1699,27 +1719,33 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     }
     // temperature-dependent opacity: kappa of the slot and of the neighbours
     // across each face, and the neighbours' iterate T^k
-    // (a tabulated opacity: the materials of the slot's cell and of the neighbours)
+    // (a tabulated opacity: the group sigma of the slot and of the neighbours at the
+    // iterate, written by the sweep before; sweep 0 takes the step's tables at T^n)
     double kap_j = 0.0, Sg = 0.0, Sn[4] = {0.0, 0.0, 0.0, 0.0};
     double kap_n[4] = {0.0, 0.0, 0.0, 0.0}, T_nb[4] = {1.0, 1.0, 1.0, 1.0};
-    int mat_j = 0, mat_n[4] = {0, 0, 0, 0};
+    double tsig_j = 0.0, tsig_n[4] = {0.0, 0.0, 0.0, 0.0};
+    int mat_j = 0;
     if (TDEP && act) {
-        if (K.table) mat_j = D.tab_mat[cell];
-        else {
+        const double* tsig = FIRST ? D.sig : D.tab_sig + (int64_t)(k & 1) * K.n_cg;
+        if (K.table) {
+            mat_j = D.tab_mat[cell];
+            tsig_j = tsig[j];
+        } else {
             kap_j = D.kappa[j];
             Sg = group_factor(D, K, I.edge_off, g, FIRST ? D.T[cell] : D.T_new[cell]);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q >= nf || !F.inside[q]) continue;
+            if (K.table) {
+                tsig_n[q] = tsig[F.nbj[q]];
+                continue;
+            }
             const bool lo = (q & 1) == 0;
             const int nbc = cell + (q < 2 ? (lo ? -1 : 1) : (lo ? -nx : nx));
             T_nb[q] = FIRST ? D.T[nbc] : D.T_new[nbc];
-            if (K.table) mat_n[q] = D.tab_mat[nbc];
-            else {
-                kap_n[q] = D.kappa[F.nbj[q]];
-                Sn[q] = K.stim ? group_factor(D, K, I.edge_off, g, T_nb[q]) : Sg;
-            }
+            kap_n[q] = D.kappa[F.nbj[q]];
+            Sn[q] = K.stim ? group_factor(D, K, I.edge_off, g, T_nb[q]) : Sg;
         }
     }
     double Tn = 1.0, Tk = 1.0, dtcv = 0.0, olH = 0.0, olchi = 0.0;
@@ -1757,8 +1783,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         if (TDEP) {
             // the coefficient step of Algorithm 2: sigma, lambda and the face
             // coefficients of this sweep from the iterate T^k
-            const double sk = K.table ? table_group_sigma(D, K, mat_j, I.edge_off, g, Tk)
-                                      : kap_j * pow(Tk, -K.t_power) * Sg;
+            const double sk = K.table ? tsig_j : kap_j * pow(Tk, -K.t_power) * Sg;
             sig = sk;
             lam = K.c * sk * K.dt / (K.eps * K.eps);
 #pragma unroll
@@ -1766,8 +1791,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
                 if (q >= nf) continue;
                 double sf = sk;
                 if (F.inside[q]) {
-                    const double sn = K.table ? table_group_sigma(D, K, mat_n[q], I.edge_off, g, T_nb[q])
-                                              : kap_n[q] * pow(T_nb[q], -K.t_power) * Sn[q];
+                    const double sn = K.table ? tsig_n[q] : kap_n[q] * pow(T_nb[q], -K.t_power) * Sn[q];
                     sf = (sk + sn > 0.0) ? 2.0 * (sk * sn) / (sk + sn) : 0.0;
                 }
                 Df[q] = face_coef(K, sf, q < 2 ? I.dx : I.dy);
@@ -1860,6 +1884,9 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
         if (FIRST) D.Q[j] = Qj;
         rho_out[j] = r;
         phi_out[j] = phi_new;
+        // a tabulated opacity: the next sweep's group sigma, at this sweep's T^{k+1}
+        if (TDEP && K.table)
+            D.tab_sig[(int64_t)((k + 1) & 1) * K.n_cg + j] = table_group_sigma(D, K, mat_j, I.edge_off + g, Tnew);
         // the boundary wave inflow: summed here, or with the wave flux of every
         // sweep from its iterate kept per slot for the commit (that of the last sweep)
         if (FIRST && (K.flags & UGKWP_FLAG_WAVE_ITER)) D.winflow[j] = inflow;
@@ -2084,7 +2111,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int la
         // temperature-dependent opacity: the boundary faces' coefficients at the
         // step's final temperature (the iteration has converged on it)
         const double Tf = D.T_new[cell];
-        const double sk = K.table ? table_group_sigma(D, K, D.tab_mat[cell], I.edge_off, g, Tf)
+        const double sk = K.table ? table_group_sigma(D, K, D.tab_mat[cell], I.edge_off + g, Tf)
                                   : D.kappa[j] * pow(Tf, -K.t_power) * group_factor(D, K, I.edge_off, g, Tf);
 #pragma unroll
         for (int q = 0; q < 2 * DIM; ++q)
@@ -2224,6 +2251,11 @@ void launch_tables(const Dev& D, const Consts& K, hipStream_t st)
 void launch_tab_logs(double* v, int64_t n, hipStream_t st)
 {
     if (n > 0) k_tab_logs<<<blocks(n, 256), 256, 0, st>>>(v, n);
+}
+
+void launch_tab_groups(const Dev& D, const Consts& K, int64_t n_edges, hipStream_t st)
+{
+    if (n_edges > 1) k_tab_groups<<<blocks(n_edges, 256), 256, 0, st>>>(D, K, n_edges);
 }
 
 void launch_face_D(const Dev& D, const Consts& K, int inst, int axis, int64_t nslots, hipStream_t st)

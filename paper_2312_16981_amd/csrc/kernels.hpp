@@ -17,6 +17,8 @@ hipError_t set_head_series(const HeadSeries& hs);
 void launch_tables(const Dev& D, const Consts& K, hipStream_t st);
 // ln of n doubles in place (the opacity table's nodes and values at set-up).
 void launch_tab_logs(double* v, int64_t n, hipStream_t st);
+// the nu positions of every group's Simpson points in the table (after the logs)
+void launch_tab_groups(const Dev& D, const Consts& K, int64_t n_edges, hipStream_t st);
 void launch_face_D(const Dev& D, const Consts& K, int inst, int axis, int64_t nslots, hipStream_t st);
 void launch_ghost_phi(const Dev& D, const Consts& K, double* phib, hipStream_t st);
 void launch_init_rho(const Dev& D, const Consts& K, const double* Tr0, hipStream_t st);

@@ -189,6 +189,7 @@ struct ugkwp_ctx {
     double* qsrc_buf = nullptr;
     int* src_on_buf = nullptr;
     int32_t* tab_mat_buf = nullptr;
+    double* tab_sig_buf = nullptr;
 
     // step records: counters | birth totals | per-instance state | per-instance
     // energy sums [| their sub-slots], N_RECORDS of them on the device (every
@@ -286,6 +287,7 @@ struct ugkwp_ctx {
         olH_buf = olchi_buf = uend_buf = qsrc_buf = nullptr;
         src_on_buf = nullptr;
         tab_mat_buf = nullptr;
+        tab_sig_buf = nullptr;
         K.olson = K.table = K.has_src = 0;
     }
 
@@ -737,6 +739,9 @@ struct ugkwp_ctx {
         double* dT = dalloc<double>(owned, (size_t)nT);
         double* dsig = dalloc<double>(owned, nt);
         double* drow = dalloc<double>(owned, (size_t)ncell * nnu);
+        int32_t* dgi = dalloc<int32_t>(owned, (size_t)n_edges * 3);
+        double* dga = dalloc<double>(owned, (size_t)n_edges * 3);
+        double* dtsig = model_array(tab_sig_buf, (size_t)K.n_cg * 2);
         HIPCHK(hipMemcpyAsync(dmat, mat, sizeof(int32_t) * ncell, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(dnu, nu, sizeof(double) * nnu, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(dT, T, sizeof(double) * nT, hipMemcpyHostToDevice, st));
@@ -749,9 +754,14 @@ struct ugkwp_ctx {
         D.tab_lT = dT;
         D.tab_lsig = dsig;
         D.tab_row = drow;
+        D.tab_gi = dgi;
+        D.tab_ga = dga;
+        D.tab_sig = dtsig;
         K.table = 1;
         K.tab_nnu = nnu;
         K.tab_nT = nT;
+        launch_tab_groups(D, K, n_edges, st);
+        HIPCHK(hipMemsetAsync(dtsig, 0, sizeof(double) * 2 * (size_t)K.n_cg, st));
         // the push now runs the table's flights: its default launch shape follows
         push_shape = push_default_shape(dim, K);
         push_shape.blocks = std::min(push_shape.blocks, MAX_PUSH_BLOCKS);
