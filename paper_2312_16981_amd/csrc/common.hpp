@@ -53,6 +53,8 @@ struct Consts {
     int olson;             // 1: per-cell Olson heat capacity (D.olH, D.olchi) in some cells
     int table;             // 1: tabulated sigma(nu, T) per material replaces kappa nu^-p T^-q
     int tab_nnu, tab_nT;   // table nodes in nu and T
+    double tab_lT_inv;     // 1 / spacing of ln T when the T nodes are evenly spaced in ln T (else 0):
+                           // a first guess of the interval, bisection's result kept
     int has_src;           // 1: a volumetric source D.qsrc
     double q_toff;         // the source acts in steps that start before this time
     double si_tol;

@@ -196,15 +196,48 @@ __host__ __device__ inline double coef_c4(double s)
     return s == 0.0 ? 1.0 : -expm1(-s) / s;
 }
 
-// C4 - e^{-s}; alternating series below s = 1 to avoid cancellation.
+// The power-series coefficients of the functions below, fixed at compile time
+// (each a ratio of integers rounded once), so that a term costs a multiply
+// and no division.  Index n is the series' own summation index.
+struct SeriesCoefs {
+    double w[61];     // n / (n+1)!                       C4 - e^{-s}
+    double c2[81];    // (n-1) / (n+1)!                   C2/dt
+    double c5[81];    // 1 / (n! (n+2))                   C5/dt
+    double w5[81];    // n / (2 n! (n+2))                 (C5 + dt/2 e^{-s})/dt
+    double wos[61];   // n / (n+1)!                       (C4 - e^{-s})/s
+    double c2ds[81];  // (n-1)^2 / (n+1)!                 d(C2/dt)/ds
+};
+
+constexpr SeriesCoefs make_series_coefs()
+{
+    SeriesCoefs t{};
+    double fact = 1.0;                       // n!
+    for (int n = 0; n < 81; ++n) {
+        if (n > 0) fact *= (double)n;
+        const double fact1 = fact * (double)(n + 1);     // (n+1)!
+        if (n < 61) {
+            t.w[n] = (double)n / fact1;
+            t.wos[n] = (double)n / fact1;
+        }
+        t.c2[n] = (double)(n - 1) / fact1;
+        t.c5[n] = 1.0 / (fact * (double)(n + 2));
+        t.w5[n] = (double)n / (2.0 * fact * (double)(n + 2));
+        t.c2ds[n] = (double)((n - 1) * (n - 1)) / fact1;
+    }
+    return t;
+}
+
+constexpr SeriesCoefs kSeries = make_series_coefs();
+
+// C4 - e^{-s}; alternating series sum_{n>=1} (-1)^{n+1} n s^n/(n+1)! below s = 1 to
+// avoid cancellation.
 __host__ __device__ inline double coef_w(double s)
 {
     if (s < 1.0) {
-        double term_pow = 1.0, inv_fact = 1.0, sum = 0.0;
+        double p = 1.0, sum = 0.0;
         for (int n = 1; n < 60; ++n) {
-            term_pow *= s;
-            inv_fact /= (double)(n + 1);
-            const double t = (double)n * term_pow * inv_fact;
+            p *= s;
+            const double t = kSeries.w[n] * p;
             sum += (n & 1) ? t : -t;
             if (t < 1e-18 * fabs(sum)) break;
         }
@@ -217,11 +250,10 @@ __host__ __device__ inline double coef_w(double s)
 __host__ __device__ inline double coef_c2_over_dt(double s)
 {
     if (s < 2.0) {
-        double p = 1.0, inv_fact = 0.5, sum = 0.0;       // p = s^{n-1}, inv_fact = 1/(n+1)!
+        double p = 1.0, sum = 0.0;                       // p = s^{n-1}
         for (int n = 2; n < 80; ++n) {
             p *= s;
-            inv_fact /= (double)(n + 1);
-            const double t = (double)(n - 1) * p * inv_fact;
+            const double t = kSeries.c2[n] * p;
             sum += (n & 1) ? t : -t;
             if (t < 1e-18 * fabs(sum)) break;
         }
@@ -236,11 +268,10 @@ __host__ __device__ inline double coef_c2_over_dt(double s)
 __host__ __device__ inline double coef_c5(double s)
 {
     if (s < 2.0) {
-        double p = 1.0, inv_fact = 1.0, sum = -0.5;      // n = 0 term
+        double p = 1.0, sum = -0.5;                      // n = 0 term
         for (int n = 1; n < 80; ++n) {
             p *= s;
-            inv_fact /= (double)n;
-            const double t = p * inv_fact / (double)(n + 2);
+            const double t = kSeries.c5[n] * p;
             sum += (n & 1) ? t : -t;
             if (t < 1e-18 * fabs(sum)) break;
         }
@@ -255,11 +286,10 @@ __host__ __device__ inline double coef_c5(double s)
 __host__ __device__ inline double coef_w5(double s)
 {
     if (s < 2.0) {
-        double p = 1.0, inv_fact = 1.0, sum = 0.0;
+        double p = 1.0, sum = 0.0;
         for (int n = 1; n < 80; ++n) {
             p *= s;
-            inv_fact /= (double)n;
-            const double t = 0.5 * (double)n * p * inv_fact / (double)(n + 2);
+            const double t = kSeries.w5[n] * p;
             sum += (n & 1) ? -t : t;
             if (t < 1e-18 * fabs(sum)) break;
         }
@@ -276,11 +306,10 @@ __host__ __device__ inline double coef_w5(double s)
 __host__ __device__ inline double coef_w_over_s(double s)
 {
     if (s < 1.0) {
-        double p = 1.0, inv_fact = 0.5, sum = 0.5;      // n = 1 term: 1/2
+        double p = 1.0, sum = 0.5;                      // n = 1 term: 1/2
         for (int n = 2; n < 60; ++n) {
             p *= s;                                     // s^{n-1}
-            inv_fact /= (double)(n + 1);                // 1/(n+1)!
-            const double t = (double)n * p * inv_fact;
+            const double t = kSeries.wos[n] * p;
             sum += (n & 1) ? t : -t;
             if (t < 1e-18 * fabs(sum)) break;
         }
@@ -296,11 +325,10 @@ __host__ __device__ inline double coef_w_ds(double s) { return exp(-s) - coef_w_
 __host__ __device__ inline double coef_c2_over_dt_ds(double s)
 {
     if (s < 2.0) {
-        double p = 1.0, inv_fact = 1.0 / 6.0, sum = -1.0 / 6.0;   // n = 2 term
+        double p = 1.0, sum = -1.0 / 6.0;               // n = 2 term
         for (int n = 3; n < 80; ++n) {
             p *= s;                                     // s^{n-2}
-            inv_fact /= (double)(n + 1);
-            const double t = (double)((n - 1) * (n - 1)) * p * inv_fact;
+            const double t = kSeries.c2ds[n] * p;
             sum += (n & 1) ? t : -t;
             if (t < 1e-18 * fabs(sum)) break;
         }
@@ -423,6 +451,24 @@ __host__ __device__ inline int table_locate(const double* nodes, int n, double x
     }
     *frac = (x - nodes[lo]) / (nodes[lo + 1] - nodes[lo]);
     return lo;
+}
+
+// The same interval found from a first guess: for nodes evenly spaced from
+// nodes[0] with 1/spacing inv (inv = 0: no guess, plain bisection) the guess is
+// the interval of x on that grid, then moved until nodes[i] <= x < nodes[i+1]
+// holds as bisection would leave it.  Same result as table_locate.
+__host__ __device__ inline int table_locate_guess(const double* nodes, int n, double x, double inv,
+                                                  double* frac)
+{
+    if (!(inv > 0.0)) return table_locate(nodes, n, x, frac);
+    if (x <= nodes[0]) { *frac = 0.0; return 0; }
+    if (x >= nodes[n - 1]) { *frac = 1.0; return n - 2; }
+    double gq = (x - nodes[0]) * inv;
+    int i = gq < 0.0 ? 0 : (gq > (double)(n - 2) ? n - 2 : (int)gq);
+    while (i > 0 && nodes[i] > x) --i;
+    while (i < n - 2 && nodes[i + 1] <= x) ++i;
+    *frac = (x - nodes[i]) / (nodes[i + 1] - nodes[i]);
+    return i;
 }
 
 // nu^-p with the exact cube for the paper's p = 3.

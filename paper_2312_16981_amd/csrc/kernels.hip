@@ -109,7 +109,7 @@ __device__ inline double group_factor(const Dev& D, const Consts& K, int edge_of
 __device__ inline double table_group_sigma(const Dev& D, const Consts& K, int m, int e, double T)
 {
     double b;
-    const int jt = table_locate(D.tab_lT, K.tab_nT, log(T), &b);
+    const int jt = table_locate_guess(D.tab_lT, K.tab_nT, log(T), K.tab_lT_inv, &b);
     const int n = K.tab_nnu;
     const double* L0 = D.tab_lsig + ((int64_t)m * K.tab_nT + jt) * n;
     double v[3];
@@ -204,7 +204,7 @@ __global__ void k_tab_rows(Dev D, Consts K)
     if (j >= (int64_t)K.ncell * K.tab_nnu) return;
     const int cell = (int)(j / K.tab_nnu), i = (int)(j % K.tab_nnu);
     double b;
-    const int jt = table_locate(D.tab_lT, K.tab_nT, log(D.T[cell]), &b);
+    const int jt = table_locate_guess(D.tab_lT, K.tab_nT, log(D.T[cell]), K.tab_lT_inv, &b);
     const double* L = D.tab_lsig + ((int64_t)D.tab_mat[cell] * K.tab_nT + jt) * K.tab_nnu + i;
     D.tab_row[j] = (1.0 - b) * L[0] + b * L[K.tab_nnu];
 }

@@ -760,6 +760,14 @@ struct ugkwp_ctx {
         K.table = 1;
         K.tab_nnu = nnu;
         K.tab_nT = nT;
+        {
+            // evenly spaced in ln T: the locate may start from the grid's guess
+            const double d0 = (std::log(T[nT - 1]) - std::log(T[0])) / (nT - 1);
+            bool even = d0 > 0;
+            for (int k = 0; k + 1 < nT && even; ++k)
+                even = std::fabs((std::log(T[k + 1]) - std::log(T[k])) - d0) <= 1e-9 * d0;
+            K.tab_lT_inv = even ? 1.0 / d0 : 0.0;
+        }
         launch_tab_groups(D, K, n_edges, st);
         HIPCHK(hipMemsetAsync(dtsig, 0, sizeof(double) * 2 * (size_t)K.n_cg, st));
         // the push now runs the table's flights: its default launch shape follows
