@@ -1335,16 +1335,34 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(Dev D, Consts K, 
         __syncthreads();
         int slot[SORT_PPT];          // table entry (>= 0), -1 empty slot, -2 ranked globally
         int64_t pos[SORT_PPT];       // local rank, or the global position when ranked globally
+        // the records, read while the ranks are found (their stores come after the
+        // block's ranks, and loads issued after a store could not pass it)
+        double rx[SORT_PPT], ry[SORT_PPT], rox[SORT_PPT], roy[SORT_PPT], rnu[SORT_PPT], rw[SORT_PPT];
+        uint64_t rid[SORT_PPT];
+        int32_t rword[SORT_PPT], rg[SORT_PPT];
 #pragma unroll
         for (int r = 0; r < SORT_PPT; ++r) {
             const int64_t i = c0 + (int64_t)r * SORT_THREADS + threadIdx.x;
             slot[r] = -1;
             pos[r] = 0;
+            rword[r] = -1;
+            rg[r] = 0;
             if (i >= n) continue;
             const int32_t word = In.cell[i];
+            rword[r] = word;
             if (word < 0) continue;
             const int cell = word & CELL_MASK;
             const int g = In.g[i];
+            rg[r] = g;
+            rx[r] = In.x[i];
+            rox[r] = In.ox[i];
+            if (DIM == 2) {
+                ry[r] = In.y[i];
+                roy[r] = In.oy[i];
+            }
+            rnu[r] = In.nu[i];
+            rw[r] = In.w[i];
+            rid[r] = In.id[i];
             bool ok = cell < K.ncell;
             int64_t key = 0;
             if (ok) {
@@ -1385,24 +1403,23 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(Dev D, Consts K, 
 #pragma unroll
         for (int r = 0; r < SORT_PPT; ++r) {
             if (slot[r] == -1) continue;
-            const int64_t i = c0 + (int64_t)r * SORT_THREADS + threadIdx.x;
             const int64_t o = slot[r] >= 0 ? (int64_t)R.base[slot[r]] + pos[r] : pos[r];
             if (o < 0 || o >= nlive) {
                 atomicOr((unsigned long long*)(D.counters + CNT_ERR), ERR_COUNT);
                 continue;
             }
-            const int32_t word = In.cell[i];
-            Out.x[o] = In.x[i];
-            Out.ox[o] = (word & FLIP_X) ? -In.ox[i] : In.ox[i];
+            const int32_t word = rword[r];
+            Out.x[o] = rx[r];
+            Out.ox[o] = (word & FLIP_X) ? -rox[r] : rox[r];
             if (DIM == 2) {
-                Out.y[o] = In.y[i];
-                Out.oy[o] = (word & FLIP_Y) ? -In.oy[i] : In.oy[i];
+                Out.y[o] = ry[r];
+                Out.oy[o] = (word & FLIP_Y) ? -roy[r] : roy[r];
             }
-            Out.nu[o] = In.nu[i];
-            Out.w[o] = In.w[i];
-            Out.id[o] = In.id[i];
+            Out.nu[o] = rnu[r];
+            Out.w[o] = rw[r];
+            Out.id[o] = rid[r];
             Out.cell[o] = word & CELL_MASK;
-            Out.g[o] = In.g[i];
+            Out.g[o] = rg[r];
         }
         __syncthreads();
     }
