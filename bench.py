@@ -105,17 +105,20 @@ def cpu_baseline_window(prob, n_particles, budget_s=15.0):
     sim = oracle.Sim(q)
     sim.set_pool(st["pool"], st["births"], st["rhop"])
     del st
-    pushes = steps = 0
+    pushes = steps = cgu = 0
+    ncg = prob.ncell * prob.G
     with pinned_to_one_cpu() as pin:
         t0 = time.perf_counter()
         while steps == 0 or time.perf_counter() - t0 < budget_s:
             sim.step(1)
             d = sim.diag()
             pushes += d["n_alive_in"] + d["n_births"]
+            cgu += ncg * d["sweeps"]
             steps += 1
         dt = time.perf_counter() - t0
     model, ncpu, _ = cpu_info()
     return {"value": pushes / dt, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
+            "cell_group_updates_per_s": cgu / dt,
             "sample": f"{steps} steps of the 256x256x32 lattice from a seeded synthetic state holding the "
                       f"timed window's {int(n_particles)} particles ({pushes} pushes, {dt:.1f} s)",
             "cpu_model": model, "host_logical_cpus": ncpu, "pinned_cpu": pin.cpu}
@@ -128,6 +131,7 @@ def cpu_baseline(probs, budget_s=15.0):
     pin = pinned_to_one_cpu().__enter__()
     pushes = 0
     steps = 0
+    cgu = 0
     t0 = time.perf_counter()
     sims = []
     done = False
@@ -138,6 +142,7 @@ def cpu_baseline(probs, budget_s=15.0):
             sim.step(1)
             d = sim.diag()
             pushes += d["n_alive_in"] + d["n_births"]
+            cgu += prob.ncell * prob.G * d["sweeps"]
             steps += 1
             if time.perf_counter() - t0 >= budget_s:
                 done = True
@@ -150,6 +155,7 @@ def cpu_baseline(probs, budget_s=15.0):
             f"{steps} instance-steps of the first {len(sims)} instances from t=0")
     model, ncpu, _ = cpu_info()
     return {"value": pushes / dt, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
+            "cell_group_updates_per_s": cgu / dt,
             "sample": f"{what} ({pushes} pushes, {dt:.1f} s, single thread)",
             "cpu_model": model, "host_logical_cpus": ncpu, "pinned_cpu": pin.cpu}
 
