@@ -401,6 +401,9 @@ def main():
                     default="lattice")
     ap.add_argument("--per-instance", action="store_true",
                     help="batch workload: one context per instance instead of one batched context")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="batch workload: leave out the batched-vs-per-instance comparison (for kernel traces "
+                         "of the batched run alone)")
     ap.add_argument("--spinup", type=int, default=-1, help="untimed steps from t=0 (default per workload)")
     ap.add_argument("--sort-interval", type=int, default=0,
                     help="steps between counting sorts of the pool (0 = library default)")
@@ -582,7 +585,7 @@ def main():
                            "kernel": "k_si_sweep (the source-iteration phase: sweeps and decides)",
                            "algorithmic_bytes_per_update": SI_SWEEP_BYTES,
                            "from": f"{nph} further steps with every phase timed"}
-    if wl == "batch" and not args.per_instance:
+    if wl == "batch" and not args.per_instance and not args.no_compare:
         del ctxs
         out["batched_vs_per_instance"] = batched_vs_per_instance(probs, stream, spin, 20, args.sort_interval)
     if not args.no_cpu_baseline:
