@@ -1,0 +1,93 @@
+"""GPU vs FP64 oracle on the degenerate and extreme inputs of the method: a
+single cell between mirrors (0-D relaxation with particles), one-cell-wide
+2-D strips in either direction, a 2-D medium with no opacity (free streaming
+only: no collision ever), a 2-D mesh at the largest group count (64), a batch
+whose instances include a single cell and a strip, and zero steps.  Same bar as
+the other parity tests: integers bit-exact, every field, tally and particle
+within 1e-10 of its array's max-norm."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_16981_amd import ugkwp
+from paper_2312_16981_amd import workloads as W
+from test_gpu_parity import compare_pool, compare_state, run_pair, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _one_cell(flags=0):
+    p = W.slab(1, 5, lambda x: np.full_like(x, 0.5), dt=0.02, steps=0, w_ref=1e-4, T0=0.3, pool_cap=1 << 18,
+               flags=flags, name=f"one_cell_f{flags}")
+    return p.with_(bc=[W.BC_REFLECT, W.BC_REFLECT, 0, 0], Tr0=np.array([0.8]))
+
+
+@pytest.mark.parametrize("flags", [0, W.FLAG_SI_LINEARIZED | W.FLAG_SLOPES])
+def test_single_cell_between_mirrors(flags):
+    ctx, sim = run_pair(_one_cell(flags), 10, every=2)
+    assert sim.diag()["n_alive_out"] > 0
+
+
+def _strip(nx, ny, kappa=1.0, bc=None, bcT=None, G=6):
+    L = 1.0
+    ncell = nx * ny
+    p = W.c5_lognormal(n=4, G=G, dt=2e-3, w_ref=1e-4, pool_cap=1 << 20)
+    return p.with_(name=f"strip{nx}x{ny}", nx=nx, ny=ny, x1=L * nx / max(nx, ny), y1=L * ny / max(nx, ny),
+                   kappa=np.full((ncell, G), kappa), cv=np.ones(ncell), T0=np.full(ncell, 1e-3),
+                   Tr0=np.full(ncell, 1e-3), pinned=np.zeros(ncell, np.uint8),
+                   bc=bc or [W.BC_PLANCK, W.BC_VACUUM, W.BC_REFLECT, W.BC_REFLECT], bcT=bcT or [1.0, 0.0, 0.0, 0.0])
+
+
+@pytest.mark.parametrize("shape", [(40, 1), (1, 40)])
+def test_one_cell_wide_2d_strips(shape):
+    nx, ny = shape
+    if ny == 1:
+        bc, bcT = [W.BC_PLANCK, W.BC_VACUUM, W.BC_REFLECT, W.BC_REFLECT], [1.0, 0.0, 0.0, 0.0]
+    else:
+        bc, bcT = [W.BC_REFLECT, W.BC_REFLECT, W.BC_PLANCK, W.BC_VACUUM], [0.0, 0.0, 1.0, 0.0]
+    run_pair(_strip(nx, ny, bc=bc, bcT=bcT), 8, every=4)
+
+
+def test_transparent_2d_medium_never_collides():
+    p = _strip(24, 24, kappa=0.0)
+    ctx, sim = run_pair(p, 6, every=3)
+    t = ctx.get_tallies(0)
+    assert np.all(t["dep"] == 0.0)
+
+
+def test_largest_group_count_in_2d():
+    run_pair(W.c5_lognormal(n=20, G=64, dt=2e-2, w_ref=2e-4, pool_cap=1 << 21), 4, every=2)
+
+
+def test_batch_with_a_single_cell_and_a_strip():
+    probs = [_one_cell().with_(seed=11),
+             W.slab(2, 3, lambda x: np.full_like(x, 5.0), dt=1e-3, steps=0, w_ref=3e-5, seed=12,
+                    pool_cap=1 << 17, name="two_cells"),
+             W.slab(70, 64, lambda x: np.where(x < 0.3, 0.1, 50.0), dt=1e-3, steps=0, w_ref=3e-5, seed=13,
+                    pool_cap=1 << 18, name="seventy_cells")]
+    probs[0] = probs[0].with_(dt=1e-3)
+    say("[edges] batch of", len(probs))
+    ctx = ugkwp.from_batch(probs)
+    sims = [oracle.Sim(q) for q in probs]
+    for n in range(8):
+        ctx.step(1)
+        for s in sims:
+            s.step(1)
+    for k, (q, s) in enumerate(zip(probs, sims)):
+        compare_state(ctx, s, q, inst=k, what=f"edge batch instance {k}")
+
+
+def test_zero_steps_change_nothing():
+    p = W.c1_marshak_like()
+    ctx = ugkwp.from_problem(p)
+    sim = oracle.Sim(p)
+    ctx.step(3)
+    sim.step(3)
+    before = [a.copy() for a in ctx.get_fields(0)]
+    counters = ctx.get_counters(0)
+    ctx.step(0)
+    for a, b in zip(before, ctx.get_fields(0)):
+        np.testing.assert_array_equal(a, b)
+    assert ctx.get_counters(0) == counters
+    compare_state(ctx, sim, p, what="after zero steps")
+    compare_pool(ctx, sim, 1)
