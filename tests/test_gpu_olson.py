@@ -53,16 +53,18 @@ def test_olson_1d(flags):
     run_pair(p.with_(name=f"olson1d_f{flags}"), 12, every=4)
 
 
-def test_olson_1d_many_steps_in_one_call():
+def test_olson_1d_whole_run_in_one_call():
+    """The whole run to c t = 4 (107 steps; the source switches off at c t = 2) in one
+    call, compared with the oracle at the end."""
     p = W.olson1d()
     ctx = ugkwp.from_problem(p)
     sim = oracle.Sim(p)
-    say("[olson] olson1d, 60 steps in one call")
-    ctx.step(60)
-    sim.step(60)
-    compare_state(ctx, sim, p, what="olson1d step 60")
+    say(f"[olson] olson1d, {p.steps} steps in one call")
+    ctx.step(p.steps)
+    sim.step(p.steps)
+    compare_state(ctx, sim, p, what=f"olson1d step {p.steps}")
     compare_pool(ctx, sim, 1)
-    assert ctx.get_diag()["injection"] == 0.0          # c t = 2.25 > 2: the source is off
+    assert ctx.get_diag()["injection"] == 0.0          # c t = 4 > 2: the source is off
 
 
 @pytest.mark.parametrize("flags", [LIN, LIN | SL])
