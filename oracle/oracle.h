@@ -15,9 +15,12 @@
  * Parity status: the whole-step result has no printed value in the paper
  * ("parity unpinned" beyond the invariants the tests check: free streaming,
  * diffusion limit, equilibrium, 0-D relaxation, energy conservation, per-cell
- * particle ledger, symmetry).  The scalar pieces (Philox, Planck integral,
- * flux coefficients, frequency sampler) are pinned against independent
- * implementations / closed forms / brute force.
+ * particle ledger, symmetry, the particle/wave flux correspondence, collision
+ * and reset laws, implicit 0-D steps with each material model).  The scalar
+ * pieces (Philox, Planck integral, flux and slope coefficients, frequency
+ * sampler and slope offset, Olson's ionisation fraction, heat capacity and
+ * material energy, the opacity table) are pinned against independent
+ * implementations, closed forms, quadrature or brute force.
  */
 #ifndef UGKWP_ORACLE_H
 #define UGKWP_ORACLE_H
