@@ -575,6 +575,14 @@ def main():
                      "kernel": f"k_push<{probs[0].dim}>", "algorithmic_bytes_per_push":
                      f"{br} read + {bw} per survivor + {bd} per absorbed/escaped particle"},
     }
+    if ms_si_ph > 0:
+        # the source-iteration phase as a second roofline object (every sweep and decide
+        # launch between two events, from the phase-timed steps)
+        si_ach = SI_SWEEP_BYTES * ph_cgu / (ms_si_ph * 1e-3) / 1e9
+        out["roofline_si"] = {"bound": "hbm", "achieved": si_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": si_ach / HBM_PEAK_GBS, "kernel": "k_si_sweep (the source-iteration phase)",
+                              "algorithmic_bytes_per_update": SI_SWEEP_BYTES,
+                              "from": f"{nph} further steps with every phase timed"}
     if wl == "batch" and ms_si_ph > 0:
         # the source iteration dominates the batched step: its phase (every sweep and
         # decide launch between two events) is the roofline kernel, the push is kept
