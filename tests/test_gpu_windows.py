@@ -160,3 +160,26 @@ def test_adjoint_full_workload_against_oracle():
     e = relerr(g, o)
     say(f"[window] adjoint: max-norm relative error {e:.2e}")
     assert e <= TOL
+
+
+@pytest.mark.parametrize("which", ["slab_all_flags", "olson1d"])
+def test_graph_replay_of_the_later_variants_matches_oracle(which):
+    """HIP-graph replays with the second-order wave part, the iterate's wave flux and
+    boundary particles, and with Olson's models (tabulated opacity, heat capacity, a
+    source that switches off inside the run), against the oracle."""
+    if which == "slab_all_flags":
+        p = W.c1_marshak_like().with_(flags=W.FLAG_SLOPES | W.FLAG_WAVE_ITER | W.FLAG_BOUNDARY_PARTICLES,
+                                      name="slab100_graph_all_flags")
+        n = 24
+    else:
+        p = W.olson1d().with_(name="olson1d_graph")
+        n = 60                                   # the source switches off at step 54 (c t = 2)
+    say(f"[graph] {p.name}, {n} steps")
+    ctx = ugkwp.from_problem(p, extra_flags=ugkwp.FLAG_GRAPH)
+    sim = oracle.Sim(p)
+    for k in range(n):
+        ctx.step(1)
+        sim.step(1)
+        if (k + 1) % 12 == 0:
+            compare_state(ctx, sim, p, what=f"{p.name} step {k}")
+    compare_pool(ctx, sim, p.dim)
