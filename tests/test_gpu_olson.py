@@ -139,3 +139,30 @@ def test_recording_and_bad_input_refused():
     ctx.step(3)
     sim.step(3)
     compare_state(ctx, sim, p, what="after refused calls")
+
+
+@pytest.mark.parametrize("which", ["olson1d", "slab_all_flags"])
+def test_checkpoint_restart_with_the_later_variants(which):
+    """A saved state restored into a fresh context continues like the oracle's
+    uninterrupted run: with Olson's models across the source's switch-off (steps
+    0-39 saved, 40-79 restored), and with every second-order flag."""
+    from test_gpu_parity import TOL, relerr
+    if which == "olson1d":
+        p, n = W.olson1d(), 40
+    else:
+        p, n = W.c1_marshak_like().with_(flags=SL | WI | W.FLAG_BOUNDARY_PARTICLES, name="slab_all_flags"), 12
+    say(f"[checkpoint] {p.name} steps {n} + {n}")
+    a = ugkwp.from_problem(p)
+    a.step(n)
+    buf = a.get_state()
+    b = ugkwp.from_problem(p)
+    b.set_state(buf)
+    b.step(n)
+    sim = oracle.Sim(p)
+    sim.step(2 * n)
+    compare_state(b, sim, p, what=f"{p.name} restored")
+    compare_pool(b, sim, p.dim)
+    a.step(n)
+    ra, ta, _ = a.get_fields()
+    rb, tb, _ = b.get_fields()
+    assert relerr(rb, ra) <= TOL and relerr(tb, ta) <= TOL
