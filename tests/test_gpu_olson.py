@@ -166,3 +166,19 @@ def test_checkpoint_restart_with_the_later_variants(which):
     ra, ta, _ = a.get_fields()
     rb, tb, _ = b.get_fields()
     assert relerr(rb, ra) <= TOL and relerr(tb, ta) <= TOL
+
+
+def test_autotune_with_tabulated_flights():
+    """The push's launch-shape autotuner on the table's flights (and its restore of
+    the tallies and counters it touched): the run goes on like the oracle's."""
+    p = W.olson2d(n=40, G=8).with_(name="olson2d_40_autotune")
+    ctx = ugkwp.from_problem(p)
+    sim = oracle.Sim(p)
+    ctx.step(4)
+    sim.step(4)
+    res = ctx.autotune()
+    assert res["threads"] in (256, 512) and res["candidates"] >= 6
+    ctx.step(3)
+    sim.step(3)
+    compare_state(ctx, sim, p, what="olson2d after autotune")
+    compare_pool(ctx, sim, 2)
