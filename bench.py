@@ -51,8 +51,8 @@ SI_SWEEP_BYTES = 64        # Q, lambda, sigma, phi^k, rho^k, one face D read; rh
 # to those sources makes bench.py report the traffic as unknown.
 PUSH_SOURCES = ("kernels.hip", "device_math.hpp", "device_common.hpp", "common.hpp")
 PUSH_TRAFFIC = {
-    "slab": {"sources": "499181cc81b94de4", "read_per_push": 49.13, "write_per_push": 12.87},
-    "lattice": {"sources": "499181cc81b94de4", "read_per_push": 66.53, "write_per_push": 21.53},
+    "slab": {"sources": "3a8581fc96788ca8", "read_per_push": 49.14, "write_per_push": 12.88},
+    "lattice": {"sources": "3a8581fc96788ca8", "read_per_push": 66.52, "write_per_push": 21.53},
 }
 
 
@@ -334,16 +334,23 @@ def batched_vs_per_instance(probs, stream, spin, nsteps=20, sort_interval=0):
 
 def copy_probe(mib=1024, reps=5):
     """A plain elementwise copy (dst = -src, float64) of `mib` MiB read and
-    `mib` MiB written, repeated: the known-size reference for HBM byte counters."""
+    `mib` MiB written, repeated: the known-size reference for HBM byte counters,
+    and the copy rate this GPU reaches (read + written bytes over the mean time
+    of the repetitions after the first, by events on torch's stream)."""
     import torch
     n = mib * (1 << 20) // 8
     src = torch.ones(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(reps):
+    torch.neg(src, out=dst)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps - 1):
         torch.neg(src, out=dst)
+    ev[1].record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
-                      "reps": reps}), flush=True)
+    ms = ev[0].elapsed_time(ev[1]) / max(1, reps - 1)
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "reps": reps,
+                      "copy_ms": ms, "copy_GBps": 2 * n * 8 / ms / 1e6}), flush=True)
 
 
 def workload_name(wl, probs, spin, args):

@@ -962,19 +962,20 @@ __device__ inline int fly(const Dev& D, const Consts& K, const Geo& I, TallyTabl
                           uint32_t step, double tfac, int g, double nu, double w, Flight& f)
 {
     for (;;) {
+        // time to the face ahead on each axis: the face is selected first and
+        // divided once (a branch per sign would make a wavefront holding both
+        // signs evaluate both divisions)
         const double vx = K.cv * f.ox;
         const double xl = I.x0 + (double)f.ix * I.dx, xr = I.x0 + (double)(f.ix + 1) * I.dx;
-        double tx;
-        if (vx > 0) tx = (xr - f.x) / vx;
-        else if (vx < 0) tx = (xl - f.x) / vx;
-        else tx = INFINITY;
+        const double qx = ((vx > 0 ? xr : xl) - f.x) / vx;
+        const double tx = (vx > 0 || vx < 0) ? qx : INFINITY;
         double vy = 0.0, yl = 0.0, yr = 0.0, ty = INFINITY;
         if (DIM == 2) {
             vy = K.cv * f.oy;
             yl = I.y0 + (double)f.iy * I.dy;
             yr = I.y0 + (double)(f.iy + 1) * I.dy;
-            if (vy > 0) ty = (yr - f.y) / vy;
-            else if (vy < 0) ty = (yl - f.y) / vy;
+            const double qy = ((vy > 0 ? yr : yl) - f.y) / vy;
+            ty = (vy > 0 || vy < 0) ? qy : INFINITY;
         }
         const bool xaxis = DIM == 1 || tx <= ty;
         const double tf = xaxis ? tx : ty;
@@ -1133,8 +1134,16 @@ struct PoolRec {
 // a thread handles ppt of them.  Stable fields are only read; the new
 // position and cell word go to the other moving-field buffer at the same slot,
 // so the committed pool stays intact until the step commits.
+// The wavefronts per SIMD the single-instance pushes of the nu^-3 and group
+// opacities are held to (their registers fit without spilling: 4 in 2-D, 5 in
+// 1-D); the other instances are left to the compiler.
+template <int DIM, bool SINGLE, int SM>
+constexpr int push_min_waves()
+{
+    return (!SINGLE || (SM != SIG_NU3 && SM != SIG_GROUP)) ? 1 : (DIM == 2 ? 4 : 5);
+}
 #ifndef UGK_PUSH_ATTR
-#define UGK_PUSH_ATTR
+#define UGK_PUSH_ATTR __attribute__((amdgpu_waves_per_eu(push_min_waves<DIM, SINGLE, SM>())))
 #endif
 #ifndef UGK_PUSH_PREFETCH_2D
 #define UGK_PUSH_PREFETCH_2D 1
@@ -2457,10 +2466,27 @@ void launch_push(int dim, const Dev& D, const Consts& K, const Pool& In, const P
     }
 }
 
+// The scatter runs as a persistent grid of the blocks that fit at once (a
+// second round of blocks measured about 3% slower on the 2-D lattice).
+template <int DIM, bool SINGLE>
+static unsigned sort_blocks()
+{
+    static unsigned nb = 0;
+    if (nb == 0) {
+        int per = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sort_scatter<DIM, SINGLE>, SORT_THREADS, 0) !=
+                hipSuccess || per < 1)
+            per = 4;
+        nb = (unsigned)(per * num_cus());
+    }
+    return nb;
+}
+
 void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& In, const Pool& Out, hipStream_t st)
 {
     const bool single = K.n_inst == 1;
-    const unsigned nb = 2048;
+    const unsigned nb = dim == 1 ? (single ? sort_blocks<1, true>() : sort_blocks<1, false>())
+                                 : (single ? sort_blocks<2, true>() : sort_blocks<2, false>());
     if (dim == 1) {
         if (single) k_sort_scatter<1, true><<<nb, SORT_THREADS, 0, st>>>(D, K, In, Out);
         else k_sort_scatter<1, false><<<nb, SORT_THREADS, 0, st>>>(D, K, In, Out);
