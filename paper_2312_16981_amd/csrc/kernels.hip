@@ -2471,15 +2471,15 @@ void launch_push(int dim, const Dev& D, const Consts& K, const Pool& In, const P
 template <int DIM, bool SINGLE>
 static unsigned sort_blocks()
 {
-    static unsigned nb = 0;
-    if (nb == 0) {
-        int per = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sort_scatter<DIM, SINGLE>, SORT_THREADS, 0) !=
-                hipSuccess || per < 1)
-            per = 4;
-        nb = (unsigned)(per * num_cus());
+    static int per = 0;     // resident blocks per CU (a property of the kernel)
+    if (per == 0) {
+        int q = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, k_sort_scatter<DIM, SINGLE>, SORT_THREADS, 0) !=
+                hipSuccess || q < 1)
+            q = 4;
+        per = q;
     }
-    return nb;
+    return (unsigned)(per * num_cus());
 }
 
 void launch_sort_scatter(int dim, const Dev& D, const Consts& K, const Pool& In, const Pool& Out, hipStream_t st)
