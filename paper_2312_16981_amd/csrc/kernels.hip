@@ -2348,10 +2348,26 @@ void launch_slopes(int dim, const Dev& D, const Consts& K, const double* src, bo
     else k_slopes<2><<<blocks(K.n_cg, 256), 256, 0, st>>>(D, K, src, sub_rhop ? 1 : 0);
 }
 
+static int num_cus();
+
+// The sampler runs as a grid of the blocks that fit at once (its wavefronts
+// take 64 births per round; 512 blocks left the 2-D sampler at half occupancy).
+template <int DIM>
+static unsigned sample_blocks()
+{
+    static int per = 0;     // resident blocks per CU (a property of the kernel)
+    if (per == 0) {
+        int q = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, k_sample<DIM>, 256, 0) != hipSuccess || q < 1) q = 2;
+        per = q;
+    }
+    return (unsigned)(per * num_cus());
+}
+
 void launch_sample(int dim, const Dev& D, const Consts& K, const Pool& P, hipStream_t st)
 {
-    if (dim == 1) k_sample<1><<<512, 256, 0, st>>>(D, K, P);
-    else k_sample<2><<<512, 256, 0, st>>>(D, K, P);
+    if (dim == 1) k_sample<1><<<sample_blocks<1>(), 256, 0, st>>>(D, K, P);
+    else k_sample<2><<<sample_blocks<2>(), 256, 0, st>>>(D, K, P);
 }
 
 // Push block sizes the launch shape may take (threads per block).
