@@ -41,7 +41,7 @@ PUSH_BYTES_WRITE = 12      # new position and cell word of a survivor (updated i
 PUSH_BYTES_DEAD = 4        # empty-slot mark of a particle absorbed or gone
 SPINUP = {"slab": 500, "lattice": 300, "batch": 100, "adjoint": 0, "thickthin": 200, "marshak": 100, "larsen": 100,
           "olson1d": 0, "olson2d": 0}
-ADJ_SWEEP_BYTES = 48       # rbar, lambda, sigma, phi' and two face coefficients per (cell, group) update
+ADJ_SWEEP_BYTES = 40       # rbar, sigma, phi' and two face coefficients per (cell, group) update (lambda is formed from sigma)
 SI_SWEEP_BYTES = 64        # Q, lambda, sigma, phi^k, rho^k, one face D read; rho^{k+1}, phi^{k+1} written
 
 # HBM bytes per push of k_push measured with rocprofv3 FETCH_SIZE / WRITE_SIZE,

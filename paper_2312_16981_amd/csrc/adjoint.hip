@@ -192,8 +192,9 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_prep(Dev D, Consts K, Adj A
 __device__ inline double bbar_of(const Dev& D, const Consts& K, const Adj& A, const double* mu, int64_t jj,
                                  int c)
 {
-    const double lam = D.sv[jj];
-    return temp_weight(D, K, c) * D.sig[jj] / (1.0 + lam) * mu[c] + A.rbar[jj] / (1.0 + lam);
+    const double sg = D.sig[jj];
+    const double lam = s_of_sigma(K, sg);
+    return temp_weight(D, K, c) * sg / (1.0 + lam) * mu[c] + A.rbar[jj] / (1.0 + lam);
 }
 
 // Face q (XLO, XHI, YLO, YHI) of slot j: neighbour slot and cell, face slot, area.
@@ -285,10 +286,10 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
         Df[q] = nlam[q] = ntw[q] = nsig[q] = nmu[q] = nrb[q] = 0.0;
     }
     if (act) {
-        lam = D.sv[j];
         mui = mu_in[cell];
         tw = temp_weight(D, K, cell);
         sg = D.sig[j];
+        lam = s_of_sigma(K, sg);
         rb = A.rbar[j];
         dphi = A.dphi[j];
 #pragma unroll
@@ -296,9 +297,9 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_sweep(Dev D, Consts K, Adj 
             if (q >= nf) continue;
             Df[q] = (q >> 1) == 0 ? D.Dx[fr[q].fslot] : D.Dy[fr[q].fslot];
             if (fr[q].inside) {
-                nlam[q] = D.sv[fr[q].nbj];
                 ntw[q] = temp_weight(D, K, fr[q].nbcell);
                 nsig[q] = D.sig[fr[q].nbj];
+                nlam[q] = s_of_sigma(K, nsig[q]);
                 nmu[q] = mu_in[fr[q].nbcell];
                 nrb[q] = A.rbar[fr[q].nbj];
             }
@@ -433,8 +434,8 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_grad(Dev D, Consts K, Adj A
     }
     if (act) {
         wi = temp_weight(D, K, cell);
-        lam = D.sv[j];
         sig = D.sig[j];
+        lam = s_of_sigma(K, sig);
         rb = A.rbar[j];
         phik = A.phi[j];
         rQ = A.rQ[o];
@@ -456,7 +457,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_grad(Dev D, Consts K, Adj A
                 phin[q] = A.phi[fr[q].nbj];
                 nw[q] = temp_weight(D, K, fr[q].nbcell);
                 nsig[q] = D.sig[fr[q].nbj];
-                nlam[q] = D.sv[fr[q].nbj];
+                nlam[q] = s_of_sigma(K, nsig[q]);
                 nrb[q] = A.rbar[fr[q].nbj];
             } else if (I.bc[q] == BC_PLANCK) {
                 ghost[q] = phib[q * MAX_G + g];

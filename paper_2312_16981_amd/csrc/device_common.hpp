@@ -12,6 +12,11 @@ namespace ugk {
 // have (after = 1).  Behind a step that did not commit, every later step's
 // launches therefore return at once and leave that step's state as its
 // failure left it.  The value read is uniform, so whole grids return together.
+// s = c sigma dt / eps^2 of a slot from its opacity, in one evaluation order:
+// the coefficient tables store it and the sweeps re-form it from sigma alone
+// (the same bits), so that they need not read both.
+__device__ inline double s_of_sigma(const Consts& K, double sg) { return K.c * sg * K.dt / (K.eps * K.eps); }
+
 __device__ inline bool gate_open(const Dev& D, const Consts& K, uint32_t after)
 {
     return K.gate == GATE_OFF || *D.step == K.gate + after;

@@ -186,7 +186,7 @@ __global__ void k_tables(Dev D, Consts K)
     D.inv_kappa[j] = ((K.stim || K.table) && (K.flags & 1u)) ? D.simpson[I.edge_off + s.g] / sg
                      : K.table ? 1.0 / sg
                                : 1.0 / kap;   // +inf for kappa = 0: no collision
-    const double sv = K.c * sg * K.dt / (K.eps * K.eps);
+    const double sv = s_of_sigma(K, sg);
     D.sig[j] = sg;
     D.sv[j] = sv;
     D.es[j] = exp(-sv);
@@ -237,7 +237,7 @@ __global__ void k_tab_logs(double* v, int64_t n)
 // D of a face with face opacity sf and centre distance h (Appendix B, Eq. C2Formula).
 __device__ inline double face_coef(const Consts& K, double sf, double h)
 {
-    const double s = K.c * sf * K.dt / (K.eps * K.eps);
+    const double s = s_of_sigma(K, sf);
     const double c2 = K.dt * coef_c2_over_dt(s);
     return -(K.c * K.c / (3.0 * K.eps * K.eps)) * c2 / h;
 }
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroLi
         rho = D.rho[j];
         rhop = D.rhop[j];
         es = D.es[j];
-        sv = D.sv[j];
+        if (K.flags & UGKWP_FLAG_SLOPES) sv = D.sv[j];    // the slope coefficient's s
         nl = D.nu[I.edge_off + s.g];
         nh = D.nu[I.edge_off + s.g + 1];
         T = D.T[I.cell_off + s.lcell];
@@ -1732,8 +1732,12 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
     if (act) {
         phi = phi_in[j];
         if (!FIRST) Qj = D.Q[j];
-        lam = D.sv[j];
-        sig = D.sig[j];
+        if (!TDEP) {
+            // (TDEP sweeps form both from T^k; reading s here costs less than
+            // forming it from sigma, a division per slot)
+            lam = D.sv[j];
+            sig = D.sig[j];
+        }
         rho_prev = rho_in[j];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -1811,7 +1815,7 @@ __global__ __launch_bounds__(SI_THREADS) void k_si_sweep(Dev D, Consts K, int k,
             // coefficients of this sweep from the iterate T^k
             const double sk = K.table ? tsig_j : kap_j * pow(Tk, -K.t_power) * Sg;
             sig = sk;
-            lam = K.c * sk * K.dt / (K.eps * K.eps);
+            lam = s_of_sigma(K, sk);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if (q >= nf) continue;
