@@ -36,7 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PUSH_BYTES_READ = 48       # x, mu, nu, w, id (8 B each) + cell word, group (4 B each)
+PUSH_BYTES_READ = 44       # x, mu, nu, w, id and group word (8 B each) + cell word (4 B)
 PUSH_BYTES_WRITE = 12      # new position and cell word of a survivor (updated in place)
 PUSH_BYTES_DEAD = 4        # empty-slot mark of a particle absorbed or gone
 SPINUP = {"slab": 500, "lattice": 300, "batch": 100, "adjoint": 0, "thickthin": 200, "marshak": 100, "larsen": 100,
@@ -63,7 +63,7 @@ def push_sources_digest():
         with open(os.path.join(ROOT, "paper_2312_16981_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
-BYTES_2D = (64, 20, 4)     # 2-D: x, y, ox, oy, nu, w, id + cell word, group; writes x, y, cell word
+BYTES_2D = (60, 20, 4)     # 2-D: x, y, ox, oy, nu, w, id and group word + cell word; writes x, y, cell word
 
 
 def cpu_info():

@@ -121,6 +121,13 @@ constexpr int32_t DEAD = -1;
 constexpr int GHOST_SHIFT = 8;
 constexpr int32_t GROUP_MASK = (1 << GHOST_SHIFT) - 1;
 
+// The pool's id word carries the particle id in its low ID_BITS bits and the
+// group word above them, so that a record is one word shorter: the push and
+// the sort read 4 bytes less per particle.  Ids stay below 2^ID_BITS (the
+// runtime refuses a birth count that would reach it).
+constexpr int ID_BITS = 48;
+constexpr uint64_t ID_MASK = (1ull << ID_BITS) - 1ull;
+
 // A particle pool viewed as structure of arrays.  The moving fields (x, y and
 // the cell word) live in one of two buffers that alternate between steps; the
 // stable fields (direction, frequency, weight, id, group) are only appended
@@ -133,8 +140,7 @@ struct Pool {
     double* oy;
     double* nu;
     double* w;
-    uint64_t* id;
-    int32_t* g;
+    uint64_t* id;          // id | group word << ID_BITS
 };
 
 struct Dev {

@@ -769,10 +769,11 @@ __global__ void k_sample(Dev D, Consts K, Pool P)
         P.nu[o] = sample_nu(nl, nh, beta, u4);
     }
     P.w[o] = w;
-    P.id[o] = id;
+    // the group word above the id; a boundary-source particle carries its ghost
+    // side + 1 above the group bits
+    const uint32_t gw = part < 0 ? (uint32_t)g : (uint32_t)(g | ((part + 1) << GHOST_SHIFT));
+    P.id[o] = id | ((uint64_t)gw << ID_BITS);
     P.cell[o] = I.cell_off + lcell;
-    // a boundary-source particle carries its ghost side + 1 above the group bits
-    P.g[o] = part < 0 ? g : (g | ((part + 1) << GHOST_SHIFT));
     }
 }
 
@@ -1112,12 +1113,13 @@ __device__ inline T& at(T* base, uint32_t i)
 template <int DIM>
 struct PoolRec {
     double x, y, ox, oy, nu, w;
-    uint64_t id;
-    int32_t word, g;
+    uint64_t idw;          // id | group word << ID_BITS (split where it is used, so
+                           // that a load issued ahead is not waited for here)
+    int32_t word;
     __device__ inline void load(const Pool& P, uint32_t i)
     {
         word = at(P.cell, i);
-        g = at(P.g, i);
+        idw = at(P.id, i);
         x = at(P.x, i);
         ox = at(P.ox, i);
         if (DIM == 2) {
@@ -1126,7 +1128,6 @@ struct PoolRec {
         }
         nu = at(P.nu, i);
         w = at(P.w, i);
-        id = at(P.id, i);
     }
 };
 
@@ -1208,7 +1209,7 @@ __global__ __launch_bounds__(BS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool
                 at(Out.cell, iu) = DEAD;
             } else {
                 if (!PUSH_PREFETCH) {
-                    cur.g = at(In.g, iu);
+                    cur.idw = at(In.id, iu);
                     cur.x = at(In.x, iu);
                     cur.ox = at(In.ox, iu);
                     if (DIM == 2) {
@@ -1217,10 +1218,10 @@ __global__ __launch_bounds__(BS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool
                     }
                     cur.nu = at(In.nu, iu);
                     cur.w = at(In.w, iu);
-                    cur.id = at(In.id, iu);
                 }
-                const int g = cur.g & GROUP_MASK;
-                const int gside = cur.g >> GHOST_SHIFT;    // boundary-source particle: 1 + ghost side
+                const int32_t gword = (int32_t)(cur.idw >> ID_BITS);
+                const int g = gword & GROUP_MASK;
+                const int gside = gword >> GHOST_SHIFT;    // boundary-source particle: 1 + ghost side
                 const Geo I = SINGLE ? geo0 : geo_of(D.inst[D.cell_inst[cell]]);
                 Flight f;
                 f.x = cur.x;
@@ -1233,7 +1234,7 @@ __global__ __launch_bounds__(BS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool
                     f.oy = 0.0;
                 }
                 const double nu = cur.nu, w = cur.w;
-                const uint64_t id = cur.id;
+                const uint64_t id = cur.idw & ID_MASK;
                 const int lcell = cell - I.cell_off;
                 if (DIM == 1) {
                     f.ix = lcell;
@@ -1258,7 +1259,7 @@ __global__ __launch_bounds__(BS) UGK_PUSH_ATTR void k_push(Dev D, Consts K, Pool
                 } else {
                     if (gside) {
                         // entered: its flight is drawn; the group word loses the ghost mark
-                        at(In.g, iu) = g;
+                        at(In.id, iu) = id | ((uint64_t)g << ID_BITS);
                     } else if (i < n_slots) {
                         draw_flight(K, I, id, step, f);             // old particle: t_f = min(-tau ln eta, dt)
                     } else {
@@ -1348,21 +1349,21 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(Dev D, Consts K, 
         // block's ranks, and loads issued after a store could not pass it)
         double rx[SORT_PPT], ry[SORT_PPT], rox[SORT_PPT], roy[SORT_PPT], rnu[SORT_PPT], rw[SORT_PPT];
         uint64_t rid[SORT_PPT];
-        int32_t rword[SORT_PPT], rg[SORT_PPT];
+        int32_t rword[SORT_PPT];
 #pragma unroll
         for (int r = 0; r < SORT_PPT; ++r) {
             const int64_t i = c0 + (int64_t)r * SORT_THREADS + threadIdx.x;
             slot[r] = -1;
             pos[r] = 0;
             rword[r] = -1;
-            rg[r] = 0;
             if (i >= n) continue;
             const int32_t word = In.cell[i];
             rword[r] = word;
             if (word < 0) continue;
             const int cell = word & CELL_MASK;
-            const int g = In.g[i];
-            rg[r] = g;
+            const uint64_t idw = In.id[i];          // id | group word << ID_BITS
+            const int g = (int)(idw >> ID_BITS);
+            rid[r] = idw;
             rx[r] = In.x[i];
             rox[r] = In.ox[i];
             if (DIM == 2) {
@@ -1371,7 +1372,6 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(Dev D, Consts K, 
             }
             rnu[r] = In.nu[i];
             rw[r] = In.w[i];
-            rid[r] = In.id[i];
             bool ok = cell < K.ncell;
             int64_t key = 0;
             if (ok) {
@@ -1428,7 +1428,6 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(Dev D, Consts K, 
             Out.w[o] = rw[r];
             Out.id[o] = rid[r];
             Out.cell[o] = word & CELL_MASK;
-            Out.g[o] = rg[r];
         }
         __syncthreads();
     }

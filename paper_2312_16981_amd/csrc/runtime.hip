@@ -216,6 +216,7 @@ struct ugkwp_ctx {
     // launch shape of the push (default: occupancy-filled persistent grid, 4
     // particles per thread; ugkwp_autotune may change it)
     PushShape push_shape{0, 4, 256};
+    uint64_t ids_used = 0;             // the largest birth counter of an instance (particle ids below it)
 
     // each step's launch sequence captured as a HIP graph, one per launch
     // configuration (pool buffer parities, rho/T parity, sort, speculative sweeps)
@@ -533,7 +534,6 @@ struct ugkwp_ctx {
             stb[b].nu = dalloc<double>(owned, cap);
             stb[b].w = dalloc<double>(owned, cap);
             stb[b].id = dalloc<uint64_t>(owned, cap);
-            stb[b].g = dalloc<int32_t>(owned, cap);
         }
         d.blk_surv = dalloc<unsigned long long>(owned, MAX_PUSH_BLOCKS);
         push_shape = push_default_shape(dim, K);
@@ -1059,6 +1059,7 @@ struct ugkwp_ctx {
         int smax = 0, ssum = 0;
         int64_t cgu = 0;
         for (int q = 0; q < n_inst; ++q) {
+            ids_used = std::max(ids_used, (uint64_t)s.ist[q].births);
             smax = std::max(smax, s.ist[q].conv_sweeps);
             ssum += s.ist[q].conv_sweeps;
             cgu += (int64_t)s.ist[q].conv_sweeps * inst[q].ncell * inst[q].G;
@@ -1129,6 +1130,10 @@ struct ugkwp_ctx {
                 fail(UGKWP_EINVAL, "the record holds its maximum of %d steps", rec_cap);
             int m = std::min(nsteps - done, use_graph ? 1 : RUN_AHEAD);
             if (rec_cap > 0) m = std::min(m, rec_cap - nrec);
+            // particle ids share their word with the group: a batch may not
+            // number births past 2^ID_BITS (each step births fewer than the capacity)
+            if (ids_used + (uint64_t)m * (uint64_t)P.pool_capacity > ID_MASK)
+                fail(UGKWP_EPOOL, "particle ids would pass 2^%d", ID_BITS);
             const int kmax = P.si_max_iters;
             const int spec = std::min(kmax, last_sweeps + 1);
             // plan and enqueue
@@ -1519,7 +1524,7 @@ struct Tmp {
 namespace {
 
 constexpr char STATE_MAGIC[8] = {'U', 'G', 'K', 'W', 'P', 'S', 'T', '1'};
-constexpr uint32_t STATE_VERSION = 1;
+constexpr uint32_t STATE_VERSION = 2;     // 2: the group word travels in the id word
 
 struct StateHeader {
     char magic[8];
@@ -1562,7 +1567,7 @@ uint64_t state_layout(const ugkwp_ctx* c)
 
 // byte offsets of the sections of a saved state
 struct StateLayout {
-    size_t rho, rhop, phi0, T, births, x, y, ox, oy, nu, w, id, cell, g, end;
+    size_t rho, rhop, phi0, T, births, x, y, ox, oy, nu, w, id, cell, end;
 };
 
 size_t up8(size_t b) { return (b + 7) / 8 * 8; }
@@ -1585,7 +1590,6 @@ StateLayout state_sections(const ugkwp_ctx* c, int64_t n_slots)
     L.w = o;      o += 8 * ns;
     L.id = o;     o += 8 * ns;
     L.cell = o;   o += up8(4 * ns);
-    L.g = o;      o += up8(4 * ns);
     L.end = o;
     return L;
 }
@@ -1973,7 +1977,7 @@ int ugkwp_get_pool(ugkwp_ctx* ctx, double* x, double* y, double* ox, double* oy,
         hipStream_t st = ctx->st;
         std::vector<double> hx(ns), hy, hox(ns), hoy, hnu(ns), hw(ns);
         std::vector<uint64_t> hid(ns);
-        std::vector<int32_t> hcell(ns), hg(ns);
+        std::vector<int32_t> hcell(ns);
         if (ctx->dim == 2) { hy.resize(ns); hoy.resize(ns); }
         auto cp = [&](void* dst, const void* src, size_t bytes) {
             if (bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
@@ -1985,7 +1989,6 @@ int ugkwp_get_pool(ugkwp_ctx* ctx, double* x, double* y, double* ox, double* oy,
         cp(hw.data(), p.w, ns * 8);
         cp(hid.data(), p.id, ns * 8);
         cp(hcell.data(), p.cell, ns * 4);
-        cp(hg.data(), p.g, ns * 4);
         HIPCHK(hipStreamSynchronize(st));
         size_t o = 0;
         for (size_t q = 0; q < ns; ++q) {
@@ -1997,9 +2000,9 @@ int ugkwp_get_pool(ugkwp_ctx* ctx, double* x, double* y, double* ox, double* oy,
             if (oy) oy[o] = ctx->dim == 2 ? ((word & FLIP_Y) ? -hoy[q] : hoy[q]) : 0.0;
             if (nu) nu[o] = hnu[q];
             if (w) w[o] = hw[q];
-            if (id) id[o] = hid[q];
+            if (id) id[o] = hid[q] & ID_MASK;
             if (cell) cell[o] = word & CELL_MASK;
-            if (g) g[o] = hg[q];
+            if (g) g[o] = (int32_t)(hid[q] >> ID_BITS);
             ++o;
         }
         if ((int64_t)o != ctx->n_alive) fail(UGKWP_EHIP, "pool holds %zu live particles, expected %lld", o,
@@ -2020,8 +2023,10 @@ int ugkwp_set_pool(ugkwp_ctx* ctx, int64_t n, const double* x, const double* y, 
         if (ctx->dim == 2 && n > 0 && (!y || !oy)) fail(UGKWP_EINVAL, "2-D pool needs y and oy");
         const Inst& I = ctx->inst[0];
         for (int64_t q = 0; q < n; ++q)
-            if (cell[q] < 0 || cell[q] >= I.ncell || g[q] < 0 || g[q] >= I.G || !(w[q] >= 0) || !(nu[q] > 0))
-                fail(UGKWP_EINVAL, "particle %lld: cell, group, weight or frequency out of range", (long long)q);
+            if (cell[q] < 0 || cell[q] >= I.ncell || g[q] < 0 || g[q] >= I.G || !(w[q] >= 0) || !(nu[q] > 0) ||
+                id[q] > ID_MASK)
+                fail(UGKWP_EINVAL, "particle %lld: cell, group, weight, frequency or id out of range", (long long)q);
+        if (birth_counter > ID_MASK) fail(UGKWP_EINVAL, "birth counter beyond the id range");
         const Pool p = ctx->view(ctx->cur_mv, ctx->cur_st);
         hipStream_t st = ctx->st;
         auto cp = [&](void* dst, const void* src, size_t bytes) {
@@ -2033,9 +2038,10 @@ int ugkwp_set_pool(ugkwp_ctx* ctx, int64_t n, const double* x, const double* y, 
         if (ctx->dim == 2) { cp(p.y, y, nn * 8); cp(p.oy, oy, nn * 8); }
         cp(p.nu, nu, nn * 8);
         cp(p.w, w, nn * 8);
-        cp(p.id, id, nn * 8);
+        std::vector<uint64_t> idw(nn);     // id | group word << ID_BITS
+        for (size_t q = 0; q < nn; ++q) idw[q] = id[q] | ((uint64_t)(uint32_t)g[q] << ID_BITS);
+        cp(p.id, idw.data(), nn * 8);
         cp(p.cell, cell, nn * 4);
-        cp(p.g, g, nn * 4);
         std::vector<double> hp;
         if (rhop) {
             hp.assign((size_t)ctx->K.n_cg, 0.0);
@@ -2046,6 +2052,7 @@ int ugkwp_set_pool(ugkwp_ctx* ctx, int64_t n, const double* x, const double* y, 
         HIPCHK(hipMemcpyAsync(&s, ctx->D.ist, sizeof(InstState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         s.births = birth_counter;
+        ctx->ids_used = birth_counter;
         HIPCHK(hipMemcpyAsync(ctx->D.ist, &s, sizeof(InstState), hipMemcpyHostToDevice, st));
         const unsigned long long na[3] = {(unsigned long long)n, (unsigned long long)n, (unsigned long long)n};
         HIPCHK(hipMemcpyAsync(ctx->D.counters + CNT_SLOTS, na, sizeof(na), hipMemcpyHostToDevice, st));
@@ -2104,7 +2111,6 @@ int ugkwp_get_state(ugkwp_ctx* ctx, void* buf, int64_t bytes)
         cp(L.w, p.w, 8 * ns);
         cp(L.id, p.id, 8 * ns);
         cp(L.cell, p.cell, 4 * ns);
-        cp(L.g, p.g, 4 * ns);
         HIPCHK(hipStreamSynchronize(st));
         for (int k = 0; k < ctx->n_inst; ++k) std::memcpy(b + L.births + 8 * (size_t)k, &is[k].births, 8);
     });
@@ -2133,7 +2139,7 @@ int ugkwp_set_state(ugkwp_ctx* ctx, const void* buf, int64_t bytes)
         // the pool: every live slot names a cell and a group of its instance
         const size_t ns = (size_t)h.n_slots;
         const int32_t* cw = reinterpret_cast<const int32_t*>(b + L.cell);
-        const int32_t* gw = reinterpret_cast<const int32_t*>(b + L.g);
+        const uint64_t* iw = reinterpret_cast<const uint64_t*>(b + L.id);     // id | group word << ID_BITS
         std::vector<int> first(ctx->n_inst);
         for (int k = 0; k < ctx->n_inst; ++k) first[k] = ctx->inst[k].cell_off;
         int64_t live = 0;
@@ -2142,7 +2148,7 @@ int ugkwp_set_state(ugkwp_ctx* ctx, const void* buf, int64_t bytes)
             const int cell = cw[q] & CELL_MASK;
             if (cell >= ctx->ncell) fail(UGKWP_EINVAL, "saved particle %zu: cell out of range", q);
             const int k = (int)(std::upper_bound(first.begin(), first.end(), cell) - first.begin()) - 1;
-            if (gw[q] < 0 || gw[q] >= ctx->inst[k].G) fail(UGKWP_EINVAL, "saved particle %zu: group out of range", q);
+            if ((int64_t)(iw[q] >> ID_BITS) >= ctx->inst[k].G) fail(UGKWP_EINVAL, "saved particle %zu: group out of range", q);
             ++live;
         }
         if (live != h.n_alive) fail(UGKWP_EINVAL, "saved pool holds %lld live particles, header says %lld",
@@ -2150,6 +2156,11 @@ int ugkwp_set_state(ugkwp_ctx* ctx, const void* buf, int64_t bytes)
         const double* T = reinterpret_cast<const double*>(b + L.T);
         for (int i = 0; i < ctx->ncell; ++i)
             if (!(T[i] > 0) || !std::isfinite(T[i])) fail(UGKWP_EINVAL, "saved temperature not positive and finite");
+        for (int k = 0; k < ctx->n_inst; ++k) {
+            uint64_t nb = 0;
+            std::memcpy(&nb, b + L.births + 8 * (size_t)k, 8);
+            if (nb > ID_MASK) fail(UGKWP_EINVAL, "saved birth counter beyond the id range");
+        }
 
         hipStream_t st = ctx->st;
         auto cp = [&](void* dst, size_t off, size_t n) {
@@ -2168,10 +2179,13 @@ int ugkwp_set_state(ugkwp_ctx* ctx, const void* buf, int64_t bytes)
         cp(p.w, L.w, 8 * ns);
         cp(p.id, L.id, 8 * ns);
         cp(p.cell, L.cell, 4 * ns);
-        cp(p.g, L.g, 4 * ns);
         // the committed record: birth counters, pool size, step count
         std::vector<InstState> is((size_t)ctx->n_inst);
-        for (int k = 0; k < ctx->n_inst; ++k) std::memcpy(&is[k].births, b + L.births + 8 * (size_t)k, 8);
+        ctx->ids_used = 0;
+        for (int k = 0; k < ctx->n_inst; ++k) {
+            std::memcpy(&is[k].births, b + L.births + 8 * (size_t)k, 8);
+            ctx->ids_used = std::max(ctx->ids_used, (uint64_t)is[k].births);
+        }
         HIPCHK(hipMemcpyAsync(ctx->D.ist, is.data(), sizeof(InstState) * is.size(), hipMemcpyHostToDevice, st));
         std::vector<unsigned long long> cnt(N_COUNTERS, 0ull);
         cnt[CNT_SLOTS] = (unsigned long long)h.n_slots;
