@@ -2,9 +2,10 @@
 single cell between mirrors (0-D relaxation with particles), one-cell-wide
 2-D strips in either direction, a 2-D medium with no opacity (free streaming
 only: no collision ever), a 2-D mesh at the largest group count (64), a batch
-whose instances include a single cell and a strip, and zero steps.  Same bar as
-the other parity tests: integers bit-exact, every field, tally and particle
-within 1e-10 of its array's max-norm."""
+whose instances include a single cell and a strip, zero steps, and particle
+ids at the top of their 48-bit range.  Same bar as the other parity tests:
+integers bit-exact, every field, tally and particle within 1e-10 of its array's
+max-norm."""
 import numpy as np
 import pytest
 
@@ -91,3 +92,29 @@ def test_zero_steps_change_nothing():
     assert ctx.get_counters(0) == counters
     compare_state(ctx, sim, p, what="after zero steps")
     compare_pool(ctx, sim, 1)
+
+
+def test_particle_ids_kept_below_48_bits():
+    """The id word of the pool holds the particle id below bit 48 and the group
+    above it: ids and birth counters from 2^48 on are refused, and a step whose
+    births could reach 2^48 fails before it runs; the context stays usable."""
+    p = W.c1_marshak_like()
+    ctx = ugkwp.from_problem(p)
+    ctx.step(2)
+    pool = ctx.get_pool()
+    births, _ = ctx.get_counters(0)
+    bad = {k: v.copy() for k, v in pool.items()}
+    bad["id"][0] = np.uint64(1 << 48)
+    with pytest.raises(ugkwp.UGKWPError):
+        ctx.set_pool(bad, births)
+    with pytest.raises(ugkwp.UGKWPError):
+        ctx.set_pool(pool, 1 << 48)
+    ctx.set_pool(pool, (1 << 48) - 10)
+    with pytest.raises(ugkwp.UGKWPError):
+        ctx.step(1)
+    ctx.set_pool(pool, births)
+    sim = oracle.Sim(p)
+    sim.step(2)
+    ctx.step(2)
+    sim.step(2)
+    compare_state(ctx, sim, p, what="after refused ids")
