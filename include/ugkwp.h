@@ -322,7 +322,11 @@ int64_t ugkwp_pool_size(ugkwp_ctx* ctx);
 int ugkwp_get_pool(ugkwp_ctx* ctx, double* x, double* y, double* ox, double* oy,
                    double* nu, double* w, uint64_t* id, int32_t* cell, int32_t* g);
 /* Replace the pool of a single-instance context (y, oy may be NULL in 1-D) and
- * set its birth counter; rhop [ncell][G] (may be NULL) sets the survivor density. */
+ * set its birth counter; rhop [ncell][G] (may be NULL) sets the survivor density.
+ * Particle ids and the birth counter must lie below 2^48 (the library keeps a
+ * particle's group in the same 64-bit word); UGKWP_EINVAL otherwise.  A step
+ * whose births could number a particle 2^48 or above fails with UGKWP_EPOOL
+ * before it runs. */
 int ugkwp_set_pool(ugkwp_ctx* ctx, int64_t n, const double* x, const double* y,
                    const double* ox, const double* oy, const double* nu, const double* w,
                    const uint64_t* id, const int32_t* cell, const int32_t* g,
