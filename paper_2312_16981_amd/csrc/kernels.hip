@@ -426,9 +426,11 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_count(Dev D, Consts K, ZeroLi
         }
         for (int q = threadIdx.x; q < 8 * K.n_inst; q += COUNT_THREADS) D.diag[q] = 0.0;
     }
+    // Non-temporal zeros: the cleared tallies are next touched by the push's
+    // atomics, so keeping them out of the caches leaves room for the sweep inputs.
     for (int r = 0; r < Z.n; ++r) {
         uint64_t* p = (uint64_t*)Z.ptr[r];
-        for (int64_t q = j; q < Z.words[r]; q += stride) p[q] = 0ull;
+        for (int64_t q = j; q < Z.words[r]; q += stride) __builtin_nontemporal_store(0ull, p + q);
     }
     int N = 0;
     if (in) {
