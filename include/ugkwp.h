@@ -361,7 +361,9 @@ int ugkwp_set_state(ugkwp_ctx* ctx, const void* buf, int64_t bytes);
  * Times the particle push on the context's current pool for launch shapes
  * (threads per block: 256, 512; persistent blocks per CU: half, one and
  * two times what fits at that block size; particles per thread: 1, 2, 4, 8)
- * and keeps the fastest for the following steps.  Only the
+ * and keeps the fastest for the following steps if it beats the default shape
+ * (timed before and after the others, the faster of the two taken) by at
+ * least 3%, else the default.  Only the
  * speed changes: the order in which the push adds to its tallies may differ,
  * which moves floating-point sums by rounding.  The tallies and counters of the
  * last step are restored.  Needs a non-empty pool (UGKWP_EINVAL otherwise). */
