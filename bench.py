@@ -51,8 +51,8 @@ SI_SWEEP_BYTES = 64        # Q, lambda, sigma, phi^k, rho^k, one face D read; rh
 # to those sources makes bench.py report the traffic as unknown.
 PUSH_SOURCES = ("kernels.hip", "device_math.hpp", "device_common.hpp", "common.hpp")
 PUSH_TRAFFIC = {
-    "slab": {"sources": "2b138d1a683f0bd0", "read_per_push": 45.04, "write_per_push": 12.76},
-    "lattice": {"sources": "2b138d1a683f0bd0", "read_per_push": 62.23, "write_per_push": 21.61},
+    "slab": {"sources": "130a38c77fd81f1c", "read_per_push": 45.04, "write_per_push": 12.89},
+    "lattice": {"sources": "130a38c77fd81f1c", "read_per_push": 62.23, "write_per_push": 21.64},
 }
 
 

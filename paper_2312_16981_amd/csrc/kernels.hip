@@ -2025,8 +2025,16 @@ constexpr int DIAG_THREADS = 256;
 // last_sweep >= 0 (single instance): the convergence decision of that sweep
 // is taken here rather than by a decide launch; wavefront 0 of every block
 // takes it from the same residual sub-slots, and block 0 records it.
+// Occupancy floor of the commit, whose loads are all issued before its first
+// wait: 8 wavefronts per SIMD for batches (at 64 VGPRs, with some spilling: 3%
+// off a step of 512 slabs), 6 in 2-D; single 1-D instances, whose commits are
+// small and latency bound, are left to the compiler.
 template <bool SINGLE, int DIM>
-__global__ __launch_bounds__(DIAG_THREADS) void k_finish(Dev D, Consts K, int last_sweep, int push_blocks)
+constexpr int finish_min_waves() { return DIM == 2 ? 6 : (SINGLE ? 1 : 8); }
+
+template <bool SINGLE, int DIM>
+__global__ __launch_bounds__(DIAG_THREADS) __attribute__((amdgpu_waves_per_eu(finish_min_waves<SINGLE, DIM>())))
+void k_finish(Dev D, Consts K, int last_sweep, int push_blocks)
 {
     const int64_t j = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x;
     // the loads come first (nothing is stored before the gate): step count,
